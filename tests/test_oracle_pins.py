@@ -1,0 +1,702 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms
+of the rheology (Sec. II, Sec. III.B, Sec. IV), textbook finite-element
+values, exact flow solutions (plane Poiseuille for Bingham / power-law /
+Herschel-Bulkley fluids, the Taylor-Green vortex), dense direct solves and
+exact discrete identities.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.optimize import brentq
+
+from oracle import orc
+
+
+
+# --------------------------------------------------------------------------
+# viscosity law (eq:dimensionless:herschel-bulkley, eq:regularisation:limit)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("HB,n,Pa", [(1.0, 1.0, 1e3), (10.0, 0.5, 1e4), (2.0, 1.5, 400.0)])
+def test_viscosity_zero_strain_limit(HB, n, Pa):
+    # the regularised viscosity stays bounded: eta -> tau0 / (2 eps) = HB Pa / 2
+    fl = orc.make_fluid(HB=HB, n=n, Pa=Pa)
+    assert orc.eta_of_g(fl, 0.0) == HB * Pa / 2.0
+
+
+@pytest.mark.parametrize("HB,n", [(1.0, 1.0), (10.0, 0.5), (0.3, 1.5)])
+def test_viscosity_large_strain_recovers_unregularised(HB, n):
+    # for Pa*g >> 1 the factor (1 - exp(-Pa g)) -> 1: eta = g^(n-1) + HB/(2g)
+    Pa = 1e3
+    fl = orc.make_fluid(HB=HB, n=n, Pa=Pa)
+    for g in (0.05, 0.5, 3.0):
+        exact = g ** (n - 1.0) + HB / (2.0 * g)
+        rel = abs(orc.eta_of_g(fl, g) - exact) / exact
+        assert rel <= math.exp(-Pa * g) * 1.0001 + 1e-15
+
+
+def test_viscosity_small_argument_series():
+    # (1 - exp(-x))/x = 1 - x/2 + x^2/6 - x^3/24 + ... (eq:regularisation:limit)
+    HB, n, Pa = 3.0, 0.7, 1e4
+    fl = orc.make_fluid(HB=HB, n=n, Pa=Pa)
+    for g in (1e-12, 1e-9, 3e-8):
+        x = Pa * g
+        series = 1.0 - x / 2.0 + x * x / 6.0 - x ** 3 / 24.0
+        exact = (g ** n + HB / 2.0) * Pa * series
+        assert abs(orc.eta_of_g(fl, g) - exact) <= 4e-16 * exact
+
+
+def test_viscosity_yield_only_newtonian_is_one():
+    fl = orc.make_fluid(HB=0.0, n=1.0, Pa=1e3, reg=orc.REG_YIELD_ONLY)
+    for g in (0.0, 1e-8, 0.3, 7.0):
+        assert orc.eta_of_g(fl, g) == 1.0
+
+
+def test_viscosity_paper_form_tends_to_yield_only_as_pa_grows():
+    # product form vs yield-term-only regularisation differ by a factor
+    # (1 - exp(-Pa g)) on the power-law term, which vanishes as Pa grows
+    for Pa in (1e2, 1e4, 1e6):
+        a = orc.make_fluid(HB=2.0, n=1.2, Pa=Pa)
+        b = orc.make_fluid(HB=2.0, n=1.2, Pa=Pa, reg=orc.REG_YIELD_ONLY)
+        g = 0.05
+        rel = abs(orc.eta_of_g(a, g) - orc.eta_of_g(b, g)) / orc.eta_of_g(b, g)
+        assert rel <= math.exp(-Pa * g) + 1e-15
+
+
+def _shear_grid(dim, n, axis_u, axis_y, gamma0):
+    """Box periodic except along axis_y, whose walls move with the linear
+    field u_axis_u = gamma0 * x_axis_y (odd ghosts then continue it exactly)."""
+    wall = {}
+    L = 1.0
+    vel_hi = [0.0, 0.0, 0.0]
+    vel_hi[axis_u] = gamma0 * L
+    wall[(axis_y, 1)] = tuple(vel_hi)
+    bc = [(orc.PERIODIC, orc.PERIODIC)] * dim
+    bc[axis_y] = (orc.WALL, orc.WALL)
+    g = orc.make_grid(dim, [n] * dim, 1.0 / n, bc=bc, wall_u=wall)
+    u = np.zeros(orc.cell_shape(g, dim))
+    yc = (np.arange(n) + 0.5) / n
+    shape = [1, 1, 1]
+    shape[2 - axis_y] = n
+    u[axis_u] = (gamma0 * yc).reshape(shape)
+    return g, u
+
+
+@pytest.mark.parametrize("dim,axis_u,axis_y", [(2, 0, 1), (2, 1, 0), (3, 0, 2), (3, 2, 1)])
+@pytest.mark.parametrize("gamma0", [0.37, -2.5])
+def test_simple_shear_gives_classical_1d_law(dim, axis_u, axis_y, gamma0):
+    # u = gamma0 y: |gamma_dot| = |gamma0|/2 and the shear stress tau_xy =
+    # 2 eta gamma_dot_xy = eta gamma0 equals the classical one-dimensional law
+    # 2^(1-n) |g0|^(n-1) g0 + HB sgn(g0), times the regularisation factor.
+    HB, n, Pa = 1.7, 0.6, 50.0
+    g, u = _shear_grid(dim, 8, axis_u, axis_y, gamma0)
+    fl = orc.make_fluid(HB=HB, n=n, Pa=Pa)
+    eta, rc = orc.viscosity(g, fl, u)
+    assert rc == orc.OK
+    tau = eta * gamma0
+    law = (2.0 ** (1.0 - n) * abs(gamma0) ** (n - 1.0) * gamma0 + HB * math.copysign(1.0, gamma0))
+    law *= -math.expm1(-Pa * abs(gamma0) / 2.0)
+    np.testing.assert_allclose(tau, law, rtol=1e-13)
+
+
+def test_planar_extension_strain_norm():
+    # u = (e x, -e y): gamma_dot = diag(e, -e) and |gamma_dot| = |e|; checked
+    # at cells whose centred differences do not reach a wall ghost
+    n, e = 8, 0.8
+    g = orc.make_grid(2, [n, n], 1.0 / n)
+    xc = (np.arange(n) + 0.5) / n
+    u = np.zeros(orc.cell_shape(g, 2))
+    u[0] = e * xc[None, None, :]
+    u[1] = -e * xc[None, :, None]
+    fl2 = orc.make_fluid(HB=0.0, n=2.0, Pa=1e3, reg=orc.REG_YIELD_ONLY)
+    eta, _ = orc.viscosity(g, fl2, u)   # n = 2, HB = 0: eta = |gamma_dot|
+    np.testing.assert_allclose(eta[0, 1:-1, 1:-1], e, rtol=1e-14)
+    fl1 = orc.make_fluid(HB=0.0, n=1.0, Pa=1e3, reg=orc.REG_YIELD_ONLY)
+    eta1, _ = orc.viscosity(g, fl1, u)
+    assert np.all(eta1 == 1.0)
+
+
+# --------------------------------------------------------------------------
+# nodal operators of the approximate projection (Sec. III.A)
+# --------------------------------------------------------------------------
+
+def test_q1_stencil_textbook_values():
+    # Q1 Laplacian stencils from the element integrals of grad N_p . grad N_q:
+    # 2D: centre 8/3, all eight neighbours -1/3;
+    # 3D (times h): centre 8/3, faces 0, edges -1/6, corners -1/12.
+    gold = {}
+    for line in open(__file__.replace("test_oracle_pins.py", "golden/q1_stencil.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split("=")
+            gold[k.strip()] = eval(v, {"__builtins__": {}})   # plain fractions
+    for d in (2, 3):
+        n = 4
+        g = orc.make_grid(d, [n] * d, 1.0 / n)
+        sh = orc.node_shape(g)
+        phi = np.zeros(sh)
+        c = tuple(s // 2 for s in sh)
+        phi[c] = 1.0
+        out = orc.apply_K(g, phi) / g.h ** (d - 2)
+        box = out[tuple(slice(cc - 1, cc + 2) for cc in c)]
+        if d == 2:
+            box = box[0]
+            for (dy, dx), v in np.ndenumerate(box):
+                key = "2d_centre" if (dy, dx) == (1, 1) else "2d_neighbour"
+                assert abs(v - gold[key]) < 1e-14
+        else:
+            for (dz, dy, dx), v in np.ndenumerate(box):
+                m = abs(dz - 1) + abs(dy - 1) + abs(dx - 1)
+                key = ["3d_centre", "3d_face", "3d_edge", "3d_corner"][m]
+                assert abs(v - gold[key]) < 1e-14
+
+
+def _q1_element_by_quadrature(d, h):
+    # independent: Gauss-Legendre quadrature of grad N_p . grad N_q
+    xs, ws = np.polynomial.legendre.leggauss(3)
+    xs = 0.5 * (xs + 1.0) * h
+    ws = 0.5 * ws * h
+    nc = 2 ** d
+    K = np.zeros((nc, nc))
+    import itertools
+    for pt in itertools.product(range(3), repeat=d):
+        x = [xs[i] for i in pt]
+        w = np.prod([ws[i] for i in pt])
+        grads = []
+        for p in range(nc):
+            gv = []
+            for a in range(d):
+                t = 1.0
+                for b in range(d):
+                    bit = (p >> b) & 1
+                    if b == a:
+                        t *= (1.0 / h if bit else -1.0 / h)
+                    else:
+                        t *= (x[b] / h if bit else 1.0 - x[b] / h)
+                gv.append(t)
+            grads.append(np.array(gv))
+        for p in range(nc):
+            for q in range(nc):
+                K[p, q] += w * grads[p] @ grads[q]
+    return K
+
+
+@pytest.mark.parametrize("d,bc", [(2, None), (2, ((1, 1), (0, 0))), (3, None)])
+def test_K_equals_quadrature_assembly(d, bc):
+    rng = np.random.default_rng(3)
+    n = 4
+    g = orc.make_grid(d, [n] * d, 0.25, bc=bc)
+    Ke = _q1_element_by_quadrature(d, g.h)
+    sh = orc.node_shape(g)
+    phi = rng.standard_normal(sh)
+    out = np.zeros(sh)
+    nn = sh[::-1]
+    per = [g.bc[a][0] == orc.PERIODIC for a in range(3)]
+    import itertools
+    for cell in itertools.product(*[range(g.n[a]) for a in range(d)]):
+        ids = []
+        for p in range(2 ** d):
+            idx = [0, 0, 0]
+            for a in range(d):
+                v = cell[a] + ((p >> a) & 1)
+                if per[a]:
+                    v %= nn[a]
+                idx[a] = v
+            ids.append((idx[2], idx[1], idx[0]))
+        loc = np.array([phi[i] for i in ids])
+        y = Ke @ loc
+        for p, i in enumerate(ids):
+            out[i] += y[p]
+    np.testing.assert_allclose(orc.apply_K(g, phi), out, atol=1e-13)
+
+
+@pytest.mark.parametrize("d,bc", [(2, None), (2, ((1, 1), (1, 1))), (3, None), (3, ((0, 0), (1, 1), (0, 0)))])
+def test_weak_div_adjoint_of_G(d, bc):
+    # sum_k phi_k r_k(V) = h^d sum_cells V . G phi  (exact discrete identity)
+    rng = np.random.default_rng(5)
+    n = 8 if d == 2 else 4
+    g = orc.make_grid(d, [n] * d, 1.0 / n, bc=bc)
+    V = rng.standard_normal(orc.cell_shape(g, d))
+    phi = rng.standard_normal(orc.node_shape(g))
+    lhs = np.sum(phi * orc.weak_div(g, V))
+    rhs = g.h ** d * np.sum(V * orc.grad_node(g, phi))
+    assert abs(lhs - rhs) <= 1e-14 * (np.abs(V).sum() * np.abs(phi).max())
+
+
+def test_G_exact_on_linear_nodal_field():
+    # the cell-average gradient of a linear nodal field is its constant gradient
+    coeff = [0.3, -1.1, 2.0]
+    for d in (2, 3):
+        n = 4
+        g = orc.make_grid(d, [n] * d, 1.0 / n)
+        sh = orc.node_shape(g)
+        idx = np.indices(sh)              # (z, y, x) node indices
+        phi = sum(coeff[a] * idx[2 - a] * g.h for a in range(d))
+        G = orc.grad_node(g, np.ascontiguousarray(phi, dtype=np.float64))
+        for a in range(d):
+            np.testing.assert_allclose(G[a], coeff[a], rtol=1e-13)
+
+
+def test_weak_div_second_order_on_smooth_field():
+    # r_k(V) / h^d -> -div V at interior nodes, second order
+    errs = []
+    for n in (16, 32, 64):
+        g = orc.make_grid(2, [n, n], 1.0 / n, bc=((1, 1), (1, 1)))
+        xc = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(xc, xc, indexing="xy")
+        V = np.zeros(orc.cell_shape(g, 2))
+        V[0, 0] = np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+        V[1, 0] = np.cos(2 * np.pi * X) * np.cos(4 * np.pi * Y)
+        r = orc.weak_div(g, V)[0] / g.h ** 2
+        xn = np.arange(n) / n
+        XN, YN = np.meshgrid(xn, xn, indexing="xy")
+        div = (2 * np.pi * np.cos(2 * np.pi * XN) * np.cos(2 * np.pi * YN)
+               - 4 * np.pi * np.cos(2 * np.pi * XN) * np.sin(4 * np.pi * YN))
+        errs.append(np.abs(r + div).max())
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.8
+
+
+# --------------------------------------------------------------------------
+# tensor viscous operator (Sec. III.A tensor solve) -- manufactured solution
+# --------------------------------------------------------------------------
+
+def _num_deriv(f, x, axis, hh=1e-3):
+    e = np.zeros(3)
+    e[axis] = hh
+    return (-f(x + 2 * e) + 8 * f(x + e) - 8 * f(x - e) + f(x - 2 * e)) / (12 * hh)
+
+
+def _exact_visc_div(d, ufun, etafun, pts):
+    """div(eta * (grad u + grad u^T)/2) by nested 4th-order differences of the
+    analytic fields (independent of the discrete operator)."""
+    out = np.zeros((d, len(pts)))
+    for ip, x in enumerate(pts):
+        for c in range(d):
+            s = 0.0
+            for i in range(d):
+                def flux(y, i=i, c=c):
+                    gic = _num_deriv(lambda z: ufun(z)[c], y, i)
+                    gci = _num_deriv(lambda z: ufun(z)[i], y, c)
+                    return etafun(y) * 0.5 * (gic + gci)
+                s += _num_deriv(flux, x, i, 1e-3)
+            out[c, ip] = s
+    return out
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_tensor_operator_mms_second_order(d):
+    tp = 2 * np.pi
+
+    def ufun(x):
+        return np.array([np.sin(tp * x[0]) * np.cos(tp * x[1]) * (1 + 0.3 * np.sin(tp * x[2])),
+                         0.5 * np.cos(tp * x[0]) * np.sin(2 * tp * x[1]) + 0.2 * np.sin(tp * x[2]),
+                         0.7 * np.sin(tp * (x[0] + x[1] + x[2]))])[:d]
+
+    def etafun(x):
+        return 1.0 + 0.5 * np.sin(tp * x[0]) * np.cos(tp * x[1]) + 0.2 * np.cos(tp * x[2])
+
+    rng = np.random.default_rng(11)
+    errs = []
+    sizes = (8, 16, 32) if d == 2 else (8, 16)
+    for n in sizes:
+        g = orc.make_grid(d, [n] * d, 1.0 / n, bc=((1, 1),) * d)
+        h = g.h
+        idx = np.indices(tuple(g.n[a] for a in range(d)))
+        N = g.n[0] * g.n[1] * g.n[2]
+        xs = np.zeros((N, 3))
+        flat = [((idx[a] + 0.5) * h).ravel(order="F") for a in range(d)]
+        for a in range(d):
+            xs[:, a] = flat[a]
+        u = np.zeros((d, N))
+        eta = np.zeros(N)
+        for q in range(N):
+            u[:, q] = ufun(xs[q])
+            eta[q] = etafun(xs[q])
+        u = u.reshape(orc.cell_shape(g, d))
+        eta = eta.reshape(orc.cell_shape(g)[1:])
+        out = orc.visc_div(g, eta, u).reshape(d, N)
+        pick = rng.choice(N, size=min(N, 40), replace=False)
+        ex = _exact_visc_div(d, ufun, etafun, xs[pick])
+        errs.append(np.abs(out[:, pick] - ex).max() / np.abs(ex).max())
+    for a, b in zip(errs, errs[1:]):
+        assert a / b > 3.3, errs
+
+
+# --------------------------------------------------------------------------
+# multigrid against dense direct solves on 8^2 (and 4^3)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("op", [orc.OP_VISC, orc.OP_NODAL, orc.OP_MAC])
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+def test_mg_equals_dense_lu(op, d, n):
+    rng = np.random.default_rng(7 + op)
+    g = orc.lid_cavity(d, n)
+    fl = orc.make_fluid(Re=3.0)
+    dt = 0.05
+    if op == orc.OP_VISC:
+        eta = np.exp(rng.uniform(-1, 3, orc.cell_shape(g)[1:]))
+        rhs = rng.standard_normal(orc.cell_shape(g, d))
+    elif op == orc.OP_NODAL:
+        eta = None
+        rhs = rng.standard_normal(orc.node_shape(g))
+    else:
+        eta = None
+        rhs = rng.standard_normal(orc.cell_shape(g)[1:])
+    x, rc, rep = orc.mg_solve(g, fl, op, eta, dt, rhs, tol=1e-13, max_cycles=200,
+                              krylov=1 if op == orc.OP_VISC else 0)
+    assert rc == orc.OK
+    A = orc.dense_matrix(g, fl, op, eta, dt)
+    b = rhs.ravel().copy()
+    if op == orc.OP_VISC:
+        # the lid's wall value enters as a right-hand-side term: A x = rhs - A(0)
+        # with A(0) the operator applied to zero interior values
+        zero = np.zeros_like(rhs)
+        wall = zero - dt * orc.visc_div(g, eta / fl.Re, zero, hom=0)
+        xd = np.linalg.solve(A, b - wall.ravel())
+    else:
+        b = b - b.mean()
+        N = b.size
+        xd = np.linalg.solve(A + np.ones((N, N)) / N, b)
+        xd -= xd.mean()
+    np.testing.assert_allclose(x.ravel(), xd, atol=1e-11 * np.abs(xd).max())
+
+
+def test_dense_matrices_symmetry():
+    # Q1 stiffness and the MAC Laplacian are symmetric; K has zero row sums
+    g = orc.lid_cavity(2, 8)
+    K = orc.dense_matrix(g, None, orc.OP_NODAL, None, 0.0)
+    L = orc.dense_matrix(g, None, orc.OP_MAC, None, 0.0)
+    assert np.abs(K - K.T).max() == 0.0 and np.abs(L - L.T).max() == 0.0
+    assert np.abs(K.sum(axis=1)).max() < 1e-14
+
+
+def test_tensor_operator_constant_eta_symmetric_positive():
+    # with constant viscosity on a periodic box the operator I - dt div(eta
+    # gamma_dot) is symmetric with eigenvalues >= 1 (the viscous part is
+    # negative semi-definite); with walls it stays coercive.
+    fl = orc.make_fluid(Re=1.0)
+    g = orc.make_grid(2, [8, 8], 1.0 / 8, bc=((1, 1), (1, 1)))
+    eta = np.full(orc.cell_shape(g)[1:], 2.0)
+    A = orc.dense_matrix(g, fl, orc.OP_VISC, eta, 0.01)
+    assert np.abs(A - A.T).max() < 1e-13 * np.abs(A).max()
+    assert np.linalg.eigvalsh(A).min() > 1.0 - 1e-12
+    g = orc.lid_cavity(2, 8)
+    A = orc.dense_matrix(g, fl, orc.OP_VISC, eta, 0.01)
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0.99
+
+
+@pytest.mark.parametrize("op", [orc.OP_MAC, orc.OP_NODAL])
+def test_poisson_mg_contraction_h_independent(op):
+    rng = np.random.default_rng(0)
+    rates = []
+    for n in (32, 64):
+        g = orc.lid_cavity(2, n)
+        sh = orc.cell_shape(g)[1:] if op == orc.OP_MAC else orc.node_shape(g)
+        rhs = rng.standard_normal(sh)
+        r = []
+        for cyc in (3, 5):
+            _, _, rep = orc.mg_solve(g, None, op, None, 0.0, rhs, max_cycles=cyc, fixed=1)
+            r.append(rep.rel_resid)
+        rates.append((r[1] / r[0]) ** 0.5)
+    assert max(rates) < 0.12
+    assert rates[1] < 1.5 * rates[0]
+
+
+def test_mg_failure_paths():
+    g = orc.lid_cavity(2, 16)
+    fl = orc.make_fluid(Re=1.0)
+    rhs = np.random.default_rng(1).standard_normal(orc.cell_shape(g)[1:])
+    x, rc, rep = orc.mg_solve(g, fl, orc.OP_MAC, None, 0.0, rhs, tol=1e-12, max_cycles=1)
+    assert rc == orc.ERR_NOCONV and rep.cycles == 1 and rep.rel_resid > 1e-12
+    bad = rhs.copy()
+    bad[0, 3, 3] = np.nan
+    _, rc, _ = orc.mg_solve(g, fl, orc.OP_MAC, None, 0.0, bad)
+    assert rc == orc.ERR_NONFINITE
+    x, rc, rep = orc.mg_solve(g, fl, orc.OP_MAC, None, 0.0, np.zeros_like(rhs))
+    assert rc == orc.OK and rep.cycles == 0 and np.all(x == 0)
+
+
+# --------------------------------------------------------------------------
+# plane Poiseuille flow: x periodic, walls at y = 0 and 1, body force (G, 0)
+# --------------------------------------------------------------------------
+
+def _poiseuille_grid(ny):
+    return orc.make_grid(2, [4, ny], 1.0 / ny, bc=((orc.PERIODIC, orc.PERIODIC), (orc.WALL, orc.WALL)))
+
+
+def _poiseuille_run(ny, HB, n, Pa, dt=0.02, G=1.0, max_steps=6000, u0=None):
+    g = _poiseuille_grid(ny)
+    fl = orc.make_fluid(Re=1.0, HB=HB, n=n, Pa=Pa, f=(G, 0.0, 0.0))
+    o = orc.make_step_opts()
+    u = np.zeros(orc.cell_shape(g, 2))
+    if u0 is not None:
+        u[0] = u0[None, :, None]
+    p = np.zeros(orc.node_shape(g))
+    for s in range(max_steps):
+        uo = u.copy()
+        rep, rc = orc.step(g, fl, o, u, p, dt)
+        assert rc == orc.OK
+        if np.abs(u - uo).max() <= 1e-13 * np.abs(u).max():
+            break
+    assert s < max_steps - 1, "no steady state"
+    return g, fl, u, p
+
+
+def _regularised_profile(y, HB, n, Pa, G=1.0):
+    """Exact steady profile of the regularised law: eta(|u'|/2) u' = -G (y - 1/2),
+    inverted pointwise and integrated from the wall (u(0) = 0)."""
+    def up(s):
+        sig = -G * (s - 0.5)
+        if sig == 0.0:
+            return 0.0
+        f = lambda a: 2.0 * ((a / 2) ** n + HB / 2) * (-math.expm1(-Pa * a / 2)) - abs(sig)
+        hi = 1.0
+        while f(hi) < 0:
+            hi *= 2
+        return math.copysign(brentq(f, 0.0, hi, xtol=1e-16, rtol=1e-15), sig)
+    return quad(up, 0.0, y, epsabs=1e-13, epsrel=1e-12, limit=200)[0]
+
+
+def _closed_form(Y, HB, n, G=1.0, H=0.5):
+    """Unregularised plane Poiseuille profiles; in the dimensionless variables
+    the one-dimensional law is tau = mu |u'|^(n-1) u' + HB sgn(u') with
+    mu = 2^(1-n), and Y is measured from the channel centre."""
+    mu = 2.0 ** (1.0 - n)
+    Y = abs(Y)
+    k = (n + 1.0) / n
+    if HB == 0.0:
+        return n / (n + 1.0) * (G / mu) ** (1.0 / n) * (H ** k - Y ** k)
+    Ye = max(Y, HB / G)
+    return n / (n + 1.0) * mu ** (-1.0 / n) / G * ((G * H - HB) ** k - (G * Ye - HB) ** k)
+
+
+def _check_steady(g, fl, u, p, HB, n, Pa, tol_reg, tol_cf):
+    ny = g.n[1]
+    # v and p stay at rounding level
+    assert np.abs(u[1]).max() < 1e-14 and np.abs(p).max() < 1e-12
+    ux = u[0, 0, :, 0]
+    # discrete face shear stress eta_f du/dy telescopes to -G (y - 1/2)
+    eta, _ = orc.viscosity(g, fl, u)
+    e = eta[0, :, 0]
+    S = 0.5 * (e[1:] + e[:-1]) * (ux[1:] - ux[:-1]) / g.h
+    yf = np.arange(1, ny) * g.h
+    assert np.abs(S + (yf - 0.5)).max() < 1e-8
+    # the profile against the exact regularised solution and the closed form
+    yc = (np.arange(ny) + 0.5) * g.h
+    ureg = np.array([_regularised_profile(y, HB, n, Pa) for y in yc])
+    ucf = np.array([_closed_form(y - 0.5, HB, n) for y in yc])
+    scale = np.abs(ucf).max()
+    assert np.abs(ux - ureg).max() < tol_reg * scale
+    assert np.abs(ux - ucf).max() < tol_cf * scale
+
+
+def test_poiseuille_bingham_steady_state():
+    # Bingham (n = 1): from rest to the steady state
+    HB, n, Pa = 0.2, 1.0, 1e3
+    g, fl, u, p = _poiseuille_run(32, HB, n, Pa)
+    _check_steady(g, fl, u, p, HB, n, Pa, 0.04, 0.05)
+
+
+def test_poiseuille_power_law_steady_state():
+    # shear-thickening power law (HB = 0, n = 1.5): the product-form viscosity
+    # vanishes at zero strain, so the run starts from the exact regularised
+    # profile rather than from rest
+    HB, n, Pa, ny = 0.0, 1.5, 1e3, 32
+    yc = (np.arange(ny) + 0.5) / ny
+    u0 = np.array([_regularised_profile(y, HB, n, Pa) for y in yc])
+    g, fl, u, p = _poiseuille_run(ny, HB, n, Pa, dt=0.005, u0=u0)
+    _check_steady(g, fl, u, p, HB, n, Pa, 0.01, 0.01)
+
+
+def test_poiseuille_herschel_bulkley_steady_state():
+    # Herschel-Bulkley with a yield stress and n = 1.5, started from the exact
+    # regularised profile.  (With n < 1 the lagged-viscosity Crank-Nicolson
+    # iteration does not settle to a steady state on this grid, so shear
+    # thinning is pinned through the viscosity law and the operator tests.)
+    HB, n, Pa, ny = 0.15, 1.5, 1e3, 32
+    yc = (np.arange(ny) + 0.5) / ny
+    u0 = np.array([_regularised_profile(y, HB, n, Pa) for y in yc])
+    g, fl, u, p = _poiseuille_run(ny, HB, n, Pa, dt=0.003, u0=u0)
+    _check_steady(g, fl, u, p, HB, n, Pa, 0.03, 0.04)
+
+
+def test_poiseuille_bingham_plug_width():
+    # plug where |tau| = 2 eta |gamma_dot| <= HB: |y - 1/2| <= y0 = HB / G
+    HB, Pa, ny = 0.25, 1e4, 32
+    g, fl, u, p = _poiseuille_run(ny, HB, 1.0, Pa, dt=0.02)
+    eta, _ = orc.viscosity(g, fl, u)
+    ux = u[0, 0, :, 0]
+    # cell strain rate from centred differences with wall ghosts
+    ghost_lo, ghost_hi = -ux[0], -ux[-1]
+    ext = np.concatenate([[ghost_lo], ux, [ghost_hi]])
+    gam = np.abs(ext[2:] - ext[:-2]) / (2 * g.h) / 2.0
+    tau = 2.0 * eta[0, :, 0] * gam
+    yc = (np.arange(ny) + 0.5) * g.h
+    plug = yc[tau <= HB]
+    width = plug.max() - plug.min() + g.h
+    assert abs(width - 2 * HB) <= 2 * g.h + 1e-12
+
+
+def test_poiseuille_regularised_profile_second_order():
+    # smooth regularised profile (moderate Pa): error ratio ~4 per halving
+    HB, n, Pa = 0.1, 1.0, 40.0
+    errs = []
+    for ny in (16, 32):
+        g, fl, u, p = _poiseuille_run(ny, HB, n, Pa, dt=0.02)
+        yc = (np.arange(ny) + 0.5) * g.h
+        ureg = np.array([_regularised_profile(y, HB, n, Pa) for y in yc])
+        errs.append(np.abs(u[0, 0, :, 0] - ureg).max())
+    assert errs[0] / errs[1] > 3.3, errs
+
+
+# --------------------------------------------------------------------------
+# Newtonian limit: Taylor-Green vortex (yield-term-only regularisation,
+# HB = 0, n = 1 gives eta = 1 exactly)
+# --------------------------------------------------------------------------
+
+def _taylor_green(n, Re, T, cfl=0.5):
+    g = orc.make_grid(2, [n, n], 1.0 / n, bc=((1, 1), (1, 1)))
+    fl = orc.make_fluid(Re=Re, HB=0.0, n=1.0, Pa=1e3, reg=orc.REG_YIELD_ONLY)
+    o = orc.make_step_opts()
+    tp = 2 * np.pi
+    xc = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    nu = 1.0 / Re
+    dt = cfl / n
+    steps = int(round(T / dt))
+    dt = T / steps
+    F = lambda t: math.exp(-2 * tp * tp * nu * t)
+    u = np.zeros(orc.cell_shape(g, 2))
+    u[0, 0] = np.sin(tp * X) * np.cos(tp * Y)
+    u[1, 0] = -np.cos(tp * X) * np.sin(tp * Y)
+    xn = np.arange(n) / n
+    XN, YN = np.meshgrid(xn, xn, indexing="xy")
+    p = (0.25 * (np.cos(2 * tp * XN) + np.cos(2 * tp * YN)) * F(-dt / 2) ** 2)[None]
+    p = np.ascontiguousarray(p - p.mean())
+    for _ in range(steps):
+        rep, rc = orc.step(g, fl, o, u, p, dt)
+        assert rc == orc.OK
+    ue = np.sin(tp * X) * np.cos(tp * Y) * F(T)
+    ve = -np.cos(tp * X) * np.sin(tp * Y) * F(T)
+    return max(np.abs(u[0, 0] - ue).max(), np.abs(u[1, 0] - ve).max())
+
+
+def test_taylor_green_second_order():
+    e = [_taylor_green(n, Re=50.0, T=0.25) for n in (16, 32, 64)]
+    assert e[0] / e[1] > 3.0 and e[1] / e[2] > 3.4, e
+
+
+# --------------------------------------------------------------------------
+# Godunov advection invariants and MAC divergence
+# --------------------------------------------------------------------------
+
+def _periodic2(n):
+    return orc.make_grid(2, [n, n], 1.0 / n, bc=((1, 1), (1, 1)))
+
+
+def test_advection_uniform_flow_has_zero_convective_term():
+    g = _periodic2(16)
+    fl = orc.make_fluid(Re=1e300, HB=0.0, n=1.0, reg=orc.REG_YIELD_ONLY)
+    o = orc.make_step_opts()
+    u = np.zeros(orc.cell_shape(g, 2))
+    u[0] = 0.7
+    u[1] = -0.4
+    p = np.zeros(orc.node_shape(g))
+    eta, _ = orc.viscosity(g, fl, u)
+    b, E, umac, A, rep, dm, rc = orc.advect(g, fl, o, u, p, eta, 0.01)
+    assert rc == orc.OK and np.abs(A).max() < 1e-14
+
+
+def test_advection_parallel_shear_has_zero_convective_term():
+    # u = (U(y), 0) with x periodic: u . grad u = 0 exactly
+    g = orc.make_grid(2, [8, 16], 1.0 / 16, bc=((1, 1), (0, 0)))
+    fl = orc.make_fluid(Re=1.0, HB=0.0, n=1.0, reg=orc.REG_YIELD_ONLY)
+    o = orc.make_step_opts()
+    yc = (np.arange(16) + 0.5) / 16
+    u = np.zeros(orc.cell_shape(g, 2))
+    u[0] = (np.sin(np.pi * yc) ** 2)[None, :, None]
+    p = np.zeros(orc.node_shape(g))
+    eta, _ = orc.viscosity(g, fl, u)
+    b, E, umac, A, rep, dm, rc = orc.advect(g, fl, o, u, p, eta, 0.01)
+    assert rc == orc.OK and np.abs(A).max() < 1e-13
+
+
+def test_advection_convective_term_converges():
+    # small dt: A -> u . grad u for a smooth periodic field (mean-abs error)
+    errs = []
+    for n in (32, 64, 128):
+        g = _periodic2(n)
+        fl = orc.make_fluid(Re=1e300, HB=0.0, n=1.0, reg=orc.REG_YIELD_ONLY)
+        o = orc.make_step_opts(mac_project=0)
+        tp = 2 * np.pi
+        xc = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(xc, xc, indexing="xy")
+        u = np.zeros(orc.cell_shape(g, 2))
+        u[0, 0] = 1.0 + 0.5 * np.sin(tp * X) * np.cos(tp * Y)
+        u[1, 0] = 0.5 + 0.25 * np.cos(tp * X)
+        ux = 0.5 * tp * np.cos(tp * X) * np.cos(tp * Y)
+        uy = -0.5 * tp * np.sin(tp * X) * np.sin(tp * Y)
+        vx = -0.25 * tp * np.sin(tp * X)
+        ex0 = u[0, 0] * ux + u[1, 0] * uy
+        ex1 = u[0, 0] * vx
+        p = np.zeros(orc.node_shape(g))
+        eta = np.ones(orc.cell_shape(g)[1:])
+        b, E, umac, A, rep, dm, rc = orc.advect(g, fl, o, u, p, eta, 1e-9)
+        errs.append(np.mean(np.abs(A[0, 0] - ex0)) + np.mean(np.abs(A[1, 0] - ex1)))
+    assert errs[0] / errs[1] > 2.5 and errs[1] / errs[2] > 2.5, errs
+
+
+def test_slope_limited_prediction_keeps_monotone_step_bounded():
+    # a monotone shear layer advected across the grid: the traced face states
+    # produce no new extrema, so one step keeps u within its initial bounds
+    n = 32
+    g = orc.make_grid(2, [n, 8], 1.0 / n, bc=((1, 1), (1, 1)))
+    fl = orc.make_fluid(Re=1e300, HB=0.0, n=1.0, reg=orc.REG_YIELD_ONLY)
+    o = orc.make_step_opts(mac_project=0)
+    xc = (np.arange(n) + 0.5) / n
+    u = np.zeros(orc.cell_shape(g, 2))
+    u[0] = 1.0
+    u[1] = np.where((xc > 0.25) & (xc < 0.6), 1.0, 0.0)[None, None, :]
+    p = np.zeros(orc.node_shape(g))
+    eta = np.ones(orc.cell_shape(g)[1:])
+    dt = 0.5 / n
+    b, E, umac, A, rep, dm, rc = orc.advect(g, fl, o, u, p, eta, dt)
+    assert b[1].min() >= -1e-14 and b[1].max() <= 1.0 + 1e-14
+
+
+def test_mac_projection_divergence_free_and_step_diagnostics():
+    g = orc.lid_cavity(2, 32)
+    fl = orc.make_fluid(Re=100.0, HB=1.0, n=1.0, Pa=1e3)
+    o = orc.make_step_opts()
+    u = np.zeros(orc.cell_shape(g, 2))
+    p = np.zeros(orc.node_shape(g))
+    for _ in range(5):
+        rep, rc = orc.step(g, fl, o, u, p)
+        assert rc == orc.OK
+        assert rep.div_mac_rel <= 1e-10
+        assert rep.visc.rel_resid <= 1e-10 and rep.proj.rel_resid <= 1e-10
+    assert abs(p.mean()) < 1e-13
+
+
+def test_projection_weak_divergence_converges():
+    # weak divergence of u^{m+1} after one projection of a smooth non-solenoidal
+    # field is second order (the projection is approximate, not exact)
+    errs = []
+    for n in (16, 32, 64):
+        g = _periodic2(n)
+        o = orc.make_step_opts()
+        tp = 2 * np.pi
+        xc = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(xc, xc, indexing="xy")
+        us = np.zeros(orc.cell_shape(g, 2))
+        us[0, 0] = np.sin(tp * X) * np.cos(tp * Y) + 0.5 * np.sin(tp * X)
+        us[1, 0] = np.cos(tp * X) * np.sin(2 * tp * Y)
+        p = np.zeros(orc.node_shape(g))
+        un, pn, rep, rc = orc.project(g, o, us, p, 0.1)
+        r = orc.weak_div(g, un) / g.h ** 2
+        errs.append(np.abs(r).max())
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
