@@ -108,6 +108,8 @@ int orc_mg_solve(const orc_grid* g, const orc_fluid* fl, int op, const double* e
 int orc_dense_matrix(const orc_grid* g, const orc_fluid* fl, int op, const double* eta,
                      double dt, double* A);
 int orc_dense_solve(int N, double* A, double* b);  /* LU, partial pivoting, in place */
+/* Diagonal used by the tensor Gauss-Seidel smoother ([dim][cells]). */
+int orc_tensor_diagonal(const orc_grid* g, const orc_fluid* fl, const double* eta, double dt, double* out);
 
 /* ---- the step ------------------------------------------------------------ */
 double orc_cfl_dt(const orc_grid* g, double cfl, const double* u);

@@ -97,6 +97,7 @@ def lib():
                                    P(MGOpts), P(MGReport)]
         L.orc_dense_matrix.argtypes = [P(Grid), P(Fluid), C.c_int, dp, C.c_double, dp]
         L.orc_dense_solve.argtypes = [C.c_int, dp, dp]
+        L.orc_tensor_diagonal.argtypes = [P(Grid), P(Fluid), dp, C.c_double, dp]
         L.orc_cfl_dt.restype = C.c_double
         L.orc_cfl_dt.argtypes = [P(Grid), C.c_double, dp]
         L.orc_advect.argtypes = [P(Grid), P(Fluid), P(StepOpts), dp, dp, dp, C.c_double,
@@ -259,6 +260,13 @@ def dense_matrix(g, fl, op, eta, dt):
     lib().orc_dense_matrix(C.byref(g), C.byref(fl) if fl is not None else None, op, _p(e),
                            float(dt), _p(A))
     return A
+
+
+def tensor_diagonal(g, fl, eta, dt):
+    eta = np.ascontiguousarray(eta, dtype=np.float64)
+    out = np.zeros(cell_shape(g, g.dim), dtype=np.float64)
+    lib().orc_tensor_diagonal(C.byref(g), C.byref(fl), _p(eta), float(dt), _p(out))
+    return out
 
 
 def cfl_dt(g, cfl, u):

@@ -607,3 +607,21 @@ int orc_dense_matrix(const orc_grid* g, const orc_fluid* fl, int op, const doubl
     free(L->beta);
     return ORC_OK;
 }
+
+/* Diagonal the tensor smoother divides by, for every component and cell. */
+int orc_tensor_diagonal(const orc_grid* g, const orc_fluid* fl, const double* eta, double dt, double* out)
+{
+    const long N = ncells(g);
+    double* eta_e = (double*)xcalloc(N, sizeof(double));
+    double* beta = (double*)xcalloc(nface_total(g), sizeof(double));
+    for (long i = 0; i < N; ++i) eta_e[i] = eta[i] / fl->Re;
+    orc_eta_faces(g, eta_e, beta);
+    for (int c = 0; c < g->dim; ++c)
+        for (int k = 0; k < g->n[2]; ++k)
+            for (int j = 0; j < g->n[1]; ++j)
+                for (int i = 0; i < g->n[0]; ++i)
+                    out[(long)c * N + cid(g, i, j, k)] = orc_tensor_diag(g, beta, dt, c, i, j, k);
+    free(eta_e);
+    free(beta);
+    return ORC_OK;
+}

@@ -389,6 +389,17 @@ def test_tensor_operator_constant_eta_symmetric_positive():
     assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0.99
 
 
+@pytest.mark.parametrize("d,bc", [(2, None), (2, ((1, 1), (0, 0))), (3, None)])
+def test_smoother_diagonal_is_operator_diagonal(d, bc):
+    rng = np.random.default_rng(9)
+    n = 8 if d == 2 else 4
+    g = orc.make_grid(d, [n] * d, 1.0 / n, bc=bc, wall_u={(d - 1, 1): (1.0, 0.0, 0.0)})
+    fl = orc.make_fluid(Re=2.0)
+    eta = np.exp(rng.uniform(-1, 3, orc.cell_shape(g)[1:]))
+    A = orc.dense_matrix(g, fl, orc.OP_VISC, eta, 0.03)
+    np.testing.assert_allclose(orc.tensor_diagonal(g, fl, eta, 0.03).ravel(), np.diag(A), rtol=1e-14)
+
+
 @pytest.mark.parametrize("op", [orc.OP_MAC, orc.OP_NODAL])
 def test_poisson_mg_contraction_h_independent(op):
     rng = np.random.default_rng(0)
@@ -700,3 +711,96 @@ def test_projection_weak_divergence_converges():
         r = orc.weak_div(g, un) / g.h ** 2
         errs.append(np.abs(r).max())
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+# --------------------------------------------------------------------------
+# symmetry of the whole advection stage: mirror and axis exchange
+# --------------------------------------------------------------------------
+
+def _mirror_case(d, axis):
+    """Cavity with walls and a lid; returns (g, gm, u, um, p, pm, flip) where
+    the 'm' objects are the mirror images across the mid-plane normal to axis."""
+    rng = np.random.default_rng(21 + axis)
+    n = 16 if d == 2 else 8
+    lid_axis = d - 1
+    g = orc.make_grid(d, [n] * d, 1.0 / n, wall_u={(lid_axis, 1): (1.0, 0.3, -0.2)[:d] + (0.0,) * (3 - d)})
+    wm = {}
+    for a in range(d):
+        for s in range(2):
+            vel = [g.wall_u[a][s][c] for c in range(3)]
+            if any(vel):
+                vel[axis] = -vel[axis]
+                side = 1 - s if a == axis else s
+                wm[(a, side)] = tuple(vel)
+    gm = orc.make_grid(d, [n] * d, 1.0 / n, wall_u=wm)
+    u = rng.standard_normal(orc.cell_shape(g, d)) * 0.3
+    p = rng.standard_normal(orc.node_shape(g))
+    ax_np = 3 - 1 - axis      # numpy axis of a (z, y, x) field
+    um = np.flip(u, axis=1 + ax_np).copy()
+    um[axis] *= -1.0
+    pm = np.flip(p, axis=ax_np).copy()
+    return g, gm, u, um, p, pm
+
+
+@pytest.mark.parametrize("d,axis", [(2, 0), (2, 1), (3, 0), (3, 2)])
+def test_advection_mirror_equivariance(d, axis):
+    # reflecting the domain maps left traced states to right ones; the step's
+    # advection stage (slopes, traced and transverse states, Riemann problems,
+    # MAC projection, upwinding) must commute with the reflection
+    g, gm, u, um, p, pm = _mirror_case(d, axis)
+    fl = orc.make_fluid(Re=50.0, HB=1.0, n=0.8, Pa=100.0)
+    o = orc.make_step_opts()
+    dt = 0.4 / g.n[0]
+    eta, _ = orc.viscosity(g, fl, u)
+    etam, _ = orc.viscosity(gm, fl, um)
+    ax_np = 2 - axis
+    np.testing.assert_allclose(etam, np.flip(eta, axis=ax_np), rtol=1e-13)
+    b = orc.advect(g, fl, o, u, p, eta, dt)[0]
+    bm = orc.advect(gm, fl, o, um, pm, etam, dt)[0]
+    ref = np.flip(b, axis=1 + ax_np).copy()
+    ref[axis] *= -1.0
+    np.testing.assert_allclose(bm, ref, atol=1e-11 * np.abs(b).max())
+
+
+def test_advection_axis_exchange_equivariance():
+    # exchanging x and y (and the velocity components) commutes with the stage
+    rng = np.random.default_rng(4)
+    n = 16
+    g = orc.make_grid(2, [n, n], 1.0 / n, wall_u={(1, 1): (1.0, 0.0, 0.0)})
+    gt = orc.make_grid(2, [n, n], 1.0 / n, wall_u={(0, 1): (0.0, 1.0, 0.0)})
+    u = rng.standard_normal(orc.cell_shape(g, 2)) * 0.3
+    p = rng.standard_normal(orc.node_shape(g))
+    ut = np.ascontiguousarray(np.swapaxes(u[::-1], 2, 3))
+    pt = np.ascontiguousarray(np.swapaxes(p, 1, 2))
+    fl = orc.make_fluid(Re=50.0, HB=1.0, n=0.8, Pa=100.0)
+    o = orc.make_step_opts()
+    eta, _ = orc.viscosity(g, fl, u)
+    etat, _ = orc.viscosity(gt, fl, ut)
+    b = orc.advect(g, fl, o, u, p, eta, 0.02)[0]
+    bt = orc.advect(gt, fl, o, ut, pt, etat, 0.02)[0]
+    np.testing.assert_allclose(bt, np.swapaxes(b[::-1], 2, 3), atol=1e-11 * np.abs(b).max())
+
+
+def test_advection_translation_third_order_local_error():
+    # a small perturbation on a uniform stream is translated by (U, V) dt;
+    # the unsplit second-order predictor has a local error O(h^3) at fixed CFL
+    def run(n, U0=-0.8, V0=-0.5, eps=1e-6):
+        g = _periodic2(n)
+        fl = orc.make_fluid(Re=1e300, HB=0.0, n=1.0, reg=orc.REG_YIELD_ONLY)
+        o = orc.make_step_opts(mac_project=0)
+        tp = 2 * np.pi
+        xc = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(xc, xc, indexing="xy")
+        dt = 0.5 / n
+        f = lambda x, y: np.sin(tp * x) * np.cos(tp * y) + 0.5 * np.cos(tp * (x + 2 * y))
+        u = np.zeros(orc.cell_shape(g, 2))
+        u[0, 0] = U0 + eps * f(X, Y)
+        u[1, 0] = V0 + eps * 0.7 * f(X + 0.3, Y)
+        p = np.zeros(orc.node_shape(g))
+        eta = np.ones(orc.cell_shape(g)[1:])
+        b = orc.advect(g, fl, o, u, p, eta, dt)[0]
+        ex0 = U0 + eps * f(X - U0 * dt, Y - V0 * dt)
+        ex1 = V0 + eps * 0.7 * f(X + 0.3 - U0 * dt, Y - V0 * dt)
+        return (np.mean(np.abs(b[0, 0] - ex0)) + np.mean(np.abs(b[1, 0] - ex1))) / eps
+    e = [run(n) for n in (32, 64, 128)]
+    assert e[0] / e[1] > 6.5 and e[1] / e[2] > 6.5, e
