@@ -1,0 +1,178 @@
+/*
+ * hb.h -- C ABI of the MI355X (gfx950) library for one semi-implicit time
+ * step of the Papanastasiou-regularised Herschel-Bulkley incompressible flow
+ * solver of Sverdrup, Nikiforakis & Almgren, arXiv 1803.00417.
+ *
+ * The step (Sec. III.A) on one uniform level of a structured grid:
+ *   1. strain rate and regularised apparent viscosity
+ *      (eq:rheology:papanastasiou in the dimensionless form
+ *       eq:dimensionless:herschel-bulkley, Sec. IV);
+ *   2. second-order Godunov prediction of face states at t^{m+1/2}
+ *      (Taylor extrapolation with Colella's limited slopes, transverse terms,
+ *       eq:iamr:extrap) and upwinding by a projected face velocity;
+ *   3. the coupled tensor viscous (Helmholtz) solve with the lagged viscosity
+ *      eta^m (Crank-Nicolson);
+ *   4. the approximate nodal projection and pressure update.
+ * Both solves use geometric multigrid V-cycles run by HIP kernels.
+ *
+ * Memory.  Every array argument is caller-owned DEVICE memory (e.g. a torch
+ * CUDA/HIP tensor), contiguous FP64, x fastest, without ghost cells:
+ *   cell field with C components : [C][nz][ny][nx]      (nz = 1 in 2D)
+ *   nodal field                  : [nnz][nny][nnx], nn_a = n_a + 1 on wall
+ *                                  axes, n_a on periodic axes, 1 on unused axes
+ *   face fields (umac)           : one array per axis, concatenated; the
+ *                                  array of axis a has n_a + 1 (wall) or n_a
+ *                                  (periodic) faces along a and n_b cells
+ *                                  along the other axes.
+ * The library owns only the scratch it allocates in hb_create (multigrid
+ * hierarchies, face arrays, reduction buffers); it never allocates afterwards
+ * and never frees caller memory.
+ *
+ * Streams.  Work runs asynchronously on the hipStream_t given to hb_create
+ * (NULL = the default stream).  A call that fills a report, or that must
+ * choose dt from the CFL condition or decide multigrid convergence, reads
+ * scalars back and therefore synchronises the stream before returning.
+ *
+ * Errors.  Functions return HB_OK or a negative code; nothing throws or
+ * aborts across the ABI.  Arguments are checked before any device work.
+ * hb_last_error gives a message for the last failing call on a context (or,
+ * with ctx == NULL, for the last failing hb_create on this thread).
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HB_OK = 0,
+    HB_ERR_ARG = -1,        /* invalid argument; nothing was launched */
+    HB_ERR_DEVICE = -2,     /* a HIP call failed */
+    HB_ERR_NOCONV = -3,     /* a solve hit max_cycles; outputs hold the last iterate */
+    HB_ERR_NONFINITE = -4,  /* NaN/Inf in an input or produced by a solve */
+    HB_ERR_OOM = -5         /* device allocation failed in hb_create */
+};
+
+enum { HB_BC_WALL = 0, HB_BC_PERIODIC = 1 };
+
+/* Regularisation: PAPER multiplies the whole apparent viscosity by
+ * (1 - exp(-Pa |gamma_dot|)) as printed (eq:rheology:papanastasiou);
+ * YIELD_ONLY applies the factor to the yield-stress term only (needs n >= 1),
+ * which gives exactly eta = 1 for HB = 0, n = 1 (the Newtonian limit). */
+enum { HB_REG_PAPER = 0, HB_REG_YIELD_ONLY = 1 };
+
+enum { HB_OP_VISC = 0, HB_OP_NODAL = 1, HB_OP_MAC = 2 };
+
+enum { HB_PREC_FP64 = 0, HB_PREC_MIXED = 1 };
+
+/* Grid: n[a] cells per axis (n[2] = 1 when dim = 2), uniform spacing h.
+ * Each n[a] (a < dim) must be c * 2^k with c in {1, 2, 3} and n[a] >= 4.
+ * bc[a][side]: HB_BC_WALL or HB_BC_PERIODIC; periodic faces come in pairs.
+ * wall_u[a][side][c]: velocity of a wall face (lid), component c. */
+typedef struct {
+    int32_t dim;
+    int32_t n[3];
+    double h;
+    int32_t bc[3][2];
+    double wall_u[3][2][3];
+} hb_grid;
+
+/* Fluid: dimensionless groups Re, HB (Herschel-Bulkley number), n (flow
+ * index), Pa (Papanastasiou number) of Sec. IV; constant body force f. */
+typedef struct {
+    double Re, HB, n, Pa;
+    int32_t reg;
+    double f[3];
+} hb_fluid;
+
+/* Multigrid options.  A solve stops when |b - A x|_inf <= tol_rel |b|_inf
+ * (checked before the first cycle and after each); fixed_cycles = 1 runs
+ * exactly max_cycles V-cycles.  krylov = 1 wraps the V-cycle in BiCGStab
+ * (one V-cycle per preconditioner application).  precision selects FP64 or
+ * mixed FP32-smoothing / FP64-residual cycles. */
+typedef struct {
+    double tol_rel;
+    int32_t max_cycles, fixed_cycles, nu1, nu2, krylov, precision;
+} hb_mg_opts;
+
+typedef struct {
+    int32_t cycles;      /* V-cycles run */
+    double rel_resid;    /* |b - A x|_inf / |b|_inf at exit */
+    double bnorm;        /* |b|_inf of the system solved */
+} hb_mg_report;
+
+typedef struct {
+    double cfl;          /* dt = cfl h / max(U_wall, max |u|) when dt <= 0 */
+    int32_t mac_project; /* 1: project the face advection velocity (default) */
+    hb_mg_opts mac, visc, proj;
+} hb_step_opts;
+
+typedef struct {
+    double dt, max_u;
+    double div_mac_rel;  /* |D_mac u^MAC|_inf / |D_mac u^adv|_inf */
+    double div_node;     /* max_k |weak div(u^{m+1})_k| / h^d */
+    hb_mg_report mac, visc, proj;
+} hb_step_report;
+
+typedef struct hb_ctx hb_ctx;
+
+/* Create a context for one grid, fluid and option set; allocates every
+ * device buffer the step needs on the current device.  hip_stream: a
+ * hipStream_t (NULL: default stream).  Returns HB_ERR_ARG for an invalid
+ * descriptor, HB_ERR_OOM / HB_ERR_DEVICE on HIP failures. */
+int hb_create(const hb_grid* grid, const hb_fluid* fluid, const hb_step_opts* opts,
+              void* hip_stream, hb_ctx** out);
+void hb_destroy(hb_ctx* ctx);
+const char* hb_last_error(const hb_ctx* ctx);
+
+/* Regularised apparent viscosity per cell (Sec. III.B, Sec. IV):
+ *   g = |gamma_dot|, gamma_dot = (grad u + grad u^T)/2 by centred differences
+ *   with wall ghosts (odd reflection about the wall velocity);
+ *   PAPER:      eta = (g^n + HB/2) (1 - exp(-Pa g)) / g   (bounded: HB Pa/2 at g = 0)
+ *   YIELD_ONLY: eta = g^(n-1) + (HB/2) (1 - exp(-Pa g)) / g.
+ * u: [dim][cells] in, eta: [cells] out (dimensionless, not divided by Re). */
+int hb_viscosity(hb_ctx* ctx, const double* u, double* eta);
+
+/* One multigrid solve on the context's grid (Sec. III.A):
+ *   HB_OP_VISC : (I - dt div(eta/Re gamma_dot(.))) x = rhs with the grid's
+ *                wall velocities; eta [cells] is the dimensionless viscosity;
+ *                x, rhs: [dim][cells];
+ *   HB_OP_NODAL: K x = rhs, K the Q1 stiffness (Neumann); rhs [nodes] has its
+ *                mean removed, x is returned with zero mean;
+ *   HB_OP_MAC  : L_mac x = rhs (cell-centred, zero wall flux), same mean rules.
+ * x: in initial guess, out solution (last iterate on HB_ERR_NOCONV).
+ * opts NULL: the context's option set for that operator.  report nullable. */
+int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt,
+                const double* rhs, double* x, const hb_mg_opts* opts,
+                hb_mg_report* report);
+
+/* The advection stage: viscosity-weighted explicit term E = div(eta/Re
+ * gamma_dot(u)), the Godunov prediction with forcing -G p + 2E + f, the MAC
+ * projection of the face velocity, and the viscous-solve right-hand side
+ *   b = u - dt [u^MAC . grad u~] + dt (-G p + E + f).
+ * u: [dim][cells], p: nodes, eta: [cells] (from hb_viscosity), b: [dim][cells]
+ * out.  umac (faces), conv ([dim][cells], the convective term) nullable. */
+int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta,
+              double dt, double* b, double* umac, double* conv,
+              hb_mg_report* mac_report);
+
+/* Approximate projection: V = ustar/dt + G p; K phi = weak div V;
+ * u = ustar + dt (G p - G phi); p = phi (mean zero).  ustar [dim][cells] in,
+ * p nodes in/out, u [dim][cells] out (may alias ustar). */
+int hb_project(hb_ctx* ctx, const double* ustar, double* p, double dt, double* u,
+               hb_mg_report* report);
+
+/* dt from the CFL condition: cfl h / max(max wall speed, max |u|). */
+int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out);
+
+/* One full time step in place: u^m -> u^{m+1}, p^{m-1/2} -> p^{m+1/2}.
+ * dt <= 0 selects the CFL time step.  report nullable. */
+int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,629 @@
+// hb_host.hip -- context set-up, multigrid drivers (V-cycle and BiCGStab
+// acceleration), the time step and the C ABI of include/hb.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hb_internal.h"
+
+namespace hb {
+
+static thread_local std::string g_create_err;
+
+#define HB_TRY(expr)                                                         \
+    do {                                                                     \
+        hipError_t e_ = (expr);                                              \
+        if (e_ != hipSuccess) {                                              \
+            c->err = std::string(#expr) + ": " + hipGetErrorString(e_);      \
+            return HB_ERR_DEVICE;                                            \
+        }                                                                    \
+    } while (0)
+
+static int fail(Ctx* c, int code, const std::string& msg)
+{
+    c->err = msg;
+    return code;
+}
+
+static bool valid_extent(int n)
+{
+    if (n < 4) return false;
+    while (n % 2 == 0) n /= 2;
+    return n == 1 || n == 3;
+}
+
+static GridD make_gridd(const hb_grid& g)
+{
+    GridD d;
+    memset(&d, 0, sizeof(d));
+    d.dim = g.dim;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = a < g.dim ? g.n[a] : 1;
+        d.per[a] = a < g.dim ? (g.bc[a][0] == HB_BC_PERIODIC) : 0;
+        for (int s = 0; s < 2; ++s)
+            for (int q = 0; q < 3; ++q) d.wall_u[a][s][q] = (a < g.dim && !d.per[a]) ? g.wall_u[a][s][q] : 0.0;
+    }
+    d.h = g.h;
+    return d;
+}
+
+static long unknowns(const GridD& g, int op)
+{
+    if (op == HB_OP_VISC) return ncells(g) * g.dim;
+    if (op == HB_OP_MAC) return ncells(g);
+    return nnodes(g);
+}
+
+static long nface_total(const GridD& g)
+{
+    long n = 0;
+    for (int a = 0; a < g.dim; ++a) n += fcount(g, a);
+    return n;
+}
+
+template <typename T>
+static hipError_t dalloc(T** p, long n)
+{
+    return hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1));
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy
+// ---------------------------------------------------------------------------
+
+static int build_mg(Ctx* c, MG& m, int op)
+{
+    m.op = op;
+    GridD cur = c->g;
+    int l = 0;
+    for (;;) {
+        if (l >= kMaxLev) return fail(c, HB_ERR_ARG, "too many multigrid levels");
+        Level& L = m.L[l];
+        L.g = cur;
+        L.nu = unknowns(cur, op);
+        if (l > 0) {
+            HB_TRY(dalloc(&L.x, L.nu));
+            HB_TRY(dalloc(&L.b, L.nu));
+        }
+        HB_TRY(dalloc(&L.r, L.nu));
+        if (op == HB_OP_VISC) HB_TRY(dalloc(&L.beta, nface_total(cur)));
+        ++l;
+        bool can = true;
+        for (int a = 0; a < cur.dim; ++a)
+            if ((cur.n[a] & 1) || cur.n[a] / 2 < 2) can = false;
+        if (!can) break;
+        GridD nx = cur;
+        for (int a = 0; a < cur.dim; ++a) nx.n[a] = cur.n[a] / 2;
+        nx.h = cur.h * 2.0;
+        memset(nx.wall_u, 0, sizeof(nx.wall_u));
+        cur = nx;
+    }
+    m.nlev = l;
+    m.ncoarse = (int)m.L[l - 1].nu;
+    if (m.ncoarse > 4096) return fail(c, HB_ERR_ARG, "coarsest multigrid level too large for the dense solve");
+    HB_TRY(dalloc(&m.A, (long)m.ncoarse * m.ncoarse));
+    HB_TRY(dalloc(&m.piv, m.ncoarse));
+    HB_TRY(dalloc(&m.lvl0_b, m.L[0].nu));
+    HB_TRY(dalloc(&m.lvl0_x, m.L[0].nu));
+    return HB_OK;
+}
+
+static void free_mg(MG& m)
+{
+    for (int l = 0; l < m.nlev; ++l) {
+        if (l > 0) {
+            (void)hipFree(m.L[l].x);
+            (void)hipFree(m.L[l].b);
+        }
+        (void)hipFree(m.L[l].r);
+        (void)hipFree(m.L[l].beta);
+    }
+    (void)hipFree(m.A);
+    (void)hipFree(m.piv);
+    (void)hipFree(m.lvl0_b);
+    (void)hipFree(m.lvl0_x);
+}
+
+__global__ void k_identity(int N, double* E)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)N * N) return;
+    E[t] = (t / N == t % N) ? 1.0 : 0.0;
+}
+
+// dense coarsest matrix of the current coefficients, then LU
+static void factor_coarsest(Ctx* c, MG& m)
+{
+    const int N = m.ncoarse;
+    const Level& C = m.L[m.nlev - 1];
+    const long nn = (long)N * N;
+    k_identity<<<(unsigned)((nn + 255) / 256), 256, 0, c->s>>>(N, c->dense_E);
+    if (m.op == HB_OP_VISC) launch_visc_dense(c, C, m.dt, N, c->dense_E, m.A);
+    else if (m.op == HB_OP_MAC) launch_mac_dense(c, C, N, c->dense_E, m.A);
+    else launch_nodal_dense(c, C, N, c->dense_E, m.A);
+    if (m.op != HB_OP_VISC) launch_add_ones(c, N, m.A);
+    launch_lu_factor(c, N, m.A, m.piv);
+}
+
+// face viscosities of every level from the cell viscosity eta (not /Re)
+static void visc_setup(Ctx* c, const double* eta, double dt)
+{
+    MG& m = c->visc;
+    launch_eta_faces(c, m.L[0].g, eta, m.L[0].beta);
+    for (int l = 1; l < m.nlev; ++l) launch_restrict_faces(c, m.L[l - 1].g, m.L[l].g, m.L[l - 1].beta, m.L[l].beta);
+    m.dt = dt;
+    factor_coarsest(c, m);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+
+static void smooth(Ctx* c, MG& m, Level& L, int sweeps)
+{
+    for (int s = 0; s < sweeps; ++s) {
+        if (m.op == HB_OP_VISC) {
+            for (int q = 0; q < L.g.dim; ++q)
+                for (int colour = 0; colour < 2; ++colour) launch_visc_rb(c, L, m.dt, q, colour);
+        } else if (m.op == HB_OP_MAC) {
+            for (int colour = 0; colour < 2; ++colour) launch_mac_rb(c, L, colour);
+        } else {
+            for (int colour = 0; colour < (1 << L.g.dim); ++colour) launch_nodal_gs(c, L, colour);
+        }
+    }
+}
+
+static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
+{
+    Level& L = m.L[l];
+    if (l == m.nlev - 1) {
+        launch_lu_solve(c, m.ncoarse, m.A, m.piv, L.b, L.x);
+        return;
+    }
+    Level& C = m.L[l + 1];
+    smooth(c, m, L, nu1);
+    if (m.op == HB_OP_VISC) launch_visc_resid_restrict(c, L, C, m.dt);
+    else if (m.op == HB_OP_MAC) launch_mac_resid_restrict(c, L, C);
+    else {
+        launch_nodal_resid(c, L, L.x, L.b, L.r, -1);
+        launch_nodal_restrict(c, L, C);
+    }
+    vcycle(c, m, l + 1, nu1, nu2);
+    if (m.op == HB_OP_NODAL) launch_nodal_prolong(c, L, C);
+    else launch_prolong_cells(c, L, C, m.op == HB_OP_VISC ? L.g.dim : 1, m.op == HB_OP_VISC ? -1.0 : 1.0);
+    smooth(c, m, L, nu2);
+}
+
+// r = b - A x on level 0 and its max-norm into slot S_MAX
+static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r)
+{
+    set_slot_zero(c, S_MAX);
+    const Level& L = m.L[0];
+    if (m.op == HB_OP_VISC) launch_visc_resid(c, L, m.dt, x, b, r, S_MAX);
+    else if (m.op == HB_OP_MAC) launch_mac_resid(c, L, x, b, r, S_MAX);
+    else launch_nodal_resid(c, L, x, b, r, S_MAX);
+}
+
+static void apply0(Ctx* c, MG& m, const double* x, double* y)
+{
+    const Level& L = m.L[0];
+    if (m.op == HB_OP_VISC) launch_visc_apply(c, L, m.dt, x, y);
+    else if (m.op == HB_OP_MAC) launch_mac_apply(c, L, x, y);
+    else launch_nodal_apply(c, L, x, y);
+}
+
+// z = M^{-1} r: one V-cycle from zero on level 0
+static void precond(Ctx* c, MG& m, const double* r, double* z, int nu1, int nu2)
+{
+    Level& L = m.L[0];
+    double* sx = L.x;
+    double* sb = L.b;
+    L.b = const_cast<double*>(r);
+    L.x = z;
+    fill(c, z, 0.0, L.nu);
+    vcycle(c, m, 0, nu1, nu2);
+    L.x = sx;
+    L.b = sb;
+}
+
+static double fetch_max(Ctx* c)
+{
+    fetch_slots(c);
+    return c->hsc[S_MAX];
+}
+
+// Multigrid (optionally BiCGStab-accelerated) solve of A x = b on the
+// prepared level-0 system; x in/out.  bn = |b|_inf.
+static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_mg_opts& o, hb_mg_report* rep)
+{
+    Level& L = m.L[0];
+    const long n = L.nu;
+    L.x = x;
+    L.b = b;
+    int cycles = 0, rc = HB_OK;
+    double rel = 0.0;
+    if (bn == 0.0) {
+        fill(c, x, 0.0, n);
+    } else if (!o.krylov) {
+        resid0(c, m, x, b, L.r);
+        rel = fetch_max(c) / bn;
+        for (;;) {
+            if (o.fixed_cycles) {
+                if (cycles >= o.max_cycles) break;
+            } else {
+                if (rel <= o.tol_rel) break;
+                if (cycles >= o.max_cycles) { rc = HB_ERR_NOCONV; break; }
+            }
+            vcycle(c, m, 0, o.nu1, o.nu2);
+            ++cycles;
+            resid0(c, m, x, b, L.r);
+            rel = fetch_max(c) / bn;
+            if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
+        }
+    } else {
+        double *r = c->kr, *rh = c->krh, *p = c->kp, *v = c->kv, *ph = c->kph, *s = c->ks, *sh = c->ksh, *t = c->kt;
+        resid0(c, m, x, b, r);
+        copy(c, rh, r, n);
+        fill(c, p, 0.0, n);
+        fill(c, v, 0.0, n);
+        rel = fetch_max(c) / bn;
+        double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+        for (;;) {
+            if (o.fixed_cycles) {
+                if (cycles >= o.max_cycles) break;
+            } else {
+                if (rel <= o.tol_rel) break;
+                if (cycles >= o.max_cycles) { rc = HB_ERR_NOCONV; break; }
+            }
+            red_dot(c, rh, r, n, S_DOT0);
+            fetch_slots(c);
+            const double rho = c->hsc[S_DOT0];
+            if (rho == 0.0) { rc = HB_ERR_NOCONV; break; }
+            const double beta = (rho / rho_prev) * (alpha / omega);
+            bicg_p(c, p, r, v, beta, omega, n);
+            precond(c, m, p, ph, o.nu1, o.nu2);
+            ++cycles;
+            apply0(c, m, ph, v);
+            red_dot(c, rh, v, n, S_DOT0);
+            fetch_slots(c);
+            alpha = rho / c->hsc[S_DOT0];
+            sub_scaled_max(c, s, r, alpha, v, n, S_MAX);
+            const double srel = fetch_max(c) / bn;
+            if ((!o.fixed_cycles && srel <= o.tol_rel) || (o.fixed_cycles && cycles >= o.max_cycles)) {
+                axpby(c, x, alpha, ph, 1.0, n);
+                copy(c, r, s, n);
+                rel = srel;
+                break;
+            }
+            precond(c, m, s, sh, o.nu1, o.nu2);
+            ++cycles;
+            apply0(c, m, sh, t);
+            red_dot(c, t, t, n, S_DOT0);
+            red_dot(c, t, s, n, S_DOT1);
+            fetch_slots(c);
+            const double tt = c->hsc[S_DOT0];
+            omega = tt > 0.0 ? c->hsc[S_DOT1] / tt : 0.0;
+            bicg_x(c, x, ph, sh, alpha, omega, n);
+            sub_scaled_max(c, r, s, omega, t, n, S_MAX);
+            rel = fetch_max(c) / bn;
+            if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
+            if (omega == 0.0) { rc = HB_ERR_NOCONV; break; }
+            rho_prev = rho;
+        }
+        resid0(c, m, x, b, L.r);
+        rel = fetch_max(c) / bn;
+        if (!std::isfinite(rel)) rc = HB_ERR_NONFINITE;
+    }
+    if (rep) {
+        rep->cycles = cycles;
+        rep->rel_resid = rel;
+        rep->bnorm = bn;
+    }
+    return rc;
+}
+
+// solve with the right-hand side already in m.lvl0_b (VISC: wall part added,
+// NODAL/MAC: mean removed by this function)
+static int solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o, hb_mg_report* rep)
+{
+    const long n = m.L[0].nu;
+    if (m.op != HB_OP_VISC) sub_mean(c, m.lvl0_b, n);
+    red_maxabs(c, m.lvl0_b, n, S_MAX);
+    red_maxabs(c, x, n, S_MAX2);
+    fetch_slots(c);
+    const double bn = c->hsc[S_MAX];
+    if (!std::isfinite(bn) || !std::isfinite(c->hsc[S_MAX2])) return fail(c, HB_ERR_NONFINITE, "non-finite right-hand side or guess");
+    int rc = solve_core(c, m, x, m.lvl0_b, bn, o, rep);
+    if (m.op != HB_OP_VISC) sub_mean(c, x, n);
+    if (rc == HB_ERR_NOCONV) c->err = "multigrid did not reach the tolerance within max_cycles";
+    if (rc == HB_ERR_NONFINITE) c->err = "multigrid produced a non-finite residual";
+    return rc;
+}
+
+static bool valid_opts(const hb_mg_opts& o)
+{
+    return o.max_cycles >= 0 && o.max_cycles <= 100000 && o.nu1 >= 0 && o.nu2 >= 0 && o.nu1 + o.nu2 > 0 &&
+           o.tol_rel >= 0.0 && (o.precision == HB_PREC_FP64 || o.precision == HB_PREC_MIXED);
+}
+
+// ---------------------------------------------------------------------------
+// stages of the step
+// ---------------------------------------------------------------------------
+
+// advection stage; requires visc_setup(eta, dt) and S_MAXU = max|u|
+static int advect_stage(Ctx* c, const double* u, const double* p, double dt, double* b, double* conv,
+                        hb_mg_report* mac_rep, double* div_mac_rel)
+{
+    const MG& vm = c->visc;
+    launch_visc_div(c, c->g, vm.L[0].beta, u, c->E);
+    launch_grad_node(c, p, c->Gp);
+    launch_forcing(c);
+    launch_slopes(c, u);
+    launch_trace_normal(c, u, dt);
+    launch_transverse(c);
+    launch_trace_full(c, u, dt);
+    int rc = HB_OK;
+    if (c->opts.mac_project) {
+        launch_mac_div(c, c->uadv, c->mac.lvl0_b);
+        double d0 = 0.0;
+        if (div_mac_rel) {
+            red_maxabs(c, c->mac.lvl0_b, c->nc, S_MAX);
+            fetch_slots(c);
+            d0 = c->hsc[S_MAX];
+        }
+        fill(c, c->macphi, 0.0, c->nc);
+        rc = solve_prepared(c, c->mac, c->macphi, c->opts.mac, mac_rep);
+        launch_mac_update(c);
+        if (div_mac_rel) {
+            launch_mac_div(c, c->umac, c->macrhs);
+            red_maxabs(c, c->macrhs, c->nc, S_MAX);
+            fetch_slots(c);
+            *div_mac_rel = d0 > 0.0 ? c->hsc[S_MAX] / d0 : 0.0;
+        }
+    } else {
+        copy(c, c->umac, c->uadv, c->nf);
+        if (mac_rep) memset(mac_rep, 0, sizeof(*mac_rep));
+        if (div_mac_rel) *div_mac_rel = 0.0;
+    }
+    launch_advect_rhs(c, u, dt, b, conv);
+    return rc;
+}
+
+static int project_stage(Ctx* c, const double* ustar, double* p, double dt, double* u, hb_mg_report* rep)
+{
+    launch_grad_node(c, p, c->Gp);
+    launch_proj_rhs(c, ustar, dt, c->nodal.lvl0_b);
+    copy(c, c->phi, p, c->nn);
+    int rc = solve_prepared(c, c->nodal, c->phi, c->opts.proj, rep);
+    launch_proj_update(c, ustar, c->phi, dt, u);
+    copy(c, p, c->phi, c->nn);
+    return rc;
+}
+
+static bool worse(int rc, int cur) { return cur == HB_OK || (cur == HB_ERR_NOCONV && rc != HB_OK); }
+
+}  // namespace hb
+
+using namespace hb;
+
+struct hb_ctx : public Ctx {};
+
+extern "C" {
+
+const char* hb_last_error(const hb_ctx* ctx)
+{
+    if (!ctx) return g_create_err.c_str();
+    return ctx->err.c_str();
+}
+
+void hb_destroy(hb_ctx* ctx)
+{
+    if (!ctx) return;
+    Ctx* c = ctx;
+    free_mg(c->visc);
+    free_mg(c->mac);
+    free_mg(c->nodal);
+    double* bufs[] = {c->eta, c->E, c->Gp, c->F, c->S, c->trans, c->uhat, c->qhat, c->qLf, c->qRf, c->uadv,
+                      c->umac, c->macphi, c->macrhs, c->b, c->ustar, c->rnode, c->phi, c->conv, c->kr, c->krh,
+                      c->kp, c->kv, c->kph, c->ks, c->ksh, c->kt, c->dense_E, c->sc, c->partial};
+    for (double* p : bufs) (void)hipFree(p);
+    if (c->hsc) (void)hipHostFree(c->hsc);
+    delete ctx;
+}
+
+int hb_create(const hb_grid* grid, const hb_fluid* fluid, const hb_step_opts* opts, void* hip_stream, hb_ctx** out)
+{
+    if (out) *out = nullptr;
+    auto bad = [](const char* m) { g_create_err = m; return HB_ERR_ARG; };
+    if (!grid || !fluid || !opts || !out) return bad("null argument");
+    if (grid->dim != 2 && grid->dim != 3) return bad("dim must be 2 or 3");
+    for (int a = 0; a < grid->dim; ++a) {
+        if (!valid_extent(grid->n[a])) return bad("each n[a] must be c*2^k, c in {1,2,3}, n >= 4");
+        if (grid->bc[a][0] != grid->bc[a][1] && (grid->bc[a][0] == HB_BC_PERIODIC || grid->bc[a][1] == HB_BC_PERIODIC))
+            return bad("periodic faces must come in pairs");
+        for (int s = 0; s < 2; ++s)
+            if (grid->bc[a][s] != HB_BC_WALL && grid->bc[a][s] != HB_BC_PERIODIC) return bad("unknown boundary type");
+    }
+    if (!(grid->h > 0.0) || !std::isfinite(grid->h)) return bad("h must be positive");
+    if (!(fluid->Re > 0.0) || !(fluid->Pa > 0.0) || !(fluid->n > 0.0) || !(fluid->HB >= 0.0))
+        return bad("need Re > 0, Pa > 0, n > 0, HB >= 0");
+    if (fluid->reg != HB_REG_PAPER && fluid->reg != HB_REG_YIELD_ONLY) return bad("unknown regularisation");
+    if (fluid->reg == HB_REG_YIELD_ONLY && fluid->n < 1.0) return bad("yield-only regularisation needs n >= 1");
+    if (!valid_opts(opts->mac) || !valid_opts(opts->visc) || !valid_opts(opts->proj)) return bad("invalid multigrid options");
+    if (!(opts->cfl > 0.0)) return bad("cfl must be positive");
+
+    hb_ctx* ctx = new (std::nothrow) hb_ctx();
+    if (!ctx) return bad("out of host memory");
+    Ctx* c = ctx;
+    c->grid = *grid;
+    c->fluid = *fluid;
+    c->opts = *opts;
+    c->s = (hipStream_t)hip_stream;
+    c->g = make_gridd(*grid);
+    c->fl.Re = fluid->Re;
+    c->fl.HB = fluid->HB;
+    c->fl.n = fluid->n;
+    c->fl.Pa = fluid->Pa;
+    c->fl.reg = fluid->reg;
+    for (int q = 0; q < 3; ++q) c->fl.f[q] = q < grid->dim ? fluid->f[q] : 0.0;
+    c->dim = grid->dim;
+    c->nc = ncells(c->g);
+    c->nn = nnodes(c->g);
+    c->nf = nface_total(c->g);
+    c->ulid = 0.0;
+    for (int a = 0; a < c->dim; ++a)
+        for (int s = 0; s < 2; ++s)
+            for (int q = 0; q < 3; ++q) c->ulid = std::fmax(c->ulid, std::fabs(c->g.wall_u[a][s][q]));
+
+    auto oom = [&](const std::string& m) {
+        g_create_err = m.empty() ? "device allocation failed" : m;
+        hb_destroy(ctx);
+        return HB_ERR_OOM;
+    };
+    int rc;
+    if ((rc = build_mg(c, c->visc, HB_OP_VISC)) != HB_OK) { g_create_err = c->err; hb_destroy(ctx); return rc; }
+    if ((rc = build_mg(c, c->mac, HB_OP_MAC)) != HB_OK) { g_create_err = c->err; hb_destroy(ctx); return rc; }
+    if ((rc = build_mg(c, c->nodal, HB_OP_NODAL)) != HB_OK) { g_create_err = c->err; hb_destroy(ctx); return rc; }
+    const long d = c->dim, nc = c->nc, nf = c->nf, nn = c->nn;
+    const long nv = d * nc;
+    bool ok = true;
+    ok = ok && dalloc(&c->eta, nc) == hipSuccess && dalloc(&c->E, nv) == hipSuccess && dalloc(&c->Gp, nv) == hipSuccess;
+    ok = ok && dalloc(&c->F, nv) == hipSuccess && dalloc(&c->S, d * d * nc) == hipSuccess &&
+         dalloc(&c->trans, d * d * nc) == hipSuccess;
+    ok = ok && dalloc(&c->uhat, nf) == hipSuccess && dalloc(&c->qhat, d * nf) == hipSuccess &&
+         dalloc(&c->qLf, d * nf) == hipSuccess && dalloc(&c->qRf, d * nf) == hipSuccess;
+    ok = ok && dalloc(&c->uadv, nf) == hipSuccess && dalloc(&c->umac, nf) == hipSuccess &&
+         dalloc(&c->macphi, nc) == hipSuccess && dalloc(&c->macrhs, nc) == hipSuccess;
+    ok = ok && dalloc(&c->b, nv) == hipSuccess && dalloc(&c->ustar, nv) == hipSuccess &&
+         dalloc(&c->rnode, nn) == hipSuccess && dalloc(&c->phi, nn) == hipSuccess && dalloc(&c->conv, nv) == hipSuccess;
+    ok = ok && dalloc(&c->kr, nv) == hipSuccess && dalloc(&c->krh, nv) == hipSuccess && dalloc(&c->kp, nv) == hipSuccess &&
+         dalloc(&c->kv, nv) == hipSuccess && dalloc(&c->kph, nv) == hipSuccess && dalloc(&c->ks, nv) == hipSuccess &&
+         dalloc(&c->ksh, nv) == hipSuccess && dalloc(&c->kt, nv) == hipSuccess;
+    int nmax = c->visc.ncoarse;
+    if (c->mac.ncoarse > nmax) nmax = c->mac.ncoarse;
+    if (c->nodal.ncoarse > nmax) nmax = c->nodal.ncoarse;
+    ok = ok && dalloc(&c->dense_E, (long)nmax * nmax) == hipSuccess;
+    ok = ok && dalloc(&c->sc, S_NSLOT) == hipSuccess && dalloc(&c->partial, kRedBlocks) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&c->hsc, sizeof(double) * S_NSLOT) == hipSuccess;
+    if (!ok) return oom("");
+    fill(c, c->sc, 0.0, S_NSLOT);
+    // constant coarsest matrices of the MAC and nodal problems
+    factor_coarsest(c, c->mac);
+    factor_coarsest(c, c->nodal);
+    if (hipStreamSynchronize(c->s) != hipSuccess) return oom("stream synchronisation failed during set-up");
+    *out = ctx;
+    return HB_OK;
+}
+
+int hb_viscosity(hb_ctx* ctx, const double* u, double* eta)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = ctx;
+    if (!u || !eta) return fail(c, HB_ERR_ARG, "null array");
+    launch_viscosity(c, u, eta);
+    return hipGetLastError() == hipSuccess ? HB_OK : fail(c, HB_ERR_DEVICE, "kernel launch failed");
+}
+
+int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt, const double* rhs, double* x,
+                const hb_mg_opts* opts, hb_mg_report* report)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = ctx;
+    if (!rhs || !x) return fail(c, HB_ERR_ARG, "null array");
+    if (op != HB_OP_VISC && op != HB_OP_NODAL && op != HB_OP_MAC) return fail(c, HB_ERR_ARG, "unknown operator");
+    if (op == HB_OP_VISC && (!eta || !(dt > 0.0))) return fail(c, HB_ERR_ARG, "viscous solve needs eta and dt > 0");
+    const hb_mg_opts& o = opts ? *opts : (op == HB_OP_VISC ? c->opts.visc : (op == HB_OP_MAC ? c->opts.mac : c->opts.proj));
+    if (!valid_opts(o)) return fail(c, HB_ERR_ARG, "invalid multigrid options");
+    MG& m = op == HB_OP_VISC ? c->visc : (op == HB_OP_MAC ? c->mac : c->nodal);
+    if (op == HB_OP_VISC) {
+        visc_setup(c, eta, dt);
+        launch_visc_wall_rhs(c, c->g, m.L[0].beta, dt, rhs, m.lvl0_b);
+    } else {
+        copy(c, m.lvl0_b, rhs, m.L[0].nu);
+    }
+    return solve_prepared(c, m, x, o, report);
+}
+
+int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta, double dt, double* b, double* umac,
+              double* conv, hb_mg_report* mac_report)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = ctx;
+    if (!u || !p || !eta || !b) return fail(c, HB_ERR_ARG, "null array");
+    if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
+    red_maxabs(c, u, c->dim * c->nc, S_MAXU);
+    visc_setup(c, eta, dt);
+    int rc = advect_stage(c, u, p, dt, b, conv, mac_report, nullptr);
+    if (umac) copy(c, umac, c->umac, c->nf);
+    if (hipStreamSynchronize(c->s) != hipSuccess) return fail(c, HB_ERR_DEVICE, "stream synchronisation failed");
+    return rc;
+}
+
+int hb_project(hb_ctx* ctx, const double* ustar, double* p, double dt, double* u, hb_mg_report* report)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = ctx;
+    if (!ustar || !p || !u) return fail(c, HB_ERR_ARG, "null array");
+    if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
+    return project_stage(c, ustar, p, dt, u, report);
+}
+
+int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = ctx;
+    if (!u || !dt_out) return fail(c, HB_ERR_ARG, "null argument");
+    red_maxabs(c, u, c->dim * c->nc, S_MAXU);
+    fetch_slots(c);
+    const double m = std::fmax(c->ulid, c->hsc[S_MAXU]);
+    if (!std::isfinite(m)) return fail(c, HB_ERR_NONFINITE, "non-finite velocity");
+    *dt_out = m > 0.0 ? c->opts.cfl * c->g.h / m : 0.0;
+    return HB_OK;
+}
+
+int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = ctx;
+    if (!u || !p) return fail(c, HB_ERR_ARG, "null array");
+    const long nv = c->dim * c->nc;
+    red_maxabs(c, u, nv, S_MAXU);
+    red_maxabs(c, p, c->nn, S_MAX2);
+    fetch_slots(c);
+    if (!std::isfinite(c->hsc[S_MAXU]) || !std::isfinite(c->hsc[S_MAX2])) return fail(c, HB_ERR_NONFINITE, "non-finite u or p");
+    if (!(dt > 0.0)) {
+        const double m = std::fmax(c->ulid, c->hsc[S_MAXU]);
+        if (!(m > 0.0)) return fail(c, HB_ERR_ARG, "dt <= 0 with zero velocity everywhere");
+        dt = c->opts.cfl * c->g.h / m;
+    }
+    hb_step_report R;
+    memset(&R, 0, sizeof(R));
+    R.dt = dt;
+    launch_viscosity(c, u, c->eta);
+    visc_setup(c, c->eta, dt);
+    int rc = advect_stage(c, u, p, dt, c->b, nullptr, &R.mac, report ? &R.div_mac_rel : nullptr);
+    if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
+    int rc2 = HB_OK;
+    launch_visc_wall_rhs(c, c->g, c->visc.L[0].beta, dt, c->b, c->visc.lvl0_b);
+    copy(c, c->ustar, u, nv);
+    rc2 = solve_prepared(c, c->visc, c->ustar, c->opts.visc, &R.visc);
+    if (worse(rc2, rc)) rc = rc2;
+    if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
+    rc2 = project_stage(c, c->ustar, p, dt, u, &R.proj);
+    if (worse(rc2, rc)) rc = rc2;
+    if (report) {
+        red_maxabs(c, u, nv, S_MAX);
+        launch_weak_div(c, u, c->rnode);
+        red_maxabs(c, c->rnode, c->nn, S_MAX2);
+        fetch_slots(c);
+        R.max_u = c->hsc[S_MAX];
+        R.div_node = c->hsc[S_MAX2] / std::pow(c->g.h, c->dim);
+        *report = R;
+    }
+    if (hipGetLastError() != hipSuccess) return fail(c, HB_ERR_DEVICE, "kernel launch failed");
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// hb_reduce.hip -- reductions and vector updates on the context's stream.
+// Sums use a fixed number of blocks and fixed tree orders, so every run
+// gives the same bits; max-norms are order independent.
+#include "hb_internal.h"
+
+namespace hb {
+
+static constexpr int kT = 256;
+
+__global__ void k_set(double* p, double v) { *p = v; }
+
+void set_slot_zero(Ctx* c, int slot) { k_set<<<1, 1, 0, c->s>>>(c->sc + slot, 0.0); }
+
+__global__ void k_maxabs(const double* __restrict__ v, long n, double* __restrict__ out)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    unsigned long long m = 0ull;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const unsigned long long b = abits(v[i]);
+        m = b > m ? b : m;
+    }
+    m = block_umax(m, sh);
+    if (threadIdx.x == 0) atomic_max_bits(out, m);
+}
+
+void red_maxabs(Ctx* c, const double* v, long n, int slot, bool accumulate)
+{
+    if (!accumulate) set_slot_zero(c, slot);
+    if (n <= 0) return;
+    const long nb = (n + kT - 1) / kT;
+    k_maxabs<<<(unsigned)(nb < kRedBlocks ? nb : kRedBlocks), kT, 0, c->s>>>(v, n, c->sc + slot);
+}
+
+// partial sums of v (or of a*b): block b owns the fixed index set
+// {b*T + t + k*nblocks*T}
+__global__ void k_sum_partial(const double* __restrict__ a, const double* __restrict__ b, long n, double* __restrict__ part)
+{
+    __shared__ double sh[kT / 64];
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        s += b ? a[i] * b[i] : a[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_sum_final(const double* __restrict__ part, int nb, double* __restrict__ out)
+{
+    __shared__ double sh[kT / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+static void sum_impl(Ctx* c, const double* a, const double* b, long n, int slot)
+{
+    k_sum_partial<<<kRedBlocks, kT, 0, c->s>>>(a, b, n, c->partial);
+    k_sum_final<<<1, kT, 0, c->s>>>(c->partial, kRedBlocks, c->sc + slot);
+}
+
+void red_sum(Ctx* c, const double* v, long n, int slot) { sum_impl(c, v, nullptr, n, slot); }
+void red_dot(Ctx* c, const double* a, const double* b, long n, int slot) { sum_impl(c, a, b, n, slot); }
+
+void fetch_slots(Ctx* c)
+{
+    (void)hipMemcpyAsync(c->hsc, c->sc, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, c->s);
+    (void)hipStreamSynchronize(c->s);
+}
+
+// v -= sum(v) / n, the sum taken from the slot (no host round trip)
+__global__ void k_sub_mean(double* __restrict__ v, long n, const double* __restrict__ sum)
+{
+    const double m = *sum / (double)n;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) v[i] -= m;
+}
+
+void sub_mean(Ctx* c, double* v, long n)
+{
+    red_sum(c, v, n, S_SUM);
+    const long nb = (n + kT - 1) / kT;
+    k_sub_mean<<<(unsigned)(nb < 4096 ? nb : 4096), kT, 0, c->s>>>(v, n, c->sc + S_SUM);
+}
+
+__global__ void k_axpby(double* __restrict__ y, double a, const double* __restrict__ x, double b, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = a * x[i] + b * y[i];
+}
+
+void axpby(Ctx* c, double* y, double a, const double* x, double b, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_axpby<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(y, a, x, b, n);
+}
+
+__global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+void copy(Ctx* c, double* dst, const double* src, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_copy<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(dst, src, n);
+}
+
+__global__ void k_fill(double* __restrict__ d, double v, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = v;
+}
+
+void fill(Ctx* c, double* dst, double v, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_fill<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(dst, v, n);
+}
+
+// ---- BiCGStab updates (same element formulas as the textbook algorithm) ----
+
+// p = r + beta (p - omega v)
+__global__ void k_bicg_p(double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
+                         double beta, double omega, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// out = a - s b, with the max-norm of out into *mx
+__global__ void k_sub_scaled_max(double* __restrict__ out, const double* __restrict__ a, double s,
+                                 const double* __restrict__ b, long n, double* __restrict__ mx)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    unsigned long long m = 0ull;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = a[i] - s * b[i];
+        out[i] = v;
+        const unsigned long long bb = abits(v);
+        m = bb > m ? bb : m;
+    }
+    m = block_umax(m, sh);
+    if (threadIdx.x == 0) atomic_max_bits(mx, m);
+}
+
+// x += alpha ph + omega sh
+__global__ void k_bicg_x(double* __restrict__ x, const double* __restrict__ ph, const double* __restrict__ sh_,
+                         double alpha, double omega, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] += alpha * ph[i] + omega * sh_[i];
+}
+
+void bicg_p(Ctx* c, double* p, const double* r, const double* v, double beta, double omega, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_bicg_p<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(p, r, v, beta, omega, n);
+}
+
+void sub_scaled_max(Ctx* c, double* out, const double* a, double s, const double* b, long n, int slot)
+{
+    set_slot_zero(c, slot);
+    const long nb = (n + kT - 1) / kT;
+    k_sub_scaled_max<<<(unsigned)(nb < kRedBlocks ? nb : kRedBlocks), kT, 0, c->s>>>(out, a, s, b, n, c->sc + slot);
+}
+
+void bicg_x(Ctx* c, double* x, const double* ph, const double* sh, double alpha, double omega, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_bicg_x<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(x, ph, sh, alpha, omega, n);
+}
+
+}  // namespace hb

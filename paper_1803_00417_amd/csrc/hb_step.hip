@@ -1,0 +1,423 @@
+// hb_step.hip -- kernels of the advection stage (Godunov prediction of face
+// states at t^{m+1/2}, MAC divergence/update, convective term and viscous
+// right-hand side) and of the approximate nodal projection.  gfx950, FP64.
+//
+// Layouts: slopes S[a][q][cell], transverse terms T[b][q][cell]; face arrays
+// are concatenated per axis (total nf faces): uhat[f], qhat[q][f], qLf[q][f],
+// qRf[q][f], uadv[f], umac[f].
+#include "hb_internal.h"
+
+namespace hb {
+
+static const dim3 kBlk(64, 4, 1);
+
+__device__ inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+__device__ inline double lesser(double a, double b) { return a < b ? a : b; }
+
+// fourth-order monotonicity-limited slope (Colella 1985), per cell, from the
+// five values q[0..4] centred on q[2]
+__device__ inline double limited_slope(const double q[5])
+{
+    double dc[3], dl[3], df[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const double dp = q[t + 2] - q[t + 1], dm = q[t + 1] - q[t];
+        dc[t] = 0.5 * (q[t + 2] - q[t]);
+        dl[t] = (dp * dm > 0.0) ? 2.0 * lesser(fabs(dp), fabs(dm)) : 0.0;
+        df[t] = sgn(dc[t]) * lesser(fabs(dc[t]), dl[t]);
+    }
+    const double d4 = (4.0 / 3.0) * dc[1] - (1.0 / 6.0) * (df[2] + df[0]);
+    return sgn(dc[1]) * lesser(fabs(d4), dl[1]);
+}
+
+// Burgers Riemann solution for the normal velocity
+__device__ inline double burgers(double uL, double uR)
+{
+    if (uL > 0.0 && uL + uR > 0.0) return uL;
+    if (uR < 0.0 && uL + uR < 0.0) return uR;
+    return 0.0;
+}
+
+__device__ inline double upwind(double vel, double qL, double qR, double delta)
+{
+    if (vel > delta) return qL;
+    if (vel < -delta) return qR;
+    return 0.5 * (qL + qR);
+}
+
+__device__ inline double deadband(const double* sc, double ulid)
+{
+    return 1e-12 * fmax(ulid, sc[S_MAXU]);
+}
+
+// ---------------------------------------------------------------------------
+// nodal gradient and forcing
+// ---------------------------------------------------------------------------
+
+// cell average of the Q1 gradient of a nodal field
+__device__ inline double grad_node_at(const GridD& g, const double* __restrict__ p, int a, int i, int j, int k)
+{
+    const int nc = 1 << g.dim;
+    double s = 0.0;
+    for (int bits = 0; bits < nc; ++bits) {
+        if (!((bits >> a) & 1)) continue;
+        int hi[3] = {i, j, k}, lo[3] = {i, j, k};
+        for (int b = 0; b < g.dim; ++b) {
+            hi[b] += (bits >> b) & 1;
+            lo[b] += ((bits & ~(1 << a)) >> b) & 1;
+            if (g.per[b] && hi[b] == g.n[b]) hi[b] = 0;
+            if (g.per[b] && lo[b] == g.n[b]) lo[b] = 0;
+        }
+        s += (p[nid(g, hi[0], hi[1], hi[2])] - p[nid(g, lo[0], lo[1], lo[2])]) / g.h;
+    }
+    return s / (double)(nc / 2);
+}
+
+__global__ void k_grad_node(GridD g, const double* __restrict__ p, double* __restrict__ Gp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long N = ncells(g), q = cid(g, i, j, k);
+    for (int a = 0; a < g.dim; ++a) Gp[a * N + q] = grad_node_at(g, p, a, i, j, k);
+}
+
+void launch_grad_node(Ctx* c, const double* p, double* Gp)
+{
+    k_grad_node<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, p, Gp);
+}
+
+// F = -G p + 2E + f (the forcing of the Taylor prediction)
+__global__ void k_forcing(long n, int dim, double f0, double f1, double f2, const double* __restrict__ Gp,
+                          const double* __restrict__ E, double* __restrict__ F)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * dim) return;
+    const int c = (int)(t / n);
+    const double f = c == 0 ? f0 : (c == 1 ? f1 : f2);
+    F[t] = -Gp[t] + 2.0 * E[t] + f;
+}
+
+void launch_forcing(Ctx* c)
+{
+    const long n = c->nc * c->dim;
+    k_forcing<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(c->nc, c->dim, c->fl.f[0], c->fl.f[1], c->fl.f[2], c->Gp, c->E, c->F);
+}
+
+// ---------------------------------------------------------------------------
+// Godunov prediction
+// ---------------------------------------------------------------------------
+
+__global__ void k_slopes(GridD g, const double* __restrict__ u, double* __restrict__ S)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long N = ncells(g), q0 = cid(g, i, j, k);
+    const int d = g.dim;
+    for (int a = 0; a < d; ++a)
+        for (int q = 0; q < d; ++q) {
+            double st[5];
+            for (int t = 0; t < 5; ++t) {
+                int p[3] = {i, j, k};
+                p[a] += t - 2;
+                st[t] = cval<false>(g, u + (long)q * N, q, p[0], p[1], p[2]);
+            }
+            S[((long)a * d + q) * N + q0] = limited_slope(st);
+        }
+}
+
+void launch_slopes(Ctx* c, const double* u)
+{
+    k_slopes<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, u, c->S);
+}
+
+// normal-only traced states on a-faces, upwinded by their Burgers solution
+__global__ void k_trace_normal(GridD g, int a, double dt, double ulid, const double* __restrict__ sc,
+                               const double* __restrict__ u, const double* __restrict__ S, long nf,
+                               double* __restrict__ uhat, double* __restrict__ qhat)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= fext(g, a, 0) || j >= fext(g, a, 1)) return;
+    const int d = g.dim;
+    const long N = ncells(g);
+    const long f = foffset(g, a) + fid(g, a, i, j, k);
+    int R[3] = {i, j, k}, L[3] = {i, j, k};
+    L[a] -= 1;
+    const bool okL = wrap(g, L), okR = wrap(g, R);
+    if (!okL || !okR) {
+        const int side = okL ? 1 : 0;
+        uhat[f] = 0.0;
+        for (int q = 0; q < d; ++q) qhat[q * nf + f] = g.wall_u[a][side][q];
+        return;
+    }
+    const long cL = cid(g, L[0], L[1], L[2]), cR = cid(g, R[0], R[1], R[2]);
+    const double delta = deadband(sc, ulid);
+    double qL[3], qR[3];
+    for (int q = 0; q < d; ++q) {
+        qL[q] = u[q * N + cL] + (0.5 - dt * u[a * N + cL] / (2.0 * g.h)) * S[((long)a * d + q) * N + cL];
+        qR[q] = u[q * N + cR] - (0.5 + dt * u[a * N + cR] / (2.0 * g.h)) * S[((long)a * d + q) * N + cR];
+    }
+    const double uh = burgers(qL[a], qR[a]);
+    uhat[f] = uh;
+    for (int q = 0; q < d; ++q) qhat[q * nf + f] = (q == a) ? uh : upwind(uh, qL[q], qR[q], delta);
+}
+
+void launch_trace_normal(Ctx* c, const double* u, double dt)
+{
+    const GridD& g = c->g;
+    for (int a = 0; a < g.dim; ++a)
+        k_trace_normal<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(
+            g, a, dt, c->ulid, c->sc, u, c->S, c->nf, c->uhat, c->qhat);
+}
+
+// transverse terms at cells: (u_b dq/dx_b)^ = mean face velocity x difference
+__global__ void k_transverse(GridD g, long nf, const double* __restrict__ uhat, const double* __restrict__ qhat,
+                             double* __restrict__ T)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const int d = g.dim;
+    const long N = ncells(g), q0 = cid(g, i, j, k);
+    for (int b = 0; b < d; ++b) {
+        int hi[3] = {i, j, k};
+        hi[b] += 1;
+        if (g.per[b] && hi[b] == g.n[b]) hi[b] = 0;
+        const long flo = foffset(g, b) + fid(g, b, i, j, k);
+        const long fhi = foffset(g, b) + fid(g, b, hi[0], hi[1], hi[2]);
+        const double ubar = 0.5 * (uhat[flo] + uhat[fhi]);
+        for (int q = 0; q < d; ++q) {
+            const double dq = (qhat[q * nf + fhi] - qhat[q * nf + flo]) / g.h;
+            T[((long)b * d + q) * N + q0] = ubar * dq;
+        }
+    }
+}
+
+void launch_transverse(Ctx* c)
+{
+    k_transverse<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, c->nf, c->uhat, c->qhat, c->trans);
+}
+
+// full face states: traced normal part - dt/2 transverse terms + dt/2 forcing;
+// the advection velocity is the Burgers solution of the normal component
+__global__ void k_trace_full(GridD g, int a, double dt, const double* __restrict__ u, const double* __restrict__ S,
+                             const double* __restrict__ T, const double* __restrict__ F, long nf,
+                             double* __restrict__ qLf, double* __restrict__ qRf, double* __restrict__ uadv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= fext(g, a, 0) || j >= fext(g, a, 1)) return;
+    const int d = g.dim;
+    const long N = ncells(g);
+    const long f = foffset(g, a) + fid(g, a, i, j, k);
+    int R[3] = {i, j, k}, L[3] = {i, j, k};
+    L[a] -= 1;
+    const bool okL = wrap(g, L), okR = wrap(g, R);
+    if (!okL || !okR) {
+        const int side = okL ? 1 : 0;
+        uadv[f] = 0.0;
+        for (int q = 0; q < d; ++q) {
+            qLf[q * nf + f] = g.wall_u[a][side][q];
+            qRf[q * nf + f] = g.wall_u[a][side][q];
+        }
+        return;
+    }
+    const long cL = cid(g, L[0], L[1], L[2]), cR = cid(g, R[0], R[1], R[2]);
+    for (int q = 0; q < d; ++q) {
+        double tl = 0.0, tr = 0.0;
+        for (int b = 0; b < d; ++b) {
+            if (b == a) continue;
+            tl += T[((long)b * d + q) * N + cL];
+            tr += T[((long)b * d + q) * N + cR];
+        }
+        const double vl = u[q * N + cL] + (0.5 - dt * u[a * N + cL] / (2.0 * g.h)) * S[((long)a * d + q) * N + cL]
+                          - 0.5 * dt * tl + 0.5 * dt * F[q * N + cL];
+        const double vr = u[q * N + cR] - (0.5 + dt * u[a * N + cR] / (2.0 * g.h)) * S[((long)a * d + q) * N + cR]
+                          - 0.5 * dt * tr + 0.5 * dt * F[q * N + cR];
+        qLf[q * nf + f] = vl;
+        qRf[q * nf + f] = vr;
+    }
+    uadv[f] = burgers(qLf[a * nf + f], qRf[a * nf + f]);
+}
+
+void launch_trace_full(Ctx* c, const double* u, double dt)
+{
+    const GridD& g = c->g;
+    for (int a = 0; a < g.dim; ++a)
+        k_trace_full<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(
+            g, a, dt, u, c->S, c->trans, c->F, c->nf, c->qLf, c->qRf, c->uadv);
+}
+
+// ---------------------------------------------------------------------------
+// MAC projection of the advection velocity
+// ---------------------------------------------------------------------------
+
+__global__ void k_mac_div(GridD g, const double* __restrict__ F, double* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    double s = 0.0;
+    for (int a = 0; a < g.dim; ++a) {
+        int hi[3] = {i, j, k};
+        hi[a] += 1;
+        if (g.per[a] && hi[a] == g.n[a]) hi[a] = 0;
+        const long off = foffset(g, a);
+        s += (F[off + fid(g, a, hi[0], hi[1], hi[2])] - F[off + fid(g, a, i, j, k)]) / g.h;
+    }
+    out[cid(g, i, j, k)] = s;
+}
+
+void launch_mac_div(Ctx* c, const double* faces, double* out)
+{
+    k_mac_div<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, faces, out);
+}
+
+// u^MAC = u^adv - G_mac phi (the gradient vanishes on wall faces)
+__global__ void k_mac_update(GridD g, int a, const double* __restrict__ uadv, const double* __restrict__ phi,
+                             double* __restrict__ umac)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= fext(g, a, 0) || j >= fext(g, a, 1)) return;
+    const long f = foffset(g, a) + fid(g, a, i, j, k);
+    int R[3] = {i, j, k}, L[3] = {i, j, k};
+    L[a] -= 1;
+    double gphi = 0.0;
+    if (wrap(g, L) && wrap(g, R)) gphi = (phi[cid(g, R[0], R[1], R[2])] - phi[cid(g, L[0], L[1], L[2])]) / g.h;
+    umac[f] = uadv[f] - gphi;
+}
+
+void launch_mac_update(Ctx* c)
+{
+    const GridD& g = c->g;
+    for (int a = 0; a < g.dim; ++a)
+        k_mac_update<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(g, a, c->uadv, c->macphi, c->umac);
+}
+
+// convective term A = sum_a mean(u^MAC_a) (q~_hi - q~_lo)/h with the full
+// states upwinded by u^MAC, and b = u - dt A + dt (-G p + E + f)
+__global__ void k_advect_rhs(GridD g, double dt, double ulid, double f0, double f1, double f2,
+                             const double* __restrict__ sc, const double* __restrict__ u,
+                             const double* __restrict__ umac, const double* __restrict__ qLf,
+                             const double* __restrict__ qRf, const double* __restrict__ Gp,
+                             const double* __restrict__ E, long nf, double* __restrict__ b, double* __restrict__ conv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const int d = g.dim;
+    const long N = ncells(g), q0 = cid(g, i, j, k);
+    const double delta = deadband(sc, ulid);
+    double A[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) {
+        int hi[3] = {i, j, k};
+        hi[a] += 1;
+        if (g.per[a] && hi[a] == g.n[a]) hi[a] = 0;
+        const long flo = foffset(g, a) + fid(g, a, i, j, k);
+        const long fhi = foffset(g, a) + fid(g, a, hi[0], hi[1], hi[2]);
+        const double ulo = umac[flo], uhi = umac[fhi];
+        for (int q = 0; q < d; ++q) {
+            const double tlo = upwind(ulo, qLf[q * nf + flo], qRf[q * nf + flo], delta);
+            const double thi = upwind(uhi, qLf[q * nf + fhi], qRf[q * nf + fhi], delta);
+            A[q] += 0.5 * (ulo + uhi) * (thi - tlo) / g.h;
+        }
+    }
+    for (int q = 0; q < d; ++q) {
+        const long e = q * N + q0;
+        const double f = q == 0 ? f0 : (q == 1 ? f1 : f2);
+        b[e] = u[e] - dt * A[q] + dt * (-Gp[e] + E[e] + f);
+        if (conv) conv[e] = A[q];
+    }
+}
+
+void launch_advect_rhs(Ctx* c, const double* u, double dt, double* b, double* conv)
+{
+    k_advect_rhs<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(
+        c->g, dt, c->ulid, c->fl.f[0], c->fl.f[1], c->fl.f[2], c->sc, u, c->umac, c->qLf, c->qRf, c->Gp, c->E, c->nf, b, conv);
+}
+
+// ---------------------------------------------------------------------------
+// approximate projection
+// ---------------------------------------------------------------------------
+
+// r_k = sum over cells touching node k of sum_a s_a (h/2)^(d-1) V_a, where
+// V = ustar/dt + G p (or V itself when dt == 0 and Gp == nullptr)
+template <bool PROJ>
+__global__ void k_weak_div(GridD g, double dt, const double* __restrict__ V, const double* __restrict__ Gp,
+                           double* __restrict__ r)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= nnode(g, 0) || j >= nnode(g, 1)) return;
+    const int d = g.dim;
+    const long N = ncells(g);
+    const double w = d == 2 ? 0.5 * g.h : (0.5 * g.h) * (0.5 * g.h);
+    const int node[3] = {i, j, k};
+    double s = 0.0;
+    for (int me = 0; me < (1 << d); ++me) {     // node is corner `me` of the cell
+        int cc[3] = {0, 0, 0};
+        bool ok = true;
+        for (int a = 0; a < d; ++a) {
+            int v = node[a] - ((me >> a) & 1);
+            if (v < 0) { if (g.per[a]) v += g.n[a]; else ok = false; }
+            if (v >= g.n[a]) ok = false;
+            cc[a] = v;
+        }
+        if (!ok) continue;
+        const long q = cid(g, cc[0], cc[1], cc[2]);
+        double t = 0.0;
+        for (int a = 0; a < d; ++a) {
+            const double sg = ((me >> a) & 1) ? 1.0 : -1.0;
+            const double Va = PROJ ? V[a * N + q] / dt + Gp[a * N + q] : V[a * N + q];
+            t += sg * w * Va;
+        }
+        s += t;
+    }
+    r[nid(g, i, j, k)] = s;
+}
+
+void launch_proj_rhs(Ctx* c, const double* ustar, double dt, double* r)
+{
+    const GridD& g = c->g;
+    k_weak_div<true><<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, dt, ustar, c->Gp, r);
+}
+
+void launch_weak_div(Ctx* c, const double* V, double* r)
+{
+    const GridD& g = c->g;
+    k_weak_div<false><<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, 0.0, V, nullptr, r);
+}
+
+// u = ustar + dt (G p - G phi)
+__global__ void k_proj_update(GridD g, double dt, const double* __restrict__ ustar, const double* __restrict__ Gp,
+                              const double* __restrict__ phi, double* __restrict__ u)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long N = ncells(g), q = cid(g, i, j, k);
+    for (int a = 0; a < g.dim; ++a) {
+        const double gphi = grad_node_at(g, phi, a, i, j, k);
+        u[a * N + q] = ustar[a * N + q] + dt * (Gp[a * N + q] - gphi);
+    }
+}
+
+void launch_proj_update(Ctx* c, const double* ustar, const double* phi, double dt, double* u)
+{
+    k_proj_update<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, dt, ustar, c->Gp, phi, u);
+}
+
+}  // namespace hb

@@ -1,0 +1,343 @@
+// hb_visc.hip -- regularised viscosity and the coupled tensor viscous
+// operator (I - dt div(beta gamma_dot(.))) with its multigrid kernels.
+// gfx950, FP64.  One thread per cell (or cell pair for red-black sweeps);
+// x is the fastest index, so a wavefront reads 64 consecutive doubles.
+#include "hb_internal.h"
+
+namespace hb {
+
+static const dim3 kBlk(64, 4, 1);
+
+// ---------------------------------------------------------------------------
+// apparent viscosity (Sec. III.B, eq:dimensionless:herschel-bulkley)
+// ---------------------------------------------------------------------------
+
+__device__ inline double eta_of_g(const FluidD& fl, double g)
+{
+    const double x = fl.Pa * g;
+    // (1 - e^{-x})/x through expm1: no cancellation for small x, 1 at x = 0
+    const double phi = (x == 0.0) ? 1.0 : -expm1(-x) / x;
+    if (fl.reg == HB_REG_YIELD_ONLY) return pow(g, fl.n - 1.0) + 0.5 * fl.HB * fl.Pa * phi;
+    return (pow(g, fl.n) + 0.5 * fl.HB) * fl.Pa * phi;
+}
+
+__global__ void k_viscosity(GridD g, FluidD fl, const double* __restrict__ u, double* __restrict__ eta)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long N = ncells(g);
+    double G[3][3];
+    for (int a = 0; a < g.dim; ++a)
+        for (int c = 0; c < g.dim; ++c) {
+            int p[3] = {i, j, k}, m[3] = {i, j, k};
+            p[a] += 1;
+            m[a] -= 1;
+            const double* q = u + (long)c * N;
+            G[a][c] = (cval<false>(g, q, c, p[0], p[1], p[2]) - cval<false>(g, q, c, m[0], m[1], m[2])) / (2.0 * g.h);
+        }
+    double s = 0.0;
+    for (int a = 0; a < g.dim; ++a)
+        for (int c = 0; c < g.dim; ++c) {
+            const double e = 0.5 * (G[a][c] + G[c][a]);
+            s += e * e;
+        }
+    eta[cid(g, i, j, k)] = eta_of_g(fl, sqrt(0.5 * s));
+}
+
+void launch_viscosity(Ctx* c, const double* u, double* eta)
+{
+    k_viscosity<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, c->fl, u, eta);
+}
+
+// ---------------------------------------------------------------------------
+// face viscosity: fine faces from cells, coarse faces from fine faces
+// ---------------------------------------------------------------------------
+
+__global__ void k_eta_faces(GridD g, int a, double Re, const double* __restrict__ eta, double* __restrict__ beta)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= fext(g, a, 0) || j >= fext(g, a, 1)) return;
+    int R[3] = {i, j, k}, L[3] = {i, j, k};
+    L[a] -= 1;
+    const bool okL = wrap(g, L), okR = wrap(g, R);
+    double v;
+    if (okL && okR)
+        v = 0.5 * (eta[cid(g, L[0], L[1], L[2])] / Re + eta[cid(g, R[0], R[1], R[2])] / Re);
+    else if (okL)
+        v = eta[cid(g, L[0], L[1], L[2])] / Re;
+    else
+        v = eta[cid(g, R[0], R[1], R[2])] / Re;
+    beta[foffset(g, a) + fid(g, a, i, j, k)] = v;
+}
+
+void launch_eta_faces(Ctx* c, const GridD& g, const double* eta, double* beta)
+{
+    for (int a = 0; a < g.dim; ++a)
+        k_eta_faces<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(g, a, c->fl.Re, eta, beta);
+}
+
+// coarse face = mean of the 2^(d-1) fine faces tiling it
+__global__ void k_restrict_faces(GridD gf, GridD gc, int a, const double* __restrict__ bf, double* __restrict__ bc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= fext(gc, a, 0) || j >= fext(gc, a, 1)) return;
+    const int I[3] = {i, j, k};
+    const double* F = bf + foffset(gf, a);
+    double s = 0.0;
+    int cnt = 0;
+    for (int t = 0; t < (1 << gf.dim); ++t) {
+        if ((t >> a) & 1) continue;
+        int p[3] = {0, 0, 0};
+        for (int b = 0; b < gf.dim; ++b) p[b] = (b == a) ? 2 * I[b] : 2 * I[b] + ((t >> b) & 1);
+        s += F[fid(gf, a, p[0], p[1], p[2])];
+        ++cnt;
+    }
+    bc[foffset(gc, a) + fid(gc, a, i, j, k)] = s / (double)cnt;
+}
+
+void launch_restrict_faces(Ctx* c, const GridD& gf, const GridD& gc, const double* bf, double* bc)
+{
+    for (int a = 0; a < gf.dim; ++a)
+        k_restrict_faces<<<grid3(fext(gc, a, 0), fext(gc, a, 1), fext(gc, a, 2), kBlk), kBlk, 0, c->s>>>(gf, gc, a, bf, bc);
+}
+
+// ---------------------------------------------------------------------------
+// tensor flux and divergence
+// ---------------------------------------------------------------------------
+
+// value of component c; ZI: the interior is zero and only wall values remain
+template <bool HOM, bool ZI>
+__device__ inline double uval(const GridD& g, const double* __restrict__ u, int c, int i, int j, int k)
+{
+    if (!ZI) return cval<HOM>(g, u + (long)c * ncells(g), c, i, j, k);
+    int p[3] = {i, j, k};
+    for (int a = 0; a < g.dim; ++a) {
+        if (p[a] >= 0 && p[a] < g.n[a]) continue;
+        if (g.per[a]) continue;
+        return 2.0 * g.wall_u[a][p[a] < 0 ? 0 : 1][c];
+    }
+    return 0.0;
+}
+
+// flux of component c through the face normal to a whose hi-side cell is
+// (i,j,k): beta (du_c/dx_a + du_a/dx_c)/2 with the transverse derivative
+// averaged from the two cells' centred differences (zero on wall faces)
+template <bool HOM, bool ZI>
+__device__ inline double visc_flux(const GridD& g, const double* __restrict__ beta, const double* __restrict__ u,
+                                   int c, int a, int i, int j, int k)
+{
+    int R[3] = {i, j, k}, L[3] = {i, j, k};
+    L[a] -= 1;
+    const bool wall = !g.per[a] && (R[a] == 0 || R[a] == g.n[a]);
+    int fp[3] = {i, j, k};
+    if (g.per[a] && fp[a] == g.n[a]) fp[a] = 0;
+    const double bf = beta[foffset(g, a) + fid(g, a, fp[0], fp[1], fp[2])];
+    const double uR = uval<HOM, ZI>(g, u, c, R[0], R[1], R[2]);
+    const double uL = uval<HOM, ZI>(g, u, c, L[0], L[1], L[2]);
+    const double dn = (uR - uL) / g.h;
+    if (a == c) return bf * dn;
+    if (wall) return bf * 0.5 * dn;
+    wrap(g, R);
+    wrap(g, L);
+    int Lp[3] = {L[0], L[1], L[2]}, Lm[3] = {L[0], L[1], L[2]};
+    int Rp[3] = {R[0], R[1], R[2]}, Rm[3] = {R[0], R[1], R[2]};
+    Lp[c] += 1; Lm[c] -= 1; Rp[c] += 1; Rm[c] -= 1;
+    const double dL = (uval<HOM, ZI>(g, u, a, Lp[0], Lp[1], Lp[2]) - uval<HOM, ZI>(g, u, a, Lm[0], Lm[1], Lm[2])) / (2.0 * g.h);
+    const double dR = (uval<HOM, ZI>(g, u, a, Rp[0], Rp[1], Rp[2]) - uval<HOM, ZI>(g, u, a, Rm[0], Rm[1], Rm[2])) / (2.0 * g.h);
+    const double cross = 0.5 * (dL + dR);
+    return bf * 0.5 * (dn + cross);
+}
+
+template <bool HOM, bool ZI>
+__device__ inline double visc_div_at(const GridD& g, const double* __restrict__ beta, const double* __restrict__ u,
+                                     int c, int i, int j, int k)
+{
+    double s = 0.0;
+    for (int a = 0; a < g.dim; ++a) {
+        int hi[3] = {i, j, k};
+        hi[a] += 1;
+        s += (visc_flux<HOM, ZI>(g, beta, u, c, a, hi[0], hi[1], hi[2]) - visc_flux<HOM, ZI>(g, beta, u, c, a, i, j, k)) / g.h;
+    }
+    return s;
+}
+
+// diagonal of the homogeneous operator for component c
+__device__ inline double visc_diag(const GridD& g, const double* __restrict__ beta, double dt, int c, int i, int j, int k)
+{
+    double coef = 0.0;
+    for (int a = 0; a < g.dim; ++a)
+        for (int side = 0; side < 2; ++side) {
+            int q[3] = {i, j, k};
+            q[a] += side;
+            const bool wall = !g.per[a] && (q[a] == 0 || q[a] == g.n[a]);
+            if (g.per[a] && q[a] == g.n[a]) q[a] = 0;
+            const double bf = beta[foffset(g, a) + fid(g, a, q[0], q[1], q[2])];
+            const double s = (a == c) ? 1.0 : 0.5;
+            coef += (wall ? 2.0 : 1.0) * s * bf;
+        }
+    return 1.0 + dt * coef / (g.h * g.h);
+}
+
+__global__ void k_visc_div(GridD g, const double* __restrict__ beta, const double* __restrict__ u, double* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long N = ncells(g), q = cid(g, i, j, k);
+    for (int c = 0; c < g.dim; ++c) out[c * N + q] = visc_div_at<false, false>(g, beta, u, c, i, j, k);
+}
+
+void launch_visc_div(Ctx* c, const GridD& g, const double* beta, const double* u, double* out)
+{
+    k_visc_div<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, beta, u, out);
+}
+
+// out = rhs + dt div(beta gamma_dot(0 with wall values)): the inhomogeneous
+// wall part of the operator moved to the right-hand side
+__global__ void k_visc_wall_rhs(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ rhs,
+                                double* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long N = ncells(g), q = cid(g, i, j, k);
+    for (int c = 0; c < g.dim; ++c)
+        out[c * N + q] = rhs[c * N + q] + dt * visc_div_at<false, true>(g, beta, nullptr, c, i, j, k);
+}
+
+void launch_visc_wall_rhs(Ctx* c, const GridD& g, const double* beta, double dt, const double* rhs, double* out)
+{
+    k_visc_wall_rhs<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, beta, dt, rhs, out);
+}
+
+// ---------------------------------------------------------------------------
+// multigrid kernels of the tensor problem
+// ---------------------------------------------------------------------------
+
+// red-black Gauss-Seidel half sweep on one component: the same-component
+// stencil is 5/7-point, so cells of one colour only read the other colour of
+// that component and the (unchanged) other components
+__global__ void k_visc_rb(GridD g, const double* __restrict__ beta, double dt, int c, int colour,
+                          double* __restrict__ x, const double* __restrict__ b)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    const int i = 2 * t + ((j + k + colour) & 1);
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long q = (long)c * ncells(g) + cid(g, i, j, k);
+    const double Au = x[q] - dt * visc_div_at<true, false>(g, beta, x, c, i, j, k);
+    const double dg = visc_diag(g, beta, dt, c, i, j, k);
+    x[q] += (b[q] - Au) / dg;
+}
+
+void launch_visc_rb(Ctx* c, const Level& l, double dt, int comp, int colour)
+{
+    k_visc_rb<<<grid3((l.g.n[0] + 1) / 2, l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, comp, colour, l.x, l.b);
+}
+
+__global__ void k_visc_resid(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ x,
+                             const double* __restrict__ b, double* __restrict__ r, double* __restrict__ mx)
+{
+    __shared__ unsigned long long sh[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    unsigned long long m = 0ull;
+    if (i < g.n[0] && j < g.n[1]) {
+        const long N = ncells(g), q = cid(g, i, j, k);
+        for (int c = 0; c < g.dim; ++c) {
+            const double Ax = x[c * N + q] - dt * visc_div_at<true, false>(g, beta, x, c, i, j, k);
+            const double rv = b[c * N + q] - Ax;
+            if (r) r[c * N + q] = rv;
+            { const unsigned long long bv = abits(rv); m = bv > m ? bv : m; }
+        }
+    }
+    if (mx) {
+        m = block_umax(m, sh);
+        if (threadIdx.x + threadIdx.y == 0) atomic_max_bits(mx, m);
+    }
+}
+
+void launch_visc_resid(Ctx* c, const Level& l, double dt, const double* x, const double* b, double* r, int slot)
+{
+    k_visc_resid<<<grid3(l.g.n[0], l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, x, b, r,
+                                                                                 slot >= 0 ? c->sc + slot : nullptr);
+}
+
+__global__ void k_visc_apply(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ x,
+                             double* __restrict__ y)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    const long N = ncells(g), q = cid(g, i, j, k);
+    for (int c = 0; c < g.dim; ++c) y[c * N + q] = x[c * N + q] - dt * visc_div_at<true, false>(g, beta, x, c, i, j, k);
+}
+
+void launch_visc_apply(Ctx* c, const Level& l, double dt, const double* x, double* y)
+{
+    k_visc_apply<<<grid3(l.g.n[0], l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, x, y);
+}
+
+// coarse right-hand side = mean of the fine residuals of the 2^d children;
+// the coarse iterate starts from zero
+__global__ void k_visc_resid_restrict(GridD gf, GridD gc, const double* __restrict__ beta, double dt,
+                                      const double* __restrict__ xf, const double* __restrict__ bf,
+                                      double* __restrict__ bc, double* __restrict__ xc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= gc.n[0] || j >= gc.n[1]) return;
+    const long Nf = ncells(gf), Nc = ncells(gc), qc = cid(gc, i, j, k);
+    const int nch = 1 << gf.dim;
+    for (int c = 0; c < gf.dim; ++c) {
+        double s = 0.0;
+        for (int bits = 0; bits < nch; ++bits) {
+            const int fi = 2 * i + (bits & 1), fj = 2 * j + ((bits >> 1) & 1), fk = gf.dim == 3 ? 2 * k + ((bits >> 2) & 1) : 0;
+            const long qf = c * Nf + cid(gf, fi, fj, fk);
+            const double Ax = xf[qf] - dt * visc_div_at<true, false>(gf, beta, xf, c, fi, fj, fk);
+            s += bf[qf] - Ax;
+        }
+        bc[c * Nc + qc] = s / (double)nch;
+        xc[c * Nc + qc] = 0.0;
+    }
+}
+
+void launch_visc_resid_restrict(Ctx* c, const Level& f, const Level& cl, double dt)
+{
+    k_visc_resid_restrict<<<grid3(cl.g.n[0], cl.g.n[1], cl.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, f.beta, dt, f.x, f.b, cl.b, cl.x);
+}
+
+// dense matrix of the homogeneous operator, column j = A e_j (E holds the
+// N unit vectors, column-major)
+__global__ void k_visc_dense(GridD g, const double* __restrict__ beta, double dt, int N, const double* __restrict__ E,
+                             double* __restrict__ A)
+{
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int col = blockIdx.y;
+    if (row >= N) return;
+    const long Nc = ncells(g);
+    const int c = (int)(row / Nc);
+    const long q = row % Nc;
+    const int i = (int)(q % g.n[0]), j = (int)((q / g.n[0]) % g.n[1]), k = (int)(q / ((long)g.n[0] * g.n[1]));
+    const double* x = E + (long)col * N;
+    A[(long)row * N + col] = x[row] - dt * visc_div_at<true, false>(g, beta, x, c, i, j, k);
+}
+
+void launch_visc_dense(Ctx* c, const Level& l, double dt, int N, double* E, double* A)
+{
+    k_visc_dense<<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, l.beta, dt, N, E, A);
+}
+
+}  // namespace hb

@@ -1,0 +1,269 @@
+"""Python binding of the HIP library ``libhb.so`` (C ABI in include/hb.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  Arrays are torch tensors on the GPU (float64,
+contiguous); torch provides device memory and the stream.  The library is
+loaded after torch so both use the same HIP runtime.  If the library is
+missing this module raises: there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhb.so")
+
+OK, ERR_ARG, ERR_DEVICE, ERR_NOCONV, ERR_NONFINITE, ERR_OOM = 0, -1, -2, -3, -4, -5
+BC_WALL, BC_PERIODIC = 0, 1
+REG_PAPER, REG_YIELD_ONLY = 0, 1
+OP_VISC, OP_NODAL, OP_MAC = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+ERR_NAMES = {OK: "HB_OK", ERR_ARG: "HB_ERR_ARG", ERR_DEVICE: "HB_ERR_DEVICE",
+             ERR_NOCONV: "HB_ERR_NOCONV", ERR_NONFINITE: "HB_ERR_NONFINITE", ERR_OOM: "HB_ERR_OOM"}
+
+# symbols declared in include/hb.h
+EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_solve",
+           "hb_advect", "hb_project", "hb_cfl_dt", "hb_step"]
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double),
+                ("bc", (C.c_int32 * 2) * 3), ("wall_u", ((C.c_double * 3) * 2) * 3)]
+
+
+class Fluid(C.Structure):
+    _fields_ = [("Re", C.c_double), ("HB", C.c_double), ("n", C.c_double), ("Pa", C.c_double),
+                ("reg", C.c_int32), ("f", C.c_double * 3)]
+
+
+class MGOpts(C.Structure):
+    _fields_ = [("tol_rel", C.c_double), ("max_cycles", C.c_int32), ("fixed_cycles", C.c_int32),
+                ("nu1", C.c_int32), ("nu2", C.c_int32), ("krylov", C.c_int32), ("precision", C.c_int32)]
+
+
+class MGReport(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("rel_resid", C.c_double), ("bnorm", C.c_double)]
+
+
+class StepOpts(C.Structure):
+    _fields_ = [("cfl", C.c_double), ("mac_project", C.c_int32),
+                ("mac", MGOpts), ("visc", MGOpts), ("proj", MGOpts)]
+
+
+class StepReport(C.Structure):
+    _fields_ = [("dt", C.c_double), ("max_u", C.c_double), ("div_mac_rel", C.c_double),
+                ("div_node", C.c_double), ("mac", MGReport), ("visc", MGReport), ("proj", MGReport)]
+
+
+_lib = None
+
+
+def load():
+    """Load libhb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libhb.so is not built (run __graft_entry__.build() or "
+                           "python paper_1803_00417_amd/build.py)")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp = C.c_void_p
+    L.hb_create.argtypes = [P(Grid), P(Fluid), P(StepOpts), vp, P(vp)]
+    L.hb_destroy.argtypes = [vp]
+    L.hb_destroy.restype = None
+    L.hb_last_error.argtypes = [vp]
+    L.hb_last_error.restype = C.c_char_p
+    L.hb_viscosity.argtypes = [vp, vp, vp]
+    L.hb_mg_solve.argtypes = [vp, C.c_int, vp, C.c_double, vp, vp, P(MGOpts), P(MGReport)]
+    L.hb_advect.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp, vp, P(MGReport)]
+    L.hb_project.argtypes = [vp, vp, vp, C.c_double, vp, P(MGReport)]
+    L.hb_cfl_dt.argtypes = [vp, vp, P(C.c_double)]
+    L.hb_step.argtypes = [vp, vp, vp, C.c_double, P(StepReport)]
+    _lib = L
+    return L
+
+
+class HBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERR_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+# ------------------------------------------------------------------ descriptors
+
+def make_grid(dim, n, h=None, bc=None, wall_u=None):
+    g = Grid()
+    g.dim = dim
+    nn = list(n) + [1] * (3 - len(n))
+    for a in range(3):
+        g.n[a] = nn[a] if a < dim else 1
+    g.h = (1.0 / nn[0]) if h is None else h
+    for a in range(3):
+        for s in range(2):
+            g.bc[a][s] = bc[a][s] if (bc is not None and a < dim) else BC_WALL
+            for c in range(3):
+                g.wall_u[a][s][c] = 0.0
+    for (a, s), vel in (wall_u or {}).items():
+        for c in range(len(vel)):
+            g.wall_u[a][s][c] = vel[c]
+    return g
+
+
+def lid_cavity(dim, n, U=1.0):
+    """Unit lid-driven cavity: y-hi lid moving +x (2D), z-hi lid moving +x (3D)."""
+    return make_grid(dim, [n] * dim, 1.0 / n, wall_u={(dim - 1, 1): (U, 0.0, 0.0)})
+
+
+def make_fluid(Re=1.0, HB=0.0, n=1.0, Pa=1e3, reg=REG_PAPER, f=(0.0, 0.0, 0.0)):
+    fl = Fluid()
+    fl.Re, fl.HB, fl.n, fl.Pa, fl.reg = Re, HB, n, Pa, reg
+    for c in range(3):
+        fl.f[c] = f[c] if c < len(f) else 0.0
+    return fl
+
+
+def mg_opts(tol=1e-10, max_cycles=100, fixed=0, nu1=2, nu2=2, krylov=0, precision=PREC_FP64):
+    o = MGOpts()
+    o.tol_rel, o.max_cycles, o.fixed_cycles = tol, max_cycles, fixed
+    o.nu1, o.nu2, o.krylov, o.precision = nu1, nu2, krylov, precision
+    return o
+
+
+def make_step_opts(cfl=0.5, tol=1e-10, max_cycles=100, nu=2, mac_project=1, fixed=0,
+                   visc_krylov=1, precision=PREC_FP64):
+    o = StepOpts()
+    o.cfl = cfl
+    o.mac_project = mac_project
+    for m in (o.mac, o.visc, o.proj):
+        m.tol_rel, m.max_cycles, m.fixed_cycles = tol, max_cycles, fixed
+        m.nu1, m.nu2, m.krylov, m.precision = nu, nu, 0, precision
+    o.visc.krylov = visc_krylov
+    return o
+
+
+def cell_shape(g, comps=1):
+    return (comps, g.n[2], g.n[1], g.n[0])
+
+
+def node_shape(g):
+    nn = []
+    for a in range(3):
+        if a >= g.dim:
+            nn.append(1)
+        else:
+            nn.append(g.n[a] if g.bc[a][0] == BC_PERIODIC else g.n[a] + 1)
+    return (nn[2], nn[1], nn[0])
+
+
+def face_total(g):
+    tot = 0
+    for a in range(g.dim):
+        c = 1
+        for b in range(3):
+            if b == a:
+                c *= g.n[b] if g.bc[b][0] == BC_PERIODIC else g.n[b] + 1
+            else:
+                c *= g.n[b]
+        tot += c
+    return tot
+
+
+# ------------------------------------------------------------------ context
+
+def _ptr(t, numel, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU torch tensor" % name)
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("%s must be contiguous float64" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One grid / fluid / option set on the current GPU and torch stream."""
+
+    def __init__(self, grid, fluid, opts=None, stream=None):
+        L = load()
+        self.grid, self.fluid = grid, fluid
+        self.opts = opts if opts is not None else make_step_opts()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        rc = L.hb_create(C.byref(grid), C.byref(fluid), C.byref(self.opts),
+                         C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise HBError(rc, L.hb_last_error(None).decode())
+        self._h = h
+        g = grid
+        self.ncell = g.n[0] * g.n[1] * g.n[2]
+        self.nvel = g.dim * self.ncell
+        self.nnode = 1
+        for s in node_shape(g):
+            self.nnode *= s
+        self.nface = face_total(g)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != OK and rc not in allow:
+            raise HBError(rc, load().hb_last_error(self._h).decode())
+        return rc
+
+    def error(self):
+        return load().hb_last_error(self._h).decode()
+
+    # -- calls ------------------------------------------------------------
+    def viscosity(self, u, eta):
+        return self._check(load().hb_viscosity(self._h, _ptr(u, self.nvel, "u"), _ptr(eta, self.ncell, "eta")))
+
+    def mg_solve(self, op, eta, dt, rhs, x, opts=None, allow=()):
+        n = {OP_VISC: self.nvel, OP_MAC: self.ncell, OP_NODAL: self.nnode}[op]
+        rep = MGReport()
+        rc = load().hb_mg_solve(self._h, op, _ptr(eta, self.ncell, "eta"), float(dt),
+                                _ptr(rhs, n, "rhs"), _ptr(x, n, "x"),
+                                C.byref(opts) if opts is not None else None, C.byref(rep))
+        self._check(rc, allow)
+        return rep, rc
+
+    def advect(self, u, p, eta, dt, b, umac=None, conv=None):
+        rep = MGReport()
+        rc = load().hb_advect(self._h, _ptr(u, self.nvel, "u"), _ptr(p, self.nnode, "p"),
+                              _ptr(eta, self.ncell, "eta"), float(dt), _ptr(b, self.nvel, "b"),
+                              _ptr(umac, self.nface, "umac"), _ptr(conv, self.nvel, "conv"), C.byref(rep))
+        self._check(rc)
+        return rep
+
+    def project(self, ustar, p, dt, u):
+        rep = MGReport()
+        rc = load().hb_project(self._h, _ptr(ustar, self.nvel, "ustar"), _ptr(p, self.nnode, "p"),
+                               float(dt), _ptr(u, self.nvel, "u"), C.byref(rep))
+        self._check(rc)
+        return rep
+
+    def cfl_dt(self, u):
+        d = C.c_double()
+        self._check(load().hb_cfl_dt(self._h, _ptr(u, self.nvel, "u"), C.byref(d)))
+        return d.value
+
+    def step(self, u, p, dt=0.0, report=True, allow=()):
+        rep = StepReport() if report else None
+        rc = load().hb_step(self._h, _ptr(u, self.nvel, "u"), _ptr(p, self.nnode, "p"), float(dt),
+                            C.byref(rep) if report else None)
+        self._check(rc, allow)
+        return rep
