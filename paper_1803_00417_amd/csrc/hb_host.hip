@@ -404,6 +404,49 @@ static int project_stage(Ctx* c, const double* ustar, double* p, double dt, doub
 
 static bool worse(int rc, int cur) { return cur == HB_OK || (cur == HB_ERR_NOCONV && rc != HB_OK); }
 
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+
+void kt_begin(Ctx* c)
+{
+    KTimer& k = c->ktm;
+    if (k.n == k.cap) kt_harvest(c);
+    (void)hipEventRecord(k.ev[2 * k.n], c->s);
+}
+
+void kt_end(Ctx* c, double bytes)
+{
+    KTimer& k = c->ktm;
+    (void)hipEventRecord(k.ev[2 * k.n + 1], c->s);
+    ++k.n;
+    ++k.launches;
+    k.bytes += bytes;
+}
+
+void kt_harvest(Ctx* c)
+{
+    KTimer& k = c->ktm;
+    if (k.n == 0) return;
+    (void)hipEventSynchronize(k.ev[2 * k.n - 1]);
+    for (int i = 0; i < k.n; ++i) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, k.ev[2 * i], k.ev[2 * i + 1]) == hipSuccess) k.ms += t;
+    }
+    k.n = 0;
+}
+
+static void kt_free(Ctx* c)
+{
+    KTimer& k = c->ktm;
+    if (!k.ev) return;
+    for (int i = 0; i < 2 * k.cap; ++i) (void)hipEventDestroy(k.ev[i]);
+    delete[] k.ev;
+    k.ev = nullptr;
+    k.cap = 0;
+    k.on = false;
+}
+
 }  // namespace hb
 
 using namespace hb;
@@ -422,6 +465,7 @@ void hb_destroy(hb_ctx* ctx)
 {
     if (!ctx) return;
     Ctx* c = ctx;
+    kt_free(c);
     free_mg(c->visc);
     free_mg(c->mac);
     free_mg(c->nodal);
@@ -624,6 +668,43 @@ int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report
     }
     if (hipGetLastError() != hipSuccess) return fail(c, HB_ERR_DEVICE, "kernel launch failed");
     return rc;
+}
+
+int hb_kernel_timing(hb_ctx* ctx, int enable)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = ctx;
+    KTimer& k = c->ktm;
+    if (enable && !k.ev) {
+        const int cap = 2048;
+        k.ev = new (std::nothrow) hipEvent_t[2 * cap];
+        if (!k.ev) return fail(c, HB_ERR_OOM, "out of host memory");
+        for (int i = 0; i < 2 * cap; ++i)
+            if (hipEventCreate(&k.ev[i]) != hipSuccess) {
+                k.cap = i / 2;
+                kt_free(c);
+                return fail(c, HB_ERR_DEVICE, "hipEventCreate failed");
+            }
+        k.cap = cap;
+    }
+    if (!enable) kt_harvest(c);
+    k.on = enable != 0;
+    k.n = 0;
+    k.launches = 0;
+    k.ms = 0.0;
+    k.bytes = 0.0;
+    return HB_OK;
+}
+
+int hb_kernel_timing_read(hb_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes)
+{
+    if (!ctx || !launches || !total_ms || !alg_bytes) return HB_ERR_ARG;
+    Ctx* c = ctx;
+    kt_harvest(c);
+    *launches = c->ktm.launches;
+    *total_ms = c->ktm.ms;
+    *alg_bytes = c->ktm.bytes;
+    return HB_OK;
 }
 
 }  // extern "C"

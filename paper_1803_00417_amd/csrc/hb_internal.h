@@ -39,6 +39,15 @@ struct MG {
     double* lvl0_x = nullptr;  // level-0 iterate storage (preconditioner use)
 };
 
+// HIP-event timing of every launch of one kernel (measurement support)
+struct KTimer {
+    bool on = false;
+    int cap = 0, n = 0;
+    hipEvent_t* ev = nullptr;   // 2 * cap events: start/stop pairs
+    long launches = 0;
+    double ms = 0.0, bytes = 0.0;
+};
+
 // scalar slots in ctx->sc (device doubles)
 enum Slot { S_MAX = 0, S_SUM = 1, S_DOT0 = 2, S_DOT1 = 3, S_MAXU = 4, S_MAX2 = 5, S_NSLOT = 8 };
 
@@ -65,8 +74,13 @@ struct Ctx {
     double* sc = nullptr;        // device scalar slots
     double* partial = nullptr;   // reduction partials
     double* hsc = nullptr;       // pinned host mirror of the slots
+    KTimer ktm;                  // timing of the tensor smoother launches
     std::string err;
 };
+
+void kt_begin(Ctx* c);
+void kt_end(Ctx* c, double bytes);
+void kt_harvest(Ctx* c);
 
 // ---- launch helpers --------------------------------------------------------
 inline dim3 grid3(int ex, int ey, int ez, dim3 blk) { return dim3((ex + blk.x - 1) / blk.x, (ey + blk.y - 1) / blk.y, ez); }

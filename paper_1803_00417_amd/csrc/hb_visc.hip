@@ -241,7 +241,17 @@ __global__ void k_visc_rb(GridD g, const double* __restrict__ beta, double dt, i
 
 void launch_visc_rb(Ctx* c, const Level& l, double dt, int comp, int colour)
 {
+    if (c->ktm.on) kt_begin(c);
     k_visc_rb<<<grid3((l.g.n[0] + 1) / 2, l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, comp, colour, l.x, l.b);
+    if (c->ktm.on) {
+        // algorithmic bytes of one half sweep: every component of x and the
+        // face viscosities read once, the active colour of b read and of x
+        // written
+        long nfb = 0;
+        for (int a = 0; a < l.g.dim; ++a) nfb += fcount(l.g, a);
+        const double N = (double)ncells(l.g);
+        kt_end(c, 8.0 * (l.g.dim * N + (double)nfb + N));
+    }
 }
 
 __global__ void k_visc_resid(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ x,

@@ -25,7 +25,8 @@ ERR_NAMES = {OK: "HB_OK", ERR_ARG: "HB_ERR_ARG", ERR_DEVICE: "HB_ERR_DEVICE",
 
 # symbols declared in include/hb.h
 EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_solve",
-           "hb_advect", "hb_project", "hb_cfl_dt", "hb_step"]
+           "hb_advect", "hb_project", "hb_cfl_dt", "hb_step", "hb_kernel_timing",
+           "hb_kernel_timing_read"]
 
 
 class Grid(C.Structure):
@@ -82,6 +83,8 @@ def load():
     L.hb_project.argtypes = [vp, vp, vp, C.c_double, vp, P(MGReport)]
     L.hb_cfl_dt.argtypes = [vp, vp, P(C.c_double)]
     L.hb_step.argtypes = [vp, vp, vp, C.c_double, P(StepReport)]
+    L.hb_kernel_timing.argtypes = [vp, C.c_int]
+    L.hb_kernel_timing_read.argtypes = [vp, P(C.c_int64), P(C.c_double), P(C.c_double)]
     _lib = L
     return L
 
@@ -260,6 +263,15 @@ class Context:
         d = C.c_double()
         self._check(load().hb_cfl_dt(self._h, _ptr(u, self.nvel, "u"), C.byref(d)))
         return d.value
+
+    def kernel_timing(self, enable):
+        self._check(load().hb_kernel_timing(self._h, int(enable)))
+
+    def kernel_timing_read(self):
+        """(launches, total_ms, algorithmic_bytes) of the timed smoother launches"""
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        self._check(load().hb_kernel_timing_read(self._h, C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
 
     def step(self, u, p, dt=0.0, report=True, allow=()):
         rep = StepReport() if report else None

@@ -161,12 +161,14 @@ def test_project_parity(case):
     assert rel_err(host(pd).reshape(p.shape), pn_o) < 1e-8
 
 
-def _run_steps(s, nsteps, dt=0.0, **opt):
+def _run_steps(s, nsteps, dt=0.0, u0_seed=None, **opt):
     go, flo = oracle_objs(s)
     ctx, g, fl = _ctx(s, **opt)
     oo = orc.make_step_opts(**opt)
     d = s["dim"]
     u = np.zeros(orc.cell_shape(go, d))
+    if u0_seed is not None:     # boxes without a moving wall start from a smooth field
+        u = inputs.smooth_cells(u.shape, seed=u0_seed, scale=0.5)
     p = np.zeros(orc.node_shape(go))
     ud, pd = dev(u), dev(p)
     worst = 0.0
@@ -195,7 +197,7 @@ def test_step_parity_cavity2d_64_fifty_steps():
 def test_step_parity_short_runs(case):
     _say("step", case)
     s = CASES[case]()
-    worst, rep, rep_o = _run_steps(s, 5)
+    worst, rep, rep_o = _run_steps(s, 5, u0_seed=31 if case.startswith("per") else None)
     assert worst < 1e-9, worst
 
 
