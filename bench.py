@@ -107,7 +107,7 @@ def main():
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_visc_rb (tensor red-black half sweep, all levels)",
+                "kernel": "k_tsmooth (tensor fused red-black sweep of one component, fine levels)",
                 "launches": launches, "avg_launch_us": 1e3 * kms / max(launches, 1),
                 "alg_bytes_per_launch": kbytes / max(launches, 1)}
     w = inputs.WORKLOADS[a.workload]

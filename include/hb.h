@@ -173,12 +173,12 @@ int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out);
 int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report);
 
 /* Measurement support.  While enabled, every launch of the tensor viscous
- * smoother (the red-black half sweep, all levels) on the context's stream is
- * bracketed by HIP events; hb_kernel_timing_read synchronises, and returns
- * the number of launches, their summed device time and their summed
- * algorithmic bytes (every x component and face viscosity read once, the
- * active colour of b read and of x written, 8-byte words).  Enabling
- * resets the counters. */
+ * smoother (one fused red-black sweep of one velocity component on a fine
+ * multigrid level) on the context's stream is bracketed by HIP events;
+ * hb_kernel_timing_read synchronises, and returns the number of launches,
+ * their summed device time and their summed algorithmic bytes (every x
+ * component and the viscosity coefficients read once, b_c read once, x_c
+ * written once; 8-byte words).  Enabling resets the counters. */
 int hb_kernel_timing(hb_ctx* ctx, int enable);
 int hb_kernel_timing_read(hb_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes);
 

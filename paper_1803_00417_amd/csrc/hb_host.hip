@@ -83,10 +83,9 @@ static int build_mg(Ctx* c, MG& m, int op)
         Level& L = m.L[l];
         L.g = cur;
         L.nu = unknowns(cur, op);
-        if (l > 0) {
-            HB_TRY(dalloc(&L.x, L.nu));
-            HB_TRY(dalloc(&L.b, L.nu));
-        }
+        HB_TRY(dalloc(&L.xb[0], L.nu));
+        HB_TRY(dalloc(&L.xb[1], L.nu));
+        if (l > 0) HB_TRY(dalloc(&L.b, L.nu));
         HB_TRY(dalloc(&L.r, L.nu));
         if (op == HB_OP_VISC) HB_TRY(dalloc(&L.beta, nface_total(cur)));
         ++l;
@@ -102,28 +101,36 @@ static int build_mg(Ctx* c, MG& m, int op)
     }
     m.nlev = l;
     m.ncoarse = (int)m.L[l - 1].nu;
-    if (m.ncoarse > 4096) return fail(c, HB_ERR_ARG, "coarsest multigrid level too large for the dense solve");
+    // The single-workgroup kernel runs the coarsest level (the dense solve).
+    // Running more coarse levels in it was measured slower than one launch per
+    // level: a workgroup is one CU, and the per-cell operator work of a few
+    // thousand cells then outweighs the launch latency it saves.
+    m.tail = m.nlev - 1;
     HB_TRY(dalloc(&m.A, (long)m.ncoarse * m.ncoarse));
     HB_TRY(dalloc(&m.piv, m.ncoarse));
     HB_TRY(dalloc(&m.lvl0_b, m.L[0].nu));
-    HB_TRY(dalloc(&m.lvl0_x, m.L[0].nu));
+    m.L[0].b = m.lvl0_b;
+    if (op == HB_OP_VISC) HB_TRY(dalloc(&m.etae, ncells(c->g)));
+    int rc = tail_setup(c, m);
+    if (rc != HB_OK) return fail(c, rc, "tail set-up failed");
     return HB_OK;
 }
 
 static void free_mg(MG& m)
 {
     for (int l = 0; l < m.nlev; ++l) {
-        if (l > 0) {
-            (void)hipFree(m.L[l].x);
-            (void)hipFree(m.L[l].b);
-        }
+        (void)hipFree(m.L[l].xb[0]);
+        (void)hipFree(m.L[l].xb[1]);
+        if (l > 0) (void)hipFree(m.L[l].b);
         (void)hipFree(m.L[l].r);
         (void)hipFree(m.L[l].beta);
     }
     (void)hipFree(m.A);
     (void)hipFree(m.piv);
     (void)hipFree(m.lvl0_b);
-    (void)hipFree(m.lvl0_x);
+    (void)hipFree(m.etae);
+    (void)hipFree(m.tailargs);
+    if (m.gexec) (void)hipGraphExecDestroy(m.gexec);
 }
 
 __global__ void k_identity(int N, double* E)
@@ -151,6 +158,8 @@ static void factor_coarsest(Ctx* c, MG& m)
 static void visc_setup(Ctx* c, const double* eta, double dt)
 {
     MG& m = c->visc;
+    set_slot(c, S_DT, dt);
+    launch_eta_over_re(c, m.L[0].g, eta, m.etae);
     launch_eta_faces(c, m.L[0].g, eta, m.L[0].beta);
     for (int l = 1; l < m.nlev; ++l) launch_restrict_faces(c, m.L[l - 1].g, m.L[l].g, m.L[l - 1].beta, m.L[l].beta);
     m.dt = dt;
@@ -161,12 +170,19 @@ static void visc_setup(Ctx* c, const double* eta, double dt)
 // V-cycle
 // ---------------------------------------------------------------------------
 
-static void smooth(Ctx* c, MG& m, Level& L, int sweeps)
+// tensor coefficients of level l for the tiled kernels: eta/Re cells on the
+// finest level, face arrays below
+static const double* tcoef(const MG& m, int l) { return l == 0 ? m.etae : m.L[l].beta; }
+
+static void smooth(Ctx* c, MG& m, int l, int sweeps)
 {
+    Level& L = m.L[l];
     for (int s = 0; s < sweeps; ++s) {
         if (m.op == HB_OP_VISC) {
+            // fused red-black sweep per component into the other buffer
             for (int q = 0; q < L.g.dim; ++q)
-                for (int colour = 0; colour < 2; ++colour) launch_visc_rb(c, L, m.dt, q, colour);
+                launch_tsmooth(c, L.g, tcoef(m, l), l == 0, c->sc + S_DT, q, L.xb[L.cur], L.xb[1 - L.cur], L.b);
+            L.cur ^= 1;
         } else if (m.op == HB_OP_MAC) {
             for (int colour = 0; colour < 2; ++colour) launch_mac_rb(c, L, colour);
         } else {
@@ -175,25 +191,67 @@ static void smooth(Ctx* c, MG& m, Level& L, int sweeps)
     }
 }
 
+static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2);
+
+// Levels 1.. of the V-cycle as one HIP graph: the coarse levels are many
+// short launches, so replaying a captured graph removes most of their host
+// launch cost.  All their kernel arguments are fixed (buffers, and dt read
+// from device memory); with an even number of sweeps per cycle every
+// double-buffered level ends the cycle in the buffer it started in.
+static void coarse_graph(Ctx* c, MG& m, int nu1, int nu2)
+{
+    if (!m.gexec || m.gnu1 != nu1 || m.gnu2 != nu2) {
+        if (m.gexec) {
+            (void)hipGraphExecDestroy(m.gexec);
+            m.gexec = nullptr;
+        }
+        if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            m.gfail = true;
+            vcycle(c, m, 1, nu1, nu2);
+            return;
+        }
+        m.capturing = true;
+        vcycle(c, m, 1, nu1, nu2);
+        m.capturing = false;
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamEndCapture(c->s, &graph) == hipSuccess && graph;
+        ok = ok && hipGraphInstantiate(&m.gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!ok) {
+            m.gfail = true;
+            m.gexec = nullptr;
+            vcycle(c, m, 1, nu1, nu2);
+            return;
+        }
+        m.gnu1 = nu1;
+        m.gnu2 = nu2;
+    }
+    (void)hipGraphLaunch(m.gexec, c->s);
+}
+
 static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
 {
     Level& L = m.L[l];
-    if (l == m.nlev - 1) {
-        launch_lu_solve(c, m.ncoarse, m.A, m.piv, L.b, L.x);
+    if (l == m.tail) {
+        launch_tail(c, m, l, nu1, nu2);
+        return;
+    }
+    if (l == 1 && !m.capturing && !m.gfail && m.tail > 1 && (nu1 + nu2) % 2 == 0) {
+        coarse_graph(c, m, nu1, nu2);
         return;
     }
     Level& C = m.L[l + 1];
-    smooth(c, m, L, nu1);
-    if (m.op == HB_OP_VISC) launch_visc_resid_restrict(c, L, C, m.dt);
+    smooth(c, m, l, nu1);
+    if (m.op == HB_OP_VISC) launch_tresid_restr(c, L.g, C.g, tcoef(m, l), l == 0, c->sc + S_DT, L.X(), L.b, C.b, C.X());
     else if (m.op == HB_OP_MAC) launch_mac_resid_restrict(c, L, C);
     else {
-        launch_nodal_resid(c, L, L.x, L.b, L.r, -1);
+        launch_nodal_resid(c, L, L.X(), L.b, L.r, -1);
         launch_nodal_restrict(c, L, C);
     }
     vcycle(c, m, l + 1, nu1, nu2);
     if (m.op == HB_OP_NODAL) launch_nodal_prolong(c, L, C);
     else launch_prolong_cells(c, L, C, m.op == HB_OP_VISC ? L.g.dim : 1, m.op == HB_OP_VISC ? -1.0 : 1.0);
-    smooth(c, m, L, nu2);
+    smooth(c, m, l, nu2);
 }
 
 // r = b - A x on level 0 and its max-norm into slot S_MAX
@@ -201,7 +259,7 @@ static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r)
 {
     set_slot_zero(c, S_MAX);
     const Level& L = m.L[0];
-    if (m.op == HB_OP_VISC) launch_visc_resid(c, L, m.dt, x, b, r, S_MAX);
+    if (m.op == HB_OP_VISC) launch_tresid(c, L.g, m.etae, true, c->sc + S_DT, x, b, r, S_MAX);
     else if (m.op == HB_OP_MAC) launch_mac_resid(c, L, x, b, r, S_MAX);
     else launch_nodal_resid(c, L, x, b, r, S_MAX);
 }
@@ -209,7 +267,7 @@ static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r)
 static void apply0(Ctx* c, MG& m, const double* x, double* y)
 {
     const Level& L = m.L[0];
-    if (m.op == HB_OP_VISC) launch_visc_apply(c, L, m.dt, x, y);
+    if (m.op == HB_OP_VISC) launch_tresid(c, L.g, m.etae, true, c->sc + S_DT, x, nullptr, y, -1);
     else if (m.op == HB_OP_MAC) launch_mac_apply(c, L, x, y);
     else launch_nodal_apply(c, L, x, y);
 }
@@ -218,13 +276,12 @@ static void apply0(Ctx* c, MG& m, const double* x, double* y)
 static void precond(Ctx* c, MG& m, const double* r, double* z, int nu1, int nu2)
 {
     Level& L = m.L[0];
-    double* sx = L.x;
     double* sb = L.b;
     L.b = const_cast<double*>(r);
-    L.x = z;
-    fill(c, z, 0.0, L.nu);
+    L.cur = 0;
+    fill(c, L.X(), 0.0, L.nu);
     vcycle(c, m, 0, nu1, nu2);
-    L.x = sx;
+    copy(c, z, L.X(), L.nu);
     L.b = sb;
 }
 
@@ -240,14 +297,16 @@ static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_m
 {
     Level& L = m.L[0];
     const long n = L.nu;
-    L.x = x;
     L.b = b;
     int cycles = 0, rc = HB_OK;
     double rel = 0.0;
     if (bn == 0.0) {
         fill(c, x, 0.0, n);
     } else if (!o.krylov) {
-        resid0(c, m, x, b, L.r);
+        // the cycles work on the level's double buffer, seeded with x
+        L.cur = 0;
+        copy(c, L.X(), x, n);
+        resid0(c, m, L.X(), b, L.r);
         rel = fetch_max(c) / bn;
         for (;;) {
             if (o.fixed_cycles) {
@@ -258,18 +317,21 @@ static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_m
             }
             vcycle(c, m, 0, o.nu1, o.nu2);
             ++cycles;
-            resid0(c, m, x, b, L.r);
+            resid0(c, m, L.X(), b, L.r);
             rel = fetch_max(c) / bn;
             if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
         }
+        copy(c, x, L.X(), n);
     } else {
+        // BiCGStab with its scalars kept on the device: two host reads per
+        // iteration (the residual norms that decide convergence)
         double *r = c->kr, *rh = c->krh, *p = c->kp, *v = c->kv, *ph = c->kph, *s = c->ks, *sh = c->ksh, *t = c->kt;
         resid0(c, m, x, b, r);
         copy(c, rh, r, n);
         fill(c, p, 0.0, n);
         fill(c, v, 0.0, n);
+        bicg_init_scalars(c);
         rel = fetch_max(c) / bn;
-        double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
         for (;;) {
             if (o.fixed_cycles) {
                 if (cycles >= o.max_cycles) break;
@@ -278,21 +340,19 @@ static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_m
                 if (cycles >= o.max_cycles) { rc = HB_ERR_NOCONV; break; }
             }
             red_dot(c, rh, r, n, S_DOT0);
-            fetch_slots(c);
-            const double rho = c->hsc[S_DOT0];
-            if (rho == 0.0) { rc = HB_ERR_NOCONV; break; }
-            const double beta = (rho / rho_prev) * (alpha / omega);
-            bicg_p(c, p, r, v, beta, omega, n);
+            bicg_beta(c);
+            bicg_p_dev(c, p, r, v, n);
             precond(c, m, p, ph, o.nu1, o.nu2);
             ++cycles;
             apply0(c, m, ph, v);
-            red_dot(c, rh, v, n, S_DOT0);
+            red_dot(c, rh, v, n, S_DOT1);
+            bicg_alpha(c);
+            sub_scaled_max_dev(c, s, r, S_ALPHA, v, n, S_MAX);
             fetch_slots(c);
-            alpha = rho / c->hsc[S_DOT0];
-            sub_scaled_max(c, s, r, alpha, v, n, S_MAX);
-            const double srel = fetch_max(c) / bn;
+            if (c->hsc[S_RHO] == 0.0) { rc = HB_ERR_NOCONV; break; }
+            const double srel = c->hsc[S_MAX] / bn;
             if ((!o.fixed_cycles && srel <= o.tol_rel) || (o.fixed_cycles && cycles >= o.max_cycles)) {
-                axpby(c, x, alpha, ph, 1.0, n);
+                bicg_x_dev(c, x, ph, nullptr, false, n);
                 copy(c, r, s, n);
                 rel = srel;
                 break;
@@ -302,15 +362,13 @@ static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_m
             apply0(c, m, sh, t);
             red_dot(c, t, t, n, S_DOT0);
             red_dot(c, t, s, n, S_DOT1);
+            bicg_omega(c);
+            bicg_x_dev(c, x, ph, sh, true, n);
+            sub_scaled_max_dev(c, r, s, S_OMEGA, t, n, S_MAX);
             fetch_slots(c);
-            const double tt = c->hsc[S_DOT0];
-            omega = tt > 0.0 ? c->hsc[S_DOT1] / tt : 0.0;
-            bicg_x(c, x, ph, sh, alpha, omega, n);
-            sub_scaled_max(c, r, s, omega, t, n, S_MAX);
-            rel = fetch_max(c) / bn;
+            rel = c->hsc[S_MAX] / bn;
             if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
-            if (omega == 0.0) { rc = HB_ERR_NOCONV; break; }
-            rho_prev = rho;
+            if (c->hsc[S_OMEGA] == 0.0) { rc = HB_ERR_NOCONV; break; }
         }
         resid0(c, m, x, b, L.r);
         rel = fetch_max(c) / bn;
@@ -453,6 +511,23 @@ using namespace hb;
 
 struct hb_ctx : public Ctx {};
 
+// Work of an ABI call runs on the library's stream, after everything queued
+// on the caller's stream before the call, and the caller's stream waits for
+// it afterwards.
+struct StreamGuard {
+    Ctx* c;
+    explicit StreamGuard(Ctx* cc) : c(cc)
+    {
+        (void)hipEventRecord(c->ev_in, c->user);
+        (void)hipStreamWaitEvent(c->s, c->ev_in, 0);
+    }
+    ~StreamGuard()
+    {
+        (void)hipEventRecord(c->ev_out, c->s);
+        (void)hipStreamWaitEvent(c->user, c->ev_out, 0);
+    }
+};
+
 extern "C" {
 
 const char* hb_last_error(const hb_ctx* ctx)
@@ -469,11 +544,15 @@ void hb_destroy(hb_ctx* ctx)
     free_mg(c->visc);
     free_mg(c->mac);
     free_mg(c->nodal);
+    if (c->s) (void)hipStreamSynchronize(c->s);
     double* bufs[] = {c->eta, c->E, c->Gp, c->F, c->S, c->trans, c->uhat, c->qhat, c->qLf, c->qRf, c->uadv,
                       c->umac, c->macphi, c->macrhs, c->b, c->ustar, c->rnode, c->phi, c->conv, c->kr, c->krh,
                       c->kp, c->kv, c->kph, c->ks, c->ksh, c->kt, c->dense_E, c->sc, c->partial};
     for (double* p : bufs) (void)hipFree(p);
     if (c->hsc) (void)hipHostFree(c->hsc);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->s) (void)hipStreamDestroy(c->s);
     delete ctx;
 }
 
@@ -504,7 +583,14 @@ int hb_create(const hb_grid* grid, const hb_fluid* fluid, const hb_step_opts* op
     c->grid = *grid;
     c->fluid = *fluid;
     c->opts = *opts;
-    c->s = (hipStream_t)hip_stream;
+    c->user = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+        g_create_err = "stream or event creation failed";
+        hb_destroy(ctx);
+        return HB_ERR_DEVICE;
+    }
     c->g = make_gridd(*grid);
     c->fl.Re = fluid->Re;
     c->fl.HB = fluid->HB;
@@ -566,6 +652,7 @@ int hb_viscosity(hb_ctx* ctx, const double* u, double* eta)
     if (!ctx) return HB_ERR_ARG;
     Ctx* c = ctx;
     if (!u || !eta) return fail(c, HB_ERR_ARG, "null array");
+    StreamGuard guard(c);
     launch_viscosity(c, u, eta);
     return hipGetLastError() == hipSuccess ? HB_OK : fail(c, HB_ERR_DEVICE, "kernel launch failed");
 }
@@ -581,6 +668,7 @@ int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt, const double*
     const hb_mg_opts& o = opts ? *opts : (op == HB_OP_VISC ? c->opts.visc : (op == HB_OP_MAC ? c->opts.mac : c->opts.proj));
     if (!valid_opts(o)) return fail(c, HB_ERR_ARG, "invalid multigrid options");
     MG& m = op == HB_OP_VISC ? c->visc : (op == HB_OP_MAC ? c->mac : c->nodal);
+    StreamGuard guard(c);
     if (op == HB_OP_VISC) {
         visc_setup(c, eta, dt);
         launch_visc_wall_rhs(c, c->g, m.L[0].beta, dt, rhs, m.lvl0_b);
@@ -597,6 +685,7 @@ int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta, 
     Ctx* c = ctx;
     if (!u || !p || !eta || !b) return fail(c, HB_ERR_ARG, "null array");
     if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
+    StreamGuard guard(c);
     red_maxabs(c, u, c->dim * c->nc, S_MAXU);
     visc_setup(c, eta, dt);
     int rc = advect_stage(c, u, p, dt, b, conv, mac_report, nullptr);
@@ -611,6 +700,7 @@ int hb_project(hb_ctx* ctx, const double* ustar, double* p, double dt, double* u
     Ctx* c = ctx;
     if (!ustar || !p || !u) return fail(c, HB_ERR_ARG, "null array");
     if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
+    StreamGuard guard(c);
     return project_stage(c, ustar, p, dt, u, report);
 }
 
@@ -619,6 +709,7 @@ int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out)
     if (!ctx) return HB_ERR_ARG;
     Ctx* c = ctx;
     if (!u || !dt_out) return fail(c, HB_ERR_ARG, "null argument");
+    StreamGuard guard(c);
     red_maxabs(c, u, c->dim * c->nc, S_MAXU);
     fetch_slots(c);
     const double m = std::fmax(c->ulid, c->hsc[S_MAXU]);
@@ -632,6 +723,7 @@ int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report
     if (!ctx) return HB_ERR_ARG;
     Ctx* c = ctx;
     if (!u || !p) return fail(c, HB_ERR_ARG, "null array");
+    StreamGuard guard(c);
     const long nv = c->dim * c->nc;
     red_maxabs(c, u, nv, S_MAXU);
     red_maxabs(c, p, c->nn, S_MAX2);

@@ -18,13 +18,15 @@ struct FluidD {
 struct Level {
     GridD g;
     long nu = 0;             // unknowns of this level
-    double* x = nullptr;     // iterate (level 0: points at the solve's x)
+    double* xb[2] = {nullptr, nullptr};  // double-buffered iterate
+    int cur = 0;             // buffer holding the current iterate
     double* b = nullptr;     // right-hand side
     double* r = nullptr;     // residual scratch
     double* beta = nullptr;  // face viscosity (tensor problem only)
     float* xs = nullptr;     // FP32 shadows for mixed-precision cycles
     float* bs = nullptr;
     float* betas = nullptr;
+    double* X() const { return xb[cur]; }
 };
 
 struct MG {
@@ -36,7 +38,14 @@ struct MG {
     int* piv = nullptr;
     double dt = 0.0;         // tensor problem: dt of the factorised matrix
     double* lvl0_b = nullptr;  // level-0 right-hand side storage
-    double* lvl0_x = nullptr;  // level-0 iterate storage (preconditioner use)
+    double* etae = nullptr;    // tensor problem: eta/Re per fine cell
+    int tail = 0;              // first level handled by the single-workgroup kernel
+    // levels 1.. of a V-cycle captured once as a HIP graph and replayed
+    hipGraphExec_t gexec = nullptr;
+    int gnu1 = -1, gnu2 = -1;
+    bool capturing = false, gfail = false;
+    void* tailargs = nullptr;  // device copy of the tail description
+    size_t tail_lds = 0;       // LDS bytes of the tail kernel
 };
 
 // HIP-event timing of every launch of one kernel (measurement support)
@@ -49,13 +58,20 @@ struct KTimer {
 };
 
 // scalar slots in ctx->sc (device doubles)
-enum Slot { S_MAX = 0, S_SUM = 1, S_DOT0 = 2, S_DOT1 = 3, S_MAXU = 4, S_MAX2 = 5, S_NSLOT = 8 };
+enum Slot {
+    S_MAX = 0, S_SUM = 1, S_DOT0 = 2, S_DOT1 = 3, S_MAXU = 4, S_MAX2 = 5, S_DT = 6,
+    // BiCGStab scalars, computed and used on the device
+    S_RHO = 8, S_RHOP = 9, S_ALPHA = 10, S_OMEGA = 11, S_BETA = 12,
+    S_NSLOT = 16
+};
 
 struct Ctx {
     hb_grid grid;
     hb_fluid fluid;
     hb_step_opts opts;
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr;      // the library's own stream (all work runs here)
+    hipStream_t user = nullptr;   // the caller's stream, ordered with s by events
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     GridD g;                 // finest grid
     FluidD fl;
     int dim = 2;
@@ -92,11 +108,20 @@ void red_sum(Ctx* c, const double* v, long n, int slot);
 void red_dot(Ctx* c, const double* a, const double* b, long n, int slot);
 void fetch_slots(Ctx* c);  // copies all slots to c->hsc and synchronises
 void set_slot_zero(Ctx* c, int slot);
+void set_slot(Ctx* c, int slot, double v);
 void sub_mean(Ctx* c, double* v, long n);   // v -= sum(v)/n (device-side)
 void axpby(Ctx* c, double* y, double a, const double* x, double b, long n);   // y = a x + b y
 void bicg_p(Ctx* c, double* p, const double* r, const double* v, double beta, double omega, long n);
 void sub_scaled_max(Ctx* c, double* out, const double* a, double s, const double* b, long n, int slot);
 void bicg_x(Ctx* c, double* x, const double* ph, const double* sh, double alpha, double omega, long n);
+// device-scalar BiCGStab steps (scalars in the slots S_RHO .. S_BETA)
+void bicg_init_scalars(Ctx* c);
+void bicg_beta(Ctx* c);             // rho = DOT0, beta = (rho/rho_prev)(alpha/omega)
+void bicg_alpha(Ctx* c);            // alpha = rho / DOT1
+void bicg_omega(Ctx* c);            // omega = DOT0 > 0 ? DOT1 / DOT0 : 0; rho_prev = rho
+void bicg_p_dev(Ctx* c, double* p, const double* r, const double* v, long n);
+void sub_scaled_max_dev(Ctx* c, double* out, const double* a, int sslot, const double* b, long n, int mslot);
+void bicg_x_dev(Ctx* c, double* x, const double* ph, const double* sh, bool with_omega, long n);
 void copy(Ctx* c, double* dst, const double* src, long n);
 void fill(Ctx* c, double* dst, double v, long n);
 
@@ -111,6 +136,16 @@ void launch_visc_resid(Ctx* c, const Level& l, double dt, const double* x, const
 void launch_visc_apply(Ctx* c, const Level& l, double dt, const double* x, double* y);
 void launch_visc_resid_restrict(Ctx* c, const Level& f, const Level& cl, double dt);
 void launch_visc_dense(Ctx* c, const Level& l, double dt, int N, double* E, double* A);
+void launch_eta_over_re(Ctx* c, const GridD& g, const double* eta, double* etae);
+
+// LDS-tiled tensor kernels (hb_tile.hip); fine = coef is eta/Re per cell
+// (dt is read from device memory, so a captured graph stays valid across steps)
+void launch_tsmooth(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp,
+                    const double* xcur, double* xnext, const double* b);
+void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, const double* x,
+                   const double* b, double* out, int slot);
+void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const double* coef, bool fine, const double* dtp,
+                         const double* x, const double* b, double* bc, double* xc);
 
 // scalar cell problem (MAC) and nodal problem, transfers, dense (hb_mg.hip)
 void launch_mac_rb(Ctx* c, const Level& l, int colour);
@@ -128,6 +163,12 @@ void launch_nodal_dense(Ctx* c, const Level& l, int N, double* E, double* A);
 void launch_add_ones(Ctx* c, int N, double* A);
 void launch_lu_factor(Ctx* c, int N, double* A, int* piv);
 void launch_lu_solve(Ctx* c, int N, const double* A, const int* piv, const double* b, double* x);
+
+// single-workgroup coarse end of a V-cycle (hb_tail.hip)
+void launch_tail(Ctx* c, const MG& m, int first, int nu1, int nu2);
+int tail_max_levels();
+size_t tail_lds_bytes(const MG& m, int first);
+int tail_setup(Ctx* c, MG& m);
 
 // step stages (hb_step.hip)
 void launch_grad_node(Ctx* c, const double* p, double* Gp);

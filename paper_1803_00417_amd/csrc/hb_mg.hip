@@ -2,6 +2,7 @@
 // and the nodal Q1 projection problem, cell prolongation shared with the
 // tensor problem, and the dense LU of the coarsest level.  gfx950, FP64.
 #include "hb_internal.h"
+#include "hb_ops.h"
 
 namespace hb {
 
@@ -10,22 +11,6 @@ static const dim3 kBlk(64, 4, 1);
 // ---------------------------------------------------------------------------
 // MAC problem: L_mac = D_mac G_mac, zero flux through wall faces
 // ---------------------------------------------------------------------------
-
-// L_mac x at one cell, as the divergence of face gradients
-__device__ inline double mac_lap_at(const GridD& g, const double* __restrict__ x, int i, int j, int k)
-{
-    const double xc = x[cid(g, i, j, k)];
-    double s = 0.0;
-    for (int a = 0; a < g.dim; ++a) {
-        int p[3] = {i, j, k}, m[3] = {i, j, k};
-        p[a] += 1;
-        m[a] -= 1;
-        const double Fhi = wrap(g, p) ? (x[cid(g, p[0], p[1], p[2])] - xc) / g.h : 0.0;
-        const double Flo = wrap(g, m) ? (xc - x[cid(g, m[0], m[1], m[2])]) / g.h : 0.0;
-        s += (Fhi - Flo) / g.h;
-    }
-    return s;
-}
 
 __global__ void k_mac_rb(GridD g, int colour, double* __restrict__ x, const double* __restrict__ b)
 {
@@ -52,7 +37,7 @@ __global__ void k_mac_rb(GridD g, int colour, double* __restrict__ x, const doub
 
 void launch_mac_rb(Ctx* c, const Level& l, int colour)
 {
-    k_mac_rb<<<grid3((l.g.n[0] + 1) / 2, l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, colour, l.x, l.b);
+    k_mac_rb<<<grid3((l.g.n[0] + 1) / 2, l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, colour, l.X(), l.b);
 }
 
 __global__ void k_mac_resid(GridD g, const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
@@ -114,7 +99,7 @@ __global__ void k_mac_resid_restrict(GridD gf, GridD gc, const double* __restric
 
 void launch_mac_resid_restrict(Ctx* c, const Level& f, const Level& cl)
 {
-    k_mac_resid_restrict<<<grid3(cl.g.n[0], cl.g.n[1], cl.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, f.x, f.b, cl.b, cl.x);
+    k_mac_resid_restrict<<<grid3(cl.g.n[0], cl.g.n[1], cl.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, f.X(), f.b, cl.b, cl.X());
 }
 
 __global__ void k_mac_dense(GridD g, int N, const double* __restrict__ E, double* __restrict__ A)
@@ -170,120 +155,12 @@ __global__ void k_prolong_cells(GridD gf, GridD gc, int ncomp, double wall_sign,
 
 void launch_prolong_cells(Ctx* c, const Level& f, const Level& cl, int ncomp, double wall_sign)
 {
-    k_prolong_cells<<<grid3(f.g.n[0], f.g.n[1], f.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, ncomp, wall_sign, cl.x, f.x);
+    k_prolong_cells<<<grid3(f.g.n[0], f.g.n[1], f.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, ncomp, wall_sign, cl.X(), f.X());
 }
 
 // ---------------------------------------------------------------------------
 // nodal problem: Q1 stiffness K (natural boundary on walls)
 // ---------------------------------------------------------------------------
-
-// Element stiffness entry of the Q1 element between local corners p and q,
-// by the number of differing coordinate bits: 2D {2/3, -1/6, -1/3};
-// 3D h {1/3, 0, -1/12, -1/12}.
-__device__ inline double q1_entry(int dim, double h, int hamming)
-{
-    if (dim == 2) return hamming == 0 ? 2.0 / 3.0 : (hamming == 1 ? -1.0 / 6.0 : -1.0 / 3.0);
-    const double v = hamming == 0 ? 1.0 / 3.0 : (hamming == 1 ? 0.0 : -1.0 / 12.0);
-    return v * h;
-}
-
-// (K x) at node (i,j,k) and its diagonal: sum over the existing elements that
-// have this node as a corner
-__device__ inline double K_at(const GridD& g, const double* __restrict__ x, int i, int j, int k, double* diag)
-{
-    const int d = g.dim;
-    const int nc = 1 << d;
-    const int node[3] = {i, j, k};
-    double s = 0.0, dg = 0.0;
-    for (int me = 0; me < nc; ++me) {     // this node is corner `me` of the element
-        int e[3] = {0, 0, 0};
-        bool ok = true;
-        for (int a = 0; a < d; ++a) {
-            int v = node[a] - ((me >> a) & 1);
-            if (v < 0) { if (g.per[a]) v += g.n[a]; else ok = false; }
-            if (v >= g.n[a]) ok = false;
-            e[a] = v;
-        }
-        if (!ok) continue;
-        for (int q = 0; q < nc; ++q) {
-            int p[3] = {0, 0, 0};
-            for (int a = 0; a < d; ++a) {
-                int v = e[a] + ((q >> a) & 1);
-                if (g.per[a] && v == g.n[a]) v = 0;
-                p[a] = v;
-            }
-            s += q1_entry(d, g.h, __popc(me ^ q)) * x[nid(g, p[0], p[1], p[2])];
-        }
-        dg += q1_entry(d, g.h, 0);
-    }
-    if (diag) *diag = dg;
-    return s;
-}
-
-// 2^d-colour Gauss-Seidel: nodes of one colour (i&1)+2(j&1)+4(k&1) share no
-// element, so they update independently
-__global__ void k_nodal_gs(GridD g, int colour, double* __restrict__ x, const double* __restrict__ b)
-{
-    const int ti = blockIdx.x * blockDim.x + threadIdx.x;
-    const int tj = blockIdx.y * blockDim.y + threadIdx.y;
-    const int tk = blockIdx.z;
-    const int i = 2 * ti + (colour & 1);
-    const int j = 2 * tj + ((colour >> 1) & 1);
-    const int k = g.dim == 3 ? 2 * tk + ((colour >> 2) & 1) : 0;
-    if (i >= nnode(g, 0) || j >= nnode(g, 1) || k >= nnode(g, 2)) return;
-    double dg;
-    const double Kx = K_at(g, x, i, j, k, &dg);
-    const long q = nid(g, i, j, k);
-    x[q] += (b[q] - Kx) / dg;
-}
-
-void launch_nodal_gs(Ctx* c, const Level& l, int colour)
-{
-    const GridD& g = l.g;
-    const int ez = g.dim == 3 ? (nnode(g, 2) + 1) / 2 : 1;
-    k_nodal_gs<<<grid3((nnode(g, 0) + 1) / 2, (nnode(g, 1) + 1) / 2, ez, kBlk), kBlk, 0, c->s>>>(g, colour, l.x, l.b);
-}
-
-__global__ void k_nodal_resid(GridD g, const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
-                              double* __restrict__ mx)
-{
-    __shared__ unsigned long long sh[16];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    unsigned long long m = 0ull;
-    if (i < nnode(g, 0) && j < nnode(g, 1)) {
-        const long q = nid(g, i, j, k);
-        const double rv = b[q] - K_at(g, x, i, j, k, nullptr);
-        if (r) r[q] = rv;
-        m = abits(rv);
-    }
-    if (mx) {
-        m = block_umax(m, sh);
-        if (threadIdx.x + threadIdx.y == 0) atomic_max_bits(mx, m);
-    }
-}
-
-void launch_nodal_resid(Ctx* c, const Level& l, const double* x, const double* b, double* r, int slot)
-{
-    const GridD& g = l.g;
-    k_nodal_resid<<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, x, b, r, slot >= 0 ? c->sc + slot : nullptr);
-}
-
-__global__ void k_nodal_apply(GridD g, const double* __restrict__ x, double* __restrict__ y)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= nnode(g, 0) || j >= nnode(g, 1)) return;
-    y[nid(g, i, j, k)] = K_at(g, x, i, j, k, nullptr);
-}
-
-void launch_nodal_apply(Ctx* c, const Level& l, const double* x, double* y)
-{
-    const GridD& g = l.g;
-    k_nodal_apply<<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, x, y);
-}
 
 // full weighting R = P^T from the fine residual r_f; coarse iterate zeroed
 __global__ void k_nodal_restrict(GridD gf, GridD gc, const double* __restrict__ rf, double* __restrict__ bc,
@@ -324,7 +201,7 @@ __global__ void k_nodal_restrict(GridD gf, GridD gc, const double* __restrict__ 
 void launch_nodal_restrict(Ctx* c, const Level& f, const Level& cl)
 {
     const GridD& g = cl.g;
-    k_nodal_restrict<<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(f.g, g, f.r, cl.b, cl.x);
+    k_nodal_restrict<<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(f.g, g, f.r, cl.b, cl.X());
 }
 
 // (bi/tri)linear nodal prolongation x_f += P e_c
@@ -361,22 +238,7 @@ __global__ void k_nodal_prolong(GridD gf, GridD gc, const double* __restrict__ e
 void launch_nodal_prolong(Ctx* c, const Level& f, const Level& cl)
 {
     const GridD& g = f.g;
-    k_nodal_prolong<<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, cl.g, cl.x, f.x);
-}
-
-__global__ void k_nodal_dense(GridD g, int N, const double* __restrict__ E, double* __restrict__ A)
-{
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    const int col = blockIdx.y;
-    if (row >= N) return;
-    const int nx = nnode(g, 0), ny = nnode(g, 1);
-    const int i = row % nx, j = (row / nx) % ny, k = row / (nx * ny);
-    A[(long)row * N + col] = K_at(g, E + (long)col * N, i, j, k, nullptr);
-}
-
-void launch_nodal_dense(Ctx* c, const Level& l, int N, double* E, double* A)
-{
-    k_nodal_dense<<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, N, E, A);
+    k_nodal_prolong<<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, cl.g, cl.X(), f.X());
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,181 @@
+// hb_nodal.hip -- LDS-tiled kernels of the nodal projection problem K x = b
+// (Q1 stiffness, natural boundary on walls): multi-colour Gauss-Seidel and
+// residual.  gfx950, FP64.
+//
+// The assembled stencil is written per node from the element stiffness: the
+// weight of neighbour node+delta is Ke(|delta|_0) times the number of
+// existing elements that contain both nodes, which factors per axis into
+// cnt_a(delta_a) (2 or 1 in the interior and on periodic axes, fewer on a
+// wall).  Ke by the number of differing coordinates: 2D {2/3, -1/6, -1/3},
+// 3D h {1/3, 0, -1/12, -1/12}.
+#include "hb_internal.h"
+#include "hb_ops.h"
+
+namespace hb {
+
+template <int DIM> struct NodalCfg;
+// threads per block (one per node of the active colour); node tile = 2x that
+template <> struct NodalCfg<2> { static constexpr int BX = 64, BY = 4, BZ = 1; };
+template <> struct NodalCfg<3> { static constexpr int BX = 32, BY = 4, BZ = 2; };
+
+template <int DIM>
+struct NTile {
+    static constexpr int TX = 2 * NodalCfg<DIM>::BX, TY = 2 * NodalCfg<DIM>::BY, TZ = DIM == 3 ? 2 * NodalCfg<DIM>::BZ : 1;
+    static constexpr int SX = TX + 2, SY = TY + 2, SZ = DIM == 3 ? TZ + 2 : 1;
+    static constexpr int NS = SX * SY * SZ;
+    static constexpr int THREADS = NodalCfg<DIM>::BX * NodalCfg<DIM>::BY * NodalCfg<DIM>::BZ;
+    __device__ static inline int at(int lx, int ly, int lz) { return (lz * SY + ly) * SX + lx; }
+};
+
+// K x at node G from the LDS tile (local index l), and the diagonal
+template <int DIM>
+__device__ inline double tile_K(const GridD& g, const double* s, const int G[3], int l, double* diag)
+{
+    using T = NTile<DIM>;
+    int cnt[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cnt[a][d] = a < DIM ? node_cnt(g, a, G[a], d - 1) : (d == 1 ? 1 : 0);
+    double acc = 0.0;
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int k = (dx != 0) + (dy != 0) + (dz != 0);
+                const double w = q1_ke(DIM, g.h, k) * (double)(cnt[0][dx + 1] * cnt[1][dy + 1] * cnt[2][dz + 1]);
+                acc += w * s[l + (dz * T::SY + dy) * T::SX + dx];
+            }
+    if (diag) *diag = q1_ke(DIM, g.h, 0) * (double)(cnt[0][1] * cnt[1][1] * cnt[2][1]);
+    return acc;
+}
+
+// stage the node tile plus a 1-node halo; all loads of a thread are issued
+// before any store so they are in flight together
+template <int DIM>
+__device__ inline void fill_nodes(const GridD& g, const double* __restrict__ x, double* s, int ox, int oy, int oz)
+{
+    using T = NTile<DIM>;
+    constexpr int K = (T::NS + T::THREADS - 1) / T::THREADS;
+    double v[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int t = threadIdx.x + u * T::THREADS;
+        const int tt = t < T::NS ? t : 0;
+        const int lx = tt % T::SX, ly = (tt / T::SX) % T::SY, lz = tt / (T::SX * T::SY);
+        v[u] = node_fetch<DIM>(g, x, ox - 1 + lx, oy - 1 + ly, DIM == 3 ? oz - 1 + lz : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int t = threadIdx.x + u * T::THREADS;
+        if (t < T::NS) s[t] = v[u];
+    }
+}
+
+// one colour (i&1) + 2(j&1) + 4(k&1) of the Gauss-Seidel sweep, in place:
+// nodes of one colour share no element
+template <int DIM>
+__global__ void __launch_bounds__(NTile<DIM>::THREADS)
+k_nodal_gs_tile(GridD g, int colour, double* __restrict__ x, const double* __restrict__ b)
+{
+    using T = NTile<DIM>;
+    __shared__ double s[T::NS];
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    fill_nodes<DIM>(g, x, s, ox, oy, oz);
+    __syncthreads();
+    const int tx = threadIdx.x % NodalCfg<DIM>::BX, ty = (threadIdx.x / NodalCfg<DIM>::BX) % NodalCfg<DIM>::BY,
+              tz = threadIdx.x / (NodalCfg<DIM>::BX * NodalCfg<DIM>::BY);
+    const int G[3] = {ox + 2 * tx + (colour & 1), oy + 2 * ty + ((colour >> 1) & 1),
+                      DIM == 3 ? oz + 2 * tz + ((colour >> 2) & 1) : 0};
+    if (G[0] >= nnode(g, 0) || G[1] >= nnode(g, 1) || G[2] >= nnode(g, 2)) return;
+    const int l = T::at(G[0] - ox + 1, G[1] - oy + 1, DIM == 3 ? G[2] - oz + 1 : 0);
+    double dg;
+    const double Kx = tile_K<DIM>(g, s, G, l, &dg);
+    const long q = nid(g, G[0], G[1], G[2]);
+    x[q] = s[l] + (b[q] - Kx) / dg;
+}
+
+// r = b - K x (and its max-norm) or y = K x over all nodes
+template <int DIM>
+__global__ void __launch_bounds__(NTile<DIM>::THREADS)
+k_nodal_resid_tile(GridD g, const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ out,
+                   double* __restrict__ mx)
+{
+    using T = NTile<DIM>;
+    __shared__ double s[T::NS];
+    __shared__ unsigned long long red[16];
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    fill_nodes<DIM>(g, x, s, ox, oy, oz);
+    __syncthreads();
+    unsigned long long m = 0ull;
+    for (int t = threadIdx.x; t < T::TX * T::TY * T::TZ; t += blockDim.x) {
+        const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
+        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
+        if (G[0] >= nnode(g, 0) || G[1] >= nnode(g, 1) || G[2] >= nnode(g, 2)) continue;
+        const int l = T::at(rx + 1, ry + 1, DIM == 3 ? rz + 1 : 0);
+        const double Kx = tile_K<DIM>(g, s, G, l, nullptr);
+        const long q = nid(g, G[0], G[1], G[2]);
+        if (b) {
+            const double rv = b[q] - Kx;
+            if (out) out[q] = rv;
+            const unsigned long long bv = abits(rv);
+            m = bv > m ? bv : m;
+        } else {
+            out[q] = Kx;
+        }
+    }
+    if (mx) {
+        m = block_umax(m, red);
+        if (threadIdx.x == 0) atomic_max_bits(mx, m);
+    }
+}
+
+template <int DIM>
+static dim3 ntile_grid(const GridD& g)
+{
+    using T = NTile<DIM>;
+    return dim3((nnode(g, 0) + T::TX - 1) / T::TX, (nnode(g, 1) + T::TY - 1) / T::TY,
+                DIM == 3 ? (nnode(g, 2) + T::TZ - 1) / T::TZ : 1);
+}
+
+void launch_nodal_gs(Ctx* c, const Level& l, int colour)
+{
+    if (l.g.dim == 2) k_nodal_gs_tile<2><<<ntile_grid<2>(l.g), NTile<2>::THREADS, 0, c->s>>>(l.g, colour, l.X(), l.b);
+    else k_nodal_gs_tile<3><<<ntile_grid<3>(l.g), NTile<3>::THREADS, 0, c->s>>>(l.g, colour, l.X(), l.b);
+}
+
+void launch_nodal_resid(Ctx* c, const Level& l, const double* x, const double* b, double* r, int slot)
+{
+    double* mx = slot >= 0 ? c->sc + slot : nullptr;
+    if (l.g.dim == 2) k_nodal_resid_tile<2><<<ntile_grid<2>(l.g), NTile<2>::THREADS, 0, c->s>>>(l.g, x, b, r, mx);
+    else k_nodal_resid_tile<3><<<ntile_grid<3>(l.g), NTile<3>::THREADS, 0, c->s>>>(l.g, x, b, r, mx);
+}
+
+void launch_nodal_apply(Ctx* c, const Level& l, const double* x, double* y)
+{
+    if (l.g.dim == 2) k_nodal_resid_tile<2><<<ntile_grid<2>(l.g), NTile<2>::THREADS, 0, c->s>>>(l.g, x, nullptr, y, nullptr);
+    else k_nodal_resid_tile<3><<<ntile_grid<3>(l.g), NTile<3>::THREADS, 0, c->s>>>(l.g, x, nullptr, y, nullptr);
+}
+
+// dense coarsest matrix with the same assembled stencil (global reads)
+template <int DIM>
+__global__ void k_nodal_dense(GridD g, int N, const double* __restrict__ E, double* __restrict__ A)
+{
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int col = blockIdx.y;
+    if (row >= N) return;
+    const int nx = nnode(g, 0), ny = nnode(g, 1);
+    const int G[3] = {row % nx, (row / nx) % ny, row / (nx * ny)};
+    const double acc = K_glob<DIM>(g, E + (long)col * N, G[0], G[1], G[2], nullptr);
+    A[(long)row * N + col] = acc;
+}
+
+void launch_nodal_dense(Ctx* c, const Level& l, int N, double* E, double* A)
+{
+    if (l.g.dim == 2) k_nodal_dense<2><<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, N, E, A);
+    else k_nodal_dense<3><<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, N, E, A);
+}
+
+}  // namespace hb

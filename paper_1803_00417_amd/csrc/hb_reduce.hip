@@ -10,6 +10,7 @@ static constexpr int kT = 256;
 __global__ void k_set(double* p, double v) { *p = v; }
 
 void set_slot_zero(Ctx* c, int slot) { k_set<<<1, 1, 0, c->s>>>(c->sc + slot, 0.0); }
+void set_slot(Ctx* c, int slot, double v) { k_set<<<1, 1, 0, c->s>>>(c->sc + slot, v); }
 
 __global__ void k_maxabs(const double* __restrict__ v, long n, double* __restrict__ out)
 {
@@ -165,6 +166,87 @@ void bicg_x(Ctx* c, double* x, const double* ph, const double* sh, double alpha,
 {
     const long nb = (n + kT - 1) / kT;
     k_bicg_x<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(x, ph, sh, alpha, omega, n);
+}
+
+// ---- the same updates with the scalars read from device slots ---------------
+
+__global__ void k_bicg_scalars(double* sc, int which)
+{
+    if (which == 0) {            // initial values
+        sc[S_RHOP] = 1.0;
+        sc[S_ALPHA] = 1.0;
+        sc[S_OMEGA] = 1.0;
+    } else if (which == 1) {     // rho and beta
+        const double rho = sc[S_DOT0];
+        sc[S_RHO] = rho;
+        sc[S_BETA] = (rho / sc[S_RHOP]) * (sc[S_ALPHA] / sc[S_OMEGA]);
+    } else if (which == 2) {     // alpha
+        sc[S_ALPHA] = sc[S_RHO] / sc[S_DOT1];
+    } else {                     // omega from (t.t, t.s); rho_prev = rho
+        const double tt = sc[S_DOT0];
+        sc[S_OMEGA] = tt > 0.0 ? sc[S_DOT1] / tt : 0.0;
+        sc[S_RHOP] = sc[S_RHO];
+    }
+}
+
+void bicg_init_scalars(Ctx* c) { k_bicg_scalars<<<1, 1, 0, c->s>>>(c->sc, 0); }
+void bicg_beta(Ctx* c) { k_bicg_scalars<<<1, 1, 0, c->s>>>(c->sc, 1); }
+void bicg_alpha(Ctx* c) { k_bicg_scalars<<<1, 1, 0, c->s>>>(c->sc, 2); }
+void bicg_omega(Ctx* c) { k_bicg_scalars<<<1, 1, 0, c->s>>>(c->sc, 3); }
+
+__global__ void k_bicg_p_dev(double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
+                             const double* __restrict__ sc, long n)
+{
+    const double beta = sc[S_BETA], omega = sc[S_OMEGA];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+void bicg_p_dev(Ctx* c, double* p, const double* r, const double* v, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_bicg_p_dev<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(p, r, v, c->sc, n);
+}
+
+__global__ void k_sub_scaled_max_dev(double* __restrict__ out, const double* __restrict__ a, const double* __restrict__ sp,
+                                     const double* __restrict__ b, long n, double* __restrict__ mx)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    const double s = *sp;
+    unsigned long long m = 0ull;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = a[i] - s * b[i];
+        out[i] = v;
+        const unsigned long long bb = abits(v);
+        m = bb > m ? bb : m;
+    }
+    m = block_umax(m, sh);
+    if (threadIdx.x == 0) atomic_max_bits(mx, m);
+}
+
+void sub_scaled_max_dev(Ctx* c, double* out, const double* a, int sslot, const double* b, long n, int mslot)
+{
+    set_slot_zero(c, mslot);
+    const long nb = (n + kT - 1) / kT;
+    k_sub_scaled_max_dev<<<(unsigned)(nb < kRedBlocks ? nb : kRedBlocks), kT, 0, c->s>>>(out, a, c->sc + sslot, b, n,
+                                                                                           c->sc + mslot);
+}
+
+// x += alpha ph + omega sh (with_omega), or x = alpha ph + x
+__global__ void k_bicg_x_dev(double* __restrict__ x, const double* __restrict__ ph, const double* __restrict__ sh_,
+                             const double* __restrict__ sc, int with_omega, long n)
+{
+    const double alpha = sc[S_ALPHA], omega = sc[S_OMEGA];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        if (with_omega) x[i] += alpha * ph[i] + omega * sh_[i];
+        else x[i] = alpha * ph[i] + 1.0 * x[i];
+    }
+}
+
+void bicg_x_dev(Ctx* c, double* x, const double* ph, const double* sh, bool with_omega, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_bicg_x_dev<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(x, ph, sh, c->sc, with_omega ? 1 : 0, n);
 }
 
 }  // namespace hb

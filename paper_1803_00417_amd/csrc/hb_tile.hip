@@ -1,0 +1,484 @@
+// hb_tile.hip -- LDS-tiled kernels of the tensor viscous problem for the
+// fine multigrid levels (gfx950, FP64):
+//   k_tsmooth       one component's red AND black Gauss-Seidel half sweeps in
+//                   one launch: the tile plus a 2-cell halo of every component
+//                   is staged in LDS, red cells are updated on the tile and its
+//                   1-cell ring, black cells on the tile; the result goes to
+//                   the other buffer of a double-buffered iterate, so blocks
+//                   never read values another block has already written;
+//   k_tresid        r = b - A x (max-norm reduced) or y = A x, halo 1;
+//   k_tresid_restr  fine residual and its restriction (mean of children).
+// Boundary values (odd wall reflection, periodic wrap) are produced once, when
+// the tile is filled; the stencil then reads plain LDS offsets.
+// The arithmetic per cell is the same sequence as the global-memory kernels,
+// so results do not depend on the tiling.
+#include "hb_internal.h"
+
+namespace hb {
+
+template <int DIM> struct TileCfg;
+template <> struct TileCfg<2> { static constexpr int TX = 64, TY = 8, TZ = 1, THREADS = 256; };
+template <> struct TileCfg<3> { static constexpr int TX = 32, TY = 4, TZ = 4, THREADS = 512; };
+
+
+// Homogeneous (ghost = -mirror) or periodic value of component array q at a
+// global position that may lie outside the box; positions outside along two
+// or more wall axes (never used by the stencil) read as 0.  With MIRROR the
+// wall ghost is the mirrored value itself (used for the viscosity tile).
+template <int DIM>
+__device__ inline double tile_fetch(const GridD& g, const double* __restrict__ q, int i, int j, int k, bool mirror)
+{
+    int p[3] = {i, j, k};
+    int out = 0;
+    double sg = 1.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int n = g.n[a];
+        if (p[a] >= 0 && p[a] < n) continue;
+        if (g.per[a]) {
+            p[a] = p[a] < 0 ? p[a] + n : p[a] - n;
+            if (p[a] < 0 || p[a] >= n) return 0.0;
+        } else {
+            ++out;
+            p[a] = p[a] < 0 ? -1 - p[a] : 2 * n - 1 - p[a];
+            if (p[a] < 0 || p[a] >= n) return 0.0;
+            sg = -sg;
+        }
+    }
+    if (out > 1) return 0.0;
+    const double v = q[cid(g, p[0], p[1], p[2])];
+    return mirror ? v : sg * v;
+}
+
+// LDS tile with halo H around the interior box starting at (ox, oy, oz);
+// array q at local (lx, ly, lz) is s[q * NS + (lz * SY + ly) * SX + lx]
+template <int DIM, int H>
+struct Tile {
+    static constexpr int TX = TileCfg<DIM>::TX, TY = TileCfg<DIM>::TY, TZ = TileCfg<DIM>::TZ;
+    static constexpr int HZ = DIM == 3 ? H : 0;
+    static constexpr int SX = TX + 2 * H, SY = TY + 2 * H, SZ = TZ + 2 * HZ;
+    static constexpr int NS = SX * SY * SZ;
+    __device__ static inline int at(int lx, int ly, int lz) { return (lz * SY + ly) * SX + lx; }
+};
+
+// Stage NA arrays (tile plus halo H) in LDS.  Every thread first issues all
+// of its global loads into registers, then stores them, so the loads of a
+// block are in flight together instead of one round trip per element.
+template <int DIM, int H, int NA>
+__device__ inline void fill_batched(const GridD& g, const double* const* q, const bool* mirror, double* s,
+                                    int ox, int oy, int oz)
+{
+    using T = Tile<DIM, H>;
+    constexpr int TH = TileCfg<DIM>::THREADS;
+    constexpr int K = (T::NS + TH - 1) / TH;
+    // tiles away from every domain face need no boundary logic
+    const bool inner = ox - H >= 0 && ox + T::TX + H <= g.n[0] && oy - H >= 0 && oy + T::TY + H <= g.n[1] &&
+                       (DIM == 2 || (oz - H >= 0 && oz + T::TZ + H <= g.n[2]));
+    double v[NA][K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int t = threadIdx.x + u * TH;
+        const int tt = t < T::NS ? t : 0;
+        const int lx = tt % T::SX, ly = (tt / T::SX) % T::SY, lz = tt / (T::SX * T::SY);
+        const int i = ox - H + lx, j = oy - H + ly, k = DIM == 3 ? oz - H + lz : 0;
+        if (inner) {
+            const long idx = cid(g, i, j, k);
+#pragma unroll
+            for (int a = 0; a < NA; ++a) v[a][u] = q[a][idx];
+        } else {
+#pragma unroll
+            for (int a = 0; a < NA; ++a) v[a][u] = tile_fetch<DIM>(g, q[a], i, j, k, mirror[a]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int t = threadIdx.x + u * TH;
+        if (t < T::NS)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) s[a * T::NS + t] = v[a][u];
+    }
+}
+
+// bit (2a + side) set when face `side` (0 lo, 1 hi) of the cell along a is a
+// wall face
+template <int DIM>
+__device__ inline int wall_mask(const GridD& g, const int G[3])
+{
+    int m = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        if (g.per[a]) continue;
+        if (G[a] == 0) m |= 1 << (2 * a);
+        if (G[a] == g.n[a] - 1) m |= 2 << (2 * a);
+    }
+    return m;
+}
+
+// face viscosity from the level's face arrays (coarse levels)
+__device__ inline double face_beta_global(const GridD& g, const double* __restrict__ beta, int a, const int G[3], int side)
+{
+    int R[3] = {G[0], G[1], G[2]};
+    R[a] += side;
+    if (g.per[a] && R[a] == g.n[a]) R[a] = 0;
+    return beta[foffset(g, a) + fid(g, a, R[0], R[1], R[2])];
+}
+
+// div(beta gamma_dot(x))_c at a cell of an LDS tile, and the diagonal of the
+// homogeneous operator.  FINE: face viscosities from the eta/Re tile `e`
+// (mean of the two cells, the interior cell on wall faces); otherwise from
+// the global face arrays.  Same arithmetic sequence per face as the
+// global-memory operator.
+template <int DIM, int H, bool FINE>
+__device__ inline double tile_visc_div(const GridD& g, const double* __restrict__ beta, const double* s,
+                                       const double* e, int c, const int G[3], int wm, int l0, double dt,
+                                       double* diag)
+{
+    using T = Tile<DIM, H>;
+    const int off[3] = {1, T::SX, T::SX * T::SY};
+    const double* sc = s + c * T::NS;
+    double acc = 0.0, coefsum = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double flux[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int lL = l0 + (side - 1) * off[a];
+            const int lR = lL + off[a];
+            const bool wall = (wm >> (2 * a + side)) & 1;
+            double bf;
+            if (FINE) bf = wall ? e[l0] : 0.5 * (e[lL] + e[lR]);
+            else bf = face_beta_global(g, beta, a, G, side);
+            const double dn = (sc[lR] - sc[lL]) / g.h;
+            double f;
+            if (a == c) {
+                f = bf * dn;
+            } else if (wall) {
+                f = bf * 0.5 * dn;
+            } else {
+                const double* sa = s + a * T::NS;
+                const double dL = (sa[lL + off[c]] - sa[lL - off[c]]) / (2.0 * g.h);
+                const double dR = (sa[lR + off[c]] - sa[lR - off[c]]) / (2.0 * g.h);
+                const double cross = 0.5 * (dL + dR);
+                f = bf * 0.5 * (dn + cross);
+            }
+            flux[side] = f;
+            coefsum += (wall ? 2.0 : 1.0) * ((a == c) ? 1.0 : 0.5) * bf;
+        }
+        acc += (flux[1] - flux[0]) / g.h;
+    }
+    if (diag) *diag = 1.0 + dt * coefsum / (g.h * g.h);
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// fused red-black sweep of component c
+// ---------------------------------------------------------------------------
+
+// cell of the active colour walked by thread slot t of a region (the tile
+// plus `ring` cells); returns false when t is past the region or the cell lies
+// beyond a wall.  Cells across a periodic boundary are the wrapped cells.
+template <int DIM>
+__device__ inline bool colour_cell(const GridD& g, int t, int ring, int colour, int ox, int oy, int oz, int G[3],
+                                   int L[3])
+{
+    using T = Tile<DIM, 2>;
+    const int RX = T::TX + 2 * ring, RY = T::TY + 2 * ring, RZ = DIM == 3 ? T::TZ + 2 * ring : 1;
+    const int HX = RX / 2;
+    if (t >= HX * RY * RZ) return false;
+    const int px = t % HX, ry = (t / HX) % RY, rz = t / (HX * RY);
+    const int y0 = oy - ring + ry, z0 = DIM == 3 ? oz - ring + rz : 0, x0 = ox - ring;
+    const int rx = 2 * px + ((x0 + y0 + z0 + colour) & 1);
+    G[0] = x0 + rx;
+    G[1] = y0;
+    G[2] = z0;
+    L[0] = rx - ring + 2;
+    L[1] = ry - ring + 2;
+    L[2] = DIM == 3 ? rz - ring + 2 : 0;
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        if (G[a] >= 0 && G[a] < g.n[a]) continue;
+        if (g.per[a]) G[a] = G[a] < 0 ? G[a] + g.n[a] : G[a] - g.n[a];
+        if (G[a] < 0 || G[a] >= g.n[a]) inside = false;
+    }
+    return inside;
+}
+
+template <int DIM, bool FINE>
+__global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
+k_tsmooth(GridD g, const double* __restrict__ coef, const double* __restrict__ dtp, int c,
+          const double* __restrict__ xcur, const double* xnext_in, double* xnext, const double* __restrict__ b)
+{
+    const double dt = *dtp;
+    using T = Tile<DIM, 2>;
+    constexpr int TH = TileCfg<DIM>::THREADS;
+    constexpr int RZ1 = DIM == 3 ? T::TZ + 2 : 1;
+    constexpr int KR = ((T::TX + 2) / 2 * (T::TY + 2) * RZ1 + TH - 1) / TH;   // red slots per thread
+    constexpr int KB = (T::TX / 2 * T::TY * T::TZ + TH - 1) / TH;            // black slots per thread
+    extern __shared__ double s[];
+    double* e = s + DIM * T::NS;     // eta/Re tile (FINE)
+    const long N = ncells(g);
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    const double* bc = b + c * N;
+    // this thread's cells of each colour, and their right-hand sides
+    int rG[KR][3], rL[KR];
+    bool rOk[KR];
+    double rB[KR];
+#pragma unroll
+    for (int u = 0; u < KR; ++u) {
+        int L[3];
+        rOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 1, 0, ox, oy, oz, rG[u], L);
+        rL[u] = T::at(L[0], L[1], L[2]);
+        rB[u] = rOk[u] ? bc[cid(g, rG[u][0], rG[u][1], rG[u][2])] : 0.0;
+    }
+    int kG[KB][3], kL[KB];
+    bool kOk[KB];
+    double kB[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+        int L[3];
+        kOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 0, 1, ox, oy, oz, kG[u], L);
+        kL[u] = T::at(L[0], L[1], L[2]);
+        kB[u] = kOk[u] ? bc[cid(g, kG[u][0], kG[u][1], kG[u][2])] : 0.0;
+    }
+    // components already swept in this sweep live in the next buffer
+    {
+        const double* q[DIM + 1];
+        bool mir[DIM + 1];
+        for (int a = 0; a < DIM; ++a) { q[a] = (a < c ? xnext_in : xcur) + a * N; mir[a] = false; }
+        q[DIM] = coef;
+        mir[DIM] = true;
+        fill_batched<DIM, 2, DIM + (FINE ? 1 : 0)>(g, q, mir, s, ox, oy, oz);
+    }
+    __syncthreads();
+    double* sc = s + c * T::NS;
+    // red cells of the tile and its 1-cell ring, then black cells of the
+    // tile; a cell of one colour reads only the other colour of component c
+    // (face neighbours) and the other components, so each colour is updated
+    // in place
+#pragma unroll
+    for (int u = 0; u < KR; ++u) {
+        if (!rOk[u]) continue;
+        double dg;
+        const double vd = tile_visc_div<DIM, 2, FINE>(g, coef, s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
+        const double Au = sc[rL[u]] - dt * vd;
+        sc[rL[u]] += (rB[u] - Au) / dg;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+        if (!kOk[u]) continue;
+        double dg;
+        const double vd = tile_visc_div<DIM, 2, FINE>(g, coef, s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
+        const double Au = sc[kL[u]] - dt * vd;
+        sc[kL[u]] += (kB[u] - Au) / dg;
+    }
+    __syncthreads();
+    // write the tile's cells of component c
+    double* xo = xnext + c * N;
+    for (int t = threadIdx.x; t < T::TX * T::TY * T::TZ; t += blockDim.x) {
+        const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
+        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
+        if (G[0] >= g.n[0] || G[1] >= g.n[1] || G[2] >= g.n[2]) continue;
+        xo[cid(g, G[0], G[1], G[2])] = sc[T::at(rx + 2, ry + 2, DIM == 3 ? rz + 2 : 0)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// residual / operator application / residual + restriction (halo 1)
+// ---------------------------------------------------------------------------
+
+template <int DIM, bool FINE>
+__global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
+k_tresid(GridD g, const double* __restrict__ coef, const double* __restrict__ dtp, const double* __restrict__ x,
+         const double* __restrict__ b, double* __restrict__ out, double* __restrict__ mx)
+{
+    const double dt = *dtp;
+    using T = Tile<DIM, 1>;
+    extern __shared__ double s[];
+    double* e = s + DIM * T::NS;
+    __shared__ unsigned long long red[16];
+    const long N = ncells(g);
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    {
+        const double* q[DIM + 1];
+        bool mir[DIM + 1];
+        for (int a = 0; a < DIM; ++a) { q[a] = x + a * N; mir[a] = false; }
+        q[DIM] = coef;
+        mir[DIM] = true;
+        fill_batched<DIM, 1, DIM + (FINE ? 1 : 0)>(g, q, mir, s, ox, oy, oz);
+    }
+    __syncthreads();
+    unsigned long long m = 0ull;
+    for (int t = threadIdx.x; t < T::TX * T::TY * T::TZ; t += blockDim.x) {
+        const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
+        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
+        if (G[0] >= g.n[0] || G[1] >= g.n[1] || G[2] >= g.n[2]) continue;
+        const int l = T::at(rx + 1, ry + 1, DIM == 3 ? rz + 1 : 0);
+        const int wm = wall_mask<DIM>(g, G);
+        const long q0 = cid(g, G[0], G[1], G[2]);
+        for (int c = 0; c < DIM; ++c) {
+            const double vd = tile_visc_div<DIM, 1, FINE>(g, coef, s, e, c, G, wm, l, dt, nullptr);
+            const double Ax = s[c * T::NS + l] - dt * vd;
+            if (b) {
+                const double rv = b[c * N + q0] - Ax;
+                if (out) out[c * N + q0] = rv;
+                const unsigned long long bv = abits(rv);
+                m = bv > m ? bv : m;
+            } else {
+                out[c * N + q0] = Ax;
+            }
+        }
+    }
+    if (mx) {
+        m = block_umax(m, red);
+        if (threadIdx.x == 0) atomic_max_bits(mx, m);
+    }
+}
+
+template <int DIM, bool FINE>
+__global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
+k_tresid_restr(GridD g, GridD gc, const double* __restrict__ coef, const double* __restrict__ dtp,
+               const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ bcoarse,
+               double* __restrict__ xcoarse)
+{
+    const double dt = *dtp;
+    using T = Tile<DIM, 1>;
+    extern __shared__ double s[];
+    double* e = s + DIM * T::NS;
+    double* r = e + T::NS;   // residual of the tile, [c][tile cell]
+    constexpr int NT = T::TX * T::TY * T::TZ;
+    const long N = ncells(g), Nc = ncells(gc);
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    {
+        const double* q[DIM + 1];
+        bool mir[DIM + 1];
+        for (int a = 0; a < DIM; ++a) { q[a] = x + a * N; mir[a] = false; }
+        q[DIM] = coef;
+        mir[DIM] = true;
+        fill_batched<DIM, 1, DIM + (FINE ? 1 : 0)>(g, q, mir, s, ox, oy, oz);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < NT; t += blockDim.x) {
+        const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
+        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
+        if (G[0] >= g.n[0] || G[1] >= g.n[1] || G[2] >= g.n[2]) continue;
+        const int l = T::at(rx + 1, ry + 1, DIM == 3 ? rz + 1 : 0);
+        const int wm = wall_mask<DIM>(g, G);
+        const long q0 = cid(g, G[0], G[1], G[2]);
+        for (int c = 0; c < DIM; ++c) {
+            const double vd = tile_visc_div<DIM, 1, FINE>(g, coef, s, e, c, G, wm, l, dt, nullptr);
+            const double Ax = s[c * T::NS + l] - dt * vd;
+            r[c * NT + t] = b[c * N + q0] - Ax;
+        }
+    }
+    __syncthreads();
+    constexpr int CX = T::TX / 2, CY = T::TY / 2, CZ = DIM == 3 ? T::TZ / 2 : 1;
+    constexpr int nch = 1 << DIM;
+    for (int t = threadIdx.x; t < CX * CY * CZ; t += blockDim.x) {
+        const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
+        const int C[3] = {ox / 2 + cx, oy / 2 + cy, DIM == 3 ? oz / 2 + cz : 0};
+        if (C[0] >= gc.n[0] || C[1] >= gc.n[1] || C[2] >= gc.n[2]) continue;
+        const long qc = cid(gc, C[0], C[1], C[2]);
+        for (int c = 0; c < DIM; ++c) {
+            double sum = 0.0;
+            for (int bits = 0; bits < nch; ++bits) {
+                const int fx = 2 * cx + (bits & 1), fy = 2 * cy + ((bits >> 1) & 1), fz = DIM == 3 ? 2 * cz + ((bits >> 2) & 1) : 0;
+                sum += r[c * NT + (fz * T::TY + fy) * T::TX + fx];
+            }
+            bcoarse[c * Nc + qc] = sum / (double)nch;
+            xcoarse[c * Nc + qc] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <int DIM>
+static dim3 tile_grid(const GridD& g)
+{
+    using T = Tile<DIM, 1>;
+    return dim3((g.n[0] + T::TX - 1) / T::TX, (g.n[1] + T::TY - 1) / T::TY, DIM == 3 ? (g.n[2] + T::TZ - 1) / T::TZ : 1);
+}
+
+template <int DIM, bool FINE>
+static void tsmooth_impl(Ctx* c, const GridD& g, const double* coef, const double* dtp, int comp, const double* xcur,
+                         double* xnext, const double* b)
+{
+    const size_t lds = sizeof(double) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 2>::NS;
+    k_tsmooth<DIM, FINE><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, coef, dtp, comp, xcur, xnext, xnext, b);
+}
+
+void launch_tsmooth(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp, const double* xcur,
+                    double* xnext, const double* b)
+{
+    const bool timed = c->ktm.on && fine;
+    if (timed) kt_begin(c);
+    if (g.dim == 2) {
+        if (fine) tsmooth_impl<2, true>(c, g, coef, dtp, comp, xcur, xnext, b);
+        else tsmooth_impl<2, false>(c, g, coef, dtp, comp, xcur, xnext, b);
+    } else if (fine) {
+        tsmooth_impl<3, true>(c, g, coef, dtp, comp, xcur, xnext, b);
+    } else {
+        tsmooth_impl<3, false>(c, g, coef, dtp, comp, xcur, xnext, b);
+    }
+    if (timed) {
+        // algorithmic bytes of one fused red-black sweep of one component:
+        // every component of x and the coefficients (eta/Re per cell on the
+        // finest level, face viscosities below) read once, b_c read once, x_c
+        // written once
+        const double N = (double)ncells(g);
+        double coefw = N;
+        if (!fine) {
+            coefw = 0.0;
+            for (int a = 0; a < g.dim; ++a) coefw += (double)fcount(g, a);
+        }
+        kt_end(c, 8.0 * (g.dim * N + coefw + 2.0 * N));
+    }
+}
+
+template <int DIM, bool FINE>
+static void tresid_impl(Ctx* c, const GridD& g, const double* coef, const double* dtp, const double* x, const double* b,
+                        double* out, double* mx)
+{
+    const size_t lds = sizeof(double) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 1>::NS;
+    k_tresid<DIM, FINE><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, coef, dtp, x, b, out, mx);
+}
+
+void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, const double* x, const double* b,
+                   double* out, int slot)
+{
+    double* mx = slot >= 0 ? c->sc + slot : nullptr;
+    if (g.dim == 2) {
+        if (fine) tresid_impl<2, true>(c, g, coef, dtp, x, b, out, mx);
+        else tresid_impl<2, false>(c, g, coef, dtp, x, b, out, mx);
+    } else {
+        if (fine) tresid_impl<3, true>(c, g, coef, dtp, x, b, out, mx);
+        else tresid_impl<3, false>(c, g, coef, dtp, x, b, out, mx);
+    }
+}
+
+template <int DIM, bool FINE>
+static void tresid_restr_impl(Ctx* c, const GridD& g, const GridD& gc, const double* coef, const double* dtp,
+                              const double* x, const double* b, double* bc, double* xc)
+{
+    using T = Tile<DIM, 1>;
+    const size_t lds = sizeof(double) * (DIM * (T::NS + T::TX * T::TY * T::TZ) + T::NS);
+    k_tresid_restr<DIM, FINE><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, gc, coef, dtp, x, b, bc, xc);
+}
+
+void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const double* coef, bool fine, const double* dtp,
+                         const double* x, const double* b, double* bc, double* xc)
+{
+    if (g.dim == 2) {
+        if (fine) tresid_restr_impl<2, true>(c, g, gc, coef, dtp, x, b, bc, xc);
+        else tresid_restr_impl<2, false>(c, g, gc, coef, dtp, x, b, bc, xc);
+    } else {
+        if (fine) tresid_restr_impl<3, true>(c, g, gc, coef, dtp, x, b, bc, xc);
+        else tresid_restr_impl<3, false>(c, g, gc, coef, dtp, x, b, bc, xc);
+    }
+}
+
+}  // namespace hb

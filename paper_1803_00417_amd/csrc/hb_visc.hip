@@ -3,6 +3,7 @@
 // gfx950, FP64.  One thread per cell (or cell pair for red-black sweeps);
 // x is the fastest index, so a wavefront reads 64 consecutive doubles.
 #include "hb_internal.h"
+#include "hb_ops.h"
 
 namespace hb {
 
@@ -111,79 +112,6 @@ void launch_restrict_faces(Ctx* c, const GridD& gf, const GridD& gc, const doubl
 // tensor flux and divergence
 // ---------------------------------------------------------------------------
 
-// value of component c; ZI: the interior is zero and only wall values remain
-template <bool HOM, bool ZI>
-__device__ inline double uval(const GridD& g, const double* __restrict__ u, int c, int i, int j, int k)
-{
-    if (!ZI) return cval<HOM>(g, u + (long)c * ncells(g), c, i, j, k);
-    int p[3] = {i, j, k};
-    for (int a = 0; a < g.dim; ++a) {
-        if (p[a] >= 0 && p[a] < g.n[a]) continue;
-        if (g.per[a]) continue;
-        return 2.0 * g.wall_u[a][p[a] < 0 ? 0 : 1][c];
-    }
-    return 0.0;
-}
-
-// flux of component c through the face normal to a whose hi-side cell is
-// (i,j,k): beta (du_c/dx_a + du_a/dx_c)/2 with the transverse derivative
-// averaged from the two cells' centred differences (zero on wall faces)
-template <bool HOM, bool ZI>
-__device__ inline double visc_flux(const GridD& g, const double* __restrict__ beta, const double* __restrict__ u,
-                                   int c, int a, int i, int j, int k)
-{
-    int R[3] = {i, j, k}, L[3] = {i, j, k};
-    L[a] -= 1;
-    const bool wall = !g.per[a] && (R[a] == 0 || R[a] == g.n[a]);
-    int fp[3] = {i, j, k};
-    if (g.per[a] && fp[a] == g.n[a]) fp[a] = 0;
-    const double bf = beta[foffset(g, a) + fid(g, a, fp[0], fp[1], fp[2])];
-    const double uR = uval<HOM, ZI>(g, u, c, R[0], R[1], R[2]);
-    const double uL = uval<HOM, ZI>(g, u, c, L[0], L[1], L[2]);
-    const double dn = (uR - uL) / g.h;
-    if (a == c) return bf * dn;
-    if (wall) return bf * 0.5 * dn;
-    wrap(g, R);
-    wrap(g, L);
-    int Lp[3] = {L[0], L[1], L[2]}, Lm[3] = {L[0], L[1], L[2]};
-    int Rp[3] = {R[0], R[1], R[2]}, Rm[3] = {R[0], R[1], R[2]};
-    Lp[c] += 1; Lm[c] -= 1; Rp[c] += 1; Rm[c] -= 1;
-    const double dL = (uval<HOM, ZI>(g, u, a, Lp[0], Lp[1], Lp[2]) - uval<HOM, ZI>(g, u, a, Lm[0], Lm[1], Lm[2])) / (2.0 * g.h);
-    const double dR = (uval<HOM, ZI>(g, u, a, Rp[0], Rp[1], Rp[2]) - uval<HOM, ZI>(g, u, a, Rm[0], Rm[1], Rm[2])) / (2.0 * g.h);
-    const double cross = 0.5 * (dL + dR);
-    return bf * 0.5 * (dn + cross);
-}
-
-template <bool HOM, bool ZI>
-__device__ inline double visc_div_at(const GridD& g, const double* __restrict__ beta, const double* __restrict__ u,
-                                     int c, int i, int j, int k)
-{
-    double s = 0.0;
-    for (int a = 0; a < g.dim; ++a) {
-        int hi[3] = {i, j, k};
-        hi[a] += 1;
-        s += (visc_flux<HOM, ZI>(g, beta, u, c, a, hi[0], hi[1], hi[2]) - visc_flux<HOM, ZI>(g, beta, u, c, a, i, j, k)) / g.h;
-    }
-    return s;
-}
-
-// diagonal of the homogeneous operator for component c
-__device__ inline double visc_diag(const GridD& g, const double* __restrict__ beta, double dt, int c, int i, int j, int k)
-{
-    double coef = 0.0;
-    for (int a = 0; a < g.dim; ++a)
-        for (int side = 0; side < 2; ++side) {
-            int q[3] = {i, j, k};
-            q[a] += side;
-            const bool wall = !g.per[a] && (q[a] == 0 || q[a] == g.n[a]);
-            if (g.per[a] && q[a] == g.n[a]) q[a] = 0;
-            const double bf = beta[foffset(g, a) + fid(g, a, q[0], q[1], q[2])];
-            const double s = (a == c) ? 1.0 : 0.5;
-            coef += (wall ? 2.0 : 1.0) * s * bf;
-        }
-    return 1.0 + dt * coef / (g.h * g.h);
-}
-
 __global__ void k_visc_div(GridD g, const double* __restrict__ beta, const double* __restrict__ u, double* __restrict__ out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,17 +169,7 @@ __global__ void k_visc_rb(GridD g, const double* __restrict__ beta, double dt, i
 
 void launch_visc_rb(Ctx* c, const Level& l, double dt, int comp, int colour)
 {
-    if (c->ktm.on) kt_begin(c);
-    k_visc_rb<<<grid3((l.g.n[0] + 1) / 2, l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, comp, colour, l.x, l.b);
-    if (c->ktm.on) {
-        // algorithmic bytes of one half sweep: every component of x and the
-        // face viscosities read once, the active colour of b read and of x
-        // written
-        long nfb = 0;
-        for (int a = 0; a < l.g.dim; ++a) nfb += fcount(l.g, a);
-        const double N = (double)ncells(l.g);
-        kt_end(c, 8.0 * (l.g.dim * N + (double)nfb + N));
-    }
+    k_visc_rb<<<grid3((l.g.n[0] + 1) / 2, l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, comp, colour, l.X(), l.b);
 }
 
 __global__ void k_visc_resid(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ x,
@@ -326,7 +244,7 @@ __global__ void k_visc_resid_restrict(GridD gf, GridD gc, const double* __restri
 
 void launch_visc_resid_restrict(Ctx* c, const Level& f, const Level& cl, double dt)
 {
-    k_visc_resid_restrict<<<grid3(cl.g.n[0], cl.g.n[1], cl.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, f.beta, dt, f.x, f.b, cl.b, cl.x);
+    k_visc_resid_restrict<<<grid3(cl.g.n[0], cl.g.n[1], cl.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, f.beta, dt, f.X(), f.b, cl.b, cl.X());
 }
 
 // dense matrix of the homogeneous operator, column j = A e_j (E holds the
@@ -348,6 +266,18 @@ __global__ void k_visc_dense(GridD g, const double* __restrict__ beta, double dt
 void launch_visc_dense(Ctx* c, const Level& l, double dt, int N, double* E, double* A)
 {
     k_visc_dense<<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, l.beta, dt, N, E, A);
+}
+
+__global__ void k_eta_over_re(long n, double Re, const double* __restrict__ eta, double* __restrict__ etae)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) etae[i] = eta[i] / Re;
+}
+
+void launch_eta_over_re(Ctx* c, const GridD& g, const double* eta, double* etae)
+{
+    const long n = ncells(g);
+    k_eta_over_re<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(n, c->fl.Re, eta, etae);
 }
 
 }  // namespace hb
