@@ -105,12 +105,12 @@ def main():
     value = r["ncell"] * r["steps"] / r["T"]
     launches, kms, kbytes = r["kt"]
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
+    w = inputs.WORKLOADS[a.workload]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_tsmooth (tensor fused red-black sweep of one component, fine levels)",
+                "kernel": ("k_tsmooth (2D: fused red-black sweep of one velocity component, finest level)" if w["dim"] == 2 else "k_trb3 (3D: one colour of one velocity component, finest level)"),
                 "launches": launches, "avg_launch_us": 1e3 * kms / max(launches, 1),
                 "alg_bytes_per_launch": kbytes / max(launches, 1)}
-    w = inputs.WORKLOADS[a.workload]
     out = {"metric": "cell-steps/s", "value": value, "unit": "cell-steps/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * r["T"] / r["steps"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",

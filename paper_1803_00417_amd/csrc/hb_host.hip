@@ -178,11 +178,18 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps)
 {
     Level& L = m.L[l];
     for (int s = 0; s < sweeps; ++s) {
-        if (m.op == HB_OP_VISC) {
-            // fused red-black sweep per component into the other buffer
+        if (m.op == HB_OP_VISC && (L.g.dim == 2 || l > 0)) {
+            // fused red-black sweep per component into the other buffer (2D,
+            // and the small 3D levels, where it halves the launches)
             for (int q = 0; q < L.g.dim; ++q)
                 launch_tsmooth(c, L.g, tcoef(m, l), l == 0, c->sc + S_DT, q, L.xb[L.cur], L.xb[1 - L.cur], L.b);
             L.cur ^= 1;
+        } else if (m.op == HB_OP_VISC) {
+            // finest 3D level: one colour of one component per launch, in
+            // place (a 2-cell halo is costly on a 3D tile)
+            for (int q = 0; q < L.g.dim; ++q)
+                for (int colour = 0; colour < 2; ++colour)
+                    launch_trb3(c, L.g, tcoef(m, l), l == 0, c->sc + S_DT, q, colour, L.X(), L.b);
         } else if (m.op == HB_OP_MAC) {
             for (int colour = 0; colour < 2; ++colour) launch_mac_rb(c, L, colour);
         } else {

@@ -142,6 +142,8 @@ void launch_eta_over_re(Ctx* c, const GridD& g, const double* eta, double* etae)
 // (dt is read from device memory, so a captured graph stays valid across steps)
 void launch_tsmooth(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp,
                     const double* xcur, double* xnext, const double* b);
+void launch_trb3(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp, int colour,
+                 double* x, const double* b);
 void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, const double* x,
                    const double* b, double* out, int slot);
 void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const double* coef, bool fine, const double* dtp,

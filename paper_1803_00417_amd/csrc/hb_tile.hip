@@ -99,6 +99,42 @@ __device__ inline void fill_batched(const GridD& g, const double* const* q, cons
     }
 }
 
+// fill of the 3D halo-1 tile by a 256-thread block (k_trb3)
+template <bool FINE>
+__device__ inline void fill_tile1(const GridD& g, const double* const* q, const bool* mirror, double* s, int ox, int oy,
+                                  int oz)
+{
+    using T = Tile<3, 1>;
+    constexpr int TH = 256;
+    constexpr int NA = FINE ? 4 : 3;
+    constexpr int K = (T::NS + TH - 1) / TH;
+    const bool inner = ox - 1 >= 0 && ox + T::TX + 1 <= g.n[0] && oy - 1 >= 0 && oy + T::TY + 1 <= g.n[1] &&
+                       oz - 1 >= 0 && oz + T::TZ + 1 <= g.n[2];
+    double v[NA][K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int t = threadIdx.x + u * TH;
+        const int tt = t < T::NS ? t : 0;
+        const int lx = tt % T::SX, ly = (tt / T::SX) % T::SY, lz = tt / (T::SX * T::SY);
+        const int i = ox - 1 + lx, j = oy - 1 + ly, k = oz - 1 + lz;
+        if (inner) {
+            const long idx = cid(g, i, j, k);
+#pragma unroll
+            for (int a = 0; a < NA; ++a) v[a][u] = q[a][idx];
+        } else {
+#pragma unroll
+            for (int a = 0; a < NA; ++a) v[a][u] = tile_fetch<3>(g, q[a], i, j, k, mirror[a]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int t = threadIdx.x + u * TH;
+        if (t < T::NS)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) s[a * T::NS + t] = v[a][u];
+    }
+}
+
 // bit (2a + side) set when face `side` (0 lo, 1 hi) of the cell along a is a
 // wall face
 template <int DIM>
@@ -478,6 +514,71 @@ void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const double* 
     } else {
         if (fine) tresid_restr_impl<3, true>(c, g, gc, coef, dtp, x, b, bc, xc);
         else tresid_restr_impl<3, false>(c, g, gc, coef, dtp, x, b, bc, xc);
+    }
+}
+
+}  // namespace hb
+
+namespace hb {
+
+// ---------------------------------------------------------------------------
+// 3D: one colour of one component per launch, updated in place.  The cells
+// of one colour read only the other colour of component c and the other
+// components, none of which change in the launch, so blocks can update their
+// tiles in place without a second buffer; the tile needs a 1-cell halo only.
+// In 3D this needs fewer operator evaluations and less LDS than the fused
+// two-colour sweep (whose 2-cell halo is large relative to a 3D tile).
+// ---------------------------------------------------------------------------
+
+template <bool FINE>
+__global__ void __launch_bounds__(256)
+k_trb3(GridD g, const double* __restrict__ coef, const double* __restrict__ dtp, int c, int colour, double* x,
+       const double* __restrict__ b)
+{
+    using T = Tile<3, 1>;
+    static_assert(T::TX * T::TY * T::TZ / 2 == 256, "one cell of the colour per thread");
+    extern __shared__ double s[];
+    double* e = s + 3 * T::NS;
+    const double dt = *dtp;
+    const long N = ncells(g);
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    // this thread's cell of the colour and its right-hand side
+    const int t = threadIdx.x;
+    const int px = t % (T::TX / 2), ry = (t / (T::TX / 2)) % T::TY, rz = t / (T::TX / 2 * T::TY);
+    const int G[3] = {ox + 2 * px + ((ox + oy + ry + oz + rz + colour) & 1), oy + ry, oz + rz};
+    const bool ok = G[0] < g.n[0] && G[1] < g.n[1] && G[2] < g.n[2];
+    const long q0 = ok ? cid(g, G[0], G[1], G[2]) : 0;
+    const double bv = ok ? b[c * N + q0] : 0.0;
+    {
+        const double* q[4] = {x, x + N, x + 2 * N, coef};
+        const bool mir[4] = {false, false, false, true};
+        fill_tile1<FINE>(g, q, mir, s, ox, oy, oz);
+    }
+    __syncthreads();
+    if (!ok) return;
+    const int l = T::at(G[0] - ox + 1, ry + 1, rz + 1);
+    double dg;
+    const double vd = tile_visc_div<3, 1, FINE>(g, coef, s, e, c, G, wall_mask<3>(g, G), l, dt, &dg);
+    const double xc = s[c * T::NS + l];
+    const double Au = xc - dt * vd;
+    x[c * N + q0] = xc + (bv - Au) / dg;
+}
+
+void launch_trb3(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp, int colour,
+                 double* x, const double* b)
+{
+    using T = Tile<3, 1>;
+    const bool timed = c->ktm.on && fine;
+    if (timed) kt_begin(c);
+    const size_t lds = sizeof(double) * (3 + (fine ? 1 : 0)) * T::NS;
+    const dim3 grid = tile_grid<3>(g);
+    if (fine) k_trb3<true><<<grid, 256, lds, c->s>>>(g, coef, dtp, comp, colour, x, b);
+    else k_trb3<false><<<grid, 256, lds, c->s>>>(g, coef, dtp, comp, colour, x, b);
+    if (timed) {
+        // algorithmic bytes of one half sweep: every component of x and the
+        // coefficients read once, the active colour of b read and of x written
+        const double N = (double)ncells(g);
+        kt_end(c, 8.0 * (3.0 * N + N + N));
     }
 }
 
