@@ -6,10 +6,13 @@ projection, all solves to a relative residual of 1e-10.  The workload is the
 2D 512^2 lid-driven cavity (Herschel-Bulkley n = 0.5, Bi = 10, Re = 1000,
 Pa = 1e4, CFL 0.5) started from rest: W untimed warm-up steps, then K timed
 steps.  value = cells x K / T (cell-steps/s), with the inputs resident in
-HBM.  The 3D 128^3 Bingham cavity is timed the same way and reported beside
-it.  The roofline object describes the tensor smoother (the red-black half
-sweep), timed with HIP events on the library's stream inside the timed
-region; cpu_baseline times the FP64 CPU oracle on a bounded sample.
+HBM, all multigrid cycles in FP64.  Beside it: the same workload with
+mixed-precision cycles (FP32 V-cycles inside FP64 defect correction, same
+1e-10 residual), the n = 1.5 fluid, and the 3D 128^3 Bingham cavity in both
+modes.  The roofline object describes the finest-level tensor smoother,
+timed with HIP events on the library's stream inside the timed region;
+cpu_baseline times the FP64 CPU oracle on the first steps of the workload,
+and the GPU runs of those same steps are compared with it.
 """
 import argparse
 import json
@@ -29,20 +32,27 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cavity2d_512_n0.5")
-    ap.add_argument("--also", default="cavity3d_128", help="second workload ('' for none)")
+    ap.add_argument("--also", default="cavity2d_512_n1.5,cavity3d_128",
+                    help="comma-separated further workloads ('' for none)")
     ap.add_argument("--also-steps", type=int, default=10)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     return ap.parse_args()
 
 
-def run_gpu(name, steps, warmup, timing=True):
-    import torch
+def _context(name, precision):
     from paper_1803_00417_amd import hb, inputs
     w = inputs.WORKLOADS[name]
     g = hb.lid_cavity(w["dim"], w["n"])
     fl = hb.make_fluid(Re=w["Re"], HB=w["HB"], n=w["nidx"], Pa=w["Pa"])
-    ctx = hb.Context(g, fl, hb.make_step_opts(cfl=w["cfl"]))
+    return hb.Context(g, fl, hb.make_step_opts(cfl=w["cfl"], precision=precision)), g, w
+
+
+def run_gpu(name, steps, warmup, precision=0, timing=True):
+    import torch
+    from paper_1803_00417_amd import hb
+    ctx, g, w = _context(name, precision)
     u = torch.zeros(hb.cell_shape(g, w["dim"]), dtype=torch.float64, device="cuda")
     p = torch.zeros(hb.node_shape(g), dtype=torch.float64, device="cuda")
     for k in range(warmup):
@@ -58,8 +68,9 @@ def run_gpu(name, steps, warmup, timing=True):
         cycles[1] += rep.visc.cycles
         cycles[2] += rep.proj.cycles
         if (k + 1) % 10 == 0:
-            print("[bench] %s step %d/%d dt %.3e max|u| %.4f cycles mac/visc/proj %d/%d/%d"
-                  % (name, k + 1, steps, rep.dt, rep.max_u, rep.mac.cycles, rep.visc.cycles, rep.proj.cycles),
+            print("[bench] %s %s step %d/%d dt %.3e max|u| %.4f cycles mac/visc/proj %d/%d/%d"
+                  % (name, "mixed" if precision else "fp64", k + 1, steps, rep.dt, rep.max_u, rep.mac.cycles,
+                     rep.visc.cycles, rep.proj.cycles),
                   file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
@@ -67,10 +78,12 @@ def run_gpu(name, steps, warmup, timing=True):
     ctx.kernel_timing(False)
     ncell = g.n[0] * g.n[1] * g.n[2]
     ctx.close()
-    return dict(T=T, ncell=ncell, steps=steps, cycles=[c / steps for c in cycles], kt=kt)
+    return dict(T=T, ncell=ncell, steps=steps, warmup=warmup, cycles=[c / steps for c in cycles], kt=kt)
 
 
 def cpu_baseline(name, nsteps):
+    """The FP64 oracle on the first nsteps steps of the workload from rest
+    (single thread); returns the record and the oracle's u, p after them."""
     from oracle import orc
     import numpy as np
     from paper_1803_00417_amd import inputs
@@ -85,9 +98,39 @@ def cpu_baseline(name, nsteps):
         rep, rc = orc.step(g, fl, o, u, p)
     T = time.perf_counter() - t0
     ncell = g.n[0] * g.n[1] * g.n[2]
-    return dict(value=ncell * nsteps / T, unit="cell-steps/s", cores=1, kind="oracle",
-                sample="first %d step(s) of the %s workload from rest, single-threaded FP64 C "
-                       "oracle (%.1f s)" % (nsteps, name, T))
+    rec = dict(value=ncell * nsteps / T, unit="cell-steps/s", cores=1, kind="oracle",
+               sample="first %d step(s) of the %s workload from rest, single-threaded FP64 C "
+                      "oracle (%.1f s)" % (nsteps, name, T))
+    return rec, u, p
+
+
+def error_vs_oracle(name, nsteps, precision, u_o, p_o):
+    """max-norm relative difference of u and p after the first nsteps GPU
+    steps from rest against the oracle's"""
+    import numpy as np
+    import torch
+    from paper_1803_00417_amd import hb
+    ctx, g, w = _context(name, precision)
+    u = torch.zeros(hb.cell_shape(g, w["dim"]), dtype=torch.float64, device="cuda")
+    p = torch.zeros(hb.node_shape(g), dtype=torch.float64, device="cuda")
+    for _ in range(nsteps):
+        ctx.step(u, p, report=False)
+    torch.cuda.synchronize()
+    ctx.close()
+    uh = u.cpu().numpy().reshape(u_o.shape)
+    ph = p.cpu().numpy().reshape(p_o.shape)
+    eu = float(np.abs(uh - u_o).max() / max(np.abs(u_o).max(), 1e-300))
+    ep = float(np.abs(ph - p_o).max() / max(np.abs(p_o).max(), np.abs(u_o).max() ** 2))
+    return max(eu, ep)
+
+
+def _summary(r, w):
+    launches, kms, kbytes = r["kt"]
+    ach = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
+    return {"value": r["ncell"] * r["steps"] / r["T"], "unit": "cell-steps/s",
+            "ms_per_step": 1e3 * r["T"] / r["steps"], "steps": r["steps"], "warmup": r["warmup"],
+            "cycles_per_step_mac_visc_proj": r["cycles"], "smoother_GBs": ach, "smoother_frac": ach / HBM_PEAK_GBS,
+            "desc": w["desc"]}
 
 
 def main():
@@ -118,19 +161,30 @@ def main():
            "config": {"workload": w["desc"] + ", from rest, tol 1e-10", "cells": r["ncell"],
                       "cycles_per_step_mac_visc_proj": r["cycles"]},
            "roofline": roofline}
-    if a.also:
-        print("[bench] workload %s: 2 warm-up + %d timed steps" % (a.also, a.also_steps), file=sys.stderr, flush=True)
-        r2 = run_gpu(a.also, a.also_steps, 2)
-        l2, ms2, b2 = r2["kt"]
-        ach2 = (b2 / 1e9) / (ms2 / 1e3) if ms2 > 0 else 0.0
-        out["also"] = {a.also: {"value": r2["ncell"] * r2["steps"] / r2["T"], "unit": "cell-steps/s",
-                                "ms_per_step": 1e3 * r2["T"] / r2["steps"], "steps": r2["steps"], "warmup": 2,
-                                "cycles_per_step_mac_visc_proj": r2["cycles"],
-                                "smoother_GBs": ach2, "smoother_frac": ach2 / HBM_PEAK_GBS,
-                                "desc": inputs.WORKLOADS[a.also]["desc"]}}
+    also = {}
+    runs = [(a.workload, 1)] if not a.no_mixed else []
+    for nm in [x for x in a.also.split(",") if x]:
+        runs.append((nm, 0))
+        if not a.no_mixed:
+            runs.append((nm, 1))
+    for nm, prec in runs:
+        st = a.steps if nm == a.workload else a.also_steps
+        wu = a.warmup if nm == a.workload else 2
+        print("[bench] workload %s (%s): %d warm-up + %d timed steps" % (nm, "mixed" if prec else "fp64", wu, st),
+              file=sys.stderr, flush=True)
+        r2 = run_gpu(nm, st, wu, precision=prec)
+        also["%s_%s" % (nm, "mixed" if prec else "fp64")] = _summary(r2, inputs.WORKLOADS[nm])
+    if also:
+        out["also"] = also
     if not a.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_steps)
+        print("[bench] cpu baseline (oracle, %d steps)" % a.cpu_steps, file=sys.stderr, flush=True)
+        rec, u_o, p_o = cpu_baseline(a.workload, a.cpu_steps)
+        out["cpu_baseline"] = rec
+        # error of the GPU paths against the oracle on those same first steps
+        err = {"steps": a.cpu_steps, "fp64": error_vs_oracle(a.workload, a.cpu_steps, 0, u_o, p_o)}
+        if not a.no_mixed:
+            err["mixed"] = error_vs_oracle(a.workload, a.cpu_steps, 1, u_o, p_o)
+        out["error_vs_oracle"] = err
     print(json.dumps(out), flush=True)
 
 

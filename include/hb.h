@@ -91,8 +91,12 @@ typedef struct {
 /* Multigrid options.  A solve stops when |b - A x|_inf <= tol_rel |b|_inf
  * (checked before the first cycle and after each); fixed_cycles = 1 runs
  * exactly max_cycles V-cycles.  krylov = 1 wraps the V-cycle in BiCGStab
- * (one V-cycle per preconditioner application).  precision selects FP64 or
- * mixed FP32-smoothing / FP64-residual cycles. */
+ * (one V-cycle per preconditioner application).  precision: HB_PREC_FP64
+ * runs every cycle in FP64; HB_PREC_MIXED runs each V-cycle in FP32 (FP32
+ * copies of the coefficients, smoothing, transfers) on the FP64 residual and
+ * adds the correction to the FP64 iterate (defect correction); the residual,
+ * the convergence test, the viscosity and the coarsest dense solve stay FP64,
+ * so the tolerance means the same in both modes. */
 typedef struct {
     double tol_rel;
     int32_t max_cycles, fixed_cycles, nu1, nu2, krylov, precision;

@@ -88,6 +88,11 @@ static int build_mg(Ctx* c, MG& m, int op)
         if (l > 0) HB_TRY(dalloc(&L.b, L.nu));
         HB_TRY(dalloc(&L.r, L.nu));
         if (op == HB_OP_VISC) HB_TRY(dalloc(&L.beta, nface_total(cur)));
+        HB_TRY(dalloc(&L.fx[0], L.nu));
+        HB_TRY(dalloc(&L.fx[1], L.nu));
+        HB_TRY(dalloc(&L.fb, L.nu));
+        if (op == HB_OP_NODAL) HB_TRY(dalloc(&L.fr, L.nu));
+        if (op == HB_OP_VISC && l > 0) HB_TRY(dalloc(&L.fbeta, nface_total(cur)));
         ++l;
         bool can = true;
         for (int a = 0; a < cur.dim; ++a)
@@ -101,36 +106,41 @@ static int build_mg(Ctx* c, MG& m, int op)
     }
     m.nlev = l;
     m.ncoarse = (int)m.L[l - 1].nu;
-    // The single-workgroup kernel runs the coarsest level (the dense solve).
-    // Running more coarse levels in it was measured slower than one launch per
-    // level: a workgroup is one CU, and the per-cell operator work of a few
-    // thousand cells then outweighs the launch latency it saves.
-    m.tail = m.nlev - 1;
     HB_TRY(dalloc(&m.A, (long)m.ncoarse * m.ncoarse));
+    HB_TRY(dalloc(&m.Ainv, (long)m.ncoarse * m.ncoarse));
     HB_TRY(dalloc(&m.piv, m.ncoarse));
     HB_TRY(dalloc(&m.lvl0_b, m.L[0].nu));
     m.L[0].b = m.lvl0_b;
-    if (op == HB_OP_VISC) HB_TRY(dalloc(&m.etae, ncells(c->g)));
-    int rc = tail_setup(c, m);
-    if (rc != HB_OK) return fail(c, rc, "tail set-up failed");
+    if (op == HB_OP_VISC) {
+        HB_TRY(dalloc(&m.etae, ncells(c->g)));
+        HB_TRY(dalloc(&m.etae32, ncells(c->g)));
+    }
     return HB_OK;
 }
 
 static void free_mg(MG& m)
 {
     for (int l = 0; l < m.nlev; ++l) {
-        (void)hipFree(m.L[l].xb[0]);
-        (void)hipFree(m.L[l].xb[1]);
-        if (l > 0) (void)hipFree(m.L[l].b);
-        (void)hipFree(m.L[l].r);
-        (void)hipFree(m.L[l].beta);
+        Level& L = m.L[l];
+        (void)hipFree(L.xb[0]);
+        (void)hipFree(L.xb[1]);
+        if (l > 0) (void)hipFree(L.b);
+        (void)hipFree(L.r);
+        (void)hipFree(L.beta);
+        (void)hipFree(L.fx[0]);
+        (void)hipFree(L.fx[1]);
+        (void)hipFree(L.fb);
+        (void)hipFree(L.fr);
+        (void)hipFree(L.fbeta);
     }
     (void)hipFree(m.A);
+    (void)hipFree(m.Ainv);
     (void)hipFree(m.piv);
     (void)hipFree(m.lvl0_b);
     (void)hipFree(m.etae);
-    (void)hipFree(m.tailargs);
-    if (m.gexec) (void)hipGraphExecDestroy(m.gexec);
+    (void)hipFree(m.etae32);
+    for (int p = 0; p < 2; ++p)
+        if (m.gexec[p]) (void)hipGraphExecDestroy(m.gexec[p]);
 }
 
 __global__ void k_identity(int N, double* E)
@@ -152,6 +162,7 @@ static void factor_coarsest(Ctx* c, MG& m)
     else launch_nodal_dense(c, C, N, c->dense_E, m.A);
     if (m.op != HB_OP_VISC) launch_add_ones(c, N, m.A);
     launch_lu_factor(c, N, m.A, m.piv);
+    launch_lu_inverse(c, N, m.A, m.piv, m.Ainv);
 }
 
 // face viscosities of every level from the cell viscosity eta (not /Re)
@@ -163,7 +174,18 @@ static void visc_setup(Ctx* c, const double* eta, double dt)
     launch_eta_faces(c, m.L[0].g, eta, m.L[0].beta);
     for (int l = 1; l < m.nlev; ++l) launch_restrict_faces(c, m.L[l - 1].g, m.L[l].g, m.L[l - 1].beta, m.L[l].beta);
     m.dt = dt;
+    m.f32_ready = false;
     factor_coarsest(c, m);
+}
+
+// FP32 copies of the tensor coefficients for mixed-precision cycles (the
+// coarsest matrix stays the FP64 one)
+static void ensure_f32(Ctx* c, MG& m)
+{
+    if (m.op != HB_OP_VISC || m.f32_ready) return;
+    to_f32(c, m.etae, m.etae32, nullptr, ncells(m.L[0].g));
+    for (int l = 1; l < m.nlev; ++l) to_f32(c, m.L[l].beta, m.L[l].fbeta, nullptr, nface_total(m.L[l].g));
+    m.f32_ready = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -172,122 +194,142 @@ static void visc_setup(Ctx* c, const double* eta, double dt)
 
 // tensor coefficients of level l for the tiled kernels: eta/Re cells on the
 // finest level, face arrays below
-static const double* tcoef(const MG& m, int l) { return l == 0 ? m.etae : m.L[l].beta; }
+template <typename R> static const R* tcoef(const MG& m, int l);
+template <> const double* tcoef<double>(const MG& m, int l) { return l == 0 ? m.etae : m.L[l].beta; }
+template <> const float* tcoef<float>(const MG& m, int l) { return l == 0 ? m.etae32 : m.L[l].fbeta; }
 
+template <typename R> constexpr int prec_index() { return sizeof(R) == sizeof(double) ? 0 : 1; }
+
+template <typename R>
 static void smooth(Ctx* c, MG& m, int l, int sweeps)
 {
+    using B = LB<R>;
     Level& L = m.L[l];
     for (int s = 0; s < sweeps; ++s) {
         if (m.op == HB_OP_VISC && (L.g.dim == 2 || l > 0)) {
             // fused red-black sweep per component into the other buffer (2D,
             // and the small 3D levels, where it halves the launches)
             for (int q = 0; q < L.g.dim; ++q)
-                launch_tsmooth(c, L.g, tcoef(m, l), l == 0, c->sc + S_DT, q, L.xb[L.cur], L.xb[1 - L.cur], L.b);
+                launch_tsmooth<R>(c, L.g, tcoef<R>(m, l), l == 0, c->sc + S_DT, q, B::x(L), B::xo(L), B::b(L));
             L.cur ^= 1;
         } else if (m.op == HB_OP_VISC) {
             // finest 3D level: one colour of one component per launch, in
             // place (a 2-cell halo is costly on a 3D tile)
             for (int q = 0; q < L.g.dim; ++q)
                 for (int colour = 0; colour < 2; ++colour)
-                    launch_trb3(c, L.g, tcoef(m, l), l == 0, c->sc + S_DT, q, colour, L.X(), L.b);
+                    launch_trb3<R>(c, L.g, tcoef<R>(m, l), l == 0, c->sc + S_DT, q, colour, B::x(L), B::b(L));
         } else if (m.op == HB_OP_MAC) {
-            for (int colour = 0; colour < 2; ++colour) launch_mac_rb(c, L, colour);
+            for (int colour = 0; colour < 2; ++colour) launch_mac_rb<R>(c, L.g, colour, B::x(L), B::b(L));
         } else {
-            for (int colour = 0; colour < (1 << L.g.dim); ++colour) launch_nodal_gs(c, L, colour);
+            for (int colour = 0; colour < (1 << L.g.dim); ++colour) launch_nodal_gs<R>(c, L.g, colour, B::x(L), B::b(L));
         }
     }
 }
 
-static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2);
+template <typename R> static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2);
 
-// Levels 1.. of the V-cycle as one HIP graph: the coarse levels are many
-// short launches, so replaying a captured graph removes most of their host
-// launch cost.  All their kernel arguments are fixed (buffers, and dt read
-// from device memory); with an even number of sweeps per cycle every
-// double-buffered level ends the cycle in the buffer it started in.
+// Levels 1.. of the V-cycle as one HIP graph per precision: the coarse
+// levels are many short launches, so replaying a captured graph removes most
+// of their host launch cost.  All their kernel arguments are fixed (buffers,
+// and dt read from device memory); with an even number of sweeps per cycle
+// every double-buffered level ends the cycle in the buffer it started in.
+template <typename R>
 static void coarse_graph(Ctx* c, MG& m, int nu1, int nu2)
 {
-    if (!m.gexec || m.gnu1 != nu1 || m.gnu2 != nu2) {
-        if (m.gexec) {
-            (void)hipGraphExecDestroy(m.gexec);
-            m.gexec = nullptr;
+    const int pi = prec_index<R>();
+    if (!m.gexec[pi] || m.gnu1[pi] != nu1 || m.gnu2[pi] != nu2) {
+        if (m.gexec[pi]) {
+            (void)hipGraphExecDestroy(m.gexec[pi]);
+            m.gexec[pi] = nullptr;
         }
         if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            m.gfail = true;
-            vcycle(c, m, 1, nu1, nu2);
+            m.gfail[pi] = true;
+            vcycle<R>(c, m, 1, nu1, nu2);
             return;
         }
         m.capturing = true;
-        vcycle(c, m, 1, nu1, nu2);
+        vcycle<R>(c, m, 1, nu1, nu2);
         m.capturing = false;
         hipGraph_t graph = nullptr;
         bool ok = hipStreamEndCapture(c->s, &graph) == hipSuccess && graph;
-        ok = ok && hipGraphInstantiate(&m.gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+        ok = ok && hipGraphInstantiate(&m.gexec[pi], graph, nullptr, nullptr, 0) == hipSuccess;
         if (graph) (void)hipGraphDestroy(graph);
         if (!ok) {
-            m.gfail = true;
-            m.gexec = nullptr;
-            vcycle(c, m, 1, nu1, nu2);
+            m.gfail[pi] = true;
+            m.gexec[pi] = nullptr;
+            vcycle<R>(c, m, 1, nu1, nu2);
             return;
         }
-        m.gnu1 = nu1;
-        m.gnu2 = nu2;
+        m.gnu1[pi] = nu1;
+        m.gnu2[pi] = nu2;
     }
-    (void)hipGraphLaunch(m.gexec, c->s);
+    (void)hipGraphLaunch(m.gexec[pi], c->s);
 }
 
+// one V-cycle from level l in precision R; the coarsest level is solved with
+// the FP64 inverse of its dense matrix
+template <typename R>
 static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
 {
+    using B = LB<R>;
     Level& L = m.L[l];
-    if (l == m.tail) {
-        launch_tail(c, m, l, nu1, nu2);
+    if (l == m.nlev - 1) {
+        launch_coarse_solve<R>(c, m.ncoarse, m.Ainv, B::b(L), B::x(L));
         return;
     }
-    if (l == 1 && !m.capturing && !m.gfail && m.tail > 1 && (nu1 + nu2) % 2 == 0) {
-        coarse_graph(c, m, nu1, nu2);
+    if (l == 1 && !m.capturing && !m.gfail[prec_index<R>()] && m.nlev > 2 && (nu1 + nu2) % 2 == 0) {
+        coarse_graph<R>(c, m, nu1, nu2);
         return;
     }
     Level& C = m.L[l + 1];
-    smooth(c, m, l, nu1);
-    if (m.op == HB_OP_VISC) launch_tresid_restr(c, L.g, C.g, tcoef(m, l), l == 0, c->sc + S_DT, L.X(), L.b, C.b, C.X());
-    else if (m.op == HB_OP_MAC) launch_mac_resid_restrict(c, L, C);
-    else {
-        launch_nodal_resid(c, L, L.X(), L.b, L.r, -1);
-        launch_nodal_restrict(c, L, C);
+    smooth<R>(c, m, l, nu1);
+    if (m.op == HB_OP_VISC) {
+        launch_tresid_restr<R>(c, L.g, C.g, tcoef<R>(m, l), l == 0, c->sc + S_DT, B::x(L), B::b(L), B::b(C), B::x(C));
+    } else if (m.op == HB_OP_MAC) {
+        launch_mac_resid_restrict<R>(c, L.g, C.g, B::x(L), B::b(L), B::b(C), B::x(C));
+    } else {
+        launch_nodal_resid<R>(c, L.g, B::x(L), B::b(L), B::r(L), -1);
+        launch_nodal_restrict<R>(c, L.g, C.g, B::r(L), B::b(C), B::x(C));
     }
-    vcycle(c, m, l + 1, nu1, nu2);
-    if (m.op == HB_OP_NODAL) launch_nodal_prolong(c, L, C);
-    else launch_prolong_cells(c, L, C, m.op == HB_OP_VISC ? L.g.dim : 1, m.op == HB_OP_VISC ? -1.0 : 1.0);
-    smooth(c, m, l, nu2);
+    vcycle<R>(c, m, l + 1, nu1, nu2);
+    if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L.g, C.g, B::x(C), B::x(L));
+    else launch_prolong_cells<R>(c, L.g, C.g, m.op == HB_OP_VISC ? L.g.dim : 1, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
+    smooth<R>(c, m, l, nu2);
 }
 
-// r = b - A x on level 0 and its max-norm into slot S_MAX
+// r = b - A x on level 0 (FP64) and its max-norm into slot S_MAX
 static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r)
 {
     set_slot_zero(c, S_MAX);
     const Level& L = m.L[0];
     if (m.op == HB_OP_VISC) launch_tresid(c, L.g, m.etae, true, c->sc + S_DT, x, b, r, S_MAX);
-    else if (m.op == HB_OP_MAC) launch_mac_resid(c, L, x, b, r, S_MAX);
-    else launch_nodal_resid(c, L, x, b, r, S_MAX);
+    else if (m.op == HB_OP_MAC) launch_mac_resid(c, L.g, x, b, r, S_MAX);
+    else launch_nodal_resid<double>(c, L.g, x, b, r, S_MAX);
 }
 
 static void apply0(Ctx* c, MG& m, const double* x, double* y)
 {
     const Level& L = m.L[0];
     if (m.op == HB_OP_VISC) launch_tresid(c, L.g, m.etae, true, c->sc + S_DT, x, nullptr, y, -1);
-    else if (m.op == HB_OP_MAC) launch_mac_apply(c, L, x, y);
-    else launch_nodal_apply(c, L, x, y);
+    else if (m.op == HB_OP_MAC) launch_mac_apply(c, L.g, x, y);
+    else launch_nodal_resid<double>(c, L.g, x, nullptr, y, -1);
 }
 
-// z = M^{-1} r: one V-cycle from zero on level 0
-static void precond(Ctx* c, MG& m, const double* r, double* z, int nu1, int nu2)
+// z = M^{-1} r: one V-cycle from zero on level 0, in FP64 or (lo) in FP32
+static void precond(Ctx* c, MG& m, const double* r, double* z, int nu1, int nu2, bool lo)
 {
     Level& L = m.L[0];
+    L.cur = 0;
+    if (lo) {
+        to_f32(c, r, L.fb, L.fx[0], L.nu);
+        vcycle<float>(c, m, 0, nu1, nu2);
+        from_f32(c, LB<float>::x(L), z, L.nu);
+        return;
+    }
     double* sb = L.b;
     L.b = const_cast<double*>(r);
-    L.cur = 0;
     fill(c, L.X(), 0.0, L.nu);
-    vcycle(c, m, 0, nu1, nu2);
+    vcycle<double>(c, m, 0, nu1, nu2);
     copy(c, z, L.X(), L.nu);
     L.b = sb;
 }
@@ -299,7 +341,9 @@ static double fetch_max(Ctx* c)
 }
 
 // Multigrid (optionally BiCGStab-accelerated) solve of A x = b on the
-// prepared level-0 system; x in/out.  bn = |b|_inf.
+// prepared level-0 system; x in/out.  bn = |b|_inf.  With mixed precision
+// every V-cycle runs in FP32 on the FP64 residual (defect correction, or the
+// BiCGStab preconditioner); residuals, norms and the iterate stay FP64.
 static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_mg_opts& o, hb_mg_report* rep)
 {
     Level& L = m.L[0];
@@ -307,9 +351,10 @@ static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_m
     L.b = b;
     int cycles = 0, rc = HB_OK;
     double rel = 0.0;
+    const bool lo = o.precision == HB_PREC_MIXED;
     if (bn == 0.0) {
         fill(c, x, 0.0, n);
-    } else if (!o.krylov) {
+    } else if (!o.krylov && !lo) {
         // the cycles work on the level's double buffer, seeded with x
         L.cur = 0;
         copy(c, L.X(), x, n);
@@ -322,13 +367,37 @@ static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_m
                 if (rel <= o.tol_rel) break;
                 if (cycles >= o.max_cycles) { rc = HB_ERR_NOCONV; break; }
             }
-            vcycle(c, m, 0, o.nu1, o.nu2);
+            vcycle<double>(c, m, 0, o.nu1, o.nu2);
             ++cycles;
             resid0(c, m, L.X(), b, L.r);
             rel = fetch_max(c) / bn;
             if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
         }
         copy(c, x, L.X(), n);
+    } else if (!o.krylov) {
+        // defect correction: FP64 residual r = b - A x, one FP32 V-cycle
+        // from zero on A e = r, x += e
+        double* xw = L.xb[0];
+        copy(c, xw, x, n);
+        resid0(c, m, xw, b, L.r);
+        rel = fetch_max(c) / bn;
+        for (;;) {
+            if (o.fixed_cycles) {
+                if (cycles >= o.max_cycles) break;
+            } else {
+                if (rel <= o.tol_rel) break;
+                if (cycles >= o.max_cycles) { rc = HB_ERR_NOCONV; break; }
+            }
+            L.cur = 0;
+            to_f32(c, L.r, L.fb, L.fx[0], n);
+            vcycle<float>(c, m, 0, o.nu1, o.nu2);
+            ++cycles;
+            add_f32(c, xw, LB<float>::x(L), n);
+            resid0(c, m, xw, b, L.r);
+            rel = fetch_max(c) / bn;
+            if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
+        }
+        copy(c, x, xw, n);
     } else {
         // BiCGStab with its scalars kept on the device: two host reads per
         // iteration (the residual norms that decide convergence)
@@ -349,7 +418,7 @@ static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_m
             red_dot(c, rh, r, n, S_DOT0);
             bicg_beta(c);
             bicg_p_dev(c, p, r, v, n);
-            precond(c, m, p, ph, o.nu1, o.nu2);
+            precond(c, m, p, ph, o.nu1, o.nu2, lo);
             ++cycles;
             apply0(c, m, ph, v);
             red_dot(c, rh, v, n, S_DOT1);
@@ -364,7 +433,7 @@ static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_m
                 rel = srel;
                 break;
             }
-            precond(c, m, s, sh, o.nu1, o.nu2);
+            precond(c, m, s, sh, o.nu1, o.nu2, lo);
             ++cycles;
             apply0(c, m, sh, t);
             red_dot(c, t, t, n, S_DOT0);
@@ -400,6 +469,7 @@ static int solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o, hb_mg_r
     fetch_slots(c);
     const double bn = c->hsc[S_MAX];
     if (!std::isfinite(bn) || !std::isfinite(c->hsc[S_MAX2])) return fail(c, HB_ERR_NONFINITE, "non-finite right-hand side or guess");
+    if (o.precision == HB_PREC_MIXED) ensure_f32(c, m);
     int rc = solve_core(c, m, x, m.lvl0_b, bn, o, rep);
     if (m.op != HB_OP_VISC) sub_mean(c, x, n);
     if (rc == HB_ERR_NOCONV) c->err = "multigrid did not reach the tolerance within max_cycles";

@@ -18,15 +18,35 @@ struct FluidD {
 struct Level {
     GridD g;
     long nu = 0;             // unknowns of this level
-    double* xb[2] = {nullptr, nullptr};  // double-buffered iterate
     int cur = 0;             // buffer holding the current iterate
+    // FP64 arrays
+    double* xb[2] = {nullptr, nullptr};  // double-buffered iterate
     double* b = nullptr;     // right-hand side
     double* r = nullptr;     // residual scratch
     double* beta = nullptr;  // face viscosity (tensor problem only)
-    float* xs = nullptr;     // FP32 shadows for mixed-precision cycles
-    float* bs = nullptr;
-    float* betas = nullptr;
+    // FP32 arrays of the mixed-precision correction cycles
+    float* fx[2] = {nullptr, nullptr};
+    float* fb = nullptr;
+    float* fr = nullptr;
+    float* fbeta = nullptr;
     double* X() const { return xb[cur]; }
+};
+
+// the arrays of a level in storage precision R
+template <typename R> struct LB;
+template <> struct LB<double> {
+    static double* x(const Level& L) { return L.xb[L.cur]; }
+    static double* xo(const Level& L) { return L.xb[1 - L.cur]; }
+    static double* b(const Level& L) { return L.b; }
+    static double* r(const Level& L) { return L.r; }
+    static const double* beta(const Level& L) { return L.beta; }
+};
+template <> struct LB<float> {
+    static float* x(const Level& L) { return L.fx[L.cur]; }
+    static float* xo(const Level& L) { return L.fx[1 - L.cur]; }
+    static float* b(const Level& L) { return L.fb; }
+    static float* r(const Level& L) { return L.fr; }
+    static const float* beta(const Level& L) { return L.fbeta; }
 };
 
 struct MG {
@@ -36,16 +56,18 @@ struct MG {
     int ncoarse = 0;         // unknowns on the coarsest level
     double* A = nullptr;     // coarsest dense matrix -> LU factors
     int* piv = nullptr;
+    double* Ainv = nullptr;  // inverse of the coarsest matrix (from the LU factors)
     double dt = 0.0;         // tensor problem: dt of the factorised matrix
     double* lvl0_b = nullptr;  // level-0 right-hand side storage
     double* etae = nullptr;    // tensor problem: eta/Re per fine cell
-    int tail = 0;              // first level handled by the single-workgroup kernel
-    // levels 1.. of a V-cycle captured once as a HIP graph and replayed
-    hipGraphExec_t gexec = nullptr;
-    int gnu1 = -1, gnu2 = -1;
-    bool capturing = false, gfail = false;
-    void* tailargs = nullptr;  // device copy of the tail description
-    size_t tail_lds = 0;       // LDS bytes of the tail kernel
+    float* etae32 = nullptr;   // its FP32 copy
+    bool f32_ready = false;    // FP32 coefficient copies match the FP64 ones
+    // levels 1.. of a V-cycle captured once per precision as a HIP graph and
+    // replayed (index 0: FP64, 1: FP32)
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gnu1[2] = {-1, -1}, gnu2[2] = {-1, -1};
+    bool gfail[2] = {false, false};
+    bool capturing = false;
 };
 
 // HIP-event timing of every launch of one kernel (measurement support)
@@ -110,10 +132,6 @@ void fetch_slots(Ctx* c);  // copies all slots to c->hsc and synchronises
 void set_slot_zero(Ctx* c, int slot);
 void set_slot(Ctx* c, int slot, double v);
 void sub_mean(Ctx* c, double* v, long n);   // v -= sum(v)/n (device-side)
-void axpby(Ctx* c, double* y, double a, const double* x, double b, long n);   // y = a x + b y
-void bicg_p(Ctx* c, double* p, const double* r, const double* v, double beta, double omega, long n);
-void sub_scaled_max(Ctx* c, double* out, const double* a, double s, const double* b, long n, int slot);
-void bicg_x(Ctx* c, double* x, const double* ph, const double* sh, double alpha, double omega, long n);
 // device-scalar BiCGStab steps (scalars in the slots S_RHO .. S_BETA)
 void bicg_init_scalars(Ctx* c);
 void bicg_beta(Ctx* c);             // rho = DOT0, beta = (rho/rho_prev)(alpha/omega)
@@ -131,46 +149,52 @@ void launch_eta_faces(Ctx* c, const GridD& g, const double* eta, double* beta);
 void launch_restrict_faces(Ctx* c, const GridD& gf, const GridD& gc, const double* bf, double* bc);
 void launch_visc_div(Ctx* c, const GridD& g, const double* beta, const double* u, double* out);
 void launch_visc_wall_rhs(Ctx* c, const GridD& g, const double* beta, double dt, const double* rhs, double* out);
-void launch_visc_rb(Ctx* c, const Level& l, double dt, int comp, int colour);
-void launch_visc_resid(Ctx* c, const Level& l, double dt, const double* x, const double* b, double* r, int slot);
-void launch_visc_apply(Ctx* c, const Level& l, double dt, const double* x, double* y);
-void launch_visc_resid_restrict(Ctx* c, const Level& f, const Level& cl, double dt);
 void launch_visc_dense(Ctx* c, const Level& l, double dt, int N, double* E, double* A);
 void launch_eta_over_re(Ctx* c, const GridD& g, const double* eta, double* etae);
 
-// LDS-tiled tensor kernels (hb_tile.hip); fine = coef is eta/Re per cell
-// (dt is read from device memory, so a captured graph stays valid across steps)
-void launch_tsmooth(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp,
-                    const double* xcur, double* xnext, const double* b);
-void launch_trb3(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp, int colour,
-                 double* x, const double* b);
+// LDS-tiled tensor kernels (hb_tile.hip), R = storage and arithmetic
+// precision of the multigrid cycle; fine = coef is eta/Re per cell (else the
+// level's face viscosities).  dt is read from device memory, so a captured
+// graph stays valid across steps.
+template <typename R>
+void launch_tsmooth(Ctx* c, const GridD& g, const R* coef, bool fine, const double* dtp, int comp, const R* xcur,
+                    R* xnext, const R* b);
+template <typename R>
+void launch_trb3(Ctx* c, const GridD& g, const R* coef, bool fine, const double* dtp, int comp, int colour, R* x,
+                 const R* b);
+template <typename R>
+void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const R* coef, bool fine, const double* dtp,
+                         const R* x, const R* b, R* bc, R* xc);
+// FP64 finest-level residual r = b - A x (max-norm into slot) or y = A x (b null)
 void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, const double* x,
                    const double* b, double* out, int slot);
-void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const double* coef, bool fine, const double* dtp,
-                         const double* x, const double* b, double* bc, double* xc);
 
-// scalar cell problem (MAC) and nodal problem, transfers, dense (hb_mg.hip)
-void launch_mac_rb(Ctx* c, const Level& l, int colour);
-void launch_mac_resid(Ctx* c, const Level& l, const double* x, const double* b, double* r, int slot);
-void launch_mac_apply(Ctx* c, const Level& l, const double* x, double* y);
-void launch_mac_resid_restrict(Ctx* c, const Level& f, const Level& cl);
+// scalar cell problem (MAC) and nodal problem, transfers, coarsest solve
+// (hb_mg.hip, hb_nodal.hip)
+template <typename R> void launch_mac_rb(Ctx* c, const GridD& g, int colour, R* x, const R* b);
+template <typename R>
+void launch_mac_resid_restrict(Ctx* c, const GridD& gf, const GridD& gc, const R* xf, const R* bf, R* bc, R* xc);
+void launch_mac_resid(Ctx* c, const GridD& g, const double* x, const double* b, double* r, int slot);
+void launch_mac_apply(Ctx* c, const GridD& g, const double* x, double* y);
 void launch_mac_dense(Ctx* c, const Level& l, int N, double* E, double* A);
-void launch_prolong_cells(Ctx* c, const Level& f, const Level& cl, int ncomp, double wall_sign);
-void launch_nodal_gs(Ctx* c, const Level& l, int colour);
-void launch_nodal_resid(Ctx* c, const Level& l, const double* x, const double* b, double* r, int slot);
-void launch_nodal_apply(Ctx* c, const Level& l, const double* x, double* y);
-void launch_nodal_restrict(Ctx* c, const Level& f, const Level& cl);
-void launch_nodal_prolong(Ctx* c, const Level& f, const Level& cl);
+template <typename R>
+void launch_prolong_cells(Ctx* c, const GridD& gf, const GridD& gc, int ncomp, double wall_sign, const R* e, R* x);
+template <typename R> void launch_nodal_gs(Ctx* c, const GridD& g, int colour, R* x, const R* b);
+// r = b - K x (slot >= 0: FP64 only, max-norm into the slot) or y = K x (b null)
+template <typename R> void launch_nodal_resid(Ctx* c, const GridD& g, const R* x, const R* b, R* r, int slot);
+template <typename R> void launch_nodal_restrict(Ctx* c, const GridD& gf, const GridD& gc, const R* rf, R* bc, R* xc);
+template <typename R> void launch_nodal_prolong(Ctx* c, const GridD& gf, const GridD& gc, const R* e, R* x);
 void launch_nodal_dense(Ctx* c, const Level& l, int N, double* E, double* A);
 void launch_add_ones(Ctx* c, int N, double* A);
 void launch_lu_factor(Ctx* c, int N, double* A, int* piv);
-void launch_lu_solve(Ctx* c, int N, const double* A, const int* piv, const double* b, double* x);
+void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* Ainv);
+// x = A^{-1} b on the coarsest level, accumulated in FP64
+template <typename R> void launch_coarse_solve(Ctx* c, int N, const double* Ainv, const R* b, R* x);
 
-// single-workgroup coarse end of a V-cycle (hb_tail.hip)
-void launch_tail(Ctx* c, const MG& m, int first, int nu1, int nu2);
-int tail_max_levels();
-size_t tail_lds_bytes(const MG& m, int first);
-int tail_setup(Ctx* c, MG& m);
+// precision conversions of the mixed-precision cycles (hb_reduce.hip)
+void to_f32(Ctx* c, const double* src, float* dst, float* zero, long n);   // dst = src, zero = 0 (nullable)
+void add_f32(Ctx* c, double* x, const float* e, long n);                   // x += e
+void from_f32(Ctx* c, const float* e, double* x, long n);                  // x = e
 
 // step stages (hb_step.hip)
 void launch_grad_node(Ctx* c, const double* p, double* Gp);

@@ -1,6 +1,8 @@
 // hb_mg.hip -- multigrid kernels of the cell-centred scalar (MAC) problem
 // and the nodal Q1 projection problem, cell prolongation shared with the
-// tensor problem, and the dense LU of the coarsest level.  gfx950, FP64.
+// tensor problem, and the dense coarsest-level solve.  gfx950; the cycle
+// kernels are templated on the storage and arithmetic type R (double, or
+// float in the mixed-precision correction cycles).
 #include "hb_internal.h"
 #include "hb_ops.h"
 
@@ -12,7 +14,8 @@ static const dim3 kBlk(64, 4, 1);
 // MAC problem: L_mac = D_mac G_mac, zero flux through wall faces
 // ---------------------------------------------------------------------------
 
-__global__ void k_mac_rb(GridD g, int colour, double* __restrict__ x, const double* __restrict__ b)
+template <typename R>
+__global__ void k_mac_rb(GridD g, int colour, R* __restrict__ x, const R* __restrict__ b)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -20,8 +23,9 @@ __global__ void k_mac_rb(GridD g, int colour, double* __restrict__ x, const doub
     const int i = 2 * t + ((j + k + colour) & 1);
     if (i >= g.n[0] || j >= g.n[1]) return;
     const long q = cid(g, i, j, k);
-    const double ih2 = 1.0 / (g.h * g.h);
-    double Lx = 0.0;
+    const R h = (R)g.h;
+    const R ih2 = R(1) / (h * h);
+    R Lx = 0;
     int cnt = 0;
     for (int a = 0; a < g.dim; ++a)
         for (int side = 0; side < 2; ++side) {
@@ -31,13 +35,14 @@ __global__ void k_mac_rb(GridD g, int colour, double* __restrict__ x, const doub
             Lx += (x[cid(g, p[0], p[1], p[2])] - x[q]) * ih2;
             ++cnt;
         }
-    const double dg = -(double)cnt * ih2;
+    const R dg = -(R)cnt * ih2;
     x[q] += (b[q] - Lx) / dg;
 }
 
-void launch_mac_rb(Ctx* c, const Level& l, int colour)
+template <typename R>
+void launch_mac_rb(Ctx* c, const GridD& g, int colour, R* x, const R* b)
 {
-    k_mac_rb<<<grid3((l.g.n[0] + 1) / 2, l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, colour, l.X(), l.b);
+    k_mac_rb<R><<<grid3((g.n[0] + 1) / 2, g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, colour, x, b);
 }
 
 __global__ void k_mac_resid(GridD g, const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
@@ -50,7 +55,7 @@ __global__ void k_mac_resid(GridD g, const double* __restrict__ x, const double*
     unsigned long long m = 0ull;
     if (i < g.n[0] && j < g.n[1]) {
         const long q = cid(g, i, j, k);
-        const double rv = b[q] - mac_lap_at(g, x, i, j, k);
+        const double rv = b[q] - mac_lap_at<double>(g, x, i, j, k);
         if (r) r[q] = rv;
         m = abits(rv);
     }
@@ -60,9 +65,9 @@ __global__ void k_mac_resid(GridD g, const double* __restrict__ x, const double*
     }
 }
 
-void launch_mac_resid(Ctx* c, const Level& l, const double* x, const double* b, double* r, int slot)
+void launch_mac_resid(Ctx* c, const GridD& g, const double* x, const double* b, double* r, int slot)
 {
-    k_mac_resid<<<grid3(l.g.n[0], l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, x, b, r, slot >= 0 ? c->sc + slot : nullptr);
+    k_mac_resid<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, x, b, r, slot >= 0 ? c->sc + slot : nullptr);
 }
 
 __global__ void k_mac_apply(GridD g, const double* __restrict__ x, double* __restrict__ y)
@@ -71,35 +76,37 @@ __global__ void k_mac_apply(GridD g, const double* __restrict__ x, double* __res
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = blockIdx.z;
     if (i >= g.n[0] || j >= g.n[1]) return;
-    y[cid(g, i, j, k)] = mac_lap_at(g, x, i, j, k);
+    y[cid(g, i, j, k)] = mac_lap_at<double>(g, x, i, j, k);
 }
 
-void launch_mac_apply(Ctx* c, const Level& l, const double* x, double* y)
+void launch_mac_apply(Ctx* c, const GridD& g, const double* x, double* y)
 {
-    k_mac_apply<<<grid3(l.g.n[0], l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, x, y);
+    k_mac_apply<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, x, y);
 }
 
-__global__ void k_mac_resid_restrict(GridD gf, GridD gc, const double* __restrict__ xf, const double* __restrict__ bf,
-                                     double* __restrict__ bc, double* __restrict__ xc)
+template <typename R>
+__global__ void k_mac_resid_restrict(GridD gf, GridD gc, const R* __restrict__ xf, const R* __restrict__ bf,
+                                     R* __restrict__ bc, R* __restrict__ xc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = blockIdx.z;
     if (i >= gc.n[0] || j >= gc.n[1]) return;
     const int nch = 1 << gf.dim;
-    double s = 0.0;
+    R s = 0;
     for (int bits = 0; bits < nch; ++bits) {
         const int fi = 2 * i + (bits & 1), fj = 2 * j + ((bits >> 1) & 1), fk = gf.dim == 3 ? 2 * k + ((bits >> 2) & 1) : 0;
-        s += bf[cid(gf, fi, fj, fk)] - mac_lap_at(gf, xf, fi, fj, fk);
+        s += bf[cid(gf, fi, fj, fk)] - mac_lap_at<R>(gf, xf, fi, fj, fk);
     }
     const long qc = cid(gc, i, j, k);
-    bc[qc] = s / (double)nch;
-    xc[qc] = 0.0;
+    bc[qc] = s / (R)nch;
+    xc[qc] = R(0);
 }
 
-void launch_mac_resid_restrict(Ctx* c, const Level& f, const Level& cl)
+template <typename R>
+void launch_mac_resid_restrict(Ctx* c, const GridD& gf, const GridD& gc, const R* xf, const R* bf, R* bc, R* xc)
 {
-    k_mac_resid_restrict<<<grid3(cl.g.n[0], cl.g.n[1], cl.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, f.X(), f.b, cl.b, cl.X());
+    k_mac_resid_restrict<R><<<grid3(gc.n[0], gc.n[1], gc.n[2], kBlk), kBlk, 0, c->s>>>(gf, gc, xf, bf, bc, xc);
 }
 
 __global__ void k_mac_dense(GridD g, int N, const double* __restrict__ E, double* __restrict__ A)
@@ -108,7 +115,7 @@ __global__ void k_mac_dense(GridD g, int N, const double* __restrict__ E, double
     const int col = blockIdx.y;
     if (row >= N) return;
     const int i = row % g.n[0], j = (row / g.n[0]) % g.n[1], k = row / (g.n[0] * g.n[1]);
-    A[(long)row * N + col] = mac_lap_at(g, E + (long)col * N, i, j, k);
+    A[(long)row * N + col] = mac_lap_at<double>(g, E + (long)col * N, i, j, k);
 }
 
 void launch_mac_dense(Ctx* c, const Level& l, int N, double* E, double* A)
@@ -121,8 +128,8 @@ void launch_mac_dense(Ctx* c, const Level& l, int N, double* E, double* A)
 // neighbour beyond a wall takes the homogeneous ghost value wall_sign * e
 // ---------------------------------------------------------------------------
 
-__global__ void k_prolong_cells(GridD gf, GridD gc, int ncomp, double wall_sign, const double* __restrict__ e,
-                                double* __restrict__ x)
+template <typename R>
+__global__ void k_prolong_cells(GridD gf, GridD gc, int ncomp, R wall_sign, const R* __restrict__ e, R* __restrict__ x)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -132,15 +139,15 @@ __global__ void k_prolong_cells(GridD gf, GridD gc, int ncomp, double wall_sign,
     const int fi[3] = {i, j, k};
     const long Nf = ncells(gf), Nc = ncells(gc);
     for (int q = 0; q < ncomp; ++q) {
-        double s = 0.0;
+        R s = 0;
         for (int bits = 0; bits < (1 << d); ++bits) {
             int p[3] = {0, 0, 0};
-            double w = 1.0, sg = 1.0;
+            R w = 1, sg = 1;
             for (int a = 0; a < d; ++a) {
                 const int I = fi[a] >> 1;
-                if (!((bits >> a) & 1)) { p[a] = I; w *= 0.75; continue; }
+                if (!((bits >> a) & 1)) { p[a] = I; w *= R(0.75); continue; }
                 int J = (fi[a] & 1) ? I + 1 : I - 1;
-                w *= 0.25;
+                w *= R(0.25);
                 if (J < 0 || J >= gc.n[a]) {
                     if (gc.per[a]) J = J < 0 ? J + gc.n[a] : J - gc.n[a];
                     else { J = I; sg *= wall_sign; }
@@ -153,9 +160,10 @@ __global__ void k_prolong_cells(GridD gf, GridD gc, int ncomp, double wall_sign,
     }
 }
 
-void launch_prolong_cells(Ctx* c, const Level& f, const Level& cl, int ncomp, double wall_sign)
+template <typename R>
+void launch_prolong_cells(Ctx* c, const GridD& gf, const GridD& gc, int ncomp, double wall_sign, const R* e, R* x)
 {
-    k_prolong_cells<<<grid3(f.g.n[0], f.g.n[1], f.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, ncomp, wall_sign, cl.X(), f.X());
+    k_prolong_cells<R><<<grid3(gf.n[0], gf.n[1], gf.n[2], kBlk), kBlk, 0, c->s>>>(gf, gc, ncomp, (R)wall_sign, e, x);
 }
 
 // ---------------------------------------------------------------------------
@@ -163,8 +171,8 @@ void launch_prolong_cells(Ctx* c, const Level& f, const Level& cl, int ncomp, do
 // ---------------------------------------------------------------------------
 
 // full weighting R = P^T from the fine residual r_f; coarse iterate zeroed
-__global__ void k_nodal_restrict(GridD gf, GridD gc, const double* __restrict__ rf, double* __restrict__ bc,
-                                 double* __restrict__ xc)
+template <typename R>
+__global__ void k_nodal_restrict(GridD gf, GridD gc, const R* __restrict__ rf, R* __restrict__ bc, R* __restrict__ xc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -174,15 +182,15 @@ __global__ void k_nodal_restrict(GridD gf, GridD gc, const double* __restrict__ 
     const int I[3] = {i, j, k};
     int nt = 1;
     for (int a = 0; a < d; ++a) nt *= 3;
-    double s = 0.0;
+    R s = 0;
     for (int t = 0; t < nt; ++t) {
         int tt = t, p[3] = {0, 0, 0};
-        double w = 1.0;
+        R w = 1;
         bool ok = true;
         for (int a = 0; a < d; ++a) {
             const int del = tt % 3 - 1;
             tt /= 3;
-            if (del != 0) w *= 0.5;
+            if (del != 0) w *= R(0.5);
             int F = 2 * I[a] + del;
             const int nf = nnode(gf, a);
             if (F < 0 || F >= nf) {
@@ -195,17 +203,18 @@ __global__ void k_nodal_restrict(GridD gf, GridD gc, const double* __restrict__ 
     }
     const long q = nid(gc, i, j, k);
     bc[q] = s;
-    xc[q] = 0.0;
+    xc[q] = R(0);
 }
 
-void launch_nodal_restrict(Ctx* c, const Level& f, const Level& cl)
+template <typename R>
+void launch_nodal_restrict(Ctx* c, const GridD& gf, const GridD& gc, const R* rf, R* bc, R* xc)
 {
-    const GridD& g = cl.g;
-    k_nodal_restrict<<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(f.g, g, f.r, cl.b, cl.X());
+    k_nodal_restrict<R><<<grid3(nnode(gc, 0), nnode(gc, 1), nnode(gc, 2), kBlk), kBlk, 0, c->s>>>(gf, gc, rf, bc, xc);
 }
 
 // (bi/tri)linear nodal prolongation x_f += P e_c
-__global__ void k_nodal_prolong(GridD gf, GridD gc, const double* __restrict__ e, double* __restrict__ x)
+template <typename R>
+__global__ void k_nodal_prolong(GridD gf, GridD gc, const R* __restrict__ e, R* __restrict__ x)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -213,10 +222,10 @@ __global__ void k_nodal_prolong(GridD gf, GridD gc, const double* __restrict__ e
     if (i >= nnode(gf, 0) || j >= nnode(gf, 1)) return;
     const int d = gf.dim;
     const int F[3] = {i, j, k};
-    double s = 0.0;
+    R s = 0;
     for (int bits = 0; bits < (1 << d); ++bits) {
         int p[3] = {0, 0, 0};
-        double w = 1.0;
+        R w = 1;
         bool ok = true;
         for (int a = 0; a < d; ++a) {
             const int hi = (bits >> a) & 1;
@@ -224,7 +233,7 @@ __global__ void k_nodal_prolong(GridD gf, GridD gc, const double* __restrict__ e
                 if (hi) { ok = false; break; }
                 p[a] = F[a] >> 1;
             } else {
-                w *= 0.5;
+                w *= R(0.5);
                 int C = ((F[a] - 1) >> 1) + hi;
                 if (gc.per[a] && C == nnode(gc, a)) C = 0;
                 p[a] = C;
@@ -235,15 +244,15 @@ __global__ void k_nodal_prolong(GridD gf, GridD gc, const double* __restrict__ e
     x[nid(gf, i, j, k)] += s;
 }
 
-void launch_nodal_prolong(Ctx* c, const Level& f, const Level& cl)
+template <typename R>
+void launch_nodal_prolong(Ctx* c, const GridD& gf, const GridD& gc, const R* e, R* x)
 {
-    const GridD& g = f.g;
-    k_nodal_prolong<<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, cl.g, cl.X(), f.X());
+    k_nodal_prolong<R><<<grid3(nnode(gf, 0), nnode(gf, 1), nnode(gf, 2), kBlk), kBlk, 0, c->s>>>(gf, gc, e, x);
 }
 
 // ---------------------------------------------------------------------------
 // dense coarsest level: A + 1 1^T / N for the singular problems, LU with
-// partial pivoting in one workgroup, triangular solves in one thread
+// partial pivoting in one workgroup, then the explicit inverse
 // ---------------------------------------------------------------------------
 
 __global__ void k_add_ones(int N, double* A)
@@ -296,26 +305,68 @@ void launch_lu_factor(Ctx* c, int N, double* A, int* piv)
     k_lu_factor<<<1, 256, 0, c->s>>>(N, A, piv);
 }
 
-__global__ void k_lu_solve(int N, const double* __restrict__ A, const int* __restrict__ piv, const double* __restrict__ b,
-                           double* __restrict__ x)
+// column j of A^{-1} from the LU factors (thread j: permutation, forward
+// and back substitution of e_j), so the coarsest solve of every V-cycle is a
+// parallel matrix-vector product
+__global__ void k_lu_inverse(int N, const double* __restrict__ LU, const int* __restrict__ piv, double* __restrict__ Ainv)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int i = 0; i < N; ++i) x[i] = b[i];
+    const int jcol = blockIdx.x * blockDim.x + threadIdx.x;
+    if (jcol >= N) return;
+    // work in the output column (stride N): Ainv[i * N + jcol]
+    double* y = Ainv + jcol;
+    for (int i = 0; i < N; ++i) y[(long)i * N] = (i == jcol) ? 1.0 : 0.0;
     for (int k = 0; k < N; ++k) {
         const int p = piv[k];
-        if (p != k) { const double t = x[k]; x[k] = x[p]; x[p] = t; }
+        if (p != k) {
+            const double t = y[(long)k * N];
+            y[(long)k * N] = y[(long)p * N];
+            y[(long)p * N] = t;
+        }
     }
-    for (int i = 0; i < N; ++i)
-        for (int jj = 0; jj < i; ++jj) x[i] -= A[(long)i * N + jj] * x[jj];
+    for (int i = 0; i < N; ++i) {
+        double v = y[(long)i * N];
+        for (int jj = 0; jj < i; ++jj) v -= LU[(long)i * N + jj] * y[(long)jj * N];
+        y[(long)i * N] = v;
+    }
     for (int i = N - 1; i >= 0; --i) {
-        for (int jj = i + 1; jj < N; ++jj) x[i] -= A[(long)i * N + jj] * x[jj];
-        x[i] /= A[(long)i * N + i];
+        double v = y[(long)i * N];
+        for (int jj = i + 1; jj < N; ++jj) v -= LU[(long)i * N + jj] * y[(long)jj * N];
+        y[(long)i * N] = v / LU[(long)i * N + i];
     }
 }
 
-void launch_lu_solve(Ctx* c, int N, const double* A, const int* piv, const double* b, double* x)
+void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* Ainv)
 {
-    k_lu_solve<<<1, 64, 0, c->s>>>(N, A, piv, b, x);
+    k_lu_inverse<<<(N + 63) / 64, 64, 0, c->s>>>(N, LU, piv, Ainv);
 }
+
+// x = A^{-1} b, one row per thread, accumulated in FP64
+template <typename R>
+__global__ void k_coarse_solve(int N, const double* __restrict__ Ainv, const R* __restrict__ b, R* __restrict__ x)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double* row = Ainv + (long)i * N;
+    double s = 0.0;
+    for (int jj = 0; jj < N; ++jj) s += row[jj] * (double)b[jj];
+    x[i] = (R)s;
+}
+
+template <typename R>
+void launch_coarse_solve(Ctx* c, int N, const double* Ainv, const R* b, R* x)
+{
+    k_coarse_solve<R><<<(N + 255) / 256, 256, 0, c->s>>>(N, Ainv, b, x);
+}
+
+#define HB_MG_INST(R)                                                                                     \
+    template void launch_mac_rb<R>(Ctx*, const GridD&, int, R*, const R*);                                \
+    template void launch_mac_resid_restrict<R>(Ctx*, const GridD&, const GridD&, const R*, const R*, R*, R*); \
+    template void launch_prolong_cells<R>(Ctx*, const GridD&, const GridD&, int, double, const R*, R*);   \
+    template void launch_nodal_restrict<R>(Ctx*, const GridD&, const GridD&, const R*, R*, R*);           \
+    template void launch_nodal_prolong<R>(Ctx*, const GridD&, const GridD&, const R*, R*);                \
+    template void launch_coarse_solve<R>(Ctx*, int, const double*, const R*, R*);
+HB_MG_INST(double)
+HB_MG_INST(float)
+#undef HB_MG_INST
 
 }  // namespace hb

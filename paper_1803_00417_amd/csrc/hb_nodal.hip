@@ -1,6 +1,7 @@
 // hb_nodal.hip -- LDS-tiled kernels of the nodal projection problem K x = b
 // (Q1 stiffness, natural boundary on walls): multi-colour Gauss-Seidel and
-// residual.  gfx950, FP64.
+// residual.  gfx950; templated on the storage and arithmetic type R (double,
+// or float in the mixed-precision correction cycles).
 //
 // The assembled stencil is written per node from the element stiffness: the
 // weight of neighbour node+delta is Ke(|delta|_0) times the number of
@@ -28,8 +29,8 @@ struct NTile {
 };
 
 // K x at node G from the LDS tile (local index l), and the diagonal
-template <int DIM>
-__device__ inline double tile_K(const GridD& g, const double* s, const int G[3], int l, double* diag)
+template <int DIM, typename R>
+__device__ inline R tile_K(const GridD& g, const R* s, const int G[3], int l, R* diag)
 {
     using T = NTile<DIM>;
     int cnt[3][3];
@@ -37,7 +38,7 @@ __device__ inline double tile_K(const GridD& g, const double* s, const int G[3],
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int d = 0; d < 3; ++d) cnt[a][d] = a < DIM ? node_cnt(g, a, G[a], d - 1) : (d == 1 ? 1 : 0);
-    double acc = 0.0;
+    R acc = 0;
 #pragma unroll
     for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
 #pragma unroll
@@ -45,27 +46,27 @@ __device__ inline double tile_K(const GridD& g, const double* s, const int G[3],
 #pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
                 const int k = (dx != 0) + (dy != 0) + (dz != 0);
-                const double w = q1_ke(DIM, g.h, k) * (double)(cnt[0][dx + 1] * cnt[1][dy + 1] * cnt[2][dz + 1]);
+                const R w = (R)(q1_ke(DIM, g.h, k) * (double)(cnt[0][dx + 1] * cnt[1][dy + 1] * cnt[2][dz + 1]));
                 acc += w * s[l + (dz * T::SY + dy) * T::SX + dx];
             }
-    if (diag) *diag = q1_ke(DIM, g.h, 0) * (double)(cnt[0][1] * cnt[1][1] * cnt[2][1]);
+    if (diag) *diag = (R)(q1_ke(DIM, g.h, 0) * (double)(cnt[0][1] * cnt[1][1] * cnt[2][1]));
     return acc;
 }
 
 // stage the node tile plus a 1-node halo; all loads of a thread are issued
 // before any store so they are in flight together
-template <int DIM>
-__device__ inline void fill_nodes(const GridD& g, const double* __restrict__ x, double* s, int ox, int oy, int oz)
+template <int DIM, typename R>
+__device__ inline void fill_nodes(const GridD& g, const R* __restrict__ x, R* s, int ox, int oy, int oz)
 {
     using T = NTile<DIM>;
     constexpr int K = (T::NS + T::THREADS - 1) / T::THREADS;
-    double v[K];
+    R v[K];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
         const int t = threadIdx.x + u * T::THREADS;
         const int tt = t < T::NS ? t : 0;
         const int lx = tt % T::SX, ly = (tt / T::SX) % T::SY, lz = tt / (T::SX * T::SY);
-        v[u] = node_fetch<DIM>(g, x, ox - 1 + lx, oy - 1 + ly, DIM == 3 ? oz - 1 + lz : 0);
+        v[u] = node_fetch<DIM, R>(g, x, ox - 1 + lx, oy - 1 + ly, DIM == 3 ? oz - 1 + lz : 0);
     }
 #pragma unroll
     for (int u = 0; u < K; ++u) {
@@ -76,14 +77,14 @@ __device__ inline void fill_nodes(const GridD& g, const double* __restrict__ x, 
 
 // one colour (i&1) + 2(j&1) + 4(k&1) of the Gauss-Seidel sweep, in place:
 // nodes of one colour share no element
-template <int DIM>
+template <int DIM, typename R>
 __global__ void __launch_bounds__(NTile<DIM>::THREADS)
-k_nodal_gs_tile(GridD g, int colour, double* __restrict__ x, const double* __restrict__ b)
+k_nodal_gs_tile(GridD g, int colour, R* __restrict__ x, const R* __restrict__ b)
 {
     using T = NTile<DIM>;
-    __shared__ double s[T::NS];
+    __shared__ R s[T::NS];
     const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
-    fill_nodes<DIM>(g, x, s, ox, oy, oz);
+    fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
     __syncthreads();
     const int tx = threadIdx.x % NodalCfg<DIM>::BX, ty = (threadIdx.x / NodalCfg<DIM>::BX) % NodalCfg<DIM>::BY,
               tz = threadIdx.x / (NodalCfg<DIM>::BX * NodalCfg<DIM>::BY);
@@ -91,23 +92,23 @@ k_nodal_gs_tile(GridD g, int colour, double* __restrict__ x, const double* __res
                       DIM == 3 ? oz + 2 * tz + ((colour >> 2) & 1) : 0};
     if (G[0] >= nnode(g, 0) || G[1] >= nnode(g, 1) || G[2] >= nnode(g, 2)) return;
     const int l = T::at(G[0] - ox + 1, G[1] - oy + 1, DIM == 3 ? G[2] - oz + 1 : 0);
-    double dg;
-    const double Kx = tile_K<DIM>(g, s, G, l, &dg);
+    R dg;
+    const R Kx = tile_K<DIM, R>(g, s, G, l, &dg);
     const long q = nid(g, G[0], G[1], G[2]);
     x[q] = s[l] + (b[q] - Kx) / dg;
 }
 
-// r = b - K x (and its max-norm) or y = K x over all nodes
-template <int DIM>
+// r = b - K x (and, FP64, its max-norm) or y = K x over all nodes
+template <int DIM, typename R>
 __global__ void __launch_bounds__(NTile<DIM>::THREADS)
-k_nodal_resid_tile(GridD g, const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ out,
+k_nodal_resid_tile(GridD g, const R* __restrict__ x, const R* __restrict__ b, R* __restrict__ out,
                    double* __restrict__ mx)
 {
     using T = NTile<DIM>;
-    __shared__ double s[T::NS];
+    __shared__ R s[T::NS];
     __shared__ unsigned long long red[16];
     const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
-    fill_nodes<DIM>(g, x, s, ox, oy, oz);
+    fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
     __syncthreads();
     unsigned long long m = 0ull;
     for (int t = threadIdx.x; t < T::TX * T::TY * T::TZ; t += blockDim.x) {
@@ -115,12 +116,12 @@ k_nodal_resid_tile(GridD g, const double* __restrict__ x, const double* __restri
         const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
         if (G[0] >= nnode(g, 0) || G[1] >= nnode(g, 1) || G[2] >= nnode(g, 2)) continue;
         const int l = T::at(rx + 1, ry + 1, DIM == 3 ? rz + 1 : 0);
-        const double Kx = tile_K<DIM>(g, s, G, l, nullptr);
+        const R Kx = tile_K<DIM, R>(g, s, G, l, nullptr);
         const long q = nid(g, G[0], G[1], G[2]);
         if (b) {
-            const double rv = b[q] - Kx;
+            const R rv = b[q] - Kx;
             if (out) out[q] = rv;
-            const unsigned long long bv = abits(rv);
+            const unsigned long long bv = abits((double)rv);
             m = bv > m ? bv : m;
         } else {
             out[q] = Kx;
@@ -140,24 +141,25 @@ static dim3 ntile_grid(const GridD& g)
                 DIM == 3 ? (nnode(g, 2) + T::TZ - 1) / T::TZ : 1);
 }
 
-void launch_nodal_gs(Ctx* c, const Level& l, int colour)
+template <typename R>
+void launch_nodal_gs(Ctx* c, const GridD& g, int colour, R* x, const R* b)
 {
-    if (l.g.dim == 2) k_nodal_gs_tile<2><<<ntile_grid<2>(l.g), NTile<2>::THREADS, 0, c->s>>>(l.g, colour, l.X(), l.b);
-    else k_nodal_gs_tile<3><<<ntile_grid<3>(l.g), NTile<3>::THREADS, 0, c->s>>>(l.g, colour, l.X(), l.b);
+    if (g.dim == 2) k_nodal_gs_tile<2, R><<<ntile_grid<2>(g), NTile<2>::THREADS, 0, c->s>>>(g, colour, x, b);
+    else k_nodal_gs_tile<3, R><<<ntile_grid<3>(g), NTile<3>::THREADS, 0, c->s>>>(g, colour, x, b);
 }
 
-void launch_nodal_resid(Ctx* c, const Level& l, const double* x, const double* b, double* r, int slot)
+template <typename R>
+void launch_nodal_resid(Ctx* c, const GridD& g, const R* x, const R* b, R* r, int slot)
 {
     double* mx = slot >= 0 ? c->sc + slot : nullptr;
-    if (l.g.dim == 2) k_nodal_resid_tile<2><<<ntile_grid<2>(l.g), NTile<2>::THREADS, 0, c->s>>>(l.g, x, b, r, mx);
-    else k_nodal_resid_tile<3><<<ntile_grid<3>(l.g), NTile<3>::THREADS, 0, c->s>>>(l.g, x, b, r, mx);
+    if (g.dim == 2) k_nodal_resid_tile<2, R><<<ntile_grid<2>(g), NTile<2>::THREADS, 0, c->s>>>(g, x, b, r, mx);
+    else k_nodal_resid_tile<3, R><<<ntile_grid<3>(g), NTile<3>::THREADS, 0, c->s>>>(g, x, b, r, mx);
 }
 
-void launch_nodal_apply(Ctx* c, const Level& l, const double* x, double* y)
-{
-    if (l.g.dim == 2) k_nodal_resid_tile<2><<<ntile_grid<2>(l.g), NTile<2>::THREADS, 0, c->s>>>(l.g, x, nullptr, y, nullptr);
-    else k_nodal_resid_tile<3><<<ntile_grid<3>(l.g), NTile<3>::THREADS, 0, c->s>>>(l.g, x, nullptr, y, nullptr);
-}
+template void launch_nodal_gs<double>(Ctx*, const GridD&, int, double*, const double*);
+template void launch_nodal_gs<float>(Ctx*, const GridD&, int, float*, const float*);
+template void launch_nodal_resid<double>(Ctx*, const GridD&, const double*, const double*, double*, int);
+template void launch_nodal_resid<float>(Ctx*, const GridD&, const float*, const float*, float*, int);
 
 // dense coarsest matrix with the same assembled stencil (global reads)
 template <int DIM>

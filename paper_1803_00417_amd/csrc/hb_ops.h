@@ -1,7 +1,7 @@
-// hb_ops.h -- pointwise device operators shared by the per-level kernels and
-// the single-workgroup coarse-level kernel: the tensor viscous flux and
-// divergence, the MAC Laplacian and the assembled Q1 stiffness, all reading
-// global memory with boundary values produced on the fly.
+// hb_ops.h -- pointwise device operators of the global-memory kernels: the
+// tensor viscous flux and divergence, the MAC Laplacian and the assembled Q1
+// stiffness, all reading global memory with boundary values produced on the
+// fly.
 #pragma once
 #include "hb_internal.h"
 
@@ -81,17 +81,19 @@ __device__ inline double visc_diag(const GridD& g, const double* __restrict__ be
 }
 
 // L_mac x at one cell, as the divergence of face gradients
-__device__ inline double mac_lap_at(const GridD& g, const double* __restrict__ x, int i, int j, int k)
+template <typename R>
+__device__ inline R mac_lap_at(const GridD& g, const R* __restrict__ x, int i, int j, int k)
 {
-    const double xc = x[cid(g, i, j, k)];
-    double s = 0.0;
+    const R h = (R)g.h;
+    const R xc = x[cid(g, i, j, k)];
+    R s = 0;
     for (int a = 0; a < g.dim; ++a) {
         int p[3] = {i, j, k}, m[3] = {i, j, k};
         p[a] += 1;
         m[a] -= 1;
-        const double Fhi = wrap(g, p) ? (x[cid(g, p[0], p[1], p[2])] - xc) / g.h : 0.0;
-        const double Flo = wrap(g, m) ? (xc - x[cid(g, m[0], m[1], m[2])]) / g.h : 0.0;
-        s += (Fhi - Flo) / g.h;
+        const R Fhi = wrap(g, p) ? (x[cid(g, p[0], p[1], p[2])] - xc) / h : R(0);
+        const R Flo = wrap(g, m) ? (xc - x[cid(g, m[0], m[1], m[2])]) / h : R(0);
+        s += (Fhi - Flo) / h;
     }
     return s;
 }
@@ -112,15 +114,15 @@ __device__ inline int node_cnt(const GridD& g, int a, int i, int d)
 
 // value of x at node (i,j,k) (periodic wrap; outside a wall reads 0: its
 // stencil weight is zero)
-template <int DIM>
-__device__ inline double node_fetch(const GridD& g, const double* __restrict__ x, int i, int j, int k)
+template <int DIM, typename R>
+__device__ inline R node_fetch(const GridD& g, const R* __restrict__ x, int i, int j, int k)
 {
     int p[3] = {i, j, k};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int nn = nnode(g, a);
         if (p[a] >= 0 && p[a] < nn) continue;
-        if (!g.per[a]) return 0.0;
+        if (!g.per[a]) return R(0);
         p[a] = p[a] < 0 ? p[a] + nn : p[a] - nn;
     }
     return x[nid(g, p[0], p[1], p[2])];
@@ -139,7 +141,7 @@ __device__ inline double K_glob(const GridD& g, const double* __restrict__ x, in
                 const int c0 = node_cnt(g, 0, G[0], dx), c1 = node_cnt(g, 1, G[1], dy);
                 const int c2 = DIM == 3 ? node_cnt(g, 2, G[2], dz) : 1;
                 const double w = q1_ke(DIM, g.h, kk) * (double)(c0 * c1 * c2);
-                acc += w * node_fetch<DIM>(g, x, G[0] + dx, G[1] + dy, G[2] + dz);
+                acc += w * node_fetch<DIM, double>(g, x, G[0] + dx, G[1] + dy, G[2] + dz);
             }
     if (diag) {
         const int c2 = DIM == 3 ? node_cnt(g, 2, G[2], 0) : 1;

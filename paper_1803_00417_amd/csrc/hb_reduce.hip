@@ -82,17 +82,6 @@ void sub_mean(Ctx* c, double* v, long n)
     k_sub_mean<<<(unsigned)(nb < 4096 ? nb : 4096), kT, 0, c->s>>>(v, n, c->sc + S_SUM);
 }
 
-__global__ void k_axpby(double* __restrict__ y, double a, const double* __restrict__ x, double b, long n)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = a * x[i] + b * y[i];
-}
-
-void axpby(Ctx* c, double* y, double a, const double* x, double b, long n)
-{
-    const long nb = (n + kT - 1) / kT;
-    k_axpby<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(y, a, x, b, n);
-}
-
 __global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
@@ -115,60 +104,7 @@ void fill(Ctx* c, double* dst, double v, long n)
     k_fill<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(dst, v, n);
 }
 
-// ---- BiCGStab updates (same element formulas as the textbook algorithm) ----
-
-// p = r + beta (p - omega v)
-__global__ void k_bicg_p(double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
-                         double beta, double omega, long n)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        p[i] = r[i] + beta * (p[i] - omega * v[i]);
-}
-
-// out = a - s b, with the max-norm of out into *mx
-__global__ void k_sub_scaled_max(double* __restrict__ out, const double* __restrict__ a, double s,
-                                 const double* __restrict__ b, long n, double* __restrict__ mx)
-{
-    __shared__ unsigned long long sh[kT / 64];
-    unsigned long long m = 0ull;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double v = a[i] - s * b[i];
-        out[i] = v;
-        const unsigned long long bb = abits(v);
-        m = bb > m ? bb : m;
-    }
-    m = block_umax(m, sh);
-    if (threadIdx.x == 0) atomic_max_bits(mx, m);
-}
-
-// x += alpha ph + omega sh
-__global__ void k_bicg_x(double* __restrict__ x, const double* __restrict__ ph, const double* __restrict__ sh_,
-                         double alpha, double omega, long n)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        x[i] += alpha * ph[i] + omega * sh_[i];
-}
-
-void bicg_p(Ctx* c, double* p, const double* r, const double* v, double beta, double omega, long n)
-{
-    const long nb = (n + kT - 1) / kT;
-    k_bicg_p<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(p, r, v, beta, omega, n);
-}
-
-void sub_scaled_max(Ctx* c, double* out, const double* a, double s, const double* b, long n, int slot)
-{
-    set_slot_zero(c, slot);
-    const long nb = (n + kT - 1) / kT;
-    k_sub_scaled_max<<<(unsigned)(nb < kRedBlocks ? nb : kRedBlocks), kT, 0, c->s>>>(out, a, s, b, n, c->sc + slot);
-}
-
-void bicg_x(Ctx* c, double* x, const double* ph, const double* sh, double alpha, double omega, long n)
-{
-    const long nb = (n + kT - 1) / kT;
-    k_bicg_x<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(x, ph, sh, alpha, omega, n);
-}
-
-// ---- the same updates with the scalars read from device slots ---------------
+// ---- BiCGStab updates, with the scalars read from device slots ------------
 
 __global__ void k_bicg_scalars(double* sc, int which)
 {
@@ -247,6 +183,46 @@ void bicg_x_dev(Ctx* c, double* x, const double* ph, const double* sh, bool with
 {
     const long nb = (n + kT - 1) / kT;
     k_bicg_x_dev<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(x, ph, sh, c->sc, with_omega ? 1 : 0, n);
+}
+
+// ---- precision conversions of the mixed-precision correction cycles ---------
+
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, float* __restrict__ zero, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        dst[i] = (float)src[i];
+        if (zero) zero[i] = 0.0f;
+    }
+}
+
+void to_f32(Ctx* c, const double* src, float* dst, float* zero, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_to_f32<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(src, dst, zero, n);
+}
+
+__global__ void k_add_f32(double* __restrict__ x, const float* __restrict__ e, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] += (double)e[i];
+}
+
+void add_f32(Ctx* c, double* x, const float* e, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_add_f32<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(x, e, n);
+}
+
+__global__ void k_from_f32(const float* __restrict__ e, double* __restrict__ x, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] = (double)e[i];
+}
+
+void from_f32(Ctx* c, const float* e, double* x, long n)
+{
+    const long nb = (n + kT - 1) / kT;
+    k_from_f32<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(e, x, n);
 }
 
 }  // namespace hb

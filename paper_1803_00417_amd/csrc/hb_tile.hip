@@ -1,5 +1,6 @@
 // hb_tile.hip -- LDS-tiled kernels of the tensor viscous problem for the
-// fine multigrid levels (gfx950, FP64):
+// multigrid levels (gfx950), templated on the storage and arithmetic type R
+// (double, or float in the mixed-precision correction cycles):
 //   k_tsmooth       one component's red AND black Gauss-Seidel half sweeps in
 //                   one launch: the tile plus a 2-cell halo of every component
 //                   is staged in LDS, red cells are updated on the tile and its
@@ -10,8 +11,8 @@
 //   k_tresid_restr  fine residual and its restriction (mean of children).
 // Boundary values (odd wall reflection, periodic wrap) are produced once, when
 // the tile is filled; the stencil then reads plain LDS offsets.
-// The arithmetic per cell is the same sequence as the global-memory kernels,
-// so results do not depend on the tiling.
+// For R = double the arithmetic per cell is the same sequence as the
+// global-memory operator, so results do not depend on the tiling.
 #include "hb_internal.h"
 
 namespace hb {
@@ -25,28 +26,28 @@ template <> struct TileCfg<3> { static constexpr int TX = 32, TY = 4, TZ = 4, TH
 // global position that may lie outside the box; positions outside along two
 // or more wall axes (never used by the stencil) read as 0.  With MIRROR the
 // wall ghost is the mirrored value itself (used for the viscosity tile).
-template <int DIM>
-__device__ inline double tile_fetch(const GridD& g, const double* __restrict__ q, int i, int j, int k, bool mirror)
+template <int DIM, typename R>
+__device__ inline R tile_fetch(const GridD& g, const R* __restrict__ q, int i, int j, int k, bool mirror)
 {
     int p[3] = {i, j, k};
     int out = 0;
-    double sg = 1.0;
+    R sg = 1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int n = g.n[a];
         if (p[a] >= 0 && p[a] < n) continue;
         if (g.per[a]) {
             p[a] = p[a] < 0 ? p[a] + n : p[a] - n;
-            if (p[a] < 0 || p[a] >= n) return 0.0;
+            if (p[a] < 0 || p[a] >= n) return R(0);
         } else {
             ++out;
             p[a] = p[a] < 0 ? -1 - p[a] : 2 * n - 1 - p[a];
-            if (p[a] < 0 || p[a] >= n) return 0.0;
+            if (p[a] < 0 || p[a] >= n) return R(0);
             sg = -sg;
         }
     }
-    if (out > 1) return 0.0;
-    const double v = q[cid(g, p[0], p[1], p[2])];
+    if (out > 1) return R(0);
+    const R v = q[cid(g, p[0], p[1], p[2])];
     return mirror ? v : sg * v;
 }
 
@@ -64,9 +65,9 @@ struct Tile {
 // Stage NA arrays (tile plus halo H) in LDS.  Every thread first issues all
 // of its global loads into registers, then stores them, so the loads of a
 // block are in flight together instead of one round trip per element.
-template <int DIM, int H, int NA>
-__device__ inline void fill_batched(const GridD& g, const double* const* q, const bool* mirror, double* s,
-                                    int ox, int oy, int oz)
+template <int DIM, int H, int NA, typename R>
+__device__ inline void fill_batched(const GridD& g, const R* const* q, const bool* mirror, R* s, int ox, int oy,
+                                    int oz)
 {
     using T = Tile<DIM, H>;
     constexpr int TH = TileCfg<DIM>::THREADS;
@@ -74,7 +75,7 @@ __device__ inline void fill_batched(const GridD& g, const double* const* q, cons
     // tiles away from every domain face need no boundary logic
     const bool inner = ox - H >= 0 && ox + T::TX + H <= g.n[0] && oy - H >= 0 && oy + T::TY + H <= g.n[1] &&
                        (DIM == 2 || (oz - H >= 0 && oz + T::TZ + H <= g.n[2]));
-    double v[NA][K];
+    R v[NA][K];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
         const int t = threadIdx.x + u * TH;
@@ -87,7 +88,7 @@ __device__ inline void fill_batched(const GridD& g, const double* const* q, cons
             for (int a = 0; a < NA; ++a) v[a][u] = q[a][idx];
         } else {
 #pragma unroll
-            for (int a = 0; a < NA; ++a) v[a][u] = tile_fetch<DIM>(g, q[a], i, j, k, mirror[a]);
+            for (int a = 0; a < NA; ++a) v[a][u] = tile_fetch<DIM, R>(g, q[a], i, j, k, mirror[a]);
         }
     }
 #pragma unroll
@@ -100,9 +101,8 @@ __device__ inline void fill_batched(const GridD& g, const double* const* q, cons
 }
 
 // fill of the 3D halo-1 tile by a 256-thread block (k_trb3)
-template <bool FINE>
-__device__ inline void fill_tile1(const GridD& g, const double* const* q, const bool* mirror, double* s, int ox, int oy,
-                                  int oz)
+template <bool FINE, typename R>
+__device__ inline void fill_tile1(const GridD& g, const R* const* q, const bool* mirror, R* s, int ox, int oy, int oz)
 {
     using T = Tile<3, 1>;
     constexpr int TH = 256;
@@ -110,7 +110,7 @@ __device__ inline void fill_tile1(const GridD& g, const double* const* q, const 
     constexpr int K = (T::NS + TH - 1) / TH;
     const bool inner = ox - 1 >= 0 && ox + T::TX + 1 <= g.n[0] && oy - 1 >= 0 && oy + T::TY + 1 <= g.n[1] &&
                        oz - 1 >= 0 && oz + T::TZ + 1 <= g.n[2];
-    double v[NA][K];
+    R v[NA][K];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
         const int t = threadIdx.x + u * TH;
@@ -123,7 +123,7 @@ __device__ inline void fill_tile1(const GridD& g, const double* const* q, const 
             for (int a = 0; a < NA; ++a) v[a][u] = q[a][idx];
         } else {
 #pragma unroll
-            for (int a = 0; a < NA; ++a) v[a][u] = tile_fetch<3>(g, q[a], i, j, k, mirror[a]);
+            for (int a = 0; a < NA; ++a) v[a][u] = tile_fetch<3, R>(g, q[a], i, j, k, mirror[a]);
         }
     }
 #pragma unroll
@@ -151,12 +151,13 @@ __device__ inline int wall_mask(const GridD& g, const int G[3])
 }
 
 // face viscosity from the level's face arrays (coarse levels)
-__device__ inline double face_beta_global(const GridD& g, const double* __restrict__ beta, int a, const int G[3], int side)
+template <typename R>
+__device__ inline R face_beta_global(const GridD& g, const R* __restrict__ beta, int a, const int G[3], int side)
 {
-    int R[3] = {G[0], G[1], G[2]};
-    R[a] += side;
-    if (g.per[a] && R[a] == g.n[a]) R[a] = 0;
-    return beta[foffset(g, a) + fid(g, a, R[0], R[1], R[2])];
+    int F[3] = {G[0], G[1], G[2]};
+    F[a] += side;
+    if (g.per[a] && F[a] == g.n[a]) F[a] = 0;
+    return beta[foffset(g, a) + fid(g, a, F[0], F[1], F[2])];
 }
 
 // div(beta gamma_dot(x))_c at a cell of an LDS tile, and the diagonal of the
@@ -164,45 +165,45 @@ __device__ inline double face_beta_global(const GridD& g, const double* __restri
 // (mean of the two cells, the interior cell on wall faces); otherwise from
 // the global face arrays.  Same arithmetic sequence per face as the
 // global-memory operator.
-template <int DIM, int H, bool FINE>
-__device__ inline double tile_visc_div(const GridD& g, const double* __restrict__ beta, const double* s,
-                                       const double* e, int c, const int G[3], int wm, int l0, double dt,
-                                       double* diag)
+template <int DIM, int H, bool FINE, typename R>
+__device__ inline R tile_visc_div(const GridD& g, const R* __restrict__ beta, const R* s, const R* e, int c,
+                                  const int G[3], int wm, int l0, R dt, R* diag)
 {
     using T = Tile<DIM, H>;
     const int off[3] = {1, T::SX, T::SX * T::SY};
-    const double* sc = s + c * T::NS;
-    double acc = 0.0, coefsum = 0.0;
+    const R h = (R)g.h;
+    const R* sc = s + c * T::NS;
+    R acc = 0, coefsum = 0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        double flux[2];
+        R flux[2];
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int lL = l0 + (side - 1) * off[a];
             const int lR = lL + off[a];
             const bool wall = (wm >> (2 * a + side)) & 1;
-            double bf;
-            if (FINE) bf = wall ? e[l0] : 0.5 * (e[lL] + e[lR]);
-            else bf = face_beta_global(g, beta, a, G, side);
-            const double dn = (sc[lR] - sc[lL]) / g.h;
-            double f;
+            R bf;
+            if (FINE) bf = wall ? e[l0] : R(0.5) * (e[lL] + e[lR]);
+            else bf = face_beta_global<R>(g, beta, a, G, side);
+            const R dn = (sc[lR] - sc[lL]) / h;
+            R f;
             if (a == c) {
                 f = bf * dn;
             } else if (wall) {
-                f = bf * 0.5 * dn;
+                f = bf * R(0.5) * dn;
             } else {
-                const double* sa = s + a * T::NS;
-                const double dL = (sa[lL + off[c]] - sa[lL - off[c]]) / (2.0 * g.h);
-                const double dR = (sa[lR + off[c]] - sa[lR - off[c]]) / (2.0 * g.h);
-                const double cross = 0.5 * (dL + dR);
-                f = bf * 0.5 * (dn + cross);
+                const R* sa = s + a * T::NS;
+                const R dL = (sa[lL + off[c]] - sa[lL - off[c]]) / (R(2) * h);
+                const R dR = (sa[lR + off[c]] - sa[lR - off[c]]) / (R(2) * h);
+                const R cross = R(0.5) * (dL + dR);
+                f = bf * R(0.5) * (dn + cross);
             }
             flux[side] = f;
-            coefsum += (wall ? 2.0 : 1.0) * ((a == c) ? 1.0 : 0.5) * bf;
+            coefsum += (wall ? R(2) : R(1)) * ((a == c) ? R(1) : R(0.5)) * bf;
         }
-        acc += (flux[1] - flux[0]) / g.h;
+        acc += (flux[1] - flux[0]) / h;
     }
-    if (diag) *diag = 1.0 + dt * coefsum / (g.h * g.h);
+    if (diag) *diag = R(1) + dt * coefsum / (h * h);
     return acc;
 }
 
@@ -240,54 +241,57 @@ __device__ inline bool colour_cell(const GridD& g, int t, int ring, int colour, 
     return inside;
 }
 
-template <int DIM, bool FINE>
+// dynamic LDS of the tile kernels, viewed as an array of R
+extern __shared__ __align__(16) unsigned char tile_lds[];
+
+template <int DIM, bool FINE, typename R>
 __global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
-k_tsmooth(GridD g, const double* __restrict__ coef, const double* __restrict__ dtp, int c,
-          const double* __restrict__ xcur, const double* xnext_in, double* xnext, const double* __restrict__ b)
+k_tsmooth(GridD g, const R* __restrict__ coef, const double* __restrict__ dtp, int c, const R* __restrict__ xcur,
+          const R* xnext_in, R* xnext, const R* __restrict__ b)
 {
-    const double dt = *dtp;
+    const R dt = (R)*dtp;
     using T = Tile<DIM, 2>;
     constexpr int TH = TileCfg<DIM>::THREADS;
     constexpr int RZ1 = DIM == 3 ? T::TZ + 2 : 1;
     constexpr int KR = ((T::TX + 2) / 2 * (T::TY + 2) * RZ1 + TH - 1) / TH;   // red slots per thread
     constexpr int KB = (T::TX / 2 * T::TY * T::TZ + TH - 1) / TH;            // black slots per thread
-    extern __shared__ double s[];
-    double* e = s + DIM * T::NS;     // eta/Re tile (FINE)
+    R* s = reinterpret_cast<R*>(tile_lds);
+    R* e = s + DIM * T::NS;     // eta/Re tile (FINE)
     const long N = ncells(g);
     const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
-    const double* bc = b + c * N;
+    const R* bc = b + c * N;
     // this thread's cells of each colour, and their right-hand sides
     int rG[KR][3], rL[KR];
     bool rOk[KR];
-    double rB[KR];
+    R rB[KR];
 #pragma unroll
     for (int u = 0; u < KR; ++u) {
         int L[3];
         rOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 1, 0, ox, oy, oz, rG[u], L);
         rL[u] = T::at(L[0], L[1], L[2]);
-        rB[u] = rOk[u] ? bc[cid(g, rG[u][0], rG[u][1], rG[u][2])] : 0.0;
+        rB[u] = rOk[u] ? bc[cid(g, rG[u][0], rG[u][1], rG[u][2])] : R(0);
     }
     int kG[KB][3], kL[KB];
     bool kOk[KB];
-    double kB[KB];
+    R kB[KB];
 #pragma unroll
     for (int u = 0; u < KB; ++u) {
         int L[3];
         kOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 0, 1, ox, oy, oz, kG[u], L);
         kL[u] = T::at(L[0], L[1], L[2]);
-        kB[u] = kOk[u] ? bc[cid(g, kG[u][0], kG[u][1], kG[u][2])] : 0.0;
+        kB[u] = kOk[u] ? bc[cid(g, kG[u][0], kG[u][1], kG[u][2])] : R(0);
     }
     // components already swept in this sweep live in the next buffer
     {
-        const double* q[DIM + 1];
+        const R* q[DIM + 1];
         bool mir[DIM + 1];
         for (int a = 0; a < DIM; ++a) { q[a] = (a < c ? xnext_in : xcur) + a * N; mir[a] = false; }
         q[DIM] = coef;
         mir[DIM] = true;
-        fill_batched<DIM, 2, DIM + (FINE ? 1 : 0)>(g, q, mir, s, ox, oy, oz);
+        fill_batched<DIM, 2, DIM + (FINE ? 1 : 0), R>(g, q, mir, s, ox, oy, oz);
     }
     __syncthreads();
-    double* sc = s + c * T::NS;
+    R* sc = s + c * T::NS;
     // red cells of the tile and its 1-cell ring, then black cells of the
     // tile; a cell of one colour reads only the other colour of component c
     // (face neighbours) and the other components, so each colour is updated
@@ -295,23 +299,23 @@ k_tsmooth(GridD g, const double* __restrict__ coef, const double* __restrict__ d
 #pragma unroll
     for (int u = 0; u < KR; ++u) {
         if (!rOk[u]) continue;
-        double dg;
-        const double vd = tile_visc_div<DIM, 2, FINE>(g, coef, s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
-        const double Au = sc[rL[u]] - dt * vd;
+        R dg;
+        const R vd = tile_visc_div<DIM, 2, FINE, R>(g, coef, s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
+        const R Au = sc[rL[u]] - dt * vd;
         sc[rL[u]] += (rB[u] - Au) / dg;
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < KB; ++u) {
         if (!kOk[u]) continue;
-        double dg;
-        const double vd = tile_visc_div<DIM, 2, FINE>(g, coef, s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
-        const double Au = sc[kL[u]] - dt * vd;
+        R dg;
+        const R vd = tile_visc_div<DIM, 2, FINE, R>(g, coef, s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
+        const R Au = sc[kL[u]] - dt * vd;
         sc[kL[u]] += (kB[u] - Au) / dg;
     }
     __syncthreads();
     // write the tile's cells of component c
-    double* xo = xnext + c * N;
+    R* xo = xnext + c * N;
     for (int t = threadIdx.x; t < T::TX * T::TY * T::TZ; t += blockDim.x) {
         const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
         const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
@@ -321,7 +325,7 @@ k_tsmooth(GridD g, const double* __restrict__ coef, const double* __restrict__ d
 }
 
 // ---------------------------------------------------------------------------
-// residual / operator application / residual + restriction (halo 1)
+// residual / operator application (FP64, halo 1) and residual + restriction
 // ---------------------------------------------------------------------------
 
 template <int DIM, bool FINE>
@@ -331,7 +335,7 @@ k_tresid(GridD g, const double* __restrict__ coef, const double* __restrict__ dt
 {
     const double dt = *dtp;
     using T = Tile<DIM, 1>;
-    extern __shared__ double s[];
+    double* s = reinterpret_cast<double*>(tile_lds);
     double* e = s + DIM * T::NS;
     __shared__ unsigned long long red[16];
     const long N = ncells(g);
@@ -342,7 +346,7 @@ k_tresid(GridD g, const double* __restrict__ coef, const double* __restrict__ dt
         for (int a = 0; a < DIM; ++a) { q[a] = x + a * N; mir[a] = false; }
         q[DIM] = coef;
         mir[DIM] = true;
-        fill_batched<DIM, 1, DIM + (FINE ? 1 : 0)>(g, q, mir, s, ox, oy, oz);
+        fill_batched<DIM, 1, DIM + (FINE ? 1 : 0), double>(g, q, mir, s, ox, oy, oz);
     }
     __syncthreads();
     unsigned long long m = 0ull;
@@ -354,7 +358,7 @@ k_tresid(GridD g, const double* __restrict__ coef, const double* __restrict__ dt
         const int wm = wall_mask<DIM>(g, G);
         const long q0 = cid(g, G[0], G[1], G[2]);
         for (int c = 0; c < DIM; ++c) {
-            const double vd = tile_visc_div<DIM, 1, FINE>(g, coef, s, e, c, G, wm, l, dt, nullptr);
+            const double vd = tile_visc_div<DIM, 1, FINE, double>(g, coef, s, e, c, G, wm, l, dt, nullptr);
             const double Ax = s[c * T::NS + l] - dt * vd;
             if (b) {
                 const double rv = b[c * N + q0] - Ax;
@@ -372,27 +376,26 @@ k_tresid(GridD g, const double* __restrict__ coef, const double* __restrict__ dt
     }
 }
 
-template <int DIM, bool FINE>
+template <int DIM, bool FINE, typename R>
 __global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
-k_tresid_restr(GridD g, GridD gc, const double* __restrict__ coef, const double* __restrict__ dtp,
-               const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ bcoarse,
-               double* __restrict__ xcoarse)
+k_tresid_restr(GridD g, GridD gc, const R* __restrict__ coef, const double* __restrict__ dtp, const R* __restrict__ x,
+               const R* __restrict__ b, R* __restrict__ bcoarse, R* __restrict__ xcoarse)
 {
-    const double dt = *dtp;
+    const R dt = (R)*dtp;
     using T = Tile<DIM, 1>;
-    extern __shared__ double s[];
-    double* e = s + DIM * T::NS;
-    double* r = e + T::NS;   // residual of the tile, [c][tile cell]
+    R* s = reinterpret_cast<R*>(tile_lds);
+    R* e = s + DIM * T::NS;
+    R* r = e + T::NS;   // residual of the tile, [c][tile cell]
     constexpr int NT = T::TX * T::TY * T::TZ;
     const long N = ncells(g), Nc = ncells(gc);
     const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
     {
-        const double* q[DIM + 1];
+        const R* q[DIM + 1];
         bool mir[DIM + 1];
         for (int a = 0; a < DIM; ++a) { q[a] = x + a * N; mir[a] = false; }
         q[DIM] = coef;
         mir[DIM] = true;
-        fill_batched<DIM, 1, DIM + (FINE ? 1 : 0)>(g, q, mir, s, ox, oy, oz);
+        fill_batched<DIM, 1, DIM + (FINE ? 1 : 0), R>(g, q, mir, s, ox, oy, oz);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < NT; t += blockDim.x) {
@@ -403,8 +406,8 @@ k_tresid_restr(GridD g, GridD gc, const double* __restrict__ coef, const double*
         const int wm = wall_mask<DIM>(g, G);
         const long q0 = cid(g, G[0], G[1], G[2]);
         for (int c = 0; c < DIM; ++c) {
-            const double vd = tile_visc_div<DIM, 1, FINE>(g, coef, s, e, c, G, wm, l, dt, nullptr);
-            const double Ax = s[c * T::NS + l] - dt * vd;
+            const R vd = tile_visc_div<DIM, 1, FINE, R>(g, coef, s, e, c, G, wm, l, dt, nullptr);
+            const R Ax = s[c * T::NS + l] - dt * vd;
             r[c * NT + t] = b[c * N + q0] - Ax;
         }
     }
@@ -417,15 +420,58 @@ k_tresid_restr(GridD g, GridD gc, const double* __restrict__ coef, const double*
         if (C[0] >= gc.n[0] || C[1] >= gc.n[1] || C[2] >= gc.n[2]) continue;
         const long qc = cid(gc, C[0], C[1], C[2]);
         for (int c = 0; c < DIM; ++c) {
-            double sum = 0.0;
+            R sum = 0;
             for (int bits = 0; bits < nch; ++bits) {
                 const int fx = 2 * cx + (bits & 1), fy = 2 * cy + ((bits >> 1) & 1), fz = DIM == 3 ? 2 * cz + ((bits >> 2) & 1) : 0;
                 sum += r[c * NT + (fz * T::TY + fy) * T::TX + fx];
             }
-            bcoarse[c * Nc + qc] = sum / (double)nch;
-            xcoarse[c * Nc + qc] = 0.0;
+            bcoarse[c * Nc + qc] = sum / R(nch);
+            xcoarse[c * Nc + qc] = R(0);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// 3D: one colour of one component per launch, updated in place.  The cells
+// of one colour read only the other colour of component c and the other
+// components, none of which change in the launch, so blocks can update their
+// tiles in place without a second buffer; the tile needs a 1-cell halo only.
+// In 3D this needs fewer operator evaluations and less LDS than the fused
+// two-colour sweep (whose 2-cell halo is large relative to a 3D tile).
+// ---------------------------------------------------------------------------
+
+template <bool FINE, typename R>
+__global__ void __launch_bounds__(256)
+k_trb3(GridD g, const R* __restrict__ coef, const double* __restrict__ dtp, int c, int colour, R* x,
+       const R* __restrict__ b)
+{
+    using T = Tile<3, 1>;
+    static_assert(T::TX * T::TY * T::TZ / 2 == 256, "one cell of the colour per thread");
+    R* s = reinterpret_cast<R*>(tile_lds);
+    R* e = s + 3 * T::NS;
+    const R dt = (R)*dtp;
+    const long N = ncells(g);
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    // this thread's cell of the colour and its right-hand side
+    const int t = threadIdx.x;
+    const int px = t % (T::TX / 2), ry = (t / (T::TX / 2)) % T::TY, rz = t / (T::TX / 2 * T::TY);
+    const int G[3] = {ox + 2 * px + ((ox + oy + ry + oz + rz + colour) & 1), oy + ry, oz + rz};
+    const bool ok = G[0] < g.n[0] && G[1] < g.n[1] && G[2] < g.n[2];
+    const long q0 = ok ? cid(g, G[0], G[1], G[2]) : 0;
+    const R bv = ok ? b[c * N + q0] : R(0);
+    {
+        const R* q[4] = {x, x + N, x + 2 * N, coef};
+        const bool mir[4] = {false, false, false, true};
+        fill_tile1<FINE, R>(g, q, mir, s, ox, oy, oz);
+    }
+    __syncthreads();
+    if (!ok) return;
+    const int l = T::at(G[0] - ox + 1, ry + 1, rz + 1);
+    R dg;
+    const R vd = tile_visc_div<3, 1, FINE, R>(g, coef, s, e, c, G, wall_mask<3>(g, G), l, dt, &dg);
+    const R xc = s[c * T::NS + l];
+    const R Au = xc - dt * vd;
+    x[c * N + q0] = xc + (bv - Au) / dg;
 }
 
 // ---------------------------------------------------------------------------
@@ -439,26 +485,28 @@ static dim3 tile_grid(const GridD& g)
     return dim3((g.n[0] + T::TX - 1) / T::TX, (g.n[1] + T::TY - 1) / T::TY, DIM == 3 ? (g.n[2] + T::TZ - 1) / T::TZ : 1);
 }
 
-template <int DIM, bool FINE>
-static void tsmooth_impl(Ctx* c, const GridD& g, const double* coef, const double* dtp, int comp, const double* xcur,
-                         double* xnext, const double* b)
+template <int DIM, bool FINE, typename R>
+static void tsmooth_impl(Ctx* c, const GridD& g, const R* coef, const double* dtp, int comp, const R* xcur, R* xnext,
+                         const R* b)
 {
-    const size_t lds = sizeof(double) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 2>::NS;
-    k_tsmooth<DIM, FINE><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, coef, dtp, comp, xcur, xnext, xnext, b);
+    const size_t lds = sizeof(R) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 2>::NS;
+    k_tsmooth<DIM, FINE, R><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, coef, dtp, comp, xcur, xnext,
+                                                                                     xnext, b);
 }
 
-void launch_tsmooth(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp, const double* xcur,
-                    double* xnext, const double* b)
+template <typename R>
+void launch_tsmooth(Ctx* c, const GridD& g, const R* coef, bool fine, const double* dtp, int comp, const R* xcur,
+                    R* xnext, const R* b)
 {
     const bool timed = c->ktm.on && fine;
     if (timed) kt_begin(c);
     if (g.dim == 2) {
-        if (fine) tsmooth_impl<2, true>(c, g, coef, dtp, comp, xcur, xnext, b);
-        else tsmooth_impl<2, false>(c, g, coef, dtp, comp, xcur, xnext, b);
+        if (fine) tsmooth_impl<2, true, R>(c, g, coef, dtp, comp, xcur, xnext, b);
+        else tsmooth_impl<2, false, R>(c, g, coef, dtp, comp, xcur, xnext, b);
     } else if (fine) {
-        tsmooth_impl<3, true>(c, g, coef, dtp, comp, xcur, xnext, b);
+        tsmooth_impl<3, true, R>(c, g, coef, dtp, comp, xcur, xnext, b);
     } else {
-        tsmooth_impl<3, false>(c, g, coef, dtp, comp, xcur, xnext, b);
+        tsmooth_impl<3, false, R>(c, g, coef, dtp, comp, xcur, xnext, b);
     }
     if (timed) {
         // algorithmic bytes of one fused red-black sweep of one component:
@@ -471,7 +519,7 @@ void launch_tsmooth(Ctx* c, const GridD& g, const double* coef, bool fine, const
             coefw = 0.0;
             for (int a = 0; a < g.dim; ++a) coefw += (double)fcount(g, a);
         }
-        kt_end(c, 8.0 * (g.dim * N + coefw + 2.0 * N));
+        kt_end(c, sizeof(R) * (g.dim * N + coefw + 2.0 * N));
     }
 }
 
@@ -483,8 +531,8 @@ static void tresid_impl(Ctx* c, const GridD& g, const double* coef, const double
     k_tresid<DIM, FINE><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, coef, dtp, x, b, out, mx);
 }
 
-void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, const double* x, const double* b,
-                   double* out, int slot)
+void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, const double* x,
+                   const double* b, double* out, int slot)
 {
     double* mx = slot >= 0 ? c->sc + slot : nullptr;
     if (g.dim == 2) {
@@ -496,90 +544,54 @@ void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const 
     }
 }
 
-template <int DIM, bool FINE>
-static void tresid_restr_impl(Ctx* c, const GridD& g, const GridD& gc, const double* coef, const double* dtp,
-                              const double* x, const double* b, double* bc, double* xc)
+template <int DIM, bool FINE, typename R>
+static void tresid_restr_impl(Ctx* c, const GridD& g, const GridD& gc, const R* coef, const double* dtp, const R* x,
+                              const R* b, R* bc, R* xc)
 {
     using T = Tile<DIM, 1>;
-    const size_t lds = sizeof(double) * (DIM * (T::NS + T::TX * T::TY * T::TZ) + T::NS);
-    k_tresid_restr<DIM, FINE><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, gc, coef, dtp, x, b, bc, xc);
+    const size_t lds = sizeof(R) * (DIM * (T::NS + T::TX * T::TY * T::TZ) + T::NS);
+    k_tresid_restr<DIM, FINE, R><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, gc, coef, dtp, x, b, bc, xc);
 }
 
-void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const double* coef, bool fine, const double* dtp,
-                         const double* x, const double* b, double* bc, double* xc)
+template <typename R>
+void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const R* coef, bool fine, const double* dtp,
+                         const R* x, const R* b, R* bc, R* xc)
 {
     if (g.dim == 2) {
-        if (fine) tresid_restr_impl<2, true>(c, g, gc, coef, dtp, x, b, bc, xc);
-        else tresid_restr_impl<2, false>(c, g, gc, coef, dtp, x, b, bc, xc);
+        if (fine) tresid_restr_impl<2, true, R>(c, g, gc, coef, dtp, x, b, bc, xc);
+        else tresid_restr_impl<2, false, R>(c, g, gc, coef, dtp, x, b, bc, xc);
     } else {
-        if (fine) tresid_restr_impl<3, true>(c, g, gc, coef, dtp, x, b, bc, xc);
-        else tresid_restr_impl<3, false>(c, g, gc, coef, dtp, x, b, bc, xc);
+        if (fine) tresid_restr_impl<3, true, R>(c, g, gc, coef, dtp, x, b, bc, xc);
+        else tresid_restr_impl<3, false, R>(c, g, gc, coef, dtp, x, b, bc, xc);
     }
 }
 
-}  // namespace hb
-
-namespace hb {
-
-// ---------------------------------------------------------------------------
-// 3D: one colour of one component per launch, updated in place.  The cells
-// of one colour read only the other colour of component c and the other
-// components, none of which change in the launch, so blocks can update their
-// tiles in place without a second buffer; the tile needs a 1-cell halo only.
-// In 3D this needs fewer operator evaluations and less LDS than the fused
-// two-colour sweep (whose 2-cell halo is large relative to a 3D tile).
-// ---------------------------------------------------------------------------
-
-template <bool FINE>
-__global__ void __launch_bounds__(256)
-k_trb3(GridD g, const double* __restrict__ coef, const double* __restrict__ dtp, int c, int colour, double* x,
-       const double* __restrict__ b)
-{
-    using T = Tile<3, 1>;
-    static_assert(T::TX * T::TY * T::TZ / 2 == 256, "one cell of the colour per thread");
-    extern __shared__ double s[];
-    double* e = s + 3 * T::NS;
-    const double dt = *dtp;
-    const long N = ncells(g);
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
-    // this thread's cell of the colour and its right-hand side
-    const int t = threadIdx.x;
-    const int px = t % (T::TX / 2), ry = (t / (T::TX / 2)) % T::TY, rz = t / (T::TX / 2 * T::TY);
-    const int G[3] = {ox + 2 * px + ((ox + oy + ry + oz + rz + colour) & 1), oy + ry, oz + rz};
-    const bool ok = G[0] < g.n[0] && G[1] < g.n[1] && G[2] < g.n[2];
-    const long q0 = ok ? cid(g, G[0], G[1], G[2]) : 0;
-    const double bv = ok ? b[c * N + q0] : 0.0;
-    {
-        const double* q[4] = {x, x + N, x + 2 * N, coef};
-        const bool mir[4] = {false, false, false, true};
-        fill_tile1<FINE>(g, q, mir, s, ox, oy, oz);
-    }
-    __syncthreads();
-    if (!ok) return;
-    const int l = T::at(G[0] - ox + 1, ry + 1, rz + 1);
-    double dg;
-    const double vd = tile_visc_div<3, 1, FINE>(g, coef, s, e, c, G, wall_mask<3>(g, G), l, dt, &dg);
-    const double xc = s[c * T::NS + l];
-    const double Au = xc - dt * vd;
-    x[c * N + q0] = xc + (bv - Au) / dg;
-}
-
-void launch_trb3(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, int comp, int colour,
-                 double* x, const double* b)
+template <typename R>
+void launch_trb3(Ctx* c, const GridD& g, const R* coef, bool fine, const double* dtp, int comp, int colour, R* x,
+                 const R* b)
 {
     using T = Tile<3, 1>;
     const bool timed = c->ktm.on && fine;
     if (timed) kt_begin(c);
-    const size_t lds = sizeof(double) * (3 + (fine ? 1 : 0)) * T::NS;
+    const size_t lds = sizeof(R) * (3 + (fine ? 1 : 0)) * T::NS;
     const dim3 grid = tile_grid<3>(g);
-    if (fine) k_trb3<true><<<grid, 256, lds, c->s>>>(g, coef, dtp, comp, colour, x, b);
-    else k_trb3<false><<<grid, 256, lds, c->s>>>(g, coef, dtp, comp, colour, x, b);
+    if (fine) k_trb3<true, R><<<grid, 256, lds, c->s>>>(g, coef, dtp, comp, colour, x, b);
+    else k_trb3<false, R><<<grid, 256, lds, c->s>>>(g, coef, dtp, comp, colour, x, b);
     if (timed) {
         // algorithmic bytes of one half sweep: every component of x and the
         // coefficients read once, the active colour of b read and of x written
         const double N = (double)ncells(g);
-        kt_end(c, 8.0 * (3.0 * N + N + N));
+        kt_end(c, sizeof(R) * (3.0 * N + N + N));
     }
 }
+
+#define HB_TILE_INST(R)                                                                                          \
+    template void launch_tsmooth<R>(Ctx*, const GridD&, const R*, bool, const double*, int, const R*, R*, const R*); \
+    template void launch_trb3<R>(Ctx*, const GridD&, const R*, bool, const double*, int, int, R*, const R*);       \
+    template void launch_tresid_restr<R>(Ctx*, const GridD&, const GridD&, const R*, bool, const double*, const R*, \
+                                         const R*, R*, R*);
+HB_TILE_INST(double)
+HB_TILE_INST(float)
+#undef HB_TILE_INST
 
 }  // namespace hb

@@ -1,7 +1,8 @@
 // hb_visc.hip -- regularised viscosity and the coupled tensor viscous
-// operator (I - dt div(beta gamma_dot(.))) with its multigrid kernels.
-// gfx950, FP64.  One thread per cell (or cell pair for red-black sweeps);
-// x is the fastest index, so a wavefront reads 64 consecutive doubles.
+// operator (I - dt div(beta gamma_dot(.))): explicit divergence, wall
+// right-hand side, face coefficients and the dense coarsest matrix.  gfx950,
+// FP64.  One thread per cell; x is the fastest index, so a wavefront reads 64
+// consecutive doubles.  (The multigrid sweeps are the LDS-tiled kernels.)
 #include "hb_internal.h"
 #include "hb_ops.h"
 
@@ -128,7 +129,9 @@ void launch_visc_div(Ctx* c, const GridD& g, const double* beta, const double* u
 }
 
 // out = rhs + dt div(beta gamma_dot(0 with wall values)): the inhomogeneous
-// wall part of the operator moved to the right-hand side
+// wall part of the operator moved to the right-hand side.  The stencil of a
+// cell reaches one cell along each axis, so only cells in the first layer
+// along a wall axis see a wall value; elsewhere the term is zero.
 __global__ void k_visc_wall_rhs(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ rhs,
                                 double* __restrict__ out)
 {
@@ -137,114 +140,18 @@ __global__ void k_visc_wall_rhs(GridD g, const double* __restrict__ beta, double
     const int k = blockIdx.z;
     if (i >= g.n[0] || j >= g.n[1]) return;
     const long N = ncells(g), q = cid(g, i, j, k);
+    const int p[3] = {i, j, k};
+    bool edge = false;
+    for (int a = 0; a < g.dim; ++a)
+        if (!g.per[a] && (p[a] == 0 || p[a] == g.n[a] - 1)) edge = true;
     for (int c = 0; c < g.dim; ++c)
-        out[c * N + q] = rhs[c * N + q] + dt * visc_div_at<false, true>(g, beta, nullptr, c, i, j, k);
+        out[c * N + q] = edge ? rhs[c * N + q] + dt * visc_div_at<false, true>(g, beta, nullptr, c, i, j, k)
+                              : rhs[c * N + q];
 }
 
 void launch_visc_wall_rhs(Ctx* c, const GridD& g, const double* beta, double dt, const double* rhs, double* out)
 {
     k_visc_wall_rhs<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, beta, dt, rhs, out);
-}
-
-// ---------------------------------------------------------------------------
-// multigrid kernels of the tensor problem
-// ---------------------------------------------------------------------------
-
-// red-black Gauss-Seidel half sweep on one component: the same-component
-// stencil is 5/7-point, so cells of one colour only read the other colour of
-// that component and the (unchanged) other components
-__global__ void k_visc_rb(GridD g, const double* __restrict__ beta, double dt, int c, int colour,
-                          double* __restrict__ x, const double* __restrict__ b)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    const int i = 2 * t + ((j + k + colour) & 1);
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    const long q = (long)c * ncells(g) + cid(g, i, j, k);
-    const double Au = x[q] - dt * visc_div_at<true, false>(g, beta, x, c, i, j, k);
-    const double dg = visc_diag(g, beta, dt, c, i, j, k);
-    x[q] += (b[q] - Au) / dg;
-}
-
-void launch_visc_rb(Ctx* c, const Level& l, double dt, int comp, int colour)
-{
-    k_visc_rb<<<grid3((l.g.n[0] + 1) / 2, l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, comp, colour, l.X(), l.b);
-}
-
-__global__ void k_visc_resid(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ x,
-                             const double* __restrict__ b, double* __restrict__ r, double* __restrict__ mx)
-{
-    __shared__ unsigned long long sh[16];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    unsigned long long m = 0ull;
-    if (i < g.n[0] && j < g.n[1]) {
-        const long N = ncells(g), q = cid(g, i, j, k);
-        for (int c = 0; c < g.dim; ++c) {
-            const double Ax = x[c * N + q] - dt * visc_div_at<true, false>(g, beta, x, c, i, j, k);
-            const double rv = b[c * N + q] - Ax;
-            if (r) r[c * N + q] = rv;
-            { const unsigned long long bv = abits(rv); m = bv > m ? bv : m; }
-        }
-    }
-    if (mx) {
-        m = block_umax(m, sh);
-        if (threadIdx.x + threadIdx.y == 0) atomic_max_bits(mx, m);
-    }
-}
-
-void launch_visc_resid(Ctx* c, const Level& l, double dt, const double* x, const double* b, double* r, int slot)
-{
-    k_visc_resid<<<grid3(l.g.n[0], l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, x, b, r,
-                                                                                 slot >= 0 ? c->sc + slot : nullptr);
-}
-
-__global__ void k_visc_apply(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ x,
-                             double* __restrict__ y)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    const long N = ncells(g), q = cid(g, i, j, k);
-    for (int c = 0; c < g.dim; ++c) y[c * N + q] = x[c * N + q] - dt * visc_div_at<true, false>(g, beta, x, c, i, j, k);
-}
-
-void launch_visc_apply(Ctx* c, const Level& l, double dt, const double* x, double* y)
-{
-    k_visc_apply<<<grid3(l.g.n[0], l.g.n[1], l.g.n[2], kBlk), kBlk, 0, c->s>>>(l.g, l.beta, dt, x, y);
-}
-
-// coarse right-hand side = mean of the fine residuals of the 2^d children;
-// the coarse iterate starts from zero
-__global__ void k_visc_resid_restrict(GridD gf, GridD gc, const double* __restrict__ beta, double dt,
-                                      const double* __restrict__ xf, const double* __restrict__ bf,
-                                      double* __restrict__ bc, double* __restrict__ xc)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= gc.n[0] || j >= gc.n[1]) return;
-    const long Nf = ncells(gf), Nc = ncells(gc), qc = cid(gc, i, j, k);
-    const int nch = 1 << gf.dim;
-    for (int c = 0; c < gf.dim; ++c) {
-        double s = 0.0;
-        for (int bits = 0; bits < nch; ++bits) {
-            const int fi = 2 * i + (bits & 1), fj = 2 * j + ((bits >> 1) & 1), fk = gf.dim == 3 ? 2 * k + ((bits >> 2) & 1) : 0;
-            const long qf = c * Nf + cid(gf, fi, fj, fk);
-            const double Ax = xf[qf] - dt * visc_div_at<true, false>(gf, beta, xf, c, fi, fj, fk);
-            s += bf[qf] - Ax;
-        }
-        bc[c * Nc + qc] = s / (double)nch;
-        xc[c * Nc + qc] = 0.0;
-    }
-}
-
-void launch_visc_resid_restrict(Ctx* c, const Level& f, const Level& cl, double dt)
-{
-    k_visc_resid_restrict<<<grid3(cl.g.n[0], cl.g.n[1], cl.g.n[2], kBlk), kBlk, 0, c->s>>>(f.g, cl.g, f.beta, dt, f.X(), f.b, cl.b, cl.X());
 }
 
 // dense matrix of the homogeneous operator, column j = A e_j (E holds the
