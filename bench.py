@@ -36,6 +36,8 @@ def parse():
                     help="comma-separated further workloads ('' for none)")
     ap.add_argument("--also-steps", type=int, default=10)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision runs")
+    ap.add_argument("--batch", type=int, default=64, help="cavities of the batched sweep (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     return ap.parse_args()
@@ -79,6 +81,40 @@ def run_gpu(name, steps, warmup, precision=0, timing=True):
     ncell = g.n[0] * g.n[1] * g.n[2]
     ctx.close()
     return dict(T=T, ncell=ncell, steps=steps, warmup=warmup, cycles=[c / steps for c in cycles], kt=kt)
+
+
+def run_batch(steps, warmup, precision=0, count=64, seed=0):
+    """The batched sweep: count 2D cavities with SplitMix64-drawn sizes and
+    parameters, all stepped together (one launch per multigrid kernel)."""
+    import torch
+    from paper_1803_00417_amd import hb, inputs
+    cav = inputs.batch_cavities(count=count, seed=seed)
+    grids = [hb.lid_cavity(2, d["n"]) for d in cav]
+    fluids = [hb.make_fluid(Re=d["Re"], HB=d["HB"], n=d["nidx"], Pa=d["Pa"]) for d in cav]
+    bctx = hb.BatchContext(grids, fluids, hb.make_step_opts(cfl=cav[0]["cfl"], precision=precision))
+    us = [torch.zeros(hb.cell_shape(g, 2), dtype=torch.float64, device="cuda") for g in grids]
+    ps = [torch.zeros(hb.node_shape(g), dtype=torch.float64, device="cuda") for g in grids]
+    for _ in range(warmup):
+        bctx.step(us, ps, report=False)
+    torch.cuda.synchronize()
+    cyc = [0, 0, 0]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        reps = bctx.step(us, ps, report=True)
+        cyc[0] += max(r.mac.cycles for r in reps)
+        cyc[1] += max(r.visc.cycles for r in reps)
+        cyc[2] += max(r.proj.cycles for r in reps)
+        print("[bench] batch%d %s step %d/%d" % (count, "mixed" if precision else "fp64", k + 1, steps),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    bctx.close()
+    cells = sum(d["n"] ** 2 for d in cav)
+    return {"value": cells * steps / T, "unit": "cell-steps/s", "ms_per_step": 1e3 * T / steps, "steps": steps,
+            "warmup": warmup, "cells": cells, "max_cycles_per_step_mac_visc_proj": [x / steps for x in cyc],
+            "desc": "%d 2D lid-driven cavities, N from {64,96,128,192,256}, Bi log-uniform [0.1,100], "
+                    "n uniform [0.3,1.5], Re log-uniform [1,1000], m=1e3 (SplitMix64 seed %d), one batched "
+                    "step" % (count, seed)}
 
 
 def cpu_baseline(name, nsteps):
@@ -174,6 +210,11 @@ def main():
               file=sys.stderr, flush=True)
         r2 = run_gpu(nm, st, wu, precision=prec)
         also["%s_%s" % (nm, "mixed" if prec else "fp64")] = _summary(r2, inputs.WORKLOADS[nm])
+    if a.batch > 0:
+        for prec in ((0, 1) if not a.no_mixed else (0,)):
+            print("[bench] batched sweep of %d cavities (%s)" % (a.batch, "mixed" if prec else "fp64"),
+                  file=sys.stderr, flush=True)
+            also["batch%d_%s" % (a.batch, "mixed" if prec else "fp64")] = run_batch(a.batch_steps, 2, prec, a.batch)
     if also:
         out["also"] = also
     if not a.no_cpu_baseline:

@@ -176,6 +176,21 @@ int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out);
  * dt <= 0 selects the CFL time step.  report nullable. */
 int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report);
 
+/* Batched sweeps: one context holding `count` independent cavities of the
+ * same dimension (each with its own grid, fluid and wall velocities; one
+ * option set).  hb_step_batch advances every cavity by one step, as hb_step
+ * would (u[b], p[b]: cavity b's caller-owned device arrays in the hb_step
+ * layout; dt[b] <= 0 or dt NULL: cavity b's CFL step; reports: NULL or
+ * `count` entries).  The three solves of all cavities run as one batched
+ * multigrid: every launch covers all cavities, and each cavity stops at its
+ * own tolerance.  A cavity's result does not depend on the rest of the batch.
+ * The single-cavity calls above reject a context with count > 1 (HB_ERR_ARG);
+ * hb_step_batch also accepts a single-cavity context.  count: 1 .. 4096. */
+int hb_create_batch(const hb_grid* grids, const hb_fluid* fluids, int count, const hb_step_opts* opts,
+                    void* hip_stream, hb_ctx** out);
+int hb_batch_size(const hb_ctx* ctx);
+int hb_step_batch(hb_ctx* ctx, double* const* u, double* const* p, const double* dt, hb_step_report* reports);
+
 /* Measurement support.  While enabled, every launch of the tensor viscous
  * smoother (one fused red-black sweep of one velocity component on a fine
  * multigrid level) on the context's stream is bracketed by HIP events;

@@ -1,5 +1,7 @@
-// hb_host.hip -- context set-up, multigrid drivers (V-cycle and BiCGStab
-// acceleration), the time step and the C ABI of include/hb.h.
+// hb_host.hip -- context set-up, batched multigrid drivers (V-cycle and
+// BiCGStab acceleration, FP64 or mixed precision), the time step and the C
+// ABI of include/hb.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -7,6 +9,9 @@
 #include <string>
 
 #include "hb_internal.h"
+
+// the opaque handle of the C ABI is the context itself
+struct hb_ctx : public hb::Ctx {};
 
 namespace hb {
 
@@ -49,12 +54,14 @@ static GridD make_gridd(const hb_grid& g)
     return d;
 }
 
-static long unknowns(const GridD& g, int op)
+static GridD absent_grid()
 {
-    if (op == HB_OP_VISC) return ncells(g) * g.dim;
-    if (op == HB_OP_MAC) return ncells(g);
-    return nnodes(g);
+    GridD d;
+    memset(&d, 0, sizeof(d));
+    return d;
 }
+
+static long comp_count(const GridD& g, int op) { return op == HB_OP_NODAL ? nnodes(g) : ncells(g); }
 
 static long nface_total(const GridD& g)
 {
@@ -69,32 +76,25 @@ static hipError_t dalloc(T** p, long n)
     return hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1));
 }
 
+template <typename T>
+static hipError_t upload(T* dst, const std::vector<T>& src)
+{
+    return hipMemcpy(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
 // ---------------------------------------------------------------------------
 // hierarchy
 // ---------------------------------------------------------------------------
 
-static int build_mg(Ctx* c, MG& m, int op)
+// grids of the levels of one cavity: coarsen by 2 while every extent is even
+// and its half is at least 2
+static std::vector<GridD> level_grids(const GridD& g0)
 {
-    m.op = op;
-    GridD cur = c->g;
-    int l = 0;
+    std::vector<GridD> out;
+    GridD cur = g0;
     for (;;) {
-        if (l >= kMaxLev) return fail(c, HB_ERR_ARG, "too many multigrid levels");
-        Level& L = m.L[l];
-        L.g = cur;
-        L.nu = unknowns(cur, op);
-        HB_TRY(dalloc(&L.xb[0], L.nu));
-        HB_TRY(dalloc(&L.xb[1], L.nu));
-        if (l > 0) HB_TRY(dalloc(&L.b, L.nu));
-        HB_TRY(dalloc(&L.r, L.nu));
-        if (op == HB_OP_VISC) HB_TRY(dalloc(&L.beta, nface_total(cur)));
-        HB_TRY(dalloc(&L.fx[0], L.nu));
-        HB_TRY(dalloc(&L.fx[1], L.nu));
-        HB_TRY(dalloc(&L.fb, L.nu));
-        if (op == HB_OP_NODAL) HB_TRY(dalloc(&L.fr, L.nu));
-        if (op == HB_OP_VISC && l > 0) HB_TRY(dalloc(&L.fbeta, nface_total(cur)));
-        ++l;
-        bool can = true;
+        out.push_back(cur);
+        bool can = (int)out.size() < kMaxLev;
         for (int a = 0; a < cur.dim; ++a)
             if ((cur.n[a] & 1) || cur.n[a] / 2 < 2) can = false;
         if (!can) break;
@@ -104,17 +104,106 @@ static int build_mg(Ctx* c, MG& m, int op)
         memset(nx.wall_u, 0, sizeof(nx.wall_u));
         cur = nx;
     }
-    m.nlev = l;
-    m.ncoarse = (int)m.L[l - 1].nu;
-    HB_TRY(dalloc(&m.A, (long)m.ncoarse * m.ncoarse));
-    HB_TRY(dalloc(&m.Ainv, (long)m.ncoarse * m.ncoarse));
-    HB_TRY(dalloc(&m.piv, m.ncoarse));
+    return out;
+}
+
+static int build_mg(Ctx* c, MG& m, int op)
+{
+    m.op = op;
+    m.ncomp = op == HB_OP_VISC ? c->dim : 1;
+    const int nb = c->nb;
+    std::vector<std::vector<GridD>> lg(nb);
+    m.nlev = 0;
+    m.nlevc.resize(nb);
+    for (int b = 0; b < nb; ++b) {
+        lg[b] = level_grids(c->cv[b].g);
+        m.nlevc[b] = (int)lg[b].size();
+        m.nlev = std::max(m.nlev, m.nlevc[b]);
+    }
+    for (int l = 0; l < m.nlev; ++l) {
+        Level& L = m.L[l];
+        L.hg.assign(nb, absent_grid());
+        L.ho.assign(nb, 0);
+        L.hof.assign(nb, 0);
+        L.hou.assign(nb, 0);
+        L.hnu.assign(nb, 0);
+        std::vector<GridD> gsm(nb, absent_grid());
+        L.gmax = absent_grid();
+        L.gmax.dim = c->dim;
+        L.gmax.n[0] = L.gmax.n[1] = L.gmax.n[2] = 1;
+        long oc = 0, of = 0;
+        for (int b = 0; b < nb; ++b) {
+            L.ho[b] = oc;
+            L.hof[b] = of;
+            L.hou[b] = m.ncomp * oc;
+            if (l >= m.nlevc[b]) continue;
+            const GridD& g = lg[b][l];
+            L.hg[b] = g;
+            if (l < m.nlevc[b] - 1) {
+                gsm[b] = g;
+                L.any_sm = true;
+            } else {
+                L.any_cs = true;
+            }
+            for (int a = 0; a < 3; ++a) L.gmax.n[a] = std::max(L.gmax.n[a], g.n[a]);
+            const long cnt = comp_count(g, op);
+            L.hnu[b] = m.ncomp * cnt;
+            oc += cnt;
+            if (op == HB_OP_VISC) of += nface_total(g);
+        }
+        L.nu = m.ncomp * oc;
+        HB_TRY(dalloc(&L.xb[0], L.nu));
+        HB_TRY(dalloc(&L.xb[1], L.nu));
+        if (l > 0) HB_TRY(dalloc(&L.b, L.nu));
+        HB_TRY(dalloc(&L.r, L.nu));
+        if (op == HB_OP_VISC) HB_TRY(dalloc(&L.beta, of));
+        HB_TRY(dalloc(&L.fx[0], L.nu));
+        HB_TRY(dalloc(&L.fx[1], L.nu));
+        HB_TRY(dalloc(&L.fb, L.nu));
+        if (op == HB_OP_NODAL) HB_TRY(dalloc(&L.fr, L.nu));
+        if (op == HB_OP_VISC && l > 0) HB_TRY(dalloc(&L.fbeta, of));
+        HB_TRY(dalloc(&L.gall, nb));
+        HB_TRY(dalloc(&L.gsm, nb));
+        HB_TRY(dalloc(&L.o, nb));
+        HB_TRY(dalloc(&L.of, nb));
+        HB_TRY(dalloc(&L.ou, nb));
+        HB_TRY(dalloc(&L.nuc, nb));
+        HB_TRY(upload(L.gall, L.hg));
+        HB_TRY(upload(L.gsm, gsm));
+        HB_TRY(upload(L.o, L.ho));
+        HB_TRY(upload(L.of, L.hof));
+        HB_TRY(upload(L.ou, L.hou));
+        HB_TRY(upload(L.nuc, L.hnu));
+    }
+    // coarsest systems
+    m.hcs.resize(nb);
+    long aoff = 0, poff = 0;
+    m.ncmax = 0;
+    for (int b = 0; b < nb; ++b) {
+        CoarseD& d = m.hcs[b];
+        d.lev = m.nlevc[b] - 1;
+        d.N = (int)m.L[d.lev].hnu[b];
+        d.aoff = aoff;
+        d.poff = poff;
+        d.xoff = m.L[d.lev].hou[b];
+        aoff += (long)d.N * d.N;
+        poff += d.N;
+        m.ncmax = std::max(m.ncmax, d.N);
+    }
+    HB_TRY(dalloc(&m.cs, nb));
+    HB_TRY(upload(m.cs, m.hcs));
+    HB_TRY(dalloc(&m.A, aoff));
+    HB_TRY(dalloc(&m.Ainv, aoff));
+    HB_TRY(dalloc(&m.piv, poff));
     HB_TRY(dalloc(&m.lvl0_b, m.L[0].nu));
     m.L[0].b = m.lvl0_b;
     if (op == HB_OP_VISC) {
-        HB_TRY(dalloc(&m.etae, ncells(c->g)));
-        HB_TRY(dalloc(&m.etae32, ncells(c->g)));
+        HB_TRY(dalloc(&m.etae, m.L[0].nu / m.ncomp));
+        HB_TRY(dalloc(&m.etae32, m.L[0].nu / m.ncomp));
     }
+    m.seg0.off = m.L[0].ou;
+    m.seg0.n = m.L[0].nuc;
+    m.seg0.act = nullptr;
     return HB_OK;
 }
 
@@ -132,7 +221,14 @@ static void free_mg(MG& m)
         (void)hipFree(L.fb);
         (void)hipFree(L.fr);
         (void)hipFree(L.fbeta);
+        (void)hipFree(L.gall);
+        (void)hipFree(L.gsm);
+        (void)hipFree(L.o);
+        (void)hipFree(L.of);
+        (void)hipFree(L.ou);
+        (void)hipFree(L.nuc);
     }
+    (void)hipFree(m.cs);
     (void)hipFree(m.A);
     (void)hipFree(m.Ainv);
     (void)hipFree(m.piv);
@@ -143,53 +239,63 @@ static void free_mg(MG& m)
         if (m.gexec[p]) (void)hipGraphExecDestroy(m.gexec[p]);
 }
 
-__global__ void k_identity(int N, double* E)
+// dense coarsest matrix of cavity b from its current coefficients, LU and
+// inverse
+static void factor_coarsest(Ctx* c, MG& m, int b)
 {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)N * N) return;
-    E[t] = (t / N == t % N) ? 1.0 : 0.0;
+    const CoarseD& d = m.hcs[b];
+    const int N = d.N;
+    const Level& C = m.L[d.lev];
+    const GridD& g = C.hg[b];
+    double* A = m.A + d.aoff;
+    launch_identity(c, N, c->cv[b].dense_E);
+    if (m.op == HB_OP_VISC) {
+        const double dt = c->cv[b].hsc[S_DT];
+        launch_visc_dense(c, g, C.beta + C.hof[b], dt, N, c->cv[b].dense_E, A);
+    } else if (m.op == HB_OP_MAC) {
+        launch_mac_dense(c, g, N, c->cv[b].dense_E, A);
+    } else {
+        launch_nodal_dense(c, g, N, c->cv[b].dense_E, A);
+    }
+    if (m.op != HB_OP_VISC) launch_add_ones(c, N, A);
+    launch_lu_factor(c, N, A, m.piv + d.poff);
+    launch_lu_inverse(c, N, A, m.piv + d.poff, m.Ainv + d.aoff);
 }
 
-// dense coarsest matrix of the current coefficients, then LU
-static void factor_coarsest(Ctx* c, MG& m)
-{
-    const int N = m.ncoarse;
-    const Level& C = m.L[m.nlev - 1];
-    const long nn = (long)N * N;
-    k_identity<<<(unsigned)((nn + 255) / 256), 256, 0, c->s>>>(N, c->dense_E);
-    if (m.op == HB_OP_VISC) launch_visc_dense(c, C, m.dt, N, c->dense_E, m.A);
-    else if (m.op == HB_OP_MAC) launch_mac_dense(c, C, N, c->dense_E, m.A);
-    else launch_nodal_dense(c, C, N, c->dense_E, m.A);
-    if (m.op != HB_OP_VISC) launch_add_ones(c, N, m.A);
-    launch_lu_factor(c, N, m.A, m.piv);
-    launch_lu_inverse(c, N, m.A, m.piv, m.Ainv);
-}
-
-// face viscosities of every level from the cell viscosity eta (not /Re)
-static void visc_setup(Ctx* c, const double* eta, double dt)
+// face viscosities of every level of cavity b from its cell viscosity eta
+// (not /Re), its dt into the device slot, and its coarsest factorisation
+static void visc_setup(Ctx* c, int b, const double* eta, double dt)
 {
     MG& m = c->visc;
-    set_slot(c, S_DT, dt);
-    launch_eta_over_re(c, m.L[0].g, eta, m.etae);
-    launch_eta_faces(c, m.L[0].g, eta, m.L[0].beta);
-    for (int l = 1; l < m.nlev; ++l) launch_restrict_faces(c, m.L[l - 1].g, m.L[l].g, m.L[l - 1].beta, m.L[l].beta);
-    m.dt = dt;
+    Cav& v = c->cv[b];
+    v.hsc[S_DT] = dt;   // host copy, used for the dense assembly
+    set_slot(c, b, S_DT, dt);
+    launch_eta_over_re(c, v, eta, m.etae + m.L[0].ho[b]);
+    launch_eta_faces(c, v, v.g, eta, m.L[0].beta + m.L[0].hof[b]);
+    for (int l = 1; l < m.nlevc[b]; ++l)
+        launch_restrict_faces(c, m.L[l - 1].hg[b], m.L[l].hg[b], m.L[l - 1].beta + m.L[l - 1].hof[b],
+                              m.L[l].beta + m.L[l].hof[b]);
     m.f32_ready = false;
-    factor_coarsest(c, m);
+    factor_coarsest(c, m, b);
 }
 
 // FP32 copies of the tensor coefficients for mixed-precision cycles (the
-// coarsest matrix stays the FP64 one)
+// coarsest matrices stay the FP64 ones)
 static void ensure_f32(Ctx* c, MG& m)
 {
     if (m.op != HB_OP_VISC || m.f32_ready) return;
-    to_f32(c, m.etae, m.etae32, nullptr, ncells(m.L[0].g));
-    for (int l = 1; l < m.nlev; ++l) to_f32(c, m.L[l].beta, m.L[l].fbeta, nullptr, nface_total(m.L[l].g));
+    flat_to_f32(c, m.etae, m.etae32, m.L[0].nu / m.ncomp);
+    for (int l = 1; l < m.nlev; ++l) {
+        long nf = 0;
+        for (const GridD& g : m.L[l].hg)
+            if (g.dim) nf += nface_total(g);
+        flat_to_f32(c, m.L[l].beta, m.L[l].fbeta, nf);
+    }
     m.f32_ready = true;
 }
 
 // ---------------------------------------------------------------------------
-// V-cycle
+// V-cycle over the batch (cavities masked by c->act)
 // ---------------------------------------------------------------------------
 
 // tensor coefficients of level l for the tiled kernels: eta/Re cells on the
@@ -200,28 +306,32 @@ template <> const float* tcoef<float>(const MG& m, int l) { return l == 0 ? m.et
 
 template <typename R> constexpr int prec_index() { return sizeof(R) == sizeof(double) ? 0 : 1; }
 
+static BV smooth_view(const Ctx* c, const Level& L) { return BV{L.gsm, L.o, L.of, c->act, 1}; }
+static BV all_view(const Level& L, const int* act) { return BV{L.gall, L.o, L.of, act, 1}; }
+
 template <typename R>
 static void smooth(Ctx* c, MG& m, int l, int sweeps)
 {
     using B = LB<R>;
     Level& L = m.L[l];
+    const BV v = smooth_view(c, L);
     for (int s = 0; s < sweeps; ++s) {
-        if (m.op == HB_OP_VISC && (L.g.dim == 2 || l > 0)) {
+        if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0)) {
             // fused red-black sweep per component into the other buffer (2D,
             // and the small 3D levels, where it halves the launches)
-            for (int q = 0; q < L.g.dim; ++q)
-                launch_tsmooth<R>(c, L.g, tcoef<R>(m, l), l == 0, c->sc + S_DT, q, B::x(L), B::xo(L), B::b(L));
+            for (int q = 0; q < c->dim; ++q)
+                launch_tsmooth<R>(c, L, v, tcoef<R>(m, l), l == 0, q, B::x(L), B::xo(L), B::b(L));
             L.cur ^= 1;
         } else if (m.op == HB_OP_VISC) {
             // finest 3D level: one colour of one component per launch, in
             // place (a 2-cell halo is costly on a 3D tile)
-            for (int q = 0; q < L.g.dim; ++q)
+            for (int q = 0; q < c->dim; ++q)
                 for (int colour = 0; colour < 2; ++colour)
-                    launch_trb3<R>(c, L.g, tcoef<R>(m, l), l == 0, c->sc + S_DT, q, colour, B::x(L), B::b(L));
+                    launch_trb3<R>(c, L, v, tcoef<R>(m, l), l == 0, q, colour, B::x(L), B::b(L));
         } else if (m.op == HB_OP_MAC) {
-            for (int colour = 0; colour < 2; ++colour) launch_mac_rb<R>(c, L.g, colour, B::x(L), B::b(L));
+            for (int colour = 0; colour < 2; ++colour) launch_mac_rb<R>(c, L, v, colour, B::x(L), B::b(L));
         } else {
-            for (int colour = 0; colour < (1 << L.g.dim); ++colour) launch_nodal_gs<R>(c, L.g, colour, B::x(L), B::b(L));
+            for (int colour = 0; colour < (1 << c->dim); ++colour) launch_nodal_gs<R>(c, L, v, colour, B::x(L), B::b(L));
         }
     }
 }
@@ -230,9 +340,10 @@ template <typename R> static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
 
 // Levels 1.. of the V-cycle as one HIP graph per precision: the coarse
 // levels are many short launches, so replaying a captured graph removes most
-// of their host launch cost.  All their kernel arguments are fixed (buffers,
-// and dt read from device memory); with an even number of sweeps per cycle
-// every double-buffered level ends the cycle in the buffer it started in.
+// of their host launch cost.  All their kernel arguments are fixed (arenas,
+// tables, and the active flags and dt read from device memory); with an even
+// number of sweeps per cycle every double-buffered level ends the cycle in
+// the buffer it started in.
 template <typename R>
 static void coarse_graph(Ctx* c, MG& m, int nu1, int nu2)
 {
@@ -266,215 +377,314 @@ static void coarse_graph(Ctx* c, MG& m, int nu1, int nu2)
     (void)hipGraphLaunch(m.gexec[pi], c->s);
 }
 
-// one V-cycle from level l in precision R; the coarsest level is solved with
-// the FP64 inverse of its dense matrix
+// One V-cycle from level l in precision R for the active cavities.  A
+// cavity whose coarsest level is l is solved there with the FP64 inverse of
+// its dense matrix, after the level's smoothing for the other cavities (so
+// its result sits in the buffer that is current when the level returns).
 template <typename R>
 static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
 {
     using B = LB<R>;
     Level& L = m.L[l];
-    if (l == m.nlev - 1) {
-        launch_coarse_solve<R>(c, m.ncoarse, m.Ainv, B::b(L), B::x(L));
-        return;
-    }
     if (l == 1 && !m.capturing && !m.gfail[prec_index<R>()] && m.nlev > 2 && (nu1 + nu2) % 2 == 0) {
         coarse_graph<R>(c, m, nu1, nu2);
         return;
     }
-    Level& C = m.L[l + 1];
-    smooth<R>(c, m, l, nu1);
-    if (m.op == HB_OP_VISC) {
-        launch_tresid_restr<R>(c, L.g, C.g, tcoef<R>(m, l), l == 0, c->sc + S_DT, B::x(L), B::b(L), B::b(C), B::x(C));
-    } else if (m.op == HB_OP_MAC) {
-        launch_mac_resid_restrict<R>(c, L.g, C.g, B::x(L), B::b(L), B::b(C), B::x(C));
-    } else {
-        launch_nodal_resid<R>(c, L.g, B::x(L), B::b(L), B::r(L), -1);
-        launch_nodal_restrict<R>(c, L.g, C.g, B::r(L), B::b(C), B::x(C));
+    if (L.any_sm) {
+        Level& C = m.L[l + 1];
+        const BV v = smooth_view(c, L);
+        const BV vc = all_view(C, c->act);
+        smooth<R>(c, m, l, nu1);
+        if (m.op == HB_OP_VISC) {
+            launch_tresid_restr<R>(c, L, v, C.gall, C.o, tcoef<R>(m, l), l == 0, B::x(L), B::b(L), B::b(C), B::x(C));
+        } else if (m.op == HB_OP_MAC) {
+            launch_mac_resid_restrict<R>(c, C, vc, L.gall, L.o, B::x(L), B::b(L), B::b(C), B::x(C));
+        } else {
+            launch_nodal_resid<R>(c, L, v, B::x(L), B::b(L), B::r(L), -1);
+            launch_nodal_restrict<R>(c, C, vc, L.gall, L.o, B::r(L), B::b(C), B::x(C));
+        }
+        vcycle<R>(c, m, l + 1, nu1, nu2);
+        if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L, v, C.gall, C.o, B::x(C), B::x(L));
+        else launch_prolong_cells<R>(c, L, v, C.gall, C.o, m.ncomp, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
+        smooth<R>(c, m, l, nu2);
     }
-    vcycle<R>(c, m, l + 1, nu1, nu2);
-    if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L.g, C.g, B::x(C), B::x(L));
-    else launch_prolong_cells<R>(c, L.g, C.g, m.op == HB_OP_VISC ? L.g.dim : 1, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
-    smooth<R>(c, m, l, nu2);
+    if (L.any_cs) launch_coarse_solve<R>(c, m, l, c->act, B::b(L), B::x(L));
 }
 
-// r = b - A x on level 0 (FP64) and its max-norm into slot S_MAX
-static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r)
+// r = b - A x on level 0 (FP64) and its max-norm into each cavity's S_MAX
+static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r, const int* act)
 {
-    set_slot_zero(c, S_MAX);
+    seg_set_zero(c, S_MAX);
     const Level& L = m.L[0];
-    if (m.op == HB_OP_VISC) launch_tresid(c, L.g, m.etae, true, c->sc + S_DT, x, b, r, S_MAX);
-    else if (m.op == HB_OP_MAC) launch_mac_resid(c, L.g, x, b, r, S_MAX);
-    else launch_nodal_resid<double>(c, L.g, x, b, r, S_MAX);
+    const BV v = all_view(L, act);
+    if (m.op == HB_OP_VISC) launch_tresid(c, L, v, m.etae, x, b, r, S_MAX);
+    else if (m.op == HB_OP_MAC) launch_mac_resid(c, L, v, x, b, r, S_MAX);
+    else launch_nodal_resid<double>(c, L, v, x, b, r, S_MAX);
 }
 
 static void apply0(Ctx* c, MG& m, const double* x, double* y)
 {
     const Level& L = m.L[0];
-    if (m.op == HB_OP_VISC) launch_tresid(c, L.g, m.etae, true, c->sc + S_DT, x, nullptr, y, -1);
-    else if (m.op == HB_OP_MAC) launch_mac_apply(c, L.g, x, y);
-    else launch_nodal_resid<double>(c, L.g, x, nullptr, y, -1);
+    const BV v = all_view(L, c->act);
+    if (m.op == HB_OP_VISC) launch_tresid(c, L, v, m.etae, x, nullptr, y, -1);
+    else if (m.op == HB_OP_MAC) launch_mac_resid(c, L, v, x, nullptr, y, -1);
+    else launch_nodal_resid<double>(c, L, v, x, nullptr, y, -1);
 }
+
+static SegV seg_of(const MG& m, const int* act) { return SegV{m.seg0.off, m.seg0.n, act}; }
 
 // z = M^{-1} r: one V-cycle from zero on level 0, in FP64 or (lo) in FP32
 static void precond(Ctx* c, MG& m, const double* r, double* z, int nu1, int nu2, bool lo)
 {
     Level& L = m.L[0];
+    const SegV sv = seg_of(m, c->act);
     L.cur = 0;
     if (lo) {
-        to_f32(c, r, L.fb, L.fx[0], L.nu);
+        seg_to_f32(c, sv, r, L.fb, L.fx[0]);
         vcycle<float>(c, m, 0, nu1, nu2);
-        from_f32(c, LB<float>::x(L), z, L.nu);
+        seg_from_f32(c, sv, LB<float>::x(L), z);
         return;
     }
     double* sb = L.b;
     L.b = const_cast<double*>(r);
-    fill(c, L.X(), 0.0, L.nu);
+    seg_fill(c, sv, L.X(), 0.0);
     vcycle<double>(c, m, 0, nu1, nu2);
-    copy(c, z, L.X(), L.nu);
+    seg_copy(c, sv, z, L.X());
     L.b = sb;
 }
 
-static double fetch_max(Ctx* c)
+// ---- per-cavity bookkeeping of a batched solve ---------------------------
+
+struct SolveOut {
+    int cycles = 0;
+    double rel = 0.0, bn = 0.0;
+    int rc = HB_OK;
+};
+
+static void upload_flags(Ctx* c, int* dev, const int* host)
 {
-    fetch_slots(c);
-    return c->hsc[S_MAX];
+    (void)hipMemcpyAsync(dev, host, sizeof(int) * c->nb, hipMemcpyHostToDevice, c->s);
 }
 
-// Multigrid (optionally BiCGStab-accelerated) solve of A x = b on the
-// prepared level-0 system; x in/out.  bn = |b|_inf.  With mixed precision
-// every V-cycle runs in FP32 on the FP64 residual (defect correction, or the
-// BiCGStab preconditioner); residuals, norms and the iterate stay FP64.
-static int solve_core(Ctx* c, MG& m, double* x, double* b, double bn, const hb_mg_opts& o, hb_mg_report* rep)
+static double slot(const Ctx* c, int b, int s) { return c->hsc[(long)b * S_NSLOT + s]; }
+
+// the convergence test before a cycle: true when the cavity stops here
+static bool stops(SolveOut& so, const hb_mg_opts& o)
+{
+    if (o.fixed_cycles) return so.cycles >= o.max_cycles;
+    if (so.rel <= o.tol_rel) return true;
+    if (so.cycles >= o.max_cycles) {
+        so.rc = HB_ERR_NOCONV;
+        return true;
+    }
+    return false;
+}
+
+static int any_set(const Ctx* c, const int* f)
+{
+    int n = 0;
+    for (int b = 0; b < c->nb; ++b) n += f[b] != 0;
+    return n;
+}
+
+// Multigrid (optionally BiCGStab-accelerated) solves A x = b of every cavity
+// on the prepared level-0 systems; x, b are level-0 arenas.  Cavities stop
+// independently.  With mixed precision every V-cycle runs in FP32 on the
+// FP64 residual (defect correction, or the BiCGStab preconditioner);
+// residuals, norms and the iterate stay FP64.  The pinned host flag arrays
+// are written only after a synchronisation, so no upload still in flight
+// reads them.
+static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o, std::vector<SolveOut>& so)
 {
     Level& L = m.L[0];
-    const long n = L.nu;
-    L.b = b;
-    int cycles = 0, rc = HB_OK;
-    double rel = 0.0;
+    const int nb = c->nb;
     const bool lo = o.precision == HB_PREC_MIXED;
-    if (bn == 0.0) {
-        fill(c, x, 0.0, n);
-    } else if (!o.krylov && !lo) {
-        // the cycles work on the level's double buffer, seeded with x
+    int* act = c->hact;
+    int* act2 = c->hact2;
+    // cavities with b = 0 have x = 0; the others start active
+    for (int i = 0; i < nb; ++i) {
+        act[i] = so[i].rc == HB_OK && so[i].bn != 0.0;
+        act2[i] = so[i].rc == HB_OK && so[i].bn == 0.0;
+    }
+    upload_flags(c, c->act2, act2);
+    seg_fill(c, seg_of(m, c->act2), x, 0.0);
+    upload_flags(c, c->act, act);
+    const SegV sv = seg_of(m, c->act);
+    auto take_rel = [&](int i) {
+        so[i].rel = slot(c, i, S_MAX) / so[i].bn;
+        if (!std::isfinite(so[i].rel)) {
+            so[i].rc = HB_ERR_NONFINITE;
+            return false;
+        }
+        return true;
+    };
+
+    if (!o.krylov) {
+        // Plain V-cycles.  FP64: on the level's double buffer seeded with x.
+        // Mixed: x in the first FP64 buffer; each cycle corrects it by one
+        // FP32 V-cycle on A e = r.
         L.cur = 0;
-        copy(c, L.X(), x, n);
-        resid0(c, m, L.X(), b, L.r);
-        rel = fetch_max(c) / bn;
-        for (;;) {
-            if (o.fixed_cycles) {
-                if (cycles >= o.max_cycles) break;
-            } else {
-                if (rel <= o.tol_rel) break;
-                if (cycles >= o.max_cycles) { rc = HB_ERR_NOCONV; break; }
-            }
-            vcycle<double>(c, m, 0, o.nu1, o.nu2);
-            ++cycles;
-            resid0(c, m, L.X(), b, L.r);
-            rel = fetch_max(c) / bn;
-            if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
-        }
-        copy(c, x, L.X(), n);
-    } else if (!o.krylov) {
-        // defect correction: FP64 residual r = b - A x, one FP32 V-cycle
-        // from zero on A e = r, x += e
         double* xw = L.xb[0];
-        copy(c, xw, x, n);
-        resid0(c, m, xw, b, L.r);
-        rel = fetch_max(c) / bn;
-        for (;;) {
-            if (o.fixed_cycles) {
-                if (cycles >= o.max_cycles) break;
-            } else {
-                if (rel <= o.tol_rel) break;
-                if (cycles >= o.max_cycles) { rc = HB_ERR_NOCONV; break; }
-            }
-            L.cur = 0;
-            to_f32(c, L.r, L.fb, L.fx[0], n);
-            vcycle<float>(c, m, 0, o.nu1, o.nu2);
-            ++cycles;
-            add_f32(c, xw, LB<float>::x(L), n);
-            resid0(c, m, xw, b, L.r);
-            rel = fetch_max(c) / bn;
-            if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
+        seg_copy(c, sv, xw, x);
+        resid0(c, m, xw, b, L.r, c->act);
+        fetch_slots(c);
+        for (int i = 0; i < nb; ++i) {
+            c->hsel[i] = 0;
+            if (act[i] && !take_rel(i)) act[i] = 0;
         }
-        copy(c, x, xw, n);
-    } else {
-        // BiCGStab with its scalars kept on the device: two host reads per
-        // iteration (the residual norms that decide convergence)
-        double *r = c->kr, *rh = c->krh, *p = c->kp, *v = c->kv, *ph = c->kph, *s = c->ks, *sh = c->ksh, *t = c->kt;
-        resid0(c, m, x, b, r);
-        copy(c, rh, r, n);
-        fill(c, p, 0.0, n);
-        fill(c, v, 0.0, n);
-        bicg_init_scalars(c);
-        rel = fetch_max(c) / bn;
         for (;;) {
-            if (o.fixed_cycles) {
-                if (cycles >= o.max_cycles) break;
+            for (int i = 0; i < nb; ++i)
+                if (act[i] && stops(so[i], o)) {
+                    act[i] = 0;
+                    c->hsel[i] = lo ? 0 : L.cur;
+                }
+            if (!any_set(c, act)) break;
+            upload_flags(c, c->act, act);
+            if (lo) {
+                L.cur = 0;
+                seg_to_f32(c, sv, L.r, L.fb, L.fx[0]);
+                vcycle<float>(c, m, 0, o.nu1, o.nu2);
+                seg_add_f32(c, sv, xw, LB<float>::x(L));
+                resid0(c, m, xw, b, L.r, c->act);
             } else {
-                if (rel <= o.tol_rel) break;
-                if (cycles >= o.max_cycles) { rc = HB_ERR_NOCONV; break; }
+                vcycle<double>(c, m, 0, o.nu1, o.nu2);
+                resid0(c, m, L.X(), b, L.r, c->act);
             }
-            red_dot(c, rh, r, n, S_DOT0);
-            bicg_beta(c);
-            bicg_p_dev(c, p, r, v, n);
-            precond(c, m, p, ph, o.nu1, o.nu2, lo);
-            ++cycles;
-            apply0(c, m, ph, v);
-            red_dot(c, rh, v, n, S_DOT1);
-            bicg_alpha(c);
-            sub_scaled_max_dev(c, s, r, S_ALPHA, v, n, S_MAX);
             fetch_slots(c);
-            if (c->hsc[S_RHO] == 0.0) { rc = HB_ERR_NOCONV; break; }
-            const double srel = c->hsc[S_MAX] / bn;
-            if ((!o.fixed_cycles && srel <= o.tol_rel) || (o.fixed_cycles && cycles >= o.max_cycles)) {
-                bicg_x_dev(c, x, ph, nullptr, false, n);
-                copy(c, r, s, n);
-                rel = srel;
-                break;
+            for (int i = 0; i < nb; ++i) {
+                if (!act[i]) continue;
+                ++so[i].cycles;
+                if (!take_rel(i)) {
+                    act[i] = 0;
+                    c->hsel[i] = lo ? 0 : L.cur;
+                }
             }
-            precond(c, m, s, sh, o.nu1, o.nu2, lo);
-            ++cycles;
-            apply0(c, m, sh, t);
-            red_dot(c, t, t, n, S_DOT0);
-            red_dot(c, t, s, n, S_DOT1);
-            bicg_omega(c);
-            bicg_x_dev(c, x, ph, sh, true, n);
-            sub_scaled_max_dev(c, r, s, S_OMEGA, t, n, S_MAX);
-            fetch_slots(c);
-            rel = c->hsc[S_MAX] / bn;
-            if (!std::isfinite(rel)) { rc = HB_ERR_NONFINITE; break; }
-            if (c->hsc[S_OMEGA] == 0.0) { rc = HB_ERR_NOCONV; break; }
         }
-        resid0(c, m, x, b, L.r);
-        rel = fetch_max(c) / bn;
-        if (!std::isfinite(rel)) rc = HB_ERR_NONFINITE;
+        // copy out each cavity's iterate from the buffer it ended in
+        for (int i = 0; i < nb; ++i) act2[i] = so[i].bn != 0.0 && so[i].rc != HB_ERR_NONFINITE ? 1 : 0;
+        upload_flags(c, c->act2, act2);
+        upload_flags(c, c->sel, c->hsel);
+        seg_copy_sel(c, seg_of(m, c->act2), x, L.xb[0], L.xb[1], c->sel);
+        fetch_slots(c);   // the flag uploads above have completed
+        return;
     }
-    if (rep) {
-        rep->cycles = cycles;
-        rep->rel_resid = rel;
-        rep->bnorm = bn;
+
+    // BiCGStab with its scalars kept on the device, per cavity: two host
+    // reads per iteration (the residual norms that decide convergence)
+    double *r = c->kr, *rh = c->krh, *p = c->kp, *v = c->kv, *ph = c->kph, *s = c->ks, *sh = c->ksh, *t = c->kt;
+    resid0(c, m, x, b, r, c->act);
+    seg_copy(c, sv, rh, r);
+    seg_fill(c, sv, p, 0.0);
+    seg_fill(c, sv, v, 0.0);
+    bicg_init_scalars(c, c->act);
+    fetch_slots(c);
+    for (int i = 0; i < nb; ++i)
+        if (act[i] && !take_rel(i)) act[i] = 0;
+    for (;;) {
+        for (int i = 0; i < nb; ++i)
+            if (act[i] && stops(so[i], o)) act[i] = 0;
+        if (!any_set(c, act)) break;
+        upload_flags(c, c->act, act);
+        seg_dot(c, sv, rh, r, S_DOT0);
+        bicg_beta(c, c->act);
+        bicg_p_dev(c, sv, p, r, v);
+        precond(c, m, p, ph, o.nu1, o.nu2, lo);
+        apply0(c, m, ph, v);
+        seg_dot(c, sv, rh, v, S_DOT1);
+        bicg_alpha(c, c->act);
+        sub_scaled_max_dev(c, sv, s, r, S_ALPHA, v, S_MAX);
+        fetch_slots(c);
+        // cavities that finish at the half step: x += alpha ph, r = s
+        for (int i = 0; i < nb; ++i) {
+            act2[i] = 0;
+            if (!act[i]) continue;
+            ++so[i].cycles;
+            if (slot(c, i, S_RHO) == 0.0) {
+                so[i].rc = HB_ERR_NOCONV;
+                act[i] = 0;
+                continue;
+            }
+            const double srel = slot(c, i, S_MAX) / so[i].bn;
+            if ((!o.fixed_cycles && srel <= o.tol_rel) || (o.fixed_cycles && so[i].cycles >= o.max_cycles)) {
+                act2[i] = 1;
+                act[i] = 0;
+                so[i].rel = srel;
+            }
+        }
+        if (any_set(c, act2)) {
+            upload_flags(c, c->act2, act2);
+            const SegV sv2 = seg_of(m, c->act2);
+            bicg_x_dev(c, sv2, x, ph, nullptr, false);
+            seg_copy(c, sv2, r, s);
+        }
+        upload_flags(c, c->act, act);
+        if (!any_set(c, act)) {
+            fetch_slots(c);
+            break;
+        }
+        precond(c, m, s, sh, o.nu1, o.nu2, lo);
+        apply0(c, m, sh, t);
+        seg_dot(c, sv, t, t, S_DOT0);
+        seg_dot(c, sv, t, s, S_DOT1);
+        bicg_omega(c, c->act);
+        bicg_x_dev(c, sv, x, ph, sh, true);
+        sub_scaled_max_dev(c, sv, r, s, S_OMEGA, t, S_MAX);
+        fetch_slots(c);
+        for (int i = 0; i < nb; ++i) {
+            if (!act[i]) continue;
+            ++so[i].cycles;
+            if (!take_rel(i)) {
+                act[i] = 0;
+                continue;
+            }
+            if (slot(c, i, S_OMEGA) == 0.0) {
+                so[i].rc = HB_ERR_NOCONV;
+                act[i] = 0;
+            }
+        }
     }
+    // the true residual of every solved cavity
+    for (int i = 0; i < nb; ++i) act[i] = so[i].bn != 0.0 && so[i].rc != HB_ERR_NONFINITE ? 1 : 0;
+    upload_flags(c, c->act, act);
+    resid0(c, m, x, b, L.r, c->act);
+    fetch_slots(c);
+    for (int i = 0; i < nb; ++i)
+        if (act[i]) take_rel(i);
+}
+
+// Solve with the right-hand sides already in m.lvl0_b (VISC: wall part
+// added; NODAL/MAC: mean removed by this function).  x: level-0 arena.
+static int solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o, std::vector<SolveOut>& so)
+{
+    const int nb = c->nb;
+    so.assign(nb, SolveOut());
+    const SegV all = seg_of(m, nullptr);
+    if (m.op != HB_OP_VISC) seg_sub_mean(c, all, m.lvl0_b);
+    seg_maxabs(c, all, m.lvl0_b, S_MAX);
+    seg_maxabs(c, all, x, S_MAX2);
+    fetch_slots(c);
+    int rc = HB_OK;
+    for (int i = 0; i < nb; ++i) {
+        so[i].bn = slot(c, i, S_MAX);
+        if (!std::isfinite(so[i].bn) || !std::isfinite(slot(c, i, S_MAX2))) so[i].rc = HB_ERR_NONFINITE;
+    }
+    if (o.precision == HB_PREC_MIXED) ensure_f32(c, m);
+    solve_core(c, m, x, m.lvl0_b, o, so);
+    if (m.op != HB_OP_VISC) seg_sub_mean(c, all, x);
+    for (int i = 0; i < nb; ++i) {
+        if (so[i].rc == HB_ERR_NONFINITE) rc = HB_ERR_NONFINITE;
+        else if (so[i].rc == HB_ERR_NOCONV && rc == HB_OK) rc = HB_ERR_NOCONV;
+    }
+    if (rc == HB_ERR_NOCONV) c->err = "multigrid did not reach the tolerance within max_cycles";
+    if (rc == HB_ERR_NONFINITE) c->err = "non-finite right-hand side, guess or residual in a multigrid solve";
     return rc;
 }
 
-// solve with the right-hand side already in m.lvl0_b (VISC: wall part added,
-// NODAL/MAC: mean removed by this function)
-static int solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o, hb_mg_report* rep)
+static void to_report(const SolveOut& s, hb_mg_report* r)
 {
-    const long n = m.L[0].nu;
-    if (m.op != HB_OP_VISC) sub_mean(c, m.lvl0_b, n);
-    red_maxabs(c, m.lvl0_b, n, S_MAX);
-    red_maxabs(c, x, n, S_MAX2);
-    fetch_slots(c);
-    const double bn = c->hsc[S_MAX];
-    if (!std::isfinite(bn) || !std::isfinite(c->hsc[S_MAX2])) return fail(c, HB_ERR_NONFINITE, "non-finite right-hand side or guess");
-    if (o.precision == HB_PREC_MIXED) ensure_f32(c, m);
-    int rc = solve_core(c, m, x, m.lvl0_b, bn, o, rep);
-    if (m.op != HB_OP_VISC) sub_mean(c, x, n);
-    if (rc == HB_ERR_NOCONV) c->err = "multigrid did not reach the tolerance within max_cycles";
-    if (rc == HB_ERR_NONFINITE) c->err = "multigrid produced a non-finite residual";
-    return rc;
+    r->cycles = s.cycles;
+    r->rel_resid = s.rel;
+    r->bnorm = s.bn;
 }
 
 static bool valid_opts(const hb_mg_opts& o)
@@ -483,61 +693,171 @@ static bool valid_opts(const hb_mg_opts& o)
            o.tol_rel >= 0.0 && (o.precision == HB_PREC_FP64 || o.precision == HB_PREC_MIXED);
 }
 
+static int worse(int rc, int cur)
+{
+    if (cur == HB_OK) return rc;
+    if (cur == HB_ERR_NOCONV && rc != HB_OK) return rc;
+    return cur;
+}
+
 // ---------------------------------------------------------------------------
-// stages of the step
+// stages of the step (per cavity around the batched solves)
 // ---------------------------------------------------------------------------
 
-// advection stage; requires visc_setup(eta, dt) and S_MAXU = max|u|
-static int advect_stage(Ctx* c, const double* u, const double* p, double dt, double* b, double* conv,
-                        hb_mg_report* mac_rep, double* div_mac_rel)
+// the Godunov prediction up to the MAC divergence (into the MAC right-hand
+// side of cavity b); requires visc_setup and S_MAXU = max|u|
+static void advect_predict(Ctx* c, int b, const double* u, const double* p, double dt)
 {
-    const MG& vm = c->visc;
-    launch_visc_div(c, c->g, vm.L[0].beta, u, c->E);
-    launch_grad_node(c, p, c->Gp);
-    launch_forcing(c);
-    launch_slopes(c, u);
-    launch_trace_normal(c, u, dt);
-    launch_transverse(c);
-    launch_trace_full(c, u, dt);
+    Cav& v = c->cv[b];
+    launch_visc_div(c, v.g, c->visc.L[0].beta + c->visc.L[0].hof[b], u, v.E);
+    launch_grad_node(c, v, p, v.Gp);
+    launch_forcing(c, v);
+    launch_slopes(c, v, u);
+    launch_trace_normal(c, v, u, dt);
+    launch_transverse(c, v);
+    launch_trace_full(c, v, u, dt);
+    if (c->opts.mac_project) launch_mac_div(c, v, v.uadv, c->mac.lvl0_b + c->mac.L[0].ho[b]);
+}
+
+// MAC projection of every cavity's face velocity, then each cavity's
+// viscous right-hand side into rhs (and conv when given)
+static int advect_finish(Ctx* c, const std::vector<const double*>& u, const std::vector<double>& dt,
+                         const std::vector<double*>& rhs, const std::vector<double*>& conv,
+                         std::vector<hb_mg_report>* mrep, std::vector<double>* div_rel)
+{
     int rc = HB_OK;
+    const int nb = c->nb;
+    std::vector<double> d0(nb, 0.0);
     if (c->opts.mac_project) {
-        launch_mac_div(c, c->uadv, c->mac.lvl0_b);
-        double d0 = 0.0;
-        if (div_mac_rel) {
-            red_maxabs(c, c->mac.lvl0_b, c->nc, S_MAX);
+        if (div_rel) {
+            seg_maxabs(c, seg_of(c->mac, nullptr), c->mac.lvl0_b, S_MAX);
             fetch_slots(c);
-            d0 = c->hsc[S_MAX];
+            for (int b = 0; b < nb; ++b) d0[b] = slot(c, b, S_MAX);
         }
-        fill(c, c->macphi, 0.0, c->nc);
-        rc = solve_prepared(c, c->mac, c->macphi, c->opts.mac, mac_rep);
-        launch_mac_update(c);
-        if (div_mac_rel) {
-            launch_mac_div(c, c->umac, c->macrhs);
-            red_maxabs(c, c->macrhs, c->nc, S_MAX);
+        fill(c, c->macphi, 0.0, c->mac.L[0].nu);
+        std::vector<SolveOut> so;
+        rc = solve_prepared(c, c->mac, c->macphi, c->opts.mac, so);
+        for (int b = 0; b < nb; ++b) {
+            launch_mac_update(c, c->cv[b]);
+            if (mrep) to_report(so[b], &(*mrep)[b]);
+            if (div_rel) {
+                launch_mac_div(c, c->cv[b], c->cv[b].umac, c->cv[b].macrhs);
+                red_maxabs(c, b, c->cv[b].macrhs, c->cv[b].nc, S_MAX);
+            }
+        }
+        if (div_rel) {
             fetch_slots(c);
-            *div_mac_rel = d0 > 0.0 ? c->hsc[S_MAX] / d0 : 0.0;
+            for (int b = 0; b < nb; ++b) (*div_rel)[b] = d0[b] > 0.0 ? slot(c, b, S_MAX) / d0[b] : 0.0;
         }
     } else {
-        copy(c, c->umac, c->uadv, c->nf);
-        if (mac_rep) memset(mac_rep, 0, sizeof(*mac_rep));
-        if (div_mac_rel) *div_mac_rel = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            copy(c, c->cv[b].umac, c->cv[b].uadv, c->cv[b].nf);
+            if (mrep) memset(&(*mrep)[b], 0, sizeof(hb_mg_report));
+            if (div_rel) (*div_rel)[b] = 0.0;
+        }
     }
-    launch_advect_rhs(c, u, dt, b, conv);
+    for (int b = 0; b < nb; ++b) launch_advect_rhs(c, c->cv[b], u[b], dt[b], rhs[b], conv[b]);
     return rc;
 }
 
-static int project_stage(Ctx* c, const double* ustar, double* p, double dt, double* u, hb_mg_report* rep)
+// projection of every cavity: V = ustar/dt + G p, K phi = weak div V,
+// u = ustar + dt (G p - G phi), p = phi
+static int project_all(Ctx* c, const std::vector<const double*>& ustar, const std::vector<double*>& p,
+                       const std::vector<double>& dt, const std::vector<double*>& u, std::vector<hb_mg_report>* rep)
 {
-    launch_grad_node(c, p, c->Gp);
-    launch_proj_rhs(c, ustar, dt, c->nodal.lvl0_b);
-    copy(c, c->phi, p, c->nn);
-    int rc = solve_prepared(c, c->nodal, c->phi, c->opts.proj, rep);
-    launch_proj_update(c, ustar, c->phi, dt, u);
-    copy(c, p, c->phi, c->nn);
+    const int nb = c->nb;
+    for (int b = 0; b < nb; ++b) {
+        Cav& v = c->cv[b];
+        launch_grad_node(c, v, p[b], v.Gp);
+        launch_proj_rhs(c, v, ustar[b], dt[b], c->nodal.lvl0_b + c->nodal.L[0].ho[b]);
+        copy(c, v.phi, p[b], v.nn);
+    }
+    std::vector<SolveOut> so;
+    int rc = solve_prepared(c, c->nodal, c->phi, c->opts.proj, so);
+    for (int b = 0; b < nb; ++b) {
+        Cav& v = c->cv[b];
+        launch_proj_update(c, v, ustar[b], v.phi, dt[b], u[b]);
+        copy(c, p[b], v.phi, v.nn);
+        if (rep) to_report(so[b], &(*rep)[b]);
+    }
     return rc;
 }
 
-static bool worse(int rc, int cur) { return cur == HB_OK || (cur == HB_ERR_NOCONV && rc != HB_OK); }
+// One full step of every cavity in place.  dt[b] <= 0 selects the CFL time
+// step of cavity b.
+static int step_all(Ctx* c, double* const* u, double* const* p, const double* dt_in, hb_step_report* reports)
+{
+    const int nb = c->nb;
+    for (int b = 0; b < nb; ++b) {
+        red_maxabs(c, b, u[b], c->cv[b].dim * c->cv[b].nc, S_MAXU);
+        red_maxabs(c, b, p[b], c->cv[b].nn, S_MAX2);
+    }
+    fetch_slots(c);
+    std::vector<double> dt(nb);
+    for (int b = 0; b < nb; ++b) {
+        const Cav& v = c->cv[b];
+        if (!std::isfinite(slot(c, b, S_MAXU)) || !std::isfinite(slot(c, b, S_MAX2)))
+            return fail(c, HB_ERR_NONFINITE, "non-finite u or p");
+        dt[b] = dt_in ? dt_in[b] : 0.0;
+        if (!(dt[b] > 0.0)) {
+            const double mu = std::fmax(v.ulid, slot(c, b, S_MAXU));
+            if (!(mu > 0.0)) return fail(c, HB_ERR_ARG, "dt <= 0 with zero velocity everywhere");
+            dt[b] = c->opts.cfl * v.g.h / mu;
+        }
+    }
+    std::vector<hb_mg_report> mrep(nb), vrep(nb), prep(nb);
+    std::vector<double> divr(nb, 0.0);
+    std::vector<const double*> uc(nb), us(nb);
+    std::vector<double*> rhs(nb), conv(nb, nullptr), uv(nb), pv(nb);
+    for (int b = 0; b < nb; ++b) {
+        Cav& v = c->cv[b];
+        uc[b] = u[b];
+        us[b] = v.ustar;
+        rhs[b] = v.rhs;
+        uv[b] = u[b];
+        pv[b] = p[b];
+        launch_viscosity(c, v, u[b], v.eta);
+        visc_setup(c, b, v.eta, dt[b]);
+        advect_predict(c, b, u[b], p[b], dt[b]);
+    }
+    int rc = advect_finish(c, uc, dt, rhs, conv, &mrep, reports ? &divr : nullptr);
+    if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
+    for (int b = 0; b < nb; ++b) {
+        Cav& v = c->cv[b];
+        launch_visc_wall_rhs(c, v.g, c->visc.L[0].beta + c->visc.L[0].hof[b], dt[b], v.rhs,
+                             c->visc.lvl0_b + c->visc.L[0].hou[b]);
+        copy(c, v.ustar, u[b], v.dim * v.nc);
+    }
+    std::vector<SolveOut> so;
+    int rc2 = solve_prepared(c, c->visc, c->ustar, c->opts.visc, so);
+    for (int b = 0; b < nb; ++b) to_report(so[b], &vrep[b]);
+    rc = worse(rc2, rc);
+    if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
+    rc2 = project_all(c, us, pv, dt, uv, &prep);
+    rc = worse(rc2, rc);
+    if (reports) {
+        for (int b = 0; b < nb; ++b) {
+            Cav& v = c->cv[b];
+            red_maxabs(c, b, u[b], v.dim * v.nc, S_MAX);
+            launch_weak_div(c, v, u[b], v.rnode);
+            red_maxabs(c, b, v.rnode, v.nn, S_MAX2);
+        }
+        fetch_slots(c);
+        for (int b = 0; b < nb; ++b) {
+            hb_step_report& R = reports[b];
+            memset(&R, 0, sizeof(R));
+            R.dt = dt[b];
+            R.max_u = slot(c, b, S_MAX);
+            R.div_node = slot(c, b, S_MAX2) / std::pow(c->cv[b].g.h, c->dim);
+            R.div_mac_rel = divr[b];
+            R.mac = mrep[b];
+            R.visc = vrep[b];
+            R.proj = prep[b];
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return fail(c, HB_ERR_DEVICE, "kernel launch failed");
+    return rc;
+}
 
 // ---------------------------------------------------------------------------
 // kernel timing
@@ -582,11 +902,168 @@ static void kt_free(Ctx* c)
     k.on = false;
 }
 
+// ---------------------------------------------------------------------------
+// creation
+// ---------------------------------------------------------------------------
+
+static const char* check_grid(const hb_grid* grid)
+{
+    if (grid->dim != 2 && grid->dim != 3) return "dim must be 2 or 3";
+    for (int a = 0; a < grid->dim; ++a) {
+        if (!valid_extent(grid->n[a])) return "each n[a] must be c*2^k, c in {1,2,3}, n >= 4";
+        if (grid->bc[a][0] != grid->bc[a][1] && (grid->bc[a][0] == HB_BC_PERIODIC || grid->bc[a][1] == HB_BC_PERIODIC))
+            return "periodic faces must come in pairs";
+        for (int s = 0; s < 2; ++s)
+            if (grid->bc[a][s] != HB_BC_WALL && grid->bc[a][s] != HB_BC_PERIODIC) return "unknown boundary type";
+    }
+    if (!(grid->h > 0.0) || !std::isfinite(grid->h)) return "h must be positive";
+    return nullptr;
+}
+
+static const char* check_fluid(const hb_fluid* fluid)
+{
+    if (!(fluid->Re > 0.0) || !(fluid->Pa > 0.0) || !(fluid->n > 0.0) || !(fluid->HB >= 0.0))
+        return "need Re > 0, Pa > 0, n > 0, HB >= 0";
+    if (fluid->reg != HB_REG_PAPER && fluid->reg != HB_REG_YIELD_ONLY) return "unknown regularisation";
+    if (fluid->reg == HB_REG_YIELD_ONLY && fluid->n < 1.0) return "yield-only regularisation needs n >= 1";
+    return nullptr;
+}
+
+static void destroy_ctx(Ctx* c);
+
+static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, const hb_step_opts* opts,
+                      void* hip_stream, Ctx** out)
+{
+    if (out) *out = nullptr;
+    auto bad = [](const char* m) { g_create_err = m; return HB_ERR_ARG; };
+    if (!grids || !fluids || !opts || !out) return bad("null argument");
+    if (count < 1 || count > 4096) return bad("batch size must be 1 .. 4096");
+    for (int b = 0; b < count; ++b) {
+        if (const char* e = check_grid(&grids[b])) return bad(e);
+        if (const char* e = check_fluid(&fluids[b])) return bad(e);
+        if (grids[b].dim != grids[0].dim) return bad("all cavities of a batch need the same dim");
+    }
+    if (!valid_opts(opts->mac) || !valid_opts(opts->visc) || !valid_opts(opts->proj)) return bad("invalid multigrid options");
+    if (!(opts->cfl > 0.0)) return bad("cfl must be positive");
+
+    Ctx* c = new (std::nothrow) ::hb_ctx();
+    if (!c) return bad("out of host memory");
+    c->opts = *opts;
+    c->user = (hipStream_t)hip_stream;
+    c->nb = count;
+    c->dim = grids[0].dim;
+    auto give_up = [&](int code, const std::string& m) {
+        g_create_err = m;
+        destroy_ctx(c);
+        return code;
+    };
+    if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+        return give_up(HB_ERR_DEVICE, "stream or event creation failed");
+    bool ok = dalloc(&c->sc, (long)S_NSLOT * count) == hipSuccess &&
+              hipHostMalloc((void**)&c->hsc, sizeof(double) * S_NSLOT * count) == hipSuccess &&
+              dalloc(&c->partial, (long)kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
+              dalloc(&c->act2, count) == hipSuccess && dalloc(&c->sel, count) == hipSuccess &&
+              hipHostMalloc((void**)&c->hact, sizeof(int) * count) == hipSuccess &&
+              hipHostMalloc((void**)&c->hact2, sizeof(int) * count) == hipSuccess &&
+              hipHostMalloc((void**)&c->hsel, sizeof(int) * count) == hipSuccess;
+    if (!ok) return give_up(HB_ERR_OOM, "device allocation failed");
+    memset(c->hsc, 0, sizeof(double) * S_NSLOT * count);
+    c->cv.resize(count);
+    for (int b = 0; b < count; ++b) {
+        Cav& v = c->cv[b];
+        v.grid = grids[b];
+        v.fluid = fluids[b];
+        v.g = make_gridd(grids[b]);
+        v.fl.Re = fluids[b].Re;
+        v.fl.HB = fluids[b].HB;
+        v.fl.n = fluids[b].n;
+        v.fl.Pa = fluids[b].Pa;
+        v.fl.reg = fluids[b].reg;
+        for (int q = 0; q < 3; ++q) v.fl.f[q] = q < grids[b].dim ? fluids[b].f[q] : 0.0;
+        v.dim = grids[b].dim;
+        v.nc = ncells(v.g);
+        v.nn = nnodes(v.g);
+        v.nf = nface_total(v.g);
+        v.ulid = 0.0;
+        for (int a = 0; a < v.dim; ++a)
+            for (int s = 0; s < 2; ++s)
+                for (int q = 0; q < 3; ++q) v.ulid = std::fmax(v.ulid, std::fabs(v.g.wall_u[a][s][q]));
+        v.sc = c->sc + (long)b * S_NSLOT;
+        v.hsc = c->hsc + (long)b * S_NSLOT;
+    }
+    int rc;
+    if ((rc = build_mg(c, c->visc, HB_OP_VISC)) != HB_OK) return give_up(rc, c->err);
+    if ((rc = build_mg(c, c->mac, HB_OP_MAC)) != HB_OK) return give_up(rc, c->err);
+    if ((rc = build_mg(c, c->nodal, HB_OP_NODAL)) != HB_OK) return give_up(rc, c->err);
+    const long nvt = c->visc.L[0].nu;
+    ok = dalloc(&c->macphi, c->mac.L[0].nu) == hipSuccess && dalloc(&c->ustar, nvt) == hipSuccess &&
+         dalloc(&c->phi, c->nodal.L[0].nu) == hipSuccess;
+    ok = ok && dalloc(&c->kr, nvt) == hipSuccess && dalloc(&c->krh, nvt) == hipSuccess && dalloc(&c->kp, nvt) == hipSuccess &&
+         dalloc(&c->kv, nvt) == hipSuccess && dalloc(&c->kph, nvt) == hipSuccess && dalloc(&c->ks, nvt) == hipSuccess &&
+         dalloc(&c->ksh, nvt) == hipSuccess && dalloc(&c->kt, nvt) == hipSuccess;
+    for (int b = 0; ok && b < count; ++b) {
+        Cav& v = c->cv[b];
+        const long d = v.dim, nc = v.nc, nf = v.nf, nn = v.nn, nv = d * nc;
+        ok = ok && dalloc(&v.eta, nc) == hipSuccess && dalloc(&v.E, nv) == hipSuccess && dalloc(&v.Gp, nv) == hipSuccess;
+        ok = ok && dalloc(&v.F, nv) == hipSuccess && dalloc(&v.S, d * d * nc) == hipSuccess &&
+             dalloc(&v.trans, d * d * nc) == hipSuccess;
+        ok = ok && dalloc(&v.uhat, nf) == hipSuccess && dalloc(&v.qhat, d * nf) == hipSuccess &&
+             dalloc(&v.qLf, d * nf) == hipSuccess && dalloc(&v.qRf, d * nf) == hipSuccess;
+        ok = ok && dalloc(&v.uadv, nf) == hipSuccess && dalloc(&v.umac, nf) == hipSuccess &&
+             dalloc(&v.macrhs, nc) == hipSuccess && dalloc(&v.rnode, nn) == hipSuccess &&
+             dalloc(&v.conv, nv) == hipSuccess && dalloc(&v.rhs, nv) == hipSuccess;
+        const int nmax = std::max(c->visc.hcs[b].N, std::max(c->mac.hcs[b].N, c->nodal.hcs[b].N));
+        ok = ok && dalloc(&v.dense_E, (long)nmax * nmax) == hipSuccess;
+        v.macphi = c->macphi + c->mac.L[0].ho[b];
+        v.ustar = c->ustar + c->visc.L[0].hou[b];
+        v.phi = c->phi + c->nodal.L[0].ho[b];
+    }
+    if (!ok) return give_up(HB_ERR_OOM, "device allocation failed");
+    fill(c, c->sc, 0.0, (long)S_NSLOT * count);
+    // constant coarsest matrices of the MAC and nodal problems
+    for (int b = 0; b < count; ++b) {
+        factor_coarsest(c, c->mac, b);
+        factor_coarsest(c, c->nodal, b);
+    }
+    if (hipStreamSynchronize(c->s) != hipSuccess) return give_up(HB_ERR_DEVICE, "stream synchronisation failed during set-up");
+    *out = c;
+    return HB_OK;
+}
+
+static void destroy_ctx(Ctx* c)
+{
+    if (!c) return;
+    if (c->s) (void)hipStreamSynchronize(c->s);
+    kt_free(c);
+    free_mg(c->visc);
+    free_mg(c->mac);
+    free_mg(c->nodal);
+    for (Cav& v : c->cv) {
+        double* bufs[] = {v.eta, v.E, v.Gp, v.F, v.S, v.trans, v.uhat, v.qhat, v.qLf, v.qRf, v.uadv, v.umac,
+                          v.macrhs, v.rnode, v.conv, v.rhs, v.dense_E};
+        for (double* p : bufs) (void)hipFree(p);
+    }
+    double* bufs[] = {c->macphi, c->ustar, c->phi, c->kr, c->krh, c->kp, c->kv, c->kph, c->ks, c->ksh, c->kt,
+                      c->sc, c->partial};
+    for (double* p : bufs) (void)hipFree(p);
+    (void)hipFree(c->act);
+    (void)hipFree(c->act2);
+    (void)hipFree(c->sel);
+    if (c->hsc) (void)hipHostFree(c->hsc);
+    if (c->hact) (void)hipHostFree(c->hact);
+    if (c->hact2) (void)hipHostFree(c->hact2);
+    if (c->hsel) (void)hipHostFree(c->hsel);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->s) (void)hipStreamDestroy(c->s);
+    delete static_cast<::hb_ctx*>(c);
+}
+
 }  // namespace hb
 
 using namespace hb;
-
-struct hb_ctx : public Ctx {};
 
 // Work of an ABI call runs on the library's stream, after everything queued
 // on the caller's stream before the call, and the caller's stream waits for
@@ -605,132 +1082,54 @@ struct StreamGuard {
     }
 };
 
+static int single_only(Ctx* c)
+{
+    return c->nb == 1 ? HB_OK : fail(c, HB_ERR_ARG, "this call takes a single-cavity context (use hb_step_batch)");
+}
+
+static Ctx* C_(hb_ctx* h) { return static_cast<Ctx*>(h); }
+static const Ctx* C_(const hb_ctx* h) { return static_cast<const Ctx*>(h); }
+
 extern "C" {
 
 const char* hb_last_error(const hb_ctx* ctx)
 {
     if (!ctx) return g_create_err.c_str();
-    return ctx->err.c_str();
+    return C_(ctx)->err.c_str();
 }
 
 void hb_destroy(hb_ctx* ctx)
 {
-    if (!ctx) return;
-    Ctx* c = ctx;
-    kt_free(c);
-    free_mg(c->visc);
-    free_mg(c->mac);
-    free_mg(c->nodal);
-    if (c->s) (void)hipStreamSynchronize(c->s);
-    double* bufs[] = {c->eta, c->E, c->Gp, c->F, c->S, c->trans, c->uhat, c->qhat, c->qLf, c->qRf, c->uadv,
-                      c->umac, c->macphi, c->macrhs, c->b, c->ustar, c->rnode, c->phi, c->conv, c->kr, c->krh,
-                      c->kp, c->kv, c->kph, c->ks, c->ksh, c->kt, c->dense_E, c->sc, c->partial};
-    for (double* p : bufs) (void)hipFree(p);
-    if (c->hsc) (void)hipHostFree(c->hsc);
-    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
-    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
-    if (c->s) (void)hipStreamDestroy(c->s);
-    delete ctx;
+    if (ctx) destroy_ctx(C_(ctx));
 }
 
 int hb_create(const hb_grid* grid, const hb_fluid* fluid, const hb_step_opts* opts, void* hip_stream, hb_ctx** out)
 {
-    if (out) *out = nullptr;
-    auto bad = [](const char* m) { g_create_err = m; return HB_ERR_ARG; };
-    if (!grid || !fluid || !opts || !out) return bad("null argument");
-    if (grid->dim != 2 && grid->dim != 3) return bad("dim must be 2 or 3");
-    for (int a = 0; a < grid->dim; ++a) {
-        if (!valid_extent(grid->n[a])) return bad("each n[a] must be c*2^k, c in {1,2,3}, n >= 4");
-        if (grid->bc[a][0] != grid->bc[a][1] && (grid->bc[a][0] == HB_BC_PERIODIC || grid->bc[a][1] == HB_BC_PERIODIC))
-            return bad("periodic faces must come in pairs");
-        for (int s = 0; s < 2; ++s)
-            if (grid->bc[a][s] != HB_BC_WALL && grid->bc[a][s] != HB_BC_PERIODIC) return bad("unknown boundary type");
-    }
-    if (!(grid->h > 0.0) || !std::isfinite(grid->h)) return bad("h must be positive");
-    if (!(fluid->Re > 0.0) || !(fluid->Pa > 0.0) || !(fluid->n > 0.0) || !(fluid->HB >= 0.0))
-        return bad("need Re > 0, Pa > 0, n > 0, HB >= 0");
-    if (fluid->reg != HB_REG_PAPER && fluid->reg != HB_REG_YIELD_ONLY) return bad("unknown regularisation");
-    if (fluid->reg == HB_REG_YIELD_ONLY && fluid->n < 1.0) return bad("yield-only regularisation needs n >= 1");
-    if (!valid_opts(opts->mac) || !valid_opts(opts->visc) || !valid_opts(opts->proj)) return bad("invalid multigrid options");
-    if (!(opts->cfl > 0.0)) return bad("cfl must be positive");
-
-    hb_ctx* ctx = new (std::nothrow) hb_ctx();
-    if (!ctx) return bad("out of host memory");
-    Ctx* c = ctx;
-    c->grid = *grid;
-    c->fluid = *fluid;
-    c->opts = *opts;
-    c->user = (hipStream_t)hip_stream;
-    if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
-        g_create_err = "stream or event creation failed";
-        hb_destroy(ctx);
-        return HB_ERR_DEVICE;
-    }
-    c->g = make_gridd(*grid);
-    c->fl.Re = fluid->Re;
-    c->fl.HB = fluid->HB;
-    c->fl.n = fluid->n;
-    c->fl.Pa = fluid->Pa;
-    c->fl.reg = fluid->reg;
-    for (int q = 0; q < 3; ++q) c->fl.f[q] = q < grid->dim ? fluid->f[q] : 0.0;
-    c->dim = grid->dim;
-    c->nc = ncells(c->g);
-    c->nn = nnodes(c->g);
-    c->nf = nface_total(c->g);
-    c->ulid = 0.0;
-    for (int a = 0; a < c->dim; ++a)
-        for (int s = 0; s < 2; ++s)
-            for (int q = 0; q < 3; ++q) c->ulid = std::fmax(c->ulid, std::fabs(c->g.wall_u[a][s][q]));
-
-    auto oom = [&](const std::string& m) {
-        g_create_err = m.empty() ? "device allocation failed" : m;
-        hb_destroy(ctx);
-        return HB_ERR_OOM;
-    };
-    int rc;
-    if ((rc = build_mg(c, c->visc, HB_OP_VISC)) != HB_OK) { g_create_err = c->err; hb_destroy(ctx); return rc; }
-    if ((rc = build_mg(c, c->mac, HB_OP_MAC)) != HB_OK) { g_create_err = c->err; hb_destroy(ctx); return rc; }
-    if ((rc = build_mg(c, c->nodal, HB_OP_NODAL)) != HB_OK) { g_create_err = c->err; hb_destroy(ctx); return rc; }
-    const long d = c->dim, nc = c->nc, nf = c->nf, nn = c->nn;
-    const long nv = d * nc;
-    bool ok = true;
-    ok = ok && dalloc(&c->eta, nc) == hipSuccess && dalloc(&c->E, nv) == hipSuccess && dalloc(&c->Gp, nv) == hipSuccess;
-    ok = ok && dalloc(&c->F, nv) == hipSuccess && dalloc(&c->S, d * d * nc) == hipSuccess &&
-         dalloc(&c->trans, d * d * nc) == hipSuccess;
-    ok = ok && dalloc(&c->uhat, nf) == hipSuccess && dalloc(&c->qhat, d * nf) == hipSuccess &&
-         dalloc(&c->qLf, d * nf) == hipSuccess && dalloc(&c->qRf, d * nf) == hipSuccess;
-    ok = ok && dalloc(&c->uadv, nf) == hipSuccess && dalloc(&c->umac, nf) == hipSuccess &&
-         dalloc(&c->macphi, nc) == hipSuccess && dalloc(&c->macrhs, nc) == hipSuccess;
-    ok = ok && dalloc(&c->b, nv) == hipSuccess && dalloc(&c->ustar, nv) == hipSuccess &&
-         dalloc(&c->rnode, nn) == hipSuccess && dalloc(&c->phi, nn) == hipSuccess && dalloc(&c->conv, nv) == hipSuccess;
-    ok = ok && dalloc(&c->kr, nv) == hipSuccess && dalloc(&c->krh, nv) == hipSuccess && dalloc(&c->kp, nv) == hipSuccess &&
-         dalloc(&c->kv, nv) == hipSuccess && dalloc(&c->kph, nv) == hipSuccess && dalloc(&c->ks, nv) == hipSuccess &&
-         dalloc(&c->ksh, nv) == hipSuccess && dalloc(&c->kt, nv) == hipSuccess;
-    int nmax = c->visc.ncoarse;
-    if (c->mac.ncoarse > nmax) nmax = c->mac.ncoarse;
-    if (c->nodal.ncoarse > nmax) nmax = c->nodal.ncoarse;
-    ok = ok && dalloc(&c->dense_E, (long)nmax * nmax) == hipSuccess;
-    ok = ok && dalloc(&c->sc, S_NSLOT) == hipSuccess && dalloc(&c->partial, kRedBlocks) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&c->hsc, sizeof(double) * S_NSLOT) == hipSuccess;
-    if (!ok) return oom("");
-    fill(c, c->sc, 0.0, S_NSLOT);
-    // constant coarsest matrices of the MAC and nodal problems
-    factor_coarsest(c, c->mac);
-    factor_coarsest(c, c->nodal);
-    if (hipStreamSynchronize(c->s) != hipSuccess) return oom("stream synchronisation failed during set-up");
-    *out = ctx;
-    return HB_OK;
+    Ctx* c = nullptr;
+    const int rc = create_ctx(grid, fluid, 1, opts, hip_stream, &c);
+    if (out) *out = static_cast<hb_ctx*>(c);
+    return rc;
 }
+
+int hb_create_batch(const hb_grid* grids, const hb_fluid* fluids, int count, const hb_step_opts* opts,
+                    void* hip_stream, hb_ctx** out)
+{
+    Ctx* c = nullptr;
+    const int rc = create_ctx(grids, fluids, count, opts, hip_stream, &c);
+    if (out) *out = static_cast<hb_ctx*>(c);
+    return rc;
+}
+
+int hb_batch_size(const hb_ctx* ctx) { return ctx ? C_(ctx)->nb : 0; }
 
 int hb_viscosity(hb_ctx* ctx, const double* u, double* eta)
 {
     if (!ctx) return HB_ERR_ARG;
-    Ctx* c = ctx;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
     if (!u || !eta) return fail(c, HB_ERR_ARG, "null array");
     StreamGuard guard(c);
-    launch_viscosity(c, u, eta);
+    launch_viscosity(c, c->cv[0], u, eta);
     return hipGetLastError() == hipSuccess ? HB_OK : fail(c, HB_ERR_DEVICE, "kernel launch failed");
 }
 
@@ -738,7 +1137,8 @@ int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt, const double*
                 const hb_mg_opts* opts, hb_mg_report* report)
 {
     if (!ctx) return HB_ERR_ARG;
-    Ctx* c = ctx;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
     if (!rhs || !x) return fail(c, HB_ERR_ARG, "null array");
     if (op != HB_OP_VISC && op != HB_OP_NODAL && op != HB_OP_MAC) return fail(c, HB_ERR_ARG, "unknown operator");
     if (op == HB_OP_VISC && (!eta || !(dt > 0.0))) return fail(c, HB_ERR_ARG, "viscous solve needs eta and dt > 0");
@@ -747,26 +1147,34 @@ int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt, const double*
     MG& m = op == HB_OP_VISC ? c->visc : (op == HB_OP_MAC ? c->mac : c->nodal);
     StreamGuard guard(c);
     if (op == HB_OP_VISC) {
-        visc_setup(c, eta, dt);
-        launch_visc_wall_rhs(c, c->g, m.L[0].beta, dt, rhs, m.lvl0_b);
+        visc_setup(c, 0, eta, dt);
+        launch_visc_wall_rhs(c, c->cv[0].g, m.L[0].beta, dt, rhs, m.lvl0_b);
     } else {
         copy(c, m.lvl0_b, rhs, m.L[0].nu);
     }
-    return solve_prepared(c, m, x, o, report);
+    std::vector<SolveOut> so;
+    const int rc = solve_prepared(c, m, x, o, so);
+    if (report) to_report(so[0], report);
+    return rc;
 }
 
 int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta, double dt, double* b, double* umac,
               double* conv, hb_mg_report* mac_report)
 {
     if (!ctx) return HB_ERR_ARG;
-    Ctx* c = ctx;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
     if (!u || !p || !eta || !b) return fail(c, HB_ERR_ARG, "null array");
     if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
     StreamGuard guard(c);
-    red_maxabs(c, u, c->dim * c->nc, S_MAXU);
-    visc_setup(c, eta, dt);
-    int rc = advect_stage(c, u, p, dt, b, conv, mac_report, nullptr);
-    if (umac) copy(c, umac, c->umac, c->nf);
+    Cav& v = c->cv[0];
+    red_maxabs(c, 0, u, v.dim * v.nc, S_MAXU);
+    visc_setup(c, 0, eta, dt);
+    advect_predict(c, 0, u, p, dt);
+    std::vector<hb_mg_report> mrep(1);
+    const int rc = advect_finish(c, {u}, {dt}, {b}, {conv}, &mrep, nullptr);
+    if (mac_report) *mac_report = mrep[0];
+    if (umac) copy(c, umac, v.umac, v.nf);
     if (hipStreamSynchronize(c->s) != hipSuccess) return fail(c, HB_ERR_DEVICE, "stream synchronisation failed");
     return rc;
 }
@@ -774,75 +1182,58 @@ int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta, 
 int hb_project(hb_ctx* ctx, const double* ustar, double* p, double dt, double* u, hb_mg_report* report)
 {
     if (!ctx) return HB_ERR_ARG;
-    Ctx* c = ctx;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
     if (!ustar || !p || !u) return fail(c, HB_ERR_ARG, "null array");
     if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
     StreamGuard guard(c);
-    return project_stage(c, ustar, p, dt, u, report);
+    std::vector<hb_mg_report> rep(1);
+    const int rc = project_all(c, {ustar}, {p}, {dt}, {u}, &rep);
+    if (report) *report = rep[0];
+    return rc;
 }
 
 int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out)
 {
     if (!ctx) return HB_ERR_ARG;
-    Ctx* c = ctx;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
     if (!u || !dt_out) return fail(c, HB_ERR_ARG, "null argument");
     StreamGuard guard(c);
-    red_maxabs(c, u, c->dim * c->nc, S_MAXU);
+    const Cav& v = c->cv[0];
+    red_maxabs(c, 0, u, v.dim * v.nc, S_MAXU);
     fetch_slots(c);
-    const double m = std::fmax(c->ulid, c->hsc[S_MAXU]);
+    const double m = std::fmax(v.ulid, slot(c, 0, S_MAXU));
     if (!std::isfinite(m)) return fail(c, HB_ERR_NONFINITE, "non-finite velocity");
-    *dt_out = m > 0.0 ? c->opts.cfl * c->g.h / m : 0.0;
+    *dt_out = m > 0.0 ? c->opts.cfl * v.g.h / m : 0.0;
     return HB_OK;
 }
 
 int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report)
 {
     if (!ctx) return HB_ERR_ARG;
-    Ctx* c = ctx;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
     if (!u || !p) return fail(c, HB_ERR_ARG, "null array");
     StreamGuard guard(c);
-    const long nv = c->dim * c->nc;
-    red_maxabs(c, u, nv, S_MAXU);
-    red_maxabs(c, p, c->nn, S_MAX2);
-    fetch_slots(c);
-    if (!std::isfinite(c->hsc[S_MAXU]) || !std::isfinite(c->hsc[S_MAX2])) return fail(c, HB_ERR_NONFINITE, "non-finite u or p");
-    if (!(dt > 0.0)) {
-        const double m = std::fmax(c->ulid, c->hsc[S_MAXU]);
-        if (!(m > 0.0)) return fail(c, HB_ERR_ARG, "dt <= 0 with zero velocity everywhere");
-        dt = c->opts.cfl * c->g.h / m;
-    }
-    hb_step_report R;
-    memset(&R, 0, sizeof(R));
-    R.dt = dt;
-    launch_viscosity(c, u, c->eta);
-    visc_setup(c, c->eta, dt);
-    int rc = advect_stage(c, u, p, dt, c->b, nullptr, &R.mac, report ? &R.div_mac_rel : nullptr);
-    if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
-    int rc2 = HB_OK;
-    launch_visc_wall_rhs(c, c->g, c->visc.L[0].beta, dt, c->b, c->visc.lvl0_b);
-    copy(c, c->ustar, u, nv);
-    rc2 = solve_prepared(c, c->visc, c->ustar, c->opts.visc, &R.visc);
-    if (worse(rc2, rc)) rc = rc2;
-    if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
-    rc2 = project_stage(c, c->ustar, p, dt, u, &R.proj);
-    if (worse(rc2, rc)) rc = rc2;
-    if (report) {
-        red_maxabs(c, u, nv, S_MAX);
-        launch_weak_div(c, u, c->rnode);
-        red_maxabs(c, c->rnode, c->nn, S_MAX2);
-        fetch_slots(c);
-        R.max_u = c->hsc[S_MAX];
-        R.div_node = c->hsc[S_MAX2] / std::pow(c->g.h, c->dim);
-        *report = R;
-    }
-    if (hipGetLastError() != hipSuccess) return fail(c, HB_ERR_DEVICE, "kernel launch failed");
-    return rc;
+    return step_all(c, &u, &p, &dt, report);
+}
+
+int hb_step_batch(hb_ctx* ctx, double* const* u, double* const* p, const double* dt, hb_step_report* reports)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (!u || !p) return fail(c, HB_ERR_ARG, "null array");
+    for (int b = 0; b < c->nb; ++b)
+        if (!u[b] || !p[b]) return fail(c, HB_ERR_ARG, "null array");
+    StreamGuard guard(c);
+    return step_all(c, u, p, dt, reports);
 }
 
 int hb_kernel_timing(hb_ctx* ctx, int enable)
 {
     if (!ctx) return HB_ERR_ARG;
-    Ctx* c = ctx;
+    Ctx* c = C_(ctx);
     KTimer& k = c->ktm;
     if (enable && !k.ev) {
         const int cap = 2048;
@@ -868,7 +1259,7 @@ int hb_kernel_timing(hb_ctx* ctx, int enable)
 int hb_kernel_timing_read(hb_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes)
 {
     if (!ctx || !launches || !total_ms || !alg_bytes) return HB_ERR_ARG;
-    Ctx* c = ctx;
+    Ctx* c = C_(ctx);
     kt_harvest(c);
     *launches = c->ktm.launches;
     *total_ms = c->ktm.ms;

@@ -1,8 +1,17 @@
-// hb_internal.h -- host-side context, multigrid hierarchy and kernel
+// hb_internal.h -- host-side context, batched multigrid hierarchy and kernel
 // launchers of the HIP library (not part of the public ABI).
+//
+// A context holds a batch of nb independent cavities (nb = 1 for hb_create).
+// The per-step work outside the solves runs per cavity.  The three linear
+// solves run batched: every array of a multigrid level is one arena holding
+// all cavities back to back, and every multigrid kernel covers all cavities
+// in one launch, each block finding its cavity (grid, array offsets, active
+// flag) in small device tables.  Cavities converge independently: a cavity
+// that has reached its tolerance is masked out of the following launches.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <string>
+#include <vector>
 
 #include "../../include/hb.h"
 #include "hb_dev.h"
@@ -15,24 +24,71 @@ struct FluidD {
     double f[3];
 };
 
+// scalar slots of each cavity (device doubles, S_NSLOT per cavity)
+enum Slot {
+    S_MAX = 0, S_SUM = 1, S_DOT0 = 2, S_DOT1 = 3, S_MAXU = 4, S_MAX2 = 5, S_DT = 6,
+    // BiCGStab scalars, computed and used on the device
+    S_RHO = 8, S_RHOP = 9, S_ALPHA = 10, S_OMEGA = 11, S_BETA = 12,
+    S_NSLOT = 16
+};
+
+// Batched view of one multigrid level, passed by value to the cycle kernels.
+// Block z index = cavity * zb + z-block within the cavity.
+struct BV {
+    const GridD* g;     // per cavity; dim == 0: the cavity takes no part
+    const long* o;      // per cavity offset of a one-component array (cells, or nodes)
+    const long* of;     // per cavity offset of the face arrays (tensor problem)
+    const int* act;     // per cavity active flag (nullptr: all active)
+    int zb;             // z-blocks per cavity in the launch grid
+};
+
+// Segmented view of a batch vector (vector kernels and reductions)
+struct SegV {
+    const long* off;    // per cavity first element
+    const long* n;      // per cavity length
+    const int* act;     // per cavity active flag (nullptr: all)
+};
+
+// cavity of this block and the block's z index within it; false when the
+// cavity takes no part in the launch
+__device__ inline bool bv_enter(const BV& v, int& cav, int& bz, GridD& g)
+{
+    cav = blockIdx.z / v.zb;
+    bz = blockIdx.z - cav * v.zb;
+    if (v.act && !v.act[cav]) return false;
+    g = v.g[cav];
+    return g.dim != 0;
+}
+
 struct Level {
-    GridD g;
-    long nu = 0;             // unknowns of this level
+    GridD gmax;              // largest extents over the batch (launch grids)
+    long nu = 0;             // unknowns over the batch (arena length)
     int cur = 0;             // buffer holding the current iterate
-    // FP64 arrays
+    // FP64 arenas
     double* xb[2] = {nullptr, nullptr};  // double-buffered iterate
     double* b = nullptr;     // right-hand side
     double* r = nullptr;     // residual scratch
     double* beta = nullptr;  // face viscosity (tensor problem only)
-    // FP32 arrays of the mixed-precision correction cycles
+    // FP32 arenas of the mixed-precision correction cycles
     float* fx[2] = {nullptr, nullptr};
     float* fb = nullptr;
     float* fr = nullptr;
     float* fbeta = nullptr;
+    // device tables (nb entries)
+    GridD* gall = nullptr;   // cavities that have this level
+    GridD* gsm = nullptr;    // cavities that smooth here (not their coarsest level)
+    long* o = nullptr;       // component-array offsets (cells or nodes)
+    long* of = nullptr;      // face-array offsets
+    long* ou = nullptr;      // unknown offsets (ncomp * o)
+    long* nuc = nullptr;     // unknowns per cavity
+    // host copies
+    std::vector<GridD> hg;   // per cavity grid (dim == 0: absent)
+    std::vector<long> ho, hof, hou, hnu;
+    bool any_sm = false, any_cs = false;   // some cavity smooths here / is at its coarsest
     double* X() const { return xb[cur]; }
 };
 
-// the arrays of a level in storage precision R
+// the arenas of a level in storage precision R
 template <typename R> struct LB;
 template <> struct LB<double> {
     static double* x(const Level& L) { return L.xb[L.cur]; }
@@ -49,25 +105,57 @@ template <> struct LB<float> {
     static const float* beta(const Level& L) { return L.fbeta; }
 };
 
+// coarsest-level description of one cavity (device table)
+struct CoarseD {
+    int lev;        // its coarsest level
+    int N;          // unknowns there
+    long aoff;      // offset of its N x N matrix in the A / Ainv arenas
+    long poff;      // offset of its pivots
+    long xoff;      // offset of its unknowns in that level's arenas
+};
+
 struct MG {
     int op = 0;
-    int nlev = 0;
+    int nlev = 0;            // levels of the deepest cavity
+    int ncomp = 1;           // components per cell (tensor problem: dim)
     Level L[kMaxLev];
-    int ncoarse = 0;         // unknowns on the coarsest level
-    double* A = nullptr;     // coarsest dense matrix -> LU factors
+    std::vector<int> nlevc;  // levels per cavity
+    std::vector<CoarseD> hcs;
+    CoarseD* cs = nullptr;   // device copy
+    int ncmax = 0;           // largest coarsest system
+    double* A = nullptr;     // coarsest dense matrices -> LU factors (arena)
     int* piv = nullptr;
-    double* Ainv = nullptr;  // inverse of the coarsest matrix (from the LU factors)
-    double dt = 0.0;         // tensor problem: dt of the factorised matrix
-    double* lvl0_b = nullptr;  // level-0 right-hand side storage
-    double* etae = nullptr;    // tensor problem: eta/Re per fine cell
+    double* Ainv = nullptr;  // their inverses
+    double* lvl0_b = nullptr;  // level-0 right-hand side arena
+    double* etae = nullptr;    // tensor problem: eta/Re per fine cell (arena)
     float* etae32 = nullptr;   // its FP32 copy
     bool f32_ready = false;    // FP32 coefficient copies match the FP64 ones
+    SegV seg0;                 // level-0 unknowns as a segmented vector
     // levels 1.. of a V-cycle captured once per precision as a HIP graph and
     // replayed (index 0: FP64, 1: FP32)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gnu1[2] = {-1, -1}, gnu2[2] = {-1, -1};
     bool gfail[2] = {false, false};
     bool capturing = false;
+};
+
+// one cavity of a context: its descriptors and the step's scratch
+struct Cav {
+    hb_grid grid;
+    hb_fluid fluid;
+    GridD g;
+    FluidD fl;
+    int dim = 2;
+    long nc = 0, nn = 0, nf = 0;
+    double ulid = 0.0;
+    double* sc = nullptr;    // its scalar slots (device)
+    double* hsc = nullptr;   // their pinned host mirror
+    double *eta = nullptr, *E = nullptr, *Gp = nullptr, *F = nullptr, *S = nullptr, *trans = nullptr;
+    double *uhat = nullptr, *qhat = nullptr, *qLf = nullptr, *qRf = nullptr, *uadv = nullptr, *umac = nullptr;
+    double *macrhs = nullptr, *rnode = nullptr, *conv = nullptr, *rhs = nullptr;
+    double* dense_E = nullptr;   // unit vectors for the dense coarsest assembly
+    // views into the solve arenas
+    double *macphi = nullptr, *ustar = nullptr, *phi = nullptr;
 };
 
 // HIP-event timing of every launch of one kernel (measurement support)
@@ -79,40 +167,30 @@ struct KTimer {
     double ms = 0.0, bytes = 0.0;
 };
 
-// scalar slots in ctx->sc (device doubles)
-enum Slot {
-    S_MAX = 0, S_SUM = 1, S_DOT0 = 2, S_DOT1 = 3, S_MAXU = 4, S_MAX2 = 5, S_DT = 6,
-    // BiCGStab scalars, computed and used on the device
-    S_RHO = 8, S_RHOP = 9, S_ALPHA = 10, S_OMEGA = 11, S_BETA = 12,
-    S_NSLOT = 16
-};
-
 struct Ctx {
-    hb_grid grid;
-    hb_fluid fluid;
     hb_step_opts opts;
     hipStream_t s = nullptr;      // the library's own stream (all work runs here)
     hipStream_t user = nullptr;   // the caller's stream, ordered with s by events
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    GridD g;                 // finest grid
-    FluidD fl;
-    int dim = 2;
-    long nc = 0, nn = 0, nf = 0;
-    double ulid = 0.0;
+    int nb = 1;                   // cavities
+    int dim = 2;                  // common dimension
+    std::vector<Cav> cv;
     MG visc, mac, nodal;
-    // step scratch
-    double *eta = nullptr, *E = nullptr, *Gp = nullptr, *F = nullptr, *S = nullptr, *trans = nullptr;
-    double *uhat = nullptr, *qhat = nullptr, *qLf = nullptr, *qRf = nullptr, *uadv = nullptr, *umac = nullptr;
-    double *macphi = nullptr, *macrhs = nullptr, *b = nullptr, *ustar = nullptr, *rnode = nullptr;
-    double *phi = nullptr, *conv = nullptr;
-    // Krylov vectors (tensor problem size)
+    // solve arenas over the batch (offsets from the level-0 tables)
+    double *macphi = nullptr, *ustar = nullptr, *phi = nullptr;
+    // Krylov vectors (tensor problem, arena layout)
     double *kr = nullptr, *krh = nullptr, *kp = nullptr, *kv = nullptr, *kph = nullptr, *ks = nullptr,
            *ksh = nullptr, *kt = nullptr;
-    double* dense_E = nullptr;   // unit-vector scratch for dense assembly
-    double* sc = nullptr;        // device scalar slots
-    double* partial = nullptr;   // reduction partials
-    double* hsc = nullptr;       // pinned host mirror of the slots
-    KTimer ktm;                  // timing of the tensor smoother launches
+    double* sc = nullptr;        // device scalar slots, S_NSLOT per cavity
+    double* hsc = nullptr;       // pinned host mirror
+    double* partial = nullptr;   // reduction partials (kRedBlocks per cavity)
+    int* act = nullptr;          // device active flags (nb)
+    int* hact = nullptr;         // pinned host staging of the flags
+    int* act2 = nullptr;         // second flag set (cavities finishing at a half step)
+    int* hact2 = nullptr;
+    int* sel = nullptr;          // per cavity buffer choice (device) and staging
+    int* hsel = nullptr;
+    KTimer ktm;                  // timing of the finest tensor smoother launches
     std::string err;
 };
 
@@ -122,92 +200,106 @@ void kt_harvest(Ctx* c);
 
 // ---- launch helpers --------------------------------------------------------
 inline dim3 grid3(int ex, int ey, int ez, dim3 blk) { return dim3((ex + blk.x - 1) / blk.x, (ey + blk.y - 1) / blk.y, ez); }
-constexpr int kRedBlocks = 512;   // fixed block count: deterministic sums
+constexpr int kRedBlocks = 512;   // fixed block count per cavity: deterministic sums
 
-// reductions (hb_reduce.hip)
-void red_maxabs(Ctx* c, const double* v, long n, int slot, bool accumulate = false);
-void red_sum(Ctx* c, const double* v, long n, int slot);
-void red_dot(Ctx* c, const double* a, const double* b, long n, int slot);
+// ---- reductions and vector kernels (hb_reduce.hip) -------------------------
+// single-array forms, result into slot of cavity cav
+void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot);
+void set_slot(Ctx* c, int cav, int slot, double v);
 void fetch_slots(Ctx* c);  // copies all slots to c->hsc and synchronises
-void set_slot_zero(Ctx* c, int slot);
-void set_slot(Ctx* c, int slot, double v);
-void sub_mean(Ctx* c, double* v, long n);   // v -= sum(v)/n (device-side)
-// device-scalar BiCGStab steps (scalars in the slots S_RHO .. S_BETA)
-void bicg_init_scalars(Ctx* c);
-void bicg_beta(Ctx* c);             // rho = DOT0, beta = (rho/rho_prev)(alpha/omega)
-void bicg_alpha(Ctx* c);            // alpha = rho / DOT1
-void bicg_omega(Ctx* c);            // omega = DOT0 > 0 ? DOT1 / DOT0 : 0; rho_prev = rho
-void bicg_p_dev(Ctx* c, double* p, const double* r, const double* v, long n);
-void sub_scaled_max_dev(Ctx* c, double* out, const double* a, int sslot, const double* b, long n, int mslot);
-void bicg_x_dev(Ctx* c, double* x, const double* ph, const double* sh, bool with_omega, long n);
 void copy(Ctx* c, double* dst, const double* src, long n);
 void fill(Ctx* c, double* dst, double v, long n);
+// segmented forms over the batch (per cavity slot, inactive cavities skipped)
+void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot);
+void seg_set_zero(Ctx* c, int slot);                       // every cavity
+void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot);
+void seg_sub_mean(Ctx* c, const SegV& s, double* v);
+void seg_copy(Ctx* c, const SegV& s, double* dst, const double* src);
+void seg_fill(Ctx* c, const SegV& s, double* dst, double v);
+void seg_copy_sel(Ctx* c, const SegV& s, double* dst, const double* src0, const double* src1, const int* sel);
+void seg_to_f32(Ctx* c, const SegV& s, const double* src, float* dst, float* zero);
+void seg_add_f32(Ctx* c, const SegV& s, double* x, const float* e);
+void seg_from_f32(Ctx* c, const SegV& s, const float* e, double* x);
+void flat_to_f32(Ctx* c, const double* src, float* dst, long n);
+// device-scalar BiCGStab steps (scalars in each cavity's slots S_RHO .. S_BETA)
+void bicg_init_scalars(Ctx* c, const int* act);
+void bicg_beta(Ctx* c, const int* act);     // rho = DOT0, beta = (rho/rho_prev)(alpha/omega)
+void bicg_alpha(Ctx* c, const int* act);    // alpha = rho / DOT1
+void bicg_omega(Ctx* c, const int* act);    // omega = DOT0 > 0 ? DOT1 / DOT0 : 0; rho_prev = rho
+void bicg_p_dev(Ctx* c, const SegV& s, double* p, const double* r, const double* v);
+void sub_scaled_max_dev(Ctx* c, const SegV& s, double* out, const double* a, int sslot, const double* b, int mslot);
+void bicg_x_dev(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, bool with_omega);
 
-// viscosity and tensor operator (hb_visc.hip)
-void launch_viscosity(Ctx* c, const double* u, double* eta);
-void launch_eta_faces(Ctx* c, const GridD& g, const double* eta, double* beta);
+// ---- viscosity and tensor operator, per cavity (hb_visc.hip) ----------------
+void launch_viscosity(Ctx* c, const Cav& v, const double* u, double* eta);
+void launch_eta_faces(Ctx* c, const Cav& v, const GridD& g, const double* eta, double* beta);
 void launch_restrict_faces(Ctx* c, const GridD& gf, const GridD& gc, const double* bf, double* bc);
 void launch_visc_div(Ctx* c, const GridD& g, const double* beta, const double* u, double* out);
 void launch_visc_wall_rhs(Ctx* c, const GridD& g, const double* beta, double dt, const double* rhs, double* out);
-void launch_visc_dense(Ctx* c, const Level& l, double dt, int N, double* E, double* A);
-void launch_eta_over_re(Ctx* c, const GridD& g, const double* eta, double* etae);
+void launch_visc_dense(Ctx* c, const GridD& g, const double* beta, double dt, int N, const double* E, double* A);
+void launch_eta_over_re(Ctx* c, const Cav& v, const double* eta, double* etae);
 
-// LDS-tiled tensor kernels (hb_tile.hip), R = storage and arithmetic
-// precision of the multigrid cycle; fine = coef is eta/Re per cell (else the
-// level's face viscosities).  dt is read from device memory, so a captured
-// graph stays valid across steps.
+// ---- LDS-tiled tensor kernels, batched (hb_tile.hip) ------------------------
+// R = storage and arithmetic precision of the cycle; fine = coef is eta/Re
+// per cell (else the level's face viscosities).  dt is read from each
+// cavity's slot S_DT, so a captured graph stays valid across steps.
 template <typename R>
-void launch_tsmooth(Ctx* c, const GridD& g, const R* coef, bool fine, const double* dtp, int comp, const R* xcur,
-                    R* xnext, const R* b);
+void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, const R* xcur, R* xnext,
+                    const R* b);
 template <typename R>
-void launch_trb3(Ctx* c, const GridD& g, const R* coef, bool fine, const double* dtp, int comp, int colour, R* x,
-                 const R* b);
+void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b);
 template <typename R>
-void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const R* coef, bool fine, const double* dtp,
+void launch_tresid_restr(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, const R* coef, bool fine,
                          const R* x, const R* b, R* bc, R* xc);
-// FP64 finest-level residual r = b - A x (max-norm into slot) or y = A x (b null)
-void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, const double* x,
-                   const double* b, double* out, int slot);
+// FP64 finest-level residual r = b - A x (max-norm into each cavity's slot)
+// or y = A x (b null)
+void launch_tresid(Ctx* c, const Level& L, const BV& v, const double* coef, const double* x, const double* b, double* out,
+                   int slot);
 
-// scalar cell problem (MAC) and nodal problem, transfers, coarsest solve
-// (hb_mg.hip, hb_nodal.hip)
-template <typename R> void launch_mac_rb(Ctx* c, const GridD& g, int colour, R* x, const R* b);
+// ---- scalar cell problem (MAC), nodal problem, transfers, coarsest ----------
+// (hb_mg.hip, hb_nodal.hip), batched
+template <typename R> void launch_mac_rb(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b);
+// one thread per coarse cell: vc covers the coarse level, gf / of_ give the
+// fine grid and offsets of the same cavities
 template <typename R>
-void launch_mac_resid_restrict(Ctx* c, const GridD& gf, const GridD& gc, const R* xf, const R* bf, R* bc, R* xc);
-void launch_mac_resid(Ctx* c, const GridD& g, const double* x, const double* b, double* r, int slot);
-void launch_mac_apply(Ctx* c, const GridD& g, const double* x, double* y);
-void launch_mac_dense(Ctx* c, const Level& l, int N, double* E, double* A);
+void launch_mac_resid_restrict(Ctx* c, const Level& C, const BV& vc, const GridD* gf, const long* of_, const R* xf,
+                               const R* bf, R* bc, R* xc);
+// FP64 r = b - L x (max-norm into each cavity's slot) or y = L x (b null)
+void launch_mac_resid(Ctx* c, const Level& L, const BV& v, const double* x, const double* b, double* r, int slot);
+void launch_mac_dense(Ctx* c, const GridD& g, int N, const double* E, double* A);
 template <typename R>
-void launch_prolong_cells(Ctx* c, const GridD& gf, const GridD& gc, int ncomp, double wall_sign, const R* e, R* x);
-template <typename R> void launch_nodal_gs(Ctx* c, const GridD& g, int colour, R* x, const R* b);
-// r = b - K x (slot >= 0: FP64 only, max-norm into the slot) or y = K x (b null)
-template <typename R> void launch_nodal_resid(Ctx* c, const GridD& g, const R* x, const R* b, R* r, int slot);
-template <typename R> void launch_nodal_restrict(Ctx* c, const GridD& gf, const GridD& gc, const R* rf, R* bc, R* xc);
-template <typename R> void launch_nodal_prolong(Ctx* c, const GridD& gf, const GridD& gc, const R* e, R* x);
-void launch_nodal_dense(Ctx* c, const Level& l, int N, double* E, double* A);
+void launch_prolong_cells(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, int ncomp,
+                          double wall_sign, const R* e, R* x);
+template <typename R> void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b);
+// r = b - K x (slot >= 0: FP64 only, max-norm into each cavity's slot) or y = K x (b null)
+template <typename R>
+void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R* b, R* r, int slot);
+template <typename R>
+void launch_nodal_restrict(Ctx* c, const Level& C, const BV& vc, const GridD* gf, const long* of_, const R* rf, R* bc,
+                           R* xc);
+template <typename R>
+void launch_nodal_prolong(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, const R* e, R* x);
+void launch_nodal_dense(Ctx* c, const GridD& g, int N, const double* E, double* A);
 void launch_add_ones(Ctx* c, int N, double* A);
 void launch_lu_factor(Ctx* c, int N, double* A, int* piv);
 void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* Ainv);
-// x = A^{-1} b on the coarsest level, accumulated in FP64
-template <typename R> void launch_coarse_solve(Ctx* c, int N, const double* Ainv, const R* b, R* x);
+// x = A^{-1} b for the cavities whose coarsest level is lev (FP64 accumulation)
+template <typename R>
+void launch_coarse_solve(Ctx* c, const MG& m, int lev, const int* act, const R* b, R* x);
+void launch_identity(Ctx* c, int N, double* E);
 
-// precision conversions of the mixed-precision cycles (hb_reduce.hip)
-void to_f32(Ctx* c, const double* src, float* dst, float* zero, long n);   // dst = src, zero = 0 (nullable)
-void add_f32(Ctx* c, double* x, const float* e, long n);                   // x += e
-void from_f32(Ctx* c, const float* e, double* x, long n);                  // x = e
-
-// step stages (hb_step.hip)
-void launch_grad_node(Ctx* c, const double* p, double* Gp);
-void launch_forcing(Ctx* c);
-void launch_slopes(Ctx* c, const double* u);
-void launch_trace_normal(Ctx* c, const double* u, double dt);
-void launch_transverse(Ctx* c);
-void launch_trace_full(Ctx* c, const double* u, double dt);
-void launch_mac_div(Ctx* c, const double* faces, double* out);
-void launch_mac_update(Ctx* c);
-void launch_advect_rhs(Ctx* c, const double* u, double dt, double* b, double* conv);
-void launch_proj_rhs(Ctx* c, const double* ustar, double dt, double* r);
-void launch_weak_div(Ctx* c, const double* V, double* r);
-void launch_proj_update(Ctx* c, const double* ustar, const double* phi, double dt, double* u);
+// ---- step stages, per cavity (hb_step.hip) ----------------------------------
+void launch_grad_node(Ctx* c, const Cav& v, const double* p, double* Gp);
+void launch_forcing(Ctx* c, const Cav& v);
+void launch_slopes(Ctx* c, const Cav& v, const double* u);
+void launch_trace_normal(Ctx* c, const Cav& v, const double* u, double dt);
+void launch_transverse(Ctx* c, const Cav& v);
+void launch_trace_full(Ctx* c, const Cav& v, const double* u, double dt);
+void launch_mac_div(Ctx* c, const Cav& v, const double* faces, double* out);
+void launch_mac_update(Ctx* c, const Cav& v);
+void launch_advect_rhs(Ctx* c, const Cav& v, const double* u, double dt, double* b, double* conv);
+void launch_proj_rhs(Ctx* c, const Cav& v, const double* ustar, double dt, double* r);
+void launch_weak_div(Ctx* c, const Cav& v, const double* V, double* r);
+void launch_proj_update(Ctx* c, const Cav& v, const double* ustar, const double* phi, double dt, double* u);
 
 }  // namespace hb

@@ -14,14 +14,24 @@ static const dim3 kBlk(64, 4, 1);
 // MAC problem: L_mac = D_mac G_mac, zero flux through wall faces
 // ---------------------------------------------------------------------------
 
+// Batched launches: block z = cavity * zb + z index within the cavity; each
+// block takes its cavity's grid and offsets from the level tables (see
+// hb_internal.h) and returns when the cavity takes no part.
+#define PT_ENTER(k)                                \
+    int cav, k;                                    \
+    GridD g;                                       \
+    if (!bv_enter(v, cav, k, g)) return;
+
 template <typename R>
-__global__ void k_mac_rb(GridD g, int colour, R* __restrict__ x, const R* __restrict__ b)
+__global__ void k_mac_rb(BV v, int colour, R* __restrict__ xa, const R* __restrict__ ba)
 {
+    PT_ENTER(k);
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
     const int i = 2 * t + ((j + k + colour) & 1);
-    if (i >= g.n[0] || j >= g.n[1]) return;
+    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return;
+    R* x = xa + v.o[cav];
+    const R* b = ba + v.o[cav];
     const long q = cid(g, i, j, k);
     const R h = (R)g.h;
     const R ih2 = R(1) / (h * h);
@@ -40,73 +50,81 @@ __global__ void k_mac_rb(GridD g, int colour, R* __restrict__ x, const R* __rest
 }
 
 template <typename R>
-void launch_mac_rb(Ctx* c, const GridD& g, int colour, R* x, const R* b)
+void launch_mac_rb(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b)
 {
-    k_mac_rb<R><<<grid3((g.n[0] + 1) / 2, g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, colour, x, b);
+    BV vv = v;
+    vv.zb = L.gmax.n[2];
+    k_mac_rb<R><<<grid3((L.gmax.n[0] + 1) / 2, L.gmax.n[1], vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, colour, x, b);
 }
 
-__global__ void k_mac_resid(GridD g, const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
-                            double* __restrict__ mx)
+// r = b - L x (max-norm into each cavity's slot) or y = L x (b null); FP64
+__global__ void k_mac_resid(BV v, const double* __restrict__ xa, const double* __restrict__ ba, double* __restrict__ ra,
+                            double* __restrict__ scb, int slot)
 {
     __shared__ unsigned long long sh[16];
+    PT_ENTER(k);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
+    const long o = v.o[cav];
     unsigned long long m = 0ull;
-    if (i < g.n[0] && j < g.n[1]) {
+    if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
         const long q = cid(g, i, j, k);
-        const double rv = b[q] - mac_lap_at<double>(g, x, i, j, k);
-        if (r) r[q] = rv;
-        m = abits(rv);
+        const double Lx = mac_lap_at<double>(g, xa + o, i, j, k);
+        if (ba) {
+            const double rv = ba[o + q] - Lx;
+            if (ra) ra[o + q] = rv;
+            m = abits(rv);
+        } else {
+            ra[o + q] = Lx;
+        }
     }
-    if (mx) {
+    if (slot >= 0) {
         m = block_umax(m, sh);
-        if (threadIdx.x + threadIdx.y == 0) atomic_max_bits(mx, m);
+        if (threadIdx.x + threadIdx.y == 0) atomic_max_bits(scb + (long)cav * S_NSLOT + slot, m);
     }
 }
 
-void launch_mac_resid(Ctx* c, const GridD& g, const double* x, const double* b, double* r, int slot)
+void launch_mac_resid(Ctx* c, const Level& L, const BV& v, const double* x, const double* b, double* r, int slot)
 {
-    k_mac_resid<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, x, b, r, slot >= 0 ? c->sc + slot : nullptr);
+    BV vv = v;
+    vv.zb = L.gmax.n[2];
+    k_mac_resid<<<grid3(L.gmax.n[0], L.gmax.n[1], vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, x, b, r, c->sc, slot);
 }
 
-__global__ void k_mac_apply(GridD g, const double* __restrict__ x, double* __restrict__ y)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    y[cid(g, i, j, k)] = mac_lap_at<double>(g, x, i, j, k);
-}
-
-void launch_mac_apply(Ctx* c, const GridD& g, const double* x, double* y)
-{
-    k_mac_apply<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, x, y);
-}
-
+// coarse right-hand side = mean of the fine residuals of the 2^d children;
+// the coarse iterate starts from zero.  One thread per coarse cell.
 template <typename R>
-__global__ void k_mac_resid_restrict(GridD gf, GridD gc, const R* __restrict__ xf, const R* __restrict__ bf,
-                                     R* __restrict__ bc, R* __restrict__ xc)
+__global__ void k_mac_resid_restrict(BV v, const GridD* __restrict__ gft, const long* __restrict__ oft,
+                                     const R* __restrict__ xfa, const R* __restrict__ bfa, R* __restrict__ bca,
+                                     R* __restrict__ xca)
 {
+    PT_ENTER(k);
+    const GridD& gc = g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= gc.n[0] || j >= gc.n[1]) return;
+    if (i >= gc.n[0] || j >= gc.n[1] || k >= gc.n[2]) return;
+    const GridD gf = gft[cav];
+    const R* xf = xfa + oft[cav];
+    const R* bf = bfa + oft[cav];
     const int nch = 1 << gf.dim;
     R s = 0;
     for (int bits = 0; bits < nch; ++bits) {
         const int fi = 2 * i + (bits & 1), fj = 2 * j + ((bits >> 1) & 1), fk = gf.dim == 3 ? 2 * k + ((bits >> 2) & 1) : 0;
         s += bf[cid(gf, fi, fj, fk)] - mac_lap_at<R>(gf, xf, fi, fj, fk);
     }
-    const long qc = cid(gc, i, j, k);
-    bc[qc] = s / (R)nch;
-    xc[qc] = R(0);
+    const long qc = v.o[cav] + cid(gc, i, j, k);
+    bca[qc] = s / (R)nch;
+    xca[qc] = R(0);
 }
 
 template <typename R>
-void launch_mac_resid_restrict(Ctx* c, const GridD& gf, const GridD& gc, const R* xf, const R* bf, R* bc, R* xc)
+void launch_mac_resid_restrict(Ctx* c, const Level& C, const BV& vc, const GridD* gf, const long* of_, const R* xf,
+                               const R* bf, R* bc, R* xc)
 {
-    k_mac_resid_restrict<R><<<grid3(gc.n[0], gc.n[1], gc.n[2], kBlk), kBlk, 0, c->s>>>(gf, gc, xf, bf, bc, xc);
+    BV vv = vc;
+    vv.zb = C.gmax.n[2];
+    k_mac_resid_restrict<R><<<grid3(C.gmax.n[0], C.gmax.n[1], vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gf, of_, xf, bf,
+                                                                                                    bc, xc);
 }
 
 __global__ void k_mac_dense(GridD g, int N, const double* __restrict__ E, double* __restrict__ A)
@@ -118,23 +136,29 @@ __global__ void k_mac_dense(GridD g, int N, const double* __restrict__ E, double
     A[(long)row * N + col] = mac_lap_at<double>(g, E + (long)col * N, i, j, k);
 }
 
-void launch_mac_dense(Ctx* c, const Level& l, int N, double* E, double* A)
+void launch_mac_dense(Ctx* c, const GridD& g, int N, const double* E, double* A)
 {
-    k_mac_dense<<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, N, E, A);
+    k_mac_dense<<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(g, N, E, A);
 }
 
 // ---------------------------------------------------------------------------
 // cell prolongation x_f += P e_c: (bi/tri)linear, 3/4 - 1/4 per axis; a coarse
-// neighbour beyond a wall takes the homogeneous ghost value wall_sign * e
+// neighbour beyond a wall takes the homogeneous ghost value wall_sign * e.
+// One thread per fine cell.
 // ---------------------------------------------------------------------------
 
 template <typename R>
-__global__ void k_prolong_cells(GridD gf, GridD gc, int ncomp, R wall_sign, const R* __restrict__ e, R* __restrict__ x)
+__global__ void k_prolong_cells(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct, int ncomp,
+                                R wall_sign, const R* __restrict__ ea, R* __restrict__ xa)
 {
+    PT_ENTER(k);
+    const GridD& gf = g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= gf.n[0] || j >= gf.n[1]) return;
+    if (i >= gf.n[0] || j >= gf.n[1] || k >= gf.n[2]) return;
+    const GridD gc = gct[cav];
+    const R* e = ea + ncomp * oct[cav];
+    R* x = xa + ncomp * v.o[cav];
     const int d = gf.dim;
     const int fi[3] = {i, j, k};
     const long Nf = ncells(gf), Nc = ncells(gc);
@@ -161,23 +185,32 @@ __global__ void k_prolong_cells(GridD gf, GridD gc, int ncomp, R wall_sign, cons
 }
 
 template <typename R>
-void launch_prolong_cells(Ctx* c, const GridD& gf, const GridD& gc, int ncomp, double wall_sign, const R* e, R* x)
+void launch_prolong_cells(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, int ncomp,
+                          double wall_sign, const R* e, R* x)
 {
-    k_prolong_cells<R><<<grid3(gf.n[0], gf.n[1], gf.n[2], kBlk), kBlk, 0, c->s>>>(gf, gc, ncomp, (R)wall_sign, e, x);
+    BV vv = v;
+    vv.zb = L.gmax.n[2];
+    k_prolong_cells<R><<<grid3(L.gmax.n[0], L.gmax.n[1], vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gc, oc, ncomp,
+                                                                                               (R)wall_sign, e, x);
 }
 
 // ---------------------------------------------------------------------------
 // nodal problem: Q1 stiffness K (natural boundary on walls)
 // ---------------------------------------------------------------------------
 
-// full weighting R = P^T from the fine residual r_f; coarse iterate zeroed
+// full weighting R = P^T from the fine residual r_f; coarse iterate zeroed.
+// One thread per coarse node.
 template <typename R>
-__global__ void k_nodal_restrict(GridD gf, GridD gc, const R* __restrict__ rf, R* __restrict__ bc, R* __restrict__ xc)
+__global__ void k_nodal_restrict(BV v, const GridD* __restrict__ gft, const long* __restrict__ oft,
+                                 const R* __restrict__ rfa, R* __restrict__ bca, R* __restrict__ xca)
 {
+    PT_ENTER(k);
+    const GridD& gc = g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= nnode(gc, 0) || j >= nnode(gc, 1)) return;
+    if (i >= nnode(gc, 0) || j >= nnode(gc, 1) || k >= nnode(gc, 2)) return;
+    const GridD gf = gft[cav];
+    const R* rf = rfa + oft[cav];
     const int d = gf.dim;
     const int I[3] = {i, j, k};
     int nt = 1;
@@ -201,25 +234,33 @@ __global__ void k_nodal_restrict(GridD gf, GridD gc, const R* __restrict__ rf, R
         }
         if (ok) s += w * rf[nid(gf, p[0], p[1], p[2])];
     }
-    const long q = nid(gc, i, j, k);
-    bc[q] = s;
-    xc[q] = R(0);
+    const long q = v.o[cav] + nid(gc, i, j, k);
+    bca[q] = s;
+    xca[q] = R(0);
 }
 
 template <typename R>
-void launch_nodal_restrict(Ctx* c, const GridD& gf, const GridD& gc, const R* rf, R* bc, R* xc)
+void launch_nodal_restrict(Ctx* c, const Level& C, const BV& vc, const GridD* gf, const long* of_, const R* rf, R* bc,
+                           R* xc)
 {
-    k_nodal_restrict<R><<<grid3(nnode(gc, 0), nnode(gc, 1), nnode(gc, 2), kBlk), kBlk, 0, c->s>>>(gf, gc, rf, bc, xc);
+    BV vv = vc;
+    vv.zb = nnode(C.gmax, 2);
+    k_nodal_restrict<R><<<grid3(nnode(C.gmax, 0), nnode(C.gmax, 1), vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gf, of_,
+                                                                                                          rf, bc, xc);
 }
 
-// (bi/tri)linear nodal prolongation x_f += P e_c
+// (bi/tri)linear nodal prolongation x_f += P e_c; one thread per fine node
 template <typename R>
-__global__ void k_nodal_prolong(GridD gf, GridD gc, const R* __restrict__ e, R* __restrict__ x)
+__global__ void k_nodal_prolong(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct,
+                                const R* __restrict__ ea, R* __restrict__ xa)
 {
+    PT_ENTER(k);
+    const GridD& gf = g;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= nnode(gf, 0) || j >= nnode(gf, 1)) return;
+    if (i >= nnode(gf, 0) || j >= nnode(gf, 1) || k >= nnode(gf, 2)) return;
+    const GridD gc = gct[cav];
+    const R* e = ea + oct[cav];
     const int d = gf.dim;
     const int F[3] = {i, j, k};
     R s = 0;
@@ -241,13 +282,16 @@ __global__ void k_nodal_prolong(GridD gf, GridD gc, const R* __restrict__ e, R* 
         }
         if (ok) s += w * e[nid(gc, p[0], p[1], p[2])];
     }
-    x[nid(gf, i, j, k)] += s;
+    xa[v.o[cav] + nid(gf, i, j, k)] += s;
 }
 
 template <typename R>
-void launch_nodal_prolong(Ctx* c, const GridD& gf, const GridD& gc, const R* e, R* x)
+void launch_nodal_prolong(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, const R* e, R* x)
 {
-    k_nodal_prolong<R><<<grid3(nnode(gf, 0), nnode(gf, 1), nnode(gf, 2), kBlk), kBlk, 0, c->s>>>(gf, gc, e, x);
+    BV vv = v;
+    vv.zb = nnode(L.gmax, 2);
+    k_nodal_prolong<R><<<grid3(nnode(L.gmax, 0), nnode(L.gmax, 1), vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gc, oc, e,
+                                                                                                         x);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,31 +384,54 @@ void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* 
     k_lu_inverse<<<(N + 63) / 64, 64, 0, c->s>>>(N, LU, piv, Ainv);
 }
 
-// x = A^{-1} b, one row per thread, accumulated in FP64
+// x = A^{-1} b for the cavities whose coarsest level is lev; one row per
+// thread (block y = cavity), accumulated in FP64
 template <typename R>
-__global__ void k_coarse_solve(int N, const double* __restrict__ Ainv, const R* __restrict__ b, R* __restrict__ x)
+__global__ void k_coarse_solve(const CoarseD* __restrict__ cs, int lev, const int* __restrict__ act,
+                               const double* __restrict__ Ainv, const R* __restrict__ b, R* __restrict__ x)
 {
+    const int cav = blockIdx.y;
+    if (act && !act[cav]) return;
+    const CoarseD d = cs[cav];
+    if (d.lev != lev) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const double* row = Ainv + (long)i * N;
+    if (i >= d.N) return;
+    const double* row = Ainv + d.aoff + (long)i * d.N;
+    const R* bb = b + d.xoff;
     double s = 0.0;
-    for (int jj = 0; jj < N; ++jj) s += row[jj] * (double)b[jj];
-    x[i] = (R)s;
+    for (int jj = 0; jj < d.N; ++jj) s += row[jj] * (double)bb[jj];
+    x[d.xoff + i] = (R)s;
 }
 
 template <typename R>
-void launch_coarse_solve(Ctx* c, int N, const double* Ainv, const R* b, R* x)
+void launch_coarse_solve(Ctx* c, const MG& m, int lev, const int* act, const R* b, R* x)
 {
-    k_coarse_solve<R><<<(N + 255) / 256, 256, 0, c->s>>>(N, Ainv, b, x);
+    k_coarse_solve<R><<<dim3((m.ncmax + 255) / 256, c->nb), 256, 0, c->s>>>(m.cs, lev, act, m.Ainv, b, x);
 }
 
-#define HB_MG_INST(R)                                                                                     \
-    template void launch_mac_rb<R>(Ctx*, const GridD&, int, R*, const R*);                                \
-    template void launch_mac_resid_restrict<R>(Ctx*, const GridD&, const GridD&, const R*, const R*, R*, R*); \
-    template void launch_prolong_cells<R>(Ctx*, const GridD&, const GridD&, int, double, const R*, R*);   \
-    template void launch_nodal_restrict<R>(Ctx*, const GridD&, const GridD&, const R*, R*, R*);           \
-    template void launch_nodal_prolong<R>(Ctx*, const GridD&, const GridD&, const R*, R*);                \
-    template void launch_coarse_solve<R>(Ctx*, int, const double*, const R*, R*);
+__global__ void k_identity(int N, double* E)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)N * N) return;
+    E[t] = (t / N == t % N) ? 1.0 : 0.0;
+}
+
+void launch_identity(Ctx* c, int N, double* E)
+{
+    const long nn = (long)N * N;
+    k_identity<<<(unsigned)((nn + 255) / 256), 256, 0, c->s>>>(N, E);
+}
+
+#define HB_MG_INST(R)                                                                                          \
+    template void launch_mac_rb<R>(Ctx*, const Level&, const BV&, int, R*, const R*);                          \
+    template void launch_mac_resid_restrict<R>(Ctx*, const Level&, const BV&, const GridD*, const long*,       \
+                                               const R*, const R*, R*, R*);                                    \
+    template void launch_prolong_cells<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, int, double, \
+                                          const R*, R*);                                                       \
+    template void launch_nodal_restrict<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, \
+                                           R*, R*);                                                            \
+    template void launch_nodal_prolong<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, R*); \
+    template void launch_coarse_solve<R>(Ctx*, const MG&, int, const int*, const R*, R*);
 HB_MG_INST(double)
 HB_MG_INST(float)
 #undef HB_MG_INST

@@ -75,15 +75,28 @@ __device__ inline void fill_nodes(const GridD& g, const R* __restrict__ x, R* s,
     }
 }
 
+// Batched launches: block z = cavity * zb + z-tile; each block takes its
+// cavity's grid and node offset from the level tables and returns when the
+// cavity takes no part or the tile lies outside it.
+#define NTILE_ENTER(DIM, T)                                                                 \
+    int cav, bz;                                                                            \
+    GridD g;                                                                                \
+    if (!bv_enter(v, cav, bz, g)) return;                                                   \
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = DIM == 3 ? bz * T::TZ : 0; \
+    if (ox >= nnode(g, 0) || oy >= nnode(g, 1) || oz >= nnode(g, 2)) return;                \
+    const long node0 = v.o[cav];
+
 // one colour (i&1) + 2(j&1) + 4(k&1) of the Gauss-Seidel sweep, in place:
 // nodes of one colour share no element
 template <int DIM, typename R>
 __global__ void __launch_bounds__(NTile<DIM>::THREADS)
-k_nodal_gs_tile(GridD g, int colour, R* __restrict__ x, const R* __restrict__ b)
+k_nodal_gs_tile(BV v, int colour, R* __restrict__ xa, const R* __restrict__ ba)
 {
     using T = NTile<DIM>;
     __shared__ R s[T::NS];
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    NTILE_ENTER(DIM, T);
+    R* x = xa + node0;
+    const R* b = ba + node0;
     fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
     __syncthreads();
     const int tx = threadIdx.x % NodalCfg<DIM>::BX, ty = (threadIdx.x / NodalCfg<DIM>::BX) % NodalCfg<DIM>::BY,
@@ -98,16 +111,19 @@ k_nodal_gs_tile(GridD g, int colour, R* __restrict__ x, const R* __restrict__ b)
     x[q] = s[l] + (b[q] - Kx) / dg;
 }
 
-// r = b - K x (and, FP64, its max-norm) or y = K x over all nodes
+// r = b - K x (and, FP64, its max-norm into the cavity's slot) or y = K x
 template <int DIM, typename R>
 __global__ void __launch_bounds__(NTile<DIM>::THREADS)
-k_nodal_resid_tile(GridD g, const R* __restrict__ x, const R* __restrict__ b, R* __restrict__ out,
-                   double* __restrict__ mx)
+k_nodal_resid_tile(BV v, const R* __restrict__ xa, const R* __restrict__ ba, R* __restrict__ outa,
+                   double* __restrict__ scb, int slot)
 {
     using T = NTile<DIM>;
     __shared__ R s[T::NS];
     __shared__ unsigned long long red[16];
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
+    NTILE_ENTER(DIM, T);
+    const R* x = xa + node0;
+    const R* b = ba ? ba + node0 : nullptr;
+    R* out = outa ? outa + node0 : nullptr;
     fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
     __syncthreads();
     unsigned long long m = 0ull;
@@ -127,39 +143,51 @@ k_nodal_resid_tile(GridD g, const R* __restrict__ x, const R* __restrict__ b, R*
             out[q] = Kx;
         }
     }
-    if (mx) {
+    if (slot >= 0) {
         m = block_umax(m, red);
-        if (threadIdx.x == 0) atomic_max_bits(mx, m);
+        if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav * S_NSLOT + slot, m);
     }
 }
 
 template <int DIM>
-static dim3 ntile_grid(const GridD& g)
+static dim3 ntile_grid(const Ctx* c, const Level& L, BV& v)
 {
     using T = NTile<DIM>;
-    return dim3((nnode(g, 0) + T::TX - 1) / T::TX, (nnode(g, 1) + T::TY - 1) / T::TY,
-                DIM == 3 ? (nnode(g, 2) + T::TZ - 1) / T::TZ : 1);
+    const GridD& g = L.gmax;
+    v.zb = DIM == 3 ? (nnode(g, 2) + T::TZ - 1) / T::TZ : 1;
+    return dim3((nnode(g, 0) + T::TX - 1) / T::TX, (nnode(g, 1) + T::TY - 1) / T::TY, v.zb * c->nb);
 }
 
 template <typename R>
-void launch_nodal_gs(Ctx* c, const GridD& g, int colour, R* x, const R* b)
+void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b)
 {
-    if (g.dim == 2) k_nodal_gs_tile<2, R><<<ntile_grid<2>(g), NTile<2>::THREADS, 0, c->s>>>(g, colour, x, b);
-    else k_nodal_gs_tile<3, R><<<ntile_grid<3>(g), NTile<3>::THREADS, 0, c->s>>>(g, colour, x, b);
+    BV vv = v;
+    if (L.gmax.dim == 2) {
+        const dim3 grid = ntile_grid<2>(c, L, vv);
+        k_nodal_gs_tile<2, R><<<grid, NTile<2>::THREADS, 0, c->s>>>(vv, colour, x, b);
+    } else {
+        const dim3 grid = ntile_grid<3>(c, L, vv);
+        k_nodal_gs_tile<3, R><<<grid, NTile<3>::THREADS, 0, c->s>>>(vv, colour, x, b);
+    }
 }
 
 template <typename R>
-void launch_nodal_resid(Ctx* c, const GridD& g, const R* x, const R* b, R* r, int slot)
+void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R* b, R* r, int slot)
 {
-    double* mx = slot >= 0 ? c->sc + slot : nullptr;
-    if (g.dim == 2) k_nodal_resid_tile<2, R><<<ntile_grid<2>(g), NTile<2>::THREADS, 0, c->s>>>(g, x, b, r, mx);
-    else k_nodal_resid_tile<3, R><<<ntile_grid<3>(g), NTile<3>::THREADS, 0, c->s>>>(g, x, b, r, mx);
+    BV vv = v;
+    if (L.gmax.dim == 2) {
+        const dim3 grid = ntile_grid<2>(c, L, vv);
+        k_nodal_resid_tile<2, R><<<grid, NTile<2>::THREADS, 0, c->s>>>(vv, x, b, r, c->sc, slot);
+    } else {
+        const dim3 grid = ntile_grid<3>(c, L, vv);
+        k_nodal_resid_tile<3, R><<<grid, NTile<3>::THREADS, 0, c->s>>>(vv, x, b, r, c->sc, slot);
+    }
 }
 
-template void launch_nodal_gs<double>(Ctx*, const GridD&, int, double*, const double*);
-template void launch_nodal_gs<float>(Ctx*, const GridD&, int, float*, const float*);
-template void launch_nodal_resid<double>(Ctx*, const GridD&, const double*, const double*, double*, int);
-template void launch_nodal_resid<float>(Ctx*, const GridD&, const float*, const float*, float*, int);
+template void launch_nodal_gs<double>(Ctx*, const Level&, const BV&, int, double*, const double*);
+template void launch_nodal_gs<float>(Ctx*, const Level&, const BV&, int, float*, const float*);
+template void launch_nodal_resid<double>(Ctx*, const Level&, const BV&, const double*, const double*, double*, int);
+template void launch_nodal_resid<float>(Ctx*, const Level&, const BV&, const float*, const float*, float*, int);
 
 // dense coarsest matrix with the same assembled stencil (global reads)
 template <int DIM>
@@ -174,10 +202,10 @@ __global__ void k_nodal_dense(GridD g, int N, const double* __restrict__ E, doub
     A[(long)row * N + col] = acc;
 }
 
-void launch_nodal_dense(Ctx* c, const Level& l, int N, double* E, double* A)
+void launch_nodal_dense(Ctx* c, const GridD& g, int N, const double* E, double* A)
 {
-    if (l.g.dim == 2) k_nodal_dense<2><<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, N, E, A);
-    else k_nodal_dense<3><<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, N, E, A);
+    if (g.dim == 2) k_nodal_dense<2><<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(g, N, E, A);
+    else k_nodal_dense<3><<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(g, N, E, A);
 }
 
 }  // namespace hb

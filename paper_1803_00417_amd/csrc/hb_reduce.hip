@@ -1,16 +1,25 @@
-// hb_reduce.hip -- reductions and vector updates on the context's stream.
-// Sums use a fixed number of blocks and fixed tree orders, so every run
-// gives the same bits; max-norms are order independent.
+// hb_reduce.hip -- reductions and vector updates on the context's stream,
+// single-array and segmented over a batch of cavities (block y = cavity).
+// Sums use a fixed number of blocks per cavity and fixed tree orders, so
+// every run gives the same bits, and a cavity's sum does not depend on the
+// other cavities of the batch; max-norms are order independent.
 #include "hb_internal.h"
 
 namespace hb {
 
 static constexpr int kT = 256;
 
+static unsigned blocks_for(long n, long cap)
+{
+    const long nb = (n + kT - 1) / kT;
+    return (unsigned)(nb < 1 ? 1 : (nb < cap ? nb : cap));
+}
+
+// ---- single arrays ----------------------------------------------------------
+
 __global__ void k_set(double* p, double v) { *p = v; }
 
-void set_slot_zero(Ctx* c, int slot) { k_set<<<1, 1, 0, c->s>>>(c->sc + slot, 0.0); }
-void set_slot(Ctx* c, int slot, double v) { k_set<<<1, 1, 0, c->s>>>(c->sc + slot, v); }
+void set_slot(Ctx* c, int cav, int slot, double v) { k_set<<<1, 1, 0, c->s>>>(c->sc + (long)cav * S_NSLOT + slot, v); }
 
 __global__ void k_maxabs(const double* __restrict__ v, long n, double* __restrict__ out)
 {
@@ -24,62 +33,18 @@ __global__ void k_maxabs(const double* __restrict__ v, long n, double* __restric
     if (threadIdx.x == 0) atomic_max_bits(out, m);
 }
 
-void red_maxabs(Ctx* c, const double* v, long n, int slot, bool accumulate)
+void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot)
 {
-    if (!accumulate) set_slot_zero(c, slot);
+    double* out = c->sc + (long)cav * S_NSLOT + slot;
+    k_set<<<1, 1, 0, c->s>>>(out, 0.0);
     if (n <= 0) return;
-    const long nb = (n + kT - 1) / kT;
-    k_maxabs<<<(unsigned)(nb < kRedBlocks ? nb : kRedBlocks), kT, 0, c->s>>>(v, n, c->sc + slot);
+    k_maxabs<<<blocks_for(n, kRedBlocks), kT, 0, c->s>>>(v, n, out);
 }
-
-// partial sums of v (or of a*b): block b owns the fixed index set
-// {b*T + t + k*nblocks*T}
-__global__ void k_sum_partial(const double* __restrict__ a, const double* __restrict__ b, long n, double* __restrict__ part)
-{
-    __shared__ double sh[kT / 64];
-    double s = 0.0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        s += b ? a[i] * b[i] : a[i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-__global__ void k_sum_final(const double* __restrict__ part, int nb, double* __restrict__ out)
-{
-    __shared__ double sh[kT / 64];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) *out = s;
-}
-
-static void sum_impl(Ctx* c, const double* a, const double* b, long n, int slot)
-{
-    k_sum_partial<<<kRedBlocks, kT, 0, c->s>>>(a, b, n, c->partial);
-    k_sum_final<<<1, kT, 0, c->s>>>(c->partial, kRedBlocks, c->sc + slot);
-}
-
-void red_sum(Ctx* c, const double* v, long n, int slot) { sum_impl(c, v, nullptr, n, slot); }
-void red_dot(Ctx* c, const double* a, const double* b, long n, int slot) { sum_impl(c, a, b, n, slot); }
 
 void fetch_slots(Ctx* c)
 {
-    (void)hipMemcpyAsync(c->hsc, c->sc, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, c->s);
+    (void)hipMemcpyAsync(c->hsc, c->sc, sizeof(double) * S_NSLOT * c->nb, hipMemcpyDeviceToHost, c->s);
     (void)hipStreamSynchronize(c->s);
-}
-
-// v -= sum(v) / n, the sum taken from the slot (no host round trip)
-__global__ void k_sub_mean(double* __restrict__ v, long n, const double* __restrict__ sum)
-{
-    const double m = *sum / (double)n;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) v[i] -= m;
-}
-
-void sub_mean(Ctx* c, double* v, long n)
-{
-    red_sum(c, v, n, S_SUM);
-    const long nb = (n + kT - 1) / kT;
-    k_sub_mean<<<(unsigned)(nb < 4096 ? nb : 4096), kT, 0, c->s>>>(v, n, c->sc + S_SUM);
 }
 
 __global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, long n)
@@ -89,8 +54,7 @@ __global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, lon
 
 void copy(Ctx* c, double* dst, const double* src, long n)
 {
-    const long nb = (n + kT - 1) / kT;
-    k_copy<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(dst, src, n);
+    if (n > 0) k_copy<<<blocks_for(n, 8192), kT, 0, c->s>>>(dst, src, n);
 }
 
 __global__ void k_fill(double* __restrict__ d, double v, long n)
@@ -100,14 +64,206 @@ __global__ void k_fill(double* __restrict__ d, double v, long n)
 
 void fill(Ctx* c, double* dst, double v, long n)
 {
-    const long nb = (n + kT - 1) / kT;
-    k_fill<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(dst, v, n);
+    if (n > 0) k_fill<<<blocks_for(n, 8192), kT, 0, c->s>>>(dst, v, n);
 }
 
-// ---- BiCGStab updates, with the scalars read from device slots ------------
+// ---- segmented over the batch -------------------------------------------------
 
-__global__ void k_bicg_scalars(double* sc, int which)
+// this block's cavity segment; the block returns when the cavity is inactive
+#define SEG_ENTER(sv, off, n)                                  \
+    const int cav_ = blockIdx.y;                               \
+    if ((sv).act && !(sv).act[cav_]) return;                   \
+    const long off = (sv).off[cav_], n = (sv).n[cav_];
+
+#define SEG_LOOP(i, n) for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
+
+static long seg_longest(const MG& m)
 {
+    long mx = 0;
+    for (long v : m.L[0].hnu) mx = v > mx ? v : mx;
+    return mx;
+}
+
+// grid of a segmented launch: blocks per cavity sized for the longest
+// segment of any level-0 arena, at most cap blocks in total
+static dim3 seg_grid(const Ctx* c, long cap)
+{
+    long mx = seg_longest(c->visc);
+    const long a = seg_longest(c->mac), b = seg_longest(c->nodal);
+    if (a > mx) mx = a;
+    if (b > mx) mx = b;
+    long per = cap / c->nb;
+    if (per < 1) per = 1;
+    return dim3(blocks_for(mx, per), c->nb);
+}
+
+__global__ void k_seg_set(double* sc, int slot, int nb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) sc[(long)i * S_NSLOT + slot] = 0.0;
+}
+
+void seg_set_zero(Ctx* c, int slot) { k_seg_set<<<(c->nb + 63) / 64, 64, 0, c->s>>>(c->sc, slot, c->nb); }
+
+__global__ void k_seg_maxabs(SegV sv, const double* __restrict__ v, double* __restrict__ sc, int slot)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    SEG_ENTER(sv, off, n);
+    unsigned long long m = 0ull;
+    SEG_LOOP(i, n)
+    {
+        const unsigned long long b = abits(v[off + i]);
+        m = b > m ? b : m;
+    }
+    m = block_umax(m, sh);
+    if (threadIdx.x == 0) atomic_max_bits(sc + (long)cav_ * S_NSLOT + slot, m);
+}
+
+void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot)
+{
+    seg_set_zero(c, slot);
+    k_seg_maxabs<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, v, c->sc, slot);
+}
+
+// partial sums of a (or a*b) over the cavity's segment: block x of cavity y
+// owns the index set {x*T + t + k*kRedBlocks*T}
+__global__ void k_seg_sum_partial(SegV sv, const double* __restrict__ a, const double* __restrict__ b,
+                                  double* __restrict__ part)
+{
+    __shared__ double sh[kT / 64];
+    SEG_ENTER(sv, off, n);
+    double s = 0.0;
+    SEG_LOOP(i, n) s += b ? a[off + i] * b[off + i] : a[off + i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[(long)cav_ * kRedBlocks + blockIdx.x] = s;
+}
+
+__global__ void k_seg_sum_final(SegV sv, const double* __restrict__ part, double* __restrict__ sc, int slot)
+{
+    __shared__ double sh[kT / 64];
+    const int cav = blockIdx.x;
+    if (sv.act && !sv.act[cav]) return;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) s += part[(long)cav * kRedBlocks + i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) sc[(long)cav * S_NSLOT + slot] = s;
+}
+
+static void seg_sum_impl(Ctx* c, const SegV& s, const double* a, const double* b, int slot)
+{
+    k_seg_sum_partial<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, a, b, c->partial);
+    k_seg_sum_final<<<c->nb, kT, 0, c->s>>>(s, c->partial, c->sc, slot);
+}
+
+void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot) { seg_sum_impl(c, s, a, b, slot); }
+
+// v -= sum(v) / n per cavity, the sum taken from the slot
+__global__ void k_seg_sub_mean(SegV sv, double* __restrict__ v, const double* __restrict__ sc)
+{
+    SEG_ENTER(sv, off, n);
+    const double m = sc[(long)cav_ * S_NSLOT + S_SUM] / (double)n;
+    SEG_LOOP(i, n) v[off + i] -= m;
+}
+
+void seg_sub_mean(Ctx* c, const SegV& s, double* v)
+{
+    seg_sum_impl(c, s, v, nullptr, S_SUM);
+    k_seg_sub_mean<<<seg_grid(c, 4096L * c->nb), kT, 0, c->s>>>(s, v, c->sc);
+}
+
+__global__ void k_seg_copy(SegV sv, double* __restrict__ d, const double* __restrict__ s)
+{
+    SEG_ENTER(sv, off, n);
+    SEG_LOOP(i, n) d[off + i] = s[off + i];
+}
+
+void seg_copy(Ctx* c, const SegV& s, double* dst, const double* src)
+{
+    k_seg_copy<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, dst, src);
+}
+
+__global__ void k_seg_fill(SegV sv, double* __restrict__ d, double v)
+{
+    SEG_ENTER(sv, off, n);
+    SEG_LOOP(i, n) d[off + i] = v;
+}
+
+void seg_fill(Ctx* c, const SegV& s, double* dst, double v)
+{
+    k_seg_fill<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, dst, v);
+}
+
+// dst = (sel[cavity] ? src1 : src0) over each cavity's segment
+__global__ void k_seg_copy_sel(SegV sv, double* __restrict__ d, const double* __restrict__ s0,
+                               const double* __restrict__ s1, const int* __restrict__ sel)
+{
+    SEG_ENTER(sv, off, n);
+    const double* s = sel[cav_] ? s1 : s0;
+    SEG_LOOP(i, n) d[off + i] = s[off + i];
+}
+
+void seg_copy_sel(Ctx* c, const SegV& s, double* dst, const double* src0, const double* src1, const int* sel)
+{
+    k_seg_copy_sel<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, dst, src0, src1, sel);
+}
+
+// ---- precision conversions of the mixed-precision correction cycles ---------
+
+__global__ void k_seg_to_f32(SegV sv, const double* __restrict__ src, float* __restrict__ dst, float* __restrict__ zero)
+{
+    SEG_ENTER(sv, off, n);
+    SEG_LOOP(i, n)
+    {
+        dst[off + i] = (float)src[off + i];
+        if (zero) zero[off + i] = 0.0f;
+    }
+}
+
+void seg_to_f32(Ctx* c, const SegV& s, const double* src, float* dst, float* zero)
+{
+    k_seg_to_f32<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, src, dst, zero);
+}
+
+__global__ void k_seg_add_f32(SegV sv, double* __restrict__ x, const float* __restrict__ e)
+{
+    SEG_ENTER(sv, off, n);
+    SEG_LOOP(i, n) x[off + i] += (double)e[off + i];
+}
+
+void seg_add_f32(Ctx* c, const SegV& s, double* x, const float* e)
+{
+    k_seg_add_f32<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, x, e);
+}
+
+__global__ void k_seg_from_f32(SegV sv, const float* __restrict__ e, double* __restrict__ x)
+{
+    SEG_ENTER(sv, off, n);
+    SEG_LOOP(i, n) x[off + i] = (double)e[off + i];
+}
+
+void seg_from_f32(Ctx* c, const SegV& s, const float* e, double* x)
+{
+    k_seg_from_f32<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, e, x);
+}
+
+__global__ void k_flat_to_f32(const double* __restrict__ src, float* __restrict__ dst, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+void flat_to_f32(Ctx* c, const double* src, float* dst, long n)
+{
+    if (n > 0) k_flat_to_f32<<<blocks_for(n, 8192), kT, 0, c->s>>>(src, dst, n);
+}
+
+// ---- BiCGStab updates, with each cavity's scalars read from its slots -------
+
+__global__ void k_bicg_scalars(double* scb, int nb, const int* act, int which)
+{
+    const int cav = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cav >= nb || (act && !act[cav])) return;
+    double* sc = scb + (long)cav * S_NSLOT;
     if (which == 0) {            // initial values
         sc[S_RHOP] = 1.0;
         sc[S_ALPHA] = 1.0;
@@ -125,104 +281,72 @@ __global__ void k_bicg_scalars(double* sc, int which)
     }
 }
 
-void bicg_init_scalars(Ctx* c) { k_bicg_scalars<<<1, 1, 0, c->s>>>(c->sc, 0); }
-void bicg_beta(Ctx* c) { k_bicg_scalars<<<1, 1, 0, c->s>>>(c->sc, 1); }
-void bicg_alpha(Ctx* c) { k_bicg_scalars<<<1, 1, 0, c->s>>>(c->sc, 2); }
-void bicg_omega(Ctx* c) { k_bicg_scalars<<<1, 1, 0, c->s>>>(c->sc, 3); }
-
-__global__ void k_bicg_p_dev(double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
-                             const double* __restrict__ sc, long n)
+static void bicg_scalars(Ctx* c, const int* act, int which)
 {
+    k_bicg_scalars<<<(c->nb + 63) / 64, 64, 0, c->s>>>(c->sc, c->nb, act, which);
+}
+void bicg_init_scalars(Ctx* c, const int* act) { bicg_scalars(c, act, 0); }
+void bicg_beta(Ctx* c, const int* act) { bicg_scalars(c, act, 1); }
+void bicg_alpha(Ctx* c, const int* act) { bicg_scalars(c, act, 2); }
+void bicg_omega(Ctx* c, const int* act) { bicg_scalars(c, act, 3); }
+
+// p = r + beta (p - omega v)
+__global__ void k_bicg_p_dev(SegV sv, double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
+                             const double* __restrict__ scb)
+{
+    SEG_ENTER(sv, off, n);
+    const double* sc = scb + (long)cav_ * S_NSLOT;
     const double beta = sc[S_BETA], omega = sc[S_OMEGA];
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        p[i] = r[i] + beta * (p[i] - omega * v[i]);
+    SEG_LOOP(i, n) p[off + i] = r[off + i] + beta * (p[off + i] - omega * v[off + i]);
 }
 
-void bicg_p_dev(Ctx* c, double* p, const double* r, const double* v, long n)
+void bicg_p_dev(Ctx* c, const SegV& s, double* p, const double* r, const double* v)
 {
-    const long nb = (n + kT - 1) / kT;
-    k_bicg_p_dev<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(p, r, v, c->sc, n);
+    k_bicg_p_dev<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, p, r, v, c->sc);
 }
 
-__global__ void k_sub_scaled_max_dev(double* __restrict__ out, const double* __restrict__ a, const double* __restrict__ sp,
-                                     const double* __restrict__ b, long n, double* __restrict__ mx)
+// out = a - s b (s from a slot), with the max-norm of out into another slot
+__global__ void k_sub_scaled_max_dev(SegV sv, double* __restrict__ out, const double* __restrict__ a, int sslot,
+                                     const double* __restrict__ b, double* __restrict__ scb, int mslot)
 {
     __shared__ unsigned long long sh[kT / 64];
-    const double s = *sp;
+    SEG_ENTER(sv, off, n);
+    const double s = scb[(long)cav_ * S_NSLOT + sslot];
     unsigned long long m = 0ull;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double v = a[i] - s * b[i];
-        out[i] = v;
+    SEG_LOOP(i, n)
+    {
+        const double v = a[off + i] - s * b[off + i];
+        out[off + i] = v;
         const unsigned long long bb = abits(v);
         m = bb > m ? bb : m;
     }
     m = block_umax(m, sh);
-    if (threadIdx.x == 0) atomic_max_bits(mx, m);
+    if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav_ * S_NSLOT + mslot, m);
 }
 
-void sub_scaled_max_dev(Ctx* c, double* out, const double* a, int sslot, const double* b, long n, int mslot)
+void sub_scaled_max_dev(Ctx* c, const SegV& s, double* out, const double* a, int sslot, const double* b, int mslot)
 {
-    set_slot_zero(c, mslot);
-    const long nb = (n + kT - 1) / kT;
-    k_sub_scaled_max_dev<<<(unsigned)(nb < kRedBlocks ? nb : kRedBlocks), kT, 0, c->s>>>(out, a, c->sc + sslot, b, n,
-                                                                                           c->sc + mslot);
+    seg_set_zero(c, mslot);
+    k_sub_scaled_max_dev<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, a, sslot, b, c->sc, mslot);
 }
 
 // x += alpha ph + omega sh (with_omega), or x = alpha ph + x
-__global__ void k_bicg_x_dev(double* __restrict__ x, const double* __restrict__ ph, const double* __restrict__ sh_,
-                             const double* __restrict__ sc, int with_omega, long n)
+__global__ void k_bicg_x_dev(SegV sv, double* __restrict__ x, const double* __restrict__ ph,
+                             const double* __restrict__ sh_, const double* __restrict__ scb, int with_omega)
 {
+    SEG_ENTER(sv, off, n);
+    const double* sc = scb + (long)cav_ * S_NSLOT;
     const double alpha = sc[S_ALPHA], omega = sc[S_OMEGA];
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        if (with_omega) x[i] += alpha * ph[i] + omega * sh_[i];
-        else x[i] = alpha * ph[i] + 1.0 * x[i];
+    SEG_LOOP(i, n)
+    {
+        if (with_omega) x[off + i] += alpha * ph[off + i] + omega * sh_[off + i];
+        else x[off + i] = alpha * ph[off + i] + 1.0 * x[off + i];
     }
 }
 
-void bicg_x_dev(Ctx* c, double* x, const double* ph, const double* sh, bool with_omega, long n)
+void bicg_x_dev(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, bool with_omega)
 {
-    const long nb = (n + kT - 1) / kT;
-    k_bicg_x_dev<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(x, ph, sh, c->sc, with_omega ? 1 : 0, n);
-}
-
-// ---- precision conversions of the mixed-precision correction cycles ---------
-
-__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, float* __restrict__ zero, long n)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        dst[i] = (float)src[i];
-        if (zero) zero[i] = 0.0f;
-    }
-}
-
-void to_f32(Ctx* c, const double* src, float* dst, float* zero, long n)
-{
-    const long nb = (n + kT - 1) / kT;
-    k_to_f32<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(src, dst, zero, n);
-}
-
-__global__ void k_add_f32(double* __restrict__ x, const float* __restrict__ e, long n)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        x[i] += (double)e[i];
-}
-
-void add_f32(Ctx* c, double* x, const float* e, long n)
-{
-    const long nb = (n + kT - 1) / kT;
-    k_add_f32<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(x, e, n);
-}
-
-__global__ void k_from_f32(const float* __restrict__ e, double* __restrict__ x, long n)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        x[i] = (double)e[i];
-}
-
-void from_f32(Ctx* c, const float* e, double* x, long n)
-{
-    const long nb = (n + kT - 1) / kT;
-    k_from_f32<<<(unsigned)(nb < 8192 ? nb : 8192), kT, 0, c->s>>>(e, x, n);
+    k_bicg_x_dev<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, x, ph, sh, c->sc, with_omega ? 1 : 0);
 }
 
 }  // namespace hb

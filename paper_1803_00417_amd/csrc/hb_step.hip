@@ -83,9 +83,9 @@ __global__ void k_grad_node(GridD g, const double* __restrict__ p, double* __res
     for (int a = 0; a < g.dim; ++a) Gp[a * N + q] = grad_node_at(g, p, a, i, j, k);
 }
 
-void launch_grad_node(Ctx* c, const double* p, double* Gp)
+void launch_grad_node(Ctx* c, const Cav& v, const double* p, double* Gp)
 {
-    k_grad_node<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, p, Gp);
+    k_grad_node<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, p, Gp);
 }
 
 // F = -G p + 2E + f (the forcing of the Taylor prediction)
@@ -99,10 +99,10 @@ __global__ void k_forcing(long n, int dim, double f0, double f1, double f2, cons
     F[t] = -Gp[t] + 2.0 * E[t] + f;
 }
 
-void launch_forcing(Ctx* c)
+void launch_forcing(Ctx* c, const Cav& v)
 {
-    const long n = c->nc * c->dim;
-    k_forcing<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(c->nc, c->dim, c->fl.f[0], c->fl.f[1], c->fl.f[2], c->Gp, c->E, c->F);
+    const long n = v.nc * v.dim;
+    k_forcing<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(v.nc, v.dim, v.fl.f[0], v.fl.f[1], v.fl.f[2], v.Gp, v.E, v.F);
 }
 
 // ---------------------------------------------------------------------------
@@ -129,9 +129,9 @@ __global__ void k_slopes(GridD g, const double* __restrict__ u, double* __restri
         }
 }
 
-void launch_slopes(Ctx* c, const double* u)
+void launch_slopes(Ctx* c, const Cav& v, const double* u)
 {
-    k_slopes<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, u, c->S);
+    k_slopes<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, u, v.S);
 }
 
 // normal-only traced states on a-faces, upwinded by their Burgers solution
@@ -167,12 +167,12 @@ __global__ void k_trace_normal(GridD g, int a, double dt, double ulid, const dou
     for (int q = 0; q < d; ++q) qhat[q * nf + f] = (q == a) ? uh : upwind(uh, qL[q], qR[q], delta);
 }
 
-void launch_trace_normal(Ctx* c, const double* u, double dt)
+void launch_trace_normal(Ctx* c, const Cav& v, const double* u, double dt)
 {
-    const GridD& g = c->g;
+    const GridD& g = v.g;
     for (int a = 0; a < g.dim; ++a)
         k_trace_normal<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(
-            g, a, dt, c->ulid, c->sc, u, c->S, c->nf, c->uhat, c->qhat);
+            g, a, dt, v.ulid, v.sc, u, v.S, v.nf, v.uhat, v.qhat);
 }
 
 // transverse terms at cells: (u_b dq/dx_b)^ = mean face velocity x difference
@@ -199,9 +199,9 @@ __global__ void k_transverse(GridD g, long nf, const double* __restrict__ uhat, 
     }
 }
 
-void launch_transverse(Ctx* c)
+void launch_transverse(Ctx* c, const Cav& v)
 {
-    k_transverse<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, c->nf, c->uhat, c->qhat, c->trans);
+    k_transverse<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, v.nf, v.uhat, v.qhat, v.trans);
 }
 
 // full face states: traced normal part - dt/2 transverse terms + dt/2 forcing;
@@ -247,12 +247,12 @@ __global__ void k_trace_full(GridD g, int a, double dt, const double* __restrict
     uadv[f] = burgers(qLf[a * nf + f], qRf[a * nf + f]);
 }
 
-void launch_trace_full(Ctx* c, const double* u, double dt)
+void launch_trace_full(Ctx* c, const Cav& v, const double* u, double dt)
 {
-    const GridD& g = c->g;
+    const GridD& g = v.g;
     for (int a = 0; a < g.dim; ++a)
         k_trace_full<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(
-            g, a, dt, u, c->S, c->trans, c->F, c->nf, c->qLf, c->qRf, c->uadv);
+            g, a, dt, u, v.S, v.trans, v.F, v.nf, v.qLf, v.qRf, v.uadv);
 }
 
 // ---------------------------------------------------------------------------
@@ -276,9 +276,9 @@ __global__ void k_mac_div(GridD g, const double* __restrict__ F, double* __restr
     out[cid(g, i, j, k)] = s;
 }
 
-void launch_mac_div(Ctx* c, const double* faces, double* out)
+void launch_mac_div(Ctx* c, const Cav& v, const double* faces, double* out)
 {
-    k_mac_div<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, faces, out);
+    k_mac_div<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, faces, out);
 }
 
 // u^MAC = u^adv - G_mac phi (the gradient vanishes on wall faces)
@@ -297,11 +297,11 @@ __global__ void k_mac_update(GridD g, int a, const double* __restrict__ uadv, co
     umac[f] = uadv[f] - gphi;
 }
 
-void launch_mac_update(Ctx* c)
+void launch_mac_update(Ctx* c, const Cav& v)
 {
-    const GridD& g = c->g;
+    const GridD& g = v.g;
     for (int a = 0; a < g.dim; ++a)
-        k_mac_update<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(g, a, c->uadv, c->macphi, c->umac);
+        k_mac_update<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(g, a, v.uadv, v.macphi, v.umac);
 }
 
 // convective term A = sum_a mean(u^MAC_a) (q~_hi - q~_lo)/h with the full
@@ -341,10 +341,10 @@ __global__ void k_advect_rhs(GridD g, double dt, double ulid, double f0, double 
     }
 }
 
-void launch_advect_rhs(Ctx* c, const double* u, double dt, double* b, double* conv)
+void launch_advect_rhs(Ctx* c, const Cav& v, const double* u, double dt, double* b, double* conv)
 {
-    k_advect_rhs<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(
-        c->g, dt, c->ulid, c->fl.f[0], c->fl.f[1], c->fl.f[2], c->sc, u, c->umac, c->qLf, c->qRf, c->Gp, c->E, c->nf, b, conv);
+    k_advect_rhs<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(
+        v.g, dt, v.ulid, v.fl.f[0], v.fl.f[1], v.fl.f[2], v.sc, u, v.umac, v.qLf, v.qRf, v.Gp, v.E, v.nf, b, conv);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,15 +388,15 @@ __global__ void k_weak_div(GridD g, double dt, const double* __restrict__ V, con
     r[nid(g, i, j, k)] = s;
 }
 
-void launch_proj_rhs(Ctx* c, const double* ustar, double dt, double* r)
+void launch_proj_rhs(Ctx* c, const Cav& v, const double* ustar, double dt, double* r)
 {
-    const GridD& g = c->g;
-    k_weak_div<true><<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, dt, ustar, c->Gp, r);
+    const GridD& g = v.g;
+    k_weak_div<true><<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, dt, ustar, v.Gp, r);
 }
 
-void launch_weak_div(Ctx* c, const double* V, double* r)
+void launch_weak_div(Ctx* c, const Cav& v, const double* V, double* r)
 {
-    const GridD& g = c->g;
+    const GridD& g = v.g;
     k_weak_div<false><<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, 0.0, V, nullptr, r);
 }
 
@@ -415,9 +415,9 @@ __global__ void k_proj_update(GridD g, double dt, const double* __restrict__ ust
     }
 }
 
-void launch_proj_update(Ctx* c, const double* ustar, const double* phi, double dt, double* u)
+void launch_proj_update(Ctx* c, const Cav& v, const double* ustar, const double* phi, double dt, double* u)
 {
-    k_proj_update<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, dt, ustar, c->Gp, phi, u);
+    k_proj_update<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, dt, ustar, v.Gp, phi, u);
 }
 
 }  // namespace hb

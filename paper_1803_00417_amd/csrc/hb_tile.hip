@@ -244,13 +244,32 @@ __device__ inline bool colour_cell(const GridD& g, int t, int ring, int colour, 
 // dynamic LDS of the tile kernels, viewed as an array of R
 extern __shared__ __align__(16) unsigned char tile_lds[];
 
+// Batched launches: block z = cavity * zb + z-tile.  Each kernel finds its
+// cavity's grid and array offsets in the level's tables (the arenas hold the
+// cavities back to back, components of a cavity contiguous), returns when
+// the cavity takes no part or the tile lies outside it, and then runs the
+// single-grid body on that cavity's arrays.
+#define TILE_ENTER(DIM, T)                                                                  \
+    int cav, bz;                                                                            \
+    GridD g;                                                                                \
+    if (!bv_enter(v, cav, bz, g)) return;                                                   \
+    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = (DIM == 3) ? bz * T::TZ : 0; \
+    if (ox >= g.n[0] || oy >= g.n[1] || oz >= g.n[2]) return;                               \
+    const long cell0 = v.o[cav];
+
 template <int DIM, bool FINE, typename R>
 __global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
-k_tsmooth(GridD g, const R* __restrict__ coef, const double* __restrict__ dtp, int c, const R* __restrict__ xcur,
-          const R* xnext_in, R* xnext, const R* __restrict__ b)
+k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c, const R* __restrict__ xcura,
+          const R* xnext_ina, R* xnexta, const R* __restrict__ ba)
 {
-    const R dt = (R)*dtp;
     using T = Tile<DIM, 2>;
+    TILE_ENTER(DIM, T);
+    const R dt = (R)scb[(long)cav * S_NSLOT + S_DT];
+    const R* coef = FINE ? coefa + cell0 : coefa + v.of[cav];
+    const R* xcur = xcura + DIM * cell0;
+    const R* xnext_in = xnext_ina + DIM * cell0;
+    R* xnext = xnexta + DIM * cell0;
+    const R* b = ba + DIM * cell0;
     constexpr int TH = TileCfg<DIM>::THREADS;
     constexpr int RZ1 = DIM == 3 ? T::TZ + 2 : 1;
     constexpr int KR = ((T::TX + 2) / 2 * (T::TY + 2) * RZ1 + TH - 1) / TH;   // red slots per thread
@@ -258,7 +277,6 @@ k_tsmooth(GridD g, const R* __restrict__ coef, const double* __restrict__ dtp, i
     R* s = reinterpret_cast<R*>(tile_lds);
     R* e = s + DIM * T::NS;     // eta/Re tile (FINE)
     const long N = ncells(g);
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
     const R* bc = b + c * N;
     // this thread's cells of each colour, and their right-hand sides
     int rG[KR][3], rL[KR];
@@ -328,25 +346,29 @@ k_tsmooth(GridD g, const R* __restrict__ coef, const double* __restrict__ dtp, i
 // residual / operator application (FP64, halo 1) and residual + restriction
 // ---------------------------------------------------------------------------
 
-template <int DIM, bool FINE>
+template <int DIM>
 __global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
-k_tresid(GridD g, const double* __restrict__ coef, const double* __restrict__ dtp, const double* __restrict__ x,
-         const double* __restrict__ b, double* __restrict__ out, double* __restrict__ mx)
+k_tresid(BV v, const double* __restrict__ coefa, double* __restrict__ scb, const double* __restrict__ xa,
+         const double* __restrict__ ba, double* __restrict__ outa, int slot)
 {
-    const double dt = *dtp;
     using T = Tile<DIM, 1>;
+    __shared__ unsigned long long red[16];
+    TILE_ENTER(DIM, T);
+    const double dt = scb[(long)cav * S_NSLOT + S_DT];
+    const double* coef = coefa + cell0;
+    const double* x = xa + DIM * cell0;
+    const double* b = ba ? ba + DIM * cell0 : nullptr;
+    double* out = outa ? outa + DIM * cell0 : nullptr;
     double* s = reinterpret_cast<double*>(tile_lds);
     double* e = s + DIM * T::NS;
-    __shared__ unsigned long long red[16];
     const long N = ncells(g);
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
     {
         const double* q[DIM + 1];
         bool mir[DIM + 1];
         for (int a = 0; a < DIM; ++a) { q[a] = x + a * N; mir[a] = false; }
         q[DIM] = coef;
         mir[DIM] = true;
-        fill_batched<DIM, 1, DIM + (FINE ? 1 : 0), double>(g, q, mir, s, ox, oy, oz);
+        fill_batched<DIM, 1, DIM + 1, double>(g, q, mir, s, ox, oy, oz);
     }
     __syncthreads();
     unsigned long long m = 0ull;
@@ -358,7 +380,7 @@ k_tresid(GridD g, const double* __restrict__ coef, const double* __restrict__ dt
         const int wm = wall_mask<DIM>(g, G);
         const long q0 = cid(g, G[0], G[1], G[2]);
         for (int c = 0; c < DIM; ++c) {
-            const double vd = tile_visc_div<DIM, 1, FINE, double>(g, coef, s, e, c, G, wm, l, dt, nullptr);
+            const double vd = tile_visc_div<DIM, 1, true, double>(g, coef, s, e, c, G, wm, l, dt, nullptr);
             const double Ax = s[c * T::NS + l] - dt * vd;
             if (b) {
                 const double rv = b[c * N + q0] - Ax;
@@ -370,25 +392,32 @@ k_tresid(GridD g, const double* __restrict__ coef, const double* __restrict__ dt
             }
         }
     }
-    if (mx) {
+    if (slot >= 0) {
         m = block_umax(m, red);
-        if (threadIdx.x == 0) atomic_max_bits(mx, m);
+        if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav * S_NSLOT + slot, m);
     }
 }
 
 template <int DIM, bool FINE, typename R>
 __global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
-k_tresid_restr(GridD g, GridD gc, const R* __restrict__ coef, const double* __restrict__ dtp, const R* __restrict__ x,
-               const R* __restrict__ b, R* __restrict__ bcoarse, R* __restrict__ xcoarse)
+k_tresid_restr(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct, const R* __restrict__ coefa,
+               const double* __restrict__ scb, const R* __restrict__ xa, const R* __restrict__ ba,
+               R* __restrict__ bcoarsea, R* __restrict__ xcoarsea)
 {
-    const R dt = (R)*dtp;
     using T = Tile<DIM, 1>;
+    TILE_ENTER(DIM, T);
+    const R dt = (R)scb[(long)cav * S_NSLOT + S_DT];
+    const GridD gc = gct[cav];
+    const R* coef = FINE ? coefa + cell0 : coefa + v.of[cav];
+    const R* x = xa + DIM * cell0;
+    const R* b = ba + DIM * cell0;
+    R* bcoarse = bcoarsea + DIM * oct[cav];
+    R* xcoarse = xcoarsea + DIM * oct[cav];
     R* s = reinterpret_cast<R*>(tile_lds);
     R* e = s + DIM * T::NS;
     R* r = e + T::NS;   // residual of the tile, [c][tile cell]
     constexpr int NT = T::TX * T::TY * T::TZ;
     const long N = ncells(g), Nc = ncells(gc);
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
     {
         const R* q[DIM + 1];
         bool mir[DIM + 1];
@@ -442,16 +471,19 @@ k_tresid_restr(GridD g, GridD gc, const R* __restrict__ coef, const double* __re
 
 template <bool FINE, typename R>
 __global__ void __launch_bounds__(256)
-k_trb3(GridD g, const R* __restrict__ coef, const double* __restrict__ dtp, int c, int colour, R* x,
-       const R* __restrict__ b)
+k_trb3(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c, int colour, R* xa,
+       const R* __restrict__ ba)
 {
     using T = Tile<3, 1>;
     static_assert(T::TX * T::TY * T::TZ / 2 == 256, "one cell of the colour per thread");
+    TILE_ENTER(3, T);
+    const R dt = (R)scb[(long)cav * S_NSLOT + S_DT];
+    const R* coef = FINE ? coefa + cell0 : coefa + v.of[cav];
+    R* x = xa + 3 * cell0;
+    const R* b = ba + 3 * cell0;
     R* s = reinterpret_cast<R*>(tile_lds);
     R* e = s + 3 * T::NS;
-    const R dt = (R)*dtp;
     const long N = ncells(g);
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = blockIdx.z * T::TZ;
     // this thread's cell of the colour and its right-hand side
     const int t = threadIdx.x;
     const int px = t % (T::TX / 2), ry = (t / (T::TX / 2)) % T::TY, rz = t / (T::TX / 2 * T::TY);
@@ -478,118 +510,129 @@ k_trb3(GridD g, const R* __restrict__ coef, const double* __restrict__ dtp, int 
 // launchers
 // ---------------------------------------------------------------------------
 
+// tile grid over the largest cavity of the level, z-tiles times cavities
 template <int DIM>
-static dim3 tile_grid(const GridD& g)
+static dim3 tile_grid(const Ctx* c, const Level& L, BV& v)
 {
     using T = Tile<DIM, 1>;
-    return dim3((g.n[0] + T::TX - 1) / T::TX, (g.n[1] + T::TY - 1) / T::TY, DIM == 3 ? (g.n[2] + T::TZ - 1) / T::TZ : 1);
+    const GridD& g = L.gmax;
+    v.zb = DIM == 3 ? (g.n[2] + T::TZ - 1) / T::TZ : 1;
+    return dim3((g.n[0] + T::TX - 1) / T::TX, (g.n[1] + T::TY - 1) / T::TY, v.zb * c->nb);
+}
+
+static double level_cells(const Level& L)
+{
+    double n = 0.0;
+    for (const GridD& g : L.hg)
+        if (g.dim) n += (double)ncells(g);
+    return n;
+}
+
+static double level_faces(const Level& L)
+{
+    double n = 0.0;
+    for (const GridD& g : L.hg)
+        if (g.dim)
+            for (int a = 0; a < g.dim; ++a) n += (double)fcount(g, a);
+    return n;
 }
 
 template <int DIM, bool FINE, typename R>
-static void tsmooth_impl(Ctx* c, const GridD& g, const R* coef, const double* dtp, int comp, const R* xcur, R* xnext,
-                         const R* b)
+static void tsmooth_impl(Ctx* c, const Level& L, BV v, const R* coef, int comp, const R* xcur, R* xnext, const R* b)
 {
     const size_t lds = sizeof(R) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 2>::NS;
-    k_tsmooth<DIM, FINE, R><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, coef, dtp, comp, xcur, xnext,
-                                                                                     xnext, b);
+    const dim3 grid = tile_grid<DIM>(c, L, v);
+    k_tsmooth<DIM, FINE, R><<<grid, TileCfg<DIM>::THREADS, lds, c->s>>>(v, coef, c->sc, comp, xcur, xnext, xnext, b);
 }
 
 template <typename R>
-void launch_tsmooth(Ctx* c, const GridD& g, const R* coef, bool fine, const double* dtp, int comp, const R* xcur,
-                    R* xnext, const R* b)
+void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, const R* xcur, R* xnext,
+                    const R* b)
 {
     const bool timed = c->ktm.on && fine;
     if (timed) kt_begin(c);
-    if (g.dim == 2) {
-        if (fine) tsmooth_impl<2, true, R>(c, g, coef, dtp, comp, xcur, xnext, b);
-        else tsmooth_impl<2, false, R>(c, g, coef, dtp, comp, xcur, xnext, b);
+    if (L.gmax.dim == 2) {
+        if (fine) tsmooth_impl<2, true, R>(c, L, v, coef, comp, xcur, xnext, b);
+        else tsmooth_impl<2, false, R>(c, L, v, coef, comp, xcur, xnext, b);
     } else if (fine) {
-        tsmooth_impl<3, true, R>(c, g, coef, dtp, comp, xcur, xnext, b);
+        tsmooth_impl<3, true, R>(c, L, v, coef, comp, xcur, xnext, b);
     } else {
-        tsmooth_impl<3, false, R>(c, g, coef, dtp, comp, xcur, xnext, b);
+        tsmooth_impl<3, false, R>(c, L, v, coef, comp, xcur, xnext, b);
     }
     if (timed) {
         // algorithmic bytes of one fused red-black sweep of one component:
         // every component of x and the coefficients (eta/Re per cell on the
         // finest level, face viscosities below) read once, b_c read once, x_c
         // written once
-        const double N = (double)ncells(g);
-        double coefw = N;
-        if (!fine) {
-            coefw = 0.0;
-            for (int a = 0; a < g.dim; ++a) coefw += (double)fcount(g, a);
-        }
-        kt_end(c, sizeof(R) * (g.dim * N + coefw + 2.0 * N));
+        const double N = level_cells(L);
+        const double coefw = fine ? N : level_faces(L);
+        kt_end(c, sizeof(R) * (L.gmax.dim * N + coefw + 2.0 * N));
     }
 }
 
-template <int DIM, bool FINE>
-static void tresid_impl(Ctx* c, const GridD& g, const double* coef, const double* dtp, const double* x, const double* b,
-                        double* out, double* mx)
+template <int DIM>
+static void tresid_impl(Ctx* c, const Level& L, BV v, const double* coef, const double* x, const double* b, double* out,
+                        int slot)
 {
-    const size_t lds = sizeof(double) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 1>::NS;
-    k_tresid<DIM, FINE><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, coef, dtp, x, b, out, mx);
+    const size_t lds = sizeof(double) * (DIM + 1) * Tile<DIM, 1>::NS;
+    const dim3 grid = tile_grid<DIM>(c, L, v);
+    k_tresid<DIM><<<grid, TileCfg<DIM>::THREADS, lds, c->s>>>(v, coef, c->sc, x, b, out, slot);
 }
 
-void launch_tresid(Ctx* c, const GridD& g, const double* coef, bool fine, const double* dtp, const double* x,
-                   const double* b, double* out, int slot)
+void launch_tresid(Ctx* c, const Level& L, const BV& v, const double* coef, const double* x, const double* b, double* out,
+                   int slot)
 {
-    double* mx = slot >= 0 ? c->sc + slot : nullptr;
-    if (g.dim == 2) {
-        if (fine) tresid_impl<2, true>(c, g, coef, dtp, x, b, out, mx);
-        else tresid_impl<2, false>(c, g, coef, dtp, x, b, out, mx);
-    } else {
-        if (fine) tresid_impl<3, true>(c, g, coef, dtp, x, b, out, mx);
-        else tresid_impl<3, false>(c, g, coef, dtp, x, b, out, mx);
-    }
+    if (L.gmax.dim == 2) tresid_impl<2>(c, L, v, coef, x, b, out, slot);
+    else tresid_impl<3>(c, L, v, coef, x, b, out, slot);
 }
 
 template <int DIM, bool FINE, typename R>
-static void tresid_restr_impl(Ctx* c, const GridD& g, const GridD& gc, const R* coef, const double* dtp, const R* x,
+static void tresid_restr_impl(Ctx* c, const Level& L, BV v, const GridD* gc, const long* oc, const R* coef, const R* x,
                               const R* b, R* bc, R* xc)
 {
     using T = Tile<DIM, 1>;
     const size_t lds = sizeof(R) * (DIM * (T::NS + T::TX * T::TY * T::TZ) + T::NS);
-    k_tresid_restr<DIM, FINE, R><<<tile_grid<DIM>(g), TileCfg<DIM>::THREADS, lds, c->s>>>(g, gc, coef, dtp, x, b, bc, xc);
+    const dim3 grid = tile_grid<DIM>(c, L, v);
+    k_tresid_restr<DIM, FINE, R><<<grid, TileCfg<DIM>::THREADS, lds, c->s>>>(v, gc, oc, coef, c->sc, x, b, bc, xc);
 }
 
 template <typename R>
-void launch_tresid_restr(Ctx* c, const GridD& g, const GridD& gc, const R* coef, bool fine, const double* dtp,
+void launch_tresid_restr(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, const R* coef, bool fine,
                          const R* x, const R* b, R* bc, R* xc)
 {
-    if (g.dim == 2) {
-        if (fine) tresid_restr_impl<2, true, R>(c, g, gc, coef, dtp, x, b, bc, xc);
-        else tresid_restr_impl<2, false, R>(c, g, gc, coef, dtp, x, b, bc, xc);
+    if (L.gmax.dim == 2) {
+        if (fine) tresid_restr_impl<2, true, R>(c, L, v, gc, oc, coef, x, b, bc, xc);
+        else tresid_restr_impl<2, false, R>(c, L, v, gc, oc, coef, x, b, bc, xc);
     } else {
-        if (fine) tresid_restr_impl<3, true, R>(c, g, gc, coef, dtp, x, b, bc, xc);
-        else tresid_restr_impl<3, false, R>(c, g, gc, coef, dtp, x, b, bc, xc);
+        if (fine) tresid_restr_impl<3, true, R>(c, L, v, gc, oc, coef, x, b, bc, xc);
+        else tresid_restr_impl<3, false, R>(c, L, v, gc, oc, coef, x, b, bc, xc);
     }
 }
 
 template <typename R>
-void launch_trb3(Ctx* c, const GridD& g, const R* coef, bool fine, const double* dtp, int comp, int colour, R* x,
-                 const R* b)
+void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b)
 {
     using T = Tile<3, 1>;
     const bool timed = c->ktm.on && fine;
     if (timed) kt_begin(c);
     const size_t lds = sizeof(R) * (3 + (fine ? 1 : 0)) * T::NS;
-    const dim3 grid = tile_grid<3>(g);
-    if (fine) k_trb3<true, R><<<grid, 256, lds, c->s>>>(g, coef, dtp, comp, colour, x, b);
-    else k_trb3<false, R><<<grid, 256, lds, c->s>>>(g, coef, dtp, comp, colour, x, b);
+    BV vv = v;
+    const dim3 grid = tile_grid<3>(c, L, vv);
+    if (fine) k_trb3<true, R><<<grid, 256, lds, c->s>>>(vv, coef, c->sc, comp, colour, x, b);
+    else k_trb3<false, R><<<grid, 256, lds, c->s>>>(vv, coef, c->sc, comp, colour, x, b);
     if (timed) {
         // algorithmic bytes of one half sweep: every component of x and the
         // coefficients read once, the active colour of b read and of x written
-        const double N = (double)ncells(g);
+        const double N = level_cells(L);
         kt_end(c, sizeof(R) * (3.0 * N + N + N));
     }
 }
 
-#define HB_TILE_INST(R)                                                                                          \
-    template void launch_tsmooth<R>(Ctx*, const GridD&, const R*, bool, const double*, int, const R*, R*, const R*); \
-    template void launch_trb3<R>(Ctx*, const GridD&, const R*, bool, const double*, int, int, R*, const R*);       \
-    template void launch_tresid_restr<R>(Ctx*, const GridD&, const GridD&, const R*, bool, const double*, const R*, \
-                                         const R*, R*, R*);
+#define HB_TILE_INST(R)                                                                                             \
+    template void launch_tsmooth<R>(Ctx*, const Level&, const BV&, const R*, bool, int, const R*, R*, const R*);     \
+    template void launch_trb3<R>(Ctx*, const Level&, const BV&, const R*, bool, int, int, R*, const R*);             \
+    template void launch_tresid_restr<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, bool, \
+                                         const R*, const R*, R*, R*);
 HB_TILE_INST(double)
 HB_TILE_INST(float)
 #undef HB_TILE_INST

@@ -48,9 +48,9 @@ __global__ void k_viscosity(GridD g, FluidD fl, const double* __restrict__ u, do
     eta[cid(g, i, j, k)] = eta_of_g(fl, sqrt(0.5 * s));
 }
 
-void launch_viscosity(Ctx* c, const double* u, double* eta)
+void launch_viscosity(Ctx* c, const Cav& v, const double* u, double* eta)
 {
-    k_viscosity<<<grid3(c->g.n[0], c->g.n[1], c->g.n[2], kBlk), kBlk, 0, c->s>>>(c->g, c->fl, u, eta);
+    k_viscosity<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, v.fl, u, eta);
 }
 
 // ---------------------------------------------------------------------------
@@ -76,10 +76,10 @@ __global__ void k_eta_faces(GridD g, int a, double Re, const double* __restrict_
     beta[foffset(g, a) + fid(g, a, i, j, k)] = v;
 }
 
-void launch_eta_faces(Ctx* c, const GridD& g, const double* eta, double* beta)
+void launch_eta_faces(Ctx* c, const Cav& v, const GridD& g, const double* eta, double* beta)
 {
     for (int a = 0; a < g.dim; ++a)
-        k_eta_faces<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(g, a, c->fl.Re, eta, beta);
+        k_eta_faces<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(g, a, v.fl.Re, eta, beta);
 }
 
 // coarse face = mean of the 2^(d-1) fine faces tiling it
@@ -170,9 +170,9 @@ __global__ void k_visc_dense(GridD g, const double* __restrict__ beta, double dt
     A[(long)row * N + col] = x[row] - dt * visc_div_at<true, false>(g, beta, x, c, i, j, k);
 }
 
-void launch_visc_dense(Ctx* c, const Level& l, double dt, int N, double* E, double* A)
+void launch_visc_dense(Ctx* c, const GridD& g, const double* beta, double dt, int N, const double* E, double* A)
 {
-    k_visc_dense<<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(l.g, l.beta, dt, N, E, A);
+    k_visc_dense<<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(g, beta, dt, N, E, A);
 }
 
 __global__ void k_eta_over_re(long n, double Re, const double* __restrict__ eta, double* __restrict__ etae)
@@ -181,10 +181,10 @@ __global__ void k_eta_over_re(long n, double Re, const double* __restrict__ eta,
     if (i < n) etae[i] = eta[i] / Re;
 }
 
-void launch_eta_over_re(Ctx* c, const GridD& g, const double* eta, double* etae)
+void launch_eta_over_re(Ctx* c, const Cav& v, const double* eta, double* etae)
 {
-    const long n = ncells(g);
-    k_eta_over_re<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(n, c->fl.Re, eta, etae);
+    const long n = v.nc;
+    k_eta_over_re<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(n, v.fl.Re, eta, etae);
 }
 
 }  // namespace hb

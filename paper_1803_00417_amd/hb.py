@@ -25,8 +25,8 @@ ERR_NAMES = {OK: "HB_OK", ERR_ARG: "HB_ERR_ARG", ERR_DEVICE: "HB_ERR_DEVICE",
 
 # symbols declared in include/hb.h
 EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_solve",
-           "hb_advect", "hb_project", "hb_cfl_dt", "hb_step", "hb_kernel_timing",
-           "hb_kernel_timing_read"]
+           "hb_advect", "hb_project", "hb_cfl_dt", "hb_step", "hb_create_batch", "hb_batch_size",
+           "hb_step_batch", "hb_kernel_timing", "hb_kernel_timing_read"]
 
 
 class Grid(C.Structure):
@@ -83,6 +83,9 @@ def load():
     L.hb_project.argtypes = [vp, vp, vp, C.c_double, vp, P(MGReport)]
     L.hb_cfl_dt.argtypes = [vp, vp, P(C.c_double)]
     L.hb_step.argtypes = [vp, vp, vp, C.c_double, P(StepReport)]
+    L.hb_create_batch.argtypes = [P(Grid), P(Fluid), C.c_int, P(StepOpts), vp, P(vp)]
+    L.hb_batch_size.argtypes = [vp]
+    L.hb_step_batch.argtypes = [vp, P(vp), P(vp), P(C.c_double), P(StepReport)]
     L.hb_kernel_timing.argtypes = [vp, C.c_int]
     L.hb_kernel_timing_read.argtypes = [vp, P(C.c_int64), P(C.c_double), P(C.c_double)]
     _lib = L
@@ -279,3 +282,73 @@ class Context:
                             C.byref(rep) if report else None)
         self._check(rc, allow)
         return rep
+
+
+class BatchContext:
+    """A batch of independent cavities (same dimension) stepped together:
+    every multigrid launch covers all cavities, each stops at its own
+    tolerance."""
+
+    def __init__(self, grids, fluids, opts=None, stream=None):
+        L = load()
+        n = len(grids)
+        if n != len(fluids) or n < 1:
+            raise ValueError("need one fluid per grid and at least one cavity")
+        self.grids, self.fluids = list(grids), list(fluids)
+        self.opts = opts if opts is not None else make_step_opts()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        garr = (Grid * n)(*grids)
+        farr = (Fluid * n)(*fluids)
+        h = C.c_void_p()
+        rc = L.hb_create_batch(garr, farr, n, C.byref(self.opts), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise HBError(rc, L.hb_last_error(None).decode())
+        self._h = h
+        self.n = n
+        self.nvel = [g.dim * g.n[0] * g.n[1] * g.n[2] for g in grids]
+        self.nnode = []
+        for g in grids:
+            k = 1
+            for sdim in node_shape(g):
+                k *= sdim
+            self.nnode.append(k)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def size(self):
+        return load().hb_batch_size(self._h)
+
+    def step(self, us, ps, dts=None, report=True, allow=()):
+        """One step of every cavity; us[b], ps[b] GPU float64 tensors (in
+        place).  Returns the list of per-cavity reports (or None)."""
+        if len(us) != self.n or len(ps) != self.n:
+            raise ValueError("need one u and one p per cavity")
+        up = (C.c_void_p * self.n)(*[_ptr(u, self.nvel[b], "u[%d]" % b) for b, u in enumerate(us)])
+        pp = (C.c_void_p * self.n)(*[_ptr(p, self.nnode[b], "p[%d]" % b) for b, p in enumerate(ps)])
+        dt = (C.c_double * self.n)(*dts) if dts is not None else None
+        reps = (StepReport * self.n)() if report else None
+        rc = load().hb_step_batch(self._h, up, pp, dt, reps)
+        if rc != OK and rc not in allow:
+            raise HBError(rc, load().hb_last_error(self._h).decode())
+        return list(reps) if report else None
+
+    def kernel_timing(self, enable):
+        rc = load().hb_kernel_timing(self._h, int(enable))
+        if rc != OK:
+            raise HBError(rc, load().hb_last_error(self._h).decode())
+
+    def kernel_timing_read(self):
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        load().hb_kernel_timing_read(self._h, C.byref(n), C.byref(ms), C.byref(by))
+        return n.value, ms.value, by.value
