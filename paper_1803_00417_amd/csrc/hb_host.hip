@@ -461,8 +461,12 @@ struct SolveOut {
     int rc = HB_OK;
 };
 
+// copy a flag array to the device unless the device already holds it
 static void upload_flags(Ctx* c, int* dev, const int* host)
 {
+    std::vector<int>& shadow = dev == c->act ? c->dact : (dev == c->act2 ? c->dact2 : c->dsel);
+    if ((int)shadow.size() == c->nb && std::equal(shadow.begin(), shadow.end(), host)) return;
+    shadow.assign(host, host + c->nb);
     (void)hipMemcpyAsync(dev, host, sizeof(int) * c->nb, hipMemcpyHostToDevice, c->s);
 }
 

@@ -55,9 +55,11 @@ __device__ inline bool bv_enter(const BV& v, int& cav, int& bz, GridD& g)
 {
     cav = blockIdx.z / v.zb;
     bz = blockIdx.z - cav * v.zb;
-    if (v.act && !v.act[cav]) return false;
+    // both table reads are issued before either is tested, so a block pays
+    // one memory latency for them
     g = v.g[cav];
-    return g.dim != 0;
+    const bool on = !v.act || v.act[cav];
+    return on && g.dim != 0;
 }
 
 struct Level {
@@ -190,6 +192,8 @@ struct Ctx {
     int* hact2 = nullptr;
     int* sel = nullptr;          // per cavity buffer choice (device) and staging
     int* hsel = nullptr;
+    // what each device flag array holds (uploads are skipped when unchanged)
+    std::vector<int> dact, dact2, dsel;
     KTimer ktm;                  // timing of the finest tensor smoother launches
     std::string err;
 };

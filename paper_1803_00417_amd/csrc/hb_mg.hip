@@ -103,7 +103,7 @@ __global__ void k_mac_resid_restrict(BV v, const GridD* __restrict__ gft, const 
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= gc.n[0] || j >= gc.n[1] || k >= gc.n[2]) return;
-    const GridD gf = gft[cav];
+    const GridD& gf = gft[cav];   // read in place: a private copy indexed by axis would spill
     const R* xf = xfa + oft[cav];
     const R* bf = bfa + oft[cav];
     const int nch = 1 << gf.dim;
@@ -156,7 +156,7 @@ __global__ void k_prolong_cells(BV v, const GridD* __restrict__ gct, const long*
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= gf.n[0] || j >= gf.n[1] || k >= gf.n[2]) return;
-    const GridD gc = gct[cav];
+    const GridD& gc = gct[cav];   // read in place: a private copy indexed by axis would spill
     const R* e = ea + ncomp * oct[cav];
     R* x = xa + ncomp * v.o[cav];
     const int d = gf.dim;
@@ -209,7 +209,7 @@ __global__ void k_nodal_restrict(BV v, const GridD* __restrict__ gft, const long
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nnode(gc, 0) || j >= nnode(gc, 1) || k >= nnode(gc, 2)) return;
-    const GridD gf = gft[cav];
+    const GridD& gf = gft[cav];   // read in place: a private copy indexed by axis would spill
     const R* rf = rfa + oft[cav];
     const int d = gf.dim;
     const int I[3] = {i, j, k};
@@ -259,7 +259,7 @@ __global__ void k_nodal_prolong(BV v, const GridD* __restrict__ gct, const long*
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nnode(gf, 0) || j >= nnode(gf, 1) || k >= nnode(gf, 2)) return;
-    const GridD gc = gct[cav];
+    const GridD& gc = gct[cav];   // read in place: a private copy indexed by axis would spill
     const R* e = ea + oct[cav];
     const int d = gf.dim;
     const int F[3] = {i, j, k};

@@ -80,7 +80,8 @@ __device__ inline double visc_diag(const GridD& g, const double* __restrict__ be
     return 1.0 + dt * coef / (g.h * g.h);
 }
 
-// L_mac x at one cell, as the divergence of face gradients
+// L_mac x at one cell, as the divergence of face gradients (zero flux
+// through walls); the two factors 1/h are applied once, as 1/h^2
 template <typename R>
 __device__ inline R mac_lap_at(const GridD& g, const R* __restrict__ x, int i, int j, int k)
 {
@@ -91,11 +92,11 @@ __device__ inline R mac_lap_at(const GridD& g, const R* __restrict__ x, int i, i
         int p[3] = {i, j, k}, m[3] = {i, j, k};
         p[a] += 1;
         m[a] -= 1;
-        const R Fhi = wrap(g, p) ? (x[cid(g, p[0], p[1], p[2])] - xc) / h : R(0);
-        const R Flo = wrap(g, m) ? (xc - x[cid(g, m[0], m[1], m[2])]) / h : R(0);
-        s += (Fhi - Flo) / h;
+        const R Fhi = wrap(g, p) ? x[cid(g, p[0], p[1], p[2])] - xc : R(0);
+        const R Flo = wrap(g, m) ? xc - x[cid(g, m[0], m[1], m[2])] : R(0);
+        s += Fhi - Flo;
     }
-    return s;
+    return s * (R(1) / (h * h));
 }
 
 __device__ inline double q1_ke(int dim, double h, int k)

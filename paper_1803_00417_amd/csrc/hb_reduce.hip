@@ -72,8 +72,8 @@ void fill(Ctx* c, double* dst, double v, long n)
 // this block's cavity segment; the block returns when the cavity is inactive
 #define SEG_ENTER(sv, off, n)                                  \
     const int cav_ = blockIdx.y;                               \
-    if ((sv).act && !(sv).act[cav_]) return;                   \
-    const long off = (sv).off[cav_], n = (sv).n[cav_];
+    const long off = (sv).off[cav_], n = (sv).n[cav_];         \
+    if ((sv).act && !(sv).act[cav_]) return;
 
 #define SEG_LOOP(i, n) for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
 

@@ -169,9 +169,13 @@ template <int DIM, int H, bool FINE, typename R>
 __device__ inline R tile_visc_div(const GridD& g, const R* __restrict__ beta, const R* s, const R* e, int c,
                                   const int G[3], int wm, int l0, R dt, R* diag)
 {
+    // Every flux carries one factor 1/h and the divergence another, so the
+    // fluxes are formed in units of h and the sum is scaled by 1/h^2 once
+    // (no divisions in the stencil).
     using T = Tile<DIM, H>;
     const int off[3] = {1, T::SX, T::SX * T::SY};
     const R h = (R)g.h;
+    const R ihh = R(1) / (h * h);
     const R* sc = s + c * T::NS;
     R acc = 0, coefsum = 0;
 #pragma unroll
@@ -185,7 +189,7 @@ __device__ inline R tile_visc_div(const GridD& g, const R* __restrict__ beta, co
             R bf;
             if (FINE) bf = wall ? e[l0] : R(0.5) * (e[lL] + e[lR]);
             else bf = face_beta_global<R>(g, beta, a, G, side);
-            const R dn = (sc[lR] - sc[lL]) / h;
+            const R dn = sc[lR] - sc[lL];
             R f;
             if (a == c) {
                 f = bf * dn;
@@ -193,18 +197,17 @@ __device__ inline R tile_visc_div(const GridD& g, const R* __restrict__ beta, co
                 f = bf * R(0.5) * dn;
             } else {
                 const R* sa = s + a * T::NS;
-                const R dL = (sa[lL + off[c]] - sa[lL - off[c]]) / (R(2) * h);
-                const R dR = (sa[lR + off[c]] - sa[lR - off[c]]) / (R(2) * h);
-                const R cross = R(0.5) * (dL + dR);
+                // mean of the two cells' centred transverse differences
+                const R cross = R(0.25) * ((sa[lL + off[c]] - sa[lL - off[c]]) + (sa[lR + off[c]] - sa[lR - off[c]]));
                 f = bf * R(0.5) * (dn + cross);
             }
             flux[side] = f;
             coefsum += (wall ? R(2) : R(1)) * ((a == c) ? R(1) : R(0.5)) * bf;
         }
-        acc += (flux[1] - flux[0]) / h;
+        acc += flux[1] - flux[0];
     }
-    if (diag) *diag = R(1) + dt * coefsum / (h * h);
-    return acc;
+    if (diag) *diag = R(1) + dt * coefsum * ihh;
+    return acc * ihh;
 }
 
 // ---------------------------------------------------------------------------
