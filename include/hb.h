@@ -191,6 +191,47 @@ int hb_create_batch(const hb_grid* grids, const hb_fluid* fluids, int count, con
 int hb_batch_size(const hb_ctx* ctx);
 int hb_step_batch(hb_ctx* ctx, double* const* u, double* const* p, const double* dt, hb_step_report* reports);
 
+/* ---- learned warm start (BF16 U-Net on the matrix cores) -----------------
+ * A small convolutional U-Net (4 levels, 16/32/64/64 channels, two 3x3
+ * convolutions with ReLU per level, average pooling down, nearest upsampling
+ * and skip concatenation up, 3x3 head) with BF16 weights and activations and
+ * FP32 accumulation, trained on the GPU by the library's own forward and
+ * backward kernels (MSE loss, Adam).  Tensors are device FP32, [n][H][W][C]
+ * (channels fastest), H and W multiples of 8; in_ch, out_ch in 1..16.  The
+ * network allocates its activation buffers for the last (n, H, W) it saw.
+ * Parameters: a flat FP32 vector, layer by layer: weights [Cout][3][3][Cin]
+ * then biases [Cout]; the first layer has 16 input channels (the input is
+ * zero-padded) and the head 16 outputs, of which the first out_ch count. */
+typedef struct hb_nn hb_nn;
+int hb_nn_create(int in_ch, int out_ch, uint64_t seed, hb_nn** out);
+void hb_nn_destroy(hb_nn* nn);
+int64_t hb_nn_param_count(const hb_nn* nn);
+int hb_nn_get_params(hb_nn* nn, float* host_out);
+int hb_nn_set_params(hb_nn* nn, const float* host_in);
+int hb_nn_forward(hb_nn* nn, const float* x, int n, int H, int W, float* y);
+/* loss = mean over pixels and the first out_ch channels of (y - target)^2;
+ * grad_host (nullable): dloss/dparams, param_count floats */
+int hb_nn_grad(hb_nn* nn, const float* x, const float* target, int n, int H, int W, double* loss, float* grad_host);
+int hb_nn_train_step(hb_nn* nn, const float* x, const float* target, int n, int H, int W, float lr, double* loss);
+
+/* Warm start of the nodal projection solve (2D, cell counts multiples of 8):
+ * with a network set (in_ch = out_ch = 1), each solve starts from the
+ * previous pressure x0, forms r0 = b - K x0, feeds r0 / |r0|_inf averaged to
+ * cells to the network, averages its output y back to nodes, scales it by the
+ * least-squares factor s = (r0 . K y) / (K y . K y), and starts from
+ * x0 + s y only when that lowers |b - K x|_inf (otherwise from x0).  The
+ * multigrid solve and its tolerance are unchanged.  nn NULL: off.  The
+ * network must outlive its use by the context.  op: HB_OP_NODAL only. */
+int hb_set_warm_start(hb_ctx* ctx, int op, hb_nn* nn);
+/* number of solves so far that started from the network's guess */
+int hb_warm_start_uses(const hb_ctx* ctx);
+
+/* Training data: while enabled, each nodal solve of cavity 0 records its
+ * initial residual r0 = b - K x0 and its correction e = x - x0 (FP64, node
+ * layout); hb_capture_read copies the last pair to caller device arrays. */
+int hb_capture(hb_ctx* ctx, int op, int enable);
+int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e);
+
 /* Measurement support.  While enabled, every launch of the tensor viscous
  * smoother (one fused red-black sweep of one velocity component on a fine
  * multigrid level) on the context's stream is bracketed by HIP events;

@@ -656,6 +656,45 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o,
         if (act[i]) take_rel(i);
 }
 
+// Start of a nodal solve of a single-cavity context: record the initial
+// residual and guess for training data, and replace the guess x0 by the
+// network's x0 + s y when that lowers the residual (learned warm start).
+static void nodal_prestart(Ctx* c, MG& m, double* x)
+{
+    Level& L = m.L[0];
+    const long n = L.nu;
+    const GridD& g = c->cv[0].g;
+    resid0(c, m, x, m.lvl0_b, L.r, nullptr);
+    fetch_slots(c);
+    const double s0 = slot(c, 0, S_MAX);
+    if (c->cap) {
+        copy(c, c->cap_r0, L.r, n);
+        copy(c, c->cap_x0, x, n);
+    }
+    if (!c->ws || !(s0 > 0.0) || !std::isfinite(s0)) return;
+    launch_node_to_cell(c, g, L.r, 1.0 / s0, c->ws_in);
+    if (hipStreamSynchronize(c->s) != hipSuccess) return;
+    if (nn_infer(c->ws, c->ws_in, 1, g.n[1], g.n[0], c->ws_out) != HB_OK) return;
+    launch_cell_to_node(c, g, c->ws_out, c->ws_y);
+    // least-squares scale of the network's shape: min_s |r0 - s K y|_2
+    launch_nodal_resid<double>(c, L, all_view(L, nullptr), c->ws_y, nullptr, c->ws_z, -1);
+    const SegV sv = seg_of(m, nullptr);
+    seg_dot(c, sv, L.r, c->ws_z, S_DOT0);
+    seg_dot(c, sv, c->ws_z, c->ws_z, S_DOT1);
+    fetch_slots(c);
+    const double zz = slot(c, 0, S_DOT1);
+    if (!(zz > 0.0) || !std::isfinite(zz)) return;
+    const double sc = slot(c, 0, S_DOT0) / zz;
+    launch_axpy(c, c->ws_x1, x, c->ws_y, sc, n);
+    resid0(c, m, c->ws_x1, m.lvl0_b, L.r, nullptr);
+    fetch_slots(c);
+    const double s1 = slot(c, 0, S_MAX);
+    if (s1 < s0) {   // the residual check decides; otherwise keep x0
+        copy(c, x, c->ws_x1, n);
+        ++c->ws_report_used;
+    }
+}
+
 // Solve with the right-hand sides already in m.lvl0_b (VISC: wall part
 // added; NODAL/MAC: mean removed by this function).  x: level-0 arena.
 static int solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o, std::vector<SolveOut>& so)
@@ -664,6 +703,7 @@ static int solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o, std::ve
     so.assign(nb, SolveOut());
     const SegV all = seg_of(m, nullptr);
     if (m.op != HB_OP_VISC) seg_sub_mean(c, all, m.lvl0_b);
+    if (m.op == HB_OP_NODAL && (c->ws || c->cap)) nodal_prestart(c, m, x);
     seg_maxabs(c, all, m.lvl0_b, S_MAX);
     seg_maxabs(c, all, x, S_MAX2);
     fetch_slots(c);
@@ -675,6 +715,7 @@ static int solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o, std::ve
     if (o.precision == HB_PREC_MIXED) ensure_f32(c, m);
     solve_core(c, m, x, m.lvl0_b, o, so);
     if (m.op != HB_OP_VISC) seg_sub_mean(c, all, x);
+    if (m.op == HB_OP_NODAL && c->cap) launch_axpy(c, c->cap_e, x, c->cap_x0, -1.0, m.L[0].nu);
     for (int i = 0; i < nb; ++i) {
         if (so[i].rc == HB_ERR_NONFINITE) rc = HB_ERR_NONFINITE;
         else if (so[i].rc == HB_ERR_NOCONV && rc == HB_OK) rc = HB_ERR_NOCONV;
@@ -1055,6 +1096,14 @@ static void destroy_ctx(Ctx* c)
     (void)hipFree(c->act);
     (void)hipFree(c->act2);
     (void)hipFree(c->sel);
+    (void)hipFree(c->ws_in);
+    (void)hipFree(c->ws_out);
+    (void)hipFree(c->ws_y);
+    (void)hipFree(c->ws_z);
+    (void)hipFree(c->ws_x1);
+    (void)hipFree(c->cap_r0);
+    (void)hipFree(c->cap_e);
+    (void)hipFree(c->cap_x0);
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hact) (void)hipHostFree(c->hact);
     if (c->hact2) (void)hipHostFree(c->hact2);
@@ -1233,6 +1282,62 @@ int hb_step_batch(hb_ctx* ctx, double* const* u, double* const* p, const double*
     StreamGuard guard(c);
     return step_all(c, u, p, dt, reports);
 }
+
+int hb_set_warm_start(hb_ctx* ctx, int op, hb_nn* nn)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (op != HB_OP_NODAL) return fail(c, HB_ERR_ARG, "the warm start serves the nodal projection solve only");
+    if (!nn) {
+        c->ws = nullptr;
+        return HB_OK;
+    }
+    if (single_only(c)) return HB_ERR_ARG;
+    const GridD& g = c->cv[0].g;
+    if (c->dim != 2 || g.n[0] % 8 || g.n[1] % 8) return fail(c, HB_ERR_ARG, "the warm start needs a 2D grid with cell counts multiple of 8");
+    NNet* t = nn_of(nn);
+    if (nn_channels_in(t) != 1 || nn_channels_out(t) != 1) return fail(c, HB_ERR_ARG, "the warm-start network maps 1 channel to 1");
+    if (!c->ws_in) {
+        const long nc = c->cv[0].nc, nn_ = c->nodal.L[0].nu;
+        if (hipMalloc((void**)&c->ws_in, 4 * nc) != hipSuccess || hipMalloc((void**)&c->ws_out, 4 * nc) != hipSuccess ||
+            hipMalloc((void**)&c->ws_y, 8 * nn_) != hipSuccess || hipMalloc((void**)&c->ws_z, 8 * nn_) != hipSuccess ||
+            hipMalloc((void**)&c->ws_x1, 8 * nn_) != hipSuccess)
+            return fail(c, HB_ERR_OOM, "device allocation failed");
+    }
+    c->ws = t;
+    return HB_OK;
+}
+
+int hb_capture(hb_ctx* ctx, int op, int enable)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (op != HB_OP_NODAL) return fail(c, HB_ERR_ARG, "capture serves the nodal projection solve only");
+    if (single_only(c)) return HB_ERR_ARG;
+    if (enable && !c->cap_r0) {
+        const long n = c->nodal.L[0].nu;
+        if (hipMalloc((void**)&c->cap_r0, 8 * n) != hipSuccess || hipMalloc((void**)&c->cap_e, 8 * n) != hipSuccess ||
+            hipMalloc((void**)&c->cap_x0, 8 * n) != hipSuccess)
+            return fail(c, HB_ERR_OOM, "device allocation failed");
+        (void)hipMemset(c->cap_r0, 0, 8 * n);
+        (void)hipMemset(c->cap_e, 0, 8 * n);
+    }
+    c->cap = enable != 0;
+    return HB_OK;
+}
+
+int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (op != HB_OP_NODAL || !r0 || !e || !c->cap_r0) return fail(c, HB_ERR_ARG, "nothing captured");
+    StreamGuard guard(c);
+    copy(c, r0, c->cap_r0, c->nodal.L[0].nu);
+    copy(c, e, c->cap_e, c->nodal.L[0].nu);
+    return hipStreamSynchronize(c->s) == hipSuccess ? HB_OK : fail(c, HB_ERR_DEVICE, "stream synchronisation failed");
+}
+
+int hb_warm_start_uses(const hb_ctx* ctx) { return ctx ? (int)C_(ctx)->ws_report_used : 0; }
 
 int hb_kernel_timing(hb_ctx* ctx, int enable)
 {

@@ -195,6 +195,13 @@ struct Ctx {
     // what each device flag array holds (uploads are skipped when unchanged)
     std::vector<int> dact, dact2, dsel;
     KTimer ktm;                  // timing of the finest tensor smoother launches
+    // learned warm start of the nodal solve and training-data capture
+    struct NNet* ws = nullptr;
+    float *ws_in = nullptr, *ws_out = nullptr;   // cell fields of the network
+    double *ws_y = nullptr, *ws_z = nullptr, *ws_x1 = nullptr;   // node fields
+    bool cap = false;
+    double *cap_r0 = nullptr, *cap_e = nullptr, *cap_x0 = nullptr;
+    long ws_report_used = 0;      // solves that started from the network's guess
     std::string err;
 };
 
@@ -291,6 +298,18 @@ void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* 
 template <typename R>
 void launch_coarse_solve(Ctx* c, const MG& m, int lev, const int* act, const R* b, R* x);
 void launch_identity(Ctx* c, int N, double* E);
+
+// ---- learned warm start (hb_nn.hip, hb_ws.hip) --------------------------------
+struct NNet;
+int nn_infer(NNet* t, const float* x, int n, int H, int W, float* y);   // device fp32 in/out, synchronous
+NNet* nn_of(hb_nn* nn);
+int nn_channels_in(const NNet* t);
+int nn_channels_out(const NNet* t);
+// cell value = scale * mean of its 2^d corner nodes (2D), fp32 [ny][nx]
+void launch_node_to_cell(Ctx* c, const GridD& g, const double* v, double scale, float* out);
+// node value = mean of the cells around it (2D)
+void launch_cell_to_node(Ctx* c, const GridD& g, const float* v, double* out);
+void launch_axpy(Ctx* c, double* y, const double* x, const double* a, double s, long n);   // y = x + s a
 
 // ---- step stages, per cavity (hb_step.hip) ----------------------------------
 void launch_grad_node(Ctx* c, const Cav& v, const double* p, double* Gp);

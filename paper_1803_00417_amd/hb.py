@@ -26,7 +26,9 @@ ERR_NAMES = {OK: "HB_OK", ERR_ARG: "HB_ERR_ARG", ERR_DEVICE: "HB_ERR_DEVICE",
 # symbols declared in include/hb.h
 EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_solve",
            "hb_advect", "hb_project", "hb_cfl_dt", "hb_step", "hb_create_batch", "hb_batch_size",
-           "hb_step_batch", "hb_kernel_timing", "hb_kernel_timing_read"]
+           "hb_step_batch", "hb_nn_create", "hb_nn_destroy", "hb_nn_param_count", "hb_nn_get_params",
+           "hb_nn_set_params", "hb_nn_forward", "hb_nn_grad", "hb_nn_train_step", "hb_set_warm_start",
+           "hb_warm_start_uses", "hb_capture", "hb_capture_read", "hb_kernel_timing", "hb_kernel_timing_read"]
 
 
 class Grid(C.Structure):
@@ -86,6 +88,20 @@ def load():
     L.hb_create_batch.argtypes = [P(Grid), P(Fluid), C.c_int, P(StepOpts), vp, P(vp)]
     L.hb_batch_size.argtypes = [vp]
     L.hb_step_batch.argtypes = [vp, P(vp), P(vp), P(C.c_double), P(StepReport)]
+    L.hb_nn_create.argtypes = [C.c_int, C.c_int, C.c_uint64, P(vp)]
+    L.hb_nn_destroy.argtypes = [vp]
+    L.hb_nn_destroy.restype = None
+    L.hb_nn_param_count.argtypes = [vp]
+    L.hb_nn_param_count.restype = C.c_int64
+    L.hb_nn_get_params.argtypes = [vp, vp]
+    L.hb_nn_set_params.argtypes = [vp, vp]
+    L.hb_nn_forward.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, vp]
+    L.hb_nn_grad.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, P(C.c_double), vp]
+    L.hb_nn_train_step.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float, P(C.c_double)]
+    L.hb_set_warm_start.argtypes = [vp, C.c_int, vp]
+    L.hb_warm_start_uses.argtypes = [vp]
+    L.hb_capture.argtypes = [vp, C.c_int, C.c_int]
+    L.hb_capture_read.argtypes = [vp, C.c_int, vp, vp]
     L.hb_kernel_timing.argtypes = [vp, C.c_int]
     L.hb_kernel_timing_read.argtypes = [vp, P(C.c_int64), P(C.c_double), P(C.c_double)]
     _lib = L
@@ -276,6 +292,20 @@ class Context:
         self._check(load().hb_kernel_timing_read(self._h, C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
 
+    def set_warm_start(self, net):
+        """learned warm start of the nodal solve (net: Net with 1 -> 1
+        channels, or None to switch it off)"""
+        self._check(load().hb_set_warm_start(self._h, OP_NODAL, net._h if net is not None else None))
+
+    def warm_start_uses(self):
+        return load().hb_warm_start_uses(self._h)
+
+    def capture(self, enable):
+        self._check(load().hb_capture(self._h, OP_NODAL, int(enable)))
+
+    def capture_read(self, r0, e):
+        self._check(load().hb_capture_read(self._h, OP_NODAL, _ptr(r0, self.nnode, "r0"), _ptr(e, self.nnode, "e")))
+
     def step(self, u, p, dt=0.0, report=True, allow=()):
         rep = StepReport() if report else None
         rc = load().hb_step(self._h, _ptr(u, self.nvel, "u"), _ptr(p, self.nnode, "p"), float(dt),
@@ -352,3 +382,80 @@ class BatchContext:
         n, ms, by = C.c_int64(), C.c_double(), C.c_double()
         load().hb_kernel_timing_read(self._h, C.byref(n), C.byref(ms), C.byref(by))
         return n.value, ms.value, by.value
+
+
+def _fptr(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous float32 GPU tensor" % name)
+    return C.c_void_p(t.data_ptr())
+
+
+class Net:
+    """The BF16 U-Net of the learned warm start (library kernels for the
+    forward pass, the backward pass and Adam).  Tensors: float32 GPU,
+    [n][H][W][C]."""
+
+    def __init__(self, in_ch=1, out_ch=1, seed=0):
+        L = load()
+        h = C.c_void_p()
+        rc = L.hb_nn_create(in_ch, out_ch, seed, C.byref(h))
+        if rc != OK:
+            raise HBError(rc, "hb_nn_create failed")
+        self._h = h
+        self.in_ch, self.out_ch = in_ch, out_ch
+        self.nparams = L.hb_nn_param_count(h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hb_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.nparams, dtype=np.float32)
+        rc = load().hb_nn_get_params(self._h, out.ctypes.data_as(C.c_void_p))
+        if rc != OK:
+            raise HBError(rc, "hb_nn_get_params failed")
+        return out
+
+    def set_params(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.size != self.nparams:
+            raise ValueError("expected %d parameters" % self.nparams)
+        rc = load().hb_nn_set_params(self._h, w.ctypes.data_as(C.c_void_p))
+        if rc != OK:
+            raise HBError(rc, "hb_nn_set_params failed")
+
+    def forward(self, x):
+        n, H, W, _ = x.shape
+        y = torch.empty((n, H, W, self.out_ch), dtype=torch.float32, device=x.device)
+        rc = load().hb_nn_forward(self._h, _fptr(x, "x"), n, H, W, _fptr(y, "y"))
+        if rc != OK:
+            raise HBError(rc, "hb_nn_forward failed")
+        return y
+
+    def grad(self, x, t):
+        import numpy as np
+        n, H, W, _ = x.shape
+        g = np.zeros(self.nparams, dtype=np.float32)
+        loss = C.c_double()
+        rc = load().hb_nn_grad(self._h, _fptr(x, "x"), _fptr(t, "target"), n, H, W, C.byref(loss),
+                               g.ctypes.data_as(C.c_void_p))
+        if rc != OK:
+            raise HBError(rc, "hb_nn_grad failed")
+        return loss.value, g
+
+    def train_step(self, x, t, lr):
+        n, H, W, _ = x.shape
+        loss = C.c_double()
+        rc = load().hb_nn_train_step(self._h, _fptr(x, "x"), _fptr(t, "target"), n, H, W, float(lr), C.byref(loss))
+        if rc != OK:
+            raise HBError(rc, "hb_nn_train_step failed")
+        return loss.value
