@@ -36,6 +36,7 @@ def parse():
                     help="comma-separated further workloads ('' for none)")
     ap.add_argument("--also-steps", type=int, default=10)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision runs")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start runs")
     ap.add_argument("--batch", type=int, default=64, help="cavities of the batched sweep (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -51,10 +52,17 @@ def _context(name, precision):
     return hb.Context(g, fl, hb.make_step_opts(cfl=w["cfl"], precision=precision)), g, w
 
 
-def run_gpu(name, steps, warmup, precision=0, timing=True):
+def run_gpu(name, steps, warmup, precision=0, timing=True, learned=False):
     import torch
     from paper_1803_00417_amd import hb
     ctx, g, w = _context(name, precision)
+    net = None
+    if learned:
+        from paper_1803_00417_amd import warm_start
+        net = warm_start.load_net()
+        if net is None:
+            raise RuntimeError("no trained warm-start weights (run python -m paper_1803_00417_amd.warm_start)")
+        ctx.set_warm_start(net)
     u = torch.zeros(hb.cell_shape(g, w["dim"]), dtype=torch.float64, device="cuda")
     p = torch.zeros(hb.node_shape(g), dtype=torch.float64, device="cuda")
     for k in range(warmup):
@@ -79,8 +87,10 @@ def run_gpu(name, steps, warmup, precision=0, timing=True):
     kt = ctx.kernel_timing_read() if timing else (0, 0.0, 0.0)
     ctx.kernel_timing(False)
     ncell = g.n[0] * g.n[1] * g.n[2]
+    uses = ctx.warm_start_uses() if learned else 0
     ctx.close()
-    return dict(T=T, ncell=ncell, steps=steps, warmup=warmup, cycles=[c / steps for c in cycles], kt=kt)
+    return dict(T=T, ncell=ncell, steps=steps, warmup=warmup, cycles=[c / steps for c in cycles], kt=kt,
+                ws_uses=uses)
 
 
 def run_batch(steps, warmup, precision=0, count=64, seed=0):
@@ -210,6 +220,16 @@ def main():
               file=sys.stderr, flush=True)
         r2 = run_gpu(nm, st, wu, precision=prec)
         also["%s_%s" % (nm, "mixed" if prec else "fp64")] = _summary(r2, inputs.WORKLOADS[nm])
+    if not a.no_learned and inputs.WORKLOADS[a.workload]["dim"] == 2:
+        # the learned warm start of the projection solve (weights trained by
+        # paper_1803_00417_amd.warm_start on 128^2 cavities)
+        for prec in ((0, 1) if not a.no_mixed else (0,)):
+            tag = "%s_%s_learned" % (a.workload, "mixed" if prec else "fp64")
+            print("[bench] workload %s: %d warm-up + %d timed steps" % (tag, a.warmup, a.steps), file=sys.stderr, flush=True)
+            r2 = run_gpu(a.workload, a.steps, a.warmup, precision=prec, learned=True)
+            rec = _summary(r2, inputs.WORKLOADS[a.workload])
+            rec["warm_start_used_in_solves"] = r2["ws_uses"]
+            also[tag] = rec
     if a.batch > 0:
         for prec in ((0, 1) if not a.no_mixed else (0,)):
             print("[bench] batched sweep of %d cavities (%s)" % (a.batch, "mixed" if prec else "fp64"),

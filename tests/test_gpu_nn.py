@@ -182,3 +182,19 @@ def test_trained_warm_start_gain():
     _say("  projection cycles over 12 steps: previous-step guess %d, learned %d (used %d times)"
          % (sum(c0), sum(c1), uses))
     assert sum(c1) <= sum(c0) + 12
+
+
+def test_shipped_warm_start_on_held_out_cavity():
+    # the weights trained by paper_1803_00417_amd.warm_start (128^2 cavities,
+    # seeds 1..12, Pa = 1e4) on a held-out 128^2 cavity
+    _say("shipped warm start")
+    from paper_1803_00417_amd import warm_start
+    net = warm_start.load_net()
+    if net is None:
+        pytest.skip("no trained weights shipped")
+    g, fl, _ = _cavity(128, seed=99)
+    _, _, c0, _ = _run(g, fl, 16)
+    _, _, c1, uses = _run(g, fl, 16, net)
+    _say("  projection cycles over 16 steps: previous-step guess %d, learned %d (used %d times)"
+         % (sum(c0), sum(c1), uses))
+    assert sum(c1) <= sum(c0) + 16
