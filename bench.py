@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -188,6 +190,15 @@ def main():
     import torch
     from paper_1803_00417_amd import hb, inputs  # noqa: F401
     assert torch.cuda.is_available(), "no GPU"
+    if a.copy_probe:
+        n = a.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_copy": 8 * n, "copies": 5}), flush=True)
+        return
     print("[bench] workload %s: %d warm-up + %d timed steps" % (a.workload, a.warmup, a.steps),
           file=sys.stderr, flush=True)
     r = run_gpu(a.workload, a.steps, a.warmup)

@@ -49,6 +49,35 @@ struct SegV {
     const int* act;     // per cavity active flag (nullptr: all)
 };
 
+// XCD-aware tile order.  Workgroups are dispatched to the 8 XCDs (each with
+// its own L2) round-robin by linear block id; this map gives XCD k the k-th
+// contiguous eighth of the tiles (x fastest, then y, then z), so the halo a
+// tile shares with its neighbours is mostly fetched into the same L2.  It is
+// a bijection for any block count.
+__device__ inline void xcd_tile(int& bx, int& by, int& bz)
+{
+    const unsigned T = gridDim.x * gridDim.y * gridDim.z;
+    const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned q = T / 8, r = T % 8, x = b % 8;
+    const unsigned lin = x * q + (x < r ? x : r) + b / 8;
+    bx = (int)(lin % gridDim.x);
+    by = (int)((lin / gridDim.x) % gridDim.y);
+    bz = (int)(lin / (gridDim.x * gridDim.y));
+}
+
+// cavity of the block at z index bzg and its z index within the cavity;
+// false when the cavity takes no part in the launch
+__device__ inline bool bv_enter_at(const BV& v, int bzg, int& cav, int& bz, GridD& g)
+{
+    cav = bzg / v.zb;
+    bz = bzg - cav * v.zb;
+    // both table reads are issued before either is tested, so a block pays
+    // one memory latency for them
+    g = v.g[cav];
+    const bool on = !v.act || v.act[cav];
+    return on && g.dim != 0;
+}
+
 // cavity of this block and the block's z index within it; false when the
 // cavity takes no part in the launch
 __device__ inline bool bv_enter(const BV& v, int& cav, int& bz, GridD& g)

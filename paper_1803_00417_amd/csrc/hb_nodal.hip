@@ -79,10 +79,11 @@ __device__ inline void fill_nodes(const GridD& g, const R* __restrict__ x, R* s,
 // cavity's grid and node offset from the level tables and returns when the
 // cavity takes no part or the tile lies outside it.
 #define NTILE_ENTER(DIM, T)                                                                 \
-    int cav, bz;                                                                            \
+    int cav, bz, tbx, tby, tbz;                                                             \
     GridD g;                                                                                \
-    if (!bv_enter(v, cav, bz, g)) return;                                                   \
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = DIM == 3 ? bz * T::TZ : 0; \
+    xcd_tile(tbx, tby, tbz);                                                                \
+    if (!bv_enter_at(v, tbz, cav, bz, g)) return;                                           \
+    const int ox = tbx * T::TX, oy = tby * T::TY, oz = DIM == 3 ? bz * T::TZ : 0;            \
     if (ox >= nnode(g, 0) || oy >= nnode(g, 1) || oz >= nnode(g, 2)) return;                \
     const long node0 = v.o[cav];
 

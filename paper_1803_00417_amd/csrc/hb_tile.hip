@@ -253,10 +253,11 @@ extern __shared__ __align__(16) unsigned char tile_lds[];
 // the cavity takes no part or the tile lies outside it, and then runs the
 // single-grid body on that cavity's arrays.
 #define TILE_ENTER(DIM, T)                                                                  \
-    int cav, bz;                                                                            \
+    int cav, bz, tbx, tby, tbz;                                                             \
     GridD g;                                                                                \
-    if (!bv_enter(v, cav, bz, g)) return;                                                   \
-    const int ox = blockIdx.x * T::TX, oy = blockIdx.y * T::TY, oz = (DIM == 3) ? bz * T::TZ : 0; \
+    xcd_tile(tbx, tby, tbz);                                                                \
+    if (!bv_enter_at(v, tbz, cav, bz, g)) return;                                           \
+    const int ox = tbx * T::TX, oy = tby * T::TY, oz = (DIM == 3) ? bz * T::TZ : 0;          \
     if (ox >= g.n[0] || oy >= g.n[1] || oz >= g.n[2]) return;                               \
     const long cell0 = v.o[cav];
 
