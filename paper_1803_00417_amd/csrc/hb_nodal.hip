@@ -54,7 +54,9 @@ __device__ inline R tile_K(const GridD& g, const R* s, const int G[3], int l, R*
 }
 
 // stage the node tile plus a 1-node halo; all loads of a thread are issued
-// before any store so they are in flight together
+// before any store so they are in flight together.  Positions beyond a
+// wall read as 0 (their stencil weight is zero); periodic axes wrap.  The
+// load always uses an in-range index, so no branch separates the loads.
 template <int DIM, typename R>
 __device__ inline void fill_nodes(const GridD& g, const R* __restrict__ x, R* s, int ox, int oy, int oz)
 {
@@ -66,7 +68,21 @@ __device__ inline void fill_nodes(const GridD& g, const R* __restrict__ x, R* s,
         const int t = threadIdx.x + u * T::THREADS;
         const int tt = t < T::NS ? t : 0;
         const int lx = tt % T::SX, ly = (tt / T::SX) % T::SY, lz = tt / (T::SX * T::SY);
-        v[u] = node_fetch<DIM, R>(g, x, ox - 1 + lx, oy - 1 + ly, DIM == 3 ? oz - 1 + lz : 0);
+        int p[3] = {ox - 1 + lx, oy - 1 + ly, DIM == 3 ? oz - 1 + lz : 0};
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int nn = nnode(g, a);
+            int q = p[a];
+            if (g.per[a]) q = q < 0 ? q + nn : (q >= nn ? q - nn : q);
+            if (q < 0 || q >= nn) {
+                ok = false;
+                q = 0;
+            }
+            p[a] = q;
+        }
+        const R val = x[ok ? nid(g, p[0], p[1], p[2]) : 0];
+        v[u] = ok ? val : R(0);
     }
 #pragma unroll
     for (int u = 0; u < K; ++u) {

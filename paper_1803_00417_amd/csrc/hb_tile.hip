@@ -22,33 +22,40 @@ template <> struct TileCfg<2> { static constexpr int TX = 64, TY = 8, TZ = 1, TH
 template <> struct TileCfg<3> { static constexpr int TX = 32, TY = 4, TZ = 4, THREADS = 512; };
 
 
-// Homogeneous (ghost = -mirror) or periodic value of component array q at a
-// global position that may lie outside the box; positions outside along two
-// or more wall axes (never used by the stencil) read as 0.  With MIRROR the
-// wall ghost is the mirrored value itself (used for the viscosity tile).
-template <int DIM, typename R>
-__device__ inline R tile_fetch(const GridD& g, const R* __restrict__ q, int i, int j, int k, bool mirror)
+// Source of a tile position (i, j, k) that may lie outside the box:
+// periodic axes wrap; across a wall the odd reflection about the wall reads
+// the mirrored cell with the opposite sign (homogeneous ghost; arrays filled
+// with `mirror` take the mirrored value itself, as the viscosity tile does);
+// positions outside along two or more wall axes (never used by the stencil)
+// read as 0.  Returns an in-range index always, with valid = false for the
+// zero positions, so the loads of a fill issue without branches around them.
+template <int DIM>
+__device__ inline long tile_src(const GridD& g, int i, int j, int k, bool& valid, bool& neg)
 {
     int p[3] = {i, j, k};
     int out = 0;
-    R sg = 1;
+    valid = true;
+    neg = false;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int n = g.n[a];
-        if (p[a] >= 0 && p[a] < n) continue;
+        int v = p[a];
+        const bool lo = v < 0, hi = v >= n;
         if (g.per[a]) {
-            p[a] = p[a] < 0 ? p[a] + n : p[a] - n;
-            if (p[a] < 0 || p[a] >= n) return R(0);
-        } else {
+            v = lo ? v + n : (hi ? v - n : v);
+        } else if (lo || hi) {
+            v = lo ? -1 - v : 2 * n - 1 - v;
             ++out;
-            p[a] = p[a] < 0 ? -1 - p[a] : 2 * n - 1 - p[a];
-            if (p[a] < 0 || p[a] >= n) return R(0);
-            sg = -sg;
+            neg = !neg;
         }
+        if (v < 0 || v >= n) {
+            valid = false;
+            v = 0;
+        }
+        p[a] = v;
     }
-    if (out > 1) return R(0);
-    const R v = q[cid(g, p[0], p[1], p[2])];
-    return mirror ? v : sg * v;
+    if (out > 1) valid = false;
+    return valid ? cid(g, p[0], p[1], p[2]) : 0;
 }
 
 // LDS tile with halo H around the interior box starting at (ox, oy, oz);
@@ -82,13 +89,12 @@ __device__ inline void fill_batched(const GridD& g, const R* const* q, const boo
         const int tt = t < T::NS ? t : 0;
         const int lx = tt % T::SX, ly = (tt / T::SX) % T::SY, lz = tt / (T::SX * T::SY);
         const int i = ox - H + lx, j = oy - H + ly, k = DIM == 3 ? oz - H + lz : 0;
-        if (inner) {
-            const long idx = cid(g, i, j, k);
+        bool ok = true, ng = false;
+        const long idx = inner ? cid(g, i, j, k) : tile_src<DIM>(g, i, j, k, ok, ng);
 #pragma unroll
-            for (int a = 0; a < NA; ++a) v[a][u] = q[a][idx];
-        } else {
-#pragma unroll
-            for (int a = 0; a < NA; ++a) v[a][u] = tile_fetch<DIM, R>(g, q[a], i, j, k, mirror[a]);
+        for (int a = 0; a < NA; ++a) {
+            const R x = q[a][idx];
+            v[a][u] = ok ? ((ng && !mirror[a]) ? -x : x) : R(0);
         }
     }
 #pragma unroll
@@ -117,13 +123,12 @@ __device__ inline void fill_tile1(const GridD& g, const R* const* q, const bool*
         const int tt = t < T::NS ? t : 0;
         const int lx = tt % T::SX, ly = (tt / T::SX) % T::SY, lz = tt / (T::SX * T::SY);
         const int i = ox - 1 + lx, j = oy - 1 + ly, k = oz - 1 + lz;
-        if (inner) {
-            const long idx = cid(g, i, j, k);
+        bool ok = true, ng = false;
+        const long idx = inner ? cid(g, i, j, k) : tile_src<3>(g, i, j, k, ok, ng);
 #pragma unroll
-            for (int a = 0; a < NA; ++a) v[a][u] = q[a][idx];
-        } else {
-#pragma unroll
-            for (int a = 0; a < NA; ++a) v[a][u] = tile_fetch<3, R>(g, q[a], i, j, k, mirror[a]);
+        for (int a = 0; a < NA; ++a) {
+            const R x = q[a][idx];
+            v[a][u] = ok ? ((ng && !mirror[a]) ? -x : x) : R(0);
         }
     }
 #pragma unroll
