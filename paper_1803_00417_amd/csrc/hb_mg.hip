@@ -144,54 +144,95 @@ void launch_mac_dense(Ctx* c, const GridD& g, int N, const double* E, double* A)
 // ---------------------------------------------------------------------------
 // cell prolongation x_f += P e_c: (bi/tri)linear, 3/4 - 1/4 per axis; a coarse
 // neighbour beyond a wall takes the homogeneous ghost value wall_sign * e.
-// One thread per fine cell.
 // ---------------------------------------------------------------------------
 
-template <typename R>
-__global__ void k_prolong_cells(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct, int ncomp,
+// One thread per coarse cell: the 3^d coarse neighbourhood is read once
+// and the 2^d children are corrected (each child's sum in the same order
+// as a per-child evaluation: the 2^d nearest coarse cells, axis weights 3/4
+// and 1/4).  The block's launch covers the coarse cells of the cavities
+// that smooth on the fine level.
+template <int DIM, typename R>
+__global__ void __launch_bounds__(256) k_prolong_cells(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct, int ncomp,
                                 R wall_sign, const R* __restrict__ ea, R* __restrict__ xa)
 {
-    PT_ENTER(k);
+    PT_ENTER(K);
     const GridD& gf = g;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= gf.n[0] || j >= gf.n[1] || k >= gf.n[2]) return;
     const GridD& gc = gct[cav];   // read in place: a private copy indexed by axis would spill
-    const R* e = ea + ncomp * oct[cav];
-    R* x = xa + ncomp * v.o[cav];
-    const int d = gf.dim;
-    const int fi[3] = {i, j, k};
-    const long Nf = ncells(gf), Nc = ncells(gc);
-    for (int q = 0; q < ncomp; ++q) {
-        R s = 0;
-        for (int bits = 0; bits < (1 << d); ++bits) {
-            int p[3] = {0, 0, 0};
-            R w = 1, sg = 1;
-            for (int a = 0; a < d; ++a) {
-                const int I = fi[a] >> 1;
-                if (!((bits >> a) & 1)) { p[a] = I; w *= R(0.75); continue; }
-                int J = (fi[a] & 1) ? I + 1 : I - 1;
-                w *= R(0.25);
-                if (J < 0 || J >= gc.n[a]) {
-                    if (gc.per[a]) J = J < 0 ? J + gc.n[a] : J - gc.n[a];
-                    else { J = I; sg *= wall_sign; }
-                }
-                p[a] = J;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    if (I >= gc.n[0] || J >= gc.n[1] || K >= gc.n[2]) return;
+    constexpr int d = DIM;   // every loop below unrolls, so the neighbourhood stays in registers
+    const int C[3] = {I, J, K};
+    // per axis: source index and sign of the coarse neighbour at offset -1, 0, +1
+    int src[3][3];
+    R sgn[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            int J2 = C[a] + o - 1;
+            R sg = 1;
+            if (a < d && (J2 < 0 || J2 >= gc.n[a])) {
+                if (gc.per[a]) J2 = J2 < 0 ? J2 + gc.n[a] : J2 - gc.n[a];
+                else { J2 = C[a]; sg = wall_sign; }
             }
-            s += w * sg * e[q * Nc + cid(gc, p[0], p[1], p[2])];
+            if (a >= d) J2 = 0;
+            src[a][o] = J2;
+            sgn[a][o] = sg;
         }
-        x[q * Nf + cid(gf, i, j, k)] += s;
+    const R* e0 = ea + ncomp * oct[cav];
+    R* x0 = xa + ncomp * v.o[cav];
+    const long Nf = ncells(gf), Nc = ncells(gc);
+    constexpr int nz = d == 3 ? 2 : 1;
+    for (int q = 0; q < ncomp; ++q) {
+        const R* e = e0 + q * Nc;
+        R* x = x0 + q * Nf;
+        R nb[3][3][3];
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+                for (int ox = 0; ox < 3; ++ox)
+                    if (d == 3 || oz == 1) nb[oz][oy][ox] = e[cid(gc, src[0][ox], src[1][oy], src[2][oz])];
+#pragma unroll
+        for (int cz = 0; cz < nz; ++cz)
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+                for (int cx = 0; cx < 2; ++cx) {
+                    const int ch[3] = {cx, cy, cz};
+                    R s = 0;
+#pragma unroll
+                    for (int bits = 0; bits < (1 << d); ++bits) {
+                        int o[3] = {1, 1, 1};
+                        R w = 1, sg = 1;
+#pragma unroll
+                        for (int a = 0; a < d; ++a) {
+                            if (!((bits >> a) & 1)) { w *= R(0.75); continue; }
+                            w *= R(0.25);
+                            o[a] = ch[a] ? 2 : 0;   // the neighbour on the child's side
+                            sg *= sgn[a][o[a]];
+                        }
+                        s += w * sg * nb[o[2]][o[1]][o[0]];
+                    }
+                    x[cid(gf, 2 * I + cx, 2 * J + cy, d == 3 ? 2 * K + cz : 0)] += s;
+                }
     }
 }
 
+// grid over the coarse cells of the cavities that smooth on level L
 template <typename R>
 void launch_prolong_cells(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, int ncomp,
                           double wall_sign, const R* e, R* x)
 {
     BV vv = v;
-    vv.zb = L.gmax.n[2];
-    k_prolong_cells<R><<<grid3(L.gmax.n[0], L.gmax.n[1], vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gc, oc, ncomp,
-                                                                                               (R)wall_sign, e, x);
+    const int ex = (L.gmax.n[0] + 1) / 2, ey = (L.gmax.n[1] + 1) / 2, ez = L.gmax.dim == 3 ? (L.gmax.n[2] + 1) / 2 : 1;
+    vv.zb = ez;
+    if (L.gmax.dim == 2)
+        k_prolong_cells<2, R><<<grid3(ex, ey, vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gc, oc, ncomp, (R)wall_sign, e, x);
+    else
+        k_prolong_cells<3, R><<<grid3(ex, ey, vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gc, oc, ncomp, (R)wall_sign, e, x);
 }
 
 // ---------------------------------------------------------------------------

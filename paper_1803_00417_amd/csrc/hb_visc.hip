@@ -131,27 +131,39 @@ void launch_visc_div(Ctx* c, const GridD& g, const double* beta, const double* u
 // out = rhs + dt div(beta gamma_dot(0 with wall values)): the inhomogeneous
 // wall part of the operator moved to the right-hand side.  The stencil of a
 // cell reaches one cell along each axis, so only cells in the first layer
-// along a wall axis see a wall value; elsewhere the term is zero.
+// along a wall axis see a wall value; elsewhere the term is zero.  out = rhs
+// is copied first, then one thread per boundary-layer cell (block z = wall
+// face 2 a + side; a cell on several layers is taken by its lowest axis)
+// adds the wall term.
 __global__ void k_visc_wall_rhs(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ rhs,
                                 double* __restrict__ out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    const long N = ncells(g), q = cid(g, i, j, k);
-    const int p[3] = {i, j, k};
-    bool edge = false;
-    for (int a = 0; a < g.dim; ++a)
-        if (!g.per[a] && (p[a] == 0 || p[a] == g.n[a] - 1)) edge = true;
+    const int a = blockIdx.z >> 1, side = blockIdx.z & 1;
+    if (a >= g.dim || g.per[a]) return;
+    const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;
+    const int u = blockIdx.x * blockDim.x + threadIdx.x, w = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= g.n[b0] || w >= g.n[b1]) return;
+    int p[3];
+    p[a] = side ? g.n[a] - 1 : 0;
+    p[b0] = u;
+    p[b1] = w;
+    for (int b = 0; b < a; ++b)
+        if (!g.per[b] && (p[b] == 0 || p[b] == g.n[b] - 1)) return;
+    const long N = ncells(g), q = cid(g, p[0], p[1], p[2]);
     for (int c = 0; c < g.dim; ++c)
-        out[c * N + q] = edge ? rhs[c * N + q] + dt * visc_div_at<false, true>(g, beta, nullptr, c, i, j, k)
-                              : rhs[c * N + q];
+        out[c * N + q] = rhs[c * N + q] + dt * visc_div_at<false, true>(g, beta, nullptr, c, p[0], p[1], p[2]);
 }
 
 void launch_visc_wall_rhs(Ctx* c, const GridD& g, const double* beta, double dt, const double* rhs, double* out)
 {
-    k_visc_wall_rhs<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, beta, dt, rhs, out);
+    copy(c, out, rhs, (long)g.dim * ncells(g));
+    int e0 = 1, e1 = 1;
+    for (int a = 0; a < g.dim; ++a) {
+        const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;
+        e0 = e0 > g.n[b0] ? e0 : g.n[b0];
+        e1 = e1 > g.n[b1] ? e1 : g.n[b1];
+    }
+    k_visc_wall_rhs<<<grid3(e0, e1, 2 * g.dim, kBlk), kBlk, 0, c->s>>>(g, beta, dt, rhs, out);
 }
 
 // dense matrix of the homogeneous operator, column j = A e_j (E holds the
