@@ -24,6 +24,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+TILE_SOURCE = os.path.join(ROOT, "paper_1803_00417_amd", "csrc", "hb_tile.hip")
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per dispatch of the roofline kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the copy-probe
+    factors), or None when the kernel source has changed since then"""
+    import hashlib
+    if not os.path.exists(TRAFFIC_TABLE):
+        return None
+    sha = hashlib.sha256(open(TILE_SOURCE, "rb").read()).hexdigest()[:16]
+    for line in open(TRAFFIC_TABLE):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, w, fk, wk, fs, ws, src = line.split("\t")
+        if k == kernel and w == workload and src.strip() == sha:
+            return 1024.0 * (float(fk) * float(fs) + float(wk) * float(ws))
+    return None
 
 
 def parse():
@@ -206,8 +225,11 @@ def main():
     launches, kms, kbytes = r["kt"]
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
     w = inputs.WORKLOADS[a.workload]
+    kname = "hb::k_tsmooth<2,true,double>" if w["dim"] == 2 else "hb::k_trb3<true,double>"
+    wname = "cavity2d_512" if w["dim"] == 2 else "cavity3d_128"
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, wname),
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-probe scaled)",
                 "kernel": ("k_tsmooth (2D: fused red-black sweep of one velocity component, finest level)" if w["dim"] == 2 else "k_trb3 (3D: one colour of one velocity component, finest level)"),
                 "launches": launches, "avg_launch_us": 1e3 * kms / max(launches, 1),
                 "alg_bytes_per_launch": kbytes / max(launches, 1)}
