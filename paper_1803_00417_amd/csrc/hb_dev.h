@@ -7,6 +7,7 @@
 namespace hb {
 
 constexpr int kMaxLev = 24;
+constexpr int kMaxTail = 8;   // levels handled by the single-workgroup coarse V-cycle
 
 // Grid of one multigrid level, passed to kernels by value.
 struct GridD {

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -175,6 +176,32 @@ static int build_mg(Ctx* c, MG& m, int op)
         HB_TRY(upload(L.ou, L.hou));
         HB_TRY(upload(L.nuc, L.hnu));
     }
+    // single-workgroup coarse tail: the first level from which every
+    // cavity's remaining levels fit the LDS budget
+    m.tail_lt = -1;
+    if (op == HB_OP_VISC && c->lds_budget > 0) {
+        for (int l = 1; l < m.nlev && m.tail_lt < 0; ++l) {
+            if (m.nlev - l > kMaxTail) continue;
+            size_t need[2] = {0, 0};
+            std::vector<TailPlan> plans(nb);
+            for (int b = 0; b < nb; ++b) {
+                if (m.nlevc[b] - 1 < l) continue;
+                const std::vector<GridD> gl(lg[b].begin() + l, lg[b].end());
+                std::vector<long> gofs;
+                for (int k = l; k < m.nlevc[b]; ++k) gofs.push_back(m.L[k].hof[b]);
+                const long o0 = m.L[l].ho[b];
+                need[0] = std::max(need[0], visc_tail_plan(gl, gofs, o0, sizeof(double), &plans[b]));
+                need[1] = std::max(need[1], visc_tail_plan(gl, gofs, o0, sizeof(float), nullptr));
+            }
+            if (need[0] > 0 && need[0] <= c->lds_budget) {
+                m.tail_lt = l;
+                m.tail_lds[0] = need[0];
+                m.tail_lds[1] = need[1];
+                HB_TRY(dalloc(&m.tplan, nb));
+                HB_TRY(upload(m.tplan, plans));
+            }
+        }
+    }
     // coarsest systems
     m.hcs.resize(nb);
     long aoff = 0, poff = 0;
@@ -229,6 +256,7 @@ static void free_mg(MG& m)
         (void)hipFree(L.nuc);
     }
     (void)hipFree(m.cs);
+    (void)hipFree(m.tplan);
     (void)hipFree(m.A);
     (void)hipFree(m.Ainv);
     (void)hipFree(m.piv);
@@ -388,6 +416,10 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
     Level& L = m.L[l];
     if (l == 1 && !m.capturing && !m.gfail[prec_index<R>()] && m.nlev > 2 && (nu1 + nu2) % 2 == 0) {
         coarse_graph<R>(c, m, nu1, nu2);
+        return;
+    }
+    if (l == m.tail_lt) {
+        launch_visc_tail<R>(c, m, l, nu1, nu2, m.tail_lds[prec_index<R>()], c->act);
         return;
     }
     if (L.any_sm) {
@@ -1037,6 +1069,19 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
                 for (int q = 0; q < 3; ++q) v.ulid = std::fmax(v.ulid, std::fabs(v.g.wall_u[a][s][q]));
         v.sc = c->sc + (long)b * S_NSLOT;
         v.hsc = c->hsc + (long)b * S_NSLOT;
+    }
+    // LDS a coarse-tail workgroup may take: the device's per-workgroup limit
+    // less the kernel's static arrays; HB_TAIL=0 in the environment turns the
+    // tail off (every level then runs its own launches)
+    {
+        int dev = 0, lim = 0;
+        const char* e = std::getenv("HB_TAIL");
+        const bool on = !(e && e[0] == '0');
+        if (on && hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 8192) {
+            c->lds_budget = (size_t)lim - 4096;
+            tail_allow_lds(c->lds_budget);
+        }
     }
     int rc;
     if ((rc = build_mg(c, c->visc, HB_OP_VISC)) != HB_OK) return give_up(rc, c->err);

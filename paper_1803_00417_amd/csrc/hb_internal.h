@@ -145,6 +145,22 @@ struct CoarseD {
     long xoff;      // offset of its unknowns in that level's arenas
 };
 
+// one level of a cavity's coarse tail (hb_tail.hip): its grid, LDS layout
+// (offsets in storage elements) and the offset of its face arrays
+struct TailLevel {
+    int n[3], per[3];
+    int nc, ns, nf;           // cells, halo positions per component, faces
+    int xoff, boff, foff;     // LDS offsets of iterate, right-hand side, faces
+    long gofs;                // face offset of the cavity in the level arena
+    double h;
+};
+struct TailPlan {
+    int nl = 0;               // levels in the tail (0: the cavity ends above it)
+    int roff = 0;             // LDS offset of the residual scratch
+    long o0 = 0;              // component-array offset of the cavity at the first level
+    TailLevel lv[kMaxTail];
+};
+
 struct MG {
     int op = 0;
     int nlev = 0;            // levels of the deepest cavity
@@ -168,6 +184,11 @@ struct MG {
     int gnu1[2] = {-1, -1}, gnu2[2] = {-1, -1};
     bool gfail[2] = {false, false};
     bool capturing = false;
+    // levels tail_lt.. of a V-cycle run by one workgroup per cavity in LDS
+    // (-1: none); its dynamic LDS bytes per precision
+    int tail_lt = -1;
+    size_t tail_lds[2] = {0, 0};
+    TailPlan* tplan = nullptr;    // per cavity (device)
 };
 
 // one cavity of a context: its descriptors and the step's scratch
@@ -231,6 +252,7 @@ struct Ctx {
     bool cap = false;
     double *cap_r0 = nullptr, *cap_e = nullptr, *cap_x0 = nullptr;
     long ws_report_used = 0;      // solves that started from the network's guess
+    size_t lds_budget = 0;        // dynamic LDS bytes a coarse-tail workgroup may use (0: no tail)
     std::string err;
 };
 
@@ -327,6 +349,12 @@ void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* 
 template <typename R>
 void launch_coarse_solve(Ctx* c, const MG& m, int lev, const int* act, const R* b, R* x);
 void launch_identity(Ctx* c, int N, double* E);
+// the coarse end of a V-cycle from level lt in one launch (hb_tail.hip)
+size_t visc_tail_plan(const std::vector<GridD>& levels, const std::vector<long>& gofs, long o0, size_t elem,
+                      TailPlan* out);
+template <typename R>
+void launch_visc_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, const int* act);
+void tail_allow_lds(size_t bytes);
 
 // ---- learned warm start (hb_nn.hip, hb_ws.hip) --------------------------------
 struct NNet;

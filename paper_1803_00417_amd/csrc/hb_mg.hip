@@ -22,7 +22,7 @@ static const dim3 kBlk(64, 4, 1);
     GridD g;                                       \
     if (!bv_enter(v, cav, k, g)) return;
 
-template <typename R>
+template <int DIM, typename R>
 __global__ void k_mac_rb(BV v, int colour, R* __restrict__ xa, const R* __restrict__ ba)
 {
     PT_ENTER(k);
@@ -35,18 +35,26 @@ __global__ void k_mac_rb(BV v, int colour, R* __restrict__ xa, const R* __restri
     const long q = cid(g, i, j, k);
     const R h = (R)g.h;
     const R ih2 = R(1) / (h * h);
+    // all loads first (neighbours beyond a wall read the cell itself and are
+    // masked), then the sum in the order lo, hi per axis
+    const R xq = x[q], bq = b[q];
+    R xn[DIM][2];
+    bool ok[DIM][2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) xn[a][side] = x[nb_cell<DIM>(g, i, j, k, a, side ? 1 : -1, ok[a][side])];
     R Lx = 0;
     int cnt = 0;
-    for (int a = 0; a < g.dim; ++a)
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
-            int p[3] = {i, j, k};
-            p[a] += side ? 1 : -1;
-            if (!wrap(g, p)) continue;
-            Lx += (x[cid(g, p[0], p[1], p[2])] - x[q]) * ih2;
-            ++cnt;
+            Lx += ok[a][side] ? (xn[a][side] - xq) * ih2 : R(0);
+            cnt += ok[a][side] ? 1 : 0;
         }
     const R dg = -(R)cnt * ih2;
-    x[q] += (b[q] - Lx) / dg;
+    x[q] = xq + (bq - Lx) / dg;
 }
 
 template <typename R>
@@ -54,10 +62,13 @@ void launch_mac_rb(Ctx* c, const Level& L, const BV& v, int colour, R* x, const 
 {
     BV vv = v;
     vv.zb = L.gmax.n[2];
-    k_mac_rb<R><<<grid3((L.gmax.n[0] + 1) / 2, L.gmax.n[1], vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, colour, x, b);
+    const dim3 grid = grid3((L.gmax.n[0] + 1) / 2, L.gmax.n[1], vv.zb * c->nb, kBlk);
+    if (L.gmax.dim == 2) k_mac_rb<2, R><<<grid, kBlk, 0, c->s>>>(vv, colour, x, b);
+    else k_mac_rb<3, R><<<grid, kBlk, 0, c->s>>>(vv, colour, x, b);
 }
 
 // r = b - L x (max-norm into each cavity's slot) or y = L x (b null); FP64
+template <int DIM>
 __global__ void k_mac_resid(BV v, const double* __restrict__ xa, const double* __restrict__ ba, double* __restrict__ ra,
                             double* __restrict__ scb, int slot)
 {
@@ -69,7 +80,7 @@ __global__ void k_mac_resid(BV v, const double* __restrict__ xa, const double* _
     unsigned long long m = 0ull;
     if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
         const long q = cid(g, i, j, k);
-        const double Lx = mac_lap_at<double>(g, xa + o, i, j, k);
+        const double Lx = mac_lap_at<DIM, double>(g, xa + o, i, j, k);
         if (ba) {
             const double rv = ba[o + q] - Lx;
             if (ra) ra[o + q] = rv;
@@ -88,12 +99,14 @@ void launch_mac_resid(Ctx* c, const Level& L, const BV& v, const double* x, cons
 {
     BV vv = v;
     vv.zb = L.gmax.n[2];
-    k_mac_resid<<<grid3(L.gmax.n[0], L.gmax.n[1], vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, x, b, r, c->sc, slot);
+    const dim3 grid = grid3(L.gmax.n[0], L.gmax.n[1], vv.zb * c->nb, kBlk);
+    if (L.gmax.dim == 2) k_mac_resid<2><<<grid, kBlk, 0, c->s>>>(vv, x, b, r, c->sc, slot);
+    else k_mac_resid<3><<<grid, kBlk, 0, c->s>>>(vv, x, b, r, c->sc, slot);
 }
 
 // coarse right-hand side = mean of the fine residuals of the 2^d children;
 // the coarse iterate starts from zero.  One thread per coarse cell.
-template <typename R>
+template <int DIM, typename R>
 __global__ void k_mac_resid_restrict(BV v, const GridD* __restrict__ gft, const long* __restrict__ oft,
                                      const R* __restrict__ xfa, const R* __restrict__ bfa, R* __restrict__ bca,
                                      R* __restrict__ xca)
@@ -106,11 +119,12 @@ __global__ void k_mac_resid_restrict(BV v, const GridD* __restrict__ gft, const 
     const GridD& gf = gft[cav];   // read in place: a private copy indexed by axis would spill
     const R* xf = xfa + oft[cav];
     const R* bf = bfa + oft[cav];
-    const int nch = 1 << gf.dim;
+    constexpr int nch = 1 << DIM;
     R s = 0;
+#pragma unroll
     for (int bits = 0; bits < nch; ++bits) {
-        const int fi = 2 * i + (bits & 1), fj = 2 * j + ((bits >> 1) & 1), fk = gf.dim == 3 ? 2 * k + ((bits >> 2) & 1) : 0;
-        s += bf[cid(gf, fi, fj, fk)] - mac_lap_at<R>(gf, xf, fi, fj, fk);
+        const int fi = 2 * i + (bits & 1), fj = 2 * j + ((bits >> 1) & 1), fk = DIM == 3 ? 2 * k + ((bits >> 2) & 1) : 0;
+        s += bf[cid(gf, fi, fj, fk)] - mac_lap_at<DIM, R>(gf, xf, fi, fj, fk);
     }
     const long qc = v.o[cav] + cid(gc, i, j, k);
     bca[qc] = s / (R)nch;
@@ -123,8 +137,9 @@ void launch_mac_resid_restrict(Ctx* c, const Level& C, const BV& vc, const GridD
 {
     BV vv = vc;
     vv.zb = C.gmax.n[2];
-    k_mac_resid_restrict<R><<<grid3(C.gmax.n[0], C.gmax.n[1], vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gf, of_, xf, bf,
-                                                                                                    bc, xc);
+    const dim3 grid = grid3(C.gmax.n[0], C.gmax.n[1], vv.zb * c->nb, kBlk);
+    if (C.gmax.dim == 2) k_mac_resid_restrict<2, R><<<grid, kBlk, 0, c->s>>>(vv, gf, of_, xf, bf, bc, xc);
+    else k_mac_resid_restrict<3, R><<<grid, kBlk, 0, c->s>>>(vv, gf, of_, xf, bf, bc, xc);
 }
 
 __global__ void k_mac_dense(GridD g, int N, const double* __restrict__ E, double* __restrict__ A)
@@ -133,7 +148,8 @@ __global__ void k_mac_dense(GridD g, int N, const double* __restrict__ E, double
     const int col = blockIdx.y;
     if (row >= N) return;
     const int i = row % g.n[0], j = (row / g.n[0]) % g.n[1], k = row / (g.n[0] * g.n[1]);
-    A[(long)row * N + col] = mac_lap_at<double>(g, E + (long)col * N, i, j, k);
+    A[(long)row * N + col] = g.dim == 2 ? mac_lap_at<2, double>(g, E + (long)col * N, i, j, k)
+                                        : mac_lap_at<3, double>(g, E + (long)col * N, i, j, k);
 }
 
 void launch_mac_dense(Ctx* c, const GridD& g, int N, const double* E, double* A)

@@ -114,18 +114,20 @@ k_nodal_gs_tile(BV v, int colour, R* __restrict__ xa, const R* __restrict__ ba)
     NTILE_ENTER(DIM, T);
     R* x = xa + node0;
     const R* b = ba + node0;
-    fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
-    __syncthreads();
     const int tx = threadIdx.x % NodalCfg<DIM>::BX, ty = (threadIdx.x / NodalCfg<DIM>::BX) % NodalCfg<DIM>::BY,
               tz = threadIdx.x / (NodalCfg<DIM>::BX * NodalCfg<DIM>::BY);
     const int G[3] = {ox + 2 * tx + (colour & 1), oy + 2 * ty + ((colour >> 1) & 1),
                       DIM == 3 ? oz + 2 * tz + ((colour >> 2) & 1) : 0};
-    if (G[0] >= nnode(g, 0) || G[1] >= nnode(g, 1) || G[2] >= nnode(g, 2)) return;
+    const bool ok = G[0] < nnode(g, 0) && G[1] < nnode(g, 1) && G[2] < nnode(g, 2);
+    const long q = ok ? nid(g, G[0], G[1], G[2]) : 0;
+    const R bq = b[q];   // in flight with the tile fill
+    fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
+    __syncthreads();
+    if (!ok) return;
     const int l = T::at(G[0] - ox + 1, G[1] - oy + 1, DIM == 3 ? G[2] - oz + 1 : 0);
     R dg;
     const R Kx = tile_K<DIM, R>(g, s, G, l, &dg);
-    const long q = nid(g, G[0], G[1], G[2]);
-    x[q] = s[l] + (b[q] - Kx) / dg;
+    x[q] = s[l] + (bq - Kx) / dg;
 }
 
 // r = b - K x (and, FP64, its max-norm into the cavity's slot) or y = K x
@@ -141,18 +143,35 @@ k_nodal_resid_tile(BV v, const R* __restrict__ xa, const R* __restrict__ ba, R* 
     const R* x = xa + node0;
     const R* b = ba ? ba + node0 : nullptr;
     R* out = outa ? outa + node0 : nullptr;
+    // this thread's nodes and their right-hand sides, loaded with the fill
+    constexpr int NT = T::TX * T::TY * T::TZ, KT = NT / T::THREADS;
+    static_assert(NT % T::THREADS == 0, "whole node slots per thread");
+    bool tOk[KT];
+    long tq[KT];
+    R tb[KT];
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
+        const int t = threadIdx.x + u * T::THREADS;
+        const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
+        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
+        tOk[u] = G[0] < nnode(g, 0) && G[1] < nnode(g, 1) && G[2] < nnode(g, 2);
+        tq[u] = tOk[u] ? nid(g, G[0], G[1], G[2]) : 0;
+        if (b) tb[u] = b[tq[u]];
+    }
     fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
     __syncthreads();
     unsigned long long m = 0ull;
-    for (int t = threadIdx.x; t < T::TX * T::TY * T::TZ; t += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
+        if (!tOk[u]) continue;
+        const int t = threadIdx.x + u * T::THREADS;
         const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
         const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
-        if (G[0] >= nnode(g, 0) || G[1] >= nnode(g, 1) || G[2] >= nnode(g, 2)) continue;
         const int l = T::at(rx + 1, ry + 1, DIM == 3 ? rz + 1 : 0);
         const R Kx = tile_K<DIM, R>(g, s, G, l, nullptr);
-        const long q = nid(g, G[0], G[1], G[2]);
+        const long q = tq[u];
         if (b) {
-            const R rv = b[q] - Kx;
+            const R rv = tb[u] - Kx;
             if (out) out[q] = rv;
             const unsigned long long bv = abits((double)rv);
             m = bv > m ? bv : m;

@@ -80,20 +80,44 @@ __device__ inline double visc_diag(const GridD& g, const double* __restrict__ be
     return 1.0 + dt * coef / (g.h * g.h);
 }
 
+// Index of the face neighbour of cell (i,j,k) along axis a, d = -1 or +1,
+// wrapped on periodic axes.  Always in range: beyond a wall it is the cell
+// itself, with ok = false, so callers load without branching and select.
+template <int DIM>
+__device__ inline long nb_cell(const GridD& g, int i, int j, int k, int a, int d, bool& ok)
+{
+    int p[3] = {i, j, k};
+    const int n = g.n[a];
+    int v = p[a] + d;
+    ok = true;
+    if (v < 0 || v >= n) {
+        if (g.per[a]) v = v < 0 ? v + n : v - n;
+        else { ok = false; v = p[a]; }
+    }
+    p[a] = v;
+    return cid(g, p[0], p[1], p[2]);
+}
+
 // L_mac x at one cell, as the divergence of face gradients (zero flux
-// through walls); the two factors 1/h are applied once, as 1/h^2
-template <typename R>
+// through walls); the two factors 1/h are applied once, as 1/h^2.  All
+// neighbour loads issue before any is used.
+template <int DIM, typename R>
 __device__ inline R mac_lap_at(const GridD& g, const R* __restrict__ x, int i, int j, int k)
 {
     const R h = (R)g.h;
     const R xc = x[cid(g, i, j, k)];
+    R xn[DIM][2];
+    bool ok[DIM][2];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        xn[a][0] = x[nb_cell<DIM>(g, i, j, k, a, -1, ok[a][0])];
+        xn[a][1] = x[nb_cell<DIM>(g, i, j, k, a, +1, ok[a][1])];
+    }
     R s = 0;
-    for (int a = 0; a < g.dim; ++a) {
-        int p[3] = {i, j, k}, m[3] = {i, j, k};
-        p[a] += 1;
-        m[a] -= 1;
-        const R Fhi = wrap(g, p) ? x[cid(g, p[0], p[1], p[2])] - xc : R(0);
-        const R Flo = wrap(g, m) ? xc - x[cid(g, m[0], m[1], m[2])] : R(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const R Fhi = ok[a][1] ? xn[a][1] - xc : R(0);
+        const R Flo = ok[a][0] ? xc - xn[a][0] : R(0);
         s += Fhi - Flo;
     }
     return s * (R(1) / (h * h));

@@ -14,6 +14,7 @@
 // For R = double the arithmetic per cell is the same sequence as the
 // global-memory operator, so results do not depend on the tiling.
 #include "hb_internal.h"
+#include "hb_stencil.h"
 
 namespace hb {
 
@@ -140,79 +141,14 @@ __device__ inline void fill_tile1(const GridD& g, const R* const* q, const bool*
     }
 }
 
-// bit (2a + side) set when face `side` (0 lo, 1 hi) of the cell along a is a
-// wall face
-template <int DIM>
-__device__ inline int wall_mask(const GridD& g, const int G[3])
-{
-    int m = 0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        if (g.per[a]) continue;
-        if (G[a] == 0) m |= 1 << (2 * a);
-        if (G[a] == g.n[a] - 1) m |= 2 << (2 * a);
-    }
-    return m;
-}
-
-// face viscosity from the level's face arrays (coarse levels)
-template <typename R>
-__device__ inline R face_beta_global(const GridD& g, const R* __restrict__ beta, int a, const int G[3], int side)
-{
-    int F[3] = {G[0], G[1], G[2]};
-    F[a] += side;
-    if (g.per[a] && F[a] == g.n[a]) F[a] = 0;
-    return beta[foffset(g, a) + fid(g, a, F[0], F[1], F[2])];
-}
-
-// div(beta gamma_dot(x))_c at a cell of an LDS tile, and the diagonal of the
-// homogeneous operator.  FINE: face viscosities from the eta/Re tile `e`
-// (mean of the two cells, the interior cell on wall faces); otherwise from
-// the global face arrays.  Same arithmetic sequence per face as the
-// global-memory operator.
+// the stencil above on a Tile<DIM, H> (compile-time strides)
 template <int DIM, int H, bool FINE, typename R>
-__device__ inline R tile_visc_div(const GridD& g, const R* __restrict__ beta, const R* s, const R* e, int c,
-                                  const int G[3], int wm, int l0, R dt, R* diag)
+__device__ inline R tile_visc_div(const GridD& g, const R* bfc, const R* s, const R* e, int c, const int G[3], int wm,
+                                  int l0, R dt, R* diag)
 {
-    // Every flux carries one factor 1/h and the divergence another, so the
-    // fluxes are formed in units of h and the sum is scaled by 1/h^2 once
-    // (no divisions in the stencil).
     using T = Tile<DIM, H>;
-    const int off[3] = {1, T::SX, T::SX * T::SY};
-    const R h = (R)g.h;
-    const R ihh = R(1) / (h * h);
-    const R* sc = s + c * T::NS;
-    R acc = 0, coefsum = 0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        R flux[2];
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int lL = l0 + (side - 1) * off[a];
-            const int lR = lL + off[a];
-            const bool wall = (wm >> (2 * a + side)) & 1;
-            R bf;
-            if (FINE) bf = wall ? e[l0] : R(0.5) * (e[lL] + e[lR]);
-            else bf = face_beta_global<R>(g, beta, a, G, side);
-            const R dn = sc[lR] - sc[lL];
-            R f;
-            if (a == c) {
-                f = bf * dn;
-            } else if (wall) {
-                f = bf * R(0.5) * dn;
-            } else {
-                const R* sa = s + a * T::NS;
-                // mean of the two cells' centred transverse differences
-                const R cross = R(0.25) * ((sa[lL + off[c]] - sa[lL - off[c]]) + (sa[lR + off[c]] - sa[lR - off[c]]));
-                f = bf * R(0.5) * (dn + cross);
-            }
-            flux[side] = f;
-            coefsum += (wall ? R(2) : R(1)) * ((a == c) ? R(1) : R(0.5)) * bf;
-        }
-        acc += flux[1] - flux[0];
-    }
-    if (diag) *diag = R(1) + dt * coefsum * ihh;
-    return acc * ihh;
+    (void)G;
+    return visc_div_lds<DIM, FINE, R>(g, bfc, s, T::NS, T::SX, T::SX * T::SY, e, c, wm, l0, dt, diag);
 }
 
 // ---------------------------------------------------------------------------
@@ -288,25 +224,28 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int
     const long N = ncells(g);
     const R* bc = b + c * N;
     // this thread's cells of each colour, and their right-hand sides
+    constexpr int NF = FINE ? 1 : 2 * DIM;
     int rG[KR][3], rL[KR];
     bool rOk[KR];
-    R rB[KR];
+    R rB[KR], rF[KR][NF];
 #pragma unroll
     for (int u = 0; u < KR; ++u) {
         int L[3];
         rOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 1, 0, ox, oy, oz, rG[u], L);
         rL[u] = T::at(L[0], L[1], L[2]);
-        rB[u] = rOk[u] ? bc[cid(g, rG[u][0], rG[u][1], rG[u][2])] : R(0);
+        rB[u] = bc[rOk[u] ? cid(g, rG[u][0], rG[u][1], rG[u][2]) : 0];
+        if (!FINE) load_faces<DIM, R>(g, coef, rG[u], rOk[u], rF[u]);
     }
     int kG[KB][3], kL[KB];
     bool kOk[KB];
-    R kB[KB];
+    R kB[KB], kF[KB][NF];
 #pragma unroll
     for (int u = 0; u < KB; ++u) {
         int L[3];
         kOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 0, 1, ox, oy, oz, kG[u], L);
         kL[u] = T::at(L[0], L[1], L[2]);
-        kB[u] = kOk[u] ? bc[cid(g, kG[u][0], kG[u][1], kG[u][2])] : R(0);
+        kB[u] = bc[kOk[u] ? cid(g, kG[u][0], kG[u][1], kG[u][2]) : 0];
+        if (!FINE) load_faces<DIM, R>(g, coef, kG[u], kOk[u], kF[u]);
     }
     // components already swept in this sweep live in the next buffer
     {
@@ -327,7 +266,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int
     for (int u = 0; u < KR; ++u) {
         if (!rOk[u]) continue;
         R dg;
-        const R vd = tile_visc_div<DIM, 2, FINE, R>(g, coef, s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
+        const R vd = tile_visc_div<DIM, 2, FINE, R>(g, rF[u], s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
         const R Au = sc[rL[u]] - dt * vd;
         sc[rL[u]] += (rB[u] - Au) / dg;
     }
@@ -336,7 +275,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int
     for (int u = 0; u < KB; ++u) {
         if (!kOk[u]) continue;
         R dg;
-        const R vd = tile_visc_div<DIM, 2, FINE, R>(g, coef, s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
+        const R vd = tile_visc_div<DIM, 2, FINE, R>(g, kF[u], s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
         const R Au = sc[kL[u]] - dt * vd;
         sc[kL[u]] += (kB[u] - Au) / dg;
     }
@@ -371,6 +310,26 @@ k_tresid(BV v, const double* __restrict__ coefa, double* __restrict__ scb, const
     double* s = reinterpret_cast<double*>(tile_lds);
     double* e = s + DIM * T::NS;
     const long N = ncells(g);
+    constexpr int NT = T::TX * T::TY * T::TZ, TH = TileCfg<DIM>::THREADS, KT = (NT + TH - 1) / TH;
+    // this thread's cells and, for the residual, their right-hand sides
+    // (loaded with the tile fill)
+    int tG[KT][3];
+    bool tOk[KT];
+    long tq[KT];
+    double tb[KT][DIM];
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
+        const int t = threadIdx.x + u * TH;
+        const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
+        tG[u][0] = ox + rx;
+        tG[u][1] = oy + ry;
+        tG[u][2] = DIM == 3 ? oz + rz : 0;
+        tOk[u] = t < NT && tG[u][0] < g.n[0] && tG[u][1] < g.n[1] && tG[u][2] < g.n[2];
+        tq[u] = tOk[u] ? cid(g, tG[u][0], tG[u][1], tG[u][2]) : 0;
+        if (b)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) tb[u][c] = b[c * N + tq[u]];
+    }
     {
         const double* q[DIM + 1];
         bool mir[DIM + 1];
@@ -381,18 +340,21 @@ k_tresid(BV v, const double* __restrict__ coefa, double* __restrict__ scb, const
     }
     __syncthreads();
     unsigned long long m = 0ull;
-    for (int t = threadIdx.x; t < T::TX * T::TY * T::TZ; t += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
+        if (!tOk[u]) continue;
+        const int t = threadIdx.x + u * TH;
         const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
-        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
-        if (G[0] >= g.n[0] || G[1] >= g.n[1] || G[2] >= g.n[2]) continue;
+        const int* G = tG[u];
         const int l = T::at(rx + 1, ry + 1, DIM == 3 ? rz + 1 : 0);
         const int wm = wall_mask<DIM>(g, G);
-        const long q0 = cid(g, G[0], G[1], G[2]);
+        const long q0 = tq[u];
+#pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const double vd = tile_visc_div<DIM, 1, true, double>(g, coef, s, e, c, G, wm, l, dt, nullptr);
+            const double vd = tile_visc_div<DIM, 1, true, double>(g, nullptr, s, e, c, G, wm, l, dt, nullptr);
             const double Ax = s[c * T::NS + l] - dt * vd;
             if (b) {
-                const double rv = b[c * N + q0] - Ax;
+                const double rv = tb[u][c] - Ax;
                 if (out) out[c * N + q0] = rv;
                 const unsigned long long bv = abits(rv);
                 m = bv > m ? bv : m;
@@ -425,8 +387,27 @@ k_tresid_restr(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct
     R* s = reinterpret_cast<R*>(tile_lds);
     R* e = s + DIM * T::NS;
     R* r = e + T::NS;   // residual of the tile, [c][tile cell]
-    constexpr int NT = T::TX * T::TY * T::TZ;
+    constexpr int NT = T::TX * T::TY * T::TZ, TH = TileCfg<DIM>::THREADS, KT = (NT + TH - 1) / TH;
+    constexpr int NF = FINE ? 1 : 2 * DIM;
     const long N = ncells(g), Nc = ncells(gc);
+    // this thread's cells, their right-hand sides and (coarse levels) face
+    // viscosities, loaded with the tile fill
+    int tG[KT][3];
+    bool tOk[KT];
+    R tb[KT][DIM], tF[KT][NF];
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
+        const int t = threadIdx.x + u * TH;
+        const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
+        tG[u][0] = ox + rx;
+        tG[u][1] = oy + ry;
+        tG[u][2] = DIM == 3 ? oz + rz : 0;
+        tOk[u] = t < NT && tG[u][0] < g.n[0] && tG[u][1] < g.n[1] && tG[u][2] < g.n[2];
+        const long q0 = tOk[u] ? cid(g, tG[u][0], tG[u][1], tG[u][2]) : 0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) tb[u][c] = b[c * N + q0];
+        if (!FINE) load_faces<DIM, R>(g, coef, tG[u], tOk[u], tF[u]);
+    }
     {
         const R* q[DIM + 1];
         bool mir[DIM + 1];
@@ -436,17 +417,19 @@ k_tresid_restr(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct
         fill_batched<DIM, 1, DIM + (FINE ? 1 : 0), R>(g, q, mir, s, ox, oy, oz);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < NT; t += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
+        if (!tOk[u]) continue;
+        const int t = threadIdx.x + u * TH;
         const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
-        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
-        if (G[0] >= g.n[0] || G[1] >= g.n[1] || G[2] >= g.n[2]) continue;
+        const int* G = tG[u];
         const int l = T::at(rx + 1, ry + 1, DIM == 3 ? rz + 1 : 0);
         const int wm = wall_mask<DIM>(g, G);
-        const long q0 = cid(g, G[0], G[1], G[2]);
+#pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const R vd = tile_visc_div<DIM, 1, FINE, R>(g, coef, s, e, c, G, wm, l, dt, nullptr);
+            const R vd = tile_visc_div<DIM, 1, FINE, R>(g, tF[u], s, e, c, G, wm, l, dt, nullptr);
             const R Ax = s[c * T::NS + l] - dt * vd;
-            r[c * NT + t] = b[c * N + q0] - Ax;
+            r[c * NT + t] = tb[u][c] - Ax;
         }
     }
     __syncthreads();
@@ -499,7 +482,10 @@ k_trb3(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c,
     const int G[3] = {ox + 2 * px + ((ox + oy + ry + oz + rz + colour) & 1), oy + ry, oz + rz};
     const bool ok = G[0] < g.n[0] && G[1] < g.n[1] && G[2] < g.n[2];
     const long q0 = ok ? cid(g, G[0], G[1], G[2]) : 0;
-    const R bv = ok ? b[c * N + q0] : R(0);
+    const R bv = b[c * N + q0];
+    constexpr int NF = FINE ? 1 : 6;
+    R bf[NF];
+    if (!FINE) load_faces<3, R>(g, coef, G, ok, bf);
     {
         const R* q[4] = {x, x + N, x + 2 * N, coef};
         const bool mir[4] = {false, false, false, true};
@@ -509,7 +495,7 @@ k_trb3(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c,
     if (!ok) return;
     const int l = T::at(G[0] - ox + 1, ry + 1, rz + 1);
     R dg;
-    const R vd = tile_visc_div<3, 1, FINE, R>(g, coef, s, e, c, G, wall_mask<3>(g, G), l, dt, &dg);
+    const R vd = tile_visc_div<3, 1, FINE, R>(g, bf, s, e, c, G, wall_mask<3>(g, G), l, dt, &dg);
     const R xc = s[c * T::NS + l];
     const R Au = xc - dt * vd;
     x[c * N + q0] = xc + (bv - Au) / dg;

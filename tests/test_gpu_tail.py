@@ -1,0 +1,115 @@
+"""The single-workgroup coarse V-cycle (one launch for every level below a
+size limit, data in LDS) against the per-level launches it replaces.
+
+Both run the same arithmetic per cell in the same order (red-black
+Gauss-Seidel component by component, the same residual, restriction,
+prolongation and FP64 coarsest solve), with FP contraction off, so whole
+steps agree bit for bit, cycle counts included.  The per-level path is
+itself held to the oracle by the parity tests, which run with the tail on;
+the cases cover walls, periodic axes, odd coarsest extents, 2D and 3D, FP64
+and mixed precision, and a batch of uneven cavities.  HB_TAIL=0 in the
+environment at context creation turns the tail off.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import orc
+from tests.helpers import dev, hip_objs, host, lid_spec, oracle_objs, spec
+
+pytestmark = pytest.mark.gpu
+
+hb = pytest.importorskip("paper_1803_00417_amd.hb")
+
+CASES = {
+    "lid2d_64": lambda: lid_spec(2, 64, Re=100.0, HB=1.0, Pa=1e3),
+    "lid2d_96x48": lambda: spec(2, [96, 48], h=1.0 / 96, wall_u={(1, 1): (1.0, 0.0, 0.0)}, Re=50.0, HB=2.0,
+                                nidx=0.7, Pa=300.0),
+    "per2d_32": lambda: spec(2, 32, bc=((1, 1), (1, 1)), Re=10.0, HB=0.5, nidx=1.3, Pa=100.0),
+    "chan2d_8x32": lambda: spec(2, [8, 32], h=1.0 / 32, bc=((1, 1), (0, 0)), Re=1.0, HB=0.2, Pa=1e3,
+                                f=(1.0, 0.0, 0.0)),
+    "lid3d_16": lambda: lid_spec(3, 16, Re=100.0, HB=2.0, Pa=1e3),
+    "mix3d_12x16x8": lambda: spec(3, [12, 16, 8], h=1.0 / 16, bc=((1, 1), (0, 0), (0, 0)),
+                                  wall_u={(2, 1): (1.0, 0.5, 0.0)}, Re=20.0, HB=1.0, nidx=0.6, Pa=200.0),
+}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _context(make, tail):
+    old = os.environ.get("HB_TAIL")
+    os.environ["HB_TAIL"] = "1" if tail else "0"
+    try:
+        return make()
+    finally:
+        if old is None:
+            del os.environ["HB_TAIL"]
+        else:
+            os.environ["HB_TAIL"] = old
+
+
+def _start(s):
+    go, _ = oracle_objs(s)
+    u = np.zeros(orc.cell_shape(go, s["dim"]))
+    if s["bc"] is not None and all(b == (1, 1) for b in s["bc"]):
+        # a fully periodic box has no moving wall: start from a smooth field
+        from paper_1803_00417_amd import inputs
+        u = inputs.smooth_cells(u.shape, seed=31, scale=0.5)
+    return u, np.zeros(orc.node_shape(go))
+
+
+def _dt(s):
+    # a forced channel at rest has no velocity scale: fixed dt
+    return 0.01 if any(f != 0.0 for f in s["f"]) else 0.0
+
+
+def _steps(s, tail, nsteps, **opt):
+    g, fl = hip_objs(s)
+    ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts(**opt)), tail)
+    u0, p0 = _start(s)
+    u, p = dev(u0), dev(p0)
+    cyc = []
+    for _ in range(nsteps):
+        rep = ctx.step(u, p, _dt(s))
+        cyc.append((rep.mac.cycles, rep.visc.cycles, rep.proj.cycles))
+    ctx.close()
+    return host(u), host(p), cyc
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tail_equals_per_level_launches(case, precision):
+    _say("tail", case, precision)
+    s = CASES[case]()
+    opt = {} if precision == "fp64" else {"precision": hb.PREC_MIXED}
+    u1, p1, c1 = _steps(s, True, 4, **opt)
+    u0, p0, c0 = _steps(s, False, 4, **opt)
+    _say("  cycles (mac, visc, proj) per step:", c1)
+    assert c1 == c0
+    assert np.array_equal(u1, u0) and np.array_equal(p1, p0)
+
+
+def test_tail_in_batch_equals_per_level_launches():
+    _say("tail batch")
+    specs = [CASES["lid2d_64"](), CASES["lid2d_96x48"](), lid_spec(2, 16, Re=5.0, HB=3.0, nidx=0.4, Pa=400.0),
+             CASES["chan2d_8x32"]()]
+    outs = []
+    for tail in (True, False):
+        objs = [hip_objs(s) for s in specs]
+        ctx = _context(lambda: hb.BatchContext([g for g, _ in objs], [f for _, f in objs], hb.make_step_opts()),
+                       tail)
+        us, ps = [], []
+        for s in specs:
+            u0, p0 = _start(s)
+            us.append(dev(u0))
+            ps.append(dev(p0))
+        for _ in range(3):
+            ctx.step(us, ps, [_dt(s) for s in specs])
+        outs.append(([host(u) for u in us], [host(p) for p in ps]))
+        ctx.close()
+    for b in range(len(specs)):
+        assert np.array_equal(outs[0][0][b], outs[1][0][b]), b
+        assert np.array_equal(outs[0][1][b], outs[1][1][b]), b
