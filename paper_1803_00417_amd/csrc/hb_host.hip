@@ -358,6 +358,10 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps)
                     launch_trb3<R>(c, L, v, tcoef<R>(m, l), l == 0, q, colour, B::x(L), B::b(L));
         } else if (m.op == HB_OP_MAC) {
             for (int colour = 0; colour < 2; ++colour) launch_mac_rb<R>(c, L, v, colour, B::x(L), B::b(L));
+        } else if (c->fuse) {
+            // all colours of a sweep in one launch (two in 3D) into the other buffer
+            launch_nodal_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L));
+            L.cur ^= 1;
         } else {
             for (int colour = 0; colour < (1 << c->dim); ++colour) launch_nodal_gs<R>(c, L, v, colour, B::x(L), B::b(L));
         }
@@ -1041,6 +1045,8 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
     bool ok = dalloc(&c->sc, (long)S_NSLOT * count) == hipSuccess &&
               hipHostMalloc((void**)&c->hsc, sizeof(double) * S_NSLOT * count) == hipSuccess &&
               dalloc(&c->partial, (long)kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
+              dalloc(&c->mpart, (long)kSubMax * count) == hipSuccess &&
+              hipMemsetAsync(c->mpart, 0, sizeof(unsigned long long) * kSubMax * count, c->s) == hipSuccess &&
               dalloc(&c->act2, count) == hipSuccess && dalloc(&c->sel, count) == hipSuccess &&
               hipHostMalloc((void**)&c->hact, sizeof(int) * count) == hipSuccess &&
               hipHostMalloc((void**)&c->hact2, sizeof(int) * count) == hipSuccess &&
@@ -1077,6 +1083,9 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         int dev = 0, lim = 0;
         const char* e = std::getenv("HB_TAIL");
         const bool on = !(e && e[0] == '0');
+        // HB_FUSE=0: one launch per colour in the nodal smoother
+        const char* f = std::getenv("HB_FUSE");
+        c->fuse = !(f && f[0] == '0');
         if (on && hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 8192) {
             c->lds_budget = (size_t)lim - 4096;
@@ -1138,6 +1147,7 @@ static void destroy_ctx(Ctx* c)
     double* bufs[] = {c->macphi, c->ustar, c->phi, c->kr, c->krh, c->kp, c->kv, c->kph, c->ks, c->ksh, c->kt,
                       c->sc, c->partial};
     for (double* p : bufs) (void)hipFree(p);
+    (void)hipFree(c->mpart);
     (void)hipFree(c->act);
     (void)hipFree(c->act2);
     (void)hipFree(c->sel);

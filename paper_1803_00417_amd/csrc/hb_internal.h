@@ -236,6 +236,7 @@ struct Ctx {
     double* sc = nullptr;        // device scalar slots, S_NSLOT per cavity
     double* hsc = nullptr;       // pinned host mirror
     double* partial = nullptr;   // reduction partials (kRedBlocks per cavity)
+    unsigned long long* mpart = nullptr;   // max-norm partials (kSubMax per cavity, kept zero between uses)
     int* act = nullptr;          // device active flags (nb)
     int* hact = nullptr;         // pinned host staging of the flags
     int* act2 = nullptr;         // second flag set (cavities finishing at a half step)
@@ -253,6 +254,7 @@ struct Ctx {
     double *cap_r0 = nullptr, *cap_e = nullptr, *cap_x0 = nullptr;
     long ws_report_used = 0;      // solves that started from the network's guess
     size_t lds_budget = 0;        // dynamic LDS bytes a coarse-tail workgroup may use (0: no tail)
+    bool fuse = true;             // fused-colour nodal sweeps
     std::string err;
 };
 
@@ -263,6 +265,17 @@ void kt_harvest(Ctx* c);
 // ---- launch helpers --------------------------------------------------------
 inline dim3 grid3(int ex, int ey, int ez, dim3 blk) { return dim3((ex + blk.x - 1) / blk.x, (ey + blk.y - 1) / blk.y, ez); }
 constexpr int kRedBlocks = 512;   // fixed block count per cavity: deterministic sums
+constexpr int kSubMax = 1024;     // max-norm partial words per cavity
+
+// Max-norm partial of one block of cavity cav (bit pattern of |v|, as
+// abits): the blocks of a cavity spread their atomics over kSubMax words, so
+// thousands of blocks do not queue on one address; launch_max_final then
+// combines the words into the cavity's slot and clears them.
+__device__ inline void max_partial(unsigned long long* mp, int cav, long blk, unsigned long long m)
+{
+    if (m) atomicMax(mp + (long)cav * kSubMax + (blk & (kSubMax - 1)), m);
+}
+void launch_max_final(Ctx* c, const int* act, int slot);
 
 // ---- reductions and vector kernels (hb_reduce.hip) -------------------------
 // single-array forms, result into slot of cavity cav
@@ -333,6 +346,9 @@ template <typename R>
 void launch_prolong_cells(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, int ncomp,
                           double wall_sign, const R* e, R* x);
 template <typename R> void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b);
+// one whole Gauss-Seidel sweep from cur into next (one launch, two in 3D)
+template <typename R>
+void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b);
 // r = b - K x (slot >= 0: FP64 only, max-norm into each cavity's slot) or y = K x (b null)
 template <typename R>
 void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R* b, R* r, int slot);

@@ -70,7 +70,7 @@ void launch_mac_rb(Ctx* c, const Level& L, const BV& v, int colour, R* x, const 
 // r = b - L x (max-norm into each cavity's slot) or y = L x (b null); FP64
 template <int DIM>
 __global__ void k_mac_resid(BV v, const double* __restrict__ xa, const double* __restrict__ ba, double* __restrict__ ra,
-                            double* __restrict__ scb, int slot)
+                            unsigned long long* __restrict__ mp, int slot)
 {
     __shared__ unsigned long long sh[16];
     PT_ENTER(k);
@@ -91,7 +91,8 @@ __global__ void k_mac_resid(BV v, const double* __restrict__ xa, const double* _
     }
     if (slot >= 0) {
         m = block_umax(m, sh);
-        if (threadIdx.x + threadIdx.y == 0) atomic_max_bits(scb + (long)cav * S_NSLOT + slot, m);
+        if (threadIdx.x + threadIdx.y == 0)
+            max_partial(mp, cav, ((long)k * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x, m);
     }
 }
 
@@ -100,14 +101,15 @@ void launch_mac_resid(Ctx* c, const Level& L, const BV& v, const double* x, cons
     BV vv = v;
     vv.zb = L.gmax.n[2];
     const dim3 grid = grid3(L.gmax.n[0], L.gmax.n[1], vv.zb * c->nb, kBlk);
-    if (L.gmax.dim == 2) k_mac_resid<2><<<grid, kBlk, 0, c->s>>>(vv, x, b, r, c->sc, slot);
-    else k_mac_resid<3><<<grid, kBlk, 0, c->s>>>(vv, x, b, r, c->sc, slot);
+    if (L.gmax.dim == 2) k_mac_resid<2><<<grid, kBlk, 0, c->s>>>(vv, x, b, r, c->mpart, slot);
+    else k_mac_resid<3><<<grid, kBlk, 0, c->s>>>(vv, x, b, r, c->mpart, slot);
+    if (slot >= 0) launch_max_final(c, vv.act, slot);
 }
 
 // coarse right-hand side = mean of the fine residuals of the 2^d children;
 // the coarse iterate starts from zero.  One thread per coarse cell.
 template <int DIM, typename R>
-__global__ void k_mac_resid_restrict(BV v, const GridD* __restrict__ gft, const long* __restrict__ oft,
+__global__ void __launch_bounds__(256) k_mac_resid_restrict(BV v, const GridD* __restrict__ gft, const long* __restrict__ oft,
                                      const R* __restrict__ xfa, const R* __restrict__ bfa, R* __restrict__ bca,
                                      R* __restrict__ xca)
 {
@@ -256,8 +258,9 @@ void launch_prolong_cells(Ctx* c, const Level& L, const BV& v, const GridD* gc, 
 // ---------------------------------------------------------------------------
 
 // full weighting R = P^T from the fine residual r_f; coarse iterate zeroed.
-// One thread per coarse node.
-template <typename R>
+// One thread per coarse node; the 3^d fine neighbours (x fastest) are loaded
+// first (beyond a wall: an in-range index, masked), then summed in order.
+template <int DIM, typename R>
 __global__ void k_nodal_restrict(BV v, const GridD* __restrict__ gft, const long* __restrict__ oft,
                                  const R* __restrict__ rfa, R* __restrict__ bca, R* __restrict__ xca)
 {
@@ -268,28 +271,40 @@ __global__ void k_nodal_restrict(BV v, const GridD* __restrict__ gft, const long
     if (i >= nnode(gc, 0) || j >= nnode(gc, 1) || k >= nnode(gc, 2)) return;
     const GridD& gf = gft[cav];   // read in place: a private copy indexed by axis would spill
     const R* rf = rfa + oft[cav];
-    const int d = gf.dim;
     const int I[3] = {i, j, k};
-    int nt = 1;
-    for (int a = 0; a < d; ++a) nt *= 3;
-    R s = 0;
+    constexpr int nt = DIM == 3 ? 27 : 9;
+    R val[nt];
+    bool okv[nt];
+#pragma unroll
     for (int t = 0; t < nt; ++t) {
         int tt = t, p[3] = {0, 0, 0};
-        R w = 1;
         bool ok = true;
-        for (int a = 0; a < d; ++a) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
             const int del = tt % 3 - 1;
             tt /= 3;
-            if (del != 0) w *= R(0.5);
             int F = 2 * I[a] + del;
             const int nf = nnode(gf, a);
             if (F < 0 || F >= nf) {
                 if (gf.per[a]) F = F < 0 ? F + nf : F - nf;
-                else ok = false;
+                else { ok = false; F = 0; }
             }
             p[a] = F;
         }
-        if (ok) s += w * rf[nid(gf, p[0], p[1], p[2])];
+        okv[t] = ok;
+        val[t] = rf[nid(gf, p[0], p[1], p[2])];
+    }
+    R s = 0;
+#pragma unroll
+    for (int t = 0; t < nt; ++t) {
+        int tt = t;
+        R w = 1;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            if (tt % 3 != 1) w *= R(0.5);
+            tt /= 3;
+        }
+        s = okv[t] ? s + w * val[t] : s;
     }
     const long q = v.o[cav] + nid(gc, i, j, k);
     bca[q] = s;
@@ -302,12 +317,16 @@ void launch_nodal_restrict(Ctx* c, const Level& C, const BV& vc, const GridD* gf
 {
     BV vv = vc;
     vv.zb = nnode(C.gmax, 2);
-    k_nodal_restrict<R><<<grid3(nnode(C.gmax, 0), nnode(C.gmax, 1), vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gf, of_,
-                                                                                                          rf, bc, xc);
+    const dim3 grid = grid3(nnode(C.gmax, 0), nnode(C.gmax, 1), vv.zb * c->nb, kBlk);
+    if (C.gmax.dim == 2) k_nodal_restrict<2, R><<<grid, kBlk, 0, c->s>>>(vv, gf, of_, rf, bc, xc);
+    else k_nodal_restrict<3, R><<<grid, kBlk, 0, c->s>>>(vv, gf, of_, rf, bc, xc);
 }
 
-// (bi/tri)linear nodal prolongation x_f += P e_c; one thread per fine node
-template <typename R>
+// x_f += P e_c, P the (bi/tri)linear nodal interpolation: a fine node takes
+// the mean of the coarse nodes of its coarse edge, face or cell.  One thread
+// per fine node; the 2^d candidate coarse nodes are loaded first, then
+// summed in order.
+template <int DIM, typename R>
 __global__ void k_nodal_prolong(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct,
                                 const R* __restrict__ ea, R* __restrict__ xa)
 {
@@ -318,17 +337,20 @@ __global__ void k_nodal_prolong(BV v, const GridD* __restrict__ gct, const long*
     if (i >= nnode(gf, 0) || j >= nnode(gf, 1) || k >= nnode(gf, 2)) return;
     const GridD& gc = gct[cav];   // read in place: a private copy indexed by axis would spill
     const R* e = ea + oct[cav];
-    const int d = gf.dim;
     const int F[3] = {i, j, k};
-    R s = 0;
-    for (int bits = 0; bits < (1 << d); ++bits) {
+    constexpr int nt = 1 << DIM;
+    R val[nt], wv[nt];
+    bool okv[nt];
+#pragma unroll
+    for (int bits = 0; bits < nt; ++bits) {
         int p[3] = {0, 0, 0};
         R w = 1;
         bool ok = true;
-        for (int a = 0; a < d; ++a) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
             const int hi = (bits >> a) & 1;
             if (!(F[a] & 1)) {
-                if (hi) { ok = false; break; }
+                if (hi) ok = false;
                 p[a] = F[a] >> 1;
             } else {
                 w *= R(0.5);
@@ -337,8 +359,13 @@ __global__ void k_nodal_prolong(BV v, const GridD* __restrict__ gct, const long*
                 p[a] = C;
             }
         }
-        if (ok) s += w * e[nid(gc, p[0], p[1], p[2])];
+        okv[bits] = ok;
+        wv[bits] = w;
+        val[bits] = e[nid(gc, p[0], p[1], p[2])];
     }
+    R s = 0;
+#pragma unroll
+    for (int bits = 0; bits < nt; ++bits) s = okv[bits] ? s + wv[bits] * val[bits] : s;
     xa[v.o[cav] + nid(gf, i, j, k)] += s;
 }
 
@@ -347,8 +374,9 @@ void launch_nodal_prolong(Ctx* c, const Level& L, const BV& v, const GridD* gc, 
 {
     BV vv = v;
     vv.zb = nnode(L.gmax, 2);
-    k_nodal_prolong<R><<<grid3(nnode(L.gmax, 0), nnode(L.gmax, 1), vv.zb * c->nb, kBlk), kBlk, 0, c->s>>>(vv, gc, oc, e,
-                                                                                                         x);
+    const dim3 grid = grid3(nnode(L.gmax, 0), nnode(L.gmax, 1), vv.zb * c->nb, kBlk);
+    if (L.gmax.dim == 2) k_nodal_prolong<2, R><<<grid, kBlk, 0, c->s>>>(vv, gc, oc, e, x);
+    else k_nodal_prolong<3, R><<<grid, kBlk, 0, c->s>>>(vv, gc, oc, e, x);
 }
 
 // ---------------------------------------------------------------------------

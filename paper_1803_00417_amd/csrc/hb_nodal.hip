@@ -28,11 +28,11 @@ struct NTile {
     __device__ static inline int at(int lx, int ly, int lz) { return (lz * SY + ly) * SX + lx; }
 };
 
-// K x at node G from the LDS tile (local index l), and the diagonal
+// K x at node G from an LDS node block with y stride sx and z stride sxy
+// (local index l), and the diagonal
 template <int DIM, typename R>
-__device__ inline R tile_K(const GridD& g, const R* s, const int G[3], int l, R* diag)
+__device__ inline R block_K(const GridD& g, const R* s, int sx, int sxy, const int G[3], int l, R* diag)
 {
-    using T = NTile<DIM>;
     int cnt[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -47,10 +47,18 @@ __device__ inline R tile_K(const GridD& g, const R* s, const int G[3], int l, R*
             for (int dx = -1; dx <= 1; ++dx) {
                 const int k = (dx != 0) + (dy != 0) + (dz != 0);
                 const R w = (R)(q1_ke(DIM, g.h, k) * (double)(cnt[0][dx + 1] * cnt[1][dy + 1] * cnt[2][dz + 1]));
-                acc += w * s[l + (dz * T::SY + dy) * T::SX + dx];
+                acc += w * s[l + dz * sxy + dy * sx + dx];
             }
     if (diag) *diag = (R)(q1_ke(DIM, g.h, 0) * (double)(cnt[0][1] * cnt[1][1] * cnt[2][1]));
     return acc;
+}
+
+// the same on an NTile
+template <int DIM, typename R>
+__device__ inline R tile_K(const GridD& g, const R* s, const int G[3], int l, R* diag)
+{
+    using T = NTile<DIM>;
+    return block_K<DIM, R>(g, s, T::SX, T::SX * T::SY, G, l, diag);
 }
 
 // stage the node tile plus a 1-node halo; all loads of a thread are issued
@@ -134,7 +142,7 @@ k_nodal_gs_tile(BV v, int colour, R* __restrict__ xa, const R* __restrict__ ba)
 template <int DIM, typename R>
 __global__ void __launch_bounds__(NTile<DIM>::THREADS)
 k_nodal_resid_tile(BV v, const R* __restrict__ xa, const R* __restrict__ ba, R* __restrict__ outa,
-                   double* __restrict__ scb, int slot)
+                   unsigned long long* __restrict__ mp, int slot)
 {
     using T = NTile<DIM>;
     __shared__ R s[T::NS];
@@ -181,7 +189,156 @@ k_nodal_resid_tile(BV v, const R* __restrict__ xa, const R* __restrict__ ba, R* 
     }
     if (slot >= 0) {
         m = block_umax(m, red);
-        if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav * S_NSLOT + slot, m);
+        if (threadIdx.x == 0) max_partial(mp, cav, ((long)bz * gridDim.y + tby) * gridDim.x + tbx, m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused colour sweep.  The 2^d colours (i&1) + 2(j&1) + 4(k&1) of a sweep run
+// in order; the four in-plane colours of the planes of one z parity depend
+// only on each other and on the planes of the other parity.  One launch
+// therefore runs all four in-plane colours on the planes of one parity (2D:
+// the whole sweep; 3D: even planes, then odd planes).  Within the tile's
+// planes colour c is updated on the tile grown by the rings its successors
+// read (x by 3, 2, 1, 0 and y by 1, 1, 0, 0 for c = 0..3, since colour 1
+// neighbours colour 0 along x, colour 2 neighbours it along y and colour 1
+// diagonally, colour 3 neighbours all three), so the staged block needs a
+// halo of 4 nodes in x and 2 in y.  Blocks read `cur` and write the planes
+// they update to `next` (other blocks still read the old values); in 3D the
+// odd-parity launch reads the even planes from `next`.  Every node sees the
+// same neighbour values as in the one-colour-per-launch order, so the result
+// is the same bit for bit.
+// ---------------------------------------------------------------------------
+template <int DIM> struct NG4;
+template <> struct NG4<2> { static constexpr int TX = 64, TY = 16, PZ = 1, TH = 256; };
+template <> struct NG4<3> { static constexpr int TX = 64, TY = 8, PZ = 2, TH = 256; };
+
+template <int DIM>
+struct NG4Tile {
+    using C = NG4<DIM>;
+    static constexpr int HX = 4, HY = 2;                   // halo of x
+    static constexpr int SX = C::TX + 2 * HX, SY = C::TY + 2 * HY, SZ = DIM == 3 ? 2 * C::PZ + 1 : 1;
+    static constexpr int NS = SX * SY * SZ;
+    static constexpr int BX = C::TX + 6, BY = C::TY + 2;  // b on the colour-0 region
+    static constexpr int NB = BX * BY * C::PZ;
+};
+
+template <int DIM, typename R>
+__global__ void __launch_bounds__(NG4<DIM>::TH)
+k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* nexta, const R* __restrict__ ba)
+{
+    using T = NG4Tile<DIM>;
+    using CF = NG4<DIM>;
+    constexpr int TH = CF::TH;
+    __shared__ R s[T::NS];
+    __shared__ R sb[T::NB];
+    int cav, bz, tbx, tby, tbz;
+    GridD g;
+    xcd_tile(tbx, tby, tbz);
+    if (!bv_enter_at(v, tbz, cav, bz, g)) return;
+    const int nn[3] = {nnode(g, 0), nnode(g, 1), nnode(g, 2)};
+    const int ox = tbx * CF::TX, oy = tby * CF::TY;
+    const int kb = DIM == 3 ? zpar + 2 * bz * CF::PZ : 0;   // first updated plane
+    if (ox >= nn[0] || oy >= nn[1] || kb >= nn[2]) return;
+    const long node0 = v.o[cav];
+    const R* cur = cura + node0;
+    const R* fix = fixa + node0;
+    R* next = nexta + node0;
+    const R* b = ba + node0;
+    // stage x (all planes kb-1 .. kb+2PZ-1; halo 4 in x, 2 in y) and b (the
+    // updated planes on the colour-0 region); positions beyond a wall are 0,
+    // periodic axes wrap; every load uses an in-range index
+    {
+        constexpr int K = (T::NS + TH - 1) / TH;
+        R vx[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int t = threadIdx.x + u * TH;
+            const int tt = t < T::NS ? t : 0;
+            const int lx = tt % T::SX, ly = (tt / T::SX) % T::SY, lz = tt / (T::SX * T::SY);
+            int p[3] = {ox - T::HX + lx, oy - T::HY + ly, DIM == 3 ? kb - 1 + lz : 0};
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                int q = p[a];
+                if (g.per[a]) q = q < 0 ? q + nn[a] : (q >= nn[a] ? q - nn[a] : q);
+                if (q < 0 || q >= nn[a]) { ok = false; q = 0; }
+                p[a] = q;
+            }
+            const bool upd = DIM == 2 || ((p[2] & 1) == zpar);
+            const R* src = upd ? cur : fix;
+            const R val = src[nid(g, p[0], p[1], p[2])];
+            vx[u] = ok ? val : R(0);
+        }
+        constexpr int KB = (T::NB + TH - 1) / TH;
+        R vb[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int t = threadIdx.x + u * TH;
+            const int tt = t < T::NB ? t : 0;
+            const int lx = tt % T::BX, ly = (tt / T::BX) % T::BY, lz = tt / (T::BX * T::BY);
+            int p[3] = {ox - 3 + lx, oy - 1 + ly, DIM == 3 ? kb + 2 * lz : 0};
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                int q = p[a];
+                if (g.per[a]) q = q < 0 ? q + nn[a] : (q >= nn[a] ? q - nn[a] : q);
+                if (q < 0 || q >= nn[a]) { ok = false; q = 0; }
+                p[a] = q;
+            }
+            const R val = b[nid(g, p[0], p[1], p[2])];
+            vb[u] = ok ? val : R(0);
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int t = threadIdx.x + u * TH;
+            if (t < T::NS) s[t] = vx[u];
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int t = threadIdx.x + u * TH;
+            if (t < T::NB) sb[t] = vb[u];
+        }
+    }
+    __syncthreads();
+    // the four in-plane colours, each on its region of every updated plane
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+        const int gx = cc == 0 ? 3 : (cc == 1 ? 2 : (cc == 2 ? 1 : 0));
+        const int gy = cc <= 1 ? 1 : 0;
+        const int px = cc & 1, py = (cc >> 1) & 1;
+        // region [ox - gx, ox + TX + gx) x [oy - gy, oy + TY + gy); the first
+        // node of colour parity px along x, py along y
+        const int x0 = ox - gx, y0 = oy - gy;
+        const int fx = x0 + (((x0 & 1) != px) ? 1 : 0), fy = y0 + (((y0 & 1) != py) ? 1 : 0);
+        const int wx = (ox + CF::TX + gx - fx + 1) / 2, wy = (oy + CF::TY + gy - fy + 1) / 2;
+        const int cnt = wx * wy * CF::PZ;
+        for (int t = threadIdx.x; t < cnt; t += TH) {
+            const int ix = t % wx, iy = (t / wx) % wy, m = t / (wx * wy);
+            int G[3] = {fx + 2 * ix, fy + 2 * iy, DIM == 3 ? kb + 2 * m : 0};
+            const int lx = G[0] - ox + T::HX, ly = G[1] - oy + T::HY, lz = DIM == 3 ? 1 + 2 * m : 0;
+            const int lb = (m * T::BY + (G[1] - oy + 1)) * T::BX + (G[0] - ox + 3);
+            bool inside = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                if (G[a] >= 0 && G[a] < nn[a]) continue;
+                if (g.per[a]) G[a] = G[a] < 0 ? G[a] + nn[a] : G[a] - nn[a];
+                else inside = false;
+            }
+            if (!inside) continue;
+            const int l = (lz * T::SY + ly) * T::SX + lx;
+            R dg;
+            const R Kx = block_K<DIM, R>(g, s, T::SX, T::SX * T::SY, G, l, &dg);
+            s[l] = s[l] + (sb[lb] - Kx) / dg;
+        }
+        __syncthreads();
+    }
+    // the tile's nodes of the updated planes
+    for (int t = threadIdx.x; t < CF::TX * CF::TY * CF::PZ; t += TH) {
+        const int rx = t % CF::TX, ry = (t / CF::TX) % CF::TY, m = t / (CF::TX * CF::TY);
+        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? kb + 2 * m : 0};
+        if (G[0] >= nn[0] || G[1] >= nn[1] || G[2] >= nn[2]) continue;
+        next[nid(g, G[0], G[1], G[2])] = s[((DIM == 3 ? 1 + 2 * m : 0) * T::SY + ry + T::HY) * T::SX + rx + T::HX];
     }
 }
 
@@ -207,19 +364,43 @@ void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, cons
     }
 }
 
+// one Gauss-Seidel sweep (all 2^d colours) from cur into next
+template <typename R>
+void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b)
+{
+    BV vv = v;
+    if (L.gmax.dim == 2) {
+        using CF = NG4<2>;
+        vv.zb = 1;
+        const dim3 grid((nnode(L.gmax, 0) + CF::TX - 1) / CF::TX, (nnode(L.gmax, 1) + CF::TY - 1) / CF::TY, c->nb);
+        k_nodal_gs_fused<2, R><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
+    } else {
+        using CF = NG4<3>;
+        const int planes = (nnode(L.gmax, 2) + 1) / 2;   // even planes (at least as many as odd)
+        vv.zb = (planes + CF::PZ - 1) / CF::PZ;
+        const dim3 grid((nnode(L.gmax, 0) + CF::TX - 1) / CF::TX, (nnode(L.gmax, 1) + CF::TY - 1) / CF::TY,
+                        vv.zb * c->nb);
+        k_nodal_gs_fused<3, R><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
+        k_nodal_gs_fused<3, R><<<grid, CF::TH, 0, c->s>>>(vv, 1, cur, next, next, b);
+    }
+}
+
 template <typename R>
 void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R* b, R* r, int slot)
 {
     BV vv = v;
     if (L.gmax.dim == 2) {
         const dim3 grid = ntile_grid<2>(c, L, vv);
-        k_nodal_resid_tile<2, R><<<grid, NTile<2>::THREADS, 0, c->s>>>(vv, x, b, r, c->sc, slot);
+        k_nodal_resid_tile<2, R><<<grid, NTile<2>::THREADS, 0, c->s>>>(vv, x, b, r, c->mpart, slot);
     } else {
         const dim3 grid = ntile_grid<3>(c, L, vv);
-        k_nodal_resid_tile<3, R><<<grid, NTile<3>::THREADS, 0, c->s>>>(vv, x, b, r, c->sc, slot);
+        k_nodal_resid_tile<3, R><<<grid, NTile<3>::THREADS, 0, c->s>>>(vv, x, b, r, c->mpart, slot);
     }
+    if (slot >= 0) launch_max_final(c, vv.act, slot);
 }
 
+template void launch_nodal_sweep<double>(Ctx*, const Level&, const BV&, const double*, double*, const double*);
+template void launch_nodal_sweep<float>(Ctx*, const Level&, const BV&, const float*, float*, const float*);
 template void launch_nodal_gs<double>(Ctx*, const Level&, const BV&, int, double*, const double*);
 template void launch_nodal_gs<float>(Ctx*, const Level&, const BV&, int, float*, const float*);
 template void launch_nodal_resid<double>(Ctx*, const Level&, const BV&, const double*, const double*, double*, int);

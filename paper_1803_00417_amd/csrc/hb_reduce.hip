@@ -67,6 +67,29 @@ void fill(Ctx* c, double* dst, double v, long n)
     if (n > 0) k_fill<<<blocks_for(n, 8192), kT, 0, c->s>>>(dst, v, n);
 }
 
+// slot of every active cavity = max of its partial words, which are cleared
+__global__ void k_max_final(const int* __restrict__ act, unsigned long long* __restrict__ mp, double* __restrict__ sc,
+                            int slot)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    const int cav = blockIdx.x;
+    if (act && !act[cav]) return;
+    unsigned long long* w = mp + (long)cav * kSubMax;
+    unsigned long long m = 0ull;
+    for (int i = threadIdx.x; i < kSubMax; i += blockDim.x) {
+        const unsigned long long v = w[i];
+        m = v > m ? v : m;
+        w[i] = 0ull;
+    }
+    m = block_umax(m, sh);
+    if (threadIdx.x == 0) sc[(long)cav * S_NSLOT + slot] = __longlong_as_double((long long)m);
+}
+
+void launch_max_final(Ctx* c, const int* act, int slot)
+{
+    k_max_final<<<c->nb, kT, 0, c->s>>>(act, c->mpart, c->sc, slot);
+}
+
 // ---- segmented over the batch -------------------------------------------------
 
 // this block's cavity segment; the block returns when the cavity is inactive

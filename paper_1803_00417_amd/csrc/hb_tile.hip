@@ -296,8 +296,8 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int
 
 template <int DIM>
 __global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
-k_tresid(BV v, const double* __restrict__ coefa, double* __restrict__ scb, const double* __restrict__ xa,
-         const double* __restrict__ ba, double* __restrict__ outa, int slot)
+k_tresid(BV v, const double* __restrict__ coefa, const double* __restrict__ scb, const double* __restrict__ xa,
+         const double* __restrict__ ba, double* __restrict__ outa, unsigned long long* __restrict__ mp, int slot)
 {
     using T = Tile<DIM, 1>;
     __shared__ unsigned long long red[16];
@@ -365,7 +365,7 @@ k_tresid(BV v, const double* __restrict__ coefa, double* __restrict__ scb, const
     }
     if (slot >= 0) {
         m = block_umax(m, red);
-        if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav * S_NSLOT + slot, m);
+        if (threadIdx.x == 0) max_partial(mp, cav, ((long)bz * gridDim.y + tby) * gridDim.x + tbx, m);
     }
 }
 
@@ -571,7 +571,8 @@ static void tresid_impl(Ctx* c, const Level& L, BV v, const double* coef, const 
 {
     const size_t lds = sizeof(double) * (DIM + 1) * Tile<DIM, 1>::NS;
     const dim3 grid = tile_grid<DIM>(c, L, v);
-    k_tresid<DIM><<<grid, TileCfg<DIM>::THREADS, lds, c->s>>>(v, coef, c->sc, x, b, out, slot);
+    k_tresid<DIM><<<grid, TileCfg<DIM>::THREADS, lds, c->s>>>(v, coef, c->sc, x, b, out, c->mpart, slot);
+    if (slot >= 0) launch_max_final(c, v.act, slot);
 }
 
 void launch_tresid(Ctx* c, const Level& L, const BV& v, const double* coef, const double* x, const double* b, double* out,

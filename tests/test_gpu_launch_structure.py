@@ -1,14 +1,15 @@
-"""The single-workgroup coarse V-cycle (one launch for every level below a
-size limit, data in LDS) against the per-level launches it replaces.
+"""Launch structures against the plain per-level, per-colour launches they
+replace: the single-workgroup coarse V-cycle (every level below a size limit
+in one launch, data in LDS; HB_TAIL=0 turns it off) and the fused-colour
+nodal sweep (all colours of a sweep in one launch, two in 3D; HB_FUSE=0).
 
-Both run the same arithmetic per cell in the same order (red-black
-Gauss-Seidel component by component, the same residual, restriction,
-prolongation and FP64 coarsest solve), with FP contraction off, so whole
-steps agree bit for bit, cycle counts included.  The per-level path is
-itself held to the oracle by the parity tests, which run with the tail on;
-the cases cover walls, periodic axes, odd coarsest extents, 2D and 3D, FP64
-and mixed precision, and a batch of uneven cavities.  HB_TAIL=0 in the
-environment at context creation turns the tail off.
+Each runs the same arithmetic per cell or node in the same order (the same
+Gauss-Seidel ordering, residual, restriction, prolongation and FP64
+coarsest solve), with FP contraction off, so whole steps agree bit for bit,
+cycle counts included.  The plain path is itself held to the oracle by the
+parity tests, which run with both on; the cases cover walls, periodic axes,
+odd coarsest extents, 2D and 3D, FP64 and mixed precision, and a batch of
+uneven cavities.
 """
 import os
 
@@ -39,16 +40,21 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _context(make, tail):
-    old = os.environ.get("HB_TAIL")
-    os.environ["HB_TAIL"] = "1" if tail else "0"
+PLAIN = {"tail": {"HB_TAIL": "0"}, "fuse": {"HB_FUSE": "0"}, "both": {"HB_TAIL": "0", "HB_FUSE": "0"}}
+
+
+def _context(make, env):
+    old = {k: os.environ.get(k) for k in ("HB_TAIL", "HB_FUSE")}
+    for k in old:
+        os.environ.pop(k, None)
+    os.environ.update(env)
     try:
         return make()
     finally:
-        if old is None:
-            del os.environ["HB_TAIL"]
-        else:
-            os.environ["HB_TAIL"] = old
+        for k, v in old.items():
+            os.environ.pop(k, None)
+            if v is not None:
+                os.environ[k] = v
 
 
 def _start(s):
@@ -66,9 +72,9 @@ def _dt(s):
     return 0.01 if any(f != 0.0 for f in s["f"]) else 0.0
 
 
-def _steps(s, tail, nsteps, **opt):
+def _steps(s, env, nsteps, **opt):
     g, fl = hip_objs(s)
-    ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts(**opt)), tail)
+    ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts(**opt)), env)
     u0, p0 = _start(s)
     u, p = dev(u0), dev(p0)
     cyc = []
@@ -81,26 +87,27 @@ def _steps(s, tail, nsteps, **opt):
 
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_tail_equals_per_level_launches(case, precision):
-    _say("tail", case, precision)
+@pytest.mark.parametrize("plain", list(PLAIN))
+def test_launch_structure_is_bit_identical(case, precision, plain):
+    _say("launch structure", plain, case, precision)
     s = CASES[case]()
     opt = {} if precision == "fp64" else {"precision": hb.PREC_MIXED}
-    u1, p1, c1 = _steps(s, True, 4, **opt)
-    u0, p0, c0 = _steps(s, False, 4, **opt)
+    u1, p1, c1 = _steps(s, {}, 4, **opt)
+    u0, p0, c0 = _steps(s, PLAIN[plain], 4, **opt)
     _say("  cycles (mac, visc, proj) per step:", c1)
     assert c1 == c0
     assert np.array_equal(u1, u0) and np.array_equal(p1, p0)
 
 
-def test_tail_in_batch_equals_per_level_launches():
-    _say("tail batch")
+def test_launch_structure_in_batch_is_bit_identical():
+    _say("launch structure, batch")
     specs = [CASES["lid2d_64"](), CASES["lid2d_96x48"](), lid_spec(2, 16, Re=5.0, HB=3.0, nidx=0.4, Pa=400.0),
              CASES["chan2d_8x32"]()]
     outs = []
-    for tail in (True, False):
+    for env in ({}, PLAIN["both"]):
         objs = [hip_objs(s) for s in specs]
         ctx = _context(lambda: hb.BatchContext([g for g, _ in objs], [f for _, f in objs], hb.make_step_opts()),
-                       tail)
+                       env)
         us, ps = [], []
         for s in specs:
             u0, p0 = _start(s)
