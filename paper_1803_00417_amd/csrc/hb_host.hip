@@ -179,7 +179,7 @@ static int build_mg(Ctx* c, MG& m, int op)
     // single-workgroup coarse tail: the first level from which every
     // cavity's remaining levels fit the LDS budget
     m.tail_lt = -1;
-    if (op == HB_OP_VISC && c->lds_budget > 0) {
+    if ((op == HB_OP_VISC || op == HB_OP_MAC) && c->lds_budget > 0) {
         for (int l = 1; l < m.nlev && m.tail_lt < 0; ++l) {
             if (m.nlev - l > kMaxTail) continue;
             size_t need[2] = {0, 0};
@@ -190,8 +190,8 @@ static int build_mg(Ctx* c, MG& m, int op)
                 std::vector<long> gofs;
                 for (int k = l; k < m.nlevc[b]; ++k) gofs.push_back(m.L[k].hof[b]);
                 const long o0 = m.L[l].ho[b];
-                need[0] = std::max(need[0], visc_tail_plan(gl, gofs, o0, sizeof(double), &plans[b]));
-                need[1] = std::max(need[1], visc_tail_plan(gl, gofs, o0, sizeof(float), nullptr));
+                need[0] = std::max(need[0], tail_plan(op, gl, gofs, o0, sizeof(double), &plans[b]));
+                need[1] = std::max(need[1], tail_plan(op, gl, gofs, o0, sizeof(float), nullptr));
             }
             if (need[0] > 0 && need[0] <= c->lds_budget) {
                 m.tail_lt = l;
@@ -423,7 +423,8 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
         return;
     }
     if (l == m.tail_lt) {
-        launch_visc_tail<R>(c, m, l, nu1, nu2, m.tail_lds[prec_index<R>()], c->act);
+        if (m.op == HB_OP_VISC) launch_visc_tail<R>(c, m, l, nu1, nu2, m.tail_lds[prec_index<R>()], c->act);
+        else launch_mac_tail<R>(c, m, l, nu1, nu2, m.tail_lds[prec_index<R>()], c->act);
         return;
     }
     if (L.any_sm) {

@@ -366,10 +366,12 @@ template <typename R>
 void launch_coarse_solve(Ctx* c, const MG& m, int lev, const int* act, const R* b, R* x);
 void launch_identity(Ctx* c, int N, double* E);
 // the coarse end of a V-cycle from level lt in one launch (hb_tail.hip)
-size_t visc_tail_plan(const std::vector<GridD>& levels, const std::vector<long>& gofs, long o0, size_t elem,
-                      TailPlan* out);
+size_t tail_plan(int op, const std::vector<GridD>& levels, const std::vector<long>& gofs, long o0, size_t elem,
+                 TailPlan* out);
 template <typename R>
 void launch_visc_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, const int* act);
+template <typename R>
+void launch_mac_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, const int* act);
 void tail_allow_lds(size_t bytes);
 
 // ---- learned warm start (hb_nn.hip, hb_ws.hip) --------------------------------

@@ -26,6 +26,7 @@
 namespace hb {
 
 constexpr int kTailThreads = 512;
+constexpr int kMacTailKC = 4;   // MAC tail: cells of one colour per thread
 
 // LDS block of one level: `dim` components of (n0+2)(n1+2)[(n2+2)] cells
 struct TailLay {
@@ -54,7 +55,7 @@ struct Images {
 };
 
 template <int DIM>
-__device__ inline Images<DIM> cell_images(const GridD& g, const TailLay& t, const int G[3])
+__device__ inline Images<DIM> cell_images(const GridD& g, const TailLay& t, const int G[3], bool walls = true)
 {
     Images<DIM> im;
     im.neg = 0;
@@ -64,6 +65,7 @@ __device__ inline Images<DIM> cell_images(const GridD& g, const TailLay& t, cons
     for (int a = 0; a < DIM; ++a) {
         const int n = g.n[a];
         wall[a] = !g.per[a];
+        if (wall[a] && !walls) continue;
         if (G[a] == 0) { has[a] = true; ic[a] = g.per[a] ? n : -1; }
         else if (G[a] == n - 1) { has[a] = true; ic[a] = g.per[a] ? -1 : n; }
     }
@@ -95,11 +97,12 @@ __device__ inline void put_images(R* xq, int l, const Images<DIM>& im, R v)
         if (im.pos[m] >= 0) xq[im.pos[m]] = ((im.neg >> m) & 1) ? -v : v;
 }
 
-// Store v at cell G of one component and at each of its boundary images.
+// Store v at cell G of one component and at each of its boundary images
+// (walls = false: periodic images only).
 template <int DIM, typename R>
-__device__ inline void put_cell(const GridD& g, const TailLay& t, R* xq, const int G[3], R v)
+__device__ inline void put_cell(const GridD& g, const TailLay& t, R* xq, const int G[3], R v, bool walls = true)
 {
-    put_images<DIM, R>(xq, t.at(G[0], G[1], G[2]), cell_images<DIM>(g, t, G), v);
+    put_images<DIM, R>(xq, t.at(G[0], G[1], G[2]), cell_images<DIM>(g, t, G, walls), v);
 }
 
 struct TailArgs {
@@ -370,21 +373,261 @@ __global__ void __launch_bounds__(kTailThreads) k_visc_tail(TailArgs A)
     }
 }
 
-// Tail plan of one cavity from its levels lt..lc (grids gl, face offsets in
-// the level arenas gofs, component-array offset o0 at lt): the LDS layout
-// (iterates with halo, right-hand sides, face viscosities per level, then
-// one residual array of the first level).  Returns the LDS bytes for storage
-// size elem, or SIZE_MAX when the first level has more cells than the
-// smoother's one-cell-per-thread-and-colour layout covers.
-size_t visc_tail_plan(const std::vector<GridD>& gl, const std::vector<long>& gofs, long o0, size_t elem, TailPlan* out)
+// ---------------------------------------------------------------------------
+// MAC problem (cell Poisson, zero flux through walls).  The halo holds the
+// periodic images only: a neighbour beyond a wall is masked, as in the
+// per-level kernels.  Each thread owns up to KC cells of each colour.
+// ---------------------------------------------------------------------------
+
+// L_mac x at cell G of an LDS level block (as mac_lap_at)
+template <int DIM, typename R>
+__device__ inline R tail_mac_lap(const GridD& g, const TailLay& L, const R* X, const int G[3], R ihh)
+{
+    const int off[3] = {1, L.sx, L.sxy};
+    const int l0 = L.at(G[0], G[1], G[2]);
+    const R xc = X[l0];
+    R s = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const bool okh = g.per[a] || G[a] + 1 < g.n[a], okl = g.per[a] || G[a] > 0;
+        const R xh = X[l0 + off[a]], xl = X[l0 - off[a]];
+        const R Fhi = okh ? xh - xc : R(0);
+        const R Flo = okl ? xc - xl : R(0);
+        s += Fhi - Flo;
+    }
+    return s * ihh;
+}
+
+template <int DIM, typename R, int KC>
+__global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
+{
+    const int cav = blockIdx.x, tid = threadIdx.x;
+    if (A.act && !A.act[cav]) return;
+    const TailPlan* __restrict__ P = A.plan + cav;
+    const int nl = P->nl;
+    if (nl <= 0) return;
+    R* lds = reinterpret_cast<R*>(tail_lds);
+    for (int i = 0; i < nl; ++i) {
+        const TailLevel& T = P->lv[i];
+        R* X = lds + T.xoff;
+        for (int t = tid; t < T.ns; t += kTailThreads) X[t] = R(0);
+    }
+    {
+        const TailLevel& T = P->lv[0];
+        const R* gb = reinterpret_cast<const R*>(A.b) + P->o0;
+        R* B = lds + T.boff;
+        for (int t = tid; t < T.nc; t += kTailThreads) B[t] = gb[t];
+    }
+    __syncthreads();
+
+    // red-black sweeps of level i; per owned cell: LDS index, neighbour mask,
+    // diagonal, right-hand side and periodic images, set up once per visit
+    auto smooth = [&](int i, int sweeps) {
+        const GridD g = tail_grid<DIM>(P, i);
+        const TailLevel& T = P->lv[i];
+        const TailLay L = tail_lay(g);
+        const int off[3] = {1, L.sx, L.sxy};
+        const int H = T.nc / 2, hx = g.n[0] / 2;
+        const R h = (R)g.h;
+        const R ih2 = R(1) / (h * h);
+        R* X = lds + T.xoff;
+        const R* B = lds + T.boff;
+        bool on[2][KC];
+        int l0[2][KC], okm[2][KC];
+        R dg[2][KC], bq[2][KC];
+        Images<DIM> im[2][KC];
+#pragma unroll
+        for (int colour = 0; colour < 2; ++colour)
+#pragma unroll
+            for (int u = 0; u < KC; ++u) {
+                const int t0 = tid + u * kTailThreads;
+                on[colour][u] = t0 < H;
+                const int t = t0 < H ? t0 : 0;
+                const int px = t % hx, j = (t / hx) % g.n[1], k = t / (hx * g.n[1]);
+                const int G[3] = {2 * px + ((j + k + colour) & 1), j, k};
+                l0[colour][u] = L.at(G[0], j, k);
+                int m = 0, cnt = 0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const bool okl = g.per[a] || G[a] > 0, okh = g.per[a] || G[a] + 1 < g.n[a];
+                    m |= (okl ? 1 : 0) << (2 * a);
+                    m |= (okh ? 2 : 0) << (2 * a);
+                    cnt += (okl ? 1 : 0) + (okh ? 1 : 0);
+                }
+                okm[colour][u] = m;
+                dg[colour][u] = -(R)cnt * ih2;
+                bq[colour][u] = B[cid(g, G[0], j, k)];
+                im[colour][u] = cell_images<DIM>(g, L, G, false);
+            }
+        for (int s = 0; s < sweeps; ++s)
+#pragma unroll
+            for (int colour = 0; colour < 2; ++colour) {
+#pragma unroll
+                for (int u = 0; u < KC; ++u) {
+                    if (!on[colour][u]) continue;
+                    const int l = l0[colour][u];
+                    const R xq = X[l];
+                    R xn[DIM][2];
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        xn[a][0] = X[l - off[a]];
+                        xn[a][1] = X[l + off[a]];
+                    }
+                    R Lx = 0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+                        for (int side = 0; side < 2; ++side) {
+                            const bool ok = (okm[colour][u] >> (2 * a + side)) & 1;
+                            Lx += ok ? (xn[a][side] - xq) * ih2 : R(0);
+                        }
+                    put_images<DIM, R>(X, l, im[colour][u], xq + (bq[colour][u] - Lx) / dg[colour][u]);
+                }
+                __syncthreads();
+            }
+    };
+
+    // descend: smooth, then each coarse cell restricts the residuals of its
+    // children (as the per-level residual-restriction kernel)
+    for (int i = 0; i + 1 < nl; ++i) {
+        smooth(i, A.nu1);
+        const GridD g = tail_grid<DIM>(P, i);
+        const TailLay L = tail_lay(g);
+        const R h = (R)g.h;
+        const R ihh = R(1) / (h * h);
+        const R* X = lds + P->lv[i].xoff;
+        const R* B = lds + P->lv[i].boff;
+        const GridD gc = tail_grid<DIM>(P, i + 1);
+        const int Nc = P->lv[i + 1].nc;
+        R* Bc = lds + P->lv[i + 1].boff;
+        constexpr int nch = 1 << DIM;
+        for (int t = tid; t < Nc; t += kTailThreads) {
+            const int C[3] = {t % gc.n[0], (t / gc.n[0]) % gc.n[1], t / (gc.n[0] * gc.n[1])};
+            R sum = 0;
+#pragma unroll
+            for (int bits = 0; bits < nch; ++bits) {
+                const int F[3] = {2 * C[0] + (bits & 1), 2 * C[1] + ((bits >> 1) & 1),
+                                  DIM == 3 ? 2 * C[2] + ((bits >> 2) & 1) : 0};
+                sum += B[cid(g, F[0], F[1], F[2])] - tail_mac_lap<DIM, R>(g, L, X, F, ihh);
+            }
+            Bc[t] = sum / R(nch);
+        }
+        __syncthreads();
+    }
+
+    // coarsest: x = A^{-1} b, accumulated in FP64
+    {
+        const int i = nl - 1;
+        const CoarseD cd = A.cs[cav];
+        const GridD g = tail_grid<DIM>(P, i);
+        const TailLay L = tail_lay(g);
+        const R* B = lds + P->lv[i].boff;
+        R* X = lds + P->lv[i].xoff;
+        for (int r = tid; r < cd.N; r += kTailThreads) {
+            const double* row = A.Ainv + cd.aoff + (long)r * cd.N;
+            double s = 0.0;
+            for (int jj = 0; jj < cd.N; ++jj) s += row[jj] * (double)B[jj];
+            const int G[3] = {r % g.n[0], (r / g.n[0]) % g.n[1], r / (g.n[0] * g.n[1])};
+            put_cell<DIM, R>(g, L, X, G, (R)s, false);
+        }
+        __syncthreads();
+    }
+
+    // ascend: prolongation (coarse neighbour beyond a wall: the cell itself),
+    // then smoothing
+    for (int i = nl - 2; i >= 0; --i) {
+        const GridD gf = tail_grid<DIM>(P, i);
+        const GridD gc = tail_grid<DIM>(P, i + 1);
+        const TailLay Lf = tail_lay(gf), Lc = tail_lay(gc);
+        R* X = lds + P->lv[i].xoff;
+        const R* E = lds + P->lv[i + 1].xoff;
+        const int Nc = P->lv[i + 1].nc;
+        for (int t = tid; t < Nc; t += kTailThreads) {
+            const int C[3] = {t % gc.n[0], (t / gc.n[0]) % gc.n[1], t / (gc.n[0] * gc.n[1])};
+            int src[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    int J2 = C[a] + o - 1;
+                    if (a < DIM && (J2 < 0 || J2 >= gc.n[a])) {
+                        if (gc.per[a]) J2 = J2 < 0 ? J2 + gc.n[a] : J2 - gc.n[a];
+                        else J2 = C[a];
+                    }
+                    if (a >= DIM) J2 = 0;
+                    src[a][o] = J2;
+                }
+            R nb[3][3][3];
+#pragma unroll
+            for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+                    for (int ox = 0; ox < 3; ++ox)
+                        if (DIM == 3 || oz == 1) nb[oz][oy][ox] = E[Lc.at(src[0][ox], src[1][oy], src[2][oz])];
+            constexpr int nz = DIM == 3 ? 2 : 1;
+#pragma unroll
+            for (int cz = 0; cz < nz; ++cz)
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+                    for (int cx = 0; cx < 2; ++cx) {
+                        const int ch[3] = {cx, cy, cz};
+                        R s = 0;
+#pragma unroll
+                        for (int bits = 0; bits < (1 << DIM); ++bits) {
+                            int o[3] = {1, 1, 1};
+                            R w = 1, sv = 1;
+#pragma unroll
+                            for (int a = 0; a < DIM; ++a) {
+                                if (!((bits >> a) & 1)) { w *= R(0.75); continue; }
+                                w *= R(0.25);
+                                o[a] = ch[a] ? 2 : 0;
+                                sv *= R(1);
+                            }
+                            s += w * sv * nb[o[2]][o[1]][o[0]];
+                        }
+                        const int G[3] = {2 * C[0] + cx, 2 * C[1] + cy, DIM == 3 ? 2 * C[2] + cz : 0};
+                        put_cell<DIM, R>(gf, Lf, X, G, X[Lf.at(G[0], G[1], G[2])] + s, false);
+                    }
+        }
+        __syncthreads();
+        smooth(i, A.nu2);
+    }
+
+    {
+        const GridD g = tail_grid<DIM>(P, 0);
+        const TailLay L = tail_lay(g);
+        const int N = P->lv[0].nc;
+        const R* X = lds + P->lv[0].xoff;
+        R* gx = reinterpret_cast<R*>(A.x) + P->o0;
+        for (int t = tid; t < N; t += kTailThreads)
+            gx[t] = X[L.at(t % g.n[0], (t / g.n[0]) % g.n[1], t / (g.n[0] * g.n[1]))];
+    }
+}
+
+// Tail plan of one cavity from its levels lt..lc for problem op (grids gl,
+// face offsets in the level arenas gofs (tensor problem), component-array
+// offset o0 at lt): the LDS layout (per level the iterate with its halo, the
+// right-hand side and, tensor problem, the face viscosities; then, tensor
+// problem, one residual array of the first level).  Returns the LDS bytes
+// for storage size elem, or SIZE_MAX when the first level has more cells
+// per colour than the kernel's threads cover (tensor: one per thread, MAC:
+// kMacTailKC per thread).
+size_t tail_plan(int op, const std::vector<GridD>& gl, const std::vector<long>& gofs, long o0, size_t elem,
+                 TailPlan* out)
 {
     TailPlan P{};
     if (gl.empty()) {
         if (out) *out = P;
         return 0;
     }
-    if (gl.size() > (size_t)kMaxTail || (gl.size() > 1 && ncells(gl[0]) > 2L * kTailThreads)) return SIZE_MAX;
+    const bool visc = op == HB_OP_VISC;
+    const long per_thread = visc ? 1 : kMacTailKC;
+    if (gl.size() > (size_t)kMaxTail || (gl.size() > 1 && ncells(gl[0]) > 2L * kTailThreads * per_thread))
+        return SIZE_MAX;
     const int d = gl[0].dim;
+    const int nc = visc ? d : 1;
     long o = 0;
     for (size_t i = 0; i < gl.size(); ++i) {
         const GridD& g = gl[i];
@@ -397,22 +640,40 @@ size_t visc_tail_plan(const std::vector<GridD>& gl, const std::vector<long>& gof
         T.nc = (int)ncells(g);
         T.ns = (g.n[0] + 2) * (g.n[1] + 2) * (d == 3 ? g.n[2] + 2 : 1);
         long nf = 0;
-        for (int a = 0; a < d; ++a) nf += fcount(g, a);
+        if (visc)
+            for (int a = 0; a < d; ++a) nf += fcount(g, a);
         T.nf = (int)nf;
-        T.gofs = gofs[i];
+        T.gofs = visc ? gofs[i] : 0;
         T.xoff = (int)o;
-        o += (long)d * T.ns;
+        o += (long)nc * T.ns;
         T.boff = (int)o;
-        o += (long)d * T.nc;
+        o += (long)nc * T.nc;
         T.foff = (int)o;
         o += nf;
     }
     P.roff = (int)o;
-    o += (long)d * P.lv[0].nc;
+    if (visc) o += (long)d * P.lv[0].nc;
     P.nl = (int)gl.size();
     P.o0 = o0;
     if (out) *out = P;
     return (size_t)o * elem;
+}
+
+template <typename R>
+void launch_mac_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, const int* act)
+{
+    TailArgs A{};
+    A.nu1 = nu1;
+    A.nu2 = nu2;
+    A.plan = m.tplan;
+    A.x = LB<R>::x(m.L[lt]);
+    A.b = LB<R>::b(m.L[lt]);
+    A.cs = m.cs;
+    A.Ainv = m.Ainv;
+    A.act = act;
+    A.scb = c->sc;
+    if (c->dim == 2) k_mac_tail<2, R, kMacTailKC><<<c->nb, kTailThreads, lds, c->s>>>(A);
+    else k_mac_tail<3, R, kMacTailKC><<<c->nb, kTailThreads, lds, c->s>>>(A);
 }
 
 template <typename R>
@@ -436,6 +697,14 @@ void launch_visc_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds,
 // allow the tail kernels dynamic LDS up to `bytes`
 void tail_allow_lds(size_t bytes)
 {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<2, double, kMacTailKC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<3, double, kMacTailKC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<2, float, kMacTailKC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<3, float, kMacTailKC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visc_tail<2, double>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visc_tail<3, double>),
@@ -448,5 +717,7 @@ void tail_allow_lds(size_t bytes)
 
 template void launch_visc_tail<double>(Ctx*, const MG&, int, int, int, size_t, const int*);
 template void launch_visc_tail<float>(Ctx*, const MG&, int, int, int, size_t, const int*);
+template void launch_mac_tail<double>(Ctx*, const MG&, int, int, int, size_t, const int*);
+template void launch_mac_tail<float>(Ctx*, const MG&, int, int, int, size_t, const int*);
 
 }  // namespace hb
