@@ -101,6 +101,26 @@ __device__ inline bool wrap(const GridD& g, int p[3])
     return true;
 }
 
+// A uniform value (a per-cavity scalar slot such as dt) read with a vector
+// load.  Scalar loads can only be waited for all together, so a scalar read
+// from cold memory early in a kernel would hold back every later use of a
+// kernel argument, and with it the issue of the data loads; a vector load is
+// waited for with the data it travels with.
+__device__ inline double vload(const double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// cell G moved into the box (per axis clamp): an in-range index for a cell
+// whose value is then not used
+__device__ inline long cid_clamped(const GridD& g, const int G[3])
+{
+    int p[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[a] = G[a] < 0 ? 0 : (G[a] >= g.n[a] ? g.n[a] - 1 : G[a]);
+    return cid(g, p[0], p[1], p[2]);
+}
+
 // Max-norm reductions work on the bit patterns of |v| as unsigned integers:
 // they order like the values, and NaN (above +inf) propagates to the result.
 __device__ inline unsigned long long abits(double v)

@@ -334,8 +334,34 @@ template <> const float* tcoef<float>(const MG& m, int l) { return l == 0 ? m.et
 
 template <typename R> constexpr int prec_index() { return sizeof(R) == sizeof(double) ? 0 : 1; }
 
-static BV smooth_view(const Ctx* c, const Level& L) { return BV{L.gsm, L.o, L.of, c->act, 1}; }
-static BV all_view(const Level& L, const int* act) { return BV{L.gall, L.o, L.of, act, 1}; }
+// Batched views of a level: the cavities that smooth on it, or all that have
+// it.  A single-cavity context passes its grids by value (BV::one).
+static BV smooth_view(const Ctx* c, const Level& L)
+{
+    BV v{L.gsm, L.o, L.of, c->act, 1};
+    if (c->nb == 1) {
+        v.one = 1;
+        v.g1 = L.any_sm ? L.hg[0] : absent_grid();
+    }
+    return v;
+}
+
+static BV all_view(const Ctx* c, const Level& L, const int* act)
+{
+    BV v{L.gall, L.o, L.of, act, 1};
+    if (c->nb == 1) {
+        v.one = 1;
+        v.g1 = L.hg[0];
+    }
+    return v;
+}
+
+// the view with the grid of the paired level of a transfer kernel
+static BV paired(BV v, const Level& P)
+{
+    if (v.one) v.g2 = P.hg[0];
+    return v;
+}
 
 template <typename R>
 static void smooth(Ctx* c, MG& m, int l, int sweeps)
@@ -430,10 +456,11 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
     if (L.any_sm) {
         Level& C = m.L[l + 1];
         const BV v = smooth_view(c, L);
-        const BV vc = all_view(C, c->act);
+        const BV vpc = paired(v, C);                     // fine level, paired with the coarse one
+        const BV vc = paired(all_view(c, C, c->act), L);  // coarse level, paired with the fine one
         smooth<R>(c, m, l, nu1);
         if (m.op == HB_OP_VISC) {
-            launch_tresid_restr<R>(c, L, v, C.gall, C.o, tcoef<R>(m, l), l == 0, B::x(L), B::b(L), B::b(C), B::x(C));
+            launch_tresid_restr<R>(c, L, vpc, C.gall, C.o, tcoef<R>(m, l), l == 0, B::x(L), B::b(L), B::b(C), B::x(C));
         } else if (m.op == HB_OP_MAC) {
             launch_mac_resid_restrict<R>(c, C, vc, L.gall, L.o, B::x(L), B::b(L), B::b(C), B::x(C));
         } else {
@@ -441,8 +468,8 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
             launch_nodal_restrict<R>(c, C, vc, L.gall, L.o, B::r(L), B::b(C), B::x(C));
         }
         vcycle<R>(c, m, l + 1, nu1, nu2);
-        if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L, v, C.gall, C.o, B::x(C), B::x(L));
-        else launch_prolong_cells<R>(c, L, v, C.gall, C.o, m.ncomp, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
+        if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L, vpc, C.gall, C.o, B::x(C), B::x(L));
+        else launch_prolong_cells<R>(c, L, vpc, C.gall, C.o, m.ncomp, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
         smooth<R>(c, m, l, nu2);
     }
     if (L.any_cs) launch_coarse_solve<R>(c, m, l, c->act, B::b(L), B::x(L));
@@ -453,7 +480,7 @@ static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r, c
 {
     seg_set_zero(c, S_MAX);
     const Level& L = m.L[0];
-    const BV v = all_view(L, act);
+    const BV v = all_view(c, L, act);
     if (m.op == HB_OP_VISC) launch_tresid(c, L, v, m.etae, x, b, r, S_MAX);
     else if (m.op == HB_OP_MAC) launch_mac_resid(c, L, v, x, b, r, S_MAX);
     else launch_nodal_resid<double>(c, L, v, x, b, r, S_MAX);
@@ -462,7 +489,7 @@ static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r, c
 static void apply0(Ctx* c, MG& m, const double* x, double* y)
 {
     const Level& L = m.L[0];
-    const BV v = all_view(L, c->act);
+    const BV v = all_view(c, L, c->act);
     if (m.op == HB_OP_VISC) launch_tresid(c, L, v, m.etae, x, nullptr, y, -1);
     else if (m.op == HB_OP_MAC) launch_mac_resid(c, L, v, x, nullptr, y, -1);
     else launch_nodal_resid<double>(c, L, v, x, nullptr, y, -1);
@@ -714,7 +741,7 @@ static void nodal_prestart(Ctx* c, MG& m, double* x)
     if (nn_infer(c->ws, c->ws_in, 1, g.n[1], g.n[0], c->ws_out) != HB_OK) return;
     launch_cell_to_node(c, g, c->ws_out, c->ws_y);
     // least-squares scale of the network's shape: min_s |r0 - s K y|_2
-    launch_nodal_resid<double>(c, L, all_view(L, nullptr), c->ws_y, nullptr, c->ws_z, -1);
+    launch_nodal_resid<double>(c, L, all_view(c, L, nullptr), c->ws_y, nullptr, c->ws_z, -1);
     const SegV sv = seg_of(m, nullptr);
     seg_dot(c, sv, L.r, c->ws_z, S_DOT0);
     seg_dot(c, sv, c->ws_z, c->ws_z, S_DOT1);

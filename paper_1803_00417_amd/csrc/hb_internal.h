@@ -40,7 +40,19 @@ struct BV {
     const long* of;     // per cavity offset of the face arrays (tensor problem)
     const int* act;     // per cavity active flag (nullptr: all active)
     int zb;             // z-blocks per cavity in the launch grid
+    // Single-cavity contexts: the grids travel in the kernel arguments, the
+    // offsets are 0 and the cavity is active whenever the host launches, so
+    // a block's first data loads do not wait for table reads.
+    int one = 0;
+    GridD g1{};         // the cavity's grid on this level (dim 0: takes no part)
+    GridD g2{};         // its grid on the paired level of a transfer kernel
 };
+
+__device__ inline long bv_o(const BV& v, int cav) { return v.one ? 0 : v.o[cav]; }
+__device__ inline long bv_of(const BV& v, int cav) { return v.one ? 0 : v.of[cav]; }
+// grid and offset of the paired level (table t, offsets to)
+__device__ inline GridD bv_g2(const BV& v, const GridD* __restrict__ t, int cav) { return v.one ? v.g2 : t[cav]; }
+__device__ inline long bv_o2(const BV& v, const long* __restrict__ to, int cav) { return v.one ? 0 : to[cav]; }
 
 // Segmented view of a batch vector (vector kernels and reductions)
 struct SegV {
@@ -69,6 +81,12 @@ __device__ inline void xcd_tile(int& bx, int& by, int& bz)
 // false when the cavity takes no part in the launch
 __device__ inline bool bv_enter_at(const BV& v, int bzg, int& cav, int& bz, GridD& g)
 {
+    if (v.one) {
+        cav = 0;
+        bz = bzg;
+        g = v.g1;
+        return g.dim != 0;
+    }
     cav = bzg / v.zb;
     bz = bzg - cav * v.zb;
     // both table reads are issued before either is tested, so a block pays
@@ -82,6 +100,12 @@ __device__ inline bool bv_enter_at(const BV& v, int bzg, int& cav, int& bz, Grid
 // cavity takes no part in the launch
 __device__ inline bool bv_enter(const BV& v, int& cav, int& bz, GridD& g)
 {
+    if (v.one) {
+        cav = 0;
+        bz = blockIdx.z;
+        g = v.g1;
+        return g.dim != 0;
+    }
     cav = blockIdx.z / v.zb;
     bz = blockIdx.z - cav * v.zb;
     // both table reads are issued before either is tested, so a block pays

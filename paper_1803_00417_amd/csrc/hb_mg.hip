@@ -30,8 +30,8 @@ __global__ void k_mac_rb(BV v, int colour, R* __restrict__ xa, const R* __restri
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int i = 2 * t + ((j + k + colour) & 1);
     if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return;
-    R* x = xa + v.o[cav];
-    const R* b = ba + v.o[cav];
+    R* x = xa + bv_o(v, cav);
+    const R* b = ba + bv_o(v, cav);
     const long q = cid(g, i, j, k);
     const R h = (R)g.h;
     const R ih2 = R(1) / (h * h);
@@ -76,7 +76,7 @@ __global__ void k_mac_resid(BV v, const double* __restrict__ xa, const double* _
     PT_ENTER(k);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const long o = v.o[cav];
+    const long o = bv_o(v, cav);
     unsigned long long m = 0ull;
     if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
         const long q = cid(g, i, j, k);
@@ -118,9 +118,9 @@ __global__ void __launch_bounds__(256) k_mac_resid_restrict(BV v, const GridD* _
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= gc.n[0] || j >= gc.n[1] || k >= gc.n[2]) return;
-    const GridD& gf = gft[cav];   // read in place: a private copy indexed by axis would spill
-    const R* xf = xfa + oft[cav];
-    const R* bf = bfa + oft[cav];
+    const GridD gf = bv_g2(v, gft, cav);
+    const R* xf = xfa + bv_o2(v, oft, cav);
+    const R* bf = bfa + bv_o2(v, oft, cav);
     constexpr int nch = 1 << DIM;
     R s = 0;
 #pragma unroll
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_mac_resid_restrict(BV v, const GridD* _
         const int fi = 2 * i + (bits & 1), fj = 2 * j + ((bits >> 1) & 1), fk = DIM == 3 ? 2 * k + ((bits >> 2) & 1) : 0;
         s += bf[cid(gf, fi, fj, fk)] - mac_lap_at<DIM, R>(gf, xf, fi, fj, fk);
     }
-    const long qc = v.o[cav] + cid(gc, i, j, k);
+    const long qc = bv_o(v, cav) + cid(gc, i, j, k);
     bca[qc] = s / (R)nch;
     xca[qc] = R(0);
 }
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) k_prolong_cells(BV v, const GridD* __rest
 {
     PT_ENTER(K);
     const GridD& gf = g;
-    const GridD& gc = gct[cav];   // read in place: a private copy indexed by axis would spill
+    const GridD gc = bv_g2(v, gct, cav);
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;
     if (I >= gc.n[0] || J >= gc.n[1] || K >= gc.n[2]) return;
@@ -198,8 +198,8 @@ __global__ void __launch_bounds__(256) k_prolong_cells(BV v, const GridD* __rest
             src[a][o] = J2;
             sgn[a][o] = sg;
         }
-    const R* e0 = ea + ncomp * oct[cav];
-    R* x0 = xa + ncomp * v.o[cav];
+    const R* e0 = ea + ncomp * bv_o2(v, oct, cav);
+    R* x0 = xa + ncomp * bv_o(v, cav);
     const long Nf = ncells(gf), Nc = ncells(gc);
     constexpr int nz = d == 3 ? 2 : 1;
     for (int q = 0; q < ncomp; ++q) {
@@ -269,8 +269,8 @@ __global__ void k_nodal_restrict(BV v, const GridD* __restrict__ gft, const long
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nnode(gc, 0) || j >= nnode(gc, 1) || k >= nnode(gc, 2)) return;
-    const GridD& gf = gft[cav];   // read in place: a private copy indexed by axis would spill
-    const R* rf = rfa + oft[cav];
+    const GridD gf = bv_g2(v, gft, cav);
+    const R* rf = rfa + bv_o2(v, oft, cav);
     const int I[3] = {i, j, k};
     constexpr int nt = DIM == 3 ? 27 : 9;
     R val[nt];
@@ -306,7 +306,7 @@ __global__ void k_nodal_restrict(BV v, const GridD* __restrict__ gft, const long
         }
         s = okv[t] ? s + w * val[t] : s;
     }
-    const long q = v.o[cav] + nid(gc, i, j, k);
+    const long q = bv_o(v, cav) + nid(gc, i, j, k);
     bca[q] = s;
     xca[q] = R(0);
 }
@@ -335,8 +335,8 @@ __global__ void k_nodal_prolong(BV v, const GridD* __restrict__ gct, const long*
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nnode(gf, 0) || j >= nnode(gf, 1) || k >= nnode(gf, 2)) return;
-    const GridD& gc = gct[cav];   // read in place: a private copy indexed by axis would spill
-    const R* e = ea + oct[cav];
+    const GridD gc = bv_g2(v, gct, cav);
+    const R* e = ea + bv_o2(v, oct, cav);
     const int F[3] = {i, j, k};
     constexpr int nt = 1 << DIM;
     R val[nt], wv[nt];
@@ -366,7 +366,7 @@ __global__ void k_nodal_prolong(BV v, const GridD* __restrict__ gct, const long*
     R s = 0;
 #pragma unroll
     for (int bits = 0; bits < nt; ++bits) s = okv[bits] ? s + wv[bits] * val[bits] : s;
-    xa[v.o[cav] + nid(gf, i, j, k)] += s;
+    xa[bv_o(v, cav) + nid(gf, i, j, k)] += s;
 }
 
 template <typename R>

@@ -89,7 +89,7 @@ __device__ inline void fill_nodes(const GridD& g, const R* __restrict__ x, R* s,
             }
             p[a] = q;
         }
-        const R val = x[ok ? nid(g, p[0], p[1], p[2]) : 0];
+        const R val = x[nid(g, p[0], p[1], p[2])];   // every p[a] is in range
         v[u] = ok ? val : R(0);
     }
 #pragma unroll
@@ -109,7 +109,7 @@ __device__ inline void fill_nodes(const GridD& g, const R* __restrict__ x, R* s,
     if (!bv_enter_at(v, tbz, cav, bz, g)) return;                                           \
     const int ox = tbx * T::TX, oy = tby * T::TY, oz = DIM == 3 ? bz * T::TZ : 0;            \
     if (ox >= nnode(g, 0) || oy >= nnode(g, 1) || oz >= nnode(g, 2)) return;                \
-    const long node0 = v.o[cav];
+    const long node0 = bv_o(v, cav);
 
 // one colour (i&1) + 2(j&1) + 4(k&1) of the Gauss-Seidel sweep, in place:
 // nodes of one colour share no element
@@ -127,7 +127,7 @@ k_nodal_gs_tile(BV v, int colour, R* __restrict__ xa, const R* __restrict__ ba)
     const int G[3] = {ox + 2 * tx + (colour & 1), oy + 2 * ty + ((colour >> 1) & 1),
                       DIM == 3 ? oz + 2 * tz + ((colour >> 2) & 1) : 0};
     const bool ok = G[0] < nnode(g, 0) && G[1] < nnode(g, 1) && G[2] < nnode(g, 2);
-    const long q = ok ? nid(g, G[0], G[1], G[2]) : 0;
+    const long q = nid(g, G[0] < nnode(g, 0) ? G[0] : 0, G[1] < nnode(g, 1) ? G[1] : 0, G[2] < nnode(g, 2) ? G[2] : 0);
     const R bq = b[q];   // in flight with the tile fill
     fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
     __syncthreads();
@@ -163,7 +163,7 @@ k_nodal_resid_tile(BV v, const R* __restrict__ xa, const R* __restrict__ ba, R* 
         const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
         const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
         tOk[u] = G[0] < nnode(g, 0) && G[1] < nnode(g, 1) && G[2] < nnode(g, 2);
-        tq[u] = tOk[u] ? nid(g, G[0], G[1], G[2]) : 0;
+        tq[u] = nid(g, G[0] < nnode(g, 0) ? G[0] : 0, G[1] < nnode(g, 1) ? G[1] : 0, G[2] < nnode(g, 2) ? G[2] : 0);
         if (b) tb[u] = b[tq[u]];
     }
     fill_nodes<DIM, R>(g, x, s, ox, oy, oz);
@@ -240,7 +240,7 @@ k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* n
     const int ox = tbx * CF::TX, oy = tby * CF::TY;
     const int kb = DIM == 3 ? zpar + 2 * bz * CF::PZ : 0;   // first updated plane
     if (ox >= nn[0] || oy >= nn[1] || kb >= nn[2]) return;
-    const long node0 = v.o[cav];
+    const long node0 = bv_o(v, cav);
     const R* cur = cura + node0;
     const R* fix = fixa + node0;
     R* next = nexta + node0;

@@ -67,13 +67,14 @@ void fill(Ctx* c, double* dst, double v, long n)
     if (n > 0) k_fill<<<blocks_for(n, 8192), kT, 0, c->s>>>(dst, v, n);
 }
 
-// slot of every active cavity = max of its partial words, which are cleared
+// slot of every active cavity = max of its partial words; the words of
+// every cavity are cleared (a single-cavity launch writes them whether or
+// not the cavity is flagged active)
 __global__ void k_max_final(const int* __restrict__ act, unsigned long long* __restrict__ mp, double* __restrict__ sc,
                             int slot)
 {
     __shared__ unsigned long long sh[kT / 64];
     const int cav = blockIdx.x;
-    if (act && !act[cav]) return;
     unsigned long long* w = mp + (long)cav * kSubMax;
     unsigned long long m = 0ull;
     for (int i = threadIdx.x; i < kSubMax; i += blockDim.x) {
@@ -82,7 +83,7 @@ __global__ void k_max_final(const int* __restrict__ act, unsigned long long* __r
         w[i] = 0ull;
     }
     m = block_umax(m, sh);
-    if (threadIdx.x == 0) sc[(long)cav * S_NSLOT + slot] = __longlong_as_double((long long)m);
+    if (threadIdx.x == 0 && (!act || act[cav])) sc[(long)cav * S_NSLOT + slot] = __longlong_as_double((long long)m);
 }
 
 void launch_max_final(Ctx* c, const int* act, int slot)

@@ -24,20 +24,22 @@ __device__ inline int wall_mask(const GridD& g, const int G[3])
 
 // The 2*DIM face viscosities of cell G on a coarse level, [2a + side].
 // The kernels load them into registers together with the tile fill, so no
-// global load waits between the barriers of a sweep.  Cells that take no part
-// (ok = false) read index 0.
+// global load waits between the barriers of a sweep.  A cell outside the box
+// (taking no part) reads the faces of the nearest cell.
 template <int DIM, typename R>
-__device__ inline void load_faces(const GridD& g, const R* __restrict__ beta, const int G[3], bool ok, R* bf)
+__device__ inline void load_faces(const GridD& g, const R* __restrict__ beta, const int G[3], R* bf)
 {
+    int C[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) C[a] = G[a] < 0 ? 0 : (G[a] >= g.n[a] ? g.n[a] - 1 : G[a]);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-            int F[3] = {G[0], G[1], G[2]};
+            int F[3] = {C[0], C[1], C[2]};
             F[a] += side;
             if (g.per[a] && F[a] == g.n[a]) F[a] = 0;
-            const long q = ok ? foffset(g, a) + fid(g, a, F[0], F[1], F[2]) : 0;
-            bf[2 * a + side] = beta[q];
+            bf[2 * a + side] = beta[foffset(g, a) + fid(g, a, F[0], F[1], F[2])];
         }
     }
 }
@@ -69,12 +71,17 @@ __device__ inline R visc_div_ih(const R* bfc, const R* s, int ns, int sx, int sx
             const int lR = lL + off[a];
             const bool wall = (wm >> (2 * a + side)) & 1;
             // Every value is loaded whether or not the face is a wall (all
-            // positions lie in the staged halo), so a stencil's loads issue
-            // together; a wall face then selects what it uses.
+            // positions lie in the staged halo) and the wall case is chosen
+            // by multiplying with keep = 0 or 1 rather than by a select, so
+            // the compiler cannot move loads under a per-lane branch and a
+            // stencil's loads issue together.  The products and sums are the
+            // ones of the wall and interior formulas (x * 1 = x, x + 0 = x;
+            // only the sign of a zero can differ).
+            const R keep = wall ? R(0) : R(1);
             R bf;
             if (FINE) {
                 const R e0 = e[l0], eL = e[lL], eR = e[lR];
-                bf = wall ? e0 : R(0.5) * (eL + eR);
+                bf = e0 * (R(1) - keep) + R(0.5) * (eL + eR) * keep;
             } else {
                 bf = bfc[2 * a + side];
             }
@@ -85,8 +92,9 @@ __device__ inline R visc_div_ih(const R* bfc, const R* s, int ns, int sx, int sx
             } else {
                 const R* sa = s + a * ns;
                 // mean of the two cells' centred transverse differences
+                // (dropped on a wall face)
                 const R cross = R(0.25) * ((sa[lL + off[c]] - sa[lL - off[c]]) + (sa[lR + off[c]] - sa[lR - off[c]]));
-                f = wall ? bf * R(0.5) * dn : bf * R(0.5) * (dn + cross);
+                f = bf * R(0.5) * (dn + cross * keep);
             }
             flux[side] = f;
             coefsum += (wall ? R(2) : R(1)) * ((a == c) ? R(1) : R(0.5)) * bf;

@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kTailThreads) k_visc_tail(TailArgs A)
             G[colour][0] = 2 * px + ((j + k + colour) & 1);
             G[colour][1] = j;
             G[colour][2] = k;
-            load_faces<DIM, R>(g, F, G[colour], true, bf[colour]);
+            load_faces<DIM, R>(g, F, G[colour], bf[colour]);
             l0[colour] = L.at(G[colour][0], j, k);
             wm[colour] = wall_mask<DIM>(g, G[colour]);
             im[colour] = cell_images<DIM>(g, L, G[colour]);
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(kTailThreads) k_visc_tail(TailArgs A)
         for (int t = tid; t < N; t += kTailThreads) {
             const int G[3] = {t % g.n[0], (t / g.n[0]) % g.n[1], t / (g.n[0] * g.n[1])};
             R bf[2 * DIM];
-            load_faces<DIM, R>(g, F, G, true, bf);
+            load_faces<DIM, R>(g, F, G, bf);
             const int l0 = L.at(G[0], G[1], G[2]);
             const int wm = wall_mask<DIM>(g, G);
 #pragma unroll

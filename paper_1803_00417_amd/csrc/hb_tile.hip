@@ -56,7 +56,7 @@ __device__ inline long tile_src(const GridD& g, int i, int j, int k, bool& valid
         p[a] = v;
     }
     if (out > 1) valid = false;
-    return valid ? cid(g, p[0], p[1], p[2]) : 0;
+    return cid(g, p[0], p[1], p[2]);   // every p[a] is in range
 }
 
 // LDS tile with halo H around the interior box starting at (ox, oy, oz);
@@ -165,7 +165,15 @@ __device__ inline bool colour_cell(const GridD& g, int t, int ring, int colour, 
     using T = Tile<DIM, 2>;
     const int RX = T::TX + 2 * ring, RY = T::TY + 2 * ring, RZ = DIM == 3 ? T::TZ + 2 * ring : 1;
     const int HX = RX / 2;
-    if (t >= HX * RY * RZ) return false;
+    if (t >= HX * RY * RZ) {
+        // no cell: the tile's first cell, so that the slot's loads stay in range
+        G[0] = ox;
+        G[1] = oy;
+        G[2] = oz;
+        L[0] = L[1] = 2;
+        L[2] = DIM == 3 ? 2 : 0;
+        return false;
+    }
     const int px = t % HX, ry = (t / HX) % RY, rz = t / (HX * RY);
     const int y0 = oy - ring + ry, z0 = DIM == 3 ? oz - ring + rz : 0, x0 = ox - ring;
     const int rx = 2 * px + ((x0 + y0 + z0 + colour) & 1);
@@ -200,17 +208,17 @@ extern __shared__ __align__(16) unsigned char tile_lds[];
     if (!bv_enter_at(v, tbz, cav, bz, g)) return;                                           \
     const int ox = tbx * T::TX, oy = tby * T::TY, oz = (DIM == 3) ? bz * T::TZ : 0;          \
     if (ox >= g.n[0] || oy >= g.n[1] || oz >= g.n[2]) return;                               \
-    const long cell0 = v.o[cav];
+    const long cell0 = bv_o(v, cav);
 
-template <int DIM, bool FINE, typename R>
+template <int DIM, bool FINE, int c, typename R>
 __global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
-k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c, const R* __restrict__ xcura,
+k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, const R* __restrict__ xcura,
           const R* xnext_ina, R* xnexta, const R* __restrict__ ba)
 {
     using T = Tile<DIM, 2>;
     TILE_ENTER(DIM, T);
-    const R dt = (R)scb[(long)cav * S_NSLOT + S_DT];
-    const R* coef = FINE ? coefa + cell0 : coefa + v.of[cav];
+    const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
+    const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
     const R* xcur = xcura + DIM * cell0;
     const R* xnext_in = xnext_ina + DIM * cell0;
     R* xnext = xnexta + DIM * cell0;
@@ -233,8 +241,8 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int
         int L[3];
         rOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 1, 0, ox, oy, oz, rG[u], L);
         rL[u] = T::at(L[0], L[1], L[2]);
-        rB[u] = bc[rOk[u] ? cid(g, rG[u][0], rG[u][1], rG[u][2]) : 0];
-        if (!FINE) load_faces<DIM, R>(g, coef, rG[u], rOk[u], rF[u]);
+        rB[u] = bc[cid_clamped(g, rG[u])];
+        if (!FINE) load_faces<DIM, R>(g, coef, rG[u], rF[u]);
     }
     int kG[KB][3], kL[KB];
     bool kOk[KB];
@@ -244,8 +252,8 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int
         int L[3];
         kOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 0, 1, ox, oy, oz, kG[u], L);
         kL[u] = T::at(L[0], L[1], L[2]);
-        kB[u] = bc[kOk[u] ? cid(g, kG[u][0], kG[u][1], kG[u][2]) : 0];
-        if (!FINE) load_faces<DIM, R>(g, coef, kG[u], kOk[u], kF[u]);
+        kB[u] = bc[cid_clamped(g, kG[u])];
+        if (!FINE) load_faces<DIM, R>(g, coef, kG[u], kF[u]);
     }
     // components already swept in this sweep live in the next buffer
     {
@@ -261,23 +269,39 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int
     // red cells of the tile and its 1-cell ring, then black cells of the
     // tile; a cell of one colour reads only the other colour of component c
     // (face neighbours) and the other components, so each colour is updated
-    // in place
+    // in place.  Every slot is evaluated (idle slots on an in-range cell) and
+    // only real cells are stored, so a phase is straight-line code whose LDS
+    // reads issue together.
+    {
+        R nv[KR];
 #pragma unroll
-    for (int u = 0; u < KR; ++u) {
-        if (!rOk[u]) continue;
-        R dg;
-        const R vd = tile_visc_div<DIM, 2, FINE, R>(g, rF[u], s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
-        const R Au = sc[rL[u]] - dt * vd;
-        sc[rL[u]] += (rB[u] - Au) / dg;
+        for (int u = 0; u < KR; ++u) {
+            R dg;
+            const R vd =
+                tile_visc_div<DIM, 2, FINE, R>(g, rF[u], s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
+            const R xc = sc[rL[u]];
+            const R Au = xc - dt * vd;
+            nv[u] = xc + (rB[u] - Au) / dg;
+        }
+#pragma unroll
+        for (int u = 0; u < KR; ++u)
+            if (rOk[u]) sc[rL[u]] = nv[u];
     }
     __syncthreads();
+    {
+        R nv[KB];
 #pragma unroll
-    for (int u = 0; u < KB; ++u) {
-        if (!kOk[u]) continue;
-        R dg;
-        const R vd = tile_visc_div<DIM, 2, FINE, R>(g, kF[u], s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
-        const R Au = sc[kL[u]] - dt * vd;
-        sc[kL[u]] += (kB[u] - Au) / dg;
+        for (int u = 0; u < KB; ++u) {
+            R dg;
+            const R vd =
+                tile_visc_div<DIM, 2, FINE, R>(g, kF[u], s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
+            const R xc = sc[kL[u]];
+            const R Au = xc - dt * vd;
+            nv[u] = xc + (kB[u] - Au) / dg;
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            if (kOk[u]) sc[kL[u]] = nv[u];
     }
     __syncthreads();
     // write the tile's cells of component c
@@ -302,7 +326,7 @@ k_tresid(BV v, const double* __restrict__ coefa, const double* __restrict__ scb,
     using T = Tile<DIM, 1>;
     __shared__ unsigned long long red[16];
     TILE_ENTER(DIM, T);
-    const double dt = scb[(long)cav * S_NSLOT + S_DT];
+    const double dt = vload(scb + (long)cav * S_NSLOT + S_DT);
     const double* coef = coefa + cell0;
     const double* x = xa + DIM * cell0;
     const double* b = ba ? ba + DIM * cell0 : nullptr;
@@ -325,7 +349,7 @@ k_tresid(BV v, const double* __restrict__ coefa, const double* __restrict__ scb,
         tG[u][1] = oy + ry;
         tG[u][2] = DIM == 3 ? oz + rz : 0;
         tOk[u] = t < NT && tG[u][0] < g.n[0] && tG[u][1] < g.n[1] && tG[u][2] < g.n[2];
-        tq[u] = tOk[u] ? cid(g, tG[u][0], tG[u][1], tG[u][2]) : 0;
+        tq[u] = cid_clamped(g, tG[u]);
         if (b)
 #pragma unroll
             for (int c = 0; c < DIM; ++c) tb[u][c] = b[c * N + tq[u]];
@@ -377,13 +401,13 @@ k_tresid_restr(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct
 {
     using T = Tile<DIM, 1>;
     TILE_ENTER(DIM, T);
-    const R dt = (R)scb[(long)cav * S_NSLOT + S_DT];
-    const GridD gc = gct[cav];
-    const R* coef = FINE ? coefa + cell0 : coefa + v.of[cav];
+    const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
+    const GridD gc = bv_g2(v, gct, cav);
+    const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
     const R* x = xa + DIM * cell0;
     const R* b = ba + DIM * cell0;
-    R* bcoarse = bcoarsea + DIM * oct[cav];
-    R* xcoarse = xcoarsea + DIM * oct[cav];
+    R* bcoarse = bcoarsea + DIM * bv_o2(v, oct, cav);
+    R* xcoarse = xcoarsea + DIM * bv_o2(v, oct, cav);
     R* s = reinterpret_cast<R*>(tile_lds);
     R* e = s + DIM * T::NS;
     R* r = e + T::NS;   // residual of the tile, [c][tile cell]
@@ -403,10 +427,10 @@ k_tresid_restr(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct
         tG[u][1] = oy + ry;
         tG[u][2] = DIM == 3 ? oz + rz : 0;
         tOk[u] = t < NT && tG[u][0] < g.n[0] && tG[u][1] < g.n[1] && tG[u][2] < g.n[2];
-        const long q0 = tOk[u] ? cid(g, tG[u][0], tG[u][1], tG[u][2]) : 0;
+        const long q0 = cid_clamped(g, tG[u]);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) tb[u][c] = b[c * N + q0];
-        if (!FINE) load_faces<DIM, R>(g, coef, tG[u], tOk[u], tF[u]);
+        if (!FINE) load_faces<DIM, R>(g, coef, tG[u], tF[u]);
     }
     {
         const R* q[DIM + 1];
@@ -469,8 +493,8 @@ k_trb3(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c,
     using T = Tile<3, 1>;
     static_assert(T::TX * T::TY * T::TZ / 2 == 256, "one cell of the colour per thread");
     TILE_ENTER(3, T);
-    const R dt = (R)scb[(long)cav * S_NSLOT + S_DT];
-    const R* coef = FINE ? coefa + cell0 : coefa + v.of[cav];
+    const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
+    const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
     R* x = xa + 3 * cell0;
     const R* b = ba + 3 * cell0;
     R* s = reinterpret_cast<R*>(tile_lds);
@@ -481,11 +505,11 @@ k_trb3(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c,
     const int px = t % (T::TX / 2), ry = (t / (T::TX / 2)) % T::TY, rz = t / (T::TX / 2 * T::TY);
     const int G[3] = {ox + 2 * px + ((ox + oy + ry + oz + rz + colour) & 1), oy + ry, oz + rz};
     const bool ok = G[0] < g.n[0] && G[1] < g.n[1] && G[2] < g.n[2];
-    const long q0 = ok ? cid(g, G[0], G[1], G[2]) : 0;
+    const long q0 = cid_clamped(g, G);
     const R bv = b[c * N + q0];
     constexpr int NF = FINE ? 1 : 6;
     R bf[NF];
-    if (!FINE) load_faces<3, R>(g, coef, G, ok, bf);
+    if (!FINE) load_faces<3, R>(g, coef, G, bf);
     {
         const R* q[4] = {x, x + N, x + 2 * N, coef};
         const bool mir[4] = {false, false, false, true};
@@ -537,7 +561,10 @@ static void tsmooth_impl(Ctx* c, const Level& L, BV v, const R* coef, int comp, 
 {
     const size_t lds = sizeof(R) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 2>::NS;
     const dim3 grid = tile_grid<DIM>(c, L, v);
-    k_tsmooth<DIM, FINE, R><<<grid, TileCfg<DIM>::THREADS, lds, c->s>>>(v, coef, c->sc, comp, xcur, xnext, xnext, b);
+    constexpr int TH = TileCfg<DIM>::THREADS;
+    if (comp == 0) k_tsmooth<DIM, FINE, 0, R><<<grid, TH, lds, c->s>>>(v, coef, c->sc, xcur, xnext, xnext, b);
+    else if (comp == 1) k_tsmooth<DIM, FINE, 1, R><<<grid, TH, lds, c->s>>>(v, coef, c->sc, xcur, xnext, xnext, b);
+    else k_tsmooth<DIM, FINE, (DIM == 3 ? 2 : 1), R><<<grid, TH, lds, c->s>>>(v, coef, c->sc, xcur, xnext, xnext, b);
 }
 
 template <typename R>
