@@ -225,12 +225,12 @@ def main():
     launches, kms, kbytes = r["kt"]
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
     w = inputs.WORKLOADS[a.workload]
-    kname = "hb::k_tsmooth<2,true,double>" if w["dim"] == 2 else "hb::k_trb3<true,double>"
+    kname = "hb::k_tsweep2<true,double>" if w["dim"] == 2 else "hb::k_trb3<true,double>"
     wname = "cavity2d_512" if w["dim"] == 2 else "cavity3d_128"
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, wname),
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-probe scaled)",
-                "kernel": ("k_tsmooth (2D: fused red-black sweep of one velocity component, finest level)" if w["dim"] == 2 else "k_trb3 (3D: one colour of one velocity component, finest level)"),
+                "kernel": ("k_tsweep2 (2D: red-black sweep of both velocity components in one launch, finest level)" if w["dim"] == 2 else "k_trb3 (3D: one colour of one velocity component, finest level)"),
                 "launches": launches, "avg_launch_us": 1e3 * kms / max(launches, 1),
                 "alg_bytes_per_launch": kbytes / max(launches, 1)}
     out = {"metric": "cell-steps/s", "value": value, "unit": "cell-steps/s", "n_gpus": 1,

@@ -370,7 +370,11 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps)
     Level& L = m.L[l];
     const BV v = smooth_view(c, L);
     for (int s = 0; s < sweeps; ++s) {
-        if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0)) {
+        if (m.op == HB_OP_VISC && c->dim == 2 && c->fuse) {
+            // both components of the sweep in one launch
+            launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L));
+            L.cur ^= 1;
+        } else if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0)) {
             // fused red-black sweep per component into the other buffer (2D,
             // and the small 3D levels, where it halves the launches)
             for (int q = 0; q < c->dim; ++q)
@@ -972,17 +976,12 @@ static int step_all(Ctx* c, double* const* u, double* const* p, const double* dt
 // kernel timing
 // ---------------------------------------------------------------------------
 
-void kt_begin(Ctx* c)
+void kt_pair(Ctx* c, hipEvent_t* start, hipEvent_t* stop, double bytes)
 {
     KTimer& k = c->ktm;
     if (k.n == k.cap) kt_harvest(c);
-    (void)hipEventRecord(k.ev[2 * k.n], c->s);
-}
-
-void kt_end(Ctx* c, double bytes)
-{
-    KTimer& k = c->ktm;
-    (void)hipEventRecord(k.ev[2 * k.n + 1], c->s);
+    *start = k.ev[2 * k.n];
+    *stop = k.ev[2 * k.n + 1];
     ++k.n;
     ++k.launches;
     k.bytes += bytes;
@@ -1111,7 +1110,8 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         int dev = 0, lim = 0;
         const char* e = std::getenv("HB_TAIL");
         const bool on = !(e && e[0] == '0');
-        // HB_FUSE=0: one launch per colour in the nodal smoother
+        // HB_FUSE=0: one launch per colour in the nodal smoother and per
+        // component in the 2D tensor smoother
         const char* f = std::getenv("HB_FUSE");
         c->fuse = !(f && f[0] == '0');
         if (on && hipGetDevice(&dev) == hipSuccess &&

@@ -282,8 +282,9 @@ struct Ctx {
     std::string err;
 };
 
-void kt_begin(Ctx* c);
-void kt_end(Ctx* c, double bytes);
+// next start/stop event pair of the kernel timer, counting one launch of
+// `bytes` algorithmic bytes
+void kt_pair(Ctx* c, hipEvent_t* start, hipEvent_t* stop, double bytes);
 void kt_harvest(Ctx* c);
 
 // ---- launch helpers --------------------------------------------------------
@@ -345,6 +346,9 @@ void launch_eta_over_re(Ctx* c, const Cav& v, const double* eta, double* etae);
 template <typename R>
 void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, const R* xcur, R* xnext,
                     const R* b);
+// 2D: one red-black sweep of both components from xcur into xnext
+template <typename R>
+void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b);
 template <typename R>
 void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b);
 template <typename R>

@@ -16,6 +16,8 @@
 #include "hb_internal.h"
 #include "hb_stencil.h"
 
+#include <hip/hip_ext.h>
+
 namespace hb {
 
 template <int DIM> struct TileCfg;
@@ -315,6 +317,147 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
 }
 
 // ---------------------------------------------------------------------------
+// 2D: both components of a sweep in one launch.  The sweep's four half
+// steps (component 0 red, black, component 1 red, black) run on the tile
+// grown by 3, 2, 1 and 0 rings: each half step reads values of the previous
+// ones at most one cell away (face neighbours of its own component, the
+// other component at face and diagonal neighbours), so a halo of 4 cells
+// covers the sweep.  Component 1 reads component 0 at the wall ghosts as
+// well, so each update of a wall cell also writes its odd reflection into
+// the ghost position.  Every cell sees the values of the one-component-per-
+// launch order, so the result is the same bit for bit.
+// ---------------------------------------------------------------------------
+
+// cell of colour `colour` for slot t of the tile grown by `ring` (halo H
+// layout); as colour_cell
+template <int H>
+__device__ inline bool colour_cell2(const GridD& g, int t, int ring, int colour, int ox, int oy, int G[3], int& L)
+{
+    using T = Tile<2, H>;
+    const int RX = T::TX + 2 * ring, RY = T::TY + 2 * ring, HX = RX / 2;
+    if (t >= HX * RY) {
+        G[0] = ox;
+        G[1] = oy;
+        G[2] = 0;
+        L = T::at(H, H, 0);
+        return false;
+    }
+    const int px = t % HX, ry = t / HX;
+    const int y0 = oy - ring + ry, x0 = ox - ring;
+    const int rx = 2 * px + ((x0 + y0 + colour) & 1);
+    G[0] = x0 + rx;
+    G[1] = y0;
+    G[2] = 0;
+    L = T::at(rx - ring + H, ry - ring + H, 0);
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        if (G[a] >= 0 && G[a] < g.n[a]) continue;
+        if (g.per[a]) G[a] = G[a] < 0 ? G[a] + g.n[a] : G[a] - g.n[a];
+        if (G[a] < 0 || G[a] >= g.n[a]) inside = false;
+    }
+    return inside;
+}
+
+// one half step of the fused sweep: K slots per thread
+template <int C, int COLOUR, int RING, int K, bool FINE, typename R>
+struct HalfStep {
+    static constexpr int NF = FINE ? 1 : 4;
+    int G[K][3], L[K];
+    bool ok[K];
+    R bq[K], bf[K][NF];
+
+    __device__ inline void setup(const GridD& g, int ox, int oy, const R* __restrict__ bc, const R* __restrict__ coef)
+    {
+        constexpr int TH = TileCfg<2>::THREADS;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            ok[u] = colour_cell2<4>(g, threadIdx.x + u * TH, RING, COLOUR, ox, oy, G[u], L[u]);
+            bq[u] = bc[cid_clamped(g, G[u])];
+            if (!FINE) load_faces<2, R>(g, coef, G[u], bf[u]);
+        }
+    }
+
+    __device__ inline void run(const GridD& g, R* s, const R* e, R dt)
+    {
+        using T = Tile<2, 4>;
+        R* sc = s + C * T::NS;
+        R nv[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            R dg;
+            const R vd = tile_visc_div<2, 4, FINE, R>(g, bf[u], s, e, C, G[u], wall_mask<2>(g, G[u]), L[u], dt, &dg);
+            const R xc = sc[L[u]];
+            const R Au = xc - dt * vd;
+            nv[u] = xc + (bq[u] - Au) / dg;
+        }
+        const int off[2] = {1, T::SX};
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            if (!ok[u]) continue;
+            sc[L[u]] = nv[u];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                if (g.per[a]) continue;
+                if (G[u][a] == 0) sc[L[u] - off[a]] = -nv[u];
+                else if (G[u][a] == g.n[a] - 1) sc[L[u] + off[a]] = -nv[u];
+            }
+        }
+    }
+};
+
+template <bool FINE, typename R>
+__global__ void __launch_bounds__(TileCfg<2>::THREADS)
+k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, const R* __restrict__ xcura,
+          R* __restrict__ xnexta, const R* __restrict__ ba)
+{
+    using T = Tile<2, 4>;
+    constexpr int TH = TileCfg<2>::THREADS;
+    constexpr int K0 = ((T::TX + 6) / 2 * (T::TY + 6) + TH - 1) / TH;
+    constexpr int K1 = ((T::TX + 4) / 2 * (T::TY + 4) + TH - 1) / TH;
+    constexpr int K2 = ((T::TX + 2) / 2 * (T::TY + 2) + TH - 1) / TH;
+    constexpr int K3 = (T::TX / 2 * T::TY + TH - 1) / TH;
+    TILE_ENTER(2, T);
+    const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
+    const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
+    const R* xcur = xcura + 2 * cell0;
+    R* xnext = xnexta + 2 * cell0;
+    const R* b = ba + 2 * cell0;
+    const long N = ncells(g);
+    R* s = reinterpret_cast<R*>(tile_lds);
+    R* e = s + 2 * T::NS;
+    HalfStep<0, 0, 3, K0, FINE, R> h0;
+    HalfStep<0, 1, 2, K1, FINE, R> h1;
+    HalfStep<1, 0, 1, K2, FINE, R> h2;
+    HalfStep<1, 1, 0, K3, FINE, R> h3;
+    h0.setup(g, ox, oy, b, coef);
+    h1.setup(g, ox, oy, b, coef);
+    h2.setup(g, ox, oy, b + N, coef);
+    h3.setup(g, ox, oy, b + N, coef);
+    {
+        const R* q[3] = {xcur, xcur + N, coef};
+        const bool mir[3] = {false, false, true};
+        fill_batched<2, 4, FINE ? 3 : 2, R>(g, q, mir, s, ox, oy, 0);
+    }
+    __syncthreads();
+    h0.run(g, s, e, dt);
+    __syncthreads();
+    h1.run(g, s, e, dt);
+    __syncthreads();
+    h2.run(g, s, e, dt);
+    __syncthreads();
+    h3.run(g, s, e, dt);
+    __syncthreads();
+    for (int t = threadIdx.x; t < 2 * T::TX * T::TY; t += TH) {
+        const int q = t / (T::TX * T::TY), r = t - q * (T::TX * T::TY);
+        const int rx = r % T::TX, ry = r / T::TX;
+        const int G[2] = {ox + rx, oy + ry};
+        if (G[0] >= g.n[0] || G[1] >= g.n[1]) continue;
+        xnext[q * N + cid(g, G[0], G[1], 0)] = s[q * T::NS + T::at(rx + 4, ry + 4, 0)];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // residual / operator application (FP64, halo 1) and residual + restriction
 // ---------------------------------------------------------------------------
 
@@ -556,15 +699,40 @@ static double level_faces(const Level& L)
     return n;
 }
 
+// Launch kernel k on the context's stream.  With the kernel timer on, the
+// launch goes through hipExtLaunchKernelGGL with the timer's next event
+// pair, which the runtime records at the kernel's own start and end (so the
+// timing does not include the cost of separate event commands); bytes is the
+// launch's algorithmic traffic.
+template <typename K, typename... A>
+static void tlaunch(Ctx* c, bool timed, double bytes, K k, dim3 grid, dim3 block, size_t lds, A... args)
+{
+    if (timed) {
+        hipEvent_t e0, e1;
+        kt_pair(c, &e0, &e1, bytes);
+        hipExtLaunchKernelGGL(k, grid, block, (std::uint32_t)lds, c->s, e0, e1, 0u, args...);
+    } else {
+        k<<<grid, block, lds, c->s>>>(args...);
+    }
+}
+
 template <int DIM, bool FINE, typename R>
-static void tsmooth_impl(Ctx* c, const Level& L, BV v, const R* coef, int comp, const R* xcur, R* xnext, const R* b)
+static void tsmooth_impl(Ctx* c, const Level& L, BV v, const R* coef, int comp, const R* xcur, R* xnext, const R* b,
+                         bool timed, double bytes)
 {
     const size_t lds = sizeof(R) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 2>::NS;
     const dim3 grid = tile_grid<DIM>(c, L, v);
     constexpr int TH = TileCfg<DIM>::THREADS;
-    if (comp == 0) k_tsmooth<DIM, FINE, 0, R><<<grid, TH, lds, c->s>>>(v, coef, c->sc, xcur, xnext, xnext, b);
-    else if (comp == 1) k_tsmooth<DIM, FINE, 1, R><<<grid, TH, lds, c->s>>>(v, coef, c->sc, xcur, xnext, xnext, b);
-    else k_tsmooth<DIM, FINE, (DIM == 3 ? 2 : 1), R><<<grid, TH, lds, c->s>>>(v, coef, c->sc, xcur, xnext, xnext, b);
+    const R* xin = xnext;
+    if (comp == 0)
+        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, 0, R>, grid, dim3(TH), lds, v, coef, (const double*)c->sc, xcur,
+                xin, xnext, b);
+    else if (comp == 1)
+        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, 1, R>, grid, dim3(TH), lds, v, coef, (const double*)c->sc, xcur,
+                xin, xnext, b);
+    else
+        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, (DIM == 3 ? 2 : 1), R>, grid, dim3(TH), lds, v, coef,
+                (const double*)c->sc, xcur, xin, xnext, b);
 }
 
 template <typename R>
@@ -572,23 +740,20 @@ void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fin
                     const R* b)
 {
     const bool timed = c->ktm.on && fine;
-    if (timed) kt_begin(c);
+    // algorithmic bytes of one fused red-black sweep of one component: every
+    // component of x and the coefficients (eta/Re per cell on the finest
+    // level, face viscosities below) read once, b_c read once, x_c written
+    // once
+    const double N = level_cells(L);
+    const double coefw = fine ? N : level_faces(L);
+    const double bytes = sizeof(R) * (L.gmax.dim * N + coefw + 2.0 * N);
     if (L.gmax.dim == 2) {
-        if (fine) tsmooth_impl<2, true, R>(c, L, v, coef, comp, xcur, xnext, b);
-        else tsmooth_impl<2, false, R>(c, L, v, coef, comp, xcur, xnext, b);
+        if (fine) tsmooth_impl<2, true, R>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
+        else tsmooth_impl<2, false, R>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
     } else if (fine) {
-        tsmooth_impl<3, true, R>(c, L, v, coef, comp, xcur, xnext, b);
+        tsmooth_impl<3, true, R>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
     } else {
-        tsmooth_impl<3, false, R>(c, L, v, coef, comp, xcur, xnext, b);
-    }
-    if (timed) {
-        // algorithmic bytes of one fused red-black sweep of one component:
-        // every component of x and the coefficients (eta/Re per cell on the
-        // finest level, face viscosities below) read once, b_c read once, x_c
-        // written once
-        const double N = level_cells(L);
-        const double coefw = fine ? N : level_faces(L);
-        kt_end(c, sizeof(R) * (L.gmax.dim * N + coefw + 2.0 * N));
+        tsmooth_impl<3, false, R>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
     }
 }
 
@@ -633,27 +798,42 @@ void launch_tresid_restr(Ctx* c, const Level& L, const BV& v, const GridD* gc, c
 }
 
 template <typename R>
+void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b)
+{
+    using T = Tile<2, 4>;
+    const bool timed = c->ktm.on && fine;
+    BV vv = v;
+    const dim3 grid = tile_grid<2>(c, L, vv);
+    const size_t lds = sizeof(R) * (fine ? 3 : 2) * T::NS;
+    // algorithmic bytes of one sweep of both components: both components of
+    // x, eta/Re and both components of b read once, x written once
+    const double N = level_cells(L);
+    const double bytes = sizeof(R) * (2.0 * N + N + 2.0 * N + 2.0 * N);
+    const dim3 blk(TileCfg<2>::THREADS);
+    if (fine) tlaunch(c, timed, bytes, k_tsweep2<true, R>, grid, blk, lds, vv, coef, (const double*)c->sc, xcur, xnext, b);
+    else tlaunch(c, timed, bytes, k_tsweep2<false, R>, grid, blk, lds, vv, coef, (const double*)c->sc, xcur, xnext, b);
+}
+
+template <typename R>
 void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b)
 {
     using T = Tile<3, 1>;
     const bool timed = c->ktm.on && fine;
-    if (timed) kt_begin(c);
     const size_t lds = sizeof(R) * (3 + (fine ? 1 : 0)) * T::NS;
     BV vv = v;
     const dim3 grid = tile_grid<3>(c, L, vv);
-    if (fine) k_trb3<true, R><<<grid, 256, lds, c->s>>>(vv, coef, c->sc, comp, colour, x, b);
-    else k_trb3<false, R><<<grid, 256, lds, c->s>>>(vv, coef, c->sc, comp, colour, x, b);
-    if (timed) {
-        // algorithmic bytes of one half sweep: every component of x and the
-        // coefficients read once, the active colour of b read and of x written
-        const double N = level_cells(L);
-        kt_end(c, sizeof(R) * (3.0 * N + N + N));
-    }
+    // algorithmic bytes of one half sweep: every component of x and the
+    // coefficients read once, the active colour of b read and of x written
+    const double N = level_cells(L);
+    const double bytes = sizeof(R) * (3.0 * N + N + N);
+    if (fine) tlaunch(c, timed, bytes, k_trb3<true, R>, grid, dim3(256), lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
+    else tlaunch(c, timed, bytes, k_trb3<false, R>, grid, dim3(256), lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
 }
 
 #define HB_TILE_INST(R)                                                                                             \
     template void launch_tsmooth<R>(Ctx*, const Level&, const BV&, const R*, bool, int, const R*, R*, const R*);     \
     template void launch_trb3<R>(Ctx*, const Level&, const BV&, const R*, bool, int, int, R*, const R*);             \
+    template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*);          \
     template void launch_tresid_restr<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, bool, \
                                          const R*, const R*, R*, R*);
 HB_TILE_INST(double)
