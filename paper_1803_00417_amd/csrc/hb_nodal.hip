@@ -46,6 +46,7 @@ __device__ inline R block_K(const GridD& g, const R* s, int sx, int sxy, const i
 #pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
                 const int k = (dx != 0) + (dy != 0) + (dz != 0);
+                if (DIM == 3 && k == 1) continue;   // the 3D Q1 face-neighbour weight is exactly 0
                 const R w = (R)(q1_ke(DIM, g.h, k) * (double)(cnt[0][dx + 1] * cnt[1][dy + 1] * cnt[2][dz + 1]));
                 acc += w * s[l + dz * sxy + dy * sx + dx];
             }
@@ -211,7 +212,7 @@ k_nodal_resid_tile(BV v, const R* __restrict__ xa, const R* __restrict__ ba, R* 
 // ---------------------------------------------------------------------------
 template <int DIM> struct NG4;
 template <> struct NG4<2> { static constexpr int TX = 64, TY = 16, PZ = 1, TH = 256; };
-template <> struct NG4<3> { static constexpr int TX = 64, TY = 8, PZ = 2, TH = 256; };
+template <> struct NG4<3> { static constexpr int TX = 64, TY = 8, PZ = 2, TH = 512; };
 
 template <int DIM>
 struct NG4Tile {
