@@ -386,6 +386,10 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps)
             for (int q = 0; q < c->dim; ++q)
                 for (int colour = 0; colour < 2; ++colour)
                     launch_trb3<R>(c, L, v, tcoef<R>(m, l), l == 0, q, colour, B::x(L), B::b(L));
+        } else if (m.op == HB_OP_MAC && c->fuse) {
+            // both colours in one launch, into the other buffer
+            launch_mac_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L));
+            L.cur ^= 1;
         } else if (m.op == HB_OP_MAC) {
             for (int colour = 0; colour < 2; ++colour) launch_mac_rb<R>(c, L, v, colour, B::x(L), B::b(L));
         } else if (c->fuse) {
@@ -1110,8 +1114,8 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         int dev = 0, lim = 0;
         const char* e = std::getenv("HB_TAIL");
         const bool on = !(e && e[0] == '0');
-        // HB_FUSE=0: one launch per colour in the nodal smoother and per
-        // component in the 2D tensor smoother
+        // HB_FUSE=0: one launch per colour in the nodal and MAC smoothers
+        // and per component in the 2D tensor smoother
         const char* f = std::getenv("HB_FUSE");
         c->fuse = !(f && f[0] == '0');
         if (on && hipGetDevice(&dev) == hipSuccess &&

@@ -362,6 +362,8 @@ void launch_tresid(Ctx* c, const Level& L, const BV& v, const double* coef, cons
 // ---- scalar cell problem (MAC), nodal problem, transfers, coarsest ----------
 // (hb_mg.hip, hb_nodal.hip), batched
 template <typename R> void launch_mac_rb(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b);
+// both colours of a red-black sweep from cur into next (hb_tile.hip)
+template <typename R> void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b);
 // one thread per coarse cell: vc covers the coarse level, gf / of_ give the
 // fine grid and offsets of the same cavities
 template <typename R>

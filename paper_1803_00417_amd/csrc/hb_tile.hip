@@ -458,6 +458,106 @@ k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
 }
 
 // ---------------------------------------------------------------------------
+// MAC problem: both colours of a red-black sweep in one launch.  Red cells
+// of the tile and its 1-cell ring, then black cells of the tile, on the tile
+// plus a 2-cell halo staged in LDS (read from cur; the tile is written to
+// next).  A neighbour beyond a wall is masked (zero flux), as in the
+// one-colour kernel, whose per-cell arithmetic this repeats, so the result
+// is the same bit for bit.
+// ---------------------------------------------------------------------------
+template <int DIM, typename R>
+__global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
+k_mac_sweep(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* __restrict__ ba)
+{
+    using T = Tile<DIM, 2>;
+    TILE_ENTER(DIM, T);
+    constexpr int TH = TileCfg<DIM>::THREADS;
+    constexpr int RZ1 = DIM == 3 ? T::TZ + 2 : 1;
+    constexpr int KR = ((T::TX + 2) / 2 * (T::TY + 2) * RZ1 + TH - 1) / TH;
+    constexpr int KB = (T::TX / 2 * T::TY * T::TZ + TH - 1) / TH;
+    const R* cur = cura + cell0;
+    R* next = nexta + cell0;
+    const R* b = ba + cell0;
+    R* s = reinterpret_cast<R*>(tile_lds);
+    const R h = (R)g.h;
+    const R ih2 = R(1) / (h * h);
+    const int off[3] = {1, T::SX, T::SX * T::SY};
+    // a colour's slots: LDS index, neighbour mask (bit 2a + side), diagonal, b
+    auto setup = [&](int t, int ring, int colour, int& L, int& m, R& dg, R& bq) {
+        int G[3], Lc[3];
+        const bool ok = colour_cell<DIM>(g, t, ring, colour, ox, oy, oz, G, Lc);
+        L = T::at(Lc[0], Lc[1], Lc[2]);
+        int cnt = 0;
+        m = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const bool okl = g.per[a] || G[a] > 0, okh = g.per[a] || G[a] + 1 < g.n[a];
+            m |= (okl ? 1 : 0) << (2 * a);
+            m |= (okh ? 2 : 0) << (2 * a);
+            cnt += (okl ? 1 : 0) + (okh ? 1 : 0);
+        }
+        dg = -(R)cnt * ih2;
+        bq = b[cid_clamped(g, G)];
+        return ok;
+    };
+    int rL[KR], rM[KR], kL[KB], kM[KB];
+    bool rOk[KR], kOk[KB];
+    R rD[KR], rB[KR], kD[KB], kB[KB];
+#pragma unroll
+    for (int u = 0; u < KR; ++u) rOk[u] = setup(threadIdx.x + u * TH, 1, 0, rL[u], rM[u], rD[u], rB[u]);
+#pragma unroll
+    for (int u = 0; u < KB; ++u) kOk[u] = setup(threadIdx.x + u * TH, 0, 1, kL[u], kM[u], kD[u], kB[u]);
+    {
+        const R* q[1] = {cur};
+        const bool mir[1] = {false};
+        fill_batched<DIM, 2, 1, R>(g, q, mir, s, ox, oy, oz);
+    }
+    __syncthreads();
+    auto update = [&](int l, int m, R dg, R bq) {
+        const R xq = s[l];
+        R xn[DIM][2];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            xn[a][0] = s[l - off[a]];
+            xn[a][1] = s[l + off[a]];
+        }
+        R Lx = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool ok = (m >> (2 * a + side)) & 1;
+                Lx += ok ? (xn[a][side] - xq) * ih2 : R(0);
+            }
+        return xq + (bq - Lx) / dg;
+    };
+    {
+        R nv[KR];
+#pragma unroll
+        for (int u = 0; u < KR; ++u) nv[u] = update(rL[u], rM[u], rD[u], rB[u]);
+#pragma unroll
+        for (int u = 0; u < KR; ++u)
+            if (rOk[u]) s[rL[u]] = nv[u];
+    }
+    __syncthreads();
+    {
+        R nv[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) nv[u] = update(kL[u], kM[u], kD[u], kB[u]);
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            if (kOk[u]) s[kL[u]] = nv[u];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < T::TX * T::TY * T::TZ; t += TH) {
+        const int rx = t % T::TX, ry = (t / T::TX) % T::TY, rz = t / (T::TX * T::TY);
+        const int G[3] = {ox + rx, oy + ry, DIM == 3 ? oz + rz : 0};
+        if (G[0] >= g.n[0] || G[1] >= g.n[1] || G[2] >= g.n[2]) continue;
+        next[cid(g, G[0], G[1], G[2])] = s[T::at(rx + 2, ry + 2, DIM == 3 ? rz + 2 : 0)];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // residual / operator application (FP64, halo 1) and residual + restriction
 // ---------------------------------------------------------------------------
 
@@ -830,10 +930,24 @@ void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, 
     else tlaunch(c, timed, bytes, k_trb3<false, R>, grid, dim3(256), lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
 }
 
+template <typename R>
+void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b)
+{
+    BV vv = v;
+    if (L.gmax.dim == 2) {
+        const dim3 grid = tile_grid<2>(c, L, vv);
+        k_mac_sweep<2, R><<<grid, TileCfg<2>::THREADS, sizeof(R) * Tile<2, 2>::NS, c->s>>>(vv, cur, next, b);
+    } else {
+        const dim3 grid = tile_grid<3>(c, L, vv);
+        k_mac_sweep<3, R><<<grid, TileCfg<3>::THREADS, sizeof(R) * Tile<3, 2>::NS, c->s>>>(vv, cur, next, b);
+    }
+}
+
 #define HB_TILE_INST(R)                                                                                             \
     template void launch_tsmooth<R>(Ctx*, const Level&, const BV&, const R*, bool, int, const R*, R*, const R*);     \
     template void launch_trb3<R>(Ctx*, const Level&, const BV&, const R*, bool, int, int, R*, const R*);             \
     template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*);          \
+    template void launch_mac_sweep<R>(Ctx*, const Level&, const BV&, const R*, R*, const R*);                        \
     template void launch_tresid_restr<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, bool, \
                                          const R*, const R*, R*, R*);
 HB_TILE_INST(double)
