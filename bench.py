@@ -109,9 +109,16 @@ def run_gpu(name, steps, warmup, precision=0, timing=True, learned=False):
     ctx.kernel_timing(False)
     ncell = g.n[0] * g.n[1] * g.n[2]
     uses = ctx.warm_start_uses() if learned else 0
+    # tiles the autotuner chose for the fused sweeps, per level
+    tiles = {"tensor": [ctx.tile_config(hb.OP_VISC, l) for l in range(12)],
+             "nodal": [ctx.tile_config(hb.OP_NODAL, l) for l in range(12)]}
+    tiles = {k: [list(t) if t else None for t in v] for k, v in tiles.items()}
+    for k in tiles:
+        while tiles[k] and tiles[k][-1] is None:
+            tiles[k].pop()
     ctx.close()
     return dict(T=T, ncell=ncell, steps=steps, warmup=warmup, cycles=[c / steps for c in cycles], kt=kt,
-                ws_uses=uses)
+                ws_uses=uses, tiles=tiles)
 
 
 def run_batch(steps, warmup, precision=0, count=64, seed=0):
@@ -238,7 +245,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": w["desc"] + ", from rest, tol 1e-10", "cells": r["ncell"],
-                      "cycles_per_step_mac_visc_proj": r["cycles"]},
+                      "cycles_per_step_mac_visc_proj": r["cycles"], "autotuned_tiles_per_level": r["tiles"]},
            "roofline": roofline}
     also = {}
     runs = [(a.workload, 1)] if not a.no_mixed else []

@@ -372,7 +372,7 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps)
     for (int s = 0; s < sweeps; ++s) {
         if (m.op == HB_OP_VISC && c->dim == 2 && c->fuse) {
             // both components of the sweep in one launch
-            launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L));
+            launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile);
             L.cur ^= 1;
         } else if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0)) {
             // fused red-black sweep per component into the other buffer (2D,
@@ -394,7 +394,7 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps)
             for (int colour = 0; colour < 2; ++colour) launch_mac_rb<R>(c, L, v, colour, B::x(L), B::b(L));
         } else if (c->fuse) {
             // all colours of a sweep in one launch (two in 3D) into the other buffer
-            launch_nodal_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L));
+            launch_nodal_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L), L.tile);
             L.cur ^= 1;
         } else {
             for (int colour = 0; colour < (1 << c->dim); ++colour) launch_nodal_gs<R>(c, L, v, colour, B::x(L), B::b(L));
@@ -1043,6 +1043,59 @@ static const char* check_fluid(const hb_fluid* fluid)
 
 static void destroy_ctx(Ctx* c);
 
+// Tile autotuning.  For every level of the nodal problem (and, in 2D, of
+// the tensor problem) on which a fused sweep runs, each candidate tile is
+// timed on the level's own arenas (one warm-up sweep and three timed FP64
+// sweeps) and the fastest is kept.  The candidates compute the same values
+// bit for bit, so the choice changes only the speed.  HB_TILE=k in the
+// environment forces candidate k instead.
+static void autotune(Ctx* c)
+{
+    if (!c->fuse) return;
+    const char* e = std::getenv("HB_TILE");
+    const int forced = (e && e[0] >= '0' && e[0] <= '9') ? std::atoi(e) % kTileCandidates : -1;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (forced < 0 && (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)) return;
+    MG* ms[2] = {&c->visc, &c->nodal};
+    for (MG* m : ms) {
+        if (m->op == HB_OP_VISC && c->dim != 2) continue;
+        for (int l = 0; l < m->nlev; ++l) {
+            Level& L = m->L[l];
+            if (!L.any_sm || (m->tail_lt >= 0 && l >= m->tail_lt)) continue;
+            if (forced >= 0) {
+                L.tile = forced;
+                continue;
+            }
+            BV v{L.gsm, L.o, L.of, nullptr, 1};
+            if (c->nb == 1) {
+                v.one = 1;
+                v.g1 = L.hg[0];
+            }
+            auto sweep = [&](int k) {
+                if (m->op == HB_OP_VISC)
+                    launch_tsweep2<double>(c, L, v, tcoef<double>(*m, l), l == 0, L.xb[0], L.xb[1], L.b, k);
+                else
+                    launch_nodal_sweep<double>(c, L, v, L.xb[0], L.xb[1], L.b, k);
+            };
+            float best = 0.0f;
+            for (int k = 0; k < kTileCandidates; ++k) {
+                sweep(k);
+                (void)hipEventRecord(t0, c->s);
+                for (int r = 0; r < 3; ++r) sweep(k);
+                (void)hipEventRecord(t1, c->s);
+                float ms_k = 0.0f;
+                if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms_k, t0, t1) != hipSuccess) continue;
+                if (k == 0 || ms_k < best) {
+                    best = ms_k;
+                    L.tile = k;
+                }
+            }
+        }
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+}
+
 static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, const hb_step_opts* opts,
                       void* hip_stream, Ctx** out)
 {
@@ -1158,6 +1211,7 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         factor_coarsest(c, c->mac, b);
         factor_coarsest(c, c->nodal, b);
     }
+    autotune(c);
     if (hipStreamSynchronize(c->s) != hipSuccess) return give_up(HB_ERR_DEVICE, "stream synchronisation failed during set-up");
     *out = c;
     return HB_OK;
@@ -1425,6 +1479,19 @@ int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e)
 }
 
 int hb_warm_start_uses(const hb_ctx* ctx) { return ctx ? (int)C_(ctx)->ws_report_used : 0; }
+
+int hb_tile_config(const hb_ctx* ctx, int op, int level, int* tx, int* ty)
+{
+    if (!ctx || !tx || !ty) return HB_ERR_ARG;
+    const Ctx* c = C_(ctx);
+    const MG* m = op == HB_OP_VISC ? &c->visc : (op == HB_OP_NODAL ? &c->nodal : nullptr);
+    if (!m || !c->fuse || (op == HB_OP_VISC && c->dim != 2) || level < 0 || level >= m->nlev) return HB_ERR_ARG;
+    const Level& L = m->L[level];
+    if (!L.any_sm || (m->tail_lt >= 0 && level >= m->tail_lt)) return HB_ERR_ARG;
+    if (op == HB_OP_VISC) sweep2_tile(L.tile, tx, ty);
+    else nodal_sweep_tile(c->dim, L.tile, tx, ty);
+    return HB_OK;
+}
 
 int hb_kernel_timing(hb_ctx* ctx, int enable)
 {

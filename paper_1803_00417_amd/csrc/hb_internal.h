@@ -140,6 +140,7 @@ struct Level {
     std::vector<GridD> hg;   // per cavity grid (dim == 0: absent)
     std::vector<long> ho, hof, hou, hnu;
     bool any_sm = false, any_cs = false;   // some cavity smooths here / is at its coarsest
+    int tile = 0;            // smoother tile candidate chosen by the autotuner
     double* X() const { return xb[cur]; }
 };
 
@@ -346,9 +347,13 @@ void launch_eta_over_re(Ctx* c, const Cav& v, const double* eta, double* etae);
 template <typename R>
 void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, const R* xcur, R* xnext,
                     const R* b);
-// 2D: one red-black sweep of both components from xcur into xnext
+// 2D: one red-black sweep of both components from xcur into xnext, with
+// candidate tile `tile` (0 .. 2); sweep2_tile gives its extents
 template <typename R>
-void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b);
+void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b,
+                    int tile);
+void sweep2_tile(int tile, int* tx, int* ty);
+constexpr int kTileCandidates = 3;
 template <typename R>
 void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b);
 template <typename R>
@@ -376,9 +381,11 @@ template <typename R>
 void launch_prolong_cells(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, int ncomp,
                           double wall_sign, const R* e, R* x);
 template <typename R> void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b);
-// one whole Gauss-Seidel sweep from cur into next (one launch, two in 3D)
+// one whole Gauss-Seidel sweep from cur into next (one launch, two in 3D),
+// with candidate tile `tile` (0 .. 2); nodal_sweep_tile gives its extents
 template <typename R>
-void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b);
+void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile);
+void nodal_sweep_tile(int dim, int tile, int* tx, int* ty);
 // r = b - K x (slot >= 0: FP64 only, max-norm into each cavity's slot) or y = K x (b null)
 template <typename R>
 void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R* b, R* r, int slot);

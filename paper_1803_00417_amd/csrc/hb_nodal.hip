@@ -12,6 +12,9 @@
 #include "hb_internal.h"
 #include "hb_ops.h"
 
+#include <tuple>
+#include <utility>
+
 namespace hb {
 
 template <int DIM> struct NodalCfg;
@@ -210,13 +213,20 @@ k_nodal_resid_tile(BV v, const R* __restrict__ xa, const R* __restrict__ ba, R* 
 // same neighbour values as in the one-colour-per-launch order, so the result
 // is the same bit for bit.
 // ---------------------------------------------------------------------------
-template <int DIM> struct NG4;
-template <> struct NG4<2> { static constexpr int TX = 64, TY = 16, PZ = 1, TH = 256; };
-template <> struct NG4<3> { static constexpr int TX = 64, TY = 8, PZ = 2, TH = 512; };
+// tile of the fused sweep: TX x TY nodes of PZ planes of one parity, TH
+// threads; candidates per dimension, chosen per level by the autotuner
+// (index 0 is the default)
+template <int TX_, int TY_, int PZ_, int TH_>
+struct NG4 {
+    static constexpr int TX = TX_, TY = TY_, PZ = PZ_, TH = TH_;
+};
+using NG4Tiles2 = std::tuple<NG4<64, 16, 1, 256>, NG4<128, 8, 1, 256>, NG4<32, 32, 1, 256>>;
+using NG4Tiles3 = std::tuple<NG4<64, 8, 2, 512>, NG4<32, 16, 2, 512>, NG4<64, 4, 4, 512>>;
+constexpr int kNG4Tiles = 3;
 
-template <int DIM>
+template <int DIM, class CF>
 struct NG4Tile {
-    using C = NG4<DIM>;
+    using C = CF;
     static constexpr int HX = 4, HY = 2;                   // halo of x
     static constexpr int SX = C::TX + 2 * HX, SY = C::TY + 2 * HY, SZ = DIM == 3 ? 2 * C::PZ + 1 : 1;
     static constexpr int NS = SX * SY * SZ;
@@ -224,12 +234,11 @@ struct NG4Tile {
     static constexpr int NB = BX * BY * C::PZ;
 };
 
-template <int DIM, typename R>
-__global__ void __launch_bounds__(NG4<DIM>::TH)
+template <int DIM, typename R, class CF>
+__global__ void __launch_bounds__(CF::TH)
 k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* nexta, const R* __restrict__ ba)
 {
-    using T = NG4Tile<DIM>;
-    using CF = NG4<DIM>;
+    using T = NG4Tile<DIM, CF>;
     constexpr int TH = CF::TH;
     __shared__ R s[T::NS];
     __shared__ R sb[T::NB];
@@ -365,24 +374,57 @@ void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, cons
     }
 }
 
-// one Gauss-Seidel sweep (all 2^d colours) from cur into next
-template <typename R>
-void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b)
+template <int DIM, typename R, class CF>
+static void nodal_sweep_impl(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b)
 {
     BV vv = v;
-    if (L.gmax.dim == 2) {
-        using CF = NG4<2>;
+    if (DIM == 2) {
         vv.zb = 1;
         const dim3 grid((nnode(L.gmax, 0) + CF::TX - 1) / CF::TX, (nnode(L.gmax, 1) + CF::TY - 1) / CF::TY, c->nb);
-        k_nodal_gs_fused<2, R><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
+        k_nodal_gs_fused<2, R, CF><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
     } else {
-        using CF = NG4<3>;
         const int planes = (nnode(L.gmax, 2) + 1) / 2;   // even planes (at least as many as odd)
         vv.zb = (planes + CF::PZ - 1) / CF::PZ;
         const dim3 grid((nnode(L.gmax, 0) + CF::TX - 1) / CF::TX, (nnode(L.gmax, 1) + CF::TY - 1) / CF::TY,
                         vv.zb * c->nb);
-        k_nodal_gs_fused<3, R><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
-        k_nodal_gs_fused<3, R><<<grid, CF::TH, 0, c->s>>>(vv, 1, cur, next, next, b);
+        k_nodal_gs_fused<3, R, CF><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
+        k_nodal_gs_fused<3, R, CF><<<grid, CF::TH, 0, c->s>>>(vv, 1, cur, next, next, b);
+    }
+}
+
+template <int DIM, typename R, class Tiles, size_t... I>
+static void nodal_sweep_pick(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int k,
+                             std::index_sequence<I...>)
+{
+    ((k == (int)I ? nodal_sweep_impl<DIM, R, std::tuple_element_t<I, Tiles>>(c, L, v, cur, next, b) : void()), ...);
+}
+
+// one Gauss-Seidel sweep (all 2^d colours) from cur into next, with tile
+// candidate `tile`
+template <typename R>
+void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile)
+{
+    const int k = tile >= 0 && tile < kNG4Tiles ? tile : 0;
+    if (L.gmax.dim == 2) nodal_sweep_pick<2, R, NG4Tiles2>(c, L, v, cur, next, b, k, std::make_index_sequence<kNG4Tiles>{});
+    else nodal_sweep_pick<3, R, NG4Tiles3>(c, L, v, cur, next, b, k, std::make_index_sequence<kNG4Tiles>{});
+}
+
+void nodal_sweep_tile(int dim, int k, int* tx, int* ty)
+{
+    if (dim == 2) {
+        const int txs[] = {std::tuple_element_t<0, NG4Tiles2>::TX, std::tuple_element_t<1, NG4Tiles2>::TX,
+                           std::tuple_element_t<2, NG4Tiles2>::TX};
+        const int tys[] = {std::tuple_element_t<0, NG4Tiles2>::TY, std::tuple_element_t<1, NG4Tiles2>::TY,
+                           std::tuple_element_t<2, NG4Tiles2>::TY};
+        *tx = txs[k];
+        *ty = tys[k];
+    } else {
+        const int txs[] = {std::tuple_element_t<0, NG4Tiles3>::TX, std::tuple_element_t<1, NG4Tiles3>::TX,
+                           std::tuple_element_t<2, NG4Tiles3>::TX};
+        const int tys[] = {std::tuple_element_t<0, NG4Tiles3>::TY, std::tuple_element_t<1, NG4Tiles3>::TY,
+                           std::tuple_element_t<2, NG4Tiles3>::TY};
+        *tx = txs[k];
+        *ty = tys[k];
     }
 }
 
@@ -400,8 +442,8 @@ void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R
     if (slot >= 0) launch_max_final(c, vv.act, slot);
 }
 
-template void launch_nodal_sweep<double>(Ctx*, const Level&, const BV&, const double*, double*, const double*);
-template void launch_nodal_sweep<float>(Ctx*, const Level&, const BV&, const float*, float*, const float*);
+template void launch_nodal_sweep<double>(Ctx*, const Level&, const BV&, const double*, double*, const double*, int);
+template void launch_nodal_sweep<float>(Ctx*, const Level&, const BV&, const float*, float*, const float*, int);
 template void launch_nodal_gs<double>(Ctx*, const Level&, const BV&, int, double*, const double*);
 template void launch_nodal_gs<float>(Ctx*, const Level&, const BV&, int, float*, const float*);
 template void launch_nodal_resid<double>(Ctx*, const Level&, const BV&, const double*, const double*, double*, int);

@@ -18,11 +18,21 @@
 
 #include <hip/hip_ext.h>
 
+#include <tuple>
+
 namespace hb {
 
+template <int TX_, int TY_, int TZ_, int TH_>
+struct TileShape {
+    static constexpr int TX = TX_, TY = TY_, TZ = TZ_, THREADS = TH_;
+};
 template <int DIM> struct TileCfg;
-template <> struct TileCfg<2> { static constexpr int TX = 64, TY = 8, TZ = 1, THREADS = 256; };
-template <> struct TileCfg<3> { static constexpr int TX = 32, TY = 4, TZ = 4, THREADS = 512; };
+template <> struct TileCfg<2> : TileShape<64, 8, 1, 256> {};
+template <> struct TileCfg<3> : TileShape<32, 4, 4, 512> {};
+// candidate tiles of the 2D fused tensor sweep, chosen per level by the
+// autotuner (index 0 is the default)
+using Sweep2Tiles = std::tuple<TileShape<64, 8, 1, 256>, TileShape<32, 16, 1, 256>, TileShape<128, 4, 1, 256>>;
+constexpr int kSweep2Tiles = 3;
 
 
 // Source of a tile position (i, j, k) that may lie outside the box:
@@ -63,9 +73,9 @@ __device__ inline long tile_src(const GridD& g, int i, int j, int k, bool& valid
 
 // LDS tile with halo H around the interior box starting at (ox, oy, oz);
 // array q at local (lx, ly, lz) is s[q * NS + (lz * SY + ly) * SX + lx]
-template <int DIM, int H>
+template <int DIM, int H, class CF = TileCfg<DIM>>
 struct Tile {
-    static constexpr int TX = TileCfg<DIM>::TX, TY = TileCfg<DIM>::TY, TZ = TileCfg<DIM>::TZ;
+    static constexpr int TX = CF::TX, TY = CF::TY, TZ = CF::TZ;
     static constexpr int HZ = DIM == 3 ? H : 0;
     static constexpr int SX = TX + 2 * H, SY = TY + 2 * H, SZ = TZ + 2 * HZ;
     static constexpr int NS = SX * SY * SZ;
@@ -75,12 +85,12 @@ struct Tile {
 // Stage NA arrays (tile plus halo H) in LDS.  Every thread first issues all
 // of its global loads into registers, then stores them, so the loads of a
 // block are in flight together instead of one round trip per element.
-template <int DIM, int H, int NA, typename R>
+template <int DIM, int H, int NA, typename R, class CF = TileCfg<DIM>>
 __device__ inline void fill_batched(const GridD& g, const R* const* q, const bool* mirror, R* s, int ox, int oy,
                                     int oz)
 {
-    using T = Tile<DIM, H>;
-    constexpr int TH = TileCfg<DIM>::THREADS;
+    using T = Tile<DIM, H, CF>;
+    constexpr int TH = CF::THREADS;
     constexpr int K = (T::NS + TH - 1) / TH;
     // tiles away from every domain face need no boundary logic
     const bool inner = ox - H >= 0 && ox + T::TX + H <= g.n[0] && oy - H >= 0 && oy + T::TY + H <= g.n[1] &&
@@ -144,11 +154,11 @@ __device__ inline void fill_tile1(const GridD& g, const R* const* q, const bool*
 }
 
 // the stencil above on a Tile<DIM, H> (compile-time strides)
-template <int DIM, int H, bool FINE, typename R>
+template <int DIM, int H, bool FINE, typename R, class CF = TileCfg<DIM>>
 __device__ inline R tile_visc_div(const GridD& g, const R* bfc, const R* s, const R* e, int c, const int G[3], int wm,
                                   int l0, R dt, R* diag)
 {
-    using T = Tile<DIM, H>;
+    using T = Tile<DIM, H, CF>;
     (void)G;
     return visc_div_lds<DIM, FINE, R>(g, bfc, s, T::NS, T::SX, T::SX * T::SY, e, c, wm, l0, dt, diag);
 }
@@ -330,10 +340,10 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
 
 // cell of colour `colour` for slot t of the tile grown by `ring` (halo H
 // layout); as colour_cell
-template <int H>
+template <int H, class CF>
 __device__ inline bool colour_cell2(const GridD& g, int t, int ring, int colour, int ox, int oy, int G[3], int& L)
 {
-    using T = Tile<2, H>;
+    using T = Tile<2, H, CF>;
     const int RX = T::TX + 2 * ring, RY = T::TY + 2 * ring, HX = RX / 2;
     if (t >= HX * RY) {
         G[0] = ox;
@@ -360,7 +370,7 @@ __device__ inline bool colour_cell2(const GridD& g, int t, int ring, int colour,
 }
 
 // one half step of the fused sweep: K slots per thread
-template <int C, int COLOUR, int RING, int K, bool FINE, typename R>
+template <int C, int COLOUR, int RING, int K, bool FINE, typename R, class CF>
 struct HalfStep {
     static constexpr int NF = FINE ? 1 : 4;
     int G[K][3], L[K];
@@ -369,10 +379,10 @@ struct HalfStep {
 
     __device__ inline void setup(const GridD& g, int ox, int oy, const R* __restrict__ bc, const R* __restrict__ coef)
     {
-        constexpr int TH = TileCfg<2>::THREADS;
+        constexpr int TH = CF::THREADS;
 #pragma unroll
         for (int u = 0; u < K; ++u) {
-            ok[u] = colour_cell2<4>(g, threadIdx.x + u * TH, RING, COLOUR, ox, oy, G[u], L[u]);
+            ok[u] = colour_cell2<4, CF>(g, threadIdx.x + u * TH, RING, COLOUR, ox, oy, G[u], L[u]);
             bq[u] = bc[cid_clamped(g, G[u])];
             if (!FINE) load_faces<2, R>(g, coef, G[u], bf[u]);
         }
@@ -380,13 +390,14 @@ struct HalfStep {
 
     __device__ inline void run(const GridD& g, R* s, const R* e, R dt)
     {
-        using T = Tile<2, 4>;
+        using T = Tile<2, 4, CF>;
         R* sc = s + C * T::NS;
         R nv[K];
 #pragma unroll
         for (int u = 0; u < K; ++u) {
             R dg;
-            const R vd = tile_visc_div<2, 4, FINE, R>(g, bf[u], s, e, C, G[u], wall_mask<2>(g, G[u]), L[u], dt, &dg);
+            const R vd =
+                tile_visc_div<2, 4, FINE, R, CF>(g, bf[u], s, e, C, G[u], wall_mask<2>(g, G[u]), L[u], dt, &dg);
             const R xc = sc[L[u]];
             const R Au = xc - dt * vd;
             nv[u] = xc + (bq[u] - Au) / dg;
@@ -406,13 +417,13 @@ struct HalfStep {
     }
 };
 
-template <bool FINE, typename R>
-__global__ void __launch_bounds__(TileCfg<2>::THREADS)
+template <bool FINE, typename R, class CF>
+__global__ void __launch_bounds__(CF::THREADS)
 k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, const R* __restrict__ xcura,
           R* __restrict__ xnexta, const R* __restrict__ ba)
 {
-    using T = Tile<2, 4>;
-    constexpr int TH = TileCfg<2>::THREADS;
+    using T = Tile<2, 4, CF>;
+    constexpr int TH = CF::THREADS;
     constexpr int K0 = ((T::TX + 6) / 2 * (T::TY + 6) + TH - 1) / TH;
     constexpr int K1 = ((T::TX + 4) / 2 * (T::TY + 4) + TH - 1) / TH;
     constexpr int K2 = ((T::TX + 2) / 2 * (T::TY + 2) + TH - 1) / TH;
@@ -426,10 +437,10 @@ k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     const long N = ncells(g);
     R* s = reinterpret_cast<R*>(tile_lds);
     R* e = s + 2 * T::NS;
-    HalfStep<0, 0, 3, K0, FINE, R> h0;
-    HalfStep<0, 1, 2, K1, FINE, R> h1;
-    HalfStep<1, 0, 1, K2, FINE, R> h2;
-    HalfStep<1, 1, 0, K3, FINE, R> h3;
+    HalfStep<0, 0, 3, K0, FINE, R, CF> h0;
+    HalfStep<0, 1, 2, K1, FINE, R, CF> h1;
+    HalfStep<1, 0, 1, K2, FINE, R, CF> h2;
+    HalfStep<1, 1, 0, K3, FINE, R, CF> h3;
     h0.setup(g, ox, oy, b, coef);
     h1.setup(g, ox, oy, b, coef);
     h2.setup(g, ox, oy, b + N, coef);
@@ -437,7 +448,7 @@ k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     {
         const R* q[3] = {xcur, xcur + N, coef};
         const bool mir[3] = {false, false, true};
-        fill_batched<2, 4, FINE ? 3 : 2, R>(g, q, mir, s, ox, oy, 0);
+        fill_batched<2, 4, FINE ? 3 : 2, R, CF>(g, q, mir, s, ox, oy, 0);
     }
     __syncthreads();
     h0.run(g, s, e, dt);
@@ -773,10 +784,10 @@ k_trb3(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c,
 // ---------------------------------------------------------------------------
 
 // tile grid over the largest cavity of the level, z-tiles times cavities
-template <int DIM>
+template <int DIM, class CF = TileCfg<DIM>>
 static dim3 tile_grid(const Ctx* c, const Level& L, BV& v)
 {
-    using T = Tile<DIM, 1>;
+    using T = Tile<DIM, 1, CF>;
     const GridD& g = L.gmax;
     v.zb = DIM == 3 ? (g.n[2] + T::TZ - 1) / T::TZ : 1;
     return dim3((g.n[0] + T::TX - 1) / T::TX, (g.n[1] + T::TY - 1) / T::TY, v.zb * c->nb);
@@ -897,21 +908,48 @@ void launch_tresid_restr(Ctx* c, const Level& L, const BV& v, const GridD* gc, c
     }
 }
 
-template <typename R>
-void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b)
+template <bool FINE, typename R, class CF>
+static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b)
 {
-    using T = Tile<2, 4>;
-    const bool timed = c->ktm.on && fine;
+    using T = Tile<2, 4, CF>;
+    const bool timed = c->ktm.on && FINE;
     BV vv = v;
-    const dim3 grid = tile_grid<2>(c, L, vv);
-    const size_t lds = sizeof(R) * (fine ? 3 : 2) * T::NS;
+    const dim3 grid = tile_grid<2, CF>(c, L, vv);
+    const size_t lds = sizeof(R) * (FINE ? 3 : 2) * T::NS;
     // algorithmic bytes of one sweep of both components: both components of
     // x, eta/Re and both components of b read once, x written once
     const double N = level_cells(L);
     const double bytes = sizeof(R) * (2.0 * N + N + 2.0 * N + 2.0 * N);
-    const dim3 blk(TileCfg<2>::THREADS);
-    if (fine) tlaunch(c, timed, bytes, k_tsweep2<true, R>, grid, blk, lds, vv, coef, (const double*)c->sc, xcur, xnext, b);
-    else tlaunch(c, timed, bytes, k_tsweep2<false, R>, grid, blk, lds, vv, coef, (const double*)c->sc, xcur, xnext, b);
+    tlaunch(c, timed, bytes, k_tsweep2<FINE, R, CF>, grid, dim3(CF::THREADS), lds, vv, coef, (const double*)c->sc, xcur,
+            xnext, b);
+}
+
+template <bool FINE, typename R, size_t... I>
+static void tsweep2_pick(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b,
+                         int k, std::index_sequence<I...>)
+{
+    ((k == (int)I ? tsweep2_impl<FINE, R, std::tuple_element_t<I, Sweep2Tiles>>(c, L, v, coef, xcur, xnext, b)
+                  : void()),
+     ...);
+}
+
+template <typename R>
+void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b,
+                    int tile)
+{
+    const int k = tile >= 0 && tile < kSweep2Tiles ? tile : 0;
+    if (fine) tsweep2_pick<true, R>(c, L, v, coef, xcur, xnext, b, k, std::make_index_sequence<kSweep2Tiles>{});
+    else tsweep2_pick<false, R>(c, L, v, coef, xcur, xnext, b, k, std::make_index_sequence<kSweep2Tiles>{});
+}
+
+void sweep2_tile(int k, int* tx, int* ty)
+{
+    const int txs[kSweep2Tiles] = {std::tuple_element_t<0, Sweep2Tiles>::TX, std::tuple_element_t<1, Sweep2Tiles>::TX,
+                                   std::tuple_element_t<2, Sweep2Tiles>::TX};
+    const int tys[kSweep2Tiles] = {std::tuple_element_t<0, Sweep2Tiles>::TY, std::tuple_element_t<1, Sweep2Tiles>::TY,
+                                   std::tuple_element_t<2, Sweep2Tiles>::TY};
+    *tx = txs[k];
+    *ty = tys[k];
 }
 
 template <typename R>
@@ -946,7 +984,7 @@ void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next
 #define HB_TILE_INST(R)                                                                                             \
     template void launch_tsmooth<R>(Ctx*, const Level&, const BV&, const R*, bool, int, const R*, R*, const R*);     \
     template void launch_trb3<R>(Ctx*, const Level&, const BV&, const R*, bool, int, int, R*, const R*);             \
-    template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*);          \
+    template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*, int);     \
     template void launch_mac_sweep<R>(Ctx*, const Level&, const BV&, const R*, R*, const R*);                        \
     template void launch_tresid_restr<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, bool, \
                                          const R*, const R*, R*, R*);

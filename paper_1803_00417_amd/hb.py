@@ -28,7 +28,8 @@ EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_so
            "hb_advect", "hb_project", "hb_cfl_dt", "hb_step", "hb_create_batch", "hb_batch_size",
            "hb_step_batch", "hb_nn_create", "hb_nn_destroy", "hb_nn_param_count", "hb_nn_get_params",
            "hb_nn_set_params", "hb_nn_forward", "hb_nn_grad", "hb_nn_train_step", "hb_set_warm_start",
-           "hb_warm_start_uses", "hb_capture", "hb_capture_read", "hb_kernel_timing", "hb_kernel_timing_read"]
+           "hb_warm_start_uses", "hb_capture", "hb_capture_read", "hb_kernel_timing", "hb_kernel_timing_read",
+           "hb_tile_config"]
 
 
 class Grid(C.Structure):
@@ -100,6 +101,7 @@ def load():
     L.hb_nn_train_step.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float, P(C.c_double)]
     L.hb_set_warm_start.argtypes = [vp, C.c_int, vp]
     L.hb_warm_start_uses.argtypes = [vp]
+    L.hb_tile_config.argtypes = [vp, C.c_int, C.c_int, P(C.c_int), P(C.c_int)]
     L.hb_capture.argtypes = [vp, C.c_int, C.c_int]
     L.hb_capture_read.argtypes = [vp, C.c_int, vp, vp]
     L.hb_kernel_timing.argtypes = [vp, C.c_int]
@@ -300,6 +302,13 @@ class Context:
     def warm_start_uses(self):
         return load().hb_warm_start_uses(self._h)
 
+    def tile_config(self, op, level):
+        """(tx, ty) tile the autotuner chose for the fused sweep of problem op
+        on `level`, or None where no fused sweep runs"""
+        tx, ty = C.c_int(), C.c_int()
+        rc = load().hb_tile_config(self._h, op, level, C.byref(tx), C.byref(ty))
+        return (tx.value, ty.value) if rc == OK else None
+
     def capture(self, enable):
         self._check(load().hb_capture(self._h, OP_NODAL, int(enable)))
 
@@ -358,6 +367,13 @@ class BatchContext:
 
     def size(self):
         return load().hb_batch_size(self._h)
+
+    def tile_config(self, op, level):
+        """(tx, ty) tile the autotuner chose for the fused sweep of problem op
+        on `level`, or None where no fused sweep runs"""
+        tx, ty = C.c_int(), C.c_int()
+        rc = load().hb_tile_config(self._h, op, level, C.byref(tx), C.byref(ty))
+        return (tx.value, ty.value) if rc == OK else None
 
     def step(self, us, ps, dts=None, report=True, allow=()):
         """One step of every cavity; us[b], ps[b] GPU float64 tensors (in

@@ -1,7 +1,9 @@
 """Launch structures against the plain per-level, per-colour launches they
 replace: the single-workgroup coarse V-cycle (every level below a size limit
-in one launch, data in LDS; HB_TAIL=0 turns it off) and the fused-colour
-nodal sweep (all colours of a sweep in one launch, two in 3D; HB_FUSE=0).
+in one launch, data in LDS; HB_TAIL=0 turns it off), the fused sweeps (all
+colours, or in 2D both tensor components, of a sweep in one launch;
+HB_FUSE=0), and each candidate tile of the autotuned sweeps (HB_TILE=k
+forces candidate k).
 
 Each runs the same arithmetic per cell or node in the same order (the same
 Gauss-Seidel ordering, residual, restriction, prolongation and FP64
@@ -40,11 +42,12 @@ def _say(*a):
     print(*a, flush=True)
 
 
-PLAIN = {"tail": {"HB_TAIL": "0"}, "fuse": {"HB_FUSE": "0"}, "both": {"HB_TAIL": "0", "HB_FUSE": "0"}}
+PLAIN = {"tail": {"HB_TAIL": "0"}, "fuse": {"HB_FUSE": "0"}, "both": {"HB_TAIL": "0", "HB_FUSE": "0"},
+         "tile1": {"HB_TILE": "1"}, "tile2": {"HB_TILE": "2"}}
 
 
 def _context(make, env):
-    old = {k: os.environ.get(k) for k in ("HB_TAIL", "HB_FUSE")}
+    old = {k: os.environ.get(k) for k in ("HB_TAIL", "HB_FUSE", "HB_TILE")}
     for k in old:
         os.environ.pop(k, None)
     os.environ.update(env)
@@ -120,3 +123,22 @@ def test_launch_structure_in_batch_is_bit_identical():
     for b in range(len(specs)):
         assert np.array_equal(outs[0][0][b], outs[1][0][b]), b
         assert np.array_equal(outs[0][1][b], outs[1][1][b]), b
+
+
+def test_autotuner_reports_candidate_tiles():
+    _say("tile autotuner")
+    s = CASES["lid2d_96x48"]()
+    g, fl = hip_objs(s)
+    ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {})
+    cand = {"visc": {(64, 8), (32, 16), (128, 4)}, "nodal": {(64, 16), (128, 8), (32, 32)}}
+    tv = [ctx.tile_config(hb.OP_VISC, l) for l in range(8)]
+    tn = [ctx.tile_config(hb.OP_NODAL, l) for l in range(8)]
+    _say("  tensor", tv, "nodal", tn)
+    assert tv[0] in cand["visc"] and tn[0] in cand["nodal"]
+    assert all(t is None or t in cand["visc"] for t in tv)
+    assert all(t is None or t in cand["nodal"] for t in tn)
+    assert ctx.tile_config(hb.OP_MAC, 0) is None
+    ctx.close()
+    ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "2"})
+    assert ctx.tile_config(hb.OP_VISC, 0) == (128, 4) and ctx.tile_config(hb.OP_NODAL, 0) == (32, 32)
+    ctx.close()
