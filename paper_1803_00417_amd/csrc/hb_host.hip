@@ -1045,8 +1045,10 @@ static void destroy_ctx(Ctx* c);
 
 // Tile autotuning.  For every level of the nodal problem (and, in 2D, of
 // the tensor problem) on which a fused sweep runs, each candidate tile is
-// timed on the level's own arenas (one warm-up sweep and three timed FP64
-// sweeps) and the fastest is kept.  The candidates compute the same values
+// timed on the level's own arenas and the fastest is kept: after a warm-up
+// sweep per candidate, kRounds rounds time one sweep of every candidate in
+// turn (an event pair per sweep), and a candidate's time is its minimum, so
+// one slow sample does not decide.  The candidates compute the same values
 // bit for bit, so the choice changes only the speed.  HB_TILE=k in the
 // environment forces candidate k instead.
 static void autotune(Ctx* c)
@@ -1054,8 +1056,11 @@ static void autotune(Ctx* c)
     if (!c->fuse) return;
     const char* e = std::getenv("HB_TILE");
     const int forced = (e && e[0] >= '0' && e[0] <= '9') ? std::atoi(e) % kTileCandidates : -1;
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (forced < 0 && (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)) return;
+    constexpr int kRounds = 6;
+    hipEvent_t ev[2 * kRounds * kTileCandidates] = {};
+    if (forced < 0)
+        for (hipEvent_t& x : ev)
+            if (hipEventCreate(&x) != hipSuccess) return;
     MG* ms[2] = {&c->visc, &c->nodal};
     for (MG* m : ms) {
         if (m->op == HB_OP_VISC && c->dim != 2) continue;
@@ -1077,23 +1082,33 @@ static void autotune(Ctx* c)
                 else
                     launch_nodal_sweep<double>(c, L, v, L.xb[0], L.xb[1], L.b, k);
             };
+            for (int k = 0; k < kTileCandidates; ++k) sweep(k);
+            for (int r = 0; r < kRounds; ++r)
+                for (int k = 0; k < kTileCandidates; ++k) {
+                    hipEvent_t* p = ev + 2 * (r * kTileCandidates + k);
+                    (void)hipEventRecord(p[0], c->s);
+                    sweep(k);
+                    (void)hipEventRecord(p[1], c->s);
+                }
+            if (hipEventSynchronize(ev[2 * kRounds * kTileCandidates - 1]) != hipSuccess) continue;
             float best = 0.0f;
             for (int k = 0; k < kTileCandidates; ++k) {
-                sweep(k);
-                (void)hipEventRecord(t0, c->s);
-                for (int r = 0; r < 3; ++r) sweep(k);
-                (void)hipEventRecord(t1, c->s);
-                float ms_k = 0.0f;
-                if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms_k, t0, t1) != hipSuccess) continue;
-                if (k == 0 || ms_k < best) {
-                    best = ms_k;
+                float tk = 0.0f;
+                for (int r = 0; r < kRounds; ++r) {
+                    const hipEvent_t* p = ev + 2 * (r * kTileCandidates + k);
+                    float t = 0.0f;
+                    if (hipEventElapsedTime(&t, p[0], p[1]) != hipSuccess) t = 1e30f;
+                    tk = r == 0 ? t : (t < tk ? t : tk);
+                }
+                if (k == 0 || tk < best) {
+                    best = tk;
                     L.tile = k;
                 }
             }
         }
     }
-    if (t0) (void)hipEventDestroy(t0);
-    if (t1) (void)hipEventDestroy(t1);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
 }
 
 static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, const hb_step_opts* opts,
