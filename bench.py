@@ -232,7 +232,11 @@ def main():
     launches, kms, kbytes = r["kt"]
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
     w = inputs.WORKLOADS[a.workload]
-    kname = "hb::k_tsweep2<true,double>" if w["dim"] == 2 else "hb::k_trb3<true,double>"
+    # the 2D kernel's traffic depends on the tile the context kept for the
+    # finest level, so its rows are keyed by the tile shape
+    t0 = r["tiles"]["tensor"][0] if r["tiles"]["tensor"] else None
+    kname = ("hb::k_tsweep2<true,double>@%dx%d" % tuple(t0 or (0, 0)) if w["dim"] == 2
+             else "hb::k_trb3<true,double>")
     wname = "cavity2d_512" if w["dim"] == 2 else "cavity3d_128"
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, wname),
