@@ -232,16 +232,24 @@ def main():
     launches, kms, kbytes = r["kt"]
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
     w = inputs.WORKLOADS[a.workload]
-    # the 2D kernel's traffic depends on the tile the context kept for the
-    # finest level, so its rows are keyed by the tile shape
+    # the 2D kernel (and its traffic) depends on the candidate the context
+    # kept for the finest level: its rows are keyed by tile, threads and
+    # sweeps per launch
     t0 = r["tiles"]["tensor"][0] if r["tiles"]["tensor"] else None
-    kname = ("hb::k_tsweep2<true,double>@%dx%d" % tuple(t0 or (0, 0)) if w["dim"] == 2
-             else "hb::k_trb3<true,double>")
+    if w["dim"] == 2:
+        tx, ty, th, sw = t0 or (0, 0, 0, 0)
+        kname = "fine2d@%dx%dx%ds%d" % (tx, ty, th, sw)
+        klabel = ("%s (2D: %s of both velocity components in one launch, finest level, tile %dx%d, %d threads)"
+                  % ("k_tsweep2" if th == 256 else "k_tsweepN", "one red-black sweep" if sw == 1
+                     else "%d red-black sweeps" % sw, tx, ty, th))
+    else:
+        kname = "hb::k_trb3<true,double>"
+        klabel = "k_trb3 (3D: one colour of one velocity component, finest level)"
     wname = "cavity2d_512" if w["dim"] == 2 else "cavity3d_128"
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, wname),
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-probe scaled)",
-                "kernel": ("k_tsweep2 (2D: red-black sweep of both velocity components in one launch, finest level)" if w["dim"] == 2 else "k_trb3 (3D: one colour of one velocity component, finest level)"),
+                "kernel": klabel,
                 "launches": launches, "avg_launch_us": 1e3 * kms / max(launches, 1),
                 "alg_bytes_per_launch": kbytes / max(launches, 1)}
     out = {"metric": "cell-steps/s", "value": value, "unit": "cell-steps/s", "n_gpus": 1,

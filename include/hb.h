@@ -235,26 +235,36 @@ int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e);
 /* Measurement support.  While enabled, every launch of the tensor viscous
  * smoother on the finest multigrid level is timed with events that the
  * dispatch itself records (2D: one red-black sweep of both velocity
- * components; 3D: one colour of one component); hb_kernel_timing_read
+ * components, or two where the level's autotuned candidate runs two sweeps
+ * per launch; 3D: one colour of one component); hb_kernel_timing_read
  * synchronises, and returns the number of launches, their summed device
  * time and their summed algorithmic bytes (2D: both x components, eta/Re
- * and both b components read once, x written once; 3D: every x component
- * and eta/Re read once, the colour's b read and x written; words of the
- * storage type).  Enabling resets the counters. */
+ * and both b components read once, x written once, per launch whatever its
+ * sweep count; 3D: every x component and eta/Re read once, the colour's b
+ * read and x written; words of the storage type).  Enabling resets the
+ * counters. */
 int hb_kernel_timing(hb_ctx* ctx, int enable);
 int hb_kernel_timing_read(hb_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes);
 
 /* Tile autotuning (batched sweeps; Sec. III.D's tiling, chosen for the GPU
  * by measurement).  At context creation every multigrid level on which a
  * fused smoother sweep runs (nodal problem; tensor problem in 2D) times its
- * candidate tiles on its own arenas and keeps the fastest; all candidates
- * compute the same values.  hb_tile_config reports the tile (tx x ty cells
- * or nodes per plane) chosen for level `level` of problem op (HB_OP_VISC,
- * 2D only, or HB_OP_NODAL).  Returns HB_ERR_ARG for other problems, for
- * levels without sweep launches (the coarsest, and those run by the
- * single-workgroup coarse cycle) and when HB_FUSE=0 turned the fused sweeps
- * off.  HB_TILE=k in the environment at creation forces candidate k. */
-int hb_tile_config(const hb_ctx* ctx, int op, int level, int* tx, int* ty);
+ * candidates over two sweeps on its own arenas and keeps the fastest; all
+ * candidates compute the same values.  A candidate is a tile (tx x ty cells
+ * or nodes per plane) with a workgroup size and, for the 2D tensor problem,
+ * the number of sweeps one launch runs (1, or 2 with the tile's halo doubled
+ * and everything staged in LDS; two need every periodic extent of the level
+ * to be at least 8, and are used when the cycle's pre- and post-smoothing
+ * sweep counts are even with an even sum of halves, as for V(2,2)).
+ * hb_tile_config reports, for level `level` of problem op (HB_OP_VISC, 2D
+ * only, or HB_OP_NODAL), the tile, the threads per workgroup and the
+ * sweeps per launch; threads and sweeps may be NULL.  Returns HB_ERR_ARG
+ * for other problems, for levels without sweep launches (the coarsest, and
+ * those run by the single-workgroup coarse cycle) and when HB_FUSE=0 turned
+ * the fused sweeps off.  HB_TILE=k in the environment at creation forces
+ * candidate k (modulo the problem's candidate count: 6 for the 2D tensor
+ * problem, 3 for the nodal one). */
+int hb_tile_config(const hb_ctx* ctx, int op, int level, int* tx, int* ty, int* threads, int* sweeps);
 
 #ifdef __cplusplus
 }

@@ -179,7 +179,7 @@ static int build_mg(Ctx* c, MG& m, int op)
     // single-workgroup coarse tail: the first level from which every
     // cavity's remaining levels fit the LDS budget
     m.tail_lt = -1;
-    if ((op == HB_OP_VISC || op == HB_OP_MAC) && c->lds_budget > 0) {
+    if ((op == HB_OP_VISC || op == HB_OP_MAC) && c->tail && c->lds_budget > 0) {
         for (int l = 1; l < m.nlev && m.tail_lt < 0; ++l) {
             if (m.nlev - l > kMaxTail) continue;
             size_t need[2] = {0, 0};
@@ -364,16 +364,19 @@ static BV paired(BV v, const Level& P)
 }
 
 template <typename R>
-static void smooth(Ctx* c, MG& m, int l, int sweeps)
+static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair)
 {
     using B = LB<R>;
     Level& L = m.L[l];
     const BV v = smooth_view(c, L);
     for (int s = 0; s < sweeps; ++s) {
         if (m.op == HB_OP_VISC && c->dim == 2 && c->fuse) {
-            // both components of the sweep in one launch
-            launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile);
+            // both components of the sweep in one launch; with `pair`, two
+            // sweeps per launch where the level's candidate runs them so
+            const int n = (pair && L.sweeps == 2 && sweeps - s >= 2) ? 2 : 1;
+            launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n);
             L.cur ^= 1;
+            s += n - 1;
         } else if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0)) {
             // fused red-black sweep per component into the other buffer (2D,
             // and the small 3D levels, where it halves the launches)
@@ -464,9 +467,13 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
     if (L.any_sm) {
         Level& C = m.L[l + 1];
         const BV v = smooth_view(c, L);
+        // sweeps are paired into one launch only where each level then
+        // swaps its buffers an even number of times per cycle, as the
+        // captured graph of the coarse levels requires
+        const bool pair = nu1 % 2 == 0 && nu2 % 2 == 0 && ((nu1 + nu2) / 2) % 2 == 0;
         const BV vpc = paired(v, C);                     // fine level, paired with the coarse one
         const BV vc = paired(all_view(c, C, c->act), L);  // coarse level, paired with the fine one
-        smooth<R>(c, m, l, nu1);
+        smooth<R>(c, m, l, nu1, pair);
         if (m.op == HB_OP_VISC) {
             launch_tresid_restr<R>(c, L, vpc, C.gall, C.o, tcoef<R>(m, l), l == 0, B::x(L), B::b(L), B::b(C), B::x(C));
         } else if (m.op == HB_OP_MAC) {
@@ -478,7 +485,7 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
         vcycle<R>(c, m, l + 1, nu1, nu2);
         if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L, vpc, C.gall, C.o, B::x(C), B::x(L));
         else launch_prolong_cells<R>(c, L, vpc, C.gall, C.o, m.ncomp, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
-        smooth<R>(c, m, l, nu2);
+        smooth<R>(c, m, l, nu2, pair);
     }
     if (L.any_cs) launch_coarse_solve<R>(c, m, l, c->act, B::b(L), B::x(L));
 }
@@ -1043,32 +1050,59 @@ static const char* check_fluid(const hb_fluid* fluid)
 
 static void destroy_ctx(Ctx* c);
 
+// True when every periodic extent of the level's grids is at least the halo
+// of a launch that runs two tensor sweeps.
+static bool level_pairs(const Level& L)
+{
+    for (const GridD& g : L.hg)
+        for (int a = 0; a < g.dim; ++a)
+            if (g.per[a] && g.n[a] < 8) return false;
+    return true;
+}
+
 // Tile autotuning.  For every level of the nodal problem (and, in 2D, of
-// the tensor problem) on which a fused sweep runs, each candidate tile is
-// timed on the level's own arenas and the fastest is kept: after a warm-up
-// sweep per candidate, kRounds rounds time one sweep of every candidate in
-// turn (an event pair per sweep), and a candidate's time is its minimum, so
-// one slow sample does not decide.  The candidates compute the same values
-// bit for bit, so the choice changes only the speed.  HB_TILE=k in the
-// environment forces candidate k instead.
+// the tensor problem) on which a fused sweep runs, each candidate is timed
+// on the level's own arenas and the fastest is kept.  The unit timed is two
+// sweeps: two launches of one sweep, or one launch where the candidate runs
+// two sweeps in one and the level allows it.  After a warm-up unit per
+// candidate, kRounds rounds time one unit of every candidate in turn (an
+// event pair per unit), and a candidate's time is its minimum, so one slow
+// sample does not decide.  The candidates compute the same values bit for
+// bit, so the choice changes only the speed.  HB_TILE=k in the environment
+// forces candidate k instead (modulo the problem's candidate count).
 static void autotune(Ctx* c)
 {
     if (!c->fuse) return;
     const char* e = std::getenv("HB_TILE");
-    const int forced = (e && e[0] >= '0' && e[0] <= '9') ? std::atoi(e) % kTileCandidates : -1;
+    const int forced = (e && e[0] >= '0' && e[0] <= '9') ? std::atoi(e) : -1;
     constexpr int kRounds = 6;
-    hipEvent_t ev[2 * kRounds * kTileCandidates] = {};
+    constexpr int kMaxCands = kSweep2Cands > kNodalCands ? kSweep2Cands : kNodalCands;
+    hipEvent_t ev[2 * kRounds * kMaxCands] = {};
     if (forced < 0)
         for (hipEvent_t& x : ev)
             if (hipEventCreate(&x) != hipSuccess) return;
     MG* ms[2] = {&c->visc, &c->nodal};
     for (MG* m : ms) {
-        if (m->op == HB_OP_VISC && c->dim != 2) continue;
+        const bool visc = m->op == HB_OP_VISC;
+        if (visc && c->dim != 2) continue;
+        const int nc = visc ? kSweep2Cands : kNodalCands;
         for (int l = 0; l < m->nlev; ++l) {
             Level& L = m->L[l];
             if (!L.any_sm || (m->tail_lt >= 0 && l >= m->tail_lt)) continue;
+            // sweeps per launch of each candidate on this level, and whether
+            // it fits the LDS at all
+            int nsw[kMaxCands];
+            bool usable[kMaxCands];
+            for (int k = 0; k < nc; ++k) {
+                nsw[k] = 1;
+                usable[k] = true;
+                if (!visc) continue;
+                if (sweep2_shape(k).nsw >= 2 && level_pairs(L) && sweep2_lds(k, 2) <= c->lds_budget) nsw[k] = 2;
+                usable[k] = sweep2_lds(k, 1) <= c->lds_budget;
+            }
             if (forced >= 0) {
-                L.tile = forced;
+                L.tile = usable[forced % nc] ? forced % nc : 0;
+                L.sweeps = nsw[L.tile];
                 continue;
             }
             BV v{L.gsm, L.o, L.of, nullptr, 1};
@@ -1076,33 +1110,43 @@ static void autotune(Ctx* c)
                 v.one = 1;
                 v.g1 = L.hg[0];
             }
-            auto sweep = [&](int k) {
-                if (m->op == HB_OP_VISC)
-                    launch_tsweep2<double>(c, L, v, tcoef<double>(*m, l), l == 0, L.xb[0], L.xb[1], L.b, k);
-                else
+            auto unit = [&](int k) {
+                if (visc && nsw[k] == 2) {
+                    launch_tsweep2<double>(c, L, v, tcoef<double>(*m, l), l == 0, L.xb[0], L.xb[1], L.b, k, 2);
+                } else if (visc) {
+                    launch_tsweep2<double>(c, L, v, tcoef<double>(*m, l), l == 0, L.xb[0], L.xb[1], L.b, k, 1);
+                    launch_tsweep2<double>(c, L, v, tcoef<double>(*m, l), l == 0, L.xb[1], L.xb[0], L.b, k, 1);
+                } else {
                     launch_nodal_sweep<double>(c, L, v, L.xb[0], L.xb[1], L.b, k);
+                    launch_nodal_sweep<double>(c, L, v, L.xb[1], L.xb[0], L.b, k);
+                }
             };
-            for (int k = 0; k < kTileCandidates; ++k) sweep(k);
+            for (int k = 0; k < nc; ++k)
+                if (usable[k]) unit(k);
             for (int r = 0; r < kRounds; ++r)
-                for (int k = 0; k < kTileCandidates; ++k) {
-                    hipEvent_t* p = ev + 2 * (r * kTileCandidates + k);
+                for (int k = 0; k < nc; ++k) {
+                    hipEvent_t* p = ev + 2 * (r * nc + k);
                     (void)hipEventRecord(p[0], c->s);
-                    sweep(k);
+                    if (usable[k]) unit(k);
                     (void)hipEventRecord(p[1], c->s);
                 }
-            if (hipEventSynchronize(ev[2 * kRounds * kTileCandidates - 1]) != hipSuccess) continue;
+            if (hipEventSynchronize(ev[2 * kRounds * nc - 1]) != hipSuccess) continue;
             float best = 0.0f;
-            for (int k = 0; k < kTileCandidates; ++k) {
+            bool have = false;
+            for (int k = 0; k < nc; ++k) {
+                if (!usable[k]) continue;
                 float tk = 0.0f;
                 for (int r = 0; r < kRounds; ++r) {
-                    const hipEvent_t* p = ev + 2 * (r * kTileCandidates + k);
+                    const hipEvent_t* p = ev + 2 * (r * nc + k);
                     float t = 0.0f;
                     if (hipEventElapsedTime(&t, p[0], p[1]) != hipSuccess) t = 1e30f;
                     tk = r == 0 ? t : (t < tk ? t : tk);
                 }
-                if (k == 0 || tk < best) {
+                if (!have || tk < best) {
                     best = tk;
+                    have = true;
                     L.tile = k;
+                    L.sweeps = nsw[k];
                 }
             }
         }
@@ -1175,21 +1219,23 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         v.sc = c->sc + (long)b * S_NSLOT;
         v.hsc = c->hsc + (long)b * S_NSLOT;
     }
-    // LDS a coarse-tail workgroup may take: the device's per-workgroup limit
-    // less the kernel's static arrays; HB_TAIL=0 in the environment turns the
-    // tail off (every level then runs its own launches)
+    // dynamic LDS a workgroup may take (coarse tail, staged sweeps): the
+    // device's per-workgroup limit less the kernels' static arrays; HB_TAIL=0
+    // in the environment turns the tail off (every level then runs its own
+    // launches)
     {
         int dev = 0, lim = 0;
         const char* e = std::getenv("HB_TAIL");
-        const bool on = !(e && e[0] == '0');
+        c->tail = !(e && e[0] == '0');
         // HB_FUSE=0: one launch per colour in the nodal and MAC smoothers
         // and per component in the 2D tensor smoother
         const char* f = std::getenv("HB_FUSE");
         c->fuse = !(f && f[0] == '0');
-        if (on && hipGetDevice(&dev) == hipSuccess &&
+        if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 8192) {
             c->lds_budget = (size_t)lim - 4096;
             tail_allow_lds(c->lds_budget);
+            sweep2_allow_lds(c->lds_budget);
         }
     }
     int rc;
@@ -1495,7 +1541,7 @@ int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e)
 
 int hb_warm_start_uses(const hb_ctx* ctx) { return ctx ? (int)C_(ctx)->ws_report_used : 0; }
 
-int hb_tile_config(const hb_ctx* ctx, int op, int level, int* tx, int* ty)
+int hb_tile_config(const hb_ctx* ctx, int op, int level, int* tx, int* ty, int* threads, int* sweeps)
 {
     if (!ctx || !tx || !ty) return HB_ERR_ARG;
     const Ctx* c = C_(ctx);
@@ -1503,8 +1549,19 @@ int hb_tile_config(const hb_ctx* ctx, int op, int level, int* tx, int* ty)
     if (!m || !c->fuse || (op == HB_OP_VISC && c->dim != 2) || level < 0 || level >= m->nlev) return HB_ERR_ARG;
     const Level& L = m->L[level];
     if (!L.any_sm || (m->tail_lt >= 0 && level >= m->tail_lt)) return HB_ERR_ARG;
-    if (op == HB_OP_VISC) sweep2_tile(L.tile, tx, ty);
-    else nodal_sweep_tile(c->dim, L.tile, tx, ty);
+    int th = 256, sw = 1;
+    if (op == HB_OP_VISC) {
+        const SweepShape sh = sweep2_shape(L.tile);
+        *tx = sh.tx;
+        *ty = sh.ty;
+        th = sh.threads;
+        sw = L.sweeps;
+    } else {
+        nodal_sweep_tile(c->dim, L.tile, tx, ty);
+        th = c->dim == 2 ? 256 : 512;
+    }
+    if (threads) *threads = th;
+    if (sweeps) *sweeps = sw;
     return HB_OK;
 }
 

@@ -141,6 +141,7 @@ struct Level {
     std::vector<long> ho, hof, hou, hnu;
     bool any_sm = false, any_cs = false;   // some cavity smooths here / is at its coarsest
     int tile = 0;            // smoother tile candidate chosen by the autotuner
+    int sweeps = 1;          // 2D tensor problem: sweeps per launch of that candidate
     double* X() const { return xb[cur]; }
 };
 
@@ -278,7 +279,8 @@ struct Ctx {
     bool cap = false;
     double *cap_r0 = nullptr, *cap_e = nullptr, *cap_x0 = nullptr;
     long ws_report_used = 0;      // solves that started from the network's guess
-    size_t lds_budget = 0;        // dynamic LDS bytes a coarse-tail workgroup may use (0: no tail)
+    size_t lds_budget = 0;        // dynamic LDS bytes one workgroup may use
+    bool tail = false;            // coarse levels in one single-workgroup launch
     bool fuse = true;             // fused-colour nodal sweeps
     std::string err;
 };
@@ -347,13 +349,21 @@ void launch_eta_over_re(Ctx* c, const Cav& v, const double* eta, double* etae);
 template <typename R>
 void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, const R* xcur, R* xnext,
                     const R* b);
-// 2D: one red-black sweep of both components from xcur into xnext, with
-// candidate tile `tile` (0 .. 2); sweep2_tile gives its extents
+// 2D: nsw (1 or 2) red-black sweeps of both components from xcur into
+// xnext in one launch, with candidate `tile` (0 .. kSweep2Cands - 1); two
+// sweeps need a candidate whose sweeps may be paired and every periodic
+// extent of the level at least 8.  sweep2_shape gives a candidate's tile,
+// threads and most sweeps per launch, sweep2_lds its dynamic LDS bytes.
+struct SweepShape {
+    int tx, ty, threads, nsw;
+};
+constexpr int kSweep2Cands = 6;
 template <typename R>
 void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b,
-                    int tile);
-void sweep2_tile(int tile, int* tx, int* ty);
-constexpr int kTileCandidates = 3;
+                    int tile, int nsw);
+SweepShape sweep2_shape(int tile);
+size_t sweep2_lds(int tile, int nsw);
+void sweep2_allow_lds(size_t bytes);
 template <typename R>
 void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b);
 template <typename R>
@@ -382,10 +392,12 @@ void launch_prolong_cells(Ctx* c, const Level& L, const BV& v, const GridD* gc, 
                           double wall_sign, const R* e, R* x);
 template <typename R> void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b);
 // one whole Gauss-Seidel sweep from cur into next (one launch, two in 3D),
-// with candidate tile `tile` (0 .. 2); nodal_sweep_tile gives its extents
+// with candidate tile `tile` (0 .. kNodalCands - 1); nodal_sweep_tile gives
+// its extents
 template <typename R>
 void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile);
 void nodal_sweep_tile(int dim, int tile, int* tx, int* ty);
+constexpr int kNodalCands = 3;
 // r = b - K x (slot >= 0: FP64 only, max-norm into each cavity's slot) or y = K x (b null)
 template <typename R>
 void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R* b, R* r, int slot);

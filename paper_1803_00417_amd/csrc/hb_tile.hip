@@ -29,10 +29,21 @@ struct TileShape {
 template <int DIM> struct TileCfg;
 template <> struct TileCfg<2> : TileShape<64, 8, 1, 256> {};
 template <> struct TileCfg<3> : TileShape<32, 4, 4, 512> {};
-// candidate tiles of the 2D fused tensor sweep, chosen per level by the
-// autotuner (index 0 is the default)
-using Sweep2Tiles = std::tuple<TileShape<64, 8, 1, 256>, TileShape<32, 16, 1, 256>, TileShape<128, 4, 1, 256>>;
-constexpr int kSweep2Tiles = 3;
+// Candidates of the 2D fused tensor sweep, chosen per level by the
+// autotuner (index 0 is the default): the tile with its thread count, the
+// most sweeps one launch may run (NSW), and whether b and the face
+// viscosities are staged in LDS (k_tsweepN) or held in registers (k_tsweep2,
+// one sweep per launch).
+template <class CF_, int NSW_, bool STAGED_>
+struct SweepCand {
+    using CF = CF_;
+    static constexpr int NSW = NSW_;
+    static constexpr bool STAGED = STAGED_;
+};
+using Sweep2Cands = std::tuple<SweepCand<TileShape<64, 8, 1, 256>, 1, false>, SweepCand<TileShape<32, 16, 1, 256>, 1, false>,
+                               SweepCand<TileShape<128, 4, 1, 256>, 1, false>, SweepCand<TileShape<32, 16, 1, 512>, 2, true>,
+                               SweepCand<TileShape<64, 16, 1, 512>, 2, true>, SweepCand<TileShape<32, 16, 1, 1024>, 2, true>>;
+static_assert(std::tuple_size_v<Sweep2Cands> == kSweep2Cands, "candidate count");
 
 
 // Source of a tile position (i, j, k) that may lie outside the box:
@@ -465,6 +476,171 @@ k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
         const int G[2] = {ox + rx, oy + ry};
         if (G[0] >= g.n[0] || G[1] >= g.n[1]) continue;
         xnext[q * N + cid(g, G[0], G[1], 0)] = s[q * T::NS + T::at(rx + 4, ry + 4, 0)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D: NSW whole sweeps (both components) in one launch, everything staged.
+// The 4 NSW half steps run on the tile grown by 4 NSW - 1, ..., 1, 0 rings
+// (the ring argument above, applied once per half step), on a tile with a
+// halo of 4 NSW.  Besides both components of x, the fill stages both
+// components of b and the face viscosities (coarse levels: beta on the low x
+// and the low y face of each position; finest level: eta/Re) in LDS, so a
+// half step reads no global memory and holds nothing in registers across
+// the barriers.  The arithmetic per cell is that of k_tsweep2, so NSW = 2
+// gives bit for bit the result of two launches of one sweep.  A periodic
+// extent must be at least the halo (positions wrap once).
+// ---------------------------------------------------------------------------
+
+// LDS arrays of the staged tile, each Tile<2, H, CF>::NS long
+enum { ST_X0 = 0, ST_X1 = 1, ST_B0 = 2, ST_B1 = 3, ST_E = 4, ST_FX = 4, ST_FY = 5 };
+
+template <bool FINE, int H, typename R, class CF>
+__device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, const R* __restrict__ b,
+                                   const R* __restrict__ coef, R* s, int ox, int oy, long N)
+{
+    using T = Tile<2, H, CF>;
+    constexpr int TH = CF::THREADS;
+    constexpr int K = (T::NS + TH - 1) / TH;
+    constexpr int NA = FINE ? 5 : 6;
+    const bool inner = ox - H >= 0 && ox + T::TX + H <= g.n[0] && oy - H >= 0 && oy + T::TY + H <= g.n[1];
+    const long fo1 = FINE ? 0 : foffset(g, 1);
+    R v[NA][K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int t = threadIdx.x + u * TH;
+        const int tt = t < T::NS ? t : 0;
+        const int lx = tt % T::SX, ly = tt / T::SX;
+        const int i = ox - H + lx, j = oy - H + ly;
+        bool ok = true, ng = false;
+        const long idx = inner ? cid(g, i, j, 0) : tile_src<2>(g, i, j, 0, ok, ng);
+        const R x0 = x[idx], x1 = x[N + idx];
+        // b is read only at cells that are updated, which lie in the box
+        v[ST_B0][u] = b[idx];
+        v[ST_B1][u] = b[N + idx];
+        if (FINE) {
+            const R e = coef[idx];
+            v[ST_E][u] = ok ? e : R(0);
+        } else {
+            // position (i, j) holds the faces on its low x and low y side:
+            // wrapped once along periodic axes, then clamped to the face
+            // range (clamped values are read only by cells outside the box
+            // or beyond the one wrap, whose results are not kept)
+            int wi = i, wj = j;
+            if (g.per[0]) wi = i < 0 ? i + g.n[0] : (i >= g.n[0] ? i - g.n[0] : i);
+            if (g.per[1]) wj = j < 0 ? j + g.n[1] : (j >= g.n[1] ? j - g.n[1] : j);
+            const int ax = min(max(wi, 0), g.n[0] - g.per[0]);
+            const int ay = min(max(wj, 0), g.n[1] - 1);
+            const int bx = min(max(wi, 0), g.n[0] - 1);
+            const int by = min(max(wj, 0), g.n[1] - g.per[1]);
+            v[ST_FX][u] = coef[fid(g, 0, ax, ay, 0)];
+            v[ST_FY][u] = coef[fo1 + fid(g, 1, bx, by, 0)];
+        }
+        v[ST_X0][u] = ok ? (ng ? -x0 : x0) : R(0);
+        v[ST_X1][u] = ok ? (ng ? -x1 : x1) : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int t = threadIdx.x + u * TH;
+        if (t < T::NS)
+#pragma unroll
+            for (int a = 0; a < NA; ++a) s[a * T::NS + t] = v[a][u];
+    }
+}
+
+// one half step (component C, colour COLOUR, tile grown by RING) of the
+// staged sweep; the same per-cell arithmetic and ghost updates as HalfStep
+template <int C, int COLOUR, int RING, int H, bool FINE, typename R, class CF>
+__device__ inline void staged_half(const GridD& g, R* s, R dt, R ihh, int ox, int oy)
+{
+    using T = Tile<2, H, CF>;
+    constexpr int TH = CF::THREADS;
+    constexpr int K = ((T::TX + 2 * RING) / 2 * (T::TY + 2 * RING) + TH - 1) / TH;
+    R* sc = s + C * T::NS;
+    const R* sb = s + (ST_B0 + C) * T::NS;
+    const R* e = s + ST_E * T::NS;
+    const R* fx = s + ST_FX * T::NS;
+    const R* fy = s + ST_FY * T::NS;
+    int G[K][3], L[K];
+    bool ok[K];
+    R nv[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        ok[u] = colour_cell2<H, CF>(g, threadIdx.x + u * TH, RING, COLOUR, ox, oy, G[u], L[u]);
+        const int l = L[u];
+        R bf[4];
+        if (!FINE) {
+            bf[0] = fx[l];
+            bf[1] = fx[l + 1];
+            bf[2] = fy[l];
+            bf[3] = fy[l + T::SX];
+        }
+        R dg;
+        const R vd = visc_div_ih<2, FINE, R>(bf, s, T::NS, T::SX, T::SX * T::SY, e, C, wall_mask<2>(g, G[u]), l, dt,
+                                             ihh, &dg);
+        const R xc = sc[l];
+        const R Au = xc - dt * vd;
+        nv[u] = xc + (sb[l] - Au) / dg;
+    }
+    const int off[2] = {1, T::SX};
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        if (!ok[u]) continue;
+        sc[L[u]] = nv[u];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (g.per[a]) continue;
+            if (G[u][a] == 0) sc[L[u] - off[a]] = -nv[u];
+            else if (G[u][a] == g.n[a] - 1) sc[L[u] + off[a]] = -nv[u];
+        }
+    }
+}
+
+// sweep SW of NSW: its four half steps, each followed by a barrier
+template <int SW, int NSW, bool FINE, typename R, class CF>
+__device__ inline void staged_sweeps(const GridD& g, R* s, R dt, R ihh, int ox, int oy)
+{
+    if constexpr (SW < NSW) {
+        constexpr int H = 4 * NSW, R0 = H - 1 - 4 * SW;
+        staged_half<0, 0, R0, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
+        __syncthreads();
+        staged_half<0, 1, R0 - 1, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
+        __syncthreads();
+        staged_half<1, 0, R0 - 2, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
+        __syncthreads();
+        staged_half<1, 1, R0 - 3, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
+        __syncthreads();
+        staged_sweeps<SW + 1, NSW, FINE, R, CF>(g, s, dt, ihh, ox, oy);
+    }
+}
+
+template <bool FINE, typename R, class CF, int NSW>
+__global__ void __launch_bounds__(CF::THREADS)
+k_tsweepN(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, const R* __restrict__ xcura,
+          R* __restrict__ xnexta, const R* __restrict__ ba)
+{
+    constexpr int H = 4 * NSW;
+    using T = Tile<2, H, CF>;
+    constexpr int TH = CF::THREADS;
+    TILE_ENTER(2, T);
+    const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
+    const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
+    const R* xcur = xcura + 2 * cell0;
+    R* xnext = xnexta + 2 * cell0;
+    const R* b = ba + 2 * cell0;
+    const long N = ncells(g);
+    R* s = reinterpret_cast<R*>(tile_lds);
+    fill_staged<FINE, H, R, CF>(g, xcur, b, coef, s, ox, oy, N);
+    const R h = (R)g.h;
+    const R ihh = R(1) / (h * h);
+    __syncthreads();
+    staged_sweeps<0, NSW, FINE, R, CF>(g, s, dt, ihh, ox, oy);
+    for (int t = threadIdx.x; t < 2 * T::TX * T::TY; t += TH) {
+        const int q = t / (T::TX * T::TY), r = t - q * (T::TX * T::TY);
+        const int rx = r % T::TX, ry = r / T::TX;
+        const int G[2] = {ox + rx, oy + ry};
+        if (G[0] >= g.n[0] || G[1] >= g.n[1]) continue;
+        xnext[q * N + cid(g, G[0], G[1], 0)] = s[q * T::NS + T::at(rx + H, ry + H, 0)];
     }
 }
 
@@ -908,49 +1084,114 @@ void launch_tresid_restr(Ctx* c, const Level& L, const BV& v, const GridD* gc, c
     }
 }
 
-template <bool FINE, typename R, class CF>
-static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b)
+template <bool FINE, typename R, class CAND>
+static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b,
+                         int nsw)
 {
-    using T = Tile<2, 4, CF>;
+    using CF = typename CAND::CF;
     const bool timed = c->ktm.on && FINE;
     BV vv = v;
     const dim3 grid = tile_grid<2, CF>(c, L, vv);
-    const size_t lds = sizeof(R) * (FINE ? 3 : 2) * T::NS;
-    // algorithmic bytes of one sweep of both components: both components of
-    // x, eta/Re and both components of b read once, x written once
+    // algorithmic bytes of a launch (one sweep or several in LDS): both
+    // components of x, eta/Re and both components of b read once, x written once
     const double N = level_cells(L);
     const double bytes = sizeof(R) * (2.0 * N + N + 2.0 * N + 2.0 * N);
-    tlaunch(c, timed, bytes, k_tsweep2<FINE, R, CF>, grid, dim3(CF::THREADS), lds, vv, coef, (const double*)c->sc, xcur,
-            xnext, b);
+    if constexpr (!CAND::STAGED) {
+        using T = Tile<2, 4, CF>;
+        const size_t lds = sizeof(R) * (FINE ? 3 : 2) * T::NS;
+        tlaunch(c, timed, bytes, k_tsweep2<FINE, R, CF>, grid, dim3(CF::THREADS), lds, vv, coef, (const double*)c->sc,
+                xcur, xnext, b);
+    } else if (CAND::NSW >= 2 && nsw == 2) {
+        const size_t lds = sizeof(R) * (FINE ? 5 : 6) * Tile<2, 8, CF>::NS;
+        tlaunch(c, timed, bytes, k_tsweepN<FINE, R, CF, 2>, grid, dim3(CF::THREADS), lds, vv, coef,
+                (const double*)c->sc, xcur, xnext, b);
+    } else {
+        const size_t lds = sizeof(R) * (FINE ? 5 : 6) * Tile<2, 4, CF>::NS;
+        tlaunch(c, timed, bytes, k_tsweepN<FINE, R, CF, 1>, grid, dim3(CF::THREADS), lds, vv, coef,
+                (const double*)c->sc, xcur, xnext, b);
+    }
 }
 
 template <bool FINE, typename R, size_t... I>
 static void tsweep2_pick(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b,
-                         int k, std::index_sequence<I...>)
+                         int k, int nsw, std::index_sequence<I...>)
 {
-    ((k == (int)I ? tsweep2_impl<FINE, R, std::tuple_element_t<I, Sweep2Tiles>>(c, L, v, coef, xcur, xnext, b)
+    ((k == (int)I ? tsweep2_impl<FINE, R, std::tuple_element_t<I, Sweep2Cands>>(c, L, v, coef, xcur, xnext, b, nsw)
                   : void()),
      ...);
 }
 
 template <typename R>
 void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b,
-                    int tile)
+                    int tile, int nsw)
 {
-    const int k = tile >= 0 && tile < kSweep2Tiles ? tile : 0;
-    if (fine) tsweep2_pick<true, R>(c, L, v, coef, xcur, xnext, b, k, std::make_index_sequence<kSweep2Tiles>{});
-    else tsweep2_pick<false, R>(c, L, v, coef, xcur, xnext, b, k, std::make_index_sequence<kSweep2Tiles>{});
+    const int k = tile >= 0 && tile < kSweep2Cands ? tile : 0;
+    constexpr auto seq = std::make_index_sequence<kSweep2Cands>{};
+    if (fine) tsweep2_pick<true, R>(c, L, v, coef, xcur, xnext, b, k, nsw, seq);
+    else tsweep2_pick<false, R>(c, L, v, coef, xcur, xnext, b, k, nsw, seq);
 }
 
-void sweep2_tile(int k, int* tx, int* ty)
+template <size_t... I>
+static SweepShape sweep2_shape_of(int k, std::index_sequence<I...>)
 {
-    const int txs[kSweep2Tiles] = {std::tuple_element_t<0, Sweep2Tiles>::TX, std::tuple_element_t<1, Sweep2Tiles>::TX,
-                                   std::tuple_element_t<2, Sweep2Tiles>::TX};
-    const int tys[kSweep2Tiles] = {std::tuple_element_t<0, Sweep2Tiles>::TY, std::tuple_element_t<1, Sweep2Tiles>::TY,
-                                   std::tuple_element_t<2, Sweep2Tiles>::TY};
-    *tx = txs[k];
-    *ty = tys[k];
+    SweepShape out{};
+    ((k == (int)I ? (void)(out = SweepShape{std::tuple_element_t<I, Sweep2Cands>::CF::TX,
+                                            std::tuple_element_t<I, Sweep2Cands>::CF::TY,
+                                            std::tuple_element_t<I, Sweep2Cands>::CF::THREADS,
+                                            std::tuple_element_t<I, Sweep2Cands>::NSW})
+                  : void()),
+     ...);
+    return out;
 }
+
+SweepShape sweep2_shape(int k) { return sweep2_shape_of(k, std::make_index_sequence<kSweep2Cands>{}); }
+
+// the staged sweeps may use more dynamic LDS than the default limit
+template <class CAND, typename R>
+static void allow_staged(size_t bytes)
+{
+    if constexpr (CAND::STAGED) {
+        using CF = typename CAND::CF;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, 1>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, 1>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if constexpr (CAND::NSW >= 2) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, 2>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, 2>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        }
+    }
+}
+
+template <size_t... I>
+static void allow_all(size_t bytes, std::index_sequence<I...>)
+{
+    (allow_staged<std::tuple_element_t<I, Sweep2Cands>, double>(bytes), ...);
+    (allow_staged<std::tuple_element_t<I, Sweep2Cands>, float>(bytes), ...);
+}
+
+void sweep2_allow_lds(size_t bytes) { allow_all(bytes, std::make_index_sequence<kSweep2Cands>{}); }
+
+// dynamic LDS bytes of candidate k running nsw sweeps per launch (FP64,
+// coarse level: the larger case)
+template <size_t... I>
+static size_t sweep2_lds_of(int k, int nsw, std::index_sequence<I...>)
+{
+    size_t out = 0;
+    ((k == (int)I ? (void)(out = std::tuple_element_t<I, Sweep2Cands>::STAGED
+                                     ? sizeof(double) * 6 *
+                                           (nsw == 2 ? Tile<2, 8, typename std::tuple_element_t<I, Sweep2Cands>::CF>::NS
+                                                     : Tile<2, 4, typename std::tuple_element_t<I, Sweep2Cands>::CF>::NS)
+                                     : sizeof(double) * 3 *
+                                           Tile<2, 4, typename std::tuple_element_t<I, Sweep2Cands>::CF>::NS)
+                  : void()),
+     ...);
+    return out;
+}
+
+size_t sweep2_lds(int k, int nsw) { return sweep2_lds_of(k, nsw, std::make_index_sequence<kSweep2Cands>{}); }
 
 template <typename R>
 void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b)
@@ -984,7 +1225,7 @@ void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next
 #define HB_TILE_INST(R)                                                                                             \
     template void launch_tsmooth<R>(Ctx*, const Level&, const BV&, const R*, bool, int, const R*, R*, const R*);     \
     template void launch_trb3<R>(Ctx*, const Level&, const BV&, const R*, bool, int, int, R*, const R*);             \
-    template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*, int);     \
+    template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*, int, int);     \
     template void launch_mac_sweep<R>(Ctx*, const Level&, const BV&, const R*, R*, const R*);                        \
     template void launch_tresid_restr<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, bool, \
                                          const R*, const R*, R*, R*);

@@ -101,7 +101,7 @@ def load():
     L.hb_nn_train_step.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_float, P(C.c_double)]
     L.hb_set_warm_start.argtypes = [vp, C.c_int, vp]
     L.hb_warm_start_uses.argtypes = [vp]
-    L.hb_tile_config.argtypes = [vp, C.c_int, C.c_int, P(C.c_int), P(C.c_int)]
+    L.hb_tile_config.argtypes = [vp, C.c_int, C.c_int, P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_int)]
     L.hb_capture.argtypes = [vp, C.c_int, C.c_int]
     L.hb_capture_read.argtypes = [vp, C.c_int, vp, vp]
     L.hb_kernel_timing.argtypes = [vp, C.c_int]
@@ -303,11 +303,12 @@ class Context:
         return load().hb_warm_start_uses(self._h)
 
     def tile_config(self, op, level):
-        """(tx, ty) tile the autotuner chose for the fused sweep of problem op
-        on `level`, or None where no fused sweep runs"""
-        tx, ty = C.c_int(), C.c_int()
-        rc = load().hb_tile_config(self._h, op, level, C.byref(tx), C.byref(ty))
-        return (tx.value, ty.value) if rc == OK else None
+        """(tx, ty, threads, sweeps_per_launch) of the candidate the
+        autotuner chose for the fused sweep of problem op on `level`, or None
+        where no fused sweep runs"""
+        tx, ty, th, sw = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        rc = load().hb_tile_config(self._h, op, level, C.byref(tx), C.byref(ty), C.byref(th), C.byref(sw))
+        return (tx.value, ty.value, th.value, sw.value) if rc == OK else None
 
     def capture(self, enable):
         self._check(load().hb_capture(self._h, OP_NODAL, int(enable)))
@@ -369,11 +370,12 @@ class BatchContext:
         return load().hb_batch_size(self._h)
 
     def tile_config(self, op, level):
-        """(tx, ty) tile the autotuner chose for the fused sweep of problem op
-        on `level`, or None where no fused sweep runs"""
-        tx, ty = C.c_int(), C.c_int()
-        rc = load().hb_tile_config(self._h, op, level, C.byref(tx), C.byref(ty))
-        return (tx.value, ty.value) if rc == OK else None
+        """(tx, ty, threads, sweeps_per_launch) of the candidate the
+        autotuner chose for the fused sweep of problem op on `level`, or None
+        where no fused sweep runs"""
+        tx, ty, th, sw = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        rc = load().hb_tile_config(self._h, op, level, C.byref(tx), C.byref(ty), C.byref(th), C.byref(sw))
+        return (tx.value, ty.value, th.value, sw.value) if rc == OK else None
 
     def step(self, us, ps, dts=None, report=True, allow=()):
         """One step of every cavity; us[b], ps[b] GPU float64 tensors (in

@@ -3,7 +3,8 @@ replace: the single-workgroup coarse V-cycle (every level below a size limit
 in one launch, data in LDS; HB_TAIL=0 turns it off), the fused sweeps (all
 colours, or in 2D both tensor components, of a sweep in one launch;
 HB_FUSE=0), and each candidate tile of the autotuned sweeps (HB_TILE=k
-forces candidate k).
+forces candidate k; in 2D, candidates 3.. of the tensor sweep stage
+everything in LDS and run two sweeps per launch where the level allows it).
 
 Each runs the same arithmetic per cell or node in the same order (the same
 Gauss-Seidel ordering, residual, restriction, prolongation and FP64
@@ -43,7 +44,11 @@ def _say(*a):
 
 
 PLAIN = {"tail": {"HB_TAIL": "0"}, "fuse": {"HB_FUSE": "0"}, "both": {"HB_TAIL": "0", "HB_FUSE": "0"},
-         "tile1": {"HB_TILE": "1"}, "tile2": {"HB_TILE": "2"}}
+         "tile1": {"HB_TILE": "1"}, "tile2": {"HB_TILE": "2"},
+         # staged tensor sweeps, two per launch where the level allows it,
+         # on every level with the coarse tail off
+         "tile3": {"HB_TILE": "3"}, "tile4_notail": {"HB_TILE": "4", "HB_TAIL": "0"},
+         "tile5_notail": {"HB_TILE": "5", "HB_TAIL": "0"}}
 
 
 def _context(make, env):
@@ -130,7 +135,9 @@ def test_autotuner_reports_candidate_tiles():
     s = CASES["lid2d_96x48"]()
     g, fl = hip_objs(s)
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {})
-    cand = {"visc": {(64, 8), (32, 16), (128, 4)}, "nodal": {(64, 16), (128, 8), (32, 32)}}
+    cand = {"visc": {(64, 8, 256, 1), (32, 16, 256, 1), (128, 4, 256, 1), (32, 16, 512, 1), (32, 16, 512, 2),
+                     (64, 16, 512, 1), (64, 16, 512, 2), (32, 16, 1024, 1), (32, 16, 1024, 2)},
+            "nodal": {(64, 16, 256, 1), (128, 8, 256, 1), (32, 32, 256, 1)}}
     tv = [ctx.tile_config(hb.OP_VISC, l) for l in range(8)]
     tn = [ctx.tile_config(hb.OP_NODAL, l) for l in range(8)]
     _say("  tensor", tv, "nodal", tn)
@@ -140,5 +147,16 @@ def test_autotuner_reports_candidate_tiles():
     assert ctx.tile_config(hb.OP_MAC, 0) is None
     ctx.close()
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "2"})
-    assert ctx.tile_config(hb.OP_VISC, 0) == (128, 4) and ctx.tile_config(hb.OP_NODAL, 0) == (32, 32)
+    assert ctx.tile_config(hb.OP_VISC, 0) == (128, 4, 256, 1) and ctx.tile_config(hb.OP_NODAL, 0) == (32, 32, 256, 1)
+    ctx.close()
+    # walls only: the staged candidate runs two sweeps per launch
+    ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "4"})
+    assert ctx.tile_config(hb.OP_VISC, 0) == (64, 16, 512, 2) and ctx.tile_config(hb.OP_NODAL, 0) == (128, 8, 256, 1)
+    ctx.close()
+    # a periodic extent below 8 allows one sweep per launch only
+    s = CASES["chan2d_8x32"]()
+    g, fl = hip_objs(s)
+    ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "3", "HB_TAIL": "0"})
+    assert ctx.tile_config(hb.OP_VISC, 0) == (32, 16, 512, 2)
+    assert ctx.tile_config(hb.OP_VISC, 1) == (32, 16, 512, 1)
     ctx.close()
