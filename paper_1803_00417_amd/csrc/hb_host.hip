@@ -179,7 +179,7 @@ static int build_mg(Ctx* c, MG& m, int op)
     // single-workgroup coarse tail: the first level from which every
     // cavity's remaining levels fit the LDS budget
     m.tail_lt = -1;
-    if ((op == HB_OP_VISC || op == HB_OP_MAC) && c->tail && c->lds_budget > 0) {
+    if (c->tail && c->lds_budget > 0) {
         for (int l = 1; l < m.nlev && m.tail_lt < 0; ++l) {
             if (m.nlev - l > kMaxTail) continue;
             size_t need[2] = {0, 0};
@@ -461,7 +461,8 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
     }
     if (l == m.tail_lt) {
         if (m.op == HB_OP_VISC) launch_visc_tail<R>(c, m, l, nu1, nu2, m.tail_lds[prec_index<R>()], c->act);
-        else launch_mac_tail<R>(c, m, l, nu1, nu2, m.tail_lds[prec_index<R>()], c->act);
+        else if (m.op == HB_OP_MAC) launch_mac_tail<R>(c, m, l, nu1, nu2, m.tail_lds[prec_index<R>()], c->act);
+        else launch_nodal_tail<R>(c, m, l, nu1, nu2, m.tail_lds[prec_index<R>()], c->act);
         return;
     }
     if (L.any_sm) {

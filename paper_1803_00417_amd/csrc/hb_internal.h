@@ -421,6 +421,8 @@ template <typename R>
 void launch_visc_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, const int* act);
 template <typename R>
 void launch_mac_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, const int* act);
+template <typename R>
+void launch_nodal_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, const int* act);
 void tail_allow_lds(size_t bytes);
 
 // ---- learned warm start (hb_nn.hip, hb_ws.hip) --------------------------------

@@ -31,32 +31,6 @@ struct NTile {
     __device__ static inline int at(int lx, int ly, int lz) { return (lz * SY + ly) * SX + lx; }
 };
 
-// K x at node G from an LDS node block with y stride sx and z stride sxy
-// (local index l), and the diagonal
-template <int DIM, typename R>
-__device__ inline R block_K(const GridD& g, const R* s, int sx, int sxy, const int G[3], int l, R* diag)
-{
-    int cnt[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) cnt[a][d] = a < DIM ? node_cnt(g, a, G[a], d - 1) : (d == 1 ? 1 : 0);
-    R acc = 0;
-#pragma unroll
-    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int k = (dx != 0) + (dy != 0) + (dz != 0);
-                if (DIM == 3 && k == 1) continue;   // the 3D Q1 face-neighbour weight is exactly 0
-                const R w = (R)(q1_ke(DIM, g.h, k) * (double)(cnt[0][dx + 1] * cnt[1][dy + 1] * cnt[2][dz + 1]));
-                acc += w * s[l + dz * sxy + dy * sx + dx];
-            }
-    if (diag) *diag = (R)(q1_ke(DIM, g.h, 0) * (double)(cnt[0][1] * cnt[1][1] * cnt[2][1]));
-    return acc;
-}
-
 // the same on an NTile
 template <int DIM, typename R>
 __device__ inline R tile_K(const GridD& g, const R* s, const int G[3], int l, R* diag)

@@ -1,7 +1,8 @@
 // hb_ops.h -- pointwise device operators of the global-memory kernels: the
 // tensor viscous flux and divergence, the MAC Laplacian and the assembled Q1
 // stiffness, all reading global memory with boundary values produced on the
-// fly.
+// fly; and the Q1 stiffness on a staged node block (the tiled and the
+// single-workgroup nodal kernels).
 #pragma once
 #include "hb_internal.h"
 
@@ -135,6 +136,32 @@ __device__ inline int node_cnt(const GridD& g, int a, int i, int d)
     if (g.per[a]) return d == 0 ? 2 : 1;
     const int lo = i >= 1, hi = i <= g.n[a] - 1;
     return d == 0 ? lo + hi : (d > 0 ? hi : lo);
+}
+
+// K x at node G from an LDS node block with y stride sx and z stride sxy
+// (local index l), and the diagonal
+template <int DIM, typename R>
+__device__ inline R block_K(const GridD& g, const R* s, int sx, int sxy, const int G[3], int l, R* diag)
+{
+    int cnt[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cnt[a][d] = a < DIM ? node_cnt(g, a, G[a], d - 1) : (d == 1 ? 1 : 0);
+    R acc = 0;
+#pragma unroll
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int k = (dx != 0) + (dy != 0) + (dz != 0);
+                if (DIM == 3 && k == 1) continue;   // the 3D Q1 face-neighbour weight is exactly 0
+                const R w = (R)(q1_ke(DIM, g.h, k) * (double)(cnt[0][dx + 1] * cnt[1][dy + 1] * cnt[2][dz + 1]));
+                acc += w * s[l + dz * sxy + dy * sx + dx];
+            }
+    if (diag) *diag = (R)(q1_ke(DIM, g.h, 0) * (double)(cnt[0][1] * cnt[1][1] * cnt[2][1]));
+    return acc;
 }
 
 // value of x at node (i,j,k) (periodic wrap; outside a wall reads 0: its

@@ -5,10 +5,12 @@
 // levels from `lt` down to the cavity's coarsest and back up, with every
 // level's iterate (plus a 1-cell halo), right-hand side and coefficients
 // resident in LDS and barriers in place of launches.  The arithmetic per
-// cell is the one of the per-level kernels (same stencil functions, same
-// summation orders): red-black Gauss-Seidel component by component, residual
-// restricted by the mean of the 2^d children, the coarsest system solved by
-// its FP64 inverse, (bi/tri)linear prolongation.  The coarse iterate at `lt`
+// cell or node is the one of the per-level kernels (same stencil functions,
+// same summation orders).  Cell problems (tensor viscous, MAC): red-black
+// Gauss-Seidel component by component, residual restricted by the mean of
+// the 2^d children, the coarsest system solved by its FP64 inverse,
+// (bi/tri)linear prolongation.  Nodal problem: 2^d-colour Gauss-Seidel,
+// full-weighting restriction, nodal interpolation, FP64 coarsest solve.  The coarse iterate at `lt`
 // starts from zero (the restriction above zeroes it); the result is written
 // to the level's current buffer.
 //
@@ -19,6 +21,7 @@
 // halo pass is needed: on smoothing levels every extent is even, and the
 // image of a cell of one colour is read only by cells of the other colour.
 #include "hb_internal.h"
+#include "hb_ops.h"
 #include "hb_stencil.h"
 
 #include <cstdint>
@@ -606,14 +609,231 @@ __global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Nodal problem (Q1 stiffness K, natural boundary on walls).  Each level's
+// nodes sit in a block with a 1-node halo that holds the periodic images;
+// halo positions beyond a wall stay zero (their stencil weights are zero,
+// as in the tiled kernels, which read zeros there).  A sweep runs the 2^d
+// colours (i&1) + 2(j&1) + 4(k&1) in order, as the per-level sweeps; the
+// residual is stored for the full-weighting restriction; prolongation is the
+// (bi/tri)linear interpolation; the coarsest system is solved by its FP64
+// inverse.  Same per-node arithmetic and summation order as the per-level
+// kernels.  The first level holds at most 2^d * kNodalTailThreads *
+// kNodalTailKN nodes: one CU runs the whole tail, and on a larger level a
+// colour pass costs it more than the level's own launches cost the chip.
+// ---------------------------------------------------------------------------
+constexpr int kNodalTailThreads = 1024;
+constexpr int kNodalTailKN = 1;
+
+// the level's node lattice as a grid of "cells" (node counts per axis), for
+// the LDS layout and the periodic images
+__device__ inline GridD node_grid(const GridD& g)
+{
+    GridD q = g;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q.n[a] = nnode(g, a);
+    return q;
+}
+
+__device__ inline void node_of(const GridD& gn, int t, int G[3])
+{
+    G[0] = t % gn.n[0];
+    G[1] = (t / gn.n[0]) % gn.n[1];
+    G[2] = t / (gn.n[0] * gn.n[1]);
+}
+
+template <int DIM, typename R>
+__global__ void __launch_bounds__(kNodalTailThreads) k_nodal_tail(TailArgs A)
+{
+    constexpr int TH = kNodalTailThreads;
+    const int cav = blockIdx.x, tid = threadIdx.x;
+    if (A.act && !A.act[cav]) return;
+    const TailPlan* __restrict__ P = A.plan + cav;
+    const int nl = P->nl;
+    if (nl <= 0) return;
+    R* lds = reinterpret_cast<R*>(tail_lds);
+    for (int i = 0; i < nl; ++i) {
+        const TailLevel& T = P->lv[i];
+        R* X = lds + T.xoff;
+        for (int t = tid; t < T.ns; t += TH) X[t] = R(0);
+    }
+    {
+        const TailLevel& T = P->lv[0];
+        const R* gb = reinterpret_cast<const R*>(A.b) + P->o0;
+        R* B = lds + T.boff;
+        for (int t = tid; t < T.nc; t += TH) B[t] = gb[t];
+    }
+    __syncthreads();
+
+    // Gauss-Seidel sweeps of level i: the nodes of one colour share no
+    // element, and a node's periodic image is read only by nodes of other
+    // colours (periodic node counts are even on smoothing levels)
+    auto smooth = [&](int i, int sweeps) {
+        const GridD g = tail_grid<DIM>(P, i);
+        const GridD gn = node_grid(g);
+        const TailLay L = tail_lay(gn);
+        const TailLevel& T = P->lv[i];
+        R* X = lds + T.xoff;
+        const R* B = lds + T.boff;
+        for (int s = 0; s < sweeps; ++s)
+            for (int colour = 0; colour < (1 << DIM); ++colour) {
+                int par[3], cn[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    par[a] = a < DIM ? (colour >> a) & 1 : 0;
+                    cn[a] = a < DIM ? (gn.n[a] + 1 - par[a]) / 2 : 1;
+                }
+                const int cnt = cn[0] * cn[1] * cn[2];
+                for (int t = tid; t < cnt; t += TH) {
+                    const int G[3] = {2 * (t % cn[0]) + par[0], 2 * ((t / cn[0]) % cn[1]) + par[1],
+                                      DIM == 3 ? 2 * (t / (cn[0] * cn[1])) + par[2] : 0};
+                    const int l = L.at(G[0], G[1], G[2]);
+                    R dg;
+                    const R Kx = block_K<DIM, R>(g, X, L.sx, L.sxy, G, l, &dg);
+                    put_cell<DIM, R>(gn, L, X, G, X[l] + (B[nid(g, G[0], G[1], G[2])] - Kx) / dg, false);
+                }
+                __syncthreads();
+            }
+    };
+
+    // descend: smooth, residual, full-weighting restriction (the coarse
+    // iterate stays zero)
+    for (int i = 0; i + 1 < nl; ++i) {
+        smooth(i, A.nu1);
+        const GridD g = tail_grid<DIM>(P, i);
+        const GridD gn = node_grid(g);
+        const TailLay L = tail_lay(gn);
+        const TailLevel& T = P->lv[i];
+        const R* X = lds + T.xoff;
+        const R* B = lds + T.boff;
+        R* Rr = lds + P->roff;
+        for (int t = tid; t < T.nc; t += TH) {
+            int G[3];
+            node_of(gn, t, G);
+            const R Kx = block_K<DIM, R>(g, X, L.sx, L.sxy, G, L.at(G[0], G[1], G[2]), nullptr);
+            Rr[t] = B[t] - Kx;
+        }
+        __syncthreads();
+        const GridD gcn = node_grid(tail_grid<DIM>(P, i + 1));
+        const TailLevel& Tc = P->lv[i + 1];
+        R* Bc = lds + Tc.boff;
+        constexpr int nt = DIM == 3 ? 27 : 9;
+        for (int t = tid; t < Tc.nc; t += TH) {
+            int I[3];
+            node_of(gcn, t, I);
+            R s = 0;
+#pragma unroll
+            for (int u = 0; u < nt; ++u) {
+                int tt = u, p[3] = {0, 0, 0};
+                bool ok = true;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const int del = tt % 3 - 1;
+                    tt /= 3;
+                    int F = 2 * I[a] + del;
+                    const int nf = gn.n[a];
+                    if (F < 0 || F >= nf) {
+                        if (g.per[a]) F = F < 0 ? F + nf : F - nf;
+                        else { ok = false; F = 0; }
+                    }
+                    p[a] = F;
+                }
+                tt = u;
+                R w = 1;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    if (tt % 3 != 1) w *= R(0.5);
+                    tt /= 3;
+                }
+                const R val = Rr[nid(g, p[0], p[1], p[2])];
+                s = ok ? s + w * val : s;
+            }
+            Bc[t] = s;
+        }
+        __syncthreads();
+    }
+
+    // coarsest: x = A^{-1} b, accumulated in FP64
+    {
+        const int i = nl - 1;
+        const CoarseD cd = A.cs[cav];
+        const GridD gn = node_grid(tail_grid<DIM>(P, i));
+        const TailLay L = tail_lay(gn);
+        const R* B = lds + P->lv[i].boff;
+        R* X = lds + P->lv[i].xoff;
+        for (int r = tid; r < cd.N; r += TH) {
+            const double* row = A.Ainv + cd.aoff + (long)r * cd.N;
+            double s = 0.0;
+            for (int jj = 0; jj < cd.N; ++jj) s += row[jj] * (double)B[jj];
+            int G[3];
+            node_of(gn, r, G);
+            put_cell<DIM, R>(gn, L, X, G, (R)s, false);
+        }
+        __syncthreads();
+    }
+
+    // ascend: x_f += P e_c (a fine node takes the mean of the coarse nodes
+    // of its coarse edge, face or cell), then smoothing
+    for (int i = nl - 2; i >= 0; --i) {
+        const GridD gc = tail_grid<DIM>(P, i + 1);
+        const GridD gfn = node_grid(tail_grid<DIM>(P, i)), gcn = node_grid(gc);
+        const TailLay Lf = tail_lay(gfn), Lc = tail_lay(gcn);
+        R* X = lds + P->lv[i].xoff;
+        const R* E = lds + P->lv[i + 1].xoff;
+        for (int t = tid; t < P->lv[i].nc; t += TH) {
+            int F[3];
+            node_of(gfn, t, F);
+            R s = 0;
+#pragma unroll
+            for (int bits = 0; bits < (1 << DIM); ++bits) {
+                int p[3] = {0, 0, 0};
+                R w = 1;
+                bool ok = true;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const int hi = (bits >> a) & 1;
+                    if (!(F[a] & 1)) {
+                        if (hi) ok = false;
+                        p[a] = F[a] >> 1;
+                    } else {
+                        w *= R(0.5);
+                        int C = ((F[a] - 1) >> 1) + hi;
+                        if (gc.per[a] && C == gcn.n[a]) C = 0;
+                        p[a] = C;
+                    }
+                }
+                const R val = E[Lc.at(p[0], p[1], p[2])];
+                s = ok ? s + w * val : s;
+            }
+            const int l = Lf.at(F[0], F[1], F[2]);
+            put_cell<DIM, R>(gfn, Lf, X, F, X[l] + s, false);
+        }
+        __syncthreads();
+        smooth(i, A.nu2);
+    }
+
+    // result of level lt
+    {
+        const GridD gn = node_grid(tail_grid<DIM>(P, 0));
+        const TailLay L = tail_lay(gn);
+        const R* X = lds + P->lv[0].xoff;
+        R* gx = reinterpret_cast<R*>(A.x) + P->o0;
+        for (int t = tid; t < P->lv[0].nc; t += TH) {
+            int G[3];
+            node_of(gn, t, G);
+            gx[t] = X[L.at(G[0], G[1], G[2])];
+        }
+    }
+}
+
 // Tail plan of one cavity from its levels lt..lc for problem op (grids gl,
 // face offsets in the level arenas gofs (tensor problem), component-array
 // offset o0 at lt): the LDS layout (per level the iterate with its halo, the
 // right-hand side and, tensor problem, the face viscosities; then, tensor
-// problem, one residual array of the first level).  Returns the LDS bytes
-// for storage size elem, or SIZE_MAX when the first level has more cells
-// per colour than the kernel's threads cover (tensor: one per thread, MAC:
-// kMacTailKC per thread).
+// and nodal problems, one residual array of the first level).  Returns the
+// LDS bytes for storage size elem, or SIZE_MAX when the first level has
+// more unknowns per colour than the kernel's threads cover (tensor: one cell
+// per thread, MAC: kMacTailKC, nodal: kNodalTailKN nodes).
 size_t tail_plan(int op, const std::vector<GridD>& gl, const std::vector<long>& gofs, long o0, size_t elem,
                  TailPlan* out)
 {
@@ -622,11 +842,15 @@ size_t tail_plan(int op, const std::vector<GridD>& gl, const std::vector<long>& 
         if (out) *out = P;
         return 0;
     }
-    const bool visc = op == HB_OP_VISC;
-    const long per_thread = visc ? 1 : kMacTailKC;
-    if (gl.size() > (size_t)kMaxTail || (gl.size() > 1 && ncells(gl[0]) > 2L * kTailThreads * per_thread))
-        return SIZE_MAX;
+    const bool visc = op == HB_OP_VISC, nodal = op == HB_OP_NODAL;
     const int d = gl[0].dim;
+    // unknowns per level: cells, or nodes (node counts per axis nn)
+    auto count = [&](const GridD& g) {
+        return nodal ? (long)nnode(g, 0) * nnode(g, 1) * nnode(g, 2) : ncells(g);
+    };
+    const long limit = nodal ? (1L << d) * kNodalTailThreads * kNodalTailKN
+                             : 2L * kTailThreads * (visc ? 1 : kMacTailKC);
+    if (gl.size() > (size_t)kMaxTail || (gl.size() > 1 && count(gl[0]) > limit)) return SIZE_MAX;
     const int nc = visc ? d : 1;
     long o = 0;
     for (size_t i = 0; i < gl.size(); ++i) {
@@ -637,8 +861,9 @@ size_t tail_plan(int op, const std::vector<GridD>& gl, const std::vector<long>& 
             T.per[a] = g.per[a];
         }
         T.h = g.h;
-        T.nc = (int)ncells(g);
-        T.ns = (g.n[0] + 2) * (g.n[1] + 2) * (d == 3 ? g.n[2] + 2 : 1);
+        T.nc = (int)count(g);
+        const int e[3] = {nodal ? nnode(g, 0) : g.n[0], nodal ? nnode(g, 1) : g.n[1], nodal ? nnode(g, 2) : g.n[2]};
+        T.ns = (e[0] + 2) * (e[1] + 2) * (d == 3 ? e[2] + 2 : 1);
         long nf = 0;
         if (visc)
             for (int a = 0; a < d; ++a) nf += fcount(g, a);
@@ -653,6 +878,7 @@ size_t tail_plan(int op, const std::vector<GridD>& gl, const std::vector<long>& 
     }
     P.roff = (int)o;
     if (visc) o += (long)d * P.lv[0].nc;
+    if (nodal && gl.size() > 1) o += P.lv[0].nc;
     P.nl = (int)gl.size();
     P.o0 = o0;
     if (out) *out = P;
@@ -674,6 +900,23 @@ void launch_mac_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, 
     A.scb = c->sc;
     if (c->dim == 2) k_mac_tail<2, R, kMacTailKC><<<c->nb, kTailThreads, lds, c->s>>>(A);
     else k_mac_tail<3, R, kMacTailKC><<<c->nb, kTailThreads, lds, c->s>>>(A);
+}
+
+template <typename R>
+void launch_nodal_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, const int* act)
+{
+    TailArgs A{};
+    A.nu1 = nu1;
+    A.nu2 = nu2;
+    A.plan = m.tplan;
+    A.x = LB<R>::x(m.L[lt]);
+    A.b = LB<R>::b(m.L[lt]);
+    A.cs = m.cs;
+    A.Ainv = m.Ainv;
+    A.act = act;
+    A.scb = c->sc;
+    if (c->dim == 2) k_nodal_tail<2, R><<<c->nb, kNodalTailThreads, lds, c->s>>>(A);
+    else k_nodal_tail<3, R><<<c->nb, kNodalTailThreads, lds, c->s>>>(A);
 }
 
 template <typename R>
@@ -705,6 +948,14 @@ void tail_allow_lds(size_t bytes)
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<3, float, kMacTailKC>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nodal_tail<2, double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nodal_tail<3, double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nodal_tail<2, float>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nodal_tail<3, float>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visc_tail<2, double>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_visc_tail<3, double>),
@@ -718,6 +969,8 @@ void tail_allow_lds(size_t bytes)
 template void launch_visc_tail<double>(Ctx*, const MG&, int, int, int, size_t, const int*);
 template void launch_visc_tail<float>(Ctx*, const MG&, int, int, int, size_t, const int*);
 template void launch_mac_tail<double>(Ctx*, const MG&, int, int, int, size_t, const int*);
+template void launch_nodal_tail<double>(Ctx*, const MG&, int, int, int, size_t, const int*);
+template void launch_nodal_tail<float>(Ctx*, const MG&, int, int, int, size_t, const int*);
 template void launch_mac_tail<float>(Ctx*, const MG&, int, int, int, size_t, const int*);
 
 }  // namespace hb
