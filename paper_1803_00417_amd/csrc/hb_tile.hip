@@ -292,13 +292,16 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     // red cells of the tile and its 1-cell ring, then black cells of the
     // tile; a cell of one colour reads only the other colour of component c
     // (face neighbours) and the other components, so each colour is updated
-    // in place.  Every slot is evaluated (idle slots on an in-range cell) and
-    // only real cells are stored, so a phase is straight-line code whose LDS
-    // reads issue together.
+    // in place.  Every slot within the colour's region is evaluated (region
+    // positions beyond the box on an in-range cell) and only real cells are
+    // stored, so a phase is straight-line code whose LDS reads issue
+    // together; slots past the region (whole waves, but for one) skip it.
+    constexpr int NR = (T::TX + 2) / 2 * (T::TY + 2) * RZ1, NB = T::TX / 2 * T::TY * T::TZ;
     {
         R nv[KR];
 #pragma unroll
         for (int u = 0; u < KR; ++u) {
+            if (threadIdx.x + u * TH >= NR) continue;
             R dg;
             const R vd =
                 tile_visc_div<DIM, 2, FINE, R>(g, rF[u], s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
@@ -315,6 +318,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
         R nv[KB];
 #pragma unroll
         for (int u = 0; u < KB; ++u) {
+            if (threadIdx.x + u * TH >= NB) continue;
             R dg;
             const R vd =
                 tile_visc_div<DIM, 2, FINE, R>(g, kF[u], s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
