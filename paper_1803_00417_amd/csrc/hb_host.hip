@@ -363,8 +363,11 @@ static BV paired(BV v, const Level& P)
     return v;
 }
 
+// Smoothing sweeps on level l.  C (optional): the coarse level whose
+// correction the first sweep adds to the iterate first (2D tensor problem
+// with fused sweeps and a staged candidate).
 template <typename R>
-static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair)
+static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C = nullptr)
 {
     using B = LB<R>;
     Level& L = m.L[l];
@@ -374,7 +377,11 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair)
             // both components of the sweep in one launch; with `pair`, two
             // sweeps per launch where the level's candidate runs them so
             const int n = (pair && L.sweeps == 2 && sweeps - s >= 2) ? 2 : 1;
-            launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n);
+            if (s == 0 && C)
+                launch_tsweep2<R>(c, L, paired(v, *C), tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n,
+                                  B::x(*C), C->gall, C->o);
+            else
+                launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n);
             L.cur ^= 1;
             s += n - 1;
         } else if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0)) {
@@ -484,9 +491,13 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
             launch_nodal_restrict<R>(c, C, vc, L.gall, L.o, B::r(L), B::b(C), B::x(C));
         }
         vcycle<R>(c, m, l + 1, nu1, nu2);
+        // 2D tensor problem with a staged smoother: the prolongation is
+        // folded into the first post-smoothing launch
+        const bool fold = m.op == HB_OP_VISC && c->dim == 2 && c->fuse && nu2 > 0 && sweep2_shape(L.tile).staged;
         if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L, vpc, C.gall, C.o, B::x(C), B::x(L));
-        else launch_prolong_cells<R>(c, L, vpc, C.gall, C.o, m.ncomp, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
-        smooth<R>(c, m, l, nu2, pair);
+        else if (!fold)
+            launch_prolong_cells<R>(c, L, vpc, C.gall, C.o, m.ncomp, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
+        smooth<R>(c, m, l, nu2, pair, fold ? &C : nullptr);
     }
     if (L.any_cs) launch_coarse_solve<R>(c, m, l, c->act, B::b(L), B::x(L));
 }
@@ -1186,8 +1197,14 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
         return give_up(HB_ERR_DEVICE, "stream or event creation failed");
+    // the slot mirror and its publication word are coherent pinned memory
+    // the device writes directly (fetch_slots)
+    const unsigned pin = hipHostMallocMapped | hipHostMallocCoherent;
     bool ok = dalloc(&c->sc, (long)S_NSLOT * count) == hipSuccess &&
-              hipHostMalloc((void**)&c->hsc, sizeof(double) * S_NSLOT * count) == hipSuccess &&
+              hipHostMalloc((void**)&c->hsc, sizeof(double) * S_NSLOT * count, pin) == hipSuccess &&
+              hipHostMalloc((void**)&c->hseq, sizeof(unsigned long long), pin) == hipSuccess &&
+              hipHostGetDevicePointer((void**)&c->dhsc, c->hsc, 0) == hipSuccess &&
+              hipHostGetDevicePointer((void**)&c->dhseq, c->hseq, 0) == hipSuccess &&
               dalloc(&c->partial, (long)kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
               dalloc(&c->mpart, (long)kSubMax * count) == hipSuccess &&
               hipMemsetAsync(c->mpart, 0, sizeof(unsigned long long) * kSubMax * count, c->s) == hipSuccess &&
@@ -1197,6 +1214,7 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
               hipHostMalloc((void**)&c->hsel, sizeof(int) * count) == hipSuccess;
     if (!ok) return give_up(HB_ERR_OOM, "device allocation failed");
     memset(c->hsc, 0, sizeof(double) * S_NSLOT * count);
+    *c->hseq = 0;
     c->cv.resize(count);
     for (int b = 0; b < count; ++b) {
         Cav& v = c->cv[b];
@@ -1308,6 +1326,7 @@ static void destroy_ctx(Ctx* c)
     (void)hipFree(c->cap_e);
     (void)hipFree(c->cap_x0);
     if (c->hsc) (void)hipHostFree(c->hsc);
+    if (c->hseq) (void)hipHostFree(c->hseq);
     if (c->hact) (void)hipHostFree(c->hact);
     if (c->hact2) (void)hipHostFree(c->hact2);
     if (c->hsel) (void)hipHostFree(c->hsel);

@@ -260,7 +260,11 @@ struct Ctx {
     double *kr = nullptr, *krh = nullptr, *kp = nullptr, *kv = nullptr, *kph = nullptr, *ks = nullptr,
            *ksh = nullptr, *kt = nullptr;
     double* sc = nullptr;        // device scalar slots, S_NSLOT per cavity
-    double* hsc = nullptr;       // pinned host mirror
+    double* hsc = nullptr;       // pinned host mirror (coherent, device-mapped)
+    unsigned long long* hseq = nullptr;   // pinned word the device sets after publishing the slots
+    double* dhsc = nullptr;               // device addresses of hsc and hseq
+    unsigned long long* dhseq = nullptr;
+    unsigned long long pub = 0;           // last publication number
     double* partial = nullptr;   // reduction partials (kRedBlocks per cavity)
     unsigned long long* mpart = nullptr;   // max-norm partials (kSubMax per cavity, kept zero between uses)
     int* act = nullptr;          // device active flags (nb)
@@ -309,7 +313,7 @@ void launch_max_final(Ctx* c, const int* act, int slot);
 // single-array forms, result into slot of cavity cav
 void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot);
 void set_slot(Ctx* c, int cav, int slot, double v);
-void fetch_slots(Ctx* c);  // copies all slots to c->hsc and synchronises
+void fetch_slots(Ctx* c);  // all slots to c->hsc once the stream's work so far has completed
 void copy(Ctx* c, double* dst, const double* src, long n);
 void fill(Ctx* c, double* dst, double v, long n);
 // segmented forms over the batch (per cavity slot, inactive cavities skipped)
@@ -354,13 +358,18 @@ void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fin
 // sweeps need a candidate whose sweeps may be paired and every periodic
 // extent of the level at least 8.  sweep2_shape gives a candidate's tile,
 // threads and most sweeps per launch, sweep2_lds its dynamic LDS bytes.
+// pe (optional): the coarse iterate of a V-cycle, whose prolongation the
+// launch adds to xcur first (v then also carries the coarse level: gct/oct
+// its grid and offset tables); staged candidates fold it into their fill,
+// the others launch the prolongation kernel before the sweep.
 struct SweepShape {
     int tx, ty, threads, nsw;
+    bool staged;
 };
 constexpr int kSweep2Cands = 6;
 template <typename R>
 void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b,
-                    int tile, int nsw);
+                    int tile, int nsw, const R* pe = nullptr, const GridD* gct = nullptr, const long* oct = nullptr);
 SweepShape sweep2_shape(int tile);
 size_t sweep2_lds(int tile, int nsw);
 void sweep2_allow_lds(size_t bytes);

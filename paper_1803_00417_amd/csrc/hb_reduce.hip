@@ -5,6 +5,8 @@
 // other cavities of the batch; max-norms are order independent.
 #include "hb_internal.h"
 
+#include <chrono>
+
 namespace hb {
 
 static constexpr int kT = 256;
@@ -41,10 +43,37 @@ void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot)
     k_maxabs<<<blocks_for(n, kRedBlocks), kT, 0, c->s>>>(v, n, out);
 }
 
+// Publication of the slots: one block copies them into the coherent pinned
+// mirror, every thread makes its writes visible system-wide, then one
+// release store sets the publication word.  The host spins on that word: it
+// is set once every earlier command of the stream has completed (in-order
+// stream), which is all a synchronisation would give, without the copy
+// command and the wake-up of a blocking wait.
+__global__ void k_publish(const double* __restrict__ sc, double* hsc, int n, unsigned long long* seq,
+                          unsigned long long want)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) hsc[i] = sc[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(seq, want, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 void fetch_slots(Ctx* c)
 {
-    (void)hipMemcpyAsync(c->hsc, c->sc, sizeof(double) * S_NSLOT * c->nb, hipMemcpyDeviceToHost, c->s);
+    const int n = S_NSLOT * c->nb;
+    const unsigned long long want = ++c->pub;
+    k_publish<<<1, kT, 0, c->s>>>(c->sc, c->dhsc, n, c->dhseq, want);
+    // spin for a bounded time, then block on the stream (a long segment of
+    // work); if the word is still not visible, copy the slots the slow way
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned it = 1;; ++it) {
+        if (__atomic_load_n(c->hseq, __ATOMIC_ACQUIRE) == want) return;
+        __builtin_ia32_pause();
+        if ((it & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
+    }
     (void)hipStreamSynchronize(c->s);
+    if (__atomic_load_n(c->hseq, __ATOMIC_ACQUIRE) == want) return;
+    (void)hipMemcpy(c->hsc, c->sc, sizeof(double) * n, hipMemcpyDeviceToHost);
 }
 
 __global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, long n)

@@ -52,9 +52,10 @@ static_assert(std::tuple_size_v<Sweep2Cands> == kSweep2Cands, "candidate count")
 // with `mirror` take the mirrored value itself, as the viscosity tile does);
 // positions outside along two or more wall axes (never used by the stencil)
 // read as 0.  Returns an in-range index always, with valid = false for the
-// zero positions, so the loads of a fill issue without branches around them.
+// zero positions, so the loads of a fill issue without branches around them;
+// src (optional) receives the source cell's coordinates.
 template <int DIM>
-__device__ inline long tile_src(const GridD& g, int i, int j, int k, bool& valid, bool& neg)
+__device__ inline long tile_src(const GridD& g, int i, int j, int k, bool& valid, bool& neg, int* src = nullptr)
 {
     int p[3] = {i, j, k};
     int out = 0;
@@ -79,6 +80,8 @@ __device__ inline long tile_src(const GridD& g, int i, int j, int k, bool& valid
         p[a] = v;
     }
     if (out > 1) valid = false;
+    if (src)
+        for (int a = 0; a < 3; ++a) src[a] = p[a];
     return cid(g, p[0], p[1], p[2]);   // every p[a] is in range
 }
 
@@ -499,9 +502,51 @@ k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
 // LDS arrays of the staged tile, each Tile<2, H, CF>::NS long
 enum { ST_X0 = 0, ST_X1 = 1, ST_B0 = 2, ST_B1 = 3, ST_E = 4, ST_FX = 4, ST_FY = 5 };
 
-template <bool FINE, int H, typename R, class CF>
+// Prolongation correction (P e)_q at fine cell (si, sj) from the coarse
+// iterate e (components Nc apart) on grid gc: the 2^2 nearest coarse cells
+// with axis weights 3/4 and 1/4; a coarse neighbour beyond a wall is the
+// cell itself with the homogeneous ghost sign -1.  Same terms, order and
+// rounding as the prolongation kernel.
+template <typename R>
+__device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si, int sj)
+{
+    const int C[2] = {si >> 1, sj >> 1}, ch[2] = {si & 1, sj & 1};
+    int J[2];
+    R sgn[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        int J2 = C[a] + (ch[a] ? 1 : -1);
+        R sg = 1;
+        if (J2 < 0 || J2 >= gc.n[a]) {
+            if (gc.per[a]) J2 = J2 < 0 ? J2 + gc.n[a] : J2 - gc.n[a];
+            else { J2 = C[a]; sg = R(-1); }
+        }
+        J[a] = J2;
+        sgn[a] = sg;
+    }
+    const R nb[4] = {e[(long)C[1] * gc.n[0] + C[0]], e[(long)C[1] * gc.n[0] + J[0]], e[(long)J[1] * gc.n[0] + C[0]],
+                     e[(long)J[1] * gc.n[0] + J[0]]};
+    R s = 0;
+#pragma unroll
+    for (int bits = 0; bits < 4; ++bits) {
+        R w = 1, sg = 1;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (!((bits >> a) & 1)) { w *= R(0.75); continue; }
+            w *= R(0.25);
+            sg *= sgn[a];
+        }
+        s += w * sg * nb[bits];
+    }
+    return s;
+}
+
+// PRO: x of the fill is x + P e (the coarse correction of a V-cycle folded
+// into the first sweep after it): pe the coarse iterate, gc its grid.
+template <bool FINE, int H, typename R, class CF, bool PRO>
 __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, const R* __restrict__ b,
-                                   const R* __restrict__ coef, R* s, int ox, int oy, long N)
+                                   const R* __restrict__ coef, R* s, int ox, int oy, long N,
+                                   const R* __restrict__ pe, const GridD& gc)
 {
     using T = Tile<2, H, CF>;
     constexpr int TH = CF::THREADS;
@@ -517,8 +562,14 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
         const int lx = tt % T::SX, ly = tt / T::SX;
         const int i = ox - H + lx, j = oy - H + ly;
         bool ok = true, ng = false;
-        const long idx = inner ? cid(g, i, j, 0) : tile_src<2>(g, i, j, 0, ok, ng);
-        const R x0 = x[idx], x1 = x[N + idx];
+        int src[3] = {i, j, 0};
+        const long idx = inner ? cid(g, i, j, 0) : tile_src<2>(g, i, j, 0, ok, ng, src);
+        R x0 = x[idx], x1 = x[N + idx];
+        if (PRO) {
+            const long Nc = ncells(gc);
+            x0 = x0 + prolong_at<R>(gc, pe, src[0], src[1]);
+            x1 = x1 + prolong_at<R>(gc, pe + Nc, src[0], src[1]);
+        }
         // b is read only at cells that are updated, which lie in the box
         v[ST_B0][u] = b[idx];
         v[ST_B1][u] = b[N + idx];
@@ -618,10 +669,11 @@ __device__ inline void staged_sweeps(const GridD& g, R* s, R dt, R ihh, int ox, 
     }
 }
 
-template <bool FINE, typename R, class CF, int NSW>
+template <bool FINE, typename R, class CF, int NSW, bool PRO>
 __global__ void __launch_bounds__(CF::THREADS)
 k_tsweepN(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, const R* __restrict__ xcura,
-          R* __restrict__ xnexta, const R* __restrict__ ba)
+          R* __restrict__ xnexta, const R* __restrict__ ba, const R* __restrict__ pea, const GridD* __restrict__ gct,
+          const long* __restrict__ oct)
 {
     constexpr int H = 4 * NSW;
     using T = Tile<2, H, CF>;
@@ -634,7 +686,13 @@ k_tsweepN(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     const R* b = ba + 2 * cell0;
     const long N = ncells(g);
     R* s = reinterpret_cast<R*>(tile_lds);
-    fill_staged<FINE, H, R, CF>(g, xcur, b, coef, s, ox, oy, N);
+    GridD gc = g;
+    const R* pe = nullptr;
+    if (PRO) {
+        gc = bv_g2(v, gct, cav);
+        pe = pea + 2 * bv_o2(v, oct, cav);
+    }
+    fill_staged<FINE, H, R, CF, PRO>(g, xcur, b, coef, s, ox, oy, N, pe, gc);
     const R h = (R)g.h;
     const R ihh = R(1) / (h * h);
     __syncthreads();
@@ -1088,9 +1146,18 @@ void launch_tresid_restr(Ctx* c, const Level& L, const BV& v, const GridD* gc, c
     }
 }
 
+template <bool FINE, bool PRO, typename R, class CF, int NSW>
+static void staged_launch(Ctx* c, bool timed, double bytes, dim3 grid, const BV& vv, const R* coef, const R* xcur,
+                          R* xnext, const R* b, const R* pe, const GridD* gct, const long* oct)
+{
+    const size_t lds = sizeof(R) * (FINE ? 5 : 6) * Tile<2, 4 * NSW, CF>::NS;
+    tlaunch(c, timed, bytes, k_tsweepN<FINE, R, CF, NSW, PRO>, grid, dim3(CF::THREADS), lds, vv, coef,
+            (const double*)c->sc, xcur, xnext, b, pe, gct, oct);
+}
+
 template <bool FINE, typename R, class CAND>
 static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b,
-                         int nsw)
+                         int nsw, const R* pe, const GridD* gct, const long* oct)
 {
     using CF = typename CAND::CF;
     const bool timed = c->ktm.on && FINE;
@@ -1103,36 +1170,36 @@ static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, con
     if constexpr (!CAND::STAGED) {
         using T = Tile<2, 4, CF>;
         const size_t lds = sizeof(R) * (FINE ? 3 : 2) * T::NS;
+        if (pe) launch_prolong_cells<R>(c, L, v, gct, oct, 2, -1.0, pe, const_cast<R*>(xcur));
         tlaunch(c, timed, bytes, k_tsweep2<FINE, R, CF>, grid, dim3(CF::THREADS), lds, vv, coef, (const double*)c->sc,
                 xcur, xnext, b);
     } else if (CAND::NSW >= 2 && nsw == 2) {
-        const size_t lds = sizeof(R) * (FINE ? 5 : 6) * Tile<2, 8, CF>::NS;
-        tlaunch(c, timed, bytes, k_tsweepN<FINE, R, CF, 2>, grid, dim3(CF::THREADS), lds, vv, coef,
-                (const double*)c->sc, xcur, xnext, b);
+        if (pe) staged_launch<FINE, true, R, CF, 2>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct);
+        else staged_launch<FINE, false, R, CF, 2>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct);
     } else {
-        const size_t lds = sizeof(R) * (FINE ? 5 : 6) * Tile<2, 4, CF>::NS;
-        tlaunch(c, timed, bytes, k_tsweepN<FINE, R, CF, 1>, grid, dim3(CF::THREADS), lds, vv, coef,
-                (const double*)c->sc, xcur, xnext, b);
+        if (pe) staged_launch<FINE, true, R, CF, 1>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct);
+        else staged_launch<FINE, false, R, CF, 1>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct);
     }
 }
 
 template <bool FINE, typename R, size_t... I>
 static void tsweep2_pick(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b,
-                         int k, int nsw, std::index_sequence<I...>)
+                         int k, int nsw, const R* pe, const GridD* gct, const long* oct, std::index_sequence<I...>)
 {
-    ((k == (int)I ? tsweep2_impl<FINE, R, std::tuple_element_t<I, Sweep2Cands>>(c, L, v, coef, xcur, xnext, b, nsw)
+    ((k == (int)I ? tsweep2_impl<FINE, R, std::tuple_element_t<I, Sweep2Cands>>(c, L, v, coef, xcur, xnext, b, nsw, pe,
+                                                                                gct, oct)
                   : void()),
      ...);
 }
 
 template <typename R>
 void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b,
-                    int tile, int nsw)
+                    int tile, int nsw, const R* pe, const GridD* gct, const long* oct)
 {
     const int k = tile >= 0 && tile < kSweep2Cands ? tile : 0;
     constexpr auto seq = std::make_index_sequence<kSweep2Cands>{};
-    if (fine) tsweep2_pick<true, R>(c, L, v, coef, xcur, xnext, b, k, nsw, seq);
-    else tsweep2_pick<false, R>(c, L, v, coef, xcur, xnext, b, k, nsw, seq);
+    if (fine) tsweep2_pick<true, R>(c, L, v, coef, xcur, xnext, b, k, nsw, pe, gct, oct, seq);
+    else tsweep2_pick<false, R>(c, L, v, coef, xcur, xnext, b, k, nsw, pe, gct, oct, seq);
 }
 
 template <size_t... I>
@@ -1142,7 +1209,8 @@ static SweepShape sweep2_shape_of(int k, std::index_sequence<I...>)
     ((k == (int)I ? (void)(out = SweepShape{std::tuple_element_t<I, Sweep2Cands>::CF::TX,
                                             std::tuple_element_t<I, Sweep2Cands>::CF::TY,
                                             std::tuple_element_t<I, Sweep2Cands>::CF::THREADS,
-                                            std::tuple_element_t<I, Sweep2Cands>::NSW})
+                                            std::tuple_element_t<I, Sweep2Cands>::NSW,
+                                            std::tuple_element_t<I, Sweep2Cands>::STAGED})
                   : void()),
      ...);
     return out;
@@ -1151,21 +1219,23 @@ static SweepShape sweep2_shape_of(int k, std::index_sequence<I...>)
 SweepShape sweep2_shape(int k) { return sweep2_shape_of(k, std::make_index_sequence<kSweep2Cands>{}); }
 
 // the staged sweeps may use more dynamic LDS than the default limit
+template <class CF, typename R, int NSW>
+static void allow_one(size_t bytes)
+{
+    const void* k[4] = {reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, NSW, false>),
+                        reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, NSW, false>),
+                        reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, NSW, true>),
+                        reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, NSW, true>)};
+    for (const void* f : k) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <class CAND, typename R>
 static void allow_staged(size_t bytes)
 {
     if constexpr (CAND::STAGED) {
         using CF = typename CAND::CF;
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, 1>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, 1>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if constexpr (CAND::NSW >= 2) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, 2>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, 2>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        }
+        allow_one<CF, R, 1>(bytes);
+        if constexpr (CAND::NSW >= 2) allow_one<CF, R, 2>(bytes);
     }
 }
 
@@ -1229,7 +1299,8 @@ void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next
 #define HB_TILE_INST(R)                                                                                             \
     template void launch_tsmooth<R>(Ctx*, const Level&, const BV&, const R*, bool, int, const R*, R*, const R*);     \
     template void launch_trb3<R>(Ctx*, const Level&, const BV&, const R*, bool, int, int, R*, const R*);             \
-    template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*, int, int);     \
+    template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*, int, int, \
+                                     const R*, const GridD*, const long*);     \
     template void launch_mac_sweep<R>(Ctx*, const Level&, const BV&, const R*, R*, const R*);                        \
     template void launch_tresid_restr<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, bool, \
                                          const R*, const R*, R*, R*);
