@@ -232,15 +232,18 @@ int hb_warm_start_uses(const hb_ctx* ctx);
 int hb_capture(hb_ctx* ctx, int op, int enable);
 int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e);
 
-/* Measurement support.  While enabled, every launch of the tensor viscous
- * smoother on the finest multigrid level is timed with events that the
- * dispatch itself records (2D: one red-black sweep of both velocity
+/* Measurement support.  While enabled (enable = k > 0), every k-th launch
+ * of the tensor viscous smoother on the finest multigrid level (k = 1: every
+ * launch) is timed with events that the dispatch itself records; such a
+ * launch costs the host more than a plain one, so sampling keeps the timer
+ * from slowing the run it measures (2D: one red-black sweep of both velocity
  * components, or two where the level's autotuned candidate runs two sweeps
  * per launch; 3D: one colour of one component); hb_kernel_timing_read
- * synchronises, and returns the number of launches, their summed device
- * time and their summed algorithmic bytes (2D: both x components, eta/Re
+ * synchronises, and returns the number of timed launches, their summed
+ * device time and their summed algorithmic bytes (2D: both x components, eta/Re
  * and both b components read once, x written once, per launch whatever its
- * sweep count; 3D: every x component and eta/Re read once, the colour's b
+ * sweep count, plus both components of the coarse iterate where the launch
+ * adds the prolongation of a V-cycle's coarse correction; 3D: every x component and eta/Re read once, the colour's b
  * read and x written; words of the storage type).  Enabling resets the
  * counters. */
 int hb_kernel_timing(hb_ctx* ctx, int enable);

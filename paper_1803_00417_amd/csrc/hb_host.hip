@@ -1603,7 +1603,9 @@ int hb_kernel_timing(hb_ctx* ctx, int enable)
         k.cap = cap;
     }
     if (!enable) kt_harvest(c);
-    k.on = enable != 0;
+    k.on = enable > 0;
+    k.period = enable > 0 ? enable : 1;
+    k.seen = 0;
     k.n = 0;
     k.launches = 0;
     k.ms = 0.0;

@@ -239,6 +239,8 @@ struct Cav {
 // HIP-event timing of every launch of one kernel (measurement support)
 struct KTimer {
     bool on = false;
+    int period = 1;             // time every period-th candidate launch
+    long seen = 0;              // candidate launches since enabling
     int cap = 0, n = 0;
     hipEvent_t* ev = nullptr;   // 2 * cap events: start/stop pairs
     long launches = 0;
@@ -313,6 +315,13 @@ void launch_max_final(Ctx* c, const int* act, int slot);
 // single-array forms, result into slot of cavity cav
 void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot);
 void set_slot(Ctx* c, int cav, int slot, double v);
+// true when this finest-level smoother launch is to be timed (the timer is
+// on and the launch is the period-th since the last timed one)
+inline bool kt_take(Ctx* c)
+{
+    KTimer& k = c->ktm;
+    return k.on && (k.seen++ % k.period) == 0;
+}
 void fetch_slots(Ctx* c);  // all slots to c->hsc once the stream's work so far has completed
 void copy(Ctx* c, double* dst, const double* src, long n);
 void fill(Ctx* c, double* dst, double v, long n);

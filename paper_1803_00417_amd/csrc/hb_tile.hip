@@ -1088,7 +1088,7 @@ template <typename R>
 void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, const R* xcur, R* xnext,
                     const R* b)
 {
-    const bool timed = c->ktm.on && fine;
+    const bool timed = fine && kt_take(c);
     // algorithmic bytes of one fused red-black sweep of one component: every
     // component of x and the coefficients (eta/Re per cell on the finest
     // level, face viscosities below) read once, b_c read once, x_c written
@@ -1160,13 +1160,15 @@ static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, con
                          int nsw, const R* pe, const GridD* gct, const long* oct)
 {
     using CF = typename CAND::CF;
-    const bool timed = c->ktm.on && FINE;
+    const bool timed = FINE && kt_take(c);
     BV vv = v;
     const dim3 grid = tile_grid<2, CF>(c, L, vv);
     // algorithmic bytes of a launch (one sweep or several in LDS): both
-    // components of x, eta/Re and both components of b read once, x written once
+    // components of x, eta/Re and both components of b read once, x written
+    // once; with a folded prolongation also both components of the coarse
+    // iterate (N/4 cells each)
     const double N = level_cells(L);
-    const double bytes = sizeof(R) * (2.0 * N + N + 2.0 * N + 2.0 * N);
+    const double bytes = sizeof(R) * (2.0 * N + N + 2.0 * N + 2.0 * N + (pe ? 2.0 * N / 4.0 : 0.0));
     if constexpr (!CAND::STAGED) {
         using T = Tile<2, 4, CF>;
         const size_t lds = sizeof(R) * (FINE ? 3 : 2) * T::NS;
@@ -1271,7 +1273,7 @@ template <typename R>
 void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b)
 {
     using T = Tile<3, 1>;
-    const bool timed = c->ktm.on && fine;
+    const bool timed = fine && kt_take(c);
     const size_t lds = sizeof(R) * (3 + (fine ? 1 : 0)) * T::NS;
     BV vv = v;
     const dim3 grid = tile_grid<3>(c, L, vv);

@@ -286,6 +286,8 @@ class Context:
         return d.value
 
     def kernel_timing(self, enable):
+        """enable: 0 (or False) off; k > 0 (True = 1) times every k-th
+        finest-level smoother launch"""
         self._check(load().hb_kernel_timing(self._h, int(enable)))
 
     def kernel_timing_read(self):
