@@ -364,8 +364,8 @@ static BV paired(BV v, const Level& P)
 }
 
 // Smoothing sweeps on level l.  C (optional): the coarse level whose
-// correction the first sweep adds to the iterate first (2D tensor problem
-// with fused sweeps and a staged candidate).
+// correction the first sweep adds to the iterate first (2D, fused sweeps:
+// MAC problem, and tensor problem with a staged candidate).
 template <typename R>
 static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C = nullptr)
 {
@@ -397,15 +397,24 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C =
                 for (int colour = 0; colour < 2; ++colour)
                     launch_trb3<R>(c, L, v, tcoef<R>(m, l), l == 0, q, colour, B::x(L), B::b(L));
         } else if (m.op == HB_OP_MAC && c->fuse) {
-            // both colours in one launch, into the other buffer
-            launch_mac_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L));
+            // both colours in one launch, into the other buffer (2D: two
+            // sweeps per launch with `pair`)
+            const int n = (c->dim == 2 && pair && sweeps - s >= 2) ? 2 : 1;
+            if (s == 0 && C)
+                launch_mac_sweep<R>(c, L, paired(v, *C), B::x(L), B::xo(L), B::b(L), n, B::x(*C), C->gall, C->o);
+            else
+                launch_mac_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L), n);
             L.cur ^= 1;
+            s += n - 1;
         } else if (m.op == HB_OP_MAC) {
             for (int colour = 0; colour < 2; ++colour) launch_mac_rb<R>(c, L, v, colour, B::x(L), B::b(L));
         } else if (c->fuse) {
-            // all colours of a sweep in one launch (two in 3D) into the other buffer
-            launch_nodal_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L), L.tile);
+            // all colours of a sweep in one launch (two in 3D) into the other
+            // buffer; 2D: two sweeps per launch with `pair` where the level allows
+            const int n = (pair && L.sweeps == 2 && sweeps - s >= 2) ? 2 : 1;
+            launch_nodal_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L), L.tile, n);
             L.cur ^= 1;
+            s += n - 1;
         } else {
             for (int colour = 0; colour < (1 << c->dim); ++colour) launch_nodal_gs<R>(c, L, v, colour, B::x(L), B::b(L));
         }
@@ -491,9 +500,10 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
             launch_nodal_restrict<R>(c, C, vc, L.gall, L.o, B::r(L), B::b(C), B::x(C));
         }
         vcycle<R>(c, m, l + 1, nu1, nu2);
-        // 2D tensor problem with a staged smoother: the prolongation is
-        // folded into the first post-smoothing launch
-        const bool fold = m.op == HB_OP_VISC && c->dim == 2 && c->fuse && nu2 > 0 && sweep2_shape(L.tile).staged;
+        // 2D tensor problem with a staged smoother, and 2D MAC problem: the
+        // prolongation is folded into the first post-smoothing launch
+        const bool fold = c->dim == 2 && c->fuse && nu2 > 0 &&
+                          ((m.op == HB_OP_VISC && sweep2_shape(L.tile).staged) || m.op == HB_OP_MAC);
         if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L, vpc, C.gall, C.o, B::x(C), B::x(L));
         else if (!fold)
             launch_prolong_cells<R>(c, L, vpc, C.gall, C.o, m.ncomp, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
@@ -505,7 +515,8 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
 // r = b - A x on level 0 (FP64) and its max-norm into each cavity's S_MAX
 static void resid0(Ctx* c, MG& m, const double* x, const double* b, double* r, const int* act)
 {
-    seg_set_zero(c, S_MAX);
+    // the residual kernels' final max pass writes S_MAX of every active
+    // cavity (the only ones whose norm is read)
     const Level& L = m.L[0];
     const BV v = all_view(c, L, act);
     if (m.op == HB_OP_VISC) launch_tresid(c, L, v, m.etae, x, b, r, S_MAX);
@@ -536,11 +547,16 @@ static void precond(Ctx* c, MG& m, const double* r, double* z, int nu1, int nu2,
         seg_from_f32(c, sv, LB<float>::x(L), z);
         return;
     }
+    // the cycle runs on z as the first buffer of level 0 (zeroed), so it
+    // ends there when the level swaps its buffers an even number of times
     double* sb = L.b;
+    double* sx = L.xb[0];
     L.b = const_cast<double*>(r);
-    seg_fill(c, sv, L.X(), 0.0);
+    L.xb[0] = z;
+    seg_fill(c, sv, z, 0.0);
     vcycle<double>(c, m, 0, nu1, nu2);
-    seg_copy(c, sv, z, L.X());
+    if (L.cur != 0) seg_copy(c, sv, z, L.X());
+    L.xb[0] = sx;
     L.b = sb;
 }
 
@@ -680,13 +696,11 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o,
             if (act[i] && stops(so[i], o)) act[i] = 0;
         if (!any_set(c, act)) break;
         upload_flags(c, c->act, act);
-        seg_dot(c, sv, rh, r, S_DOT0);
-        bicg_beta(c, c->act);
+        seg_dot_then(c, sv, rh, r, S_DOT0, 1);   // rho, beta
         bicg_p_dev(c, sv, p, r, v);
         precond(c, m, p, ph, o.nu1, o.nu2, lo);
         apply0(c, m, ph, v);
-        seg_dot(c, sv, rh, v, S_DOT1);
-        bicg_alpha(c, c->act);
+        seg_dot_then(c, sv, rh, v, S_DOT1, 2);   // alpha
         sub_scaled_max_dev(c, sv, s, r, S_ALPHA, v, S_MAX);
         fetch_slots(c);
         // cavities that finish at the half step: x += alpha ph, r = s
@@ -719,9 +733,7 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o,
         }
         precond(c, m, s, sh, o.nu1, o.nu2, lo);
         apply0(c, m, sh, t);
-        seg_dot(c, sv, t, t, S_DOT0);
-        seg_dot(c, sv, t, s, S_DOT1);
-        bicg_omega(c, c->act);
+        seg_dot2_then(c, sv, t, t, S_DOT0, s, S_DOT1, 3);   // t.t, t.s, omega
         bicg_x_dev(c, sv, x, ph, sh, true);
         sub_scaled_max_dev(c, sv, r, s, S_OMEGA, t, S_MAX);
         fetch_slots(c);
@@ -1108,7 +1120,10 @@ static void autotune(Ctx* c)
             for (int k = 0; k < nc; ++k) {
                 nsw[k] = 1;
                 usable[k] = true;
-                if (!visc) continue;
+                if (!visc) {
+                    if (c->dim == 2 && level_pairs(L)) nsw[k] = 2;
+                    continue;
+                }
                 if (sweep2_shape(k).nsw >= 2 && level_pairs(L) && sweep2_lds(k, 2) <= c->lds_budget) nsw[k] = 2;
                 usable[k] = sweep2_lds(k, 1) <= c->lds_budget;
             }
@@ -1128,6 +1143,8 @@ static void autotune(Ctx* c)
                 } else if (visc) {
                     launch_tsweep2<double>(c, L, v, tcoef<double>(*m, l), l == 0, L.xb[0], L.xb[1], L.b, k, 1);
                     launch_tsweep2<double>(c, L, v, tcoef<double>(*m, l), l == 0, L.xb[1], L.xb[0], L.b, k, 1);
+                } else if (nsw[k] == 2) {
+                    launch_nodal_sweep<double>(c, L, v, L.xb[0], L.xb[1], L.b, k, 2);
                 } else {
                     launch_nodal_sweep<double>(c, L, v, L.xb[0], L.xb[1], L.b, k);
                     launch_nodal_sweep<double>(c, L, v, L.xb[1], L.xb[0], L.b, k);
@@ -1205,7 +1222,9 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
               hipHostMalloc((void**)&c->hseq, sizeof(unsigned long long), pin) == hipSuccess &&
               hipHostGetDevicePointer((void**)&c->dhsc, c->hsc, 0) == hipSuccess &&
               hipHostGetDevicePointer((void**)&c->dhseq, c->hseq, 0) == hipSuccess &&
-              dalloc(&c->partial, (long)kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
+              dalloc(&c->partial, 2L * kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
+              dalloc(&c->rcnt, count) == hipSuccess &&
+              hipMemsetAsync(c->rcnt, 0, sizeof(unsigned) * count, c->s) == hipSuccess &&
               dalloc(&c->mpart, (long)kSubMax * count) == hipSuccess &&
               hipMemsetAsync(c->mpart, 0, sizeof(unsigned long long) * kSubMax * count, c->s) == hipSuccess &&
               dalloc(&c->act2, count) == hipSuccess && dalloc(&c->sel, count) == hipSuccess &&
@@ -1314,6 +1333,7 @@ static void destroy_ctx(Ctx* c)
                       c->sc, c->partial};
     for (double* p : bufs) (void)hipFree(p);
     (void)hipFree(c->mpart);
+    (void)hipFree(c->rcnt);
     (void)hipFree(c->act);
     (void)hipFree(c->act2);
     (void)hipFree(c->sel);
@@ -1579,6 +1599,7 @@ int hb_tile_config(const hb_ctx* ctx, int op, int level, int* tx, int* ty, int* 
     } else {
         nodal_sweep_tile(c->dim, L.tile, tx, ty);
         th = c->dim == 2 ? 256 : 512;
+        sw = L.sweeps;
     }
     if (threads) *threads = th;
     if (sweeps) *sweeps = sw;

@@ -267,7 +267,8 @@ struct Ctx {
     double* dhsc = nullptr;               // device addresses of hsc and hseq
     unsigned long long* dhseq = nullptr;
     unsigned long long pub = 0;           // last publication number
-    double* partial = nullptr;   // reduction partials (kRedBlocks per cavity)
+    double* partial = nullptr;   // reduction partials (2 x kRedBlocks per cavity)
+    unsigned* rcnt = nullptr;    // per cavity: blocks done in a single-launch reduction (zero between launches)
     unsigned long long* mpart = nullptr;   // max-norm partials (kSubMax per cavity, kept zero between uses)
     int* act = nullptr;          // device active flags (nb)
     int* hact = nullptr;         // pinned host staging of the flags
@@ -329,6 +330,11 @@ void fill(Ctx* c, double* dst, double v, long n);
 void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot);
 void seg_set_zero(Ctx* c, int slot);                       // every cavity
 void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot);
+// the same, then BiCGStab scalar update `then` (1 rho and beta, 2 alpha)
+void seg_dot_then(Ctx* c, const SegV& s, const double* a, const double* b, int slot, int then);
+// slot0 = a.b0 and slot1 = a.b1 in one pass, then scalar update `then` (3 omega)
+void seg_dot2_then(Ctx* c, const SegV& s, const double* a, const double* b0, int slot0, const double* b1, int slot1,
+                   int then);
 void seg_sub_mean(Ctx* c, const SegV& s, double* v);
 void seg_copy(Ctx* c, const SegV& s, double* dst, const double* src);
 void seg_fill(Ctx* c, const SegV& s, double* dst, double v);
@@ -396,7 +402,12 @@ void launch_tresid(Ctx* c, const Level& L, const BV& v, const double* coef, cons
 // (hb_mg.hip, hb_nodal.hip), batched
 template <typename R> void launch_mac_rb(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b);
 // both colours of a red-black sweep from cur into next (hb_tile.hip)
-template <typename R> void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b);
+// (2D: nsw (1 or 2) sweeps per launch, every periodic extent at least 2 nsw;
+// pe: coarse iterate whose prolongation is added to cur first, v then also
+// carrying the coarse level, gct/oct its tables)
+template <typename R>
+void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int nsw = 1,
+                      const R* pe = nullptr, const GridD* gct = nullptr, const long* oct = nullptr);
 // one thread per coarse cell: vc covers the coarse level, gf / of_ give the
 // fine grid and offsets of the same cavities
 template <typename R>
@@ -409,11 +420,13 @@ template <typename R>
 void launch_prolong_cells(Ctx* c, const Level& L, const BV& v, const GridD* gc, const long* oc, int ncomp,
                           double wall_sign, const R* e, R* x);
 template <typename R> void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, const R* b);
-// one whole Gauss-Seidel sweep from cur into next (one launch, two in 3D),
+// nsw (1, or 2 in 2D with every periodic extent at least 8) whole
+// Gauss-Seidel sweeps from cur into next (one launch; 3D: one sweep, two launches),
 // with candidate tile `tile` (0 .. kNodalCands - 1); nodal_sweep_tile gives
 // its extents
 template <typename R>
-void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile);
+void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile,
+                        int nsw = 1);
 void nodal_sweep_tile(int dim, int tile, int* tx, int* ty);
 constexpr int kNodalCands = 3;
 // r = b - K x (slot >= 0: FP64 only, max-norm into each cavity's slot) or y = K x (b null)

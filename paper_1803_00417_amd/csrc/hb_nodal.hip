@@ -198,21 +198,28 @@ using NG4Tiles2 = std::tuple<NG4<64, 16, 1, 256>, NG4<128, 8, 1, 256>, NG4<32, 3
 using NG4Tiles3 = std::tuple<NG4<64, 8, 2, 512>, NG4<32, 16, 2, 512>, NG4<64, 4, 4, 512>>;
 constexpr int kNG4Tiles = 3;
 
-template <int DIM, class CF>
+// 2D, NSW = 2: two whole sweeps in one launch.  Colour c of sweep w runs on
+// the tile grown by 4 (NSW - 1 - w) + 3 - c in x and 2 (NSW - 1 - w) + (1 for
+// c <= 1) in y (the rings above, widened by what the later sweep reads), so
+// the halo is 4 NSW by 2 NSW nodes; again every node sees the values of the
+// one-colour-per-launch order.
+template <int DIM, class CF, int NSW = 1>
 struct NG4Tile {
+    static_assert(DIM == 2 || NSW == 1, "two sweeps per launch in 2D only");
     using C = CF;
-    static constexpr int HX = 4, HY = 2;                   // halo of x
+    static constexpr int HX = 4 * NSW, HY = 2 * NSW;     // halo of x
     static constexpr int SX = C::TX + 2 * HX, SY = C::TY + 2 * HY, SZ = DIM == 3 ? 2 * C::PZ + 1 : 1;
     static constexpr int NS = SX * SY * SZ;
-    static constexpr int BX = C::TX + 6, BY = C::TY + 2;  // b on the colour-0 region
+    // b on the first colour's region
+    static constexpr int BX = C::TX + 2 * (HX - 1), BY = C::TY + 2 * (HY - 1);
     static constexpr int NB = BX * BY * C::PZ;
 };
 
-template <int DIM, typename R, class CF>
+template <int DIM, typename R, class CF, int NSW = 1>
 __global__ void __launch_bounds__(CF::TH)
 k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* nexta, const R* __restrict__ ba)
 {
-    using T = NG4Tile<DIM, CF>;
+    using T = NG4Tile<DIM, CF, NSW>;
     constexpr int TH = CF::TH;
     __shared__ R s[T::NS];
     __shared__ R sb[T::NB];
@@ -261,7 +268,7 @@ k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* n
             const int t = threadIdx.x + u * TH;
             const int tt = t < T::NB ? t : 0;
             const int lx = tt % T::BX, ly = (tt / T::BX) % T::BY, lz = tt / (T::BX * T::BY);
-            int p[3] = {ox - 3 + lx, oy - 1 + ly, DIM == 3 ? kb + 2 * lz : 0};
+            int p[3] = {ox - (T::HX - 1) + lx, oy - (T::HY - 1) + ly, DIM == 3 ? kb + 2 * lz : 0};
             bool ok = true;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -285,11 +292,13 @@ k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* n
         }
     }
     __syncthreads();
-    // the four in-plane colours, each on its region of every updated plane
+    // the four in-plane colours (of each sweep), each on its region of every
+    // updated plane
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-        const int gx = cc == 0 ? 3 : (cc == 1 ? 2 : (cc == 2 ? 1 : 0));
-        const int gy = cc <= 1 ? 1 : 0;
+    for (int q = 0; q < 4 * NSW; ++q) {
+        const int cc = q & 3, w = q >> 2;
+        const int gx = 4 * (NSW - 1 - w) + 3 - cc;
+        const int gy = 2 * (NSW - 1 - w) + (cc <= 1 ? 1 : 0);
         const int px = cc & 1, py = (cc >> 1) & 1;
         // region [ox - gx, ox + TX + gx) x [oy - gy, oy + TY + gy); the first
         // node of colour parity px along x, py along y
@@ -301,7 +310,7 @@ k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* n
             const int ix = t % wx, iy = (t / wx) % wy, m = t / (wx * wy);
             int G[3] = {fx + 2 * ix, fy + 2 * iy, DIM == 3 ? kb + 2 * m : 0};
             const int lx = G[0] - ox + T::HX, ly = G[1] - oy + T::HY, lz = DIM == 3 ? 1 + 2 * m : 0;
-            const int lb = (m * T::BY + (G[1] - oy + 1)) * T::BX + (G[0] - ox + 3);
+            const int lb = (m * T::BY + (G[1] - oy + T::HY - 1)) * T::BX + (G[0] - ox + T::HX - 1);
             bool inside = true;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -349,13 +358,14 @@ void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, cons
 }
 
 template <int DIM, typename R, class CF>
-static void nodal_sweep_impl(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b)
+static void nodal_sweep_impl(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int nsw)
 {
     BV vv = v;
     if (DIM == 2) {
         vv.zb = 1;
         const dim3 grid((nnode(L.gmax, 0) + CF::TX - 1) / CF::TX, (nnode(L.gmax, 1) + CF::TY - 1) / CF::TY, c->nb);
-        k_nodal_gs_fused<2, R, CF><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
+        if (nsw == 2) k_nodal_gs_fused<2, R, CF, 2><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
+        else k_nodal_gs_fused<2, R, CF><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
     } else {
         const int planes = (nnode(L.gmax, 2) + 1) / 2;   // even planes (at least as many as odd)
         vv.zb = (planes + CF::PZ - 1) / CF::PZ;
@@ -367,20 +377,22 @@ static void nodal_sweep_impl(Ctx* c, const Level& L, const BV& v, const R* cur, 
 }
 
 template <int DIM, typename R, class Tiles, size_t... I>
-static void nodal_sweep_pick(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int k,
+static void nodal_sweep_pick(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int k, int nsw,
                              std::index_sequence<I...>)
 {
-    ((k == (int)I ? nodal_sweep_impl<DIM, R, std::tuple_element_t<I, Tiles>>(c, L, v, cur, next, b) : void()), ...);
+    ((k == (int)I ? nodal_sweep_impl<DIM, R, std::tuple_element_t<I, Tiles>>(c, L, v, cur, next, b, nsw) : void()),
+     ...);
 }
 
-// one Gauss-Seidel sweep (all 2^d colours) from cur into next, with tile
-// candidate `tile`
+// nsw Gauss-Seidel sweeps (all 2^d colours; two in 2D only) from cur into
+// next, with tile candidate `tile`
 template <typename R>
-void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile)
+void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile, int nsw)
 {
     const int k = tile >= 0 && tile < kNG4Tiles ? tile : 0;
-    if (L.gmax.dim == 2) nodal_sweep_pick<2, R, NG4Tiles2>(c, L, v, cur, next, b, k, std::make_index_sequence<kNG4Tiles>{});
-    else nodal_sweep_pick<3, R, NG4Tiles3>(c, L, v, cur, next, b, k, std::make_index_sequence<kNG4Tiles>{});
+    constexpr auto seq = std::make_index_sequence<kNG4Tiles>{};
+    if (L.gmax.dim == 2) nodal_sweep_pick<2, R, NG4Tiles2>(c, L, v, cur, next, b, k, nsw, seq);
+    else nodal_sweep_pick<3, R, NG4Tiles3>(c, L, v, cur, next, b, k, 1, seq);
 }
 
 void nodal_sweep_tile(int dim, int k, int* tx, int* ty)
@@ -416,8 +428,8 @@ void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R
     if (slot >= 0) launch_max_final(c, vv.act, slot);
 }
 
-template void launch_nodal_sweep<double>(Ctx*, const Level&, const BV&, const double*, double*, const double*, int);
-template void launch_nodal_sweep<float>(Ctx*, const Level&, const BV&, const float*, float*, const float*, int);
+template void launch_nodal_sweep<double>(Ctx*, const Level&, const BV&, const double*, double*, const double*, int, int);
+template void launch_nodal_sweep<float>(Ctx*, const Level&, const BV&, const float*, float*, const float*, int, int);
 template void launch_nodal_gs<double>(Ctx*, const Level&, const BV&, int, double*, const double*);
 template void launch_nodal_gs<float>(Ctx*, const Level&, const BV&, int, float*, const float*);
 template void launch_nodal_resid<double>(Ctx*, const Level&, const BV&, const double*, const double*, double*, int);

@@ -208,7 +208,118 @@ static void seg_sum_impl(Ctx* c, const SegV& s, const double* a, const double* b
     k_seg_sum_final<<<c->nb, kT, 0, c->s>>>(s, c->partial, c->sc, slot);
 }
 
-void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot) { seg_sum_impl(c, s, a, b, slot); }
+// one BiCGStab scalar update of a cavity's slots (which: 0 initial values,
+// 1 rho and beta, 2 alpha, 3 omega)
+__device__ inline void bicg_scalar(double* sc, int which)
+{
+    if (which == 0) {            // initial values
+        sc[S_RHOP] = 1.0;
+        sc[S_ALPHA] = 1.0;
+        sc[S_OMEGA] = 1.0;
+    } else if (which == 1) {     // rho and beta
+        const double rho = sc[S_DOT0];
+        sc[S_RHO] = rho;
+        sc[S_BETA] = (rho / sc[S_RHOP]) * (sc[S_ALPHA] / sc[S_OMEGA]);
+    } else if (which == 2) {     // alpha
+        sc[S_ALPHA] = sc[S_RHO] / sc[S_DOT1];
+    } else {                     // omega from (t.t, t.s); rho_prev = rho
+        const double tt = sc[S_DOT0];
+        sc[S_OMEGA] = tt > 0.0 ? sc[S_DOT1] / tt : 0.0;
+        sc[S_RHOP] = sc[S_RHO];
+    }
+}
+
+// Single-launch reductions.  Each block of a cavity writes its partial,
+// then adds one to the cavity's counter (acquire-release at device scope,
+// so the partial is visible before the count); the block that completes the
+// count sees every partial, finishes the reduction in the fixed order of a
+// separate final pass, and resets the counter for the next launch.
+__device__ inline bool last_block(unsigned* cnt, int cav, unsigned nblk, bool* last)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned old = __hip_atomic_fetch_add(cnt + cav, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        *last = old == nblk - 1;
+        if (*last) __hip_atomic_store(cnt + cav, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return *last;
+}
+
+// a partial written by another block of this launch (read past the CU's
+// cache)
+__device__ inline double load_dev(const double* p)
+{
+    const unsigned long long b =
+        __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)b);
+}
+
+// sum over the final pass's partials of one cavity (as k_seg_sum_final)
+__device__ inline double final_sum(const double* part, double* sh)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) s += load_dev(part + i);
+    return block_sum(s, sh);
+}
+
+// slot0 = sum(a * b0) (b0 null: sum a) and, with b1, slot1 = sum(a * b1),
+// in one pass; then (1..3) the BiCGStab scalar update that follows.  Block x
+// of cavity y owns {x*T + t + k*kRedBlocks*T}, as k_seg_sum_partial: the
+// same sums bit for bit.
+__global__ void k_seg_dot(SegV sv, const double* __restrict__ a, const double* __restrict__ b0,
+                          const double* __restrict__ b1, double* __restrict__ part, unsigned* cnt,
+                          double* __restrict__ scb, int slot0, int slot1, int then)
+{
+    __shared__ double sh[kT / 64];
+    __shared__ bool last;
+    SEG_ENTER(sv, off, n);
+    double s0 = 0.0, s1 = 0.0;
+    SEG_LOOP(i, n)
+    {
+        s0 += b0 ? a[off + i] * b0[off + i] : a[off + i];
+        if (b1) s1 += a[off + i] * b1[off + i];
+    }
+    double* p0 = part + (long)cav_ * kRedBlocks;
+    double* p1 = part + ((long)gridDim.y + cav_) * kRedBlocks;
+    s0 = block_sum(s0, sh);
+    if (threadIdx.x == 0) p0[blockIdx.x] = s0;
+    if (b1) {
+        s1 = block_sum(s1, sh);
+        if (threadIdx.x == 0) p1[blockIdx.x] = s1;
+    }
+    if (!last_block(cnt, cav_, gridDim.x, &last)) return;
+    const double t0 = final_sum(p0, sh);
+    const double t1 = b1 ? final_sum(p1, sh) : 0.0;
+    if (threadIdx.x == 0) {
+        double* sc = scb + (long)cav_ * S_NSLOT;
+        sc[slot0] = t0;
+        if (b1) sc[slot1] = t1;
+        if (then) bicg_scalar(sc, then);
+    }
+}
+
+static void dot_launch(Ctx* c, const SegV& s, const double* a, const double* b0, const double* b1, int slot0, int slot1,
+                       int then)
+{
+    k_seg_dot<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, a, b0, b1, c->partial, c->rcnt, c->sc, slot0, slot1, then);
+}
+
+void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot)
+{
+    dot_launch(c, s, a, b, nullptr, slot, 0, 0);
+}
+
+void seg_dot_then(Ctx* c, const SegV& s, const double* a, const double* b, int slot, int then)
+{
+    dot_launch(c, s, a, b, nullptr, slot, 0, then);
+}
+
+void seg_dot2_then(Ctx* c, const SegV& s, const double* a, const double* b0, int slot0, const double* b1, int slot1,
+                   int then)
+{
+    dot_launch(c, s, a, b0, b1, slot0, slot1, then);
+}
 
 // v -= sum(v) / n per cavity, the sum taken from the slot
 __global__ void k_seg_sub_mean(SegV sv, double* __restrict__ v, const double* __restrict__ sc)
@@ -316,22 +427,7 @@ __global__ void k_bicg_scalars(double* scb, int nb, const int* act, int which)
 {
     const int cav = blockIdx.x * blockDim.x + threadIdx.x;
     if (cav >= nb || (act && !act[cav])) return;
-    double* sc = scb + (long)cav * S_NSLOT;
-    if (which == 0) {            // initial values
-        sc[S_RHOP] = 1.0;
-        sc[S_ALPHA] = 1.0;
-        sc[S_OMEGA] = 1.0;
-    } else if (which == 1) {     // rho and beta
-        const double rho = sc[S_DOT0];
-        sc[S_RHO] = rho;
-        sc[S_BETA] = (rho / sc[S_RHOP]) * (sc[S_ALPHA] / sc[S_OMEGA]);
-    } else if (which == 2) {     // alpha
-        sc[S_ALPHA] = sc[S_RHO] / sc[S_DOT1];
-    } else {                     // omega from (t.t, t.s); rho_prev = rho
-        const double tt = sc[S_DOT0];
-        sc[S_OMEGA] = tt > 0.0 ? sc[S_DOT1] / tt : 0.0;
-        sc[S_RHOP] = sc[S_RHO];
-    }
+    bicg_scalar(scb + (long)cav * S_NSLOT, which);
 }
 
 static void bicg_scalars(Ctx* c, const int* act, int which)
@@ -360,7 +456,8 @@ void bicg_p_dev(Ctx* c, const SegV& s, double* p, const double* r, const double*
 
 // out = a - s b (s from a slot), with the max-norm of out into another slot
 __global__ void k_sub_scaled_max_dev(SegV sv, double* __restrict__ out, const double* __restrict__ a, int sslot,
-                                     const double* __restrict__ b, double* __restrict__ scb, int mslot)
+                                     const double* __restrict__ b, double* __restrict__ scb, int mslot,
+                                     double* __restrict__ part, unsigned* cnt)
 {
     __shared__ unsigned long long sh[kT / 64];
     SEG_ENTER(sv, off, n);
@@ -374,13 +471,24 @@ __global__ void k_sub_scaled_max_dev(SegV sv, double* __restrict__ out, const do
         m = bb > m ? bb : m;
     }
     m = block_umax(m, sh);
-    if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav_ * S_NSLOT + mslot, m);
+    // the cavity's last block takes the maximum of the blocks' maxima
+    unsigned long long* pm = reinterpret_cast<unsigned long long*>(part) + (long)cav_ * kRedBlocks;
+    if (threadIdx.x == 0) pm[blockIdx.x] = m;
+    __shared__ bool last;
+    if (!last_block(cnt, cav_, gridDim.x, &last)) return;
+    unsigned long long mm = 0ull;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+        const unsigned long long v = __hip_atomic_load(pm + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        mm = v > mm ? v : mm;
+    }
+    mm = block_umax(mm, sh);
+    if (threadIdx.x == 0) scb[(long)cav_ * S_NSLOT + mslot] = __longlong_as_double((long long)mm);
 }
 
 void sub_scaled_max_dev(Ctx* c, const SegV& s, double* out, const double* a, int sslot, const double* b, int mslot)
 {
-    seg_set_zero(c, mslot);
-    k_sub_scaled_max_dev<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, a, sslot, b, c->sc, mslot);
+    k_sub_scaled_max_dev<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, a, sslot, b, c->sc, mslot,
+                                                                              c->partial, c->rcnt);
 }
 
 // x += alpha ph + omega sh (with_omega), or x = alpha ph + x

@@ -505,10 +505,11 @@ enum { ST_X0 = 0, ST_X1 = 1, ST_B0 = 2, ST_B1 = 3, ST_E = 4, ST_FX = 4, ST_FY = 
 // Prolongation correction (P e)_q at fine cell (si, sj) from the coarse
 // iterate e (components Nc apart) on grid gc: the 2^2 nearest coarse cells
 // with axis weights 3/4 and 1/4; a coarse neighbour beyond a wall is the
-// cell itself with the homogeneous ghost sign -1.  Same terms, order and
+// cell itself with the homogeneous ghost sign wsign (tensor problem -1,
+// MAC problem +1).  Same terms, order and
 // rounding as the prolongation kernel.
 template <typename R>
-__device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si, int sj)
+__device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si, int sj, R wsign)
 {
     const int C[2] = {si >> 1, sj >> 1}, ch[2] = {si & 1, sj & 1};
     int J[2];
@@ -519,7 +520,7 @@ __device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si,
         R sg = 1;
         if (J2 < 0 || J2 >= gc.n[a]) {
             if (gc.per[a]) J2 = J2 < 0 ? J2 + gc.n[a] : J2 - gc.n[a];
-            else { J2 = C[a]; sg = R(-1); }
+            else { J2 = C[a]; sg = wsign; }
         }
         J[a] = J2;
         sgn[a] = sg;
@@ -567,8 +568,8 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
         R x0 = x[idx], x1 = x[N + idx];
         if (PRO) {
             const long Nc = ncells(gc);
-            x0 = x0 + prolong_at<R>(gc, pe, src[0], src[1]);
-            x1 = x1 + prolong_at<R>(gc, pe + Nc, src[0], src[1]);
+            x0 = x0 + prolong_at<R>(gc, pe, src[0], src[1], R(-1));
+            x1 = x1 + prolong_at<R>(gc, pe + Nc, src[0], src[1], R(-1));
         }
         // b is read only at cells that are updated, which lie in the box
         v[ST_B0][u] = b[idx];
@@ -805,6 +806,133 @@ k_mac_sweep(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* __
         next[cid(g, G[0], G[1], G[2])] = s[T::at(rx + 2, ry + 2, DIM == 3 ? rz + 2 : 0)];
     }
 }
+
+// ---------------------------------------------------------------------------
+// MAC problem, 2D: NSW whole red-black sweeps in one launch.  x and b of the
+// tile plus a halo of 2 NSW are staged in LDS; the half steps (red, black,
+// ...) walk the tile grown by 2 NSW - 1, ..., 0 rings (each reads face
+// neighbours only), so NSW = 2 gives bit for bit the result of two one-sweep
+// launches.  PRO: the fill adds the prolongation of the coarse correction
+// (wall sign +1), as the prolongation kernel would have before the sweep.
+// Per-cell arithmetic as k_mac_sweep.
+// ---------------------------------------------------------------------------
+template <int COLOUR, int RING, int H, typename R, class CF>
+__device__ inline void mac_half(const GridD& g, R* s, R ih2, int ox, int oy)
+{
+    using T = Tile<2, H, CF>;
+    constexpr int TH = CF::THREADS;
+    constexpr int K = ((T::TX + 2 * RING) / 2 * (T::TY + 2 * RING) + TH - 1) / TH;
+    const R* sb = s + T::NS;
+    const int off[2] = {1, T::SX};
+    int L[K];
+    bool ok[K];
+    R nv[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        int G[3];
+        ok[u] = colour_cell2<H, CF>(g, threadIdx.x + u * TH, RING, COLOUR, ox, oy, G, L[u]);
+        const int l = L[u];
+        int m = 0, cnt = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const bool okl = g.per[a] || G[a] > 0, okh = g.per[a] || G[a] + 1 < g.n[a];
+            m |= (okl ? 1 : 0) << (2 * a);
+            m |= (okh ? 2 : 0) << (2 * a);
+            cnt += (okl ? 1 : 0) + (okh ? 1 : 0);
+        }
+        const R dg = -(R)cnt * ih2;
+        const R xq = s[l];
+        R xn[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            xn[a][0] = s[l - off[a]];
+            xn[a][1] = s[l + off[a]];
+        }
+        R Lx = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool okf = (m >> (2 * a + side)) & 1;
+                Lx += okf ? (xn[a][side] - xq) * ih2 : R(0);
+            }
+        nv[u] = xq + (sb[l] - Lx) / dg;
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u)
+        if (ok[u]) s[L[u]] = nv[u];
+}
+
+template <int SW, int NSW, typename R, class CF>
+__device__ inline void mac_sweeps(const GridD& g, R* s, R ih2, int ox, int oy)
+{
+    if constexpr (SW < NSW) {
+        constexpr int H = 2 * NSW, R0 = H - 1 - 2 * SW;
+        mac_half<0, R0, H, R, CF>(g, s, ih2, ox, oy);
+        __syncthreads();
+        mac_half<1, R0 - 1, H, R, CF>(g, s, ih2, ox, oy);
+        __syncthreads();
+        mac_sweeps<SW + 1, NSW, R, CF>(g, s, ih2, ox, oy);
+    }
+}
+
+template <typename R, class CF, int NSW, bool PRO>
+__global__ void __launch_bounds__(CF::THREADS)
+k_mac_sweepN(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* __restrict__ ba,
+             const R* __restrict__ pea, const GridD* __restrict__ gct, const long* __restrict__ oct)
+{
+    constexpr int H = 2 * NSW;
+    using T = Tile<2, H, CF>;
+    constexpr int TH = CF::THREADS;
+    TILE_ENTER(2, T);
+    const R* cur = cura + cell0;
+    R* next = nexta + cell0;
+    const R* b = ba + cell0;
+    R* s = reinterpret_cast<R*>(tile_lds);
+    GridD gc = g;
+    const R* pe = nullptr;
+    if (PRO) {
+        gc = bv_g2(v, gct, cav);
+        pe = pea + bv_o2(v, oct, cav);
+    }
+    {
+        constexpr int K = (T::NS + TH - 1) / TH;
+        const bool inner = ox - H >= 0 && ox + T::TX + H <= g.n[0] && oy - H >= 0 && oy + T::TY + H <= g.n[1];
+        R vx[K], vb[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int t = threadIdx.x + u * TH;
+            const int tt = t < T::NS ? t : 0;
+            const int i = ox - H + tt % T::SX, j = oy - H + tt / T::SX;
+            bool ok = true, ng = false;
+            int src[3] = {i, j, 0};
+            const long idx = inner ? cid(g, i, j, 0) : tile_src<2>(g, i, j, 0, ok, ng, src);
+            R x = cur[idx];
+            if (PRO) x = x + prolong_at<R>(gc, pe, src[0], src[1], R(1));
+            vx[u] = ok ? (ng ? -x : x) : R(0);
+            vb[u] = b[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int t = threadIdx.x + u * TH;
+            if (t < T::NS) {
+                s[t] = vx[u];
+                s[T::NS + t] = vb[u];
+            }
+        }
+    }
+    const R h = (R)g.h;
+    const R ih2 = R(1) / (h * h);
+    __syncthreads();
+    mac_sweeps<0, NSW, R, CF>(g, s, ih2, ox, oy);
+    for (int t = threadIdx.x; t < T::TX * T::TY; t += TH) {
+        const int rx = t % T::TX, ry = t / T::TX;
+        if (ox + rx >= g.n[0] || oy + ry >= g.n[1]) continue;
+        next[cid(g, ox + rx, oy + ry, 0)] = s[T::at(rx + H, ry + H, 0)];
+    }
+}
+
+using MacSweepTile = TileShape<32, 16, 1, 1024>;
 
 // ---------------------------------------------------------------------------
 // residual / operator application (FP64, halo 1) and residual + restriction
@@ -1286,9 +1414,26 @@ void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, 
 }
 
 template <typename R>
-void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b)
+void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int nsw, const R* pe,
+                      const GridD* gct, const long* oct)
 {
     BV vv = v;
+    if (L.gmax.dim == 2) {
+        // staged: nsw sweeps per launch, the prolongation folded in with pe
+        using CF = MacSweepTile;
+        const dim3 grid = tile_grid<2, CF>(c, L, vv);
+        if (nsw == 2) {
+            const size_t lds = sizeof(R) * 2 * Tile<2, 4, CF>::NS;
+            if (pe) k_mac_sweepN<R, CF, 2, true><<<grid, CF::THREADS, lds, c->s>>>(vv, cur, next, b, pe, gct, oct);
+            else k_mac_sweepN<R, CF, 2, false><<<grid, CF::THREADS, lds, c->s>>>(vv, cur, next, b, pe, gct, oct);
+        } else {
+            const size_t lds = sizeof(R) * 2 * Tile<2, 2, CF>::NS;
+            if (pe) k_mac_sweepN<R, CF, 1, true><<<grid, CF::THREADS, lds, c->s>>>(vv, cur, next, b, pe, gct, oct);
+            else k_mac_sweepN<R, CF, 1, false><<<grid, CF::THREADS, lds, c->s>>>(vv, cur, next, b, pe, gct, oct);
+        }
+        return;
+    }
+    if (pe) launch_prolong_cells<R>(c, L, v, gct, oct, 1, 1.0, pe, const_cast<R*>(cur));
     if (L.gmax.dim == 2) {
         const dim3 grid = tile_grid<2>(c, L, vv);
         k_mac_sweep<2, R><<<grid, TileCfg<2>::THREADS, sizeof(R) * Tile<2, 2>::NS, c->s>>>(vv, cur, next, b);
@@ -1303,7 +1448,8 @@ void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next
     template void launch_trb3<R>(Ctx*, const Level&, const BV&, const R*, bool, int, int, R*, const R*);             \
     template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*, int, int, \
                                      const R*, const GridD*, const long*);     \
-    template void launch_mac_sweep<R>(Ctx*, const Level&, const BV&, const R*, R*, const R*);                        \
+    template void launch_mac_sweep<R>(Ctx*, const Level&, const BV&, const R*, R*, const R*, int, const R*,         \
+                                      const GridD*, const long*);                                                   \
     template void launch_tresid_restr<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, bool, \
                                          const R*, const R*, R*, R*);
 HB_TILE_INST(double)

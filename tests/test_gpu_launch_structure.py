@@ -4,7 +4,8 @@ in one launch, data in LDS; HB_TAIL=0 turns it off), the fused sweeps (all
 colours, or in 2D both tensor components, of a sweep in one launch;
 HB_FUSE=0), and each candidate tile of the autotuned sweeps (HB_TILE=k
 forces candidate k; in 2D, candidates 3.. of the tensor sweep stage
-everything in LDS and run two sweeps per launch where the level allows it).
+everything in LDS and run two sweeps per launch where the level allows it,
+as do the nodal sweeps and the MAC sweeps).
 
 Each runs the same arithmetic per cell or node in the same order (the same
 Gauss-Seidel ordering, residual, restriction, prolongation and FP64
@@ -137,7 +138,8 @@ def test_autotuner_reports_candidate_tiles():
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {})
     cand = {"visc": {(64, 8, 256, 1), (32, 16, 256, 1), (128, 4, 256, 1), (32, 16, 512, 1), (32, 16, 512, 2),
                      (64, 16, 512, 1), (64, 16, 512, 2), (32, 16, 1024, 1), (32, 16, 1024, 2)},
-            "nodal": {(64, 16, 256, 1), (128, 8, 256, 1), (32, 32, 256, 1)}}
+            "nodal": {(64, 16, 256, 1), (128, 8, 256, 1), (32, 32, 256, 1), (64, 16, 256, 2), (128, 8, 256, 2),
+                      (32, 32, 256, 2)}}
     tv = [ctx.tile_config(hb.OP_VISC, l) for l in range(8)]
     tn = [ctx.tile_config(hb.OP_NODAL, l) for l in range(8)]
     _say("  tensor", tv, "nodal", tn)
@@ -147,11 +149,11 @@ def test_autotuner_reports_candidate_tiles():
     assert ctx.tile_config(hb.OP_MAC, 0) is None
     ctx.close()
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "2"})
-    assert ctx.tile_config(hb.OP_VISC, 0) == (128, 4, 256, 1) and ctx.tile_config(hb.OP_NODAL, 0) == (32, 32, 256, 1)
+    assert ctx.tile_config(hb.OP_VISC, 0) == (128, 4, 256, 1) and ctx.tile_config(hb.OP_NODAL, 0) == (32, 32, 256, 2)
     ctx.close()
     # walls only: the staged candidate runs two sweeps per launch
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "4"})
-    assert ctx.tile_config(hb.OP_VISC, 0) == (64, 16, 512, 2) and ctx.tile_config(hb.OP_NODAL, 0) == (128, 8, 256, 1)
+    assert ctx.tile_config(hb.OP_VISC, 0) == (64, 16, 512, 2) and ctx.tile_config(hb.OP_NODAL, 0) == (128, 8, 256, 2)
     ctx.close()
     # a periodic extent below 8 allows one sweep per launch only
     s = CASES["chan2d_8x32"]()
@@ -159,4 +161,5 @@ def test_autotuner_reports_candidate_tiles():
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "3", "HB_TAIL": "0"})
     assert ctx.tile_config(hb.OP_VISC, 0) == (32, 16, 512, 2)
     assert ctx.tile_config(hb.OP_VISC, 1) == (32, 16, 512, 1)
+    assert ctx.tile_config(hb.OP_NODAL, 0)[3] == 2 and ctx.tile_config(hb.OP_NODAL, 1)[3] == 1
     ctx.close()
