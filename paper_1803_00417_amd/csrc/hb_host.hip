@@ -363,11 +363,31 @@ static BV paired(BV v, const Level& P)
     return v;
 }
 
+// True when the last pre-smoothing launch of level L may also restrict the
+// residual: its tile halo (tensor problem 4 sweeps per launch + 1, MAC 2
+// sweeps + 1, sweeps at most 2) wraps a periodic axis once, so every
+// periodic extent must be at least that halo.
+static bool periodic_at_least(const Level& L, int n)
+{
+    for (const GridD& g : L.hg)
+        for (int a = 0; a < g.dim; ++a)
+            if (g.per[a] && g.n[a] < n) return false;
+    return true;
+}
+
+static bool res_fold_ok(const Level& L, int op)
+{
+    return periodic_at_least(L, op == HB_OP_MAC ? 2 * 2 + 1 : 4 * L.sweeps + 1);
+}
+
 // Smoothing sweeps on level l.  C (optional): the coarse level whose
 // correction the first sweep adds to the iterate first (2D, fused sweeps:
 // MAC problem, and tensor problem with a staged candidate).
+// RC (optional, 2D: MAC problem, and tensor problem with a staged
+// candidate): the coarse level into which the last launch restricts the
+// residual of its result (see res_fold_ok).
 template <typename R>
-static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C = nullptr)
+static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C = nullptr, Level* RC = nullptr)
 {
     using B = LB<R>;
     Level& L = m.L[l];
@@ -380,6 +400,9 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C =
             if (s == 0 && C)
                 launch_tsweep2<R>(c, L, paired(v, *C), tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n,
                                   B::x(*C), C->gall, C->o);
+            else if (s + n == sweeps && RC)
+                launch_tsweep2<R>(c, L, paired(v, *RC), tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile,
+                                  n, nullptr, RC->gall, RC->o, B::b(*RC), B::x(*RC));
             else
                 launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n);
             L.cur ^= 1;
@@ -402,6 +425,9 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C =
             const int n = (c->dim == 2 && pair && sweeps - s >= 2) ? 2 : 1;
             if (s == 0 && C)
                 launch_mac_sweep<R>(c, L, paired(v, *C), B::x(L), B::xo(L), B::b(L), n, B::x(*C), C->gall, C->o);
+            else if (s + n == sweeps && RC)
+                launch_mac_sweep<R>(c, L, paired(v, *RC), B::x(L), B::xo(L), B::b(L), n, nullptr, RC->gall, RC->o,
+                                    B::b(*RC), B::x(*RC));
             else
                 launch_mac_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L), n);
             L.cur ^= 1;
@@ -490,11 +516,17 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
         const bool pair = nu1 % 2 == 0 && nu2 % 2 == 0 && ((nu1 + nu2) / 2) % 2 == 0;
         const BV vpc = paired(v, C);                     // fine level, paired with the coarse one
         const BV vc = paired(all_view(c, C, c->act), L);  // coarse level, paired with the fine one
-        smooth<R>(c, m, l, nu1, pair);
+        // 2D MAC problem, and 2D tensor problem with a staged smoother: the
+        // residual restriction ends the last pre-smoothing launch
+        const bool rfold = c->dim == 2 && c->fuse && nu1 > 0 && res_fold_ok(L, m.op) &&
+                           ((m.op == HB_OP_VISC && sweep2_shape(L.tile).staged) || m.op == HB_OP_MAC);
+        smooth<R>(c, m, l, nu1, pair, nullptr, rfold ? &C : nullptr);
         if (m.op == HB_OP_VISC) {
-            launch_tresid_restr<R>(c, L, vpc, C.gall, C.o, tcoef<R>(m, l), l == 0, B::x(L), B::b(L), B::b(C), B::x(C));
+            if (!rfold)
+                launch_tresid_restr<R>(c, L, vpc, C.gall, C.o, tcoef<R>(m, l), l == 0, B::x(L), B::b(L), B::b(C),
+                                       B::x(C));
         } else if (m.op == HB_OP_MAC) {
-            launch_mac_resid_restrict<R>(c, C, vc, L.gall, L.o, B::x(L), B::b(L), B::b(C), B::x(C));
+            if (!rfold) launch_mac_resid_restrict<R>(c, C, vc, L.gall, L.o, B::x(L), B::b(L), B::b(C), B::x(C));
         } else {
             launch_nodal_resid<R>(c, L, v, B::x(L), B::b(L), B::r(L), -1);
             launch_nodal_restrict<R>(c, C, vc, L.gall, L.o, B::r(L), B::b(C), B::x(C));

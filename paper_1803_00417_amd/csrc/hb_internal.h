@@ -382,9 +382,13 @@ struct SweepShape {
     bool staged;
 };
 constexpr int kSweep2Cands = 6;
+// bc/xc (optional): the launch ends a pre-smoothing and also restricts the
+// residual of its result to the coarse level (coarse b, coarse x = 0; v
+// then also carries the coarse level), as launch_tresid_restr would after it.
 template <typename R>
 void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b,
-                    int tile, int nsw, const R* pe = nullptr, const GridD* gct = nullptr, const long* oct = nullptr);
+                    int tile, int nsw, const R* pe = nullptr, const GridD* gct = nullptr, const long* oct = nullptr,
+                    R* bc = nullptr, R* xc = nullptr);
 SweepShape sweep2_shape(int tile);
 size_t sweep2_lds(int tile, int nsw);
 void sweep2_allow_lds(size_t bytes);
@@ -404,10 +408,13 @@ template <typename R> void launch_mac_rb(Ctx* c, const Level& L, const BV& v, in
 // both colours of a red-black sweep from cur into next (hb_tile.hip)
 // (2D: nsw (1 or 2) sweeps per launch, every periodic extent at least 2 nsw;
 // pe: coarse iterate whose prolongation is added to cur first, v then also
-// carrying the coarse level, gct/oct its tables)
+// carrying the coarse level, gct/oct its tables; bc/xc: the launch ends a
+// pre-smoothing and restricts the residual to the coarse level, every
+// periodic extent then at least 2 nsw + 1)
 template <typename R>
 void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int nsw = 1,
-                      const R* pe = nullptr, const GridD* gct = nullptr, const long* oct = nullptr);
+                      const R* pe = nullptr, const GridD* gct = nullptr, const long* oct = nullptr,
+                      R* bc = nullptr, R* xc = nullptr);
 // one thread per coarse cell: vc covers the coarse level, gf / of_ give the
 // fine grid and offsets of the same cavities
 template <typename R>

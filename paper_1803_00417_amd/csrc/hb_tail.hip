@@ -28,8 +28,14 @@
 
 namespace hb {
 
-constexpr int kTailThreads = 512;
-constexpr int kMacTailKC = 4;   // MAC tail: cells of one colour per thread
+constexpr int kTailThreads = 512;   // tensor tail
+// MAC tail: threads and cells of one colour per thread (2D: 1024 x 2, 3D:
+// 512 x 4, where 1024 threads would spill); both cover 4096 cells
+template <int DIM> struct MacTail {
+    static constexpr int TH = DIM == 2 ? 1024 : 512, KC = DIM == 2 ? 2 : 4;
+};
+constexpr long kMacTailCells = 2L * MacTail<2>::TH * MacTail<2>::KC;
+static_assert(kMacTailCells == 2L * MacTail<3>::TH * MacTail<3>::KC, "same first-level limit");
 
 // LDS block of one level: `dim` components of (n0+2)(n1+2)[(n2+2)] cells
 struct TailLay {
@@ -401,8 +407,8 @@ __device__ inline R tail_mac_lap(const GridD& g, const TailLay& L, const R* X, c
     return s * ihh;
 }
 
-template <int DIM, typename R, int KC>
-__global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
+template <int DIM, typename R, int KC = MacTail<DIM>::KC, int TH = MacTail<DIM>::TH>
+__global__ void __launch_bounds__(TH) k_mac_tail(TailArgs A)
 {
     const int cav = blockIdx.x, tid = threadIdx.x;
     if (A.act && !A.act[cav]) return;
@@ -413,13 +419,13 @@ __global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
     for (int i = 0; i < nl; ++i) {
         const TailLevel& T = P->lv[i];
         R* X = lds + T.xoff;
-        for (int t = tid; t < T.ns; t += kTailThreads) X[t] = R(0);
+        for (int t = tid; t < T.ns; t += TH) X[t] = R(0);
     }
     {
         const TailLevel& T = P->lv[0];
         const R* gb = reinterpret_cast<const R*>(A.b) + P->o0;
         R* B = lds + T.boff;
-        for (int t = tid; t < T.nc; t += kTailThreads) B[t] = gb[t];
+        for (int t = tid; t < T.nc; t += TH) B[t] = gb[t];
     }
     __syncthreads();
 
@@ -443,7 +449,7 @@ __global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
         for (int colour = 0; colour < 2; ++colour)
 #pragma unroll
             for (int u = 0; u < KC; ++u) {
-                const int t0 = tid + u * kTailThreads;
+                const int t0 = tid + u * TH;
                 on[colour][u] = t0 < H;
                 const int t = t0 < H ? t0 : 0;
                 const int px = t % hx, j = (t / hx) % g.n[1], k = t / (hx * g.n[1]);
@@ -504,7 +510,7 @@ __global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
         const int Nc = P->lv[i + 1].nc;
         R* Bc = lds + P->lv[i + 1].boff;
         constexpr int nch = 1 << DIM;
-        for (int t = tid; t < Nc; t += kTailThreads) {
+        for (int t = tid; t < Nc; t += TH) {
             const int C[3] = {t % gc.n[0], (t / gc.n[0]) % gc.n[1], t / (gc.n[0] * gc.n[1])};
             R sum = 0;
 #pragma unroll
@@ -526,7 +532,7 @@ __global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
         const TailLay L = tail_lay(g);
         const R* B = lds + P->lv[i].boff;
         R* X = lds + P->lv[i].xoff;
-        for (int r = tid; r < cd.N; r += kTailThreads) {
+        for (int r = tid; r < cd.N; r += TH) {
             const double* row = A.Ainv + cd.aoff + (long)r * cd.N;
             double s = 0.0;
             for (int jj = 0; jj < cd.N; ++jj) s += row[jj] * (double)B[jj];
@@ -545,7 +551,7 @@ __global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
         R* X = lds + P->lv[i].xoff;
         const R* E = lds + P->lv[i + 1].xoff;
         const int Nc = P->lv[i + 1].nc;
-        for (int t = tid; t < Nc; t += kTailThreads) {
+        for (int t = tid; t < Nc; t += TH) {
             const int C[3] = {t % gc.n[0], (t / gc.n[0]) % gc.n[1], t / (gc.n[0] * gc.n[1])};
             int src[3][3];
 #pragma unroll
@@ -604,7 +610,7 @@ __global__ void __launch_bounds__(kTailThreads) k_mac_tail(TailArgs A)
         const int N = P->lv[0].nc;
         const R* X = lds + P->lv[0].xoff;
         R* gx = reinterpret_cast<R*>(A.x) + P->o0;
-        for (int t = tid; t < N; t += kTailThreads)
+        for (int t = tid; t < N; t += TH)
             gx[t] = X[L.at(t % g.n[0], (t / g.n[0]) % g.n[1], t / (g.n[0] * g.n[1]))];
     }
 }
@@ -833,7 +839,8 @@ __global__ void __launch_bounds__(kNodalTailThreads) k_nodal_tail(TailArgs A)
 // and nodal problems, one residual array of the first level).  Returns the
 // LDS bytes for storage size elem, or SIZE_MAX when the first level has
 // more unknowns per colour than the kernel's threads cover (tensor: one cell
-// per thread, MAC: kMacTailKC, nodal: kNodalTailKN nodes).
+// per thread, MAC: kMacTailCells at the first level, nodal: kNodalTailKN
+// nodes).
 size_t tail_plan(int op, const std::vector<GridD>& gl, const std::vector<long>& gofs, long o0, size_t elem,
                  TailPlan* out)
 {
@@ -849,7 +856,7 @@ size_t tail_plan(int op, const std::vector<GridD>& gl, const std::vector<long>& 
         return nodal ? (long)nnode(g, 0) * nnode(g, 1) * nnode(g, 2) : ncells(g);
     };
     const long limit = nodal ? (1L << d) * kNodalTailThreads * kNodalTailKN
-                             : 2L * kTailThreads * (visc ? 1 : kMacTailKC);
+                             : (visc ? 2L * kTailThreads : kMacTailCells);
     if (gl.size() > (size_t)kMaxTail || (gl.size() > 1 && count(gl[0]) > limit)) return SIZE_MAX;
     const int nc = visc ? d : 1;
     long o = 0;
@@ -898,8 +905,8 @@ void launch_mac_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds, 
     A.Ainv = m.Ainv;
     A.act = act;
     A.scb = c->sc;
-    if (c->dim == 2) k_mac_tail<2, R, kMacTailKC><<<c->nb, kTailThreads, lds, c->s>>>(A);
-    else k_mac_tail<3, R, kMacTailKC><<<c->nb, kTailThreads, lds, c->s>>>(A);
+    if (c->dim == 2) k_mac_tail<2, R><<<c->nb, MacTail<2>::TH, lds, c->s>>>(A);
+    else k_mac_tail<3, R><<<c->nb, MacTail<3>::TH, lds, c->s>>>(A);
 }
 
 template <typename R>
@@ -940,13 +947,13 @@ void launch_visc_tail(Ctx* c, const MG& m, int lt, int nu1, int nu2, size_t lds,
 // allow the tail kernels dynamic LDS up to `bytes`
 void tail_allow_lds(size_t bytes)
 {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<2, double, kMacTailKC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<2, double>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<3, double, kMacTailKC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<3, double>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<2, float, kMacTailKC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<2, float>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<3, float, kMacTailKC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mac_tail<3, float>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nodal_tail<2, double>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

@@ -652,12 +652,13 @@ __device__ inline void staged_half(const GridD& g, R* s, R dt, R ihh, int ox, in
     }
 }
 
-// sweep SW of NSW: its four half steps, each followed by a barrier
-template <int SW, int NSW, bool FINE, typename R, class CF>
+// sweep SW of NSW on a tile with halo H: its four half steps, each
+// followed by a barrier (rings H - 1 - 4 SW down to H - 4 - 4 SW)
+template <int SW, int NSW, int H, bool FINE, typename R, class CF>
 __device__ inline void staged_sweeps(const GridD& g, R* s, R dt, R ihh, int ox, int oy)
 {
     if constexpr (SW < NSW) {
-        constexpr int H = 4 * NSW, R0 = H - 1 - 4 * SW;
+        constexpr int R0 = H - 1 - 4 * SW;
         staged_half<0, 0, R0, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
         __syncthreads();
         staged_half<0, 1, R0 - 1, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
@@ -666,17 +667,23 @@ __device__ inline void staged_sweeps(const GridD& g, R* s, R dt, R ihh, int ox, 
         __syncthreads();
         staged_half<1, 1, R0 - 3, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
         __syncthreads();
-        staged_sweeps<SW + 1, NSW, FINE, R, CF>(g, s, dt, ihh, ox, oy);
+        staged_sweeps<SW + 1, NSW, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
     }
 }
 
-template <bool FINE, typename R, class CF, int NSW, bool PRO>
+// RES: the launch ends a pre-smoothing; it also forms the residual of the
+// tile's cells and restricts it to the coarse level (coarse b = mean of the
+// 2x2 children, coarse x = 0), as the residual-restriction kernel would
+// after it.  The sweeps then run one ring wider (halo 4 NSW + 1, last half
+// step on ring 1), so every value the residual reads is final.
+template <bool FINE, typename R, class CF, int NSW, bool PRO, bool RES>
 __global__ void __launch_bounds__(CF::THREADS)
 k_tsweepN(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, const R* __restrict__ xcura,
           R* __restrict__ xnexta, const R* __restrict__ ba, const R* __restrict__ pea, const GridD* __restrict__ gct,
-          const long* __restrict__ oct)
+          const long* __restrict__ oct, R* __restrict__ bca, R* __restrict__ xca)
 {
-    constexpr int H = 4 * NSW;
+    static_assert(!(PRO && RES), "a launch either starts a post-smoothing or ends a pre-smoothing");
+    constexpr int H = 4 * NSW + (RES ? 1 : 0);
     using T = Tile<2, H, CF>;
     constexpr int TH = CF::THREADS;
     TILE_ENTER(2, T);
@@ -689,21 +696,67 @@ k_tsweepN(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     R* s = reinterpret_cast<R*>(tile_lds);
     GridD gc = g;
     const R* pe = nullptr;
-    if (PRO) {
-        gc = bv_g2(v, gct, cav);
-        pe = pea + 2 * bv_o2(v, oct, cav);
-    }
+    if (PRO || RES) gc = bv_g2(v, gct, cav);
+    if (PRO) pe = pea + 2 * bv_o2(v, oct, cav);
     fill_staged<FINE, H, R, CF, PRO>(g, xcur, b, coef, s, ox, oy, N, pe, gc);
     const R h = (R)g.h;
     const R ihh = R(1) / (h * h);
     __syncthreads();
-    staged_sweeps<0, NSW, FINE, R, CF>(g, s, dt, ihh, ox, oy);
+    staged_sweeps<0, NSW, H, FINE, R, CF>(g, s, dt, ihh, ox, oy);
     for (int t = threadIdx.x; t < 2 * T::TX * T::TY; t += TH) {
         const int q = t / (T::TX * T::TY), r = t - q * (T::TX * T::TY);
         const int rx = r % T::TX, ry = r / T::TX;
         const int G[2] = {ox + rx, oy + ry};
         if (G[0] >= g.n[0] || G[1] >= g.n[1]) continue;
         xnext[q * N + cid(g, G[0], G[1], 0)] = s[q * T::NS + T::at(rx + H, ry + H, 0)];
+    }
+    if constexpr (RES) {
+        // residual of the tile's cells (both components), then the 2x2 means
+        constexpr int NT = T::TX * T::TY;
+        R* rr = s + (FINE ? 5 : 6) * T::NS;
+        const R* e = s + ST_E * T::NS;
+        const R* fx = s + ST_FX * T::NS;
+        const R* fy = s + ST_FY * T::NS;
+        for (int t = threadIdx.x; t < NT; t += TH) {
+            const int rx = t % T::TX, ry = t / T::TX;
+            const int G[3] = {ox + rx, oy + ry, 0};
+            if (G[0] >= g.n[0] || G[1] >= g.n[1]) continue;
+            const int l = T::at(rx + H, ry + H, 0);
+            R bf[4];
+            if (!FINE) {
+                bf[0] = fx[l];
+                bf[1] = fx[l + 1];
+                bf[2] = fy[l];
+                bf[3] = fy[l + T::SX];
+            }
+            const int wm = wall_mask<2>(g, G);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const R vd = visc_div_ih<2, FINE, R>(bf, s, T::NS, T::SX, T::SX * T::SY, e, c, wm, l, dt, ihh, nullptr);
+                const R Ax = s[c * T::NS + l] - dt * vd;
+                rr[c * NT + t] = s[(ST_B0 + c) * T::NS + l] - Ax;
+            }
+        }
+        __syncthreads();
+        R* bcoarse = bca + 2 * bv_o2(v, oct, cav);
+        R* xcoarse = xca + 2 * bv_o2(v, oct, cav);
+        const long Nc = ncells(gc);
+        constexpr int CX = T::TX / 2, CY = T::TY / 2;
+        for (int t = threadIdx.x; t < CX * CY; t += TH) {
+            const int cx = t % CX, cy = t / CX;
+            const int C[2] = {ox / 2 + cx, oy / 2 + cy};
+            if (C[0] >= gc.n[0] || C[1] >= gc.n[1]) continue;
+            const long qc = cid(gc, C[0], C[1], 0);
+            for (int c = 0; c < 2; ++c) {
+                R sum = 0;
+                for (int bits = 0; bits < 4; ++bits) {
+                    const int fxc = 2 * cx + (bits & 1), fyc = 2 * cy + ((bits >> 1) & 1);
+                    sum += rr[c * NT + fyc * T::TX + fxc];
+                }
+                bcoarse[c * Nc + qc] = sum / R(4);
+                xcoarse[c * Nc + qc] = R(0);
+            }
+        }
     }
 }
 
@@ -863,25 +916,31 @@ __device__ inline void mac_half(const GridD& g, R* s, R ih2, int ox, int oy)
         if (ok[u]) s[L[u]] = nv[u];
 }
 
-template <int SW, int NSW, typename R, class CF>
+template <int SW, int NSW, int H, typename R, class CF>
 __device__ inline void mac_sweeps(const GridD& g, R* s, R ih2, int ox, int oy)
 {
     if constexpr (SW < NSW) {
-        constexpr int H = 2 * NSW, R0 = H - 1 - 2 * SW;
+        constexpr int R0 = H - 1 - 2 * SW;
         mac_half<0, R0, H, R, CF>(g, s, ih2, ox, oy);
         __syncthreads();
         mac_half<1, R0 - 1, H, R, CF>(g, s, ih2, ox, oy);
         __syncthreads();
-        mac_sweeps<SW + 1, NSW, R, CF>(g, s, ih2, ox, oy);
+        mac_sweeps<SW + 1, NSW, H, R, CF>(g, s, ih2, ox, oy);
     }
 }
 
-template <typename R, class CF, int NSW, bool PRO>
+// RES: the launch ends a pre-smoothing and also restricts the residual to
+// the coarse level (coarse b = mean of the children's b - L x, coarse x = 0,
+// as the residual-restriction kernel); the sweeps run one ring wider (halo
+// 2 NSW + 1) so the values the residual reads are final.
+template <typename R, class CF, int NSW, bool PRO, bool RES>
 __global__ void __launch_bounds__(CF::THREADS)
 k_mac_sweepN(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* __restrict__ ba,
-             const R* __restrict__ pea, const GridD* __restrict__ gct, const long* __restrict__ oct)
+             const R* __restrict__ pea, const GridD* __restrict__ gct, const long* __restrict__ oct,
+             R* __restrict__ bca, R* __restrict__ xca)
 {
-    constexpr int H = 2 * NSW;
+    static_assert(!(PRO && RES), "a launch either starts a post-smoothing or ends a pre-smoothing");
+    constexpr int H = 2 * NSW + (RES ? 1 : 0);
     using T = Tile<2, H, CF>;
     constexpr int TH = CF::THREADS;
     TILE_ENTER(2, T);
@@ -891,10 +950,8 @@ k_mac_sweepN(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* _
     R* s = reinterpret_cast<R*>(tile_lds);
     GridD gc = g;
     const R* pe = nullptr;
-    if (PRO) {
-        gc = bv_g2(v, gct, cav);
-        pe = pea + bv_o2(v, oct, cav);
-    }
+    if (PRO || RES) gc = bv_g2(v, gct, cav);
+    if (PRO) pe = pea + bv_o2(v, oct, cav);
     {
         constexpr int K = (T::NS + TH - 1) / TH;
         const bool inner = ox - H >= 0 && ox + T::TX + H <= g.n[0] && oy - H >= 0 && oy + T::TY + H <= g.n[1];
@@ -924,11 +981,43 @@ k_mac_sweepN(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* _
     const R h = (R)g.h;
     const R ih2 = R(1) / (h * h);
     __syncthreads();
-    mac_sweeps<0, NSW, R, CF>(g, s, ih2, ox, oy);
+    mac_sweeps<0, NSW, H, R, CF>(g, s, ih2, ox, oy);
     for (int t = threadIdx.x; t < T::TX * T::TY; t += TH) {
         const int rx = t % T::TX, ry = t / T::TX;
         if (ox + rx >= g.n[0] || oy + ry >= g.n[1]) continue;
         next[cid(g, ox + rx, oy + ry, 0)] = s[T::at(rx + H, ry + H, 0)];
+    }
+    if constexpr (RES) {
+        R* bcoarse = bca + bv_o2(v, oct, cav);
+        R* xcoarse = xca + bv_o2(v, oct, cav);
+        const R* sb = s + T::NS;
+        const int off[2] = {1, T::SX};
+        constexpr int CX = T::TX / 2, CY = T::TY / 2;
+        for (int t = threadIdx.x; t < CX * CY; t += TH) {
+            const int cx = t % CX, cy = t / CX;
+            const int C[2] = {ox / 2 + cx, oy / 2 + cy};
+            if (C[0] >= gc.n[0] || C[1] >= gc.n[1]) continue;
+            R sum = 0;
+#pragma unroll
+            for (int bits = 0; bits < 4; ++bits) {
+                const int fx = 2 * cx + (bits & 1), fy = 2 * cy + ((bits >> 1) & 1);
+                const int G[2] = {ox + fx, oy + fy};
+                const int l = T::at(fx + H, fy + H, 0);
+                const R xc = s[l];
+                R lap = 0;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const bool okl = g.per[a] || G[a] > 0, okh = g.per[a] || G[a] + 1 < g.n[a];
+                    const R Fhi = okh ? s[l + off[a]] - xc : R(0);
+                    const R Flo = okl ? xc - s[l - off[a]] : R(0);
+                    lap += Fhi - Flo;
+                }
+                sum += sb[l] - lap * ih2;
+            }
+            const long qc = cid(gc, C[0], C[1], 0);
+            bcoarse[qc] = sum / R(4);
+            xcoarse[qc] = R(0);
+        }
     }
 }
 
@@ -1274,18 +1363,24 @@ void launch_tresid_restr(Ctx* c, const Level& L, const BV& v, const GridD* gc, c
     }
 }
 
-template <bool FINE, bool PRO, typename R, class CF, int NSW>
-static void staged_launch(Ctx* c, bool timed, double bytes, dim3 grid, const BV& vv, const R* coef, const R* xcur,
-                          R* xnext, const R* b, const R* pe, const GridD* gct, const long* oct)
+// dynamic LDS of a staged launch
+template <bool FINE, typename R, class CF, int NSW, bool RES>
+constexpr size_t staged_lds()
 {
-    const size_t lds = sizeof(R) * (FINE ? 5 : 6) * Tile<2, 4 * NSW, CF>::NS;
-    tlaunch(c, timed, bytes, k_tsweepN<FINE, R, CF, NSW, PRO>, grid, dim3(CF::THREADS), lds, vv, coef,
-            (const double*)c->sc, xcur, xnext, b, pe, gct, oct);
+    return sizeof(R) * ((FINE ? 5 : 6) * Tile<2, 4 * NSW + (RES ? 1 : 0), CF>::NS + (RES ? 2 * CF::TX * CF::TY : 0));
+}
+
+template <bool FINE, bool PRO, bool RES, typename R, class CF, int NSW>
+static void staged_launch(Ctx* c, bool timed, double bytes, dim3 grid, const BV& vv, const R* coef, const R* xcur,
+                          R* xnext, const R* b, const R* pe, const GridD* gct, const long* oct, R* bc, R* xc)
+{
+    tlaunch(c, timed, bytes, k_tsweepN<FINE, R, CF, NSW, PRO, RES>, grid, dim3(CF::THREADS),
+            staged_lds<FINE, R, CF, NSW, RES>(), vv, coef, (const double*)c->sc, xcur, xnext, b, pe, gct, oct, bc, xc);
 }
 
 template <bool FINE, typename R, class CAND>
 static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b,
-                         int nsw, const R* pe, const GridD* gct, const long* oct)
+                         int nsw, const R* pe, const GridD* gct, const long* oct, R* bc, R* xc)
 {
     using CF = typename CAND::CF;
     const bool timed = FINE && kt_take(c);
@@ -1296,40 +1391,45 @@ static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, con
     // once; with a folded prolongation also both components of the coarse
     // iterate (N/4 cells each)
     const double N = level_cells(L);
-    const double bytes = sizeof(R) * (2.0 * N + N + 2.0 * N + 2.0 * N + (pe ? 2.0 * N / 4.0 : 0.0));
+    const double bytes =
+        sizeof(R) * (2.0 * N + N + 2.0 * N + 2.0 * N + (pe ? 2.0 * N / 4.0 : 0.0) + (bc ? 4.0 * N / 4.0 : 0.0));
     if constexpr (!CAND::STAGED) {
         using T = Tile<2, 4, CF>;
         const size_t lds = sizeof(R) * (FINE ? 3 : 2) * T::NS;
         if (pe) launch_prolong_cells<R>(c, L, v, gct, oct, 2, -1.0, pe, const_cast<R*>(xcur));
         tlaunch(c, timed, bytes, k_tsweep2<FINE, R, CF>, grid, dim3(CF::THREADS), lds, vv, coef, (const double*)c->sc,
                 xcur, xnext, b);
+        if (bc) launch_tresid_restr<R>(c, L, v, gct, oct, coef, FINE, xnext, b, bc, xc);
     } else if (CAND::NSW >= 2 && nsw == 2) {
-        if (pe) staged_launch<FINE, true, R, CF, 2>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct);
-        else staged_launch<FINE, false, R, CF, 2>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct);
+        if (pe) staged_launch<FINE, true, false, R, CF, 2>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct, bc, xc);
+        else if (bc) staged_launch<FINE, false, true, R, CF, 2>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct, bc, xc);
+        else staged_launch<FINE, false, false, R, CF, 2>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct, bc, xc);
     } else {
-        if (pe) staged_launch<FINE, true, R, CF, 1>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct);
-        else staged_launch<FINE, false, R, CF, 1>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct);
+        if (pe) staged_launch<FINE, true, false, R, CF, 1>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct, bc, xc);
+        else if (bc) staged_launch<FINE, false, true, R, CF, 1>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct, bc, xc);
+        else staged_launch<FINE, false, false, R, CF, 1>(c, timed, bytes, grid, vv, coef, xcur, xnext, b, pe, gct, oct, bc, xc);
     }
 }
 
 template <bool FINE, typename R, size_t... I>
 static void tsweep2_pick(Ctx* c, const Level& L, const BV& v, const R* coef, const R* xcur, R* xnext, const R* b,
-                         int k, int nsw, const R* pe, const GridD* gct, const long* oct, std::index_sequence<I...>)
+                         int k, int nsw, const R* pe, const GridD* gct, const long* oct, R* bc, R* xc,
+                         std::index_sequence<I...>)
 {
     ((k == (int)I ? tsweep2_impl<FINE, R, std::tuple_element_t<I, Sweep2Cands>>(c, L, v, coef, xcur, xnext, b, nsw, pe,
-                                                                                gct, oct)
+                                                                                gct, oct, bc, xc)
                   : void()),
      ...);
 }
 
 template <typename R>
 void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, const R* xcur, R* xnext, const R* b,
-                    int tile, int nsw, const R* pe, const GridD* gct, const long* oct)
+                    int tile, int nsw, const R* pe, const GridD* gct, const long* oct, R* bc, R* xc)
 {
     const int k = tile >= 0 && tile < kSweep2Cands ? tile : 0;
     constexpr auto seq = std::make_index_sequence<kSweep2Cands>{};
-    if (fine) tsweep2_pick<true, R>(c, L, v, coef, xcur, xnext, b, k, nsw, pe, gct, oct, seq);
-    else tsweep2_pick<false, R>(c, L, v, coef, xcur, xnext, b, k, nsw, pe, gct, oct, seq);
+    if (fine) tsweep2_pick<true, R>(c, L, v, coef, xcur, xnext, b, k, nsw, pe, gct, oct, bc, xc, seq);
+    else tsweep2_pick<false, R>(c, L, v, coef, xcur, xnext, b, k, nsw, pe, gct, oct, bc, xc, seq);
 }
 
 template <size_t... I>
@@ -1352,10 +1452,12 @@ SweepShape sweep2_shape(int k) { return sweep2_shape_of(k, std::make_index_seque
 template <class CF, typename R, int NSW>
 static void allow_one(size_t bytes)
 {
-    const void* k[4] = {reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, NSW, false>),
-                        reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, NSW, false>),
-                        reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, NSW, true>),
-                        reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, NSW, true>)};
+    const void* k[6] = {reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, NSW, false, false>),
+                        reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, NSW, false, false>),
+                        reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, NSW, true, false>),
+                        reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, NSW, true, false>),
+                        reinterpret_cast<const void*>(&k_tsweepN<true, R, CF, NSW, false, true>),
+                        reinterpret_cast<const void*>(&k_tsweepN<false, R, CF, NSW, false, true>)};
     for (const void* f : k) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -1379,15 +1481,14 @@ static void allow_all(size_t bytes, std::index_sequence<I...>)
 void sweep2_allow_lds(size_t bytes) { allow_all(bytes, std::make_index_sequence<kSweep2Cands>{}); }
 
 // dynamic LDS bytes of candidate k running nsw sweeps per launch (FP64,
-// coarse level: the larger case)
+// coarse level, with the residual epilogue: the largest case)
 template <size_t... I>
 static size_t sweep2_lds_of(int k, int nsw, std::index_sequence<I...>)
 {
     size_t out = 0;
     ((k == (int)I ? (void)(out = std::tuple_element_t<I, Sweep2Cands>::STAGED
-                                     ? sizeof(double) * 6 *
-                                           (nsw == 2 ? Tile<2, 8, typename std::tuple_element_t<I, Sweep2Cands>::CF>::NS
-                                                     : Tile<2, 4, typename std::tuple_element_t<I, Sweep2Cands>::CF>::NS)
+                                     ? (nsw == 2 ? staged_lds<false, double, typename std::tuple_element_t<I, Sweep2Cands>::CF, 2, true>()
+                                                 : staged_lds<false, double, typename std::tuple_element_t<I, Sweep2Cands>::CF, 1, true>())
                                      : sizeof(double) * 3 *
                                            Tile<2, 4, typename std::tuple_element_t<I, Sweep2Cands>::CF>::NS)
                   : void()),
@@ -1415,21 +1516,26 @@ void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, 
 
 template <typename R>
 void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int nsw, const R* pe,
-                      const GridD* gct, const long* oct)
+                      const GridD* gct, const long* oct, R* bc, R* xc)
 {
     BV vv = v;
     if (L.gmax.dim == 2) {
-        // staged: nsw sweeps per launch, the prolongation folded in with pe
+        // staged: nsw sweeps per launch, the prolongation folded in with pe,
+        // the residual restriction with bc
         using CF = MacSweepTile;
         const dim3 grid = tile_grid<2, CF>(c, L, vv);
+        auto go = [&](auto kern, int halo) {
+            kern<<<grid, CF::THREADS, sizeof(R) * 2 * (CF::TX + 2 * halo) * (CF::TY + 2 * halo), c->s>>>(
+                vv, cur, next, b, pe, gct, oct, bc, xc);
+        };
         if (nsw == 2) {
-            const size_t lds = sizeof(R) * 2 * Tile<2, 4, CF>::NS;
-            if (pe) k_mac_sweepN<R, CF, 2, true><<<grid, CF::THREADS, lds, c->s>>>(vv, cur, next, b, pe, gct, oct);
-            else k_mac_sweepN<R, CF, 2, false><<<grid, CF::THREADS, lds, c->s>>>(vv, cur, next, b, pe, gct, oct);
+            if (pe) go(k_mac_sweepN<R, CF, 2, true, false>, 4);
+            else if (bc) go(k_mac_sweepN<R, CF, 2, false, true>, 5);
+            else go(k_mac_sweepN<R, CF, 2, false, false>, 4);
         } else {
-            const size_t lds = sizeof(R) * 2 * Tile<2, 2, CF>::NS;
-            if (pe) k_mac_sweepN<R, CF, 1, true><<<grid, CF::THREADS, lds, c->s>>>(vv, cur, next, b, pe, gct, oct);
-            else k_mac_sweepN<R, CF, 1, false><<<grid, CF::THREADS, lds, c->s>>>(vv, cur, next, b, pe, gct, oct);
+            if (pe) go(k_mac_sweepN<R, CF, 1, true, false>, 2);
+            else if (bc) go(k_mac_sweepN<R, CF, 1, false, true>, 3);
+            else go(k_mac_sweepN<R, CF, 1, false, false>, 2);
         }
         return;
     }
@@ -1447,9 +1553,9 @@ void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next
     template void launch_tsmooth<R>(Ctx*, const Level&, const BV&, const R*, bool, int, const R*, R*, const R*);     \
     template void launch_trb3<R>(Ctx*, const Level&, const BV&, const R*, bool, int, int, R*, const R*);             \
     template void launch_tsweep2<R>(Ctx*, const Level&, const BV&, const R*, bool, const R*, R*, const R*, int, int, \
-                                     const R*, const GridD*, const long*);     \
+                                     const R*, const GridD*, const long*, R*, R*);  \
     template void launch_mac_sweep<R>(Ctx*, const Level&, const BV&, const R*, R*, const R*, int, const R*,         \
-                                      const GridD*, const long*);                                                   \
+                                      const GridD*, const long*, R*, R*);                                           \
     template void launch_tresid_restr<R>(Ctx*, const Level&, const BV&, const GridD*, const long*, const R*, bool, \
                                          const R*, const R*, R*, R*);
 HB_TILE_INST(double)
