@@ -365,8 +365,8 @@ static BV paired(BV v, const Level& P)
 
 // True when the last pre-smoothing launch of level L may also restrict the
 // residual: its tile halo (tensor problem 4 sweeps per launch + 1, MAC 2
-// sweeps + 1, sweeps at most 2) wraps a periodic axis once, so every
-// periodic extent must be at least that halo.
+// sweeps + 1, nodal 4 sweeps + 2; sweeps at most 2) wraps a periodic axis
+// once, so every periodic extent must be at least that halo.
 static bool periodic_at_least(const Level& L, int n)
 {
     for (const GridD& g : L.hg)
@@ -377,13 +377,13 @@ static bool periodic_at_least(const Level& L, int n)
 
 static bool res_fold_ok(const Level& L, int op)
 {
-    return periodic_at_least(L, op == HB_OP_MAC ? 2 * 2 + 1 : 4 * L.sweeps + 1);
+    return periodic_at_least(L, op == HB_OP_MAC ? 2 * 2 + 1 : 4 * L.sweeps + (op == HB_OP_NODAL ? 2 : 1));
 }
 
 // Smoothing sweeps on level l.  C (optional): the coarse level whose
 // correction the first sweep adds to the iterate first (2D, fused sweeps:
-// MAC problem, and tensor problem with a staged candidate).
-// RC (optional, 2D: MAC problem, and tensor problem with a staged
+// MAC and nodal problems, tensor problem with a staged candidate).
+// RC (optional, 2D: MAC and nodal problems, tensor problem with a staged
 // candidate): the coarse level into which the last launch restricts the
 // residual of its result (see res_fold_ok).
 template <typename R>
@@ -438,7 +438,14 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C =
             // all colours of a sweep in one launch (two in 3D) into the other
             // buffer; 2D: two sweeps per launch with `pair` where the level allows
             const int n = (pair && L.sweeps == 2 && sweeps - s >= 2) ? 2 : 1;
-            launch_nodal_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L), L.tile, n);
+            if (s == 0 && C)
+                launch_nodal_sweep<R>(c, L, paired(v, *C), B::x(L), B::xo(L), B::b(L), L.tile, n, B::x(*C), C->gall,
+                                      C->o);
+            else if (s + n == sweeps && RC)
+                launch_nodal_sweep<R>(c, L, paired(v, *RC), B::x(L), B::xo(L), B::b(L), L.tile, n, nullptr, RC->gall,
+                                      RC->o, B::b(*RC), B::x(*RC));
+            else
+                launch_nodal_sweep<R>(c, L, v, B::x(L), B::xo(L), B::b(L), L.tile, n);
             L.cur ^= 1;
             s += n - 1;
         } else {
@@ -516,10 +523,10 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
         const bool pair = nu1 % 2 == 0 && nu2 % 2 == 0 && ((nu1 + nu2) / 2) % 2 == 0;
         const BV vpc = paired(v, C);                     // fine level, paired with the coarse one
         const BV vc = paired(all_view(c, C, c->act), L);  // coarse level, paired with the fine one
-        // 2D MAC problem, and 2D tensor problem with a staged smoother: the
-        // residual restriction ends the last pre-smoothing launch
+        // 2D (MAC and nodal problems; tensor problem with a staged smoother):
+        // the residual restriction ends the last pre-smoothing launch
         const bool rfold = c->dim == 2 && c->fuse && nu1 > 0 && res_fold_ok(L, m.op) &&
-                           ((m.op == HB_OP_VISC && sweep2_shape(L.tile).staged) || m.op == HB_OP_MAC);
+                           (m.op != HB_OP_VISC || sweep2_shape(L.tile).staged);
         smooth<R>(c, m, l, nu1, pair, nullptr, rfold ? &C : nullptr);
         if (m.op == HB_OP_VISC) {
             if (!rfold)
@@ -527,17 +534,16 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
                                        B::x(C));
         } else if (m.op == HB_OP_MAC) {
             if (!rfold) launch_mac_resid_restrict<R>(c, C, vc, L.gall, L.o, B::x(L), B::b(L), B::b(C), B::x(C));
-        } else {
+        } else if (!rfold) {
             launch_nodal_resid<R>(c, L, v, B::x(L), B::b(L), B::r(L), -1);
             launch_nodal_restrict<R>(c, C, vc, L.gall, L.o, B::r(L), B::b(C), B::x(C));
         }
         vcycle<R>(c, m, l + 1, nu1, nu2);
-        // 2D tensor problem with a staged smoother, and 2D MAC problem: the
-        // prolongation is folded into the first post-smoothing launch
-        const bool fold = c->dim == 2 && c->fuse && nu2 > 0 &&
-                          ((m.op == HB_OP_VISC && sweep2_shape(L.tile).staged) || m.op == HB_OP_MAC);
-        if (m.op == HB_OP_NODAL) launch_nodal_prolong<R>(c, L, vpc, C.gall, C.o, B::x(C), B::x(L));
-        else if (!fold)
+        // 2D (MAC and nodal problems; tensor problem with a staged smoother):
+        // the prolongation is folded into the first post-smoothing launch
+        const bool fold = c->dim == 2 && c->fuse && nu2 > 0 && (m.op != HB_OP_VISC || sweep2_shape(L.tile).staged);
+        if (m.op == HB_OP_NODAL && !fold) launch_nodal_prolong<R>(c, L, vpc, C.gall, C.o, B::x(C), B::x(L));
+        else if (m.op != HB_OP_NODAL && !fold)
             launch_prolong_cells<R>(c, L, vpc, C.gall, C.o, m.ncomp, m.op == HB_OP_VISC ? -1.0 : 1.0, B::x(C), B::x(L));
         smooth<R>(c, m, l, nu2, pair, fold ? &C : nullptr);
     }

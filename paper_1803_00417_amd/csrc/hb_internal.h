@@ -431,9 +431,14 @@ template <typename R> void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, 
 // Gauss-Seidel sweeps from cur into next (one launch; 3D: one sweep, two launches),
 // with candidate tile `tile` (0 .. kNodalCands - 1); nodal_sweep_tile gives
 // its extents
+// (2D: pe folds the prolongation of the coarse iterate in, bc/xc the
+// residual restriction to the coarse level, v then also carrying the coarse
+// level, gct/oct its tables; every periodic extent at least the halo:
+// 4 nsw, or 4 nsw + 2 with the restriction)
 template <typename R>
 void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile,
-                        int nsw = 1);
+                        int nsw = 1, const R* pe = nullptr, const GridD* gct = nullptr, const long* oct = nullptr,
+                        R* bc = nullptr, R* xc = nullptr);
 void nodal_sweep_tile(int dim, int tile, int* tx, int* ty);
 constexpr int kNodalCands = 3;
 // r = b - K x (slot >= 0: FP64 only, max-norm into each cavity's slot) or y = K x (b null)

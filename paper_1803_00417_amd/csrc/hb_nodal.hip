@@ -203,11 +203,13 @@ constexpr int kNG4Tiles = 3;
 // c <= 1) in y (the rings above, widened by what the later sweep reads), so
 // the halo is 4 NSW by 2 NSW nodes; again every node sees the values of the
 // one-colour-per-launch order.
-template <int DIM, class CF, int NSW = 1>
+// EXT = 2 (a launch that ends a pre-smoothing and restricts the residual):
+// every ring two nodes wider, so x is final two nodes around the tile.
+template <int DIM, class CF, int NSW = 1, int EXT = 0>
 struct NG4Tile {
-    static_assert(DIM == 2 || NSW == 1, "two sweeps per launch in 2D only");
+    static_assert(DIM == 2 || (NSW == 1 && EXT == 0), "two sweeps and folded transfers in 2D only");
     using C = CF;
-    static constexpr int HX = 4 * NSW, HY = 2 * NSW;     // halo of x
+    static constexpr int HX = 4 * NSW + EXT, HY = 2 * NSW + EXT;   // halo of x
     static constexpr int SX = C::TX + 2 * HX, SY = C::TY + 2 * HY, SZ = DIM == 3 ? 2 * C::PZ + 1 : 1;
     static constexpr int NS = SX * SY * SZ;
     // b on the first colour's region
@@ -215,14 +217,57 @@ struct NG4Tile {
     static constexpr int NB = BX * BY * C::PZ;
 };
 
-template <int DIM, typename R, class CF, int NSW = 1>
-__global__ void __launch_bounds__(CF::TH)
-k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* nexta, const R* __restrict__ ba)
+// Nodal interpolation (P e) at fine node (i, j) from the coarse iterate e
+// on grid gc: the mean of the coarse nodes of its coarse edge or cell; same
+// terms, order and rounding as the prolongation kernel.
+template <typename R>
+__device__ inline R nodal_prolong_at(const GridD& gc, const R* __restrict__ e, int i, int j)
 {
-    using T = NG4Tile<DIM, CF, NSW>;
+    const int F[2] = {i, j};
+    R s = 0;
+#pragma unroll
+    for (int bits = 0; bits < 4; ++bits) {
+        int p[2] = {0, 0};
+        R w = 1;
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int hi = (bits >> a) & 1;
+            if (!(F[a] & 1)) {
+                if (hi) ok = false;
+                p[a] = F[a] >> 1;
+            } else {
+                w *= R(0.5);
+                int C = ((F[a] - 1) >> 1) + hi;
+                if (gc.per[a] && C == nnode(gc, a)) C = 0;
+                p[a] = C;
+            }
+        }
+        const R val = e[nid(gc, p[0], p[1], 0)];
+        s = ok ? s + w * val : s;
+    }
+    return s;
+}
+
+// PRO (2D): the fill adds the interpolated coarse correction pe to x (a
+// V-cycle's prolongation folded into the first sweep after it).  RES (2D):
+// the launch ends a pre-smoothing; it also forms the residual b - K x of
+// the tile's nodes and a ring of one below them, and restricts it by full
+// weighting to the tile's coarse nodes (coarse b, coarse x = 0), as the
+// residual and restriction kernels would after it.
+template <int DIM, typename R, class CF, int NSW = 1, bool PRO = false, bool RES = false>
+__global__ void __launch_bounds__(CF::TH)
+k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* nexta, const R* __restrict__ ba,
+                 const R* __restrict__ pea = nullptr, const GridD* __restrict__ gct = nullptr,
+                 const long* __restrict__ oct = nullptr, R* __restrict__ bca = nullptr, R* __restrict__ xca = nullptr)
+{
+    static_assert(!(PRO && RES), "a launch either starts a post-smoothing or ends a pre-smoothing");
+    using T = NG4Tile<DIM, CF, NSW, RES ? 2 : 0>;
     constexpr int TH = CF::TH;
     __shared__ R s[T::NS];
     __shared__ R sb[T::NB];
+    constexpr int RX = CF::TX + 1, RY = CF::TY + 1;   // residual positions: the tile and a ring below
+    __shared__ R rr[RES ? RX * RY : 1];
     int cav, bz, tbx, tby, tbz;
     GridD g;
     xcd_tile(tbx, tby, tbz);
@@ -236,6 +281,10 @@ k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* n
     const R* fix = fixa + node0;
     R* next = nexta + node0;
     const R* b = ba + node0;
+    GridD gc = g;
+    const R* pe = nullptr;
+    if (PRO || RES) gc = bv_g2(v, gct, cav);
+    if (PRO) pe = pea + bv_o2(v, oct, cav);
     // stage x (all planes kb-1 .. kb+2PZ-1; halo 4 in x, 2 in y) and b (the
     // updated planes on the colour-0 region); positions beyond a wall are 0,
     // periodic axes wrap; every load uses an in-range index
@@ -258,7 +307,8 @@ k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* n
             }
             const bool upd = DIM == 2 || ((p[2] & 1) == zpar);
             const R* src = upd ? cur : fix;
-            const R val = src[nid(g, p[0], p[1], p[2])];
+            R val = src[nid(g, p[0], p[1], p[2])];
+            if (PRO) val = val + nodal_prolong_at<R>(gc, pe, p[0], p[1]);
             vx[u] = ok ? val : R(0);
         }
         constexpr int KB = (T::NB + TH - 1) / TH;
@@ -297,8 +347,8 @@ k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* n
 #pragma unroll
     for (int q = 0; q < 4 * NSW; ++q) {
         const int cc = q & 3, w = q >> 2;
-        const int gx = 4 * (NSW - 1 - w) + 3 - cc;
-        const int gy = 2 * (NSW - 1 - w) + (cc <= 1 ? 1 : 0);
+        const int gx = 4 * (NSW - 1 - w) + 3 - cc + (RES ? 2 : 0);
+        const int gy = 2 * (NSW - 1 - w) + (cc <= 1 ? 1 : 0) + (RES ? 2 : 0);
         const int px = cc & 1, py = (cc >> 1) & 1;
         // region [ox - gx, ox + TX + gx) x [oy - gy, oy + TY + gy); the first
         // node of colour parity px along x, py along y
@@ -333,6 +383,62 @@ k_nodal_gs_fused(BV v, int zpar, const R* __restrict__ cura, const R* fixa, R* n
         if (G[0] >= nn[0] || G[1] >= nn[1] || G[2] >= nn[2]) continue;
         next[nid(g, G[0], G[1], G[2])] = s[((DIM == 3 ? 1 + 2 * m : 0) * T::SY + ry + T::HY) * T::SX + rx + T::HX];
     }
+    if constexpr (RES) {
+        // residual at tile offsets [-1, TX) x [-1, TY) (periodic positions
+        // are the wrapped nodes; positions beyond a wall are never read)
+        for (int t = threadIdx.x; t < RX * RY; t += TH) {
+            const int rx = t % RX - 1, ry = t / RX - 1;
+            int G[3] = {ox + rx, oy + ry, 0};
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                if (G[a] >= 0 && G[a] < nn[a]) continue;
+                if (g.per[a]) G[a] = G[a] < 0 ? G[a] + nn[a] : G[a] - nn[a];
+                else in = false;
+            }
+            R rv = R(0);
+            if (in) {
+                const int l = (ry + T::HY) * T::SX + rx + T::HX;
+                const R Kx = block_K<DIM, R>(g, s, T::SX, T::SX * T::SY, G, l, nullptr);
+                rv = sb[(ry + T::HY - 1) * T::BX + rx + T::HX - 1] - Kx;
+            }
+            rr[t] = rv;
+        }
+        __syncthreads();
+        R* bcoarse = bca + bv_o2(v, oct, cav);
+        R* xcoarse = xca + bv_o2(v, oct, cav);
+        constexpr int CX = CF::TX / 2, CY = CF::TY / 2;
+        for (int t = threadIdx.x; t < CX * CY; t += TH) {
+            const int I[2] = {ox / 2 + t % CX, oy / 2 + t / CX};
+            if (I[0] >= nnode(gc, 0) || I[1] >= nnode(gc, 1)) continue;
+            R sum = 0;
+#pragma unroll
+            for (int u = 0; u < 9; ++u) {
+                int tt = u, lr[2];
+                bool ok = true;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int del = tt % 3 - 1;
+                    tt /= 3;
+                    const int F = 2 * I[a] + del;
+                    if ((F < 0 || F >= nn[a]) && !g.per[a]) ok = false;
+                    lr[a] = F - (a == 0 ? ox : oy) + 1;
+                }
+                tt = u;
+                R w = 1;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    if (tt % 3 != 1) w *= R(0.5);
+                    tt /= 3;
+                }
+                const R val = rr[lr[1] * RX + lr[0]];
+                sum = ok ? sum + w * val : sum;
+            }
+            const long qc = nid(gc, I[0], I[1], 0);
+            bcoarse[qc] = sum;
+            xcoarse[qc] = R(0);
+        }
+    }
 }
 
 template <int DIM>
@@ -358,14 +464,23 @@ void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, int colour, R* x, cons
 }
 
 template <int DIM, typename R, class CF>
-static void nodal_sweep_impl(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int nsw)
+static void nodal_sweep_impl(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int nsw,
+                             const R* pe, const GridD* gct, const long* oct, R* bc, R* xc)
 {
     BV vv = v;
     if (DIM == 2) {
         vv.zb = 1;
         const dim3 grid((nnode(L.gmax, 0) + CF::TX - 1) / CF::TX, (nnode(L.gmax, 1) + CF::TY - 1) / CF::TY, c->nb);
-        if (nsw == 2) k_nodal_gs_fused<2, R, CF, 2><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
-        else k_nodal_gs_fused<2, R, CF><<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b);
+        auto go = [&](auto kern) { kern<<<grid, CF::TH, 0, c->s>>>(vv, 0, cur, cur, next, b, pe, gct, oct, bc, xc); };
+        if (nsw == 2) {
+            if (pe) go(k_nodal_gs_fused<2, R, CF, 2, true, false>);
+            else if (bc) go(k_nodal_gs_fused<2, R, CF, 2, false, true>);
+            else go(k_nodal_gs_fused<2, R, CF, 2, false, false>);
+        } else {
+            if (pe) go(k_nodal_gs_fused<2, R, CF, 1, true, false>);
+            else if (bc) go(k_nodal_gs_fused<2, R, CF, 1, false, true>);
+            else go(k_nodal_gs_fused<2, R, CF, 1, false, false>);
+        }
     } else {
         const int planes = (nnode(L.gmax, 2) + 1) / 2;   // even planes (at least as many as odd)
         vv.zb = (planes + CF::PZ - 1) / CF::PZ;
@@ -378,21 +493,25 @@ static void nodal_sweep_impl(Ctx* c, const Level& L, const BV& v, const R* cur, 
 
 template <int DIM, typename R, class Tiles, size_t... I>
 static void nodal_sweep_pick(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int k, int nsw,
-                             std::index_sequence<I...>)
+                             const R* pe, const GridD* gct, const long* oct, R* bc, R* xc, std::index_sequence<I...>)
 {
-    ((k == (int)I ? nodal_sweep_impl<DIM, R, std::tuple_element_t<I, Tiles>>(c, L, v, cur, next, b, nsw) : void()),
+    ((k == (int)I ? nodal_sweep_impl<DIM, R, std::tuple_element_t<I, Tiles>>(c, L, v, cur, next, b, nsw, pe, gct, oct,
+                                                                             bc, xc)
+                  : void()),
      ...);
 }
 
 // nsw Gauss-Seidel sweeps (all 2^d colours; two in 2D only) from cur into
-// next, with tile candidate `tile`
+// next, with tile candidate `tile`; 2D: pe folds in the prolongation, bc/xc
+// the residual restriction
 template <typename R>
-void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile, int nsw)
+void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile, int nsw,
+                        const R* pe, const GridD* gct, const long* oct, R* bc, R* xc)
 {
     const int k = tile >= 0 && tile < kNG4Tiles ? tile : 0;
     constexpr auto seq = std::make_index_sequence<kNG4Tiles>{};
-    if (L.gmax.dim == 2) nodal_sweep_pick<2, R, NG4Tiles2>(c, L, v, cur, next, b, k, nsw, seq);
-    else nodal_sweep_pick<3, R, NG4Tiles3>(c, L, v, cur, next, b, k, 1, seq);
+    if (L.gmax.dim == 2) nodal_sweep_pick<2, R, NG4Tiles2>(c, L, v, cur, next, b, k, nsw, pe, gct, oct, bc, xc, seq);
+    else nodal_sweep_pick<3, R, NG4Tiles3>(c, L, v, cur, next, b, k, 1, nullptr, nullptr, nullptr, nullptr, nullptr, seq);
 }
 
 void nodal_sweep_tile(int dim, int k, int* tx, int* ty)
@@ -428,8 +547,10 @@ void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R
     if (slot >= 0) launch_max_final(c, vv.act, slot);
 }
 
-template void launch_nodal_sweep<double>(Ctx*, const Level&, const BV&, const double*, double*, const double*, int, int);
-template void launch_nodal_sweep<float>(Ctx*, const Level&, const BV&, const float*, float*, const float*, int, int);
+template void launch_nodal_sweep<double>(Ctx*, const Level&, const BV&, const double*, double*, const double*, int, int,
+                                         const double*, const GridD*, const long*, double*, double*);
+template void launch_nodal_sweep<float>(Ctx*, const Level&, const BV&, const float*, float*, const float*, int, int,
+                                        const float*, const GridD*, const long*, float*, float*);
 template void launch_nodal_gs<double>(Ctx*, const Level&, const BV&, int, double*, const double*);
 template void launch_nodal_gs<float>(Ctx*, const Level&, const BV&, int, float*, const float*);
 template void launch_nodal_resid<double>(Ctx*, const Level&, const BV&, const double*, const double*, double*, int);
