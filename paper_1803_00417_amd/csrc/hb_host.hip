@@ -734,11 +734,11 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o,
             if (act[i] && stops(so[i], o)) act[i] = 0;
         if (!any_set(c, act)) break;
         upload_flags(c, c->act, act);
-        seg_dot_then(c, sv, rh, r, S_DOT0, 1);   // rho, beta
+        seg_dot_then(c, sv, rh, r, S_DOT0, 1, -1);   // rho, beta
         bicg_p_dev(c, sv, p, r, v);
         precond(c, m, p, ph, o.nu1, o.nu2, lo);
         apply0(c, m, ph, v);
-        seg_dot_then(c, sv, rh, v, S_DOT1, 2);   // alpha
+        seg_dot_then(c, sv, rh, v, S_DOT1, 2, S_MAX);   // alpha; S_MAX cleared for the max of s
         sub_scaled_max_dev(c, sv, s, r, S_ALPHA, v, S_MAX);
         fetch_slots(c);
         // cavities that finish at the half step: x += alpha ph, r = s
@@ -771,7 +771,7 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o,
         }
         precond(c, m, s, sh, o.nu1, o.nu2, lo);
         apply0(c, m, sh, t);
-        seg_dot2_then(c, sv, t, t, S_DOT0, s, S_DOT1, 3);   // t.t, t.s, omega
+        seg_dot2_then(c, sv, t, t, S_DOT0, s, S_DOT1, 3, S_MAX);   // t.t, t.s, omega; S_MAX cleared for the max of r
         bicg_x_dev(c, sv, x, ph, sh, true);
         sub_scaled_max_dev(c, sv, r, s, S_OMEGA, t, S_MAX);
         fetch_slots(c);
@@ -1261,8 +1261,6 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
               hipHostGetDevicePointer((void**)&c->dhsc, c->hsc, 0) == hipSuccess &&
               hipHostGetDevicePointer((void**)&c->dhseq, c->hseq, 0) == hipSuccess &&
               dalloc(&c->partial, 2L * kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
-              dalloc(&c->rcnt, count) == hipSuccess &&
-              hipMemsetAsync(c->rcnt, 0, sizeof(unsigned) * count, c->s) == hipSuccess &&
               dalloc(&c->mpart, (long)kSubMax * count) == hipSuccess &&
               hipMemsetAsync(c->mpart, 0, sizeof(unsigned long long) * kSubMax * count, c->s) == hipSuccess &&
               dalloc(&c->act2, count) == hipSuccess && dalloc(&c->sel, count) == hipSuccess &&
@@ -1371,7 +1369,6 @@ static void destroy_ctx(Ctx* c)
                       c->sc, c->partial};
     for (double* p : bufs) (void)hipFree(p);
     (void)hipFree(c->mpart);
-    (void)hipFree(c->rcnt);
     (void)hipFree(c->act);
     (void)hipFree(c->act2);
     (void)hipFree(c->sel);

@@ -268,7 +268,6 @@ struct Ctx {
     unsigned long long* dhseq = nullptr;
     unsigned long long pub = 0;           // last publication number
     double* partial = nullptr;   // reduction partials (2 x kRedBlocks per cavity)
-    unsigned* rcnt = nullptr;    // per cavity: blocks done in a single-launch reduction (zero between launches)
     unsigned long long* mpart = nullptr;   // max-norm partials (kSubMax per cavity, kept zero between uses)
     int* act = nullptr;          // device active flags (nb)
     int* hact = nullptr;         // pinned host staging of the flags
@@ -331,10 +330,12 @@ void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot);
 void seg_set_zero(Ctx* c, int slot);                       // every cavity
 void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot);
 // the same, then BiCGStab scalar update `then` (1 rho and beta, 2 alpha)
-void seg_dot_then(Ctx* c, const SegV& s, const double* a, const double* b, int slot, int then);
-// slot0 = a.b0 and slot1 = a.b1 in one pass, then scalar update `then` (3 omega)
+// and clearing slot `zero` (-1: none)
+void seg_dot_then(Ctx* c, const SegV& s, const double* a, const double* b, int slot, int then, int zero);
+// slot0 = a.b0 and slot1 = a.b1 in one pass, then scalar update `then` (3
+// omega) and clearing slot `zero`
 void seg_dot2_then(Ctx* c, const SegV& s, const double* a, const double* b0, int slot0, const double* b1, int slot1,
-                   int then);
+                   int then, int zero);
 void seg_sub_mean(Ctx* c, const SegV& s, double* v);
 void seg_copy(Ctx* c, const SegV& s, double* dst, const double* src);
 void seg_fill(Ctx* c, const SegV& s, double* dst, double v);

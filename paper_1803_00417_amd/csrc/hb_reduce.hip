@@ -229,50 +229,17 @@ __device__ inline void bicg_scalar(double* sc, int which)
     }
 }
 
-// Single-launch reductions.  Each block of a cavity writes its partial,
-// then adds one to the cavity's counter (acquire-release at device scope,
-// so the partial is visible before the count); the block that completes the
-// count sees every partial, finishes the reduction in the fixed order of a
-// separate final pass, and resets the counter for the next launch.
-__device__ inline bool last_block(unsigned* cnt, int cav, unsigned nblk, bool* last)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned old = __hip_atomic_fetch_add(cnt + cav, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        *last = old == nblk - 1;
-        if (*last) __hip_atomic_store(cnt + cav, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    return *last;
-}
-
-// a partial written by another block of this launch (read past the CU's
-// cache)
-__device__ inline double load_dev(const double* p)
-{
-    const unsigned long long b =
-        __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)b);
-}
-
-// sum over the final pass's partials of one cavity (as k_seg_sum_final)
-__device__ inline double final_sum(const double* part, double* sh)
-{
-    double s = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) s += load_dev(part + i);
-    return block_sum(s, sh);
-}
-
-// slot0 = sum(a * b0) (b0 null: sum a) and, with b1, slot1 = sum(a * b1),
-// in one pass; then (1..3) the BiCGStab scalar update that follows.  Block x
-// of cavity y owns {x*T + t + k*kRedBlocks*T}, as k_seg_sum_partial: the
-// same sums bit for bit.
-__global__ void k_seg_dot(SegV sv, const double* __restrict__ a, const double* __restrict__ b0,
-                          const double* __restrict__ b1, double* __restrict__ part, unsigned* cnt,
-                          double* __restrict__ scb, int slot0, int slot1, int then)
+// BiCGStab dot products: a partial pass (one or two products of a with b0,
+// b1 per block, the index sets of k_seg_sum_partial, so the same sums bit
+// for bit) and a final pass of one block per cavity that adds the partials
+// in the fixed order of k_seg_sum_final, applies the scalar update that
+// follows (`then`) and clears slot `zero` (the max-norm slot the next
+// update kernel fills with atomic maxima).  No block waits on another: a
+// device-scope release per block would write back the XCD's L2 each time.
+__global__ void k_seg_dot_partial(SegV sv, const double* __restrict__ a, const double* __restrict__ b0,
+                                  const double* __restrict__ b1, double* __restrict__ part)
 {
     __shared__ double sh[kT / 64];
-    __shared__ bool last;
     SEG_ENTER(sv, off, n);
     double s0 = 0.0, s1 = 0.0;
     SEG_LOOP(i, n)
@@ -280,45 +247,57 @@ __global__ void k_seg_dot(SegV sv, const double* __restrict__ a, const double* _
         s0 += b0 ? a[off + i] * b0[off + i] : a[off + i];
         if (b1) s1 += a[off + i] * b1[off + i];
     }
-    double* p0 = part + (long)cav_ * kRedBlocks;
-    double* p1 = part + ((long)gridDim.y + cav_) * kRedBlocks;
     s0 = block_sum(s0, sh);
-    if (threadIdx.x == 0) p0[blockIdx.x] = s0;
+    if (threadIdx.x == 0) part[(long)cav_ * kRedBlocks + blockIdx.x] = s0;
     if (b1) {
         s1 = block_sum(s1, sh);
-        if (threadIdx.x == 0) p1[blockIdx.x] = s1;
+        if (threadIdx.x == 0) part[((long)gridDim.y + cav_) * kRedBlocks + blockIdx.x] = s1;
     }
-    if (!last_block(cnt, cav_, gridDim.x, &last)) return;
-    const double t0 = final_sum(p0, sh);
-    const double t1 = b1 ? final_sum(p1, sh) : 0.0;
+}
+
+__global__ void k_seg_dot_final(SegV sv, const double* __restrict__ part, double* __restrict__ scb, int slot0,
+                                int slot1, int then, int zero)
+{
+    __shared__ double sh[kT / 64];
+    const int cav = blockIdx.x;
+    if (sv.act && !sv.act[cav]) return;
+    double t0 = 0.0, t1 = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) t0 += part[(long)cav * kRedBlocks + i];
+    t0 = block_sum(t0, sh);
+    if (slot1 >= 0) {
+        for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) t1 += part[((long)gridDim.x + cav) * kRedBlocks + i];
+        t1 = block_sum(t1, sh);
+    }
     if (threadIdx.x == 0) {
-        double* sc = scb + (long)cav_ * S_NSLOT;
+        double* sc = scb + (long)cav * S_NSLOT;
         sc[slot0] = t0;
-        if (b1) sc[slot1] = t1;
+        if (slot1 >= 0) sc[slot1] = t1;
         if (then) bicg_scalar(sc, then);
+        if (zero >= 0) sc[zero] = 0.0;
     }
 }
 
 static void dot_launch(Ctx* c, const SegV& s, const double* a, const double* b0, const double* b1, int slot0, int slot1,
-                       int then)
+                       int then, int zero)
 {
-    k_seg_dot<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, a, b0, b1, c->partial, c->rcnt, c->sc, slot0, slot1, then);
+    k_seg_dot_partial<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, a, b0, b1, c->partial);
+    k_seg_dot_final<<<c->nb, kT, 0, c->s>>>(s, c->partial, c->sc, slot0, b1 ? slot1 : -1, then, zero);
 }
 
 void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot)
 {
-    dot_launch(c, s, a, b, nullptr, slot, 0, 0);
+    dot_launch(c, s, a, b, nullptr, slot, -1, 0, -1);
 }
 
-void seg_dot_then(Ctx* c, const SegV& s, const double* a, const double* b, int slot, int then)
+void seg_dot_then(Ctx* c, const SegV& s, const double* a, const double* b, int slot, int then, int zero)
 {
-    dot_launch(c, s, a, b, nullptr, slot, 0, then);
+    dot_launch(c, s, a, b, nullptr, slot, -1, then, zero);
 }
 
 void seg_dot2_then(Ctx* c, const SegV& s, const double* a, const double* b0, int slot0, const double* b1, int slot1,
-                   int then)
+                   int then, int zero)
 {
-    dot_launch(c, s, a, b0, b1, slot0, slot1, then);
+    dot_launch(c, s, a, b0, b1, slot0, slot1, then, zero);
 }
 
 // v -= sum(v) / n per cavity, the sum taken from the slot
@@ -456,8 +435,7 @@ void bicg_p_dev(Ctx* c, const SegV& s, double* p, const double* r, const double*
 
 // out = a - s b (s from a slot), with the max-norm of out into another slot
 __global__ void k_sub_scaled_max_dev(SegV sv, double* __restrict__ out, const double* __restrict__ a, int sslot,
-                                     const double* __restrict__ b, double* __restrict__ scb, int mslot,
-                                     double* __restrict__ part, unsigned* cnt)
+                                     const double* __restrict__ b, double* __restrict__ scb, int mslot)
 {
     __shared__ unsigned long long sh[kT / 64];
     SEG_ENTER(sv, off, n);
@@ -471,24 +449,14 @@ __global__ void k_sub_scaled_max_dev(SegV sv, double* __restrict__ out, const do
         m = bb > m ? bb : m;
     }
     m = block_umax(m, sh);
-    // the cavity's last block takes the maximum of the blocks' maxima
-    unsigned long long* pm = reinterpret_cast<unsigned long long*>(part) + (long)cav_ * kRedBlocks;
-    if (threadIdx.x == 0) pm[blockIdx.x] = m;
-    __shared__ bool last;
-    if (!last_block(cnt, cav_, gridDim.x, &last)) return;
-    unsigned long long mm = 0ull;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
-        const unsigned long long v = __hip_atomic_load(pm + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        mm = v > mm ? v : mm;
-    }
-    mm = block_umax(mm, sh);
-    if (threadIdx.x == 0) scb[(long)cav_ * S_NSLOT + mslot] = __longlong_as_double((long long)mm);
+    if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav_ * S_NSLOT + mslot, m);
 }
 
+// the max-norm slot must have been cleared (the dot product's final pass
+// before it does so)
 void sub_scaled_max_dev(Ctx* c, const SegV& s, double* out, const double* a, int sslot, const double* b, int mslot)
 {
-    k_sub_scaled_max_dev<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, a, sslot, b, c->sc, mslot,
-                                                                              c->partial, c->rcnt);
+    k_sub_scaled_max_dev<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, a, sslot, b, c->sc, mslot);
 }
 
 // x += alpha ph + omega sh (with_omega), or x = alpha ph + x
