@@ -1129,7 +1129,8 @@ static bool level_pairs(const Level& L)
 // two sweeps in one and the level allows it.  After a warm-up unit per
 // candidate, kRounds rounds time one unit of every candidate in turn (an
 // event pair per unit), and a candidate's time is its minimum, so one slow
-// sample does not decide.  The candidates compute the same values bit for
+// sample does not decide; a candidate replaces an earlier one only when more
+// than 2% faster.  The candidates compute the same values bit for
 // bit, so the choice changes only the speed.  HB_TILE=k in the environment
 // forces candidate k instead (modulo the problem's candidate count).
 static void autotune(Ctx* c)
@@ -1209,7 +1210,9 @@ static void autotune(Ctx* c)
                     if (hipEventElapsedTime(&t, p[0], p[1]) != hipSuccess) t = 1e30f;
                     tk = r == 0 ? t : (t < tk ? t : tk);
                 }
-                if (!have || tk < best) {
+                // a later candidate must be more than 2% faster to replace the
+                // best so far, so near-ties resolve the same way run to run
+                if (!have || tk < 0.98f * best) {
                     best = tk;
                     have = true;
                     L.tile = k;

@@ -508,12 +508,20 @@ enum { ST_X0 = 0, ST_X1 = 1, ST_B0 = 2, ST_B1 = 3, ST_E = 4, ST_FX = 4, ST_FY = 
 // cell itself with the homogeneous ghost sign wsign (tensor problem -1,
 // MAC problem +1).  Same terms, order and
 // rounding as the prolongation kernel.
+// Prolongation correction (P e)_q at fine cell (si, sj) from the coarse
+// iterate e (components Nc apart) on grid gc: the 2^2 nearest coarse cells
+// with axis weights 3/4 and 1/4; a coarse neighbour beyond a wall is the
+// cell itself with the homogeneous ghost sign wsign (tensor problem -1,
+// MAC problem +1).  Same terms, order and rounding as the prolongation
+// kernel.  Split in two so that a fill can issue every load before it adds
+// anything: prolong_src gives the four coarse indices (order: the cell, its
+// x neighbour, its y neighbour, the diagonal) and the signs per axis,
+// prolong_sum the correction from the four loaded values.
 template <typename R>
-__device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si, int sj, R wsign)
+__device__ inline void prolong_src(const GridD& gc, int si, int sj, R wsign, long q[4], R sgn[2])
 {
     const int C[2] = {si >> 1, sj >> 1}, ch[2] = {si & 1, sj & 1};
     int J[2];
-    R sgn[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         int J2 = C[a] + (ch[a] ? 1 : -1);
@@ -525,8 +533,15 @@ __device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si,
         J[a] = J2;
         sgn[a] = sg;
     }
-    const R nb[4] = {e[(long)C[1] * gc.n[0] + C[0]], e[(long)C[1] * gc.n[0] + J[0]], e[(long)J[1] * gc.n[0] + C[0]],
-                     e[(long)J[1] * gc.n[0] + J[0]]};
+    q[0] = (long)C[1] * gc.n[0] + C[0];
+    q[1] = (long)C[1] * gc.n[0] + J[0];
+    q[2] = (long)J[1] * gc.n[0] + C[0];
+    q[3] = (long)J[1] * gc.n[0] + J[0];
+}
+
+template <typename R>
+__device__ inline R prolong_sum(const R nb[4], const R sgn[2])
+{
     R s = 0;
 #pragma unroll
     for (int bits = 0; bits < 4; ++bits) {
@@ -540,6 +555,17 @@ __device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si,
         s += w * sg * nb[bits];
     }
     return s;
+}
+
+template <typename R>
+__device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si, int sj, R wsign)
+{
+    long q[4];
+    R sgn[2], nb[4];
+    prolong_src<R>(gc, si, sj, wsign, q, sgn);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nb[k] = e[q[k]];
+    return prolong_sum<R>(nb, sgn);
 }
 
 // PRO: x of the fill is x + P e (the coarse correction of a V-cycle folded
@@ -556,6 +582,12 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
     const bool inner = ox - H >= 0 && ox + T::TX + H <= g.n[0] && oy - H >= 0 && oy + T::TY + H <= g.n[1];
     const long fo1 = FINE ? 0 : foffset(g, 1);
     R v[NA][K];
+    // PRO: the coarse values of each position, loaded with the rest and
+    // added after every load is in flight
+    constexpr int KP = PRO ? K : 1;
+    R pv[KP][2][4], ps[KP][2];
+    bool pok[K], png[K];
+    const long Nc = PRO ? ncells(gc) : 0;
 #pragma unroll
     for (int u = 0; u < K; ++u) {
         const int t = threadIdx.x + u * TH;
@@ -565,18 +597,24 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
         bool ok = true, ng = false;
         int src[3] = {i, j, 0};
         const long idx = inner ? cid(g, i, j, 0) : tile_src<2>(g, i, j, 0, ok, ng, src);
-        R x0 = x[idx], x1 = x[N + idx];
-        if (PRO) {
-            const long Nc = ncells(gc);
-            x0 = x0 + prolong_at<R>(gc, pe, src[0], src[1], R(-1));
-            x1 = x1 + prolong_at<R>(gc, pe + Nc, src[0], src[1], R(-1));
+        pok[u] = ok;
+        png[u] = ng;
+        v[ST_X0][u] = x[idx];
+        v[ST_X1][u] = x[N + idx];
+        if constexpr (PRO) {
+            long q[4];
+            prolong_src<R>(gc, src[0], src[1], R(-1), q, ps[u]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                pv[u][0][k] = pe[q[k]];
+                pv[u][1][k] = pe[Nc + q[k]];
+            }
         }
         // b is read only at cells that are updated, which lie in the box
         v[ST_B0][u] = b[idx];
         v[ST_B1][u] = b[N + idx];
         if (FINE) {
-            const R e = coef[idx];
-            v[ST_E][u] = ok ? e : R(0);
+            v[ST_E][u] = coef[idx];
         } else {
             // position (i, j) holds the faces on its low x and low y side:
             // wrapped once along periodic axes, then clamped to the face
@@ -592,8 +630,17 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
             v[ST_FX][u] = coef[fid(g, 0, ax, ay, 0)];
             v[ST_FY][u] = coef[fo1 + fid(g, 1, bx, by, 0)];
         }
-        v[ST_X0][u] = ok ? (ng ? -x0 : x0) : R(0);
-        v[ST_X1][u] = ok ? (ng ? -x1 : x1) : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        R x0 = v[ST_X0][u], x1 = v[ST_X1][u];
+        if constexpr (PRO) {
+            x0 = x0 + prolong_sum<R>(pv[u][0], ps[u]);
+            x1 = x1 + prolong_sum<R>(pv[u][1], ps[u]);
+        }
+        v[ST_X0][u] = pok[u] ? (png[u] ? -x0 : x0) : R(0);
+        v[ST_X1][u] = pok[u] ? (png[u] ? -x1 : x1) : R(0);
+        if (FINE) v[ST_E][u] = pok[u] ? v[ST_E][u] : R(0);
     }
 #pragma unroll
     for (int u = 0; u < K; ++u) {
