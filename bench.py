@@ -243,12 +243,12 @@ def main():
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
     w = inputs.WORKLOADS[a.workload]
     # the 2D kernel (and its traffic) depends on the candidate the context
-    # kept for the finest level: its rows are keyed by tile, threads and
-    # sweeps per launch
+    # kept for the finest level: its rows are keyed by tile and sweeps per
+    # launch (the thread count does not change what a launch reads)
     t0 = r["tiles"]["tensor"][0] if r["tiles"]["tensor"] else None
     if w["dim"] == 2:
         tx, ty, th, sw = t0 or (0, 0, 0, 0)
-        kname = "fine2d@%dx%dx%ds%d" % (tx, ty, th, sw)
+        kname = "fine2d@%dx%ds%d" % (tx, ty, sw)
         klabel = ("%s (2D: %s of both velocity components in one launch, finest level, tile %dx%d, %d threads)"
                   % ("k_tsweep2" if th == 256 else "k_tsweepN", "one red-black sweep" if sw == 1
                      else "%d red-black sweeps" % sw, tx, ty, th))
