@@ -346,9 +346,6 @@ void seg_from_f32(Ctx* c, const SegV& s, const float* e, double* x);
 void flat_to_f32(Ctx* c, const double* src, float* dst, long n);
 // device-scalar BiCGStab steps (scalars in each cavity's slots S_RHO .. S_BETA)
 void bicg_init_scalars(Ctx* c, const int* act);
-void bicg_beta(Ctx* c, const int* act);     // rho = DOT0, beta = (rho/rho_prev)(alpha/omega)
-void bicg_alpha(Ctx* c, const int* act);    // alpha = rho / DOT1
-void bicg_omega(Ctx* c, const int* act);    // omega = DOT0 > 0 ? DOT1 / DOT0 : 0; rho_prev = rho
 void bicg_p_dev(Ctx* c, const SegV& s, double* p, const double* r, const double* v);
 void sub_scaled_max_dev(Ctx* c, const SegV& s, double* out, const double* a, int sslot, const double* b, int mslot);
 void bicg_x_dev(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, bool with_omega);

@@ -178,36 +178,6 @@ void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot)
     k_seg_maxabs<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, v, c->sc, slot);
 }
 
-// partial sums of a (or a*b) over the cavity's segment: block x of cavity y
-// owns the index set {x*T + t + k*kRedBlocks*T}
-__global__ void k_seg_sum_partial(SegV sv, const double* __restrict__ a, const double* __restrict__ b,
-                                  double* __restrict__ part)
-{
-    __shared__ double sh[kT / 64];
-    SEG_ENTER(sv, off, n);
-    double s = 0.0;
-    SEG_LOOP(i, n) s += b ? a[off + i] * b[off + i] : a[off + i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) part[(long)cav_ * kRedBlocks + blockIdx.x] = s;
-}
-
-__global__ void k_seg_sum_final(SegV sv, const double* __restrict__ part, double* __restrict__ sc, int slot)
-{
-    __shared__ double sh[kT / 64];
-    const int cav = blockIdx.x;
-    if (sv.act && !sv.act[cav]) return;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) s += part[(long)cav * kRedBlocks + i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) sc[(long)cav * S_NSLOT + slot] = s;
-}
-
-static void seg_sum_impl(Ctx* c, const SegV& s, const double* a, const double* b, int slot)
-{
-    k_seg_sum_partial<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, a, b, c->partial);
-    k_seg_sum_final<<<c->nb, kT, 0, c->s>>>(s, c->partial, c->sc, slot);
-}
-
 // one BiCGStab scalar update of a cavity's slots (which: 0 initial values,
 // 1 rho and beta, 2 alpha, 3 omega)
 __device__ inline void bicg_scalar(double* sc, int which)
@@ -230,9 +200,9 @@ __device__ inline void bicg_scalar(double* sc, int which)
 }
 
 // BiCGStab dot products: a partial pass (one or two products of a with b0,
-// b1 per block, the index sets of k_seg_sum_partial, so the same sums bit
-// for bit) and a final pass of one block per cavity that adds the partials
-// in the fixed order of k_seg_sum_final, applies the scalar update that
+// b1 per block; block x of cavity y owns the index set
+// {x*T + t + k*kRedBlocks*T}, so every run gives the same bits) and a final pass of one block per cavity that adds the partials
+// in a fixed order, applies the scalar update that
 // follows (`then`) and clears slot `zero` (the max-norm slot the next
 // update kernel fills with atomic maxima).  No block waits on another: a
 // device-scope release per block would write back the XCD's L2 each time.
@@ -310,7 +280,7 @@ __global__ void k_seg_sub_mean(SegV sv, double* __restrict__ v, const double* __
 
 void seg_sub_mean(Ctx* c, const SegV& s, double* v)
 {
-    seg_sum_impl(c, s, v, nullptr, S_SUM);
+    dot_launch(c, s, v, nullptr, nullptr, S_SUM, -1, 0, -1);
     k_seg_sub_mean<<<seg_grid(c, 4096L * c->nb), kT, 0, c->s>>>(s, v, c->sc);
 }
 
@@ -414,9 +384,6 @@ static void bicg_scalars(Ctx* c, const int* act, int which)
     k_bicg_scalars<<<(c->nb + 63) / 64, 64, 0, c->s>>>(c->sc, c->nb, act, which);
 }
 void bicg_init_scalars(Ctx* c, const int* act) { bicg_scalars(c, act, 0); }
-void bicg_beta(Ctx* c, const int* act) { bicg_scalars(c, act, 1); }
-void bicg_alpha(Ctx* c, const int* act) { bicg_scalars(c, act, 2); }
-void bicg_omega(Ctx* c, const int* act) { bicg_scalars(c, act, 3); }
 
 // p = r + beta (p - omega v)
 __global__ void k_bicg_p_dev(SegV sv, double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
