@@ -612,7 +612,7 @@ static void upload_flags(Ctx* c, int* dev, const int* host)
     std::vector<int>& shadow = dev == c->act ? c->dact : (dev == c->act2 ? c->dact2 : c->dsel);
     if ((int)shadow.size() == c->nb && std::equal(shadow.begin(), shadow.end(), host)) return;
     shadow.assign(host, host + c->nb);
-    (void)hipMemcpyAsync(dev, host, sizeof(int) * c->nb, hipMemcpyHostToDevice, c->s);
+    set_flags(c, dev, host);
 }
 
 static double slot(const Ctx* c, int b, int s) { return c->hsc[(long)b * S_NSLOT + s]; }

@@ -322,6 +322,14 @@ inline bool kt_take(Ctx* c)
     KTimer& k = c->ktm;
     return k.on && (k.seen++ % k.period) == 0;
 }
+// per-cavity int flags host -> device (in kernel arguments up to kFlagArgs
+// cavities, else a copy from the pinned host array)
+constexpr int kFlagArgs = 64;
+struct FlagArgs {
+    int n;
+    int v[kFlagArgs];
+};
+void set_flags(Ctx* c, int* dev, const int* host);
 void fetch_slots(Ctx* c);  // all slots to c->hsc once the stream's work so far has completed
 void copy(Ctx* c, double* dst, const double* src, long n);
 void fill(Ctx* c, double* dst, double v, long n);

@@ -76,6 +76,26 @@ void fetch_slots(Ctx* c)
     (void)hipMemcpy(c->hsc, c->sc, sizeof(double) * n, hipMemcpyDeviceToHost);
 }
 
+// per-cavity flags passed by value (a copy command costs the runtime more
+// than a launch)
+__global__ void k_set_flags(int* __restrict__ dev, FlagArgs a)
+{
+    const int i = threadIdx.x;
+    if (i < a.n) dev[i] = a.v[i];
+}
+
+void set_flags(Ctx* c, int* dev, const int* host)
+{
+    if (c->nb <= kFlagArgs) {
+        FlagArgs a;
+        a.n = c->nb;
+        for (int i = 0; i < c->nb; ++i) a.v[i] = host[i];
+        k_set_flags<<<1, kFlagArgs, 0, c->s>>>(dev, a);
+    } else {
+        (void)hipMemcpyAsync(dev, host, sizeof(int) * c->nb, hipMemcpyHostToDevice, c->s);
+    }
+}
+
 __global__ void k_copy(double* __restrict__ d, const double* __restrict__ s, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
