@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
-KT_PERIOD = 8   # kernel timer: every KT_PERIOD-th finest-level smoother launch
+# kernel timer: every KT_PERIOD-th finest-level smoother launch.  Odd: those
+# launches alternate between one that folds in the prolongation and one that
+# folds in the restriction, and an even period would time only one kind.
+KT_PERIOD = 7
 TILE_SOURCE = os.path.join(ROOT, "paper_1803_00417_amd", "csrc", "hb_tile.hip")
 
 
