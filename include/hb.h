@@ -53,7 +53,8 @@ enum {
     HB_ERR_DEVICE = -2,     /* a HIP call failed */
     HB_ERR_NOCONV = -3,     /* a solve hit max_cycles; outputs hold the last iterate */
     HB_ERR_NONFINITE = -4,  /* NaN/Inf in an input or produced by a solve */
-    HB_ERR_OOM = -5         /* device allocation failed in hb_create */
+    HB_ERR_OOM = -5,        /* device allocation failed in hb_create */
+    HB_ERR_IO = -6          /* a checkpoint file could not be opened, read or written */
 };
 
 enum { HB_BC_WALL = 0, HB_BC_PERIODIC = 1 };
@@ -190,6 +191,67 @@ int hb_create_batch(const hb_grid* grids, const hb_fluid* fluids, int count, con
                     void* hip_stream, hb_ctx** out);
 int hb_batch_size(const hb_ctx* ctx);
 int hb_step_batch(hb_ctx* ctx, double* const* u, double* const* p, const double* dt, hb_step_report* reports);
+
+/* ---- steady state, grid sequencing, checkpoints ---------------------------
+ * Steadiness (Sec. III.A, the test that closes the description of the
+ * projection; Sec. IV): a run is steady once the velocity's largest relative
+ * change over one step is below a tolerance (1e-5 in the paper).  The
+ * printed quotient divides by u^m cell by cell, undefined where u^m = 0; the
+ * change used here is max|u^(m+1) - u^m| / max|u^m| (infinite while u^m is
+ * zero everywhere).
+ *
+ * hb_run_steady: hb_step on (u, p) in place (dt <= 0: the CFL step of each
+ * step, else that constant step) until the change is below tol or max_steps
+ * steps have run.  Single-cavity contexts.  Returns HB_OK when steady,
+ * HB_ERR_NOCONV when max_steps ran out or a solve of the last step did not
+ * converge (u, p hold the last state), other codes as hb_step (the run
+ * stops at the failing step).  report (nullable): steps run, steady flag,
+ * simulated time of the steps that ran, last change.  The first call
+ * allocates one velocity-sized device buffer, kept by the context.
+ *
+ * hb_refine_state (grid sequencing, Sec. III.C): the state of a run on the
+ * grid one refinement below the context's (every used cell count halved,
+ * spacing doubled, same boundaries) carried to the context's grid.  The
+ * paper does not name the interpolation; velocity: conservative linear
+ * interpolation with central slopes, child = u(C) + sum over axes (x, y, z)
+ * of (+-1/4) (u(C+1) - u(C-1))/2, + on the parent's high half, a neighbour
+ * beyond a wall being the wall ghost 2 u_wall - u(C) and beyond a periodic
+ * face the wrapped cell; pressure: multilinear interpolation between the
+ * coarse nodes.  u_coarse [dim][coarse cells], p_coarse [coarse nodes] in;
+ * u, p on the context's grid out (device, caller-owned, not aliased).
+ * HB_ERR_ARG if a cell count of the context's grid is odd.
+ *
+ * hb_run_sequenced (Sec. III.C): from rest on `coarse` to steady state, then
+ * `levels` times: refine the state by two and continue to steady state
+ * (tol, max_steps as hb_run_steady, CFL steps).  u, p (device, caller-owned)
+ * receive the state on the finest grid; the intermediate grids' contexts and
+ * arrays are created and freed inside (every level's grid must be valid for
+ * hb_create).  reports: levels + 1 entries, one per grid.  A level that is
+ * not steady within max_steps is refined all the same and the call returns
+ * HB_ERR_NOCONV at the end; any other failure stops the run and returns its
+ * code, with the message in hb_last_error(NULL).  levels: 0 .. 8.
+ *
+ * hb_checkpoint_write / hb_checkpoint_read: raw checkpoint of a run (the
+ * restart of Sec. III.C): an 80-byte header (magic "HBCKPT", version 1,
+ * dim, n[3], periodic flags[3], value counts of u and p, step, t, h) then u
+ * ([dim][cells]) and p (nodes) as raw doubles in host byte order.  The
+ * step carries no state beyond (u, p), so a run restarted from a checkpoint
+ * continues bit for bit as the uninterrupted run.  Reading checks the header
+ * against the context's grid (HB_ERR_ARG if it differs); HB_ERR_IO for a
+ * file that cannot be opened, is not a checkpoint or is truncated. */
+typedef struct {
+    int32_t steps;   /* steps run */
+    int32_t steady;  /* 1 when the last step's change was below tol */
+    double t;        /* simulated time of those steps */
+    double change;   /* max|u^(m+1) - u^m| / max|u^m| of the last step */
+} hb_steady_report;
+
+int hb_run_steady(hb_ctx* ctx, double* u, double* p, double tol, int max_steps, double dt, hb_steady_report* report);
+int hb_refine_state(hb_ctx* ctx, const double* u_coarse, const double* p_coarse, double* u, double* p);
+int hb_run_sequenced(const hb_grid* coarse, const hb_fluid* fluid, const hb_step_opts* opts, int levels, double tol,
+                     int max_steps, void* hip_stream, double* u, double* p, hb_steady_report* reports);
+int hb_checkpoint_write(hb_ctx* ctx, const char* path, const double* u, const double* p, int64_t step, double t);
+int hb_checkpoint_read(hb_ctx* ctx, const char* path, double* u, double* p, int64_t* step, double* t);
 
 /* ---- learned warm start (BF16 U-Net on the matrix cores) -----------------
  * A small convolutional U-Net (4 levels, 16/32/64/64 channels, two 3x3

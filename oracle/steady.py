@@ -128,16 +128,21 @@ def run_steady(g, fl, o, u, p, tol=1e-5, max_steps=10000, dt=0.0):
     """Step (u, p) in place until the change of one step is below tol
     (Sec. III.A) or max_steps steps have run.  dt <= 0: the CFL step of every
     step.  Returns dict(steps, t, change, steady, rc); a step that returns
-    anything but OK ends the run with its code."""
+    anything but OK ends the run with its code (the time and change of a
+    step whose solve hit its cycle limit are counted, those of a step that
+    failed otherwise are not)."""
     t = 0.0
     change = float("inf")
     for m in range(max_steps):
         u_old = u.copy()
         rep, rc = orc.step(g, fl, o, u, p, dt)
-        t += rep.dt
-        if rc != orc.OK:
+        if rc not in (orc.OK, orc.ERR_NOCONV):
             return dict(steps=m + 1, t=t, change=change, steady=False, rc=rc)
+        t += rep.dt
         change = state_change(u_old, u)
+        if rc == orc.ERR_NOCONV:
+            # a solve of this step hit its cycle limit: the step ran, the run stops
+            return dict(steps=m + 1, t=t, change=change, steady=False, rc=rc)
         if change < tol:
             return dict(steps=m + 1, t=t, change=change, steady=True, rc=orc.OK)
     return dict(steps=max_steps, t=t, change=change, steady=False, rc=orc.ERR_NOCONV)
@@ -158,6 +163,7 @@ def sequence(gc, fl, o, levels, tol=1e-5, max_steps=10000):
             g = refined_grid(g)
         r = run_steady(g, fl, o, u, p, tol, max_steps)
         reports.append(r)
-        if r["rc"] != orc.OK:
+        # a grid not steady within max_steps is refined all the same
+        if r["rc"] not in (orc.OK, orc.ERR_NOCONV):
             break
     return g, u, p, reports

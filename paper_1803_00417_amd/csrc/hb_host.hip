@@ -1369,7 +1369,7 @@ static void destroy_ctx(Ctx* c)
         for (double* p : bufs) (void)hipFree(p);
     }
     double* bufs[] = {c->macphi, c->ustar, c->phi, c->kr, c->krh, c->kp, c->kv, c->kph, c->ks, c->ksh, c->kt,
-                      c->sc, c->partial};
+                      c->sc, c->partial, c->uold};
     for (double* p : bufs) (void)hipFree(p);
     (void)hipFree(c->mpart);
     (void)hipFree(c->act);
@@ -1680,6 +1680,256 @@ int hb_kernel_timing_read(hb_ctx* ctx, int64_t* launches, double* total_ms, doub
     *launches = c->ktm.launches;
     *total_ms = c->ktm.ms;
     *alg_bytes = c->ktm.bytes;
+    return HB_OK;
+}
+
+// ---- steady state, grid sequencing, checkpoints (Sec. III.A, Sec. III.C) ---
+
+// the grid one refinement below g (every used axis halved, spacing doubled);
+// false when a used axis has an odd cell count
+static bool coarser_grid(const GridD& g, GridD* out)
+{
+    GridD c = g;
+    for (int a = 0; a < g.dim; ++a) {
+        if (g.n[a] % 2 || g.n[a] < 2) return false;
+        c.n[a] = g.n[a] / 2;
+    }
+    c.h = 2.0 * g.h;
+    *out = c;
+    return true;
+}
+
+// steps (u, p) until the largest change of u over a step, relative to the
+// largest |u| before it, is below tol (Sec. III.A), or max_steps have run
+static int run_steady(Ctx* c, double* u, double* p, double tol, int max_steps, double dt, hb_steady_report* rep)
+{
+    const Cav& v = c->cv[0];
+    const long n = (long)v.dim * v.nc;
+    if (!c->uold && dalloc(&c->uold, n) != hipSuccess) return fail(c, HB_ERR_OOM, "device allocation failed");
+    hb_steady_report R;
+    memset(&R, 0, sizeof(R));
+    R.change = HUGE_VAL;
+    int rc = HB_ERR_NOCONV;
+    for (int m = 0; m < max_steps; ++m) {
+        copy(c, c->uold, u, n);
+        const int src = step_all(c, &u, &p, &dt, nullptr);
+        R.steps = m + 1;
+        if (src != HB_OK && src != HB_ERR_NOCONV) {
+            rc = src;
+            break;
+        }
+        red_maxdiff(c, 0, u, c->uold, n, S_CHG);
+        red_maxabs(c, 0, c->uold, n, S_CHGREF);
+        fetch_slots(c);
+        R.t += slot(c, 0, S_DT);
+        const double ref = slot(c, 0, S_CHGREF);
+        R.change = ref > 0.0 ? slot(c, 0, S_CHG) / ref : HUGE_VAL;
+        if (src == HB_ERR_NOCONV) {
+            rc = src;
+            break;
+        }
+        if (R.change < tol) {
+            R.steady = 1;
+            rc = HB_OK;
+            break;
+        }
+    }
+    if (rep) *rep = R;
+    if (hipGetLastError() != hipSuccess) return fail(c, HB_ERR_DEVICE, "kernel launch failed");
+    return rc;
+}
+
+int hb_run_steady(hb_ctx* ctx, double* u, double* p, double tol, int max_steps, double dt, hb_steady_report* report)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
+    if (!u || !p) return fail(c, HB_ERR_ARG, "null array");
+    if (!(tol > 0.0) || max_steps < 1) return fail(c, HB_ERR_ARG, "tol must be > 0 and max_steps >= 1");
+    StreamGuard guard(c);
+    return run_steady(c, u, p, tol, max_steps, dt, report);
+}
+
+int hb_refine_state(hb_ctx* ctx, const double* u_coarse, const double* p_coarse, double* u, double* p)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
+    if (!u_coarse || !p_coarse || !u || !p) return fail(c, HB_ERR_ARG, "null array");
+    GridD gc;
+    if (!coarser_grid(c->cv[0].g, &gc)) return fail(c, HB_ERR_ARG, "every cell count must be even");
+    StreamGuard guard(c);
+    launch_refine_state(c, gc, c->cv[0].g, u_coarse, p_coarse, u, p);
+    return hipGetLastError() == hipSuccess ? HB_OK : fail(c, HB_ERR_DEVICE, "kernel launch failed");
+}
+
+int hb_run_sequenced(const hb_grid* coarse, const hb_fluid* fluid, const hb_step_opts* opts, int levels, double tol,
+                     int max_steps, void* hip_stream, double* u, double* p, hb_steady_report* reports)
+{
+    auto bad = [](int code, const std::string& m) { g_create_err = m; return code; };
+    if (!coarse || !fluid || !opts || !u || !p || !reports) return bad(HB_ERR_ARG, "null argument");
+    if (levels < 0 || levels > 8) return bad(HB_ERR_ARG, "levels must be 0 .. 8");
+    if (!(tol > 0.0) || max_steps < 1) return bad(HB_ERR_ARG, "tol must be > 0 and max_steps >= 1");
+    hb_grid g = *coarse;
+    Ctx* prev = nullptr;
+    double *uprev = nullptr, *pprev = nullptr;
+    int rc = HB_OK;
+    memset(reports, 0, sizeof(hb_steady_report) * (levels + 1));
+    for (int l = 0; l <= levels; ++l) {
+        if (l > 0) {
+            for (int a = 0; a < g.dim; ++a) g.n[a] *= 2;
+            g.h *= 0.5;
+        }
+        Ctx* c = nullptr;
+        const int crc = create_ctx(&g, fluid, 1, opts, hip_stream, &c);
+        if (crc != HB_OK) {
+            rc = crc;
+            break;
+        }
+        const Cav& v = c->cv[0];
+        double *ul = u, *pl = p;
+        if (l < levels) {
+            ul = pl = nullptr;
+            if (dalloc(&ul, (long)v.dim * v.nc) != hipSuccess || dalloc(&pl, v.nn) != hipSuccess) {
+                (void)hipFree(ul);
+                (void)hipFree(pl);
+                destroy_ctx(c);
+                rc = bad(HB_ERR_OOM, "device allocation failed");
+                break;
+            }
+        }
+        int lrc;
+        {
+            StreamGuard guard(c);
+            if (l == 0) {
+                fill(c, ul, 0.0, (long)v.dim * v.nc);
+                fill(c, pl, 0.0, v.nn);
+            } else {
+                GridD gc;
+                coarser_grid(v.g, &gc);
+                launch_refine_state(c, gc, v.g, uprev, pprev, ul, pl);
+            }
+            lrc = run_steady(c, ul, pl, tol, max_steps, 0.0, &reports[l]);
+        }
+        if (prev) {
+            (void)hipStreamSynchronize(c->s);
+            (void)hipFree(uprev);
+            (void)hipFree(pprev);
+            destroy_ctx(prev);
+        }
+        prev = c;
+        uprev = ul;
+        pprev = pl;
+        // a level that did not become steady within max_steps is refined
+        // all the same; any other failure ends the run
+        if (lrc != HB_OK) {
+            g_create_err = c->err;
+            rc = lrc;
+            if (lrc != HB_ERR_NOCONV) break;
+        }
+    }
+    if (prev) {
+        (void)hipStreamSynchronize(prev->s);
+        if (uprev != u) (void)hipFree(uprev);
+        if (pprev != p) (void)hipFree(pprev);
+        destroy_ctx(prev);
+    }
+    return rc;
+}
+
+// checkpoint file: this header, then u ([dim][cells]) and p (nodes) as raw
+// doubles in host byte order
+struct CkptHeader {
+    char magic[8];
+    int32_t version, dim, n[3], per[3];
+    int64_t nu, np, step;
+    double t, h;
+};
+static_assert(sizeof(CkptHeader) == 80, "checkpoint header layout");
+static const char kCkptMagic[8] = {'H', 'B', 'C', 'K', 'P', 'T', '\0', '\0'};
+
+static void ckpt_header_of(const Cav& v, CkptHeader* H)
+{
+    memset(H, 0, sizeof(*H));
+    memcpy(H->magic, kCkptMagic, 8);
+    H->version = 1;
+    H->dim = v.dim;
+    for (int a = 0; a < 3; ++a) {
+        H->n[a] = v.g.n[a];
+        H->per[a] = v.g.per[a];
+    }
+    H->nu = (int64_t)v.dim * v.nc;
+    H->np = v.nn;
+    H->h = v.g.h;
+}
+
+int hb_checkpoint_write(hb_ctx* ctx, const char* path, const double* u, const double* p, int64_t step, double t)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
+    if (!path || !u || !p) return fail(c, HB_ERR_ARG, "null argument");
+    const Cav& v = c->cv[0];
+    CkptHeader H;
+    ckpt_header_of(v, &H);
+    H.step = step;
+    H.t = t;
+    std::vector<double> hu(H.nu), hp(H.np);
+    {
+        StreamGuard guard(c);
+        if (hipMemcpyAsync(hu.data(), u, sizeof(double) * H.nu, hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+            hipMemcpyAsync(hp.data(), p, sizeof(double) * H.np, hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+            hipStreamSynchronize(c->s) != hipSuccess)
+            return fail(c, HB_ERR_DEVICE, "device to host copy failed");
+    }
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(c, HB_ERR_IO, std::string("cannot open for writing: ") + path);
+    const bool ok = fwrite(&H, sizeof(H), 1, f) == 1 && fwrite(hu.data(), sizeof(double), H.nu, f) == (size_t)H.nu &&
+                    fwrite(hp.data(), sizeof(double), H.np, f) == (size_t)H.np;
+    const bool closed = fclose(f) == 0;
+    return ok && closed ? HB_OK : fail(c, HB_ERR_IO, std::string("write failed: ") + path);
+}
+
+int hb_checkpoint_read(hb_ctx* ctx, const char* path, double* u, double* p, int64_t* step, double* t)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
+    if (!path || !u || !p) return fail(c, HB_ERR_ARG, "null argument");
+    const Cav& v = c->cv[0];
+    CkptHeader want, H;
+    ckpt_header_of(v, &want);
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(c, HB_ERR_IO, std::string("cannot open for reading: ") + path);
+    std::vector<double> hu, hp;
+    bool ok = fread(&H, sizeof(H), 1, f) == 1;
+    if (ok && (memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 1)) {
+        fclose(f);
+        return fail(c, HB_ERR_IO, std::string("not a checkpoint of this format: ") + path);
+    }
+    if (ok) {
+        bool same = H.dim == want.dim && H.nu == want.nu && H.np == want.np && H.h == want.h;
+        for (int a = 0; a < 3; ++a) same = same && H.n[a] == want.n[a] && H.per[a] == want.per[a];
+        if (!same) {
+            fclose(f);
+            return fail(c, HB_ERR_ARG, "the checkpoint's grid differs from the context's");
+        }
+        hu.resize(H.nu);
+        hp.resize(H.np);
+        ok = fread(hu.data(), sizeof(double), H.nu, f) == (size_t)H.nu &&
+             fread(hp.data(), sizeof(double), H.np, f) == (size_t)H.np;
+    }
+    fclose(f);
+    if (!ok) return fail(c, HB_ERR_IO, std::string("truncated checkpoint: ") + path);
+    {
+        StreamGuard guard(c);
+        if (hipMemcpyAsync(u, hu.data(), sizeof(double) * H.nu, hipMemcpyHostToDevice, c->s) != hipSuccess ||
+            hipMemcpyAsync(p, hp.data(), sizeof(double) * H.np, hipMemcpyHostToDevice, c->s) != hipSuccess ||
+            hipStreamSynchronize(c->s) != hipSuccess)
+            return fail(c, HB_ERR_DEVICE, "host to device copy failed");
+    }
+    if (step) *step = H.step;
+    if (t) *t = H.t;
     return HB_OK;
 }
 

@@ -27,6 +27,8 @@ struct FluidD {
 // scalar slots of each cavity (device doubles, S_NSLOT per cavity)
 enum Slot {
     S_MAX = 0, S_SUM = 1, S_DOT0 = 2, S_DOT1 = 3, S_MAXU = 4, S_MAX2 = 5, S_DT = 6,
+    // steady-state driver: largest change of u over a step, largest |u| before it
+    S_CHG = 13, S_CHGREF = 14,
     // BiCGStab scalars, computed and used on the device
     S_RHO = 8, S_RHOP = 9, S_ALPHA = 10, S_OMEGA = 11, S_BETA = 12,
     S_NSLOT = 16
@@ -258,6 +260,7 @@ struct Ctx {
     MG visc, mac, nodal;
     // solve arenas over the batch (offsets from the level-0 tables)
     double *macphi = nullptr, *ustar = nullptr, *phi = nullptr;
+    double* uold = nullptr;   // steady-state driver: u before the step (allocated on first use)
     // Krylov vectors (tensor problem, arena layout)
     double *kr = nullptr, *krh = nullptr, *kp = nullptr, *kv = nullptr, *kph = nullptr, *ks = nullptr,
            *ksh = nullptr, *kt = nullptr;
@@ -314,6 +317,11 @@ void launch_max_final(Ctx* c, const int* act, int slot);
 // ---- reductions and vector kernels (hb_reduce.hip) -------------------------
 // single-array forms, result into slot of cavity cav
 void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot);
+void red_maxdiff(Ctx* c, int cav, const double* a, const double* b, long n, int slot);
+// grid sequencing (hb_seq.hip): velocity and pressure of grid gc carried to
+// gf, the grid refined by two along every used axis
+void launch_refine_state(Ctx* c, const GridD& gc, const GridD& gf, const double* uc, const double* pc, double* uf,
+                         double* pf);
 void set_slot(Ctx* c, int cav, int slot, double v);
 // true when this finest-level smoother launch is to be timed (the timer is
 // on and the launch is the period-th since the last timed one)

@@ -43,6 +43,27 @@ void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot)
     k_maxabs<<<blocks_for(n, kRedBlocks), kT, 0, c->s>>>(v, n, out);
 }
 
+// largest |a - b| (the change of a field over a step)
+__global__ void k_maxdiff(const double* __restrict__ a, const double* __restrict__ b, long n, double* __restrict__ out)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    unsigned long long m = 0ull;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const unsigned long long d = abits(a[i] - b[i]);
+        m = d > m ? d : m;
+    }
+    m = block_umax(m, sh);
+    if (threadIdx.x == 0) atomic_max_bits(out, m);
+}
+
+void red_maxdiff(Ctx* c, int cav, const double* a, const double* b, long n, int slot)
+{
+    double* out = c->sc + (long)cav * S_NSLOT + slot;
+    k_set<<<1, 1, 0, c->s>>>(out, 0.0);
+    if (n <= 0) return;
+    k_maxdiff<<<blocks_for(n, kRedBlocks), kT, 0, c->s>>>(a, b, n, out);
+}
+
 // Publication of the slots: one block copies them into the coherent pinned
 // mirror, every thread makes its writes visible system-wide, then one
 // release store sets the publication word.  The host spins on that word: it

@@ -14,14 +14,15 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhb.so")
 
-OK, ERR_ARG, ERR_DEVICE, ERR_NOCONV, ERR_NONFINITE, ERR_OOM = 0, -1, -2, -3, -4, -5
+OK, ERR_ARG, ERR_DEVICE, ERR_NOCONV, ERR_NONFINITE, ERR_OOM, ERR_IO = 0, -1, -2, -3, -4, -5, -6
 BC_WALL, BC_PERIODIC = 0, 1
 REG_PAPER, REG_YIELD_ONLY = 0, 1
 OP_VISC, OP_NODAL, OP_MAC = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 ERR_NAMES = {OK: "HB_OK", ERR_ARG: "HB_ERR_ARG", ERR_DEVICE: "HB_ERR_DEVICE",
-             ERR_NOCONV: "HB_ERR_NOCONV", ERR_NONFINITE: "HB_ERR_NONFINITE", ERR_OOM: "HB_ERR_OOM"}
+             ERR_NOCONV: "HB_ERR_NOCONV", ERR_NONFINITE: "HB_ERR_NONFINITE", ERR_OOM: "HB_ERR_OOM",
+             ERR_IO: "HB_ERR_IO"}
 
 # symbols declared in include/hb.h
 EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_solve",
@@ -29,7 +30,8 @@ EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_so
            "hb_step_batch", "hb_nn_create", "hb_nn_destroy", "hb_nn_param_count", "hb_nn_get_params",
            "hb_nn_set_params", "hb_nn_forward", "hb_nn_grad", "hb_nn_train_step", "hb_set_warm_start",
            "hb_warm_start_uses", "hb_capture", "hb_capture_read", "hb_kernel_timing", "hb_kernel_timing_read",
-           "hb_tile_config"]
+           "hb_tile_config", "hb_run_steady", "hb_refine_state", "hb_run_sequenced", "hb_checkpoint_write",
+           "hb_checkpoint_read"]
 
 
 class Grid(C.Structure):
@@ -59,6 +61,10 @@ class StepOpts(C.Structure):
 class StepReport(C.Structure):
     _fields_ = [("dt", C.c_double), ("max_u", C.c_double), ("div_mac_rel", C.c_double),
                 ("div_node", C.c_double), ("mac", MGReport), ("visc", MGReport), ("proj", MGReport)]
+
+
+class SteadyReport(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("steady", C.c_int32), ("t", C.c_double), ("change", C.c_double)]
 
 
 _lib = None
@@ -106,6 +112,12 @@ def load():
     L.hb_capture_read.argtypes = [vp, C.c_int, vp, vp]
     L.hb_kernel_timing.argtypes = [vp, C.c_int]
     L.hb_kernel_timing_read.argtypes = [vp, P(C.c_int64), P(C.c_double), P(C.c_double)]
+    L.hb_run_steady.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.c_double, P(SteadyReport)]
+    L.hb_refine_state.argtypes = [vp, vp, vp, vp, vp]
+    L.hb_run_sequenced.argtypes = [P(Grid), P(Fluid), P(StepOpts), C.c_int, C.c_double, C.c_int, vp, vp, vp,
+                                   P(SteadyReport)]
+    L.hb_checkpoint_write.argtypes = [vp, C.c_char_p, vp, vp, C.c_int64, C.c_double]
+    L.hb_checkpoint_read.argtypes = [vp, C.c_char_p, vp, vp, P(C.c_int64), P(C.c_double)]
     _lib = L
     return L
 
@@ -139,6 +151,17 @@ def make_grid(dim, n, h=None, bc=None, wall_u=None):
 def lid_cavity(dim, n, U=1.0):
     """Unit lid-driven cavity: y-hi lid moving +x (2D), z-hi lid moving +x (3D)."""
     return make_grid(dim, [n] * dim, 1.0 / n, wall_u={(dim - 1, 1): (U, 0.0, 0.0)})
+
+
+def refined_grid(g):
+    """The grid refined by two along every used axis (half the spacing, the
+    same boundaries): the next grid of a sequenced run."""
+    r = Grid()
+    C.memmove(C.byref(r), C.byref(g), C.sizeof(Grid))
+    for a in range(g.dim):
+        r.n[a] = 2 * g.n[a]
+    r.h = g.h / 2.0
+    return r
 
 
 def make_fluid(Re=1.0, HB=0.0, n=1.0, Pa=1e3, reg=REG_PAPER, f=(0.0, 0.0, 0.0)):
@@ -324,6 +347,59 @@ class Context:
                             C.byref(rep) if report else None)
         self._check(rc, allow)
         return rep
+
+    def run_steady(self, u, p, tol=1e-5, max_steps=10000, dt=0.0, allow=(ERR_NOCONV,)):
+        """hb_run_steady: step until steady; returns (SteadyReport, rc)"""
+        rep = SteadyReport()
+        rc = load().hb_run_steady(self._h, _ptr(u, self.nvel, "u"), _ptr(p, self.nnode, "p"), float(tol),
+                                  int(max_steps), float(dt), C.byref(rep))
+        self._check(rc, allow)
+        return rep, rc
+
+    def refine_state(self, u_coarse, p_coarse, u, p):
+        """hb_refine_state: the coarser grid's state onto this context's grid"""
+        cg = Grid()
+        C.memmove(C.byref(cg), C.byref(self.grid), C.sizeof(Grid))
+        for a in range(cg.dim):
+            cg.n[a] //= 2
+        ncn = 1
+        for s in node_shape(cg):
+            ncn *= s
+        nc = cg.dim * cg.n[0] * cg.n[1] * cg.n[2]
+        self._check(load().hb_refine_state(self._h, _ptr(u_coarse, nc, "u_coarse"), _ptr(p_coarse, ncn, "p_coarse"),
+                                           _ptr(u, self.nvel, "u"), _ptr(p, self.nnode, "p")))
+
+    def checkpoint_write(self, path, u, p, step=0, t=0.0):
+        self._check(load().hb_checkpoint_write(self._h, os.fsencode(path), _ptr(u, self.nvel, "u"),
+                                               _ptr(p, self.nnode, "p"), int(step), float(t)))
+
+    def checkpoint_read(self, path, u, p):
+        """reads (u, p) in place; returns (step, t)"""
+        st, t = C.c_int64(), C.c_double()
+        self._check(load().hb_checkpoint_read(self._h, os.fsencode(path), _ptr(u, self.nvel, "u"),
+                                              _ptr(p, self.nnode, "p"), C.byref(st), C.byref(t)))
+        return st.value, t.value
+
+
+def run_sequenced(coarse, fluid, opts, levels, u, p, tol=1e-5, max_steps=10000, stream=None, allow=(ERR_NOCONV,)):
+    """hb_run_sequenced: from rest on `coarse` to steady state, refined
+    `levels` times; u, p on the finest grid.  Returns (reports, rc)."""
+    L = load()
+    g = coarse
+    for _ in range(levels):
+        g = refined_grid(g)
+    nn = 1
+    for s in node_shape(g):
+        nn *= s
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    reps = (SteadyReport * (levels + 1))()
+    rc = L.hb_run_sequenced(C.byref(coarse), C.byref(fluid), C.byref(opts), int(levels), float(tol), int(max_steps),
+                            C.c_void_p(stream.cuda_stream), _ptr(u, g.dim * g.n[0] * g.n[1] * g.n[2], "u"),
+                            _ptr(p, nn, "p"), reps)
+    if rc != OK and rc not in allow:
+        raise HBError(rc, L.hb_last_error(None).decode())
+    return list(reps), rc
 
 
 class BatchContext:

@@ -37,15 +37,17 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_1803_00417_amd import hb
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hb.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                    'sizeof(hb_grid),sizeof(hb_fluid),sizeof(hb_mg_opts),sizeof(hb_mg_report),'
                    'sizeof(hb_step_opts),sizeof(hb_step_report),offsetof(hb_grid,wall_u),'
-                   'offsetof(hb_step_opts,proj));return 0;}\n')
+                   'offsetof(hb_step_opts,proj),sizeof(hb_steady_report),offsetof(hb_steady_report,change));'
+                   'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(hb.Grid), C.sizeof(hb.Fluid), C.sizeof(hb.MGOpts), C.sizeof(hb.MGReport),
-            C.sizeof(hb.StepOpts), C.sizeof(hb.StepReport), hb.Grid.wall_u.offset, hb.StepOpts.proj.offset]
+            C.sizeof(hb.StepOpts), C.sizeof(hb.StepReport), hb.Grid.wall_u.offset, hb.StepOpts.proj.offset,
+            C.sizeof(hb.SteadyReport), hb.SteadyReport.change.offset]
     assert got == want
 
 
@@ -72,4 +74,17 @@ def test_create_rejects_invalid_descriptors_without_device_work():
     assert L.hb_create(C.byref(g), C.byref(fl), C.byref(bad), None, C.byref(h)) == hb.ERR_ARG
     # null context is rejected by every entry point
     assert L.hb_step(None, None, None, 0.0, None) == hb.ERR_ARG
+    assert L.hb_run_steady(None, None, None, 1e-5, 10, 0.0, None) == hb.ERR_ARG
+    assert L.hb_refine_state(None, None, None, None, None) == hb.ERR_ARG
+    assert L.hb_checkpoint_write(None, b"x", None, None, 0, 0.0) == hb.ERR_ARG
+    assert L.hb_checkpoint_read(None, b"x", None, None, None, None) == hb.ERR_ARG
+    # the sequenced driver checks its arguments before it creates anything
+    reps = (hb.SteadyReport * 2)()
+    one = C.c_void_p(1)
+    assert L.hb_run_sequenced(None, C.byref(fl), C.byref(opts), 1, 1e-5, 10, None, one, one, reps) == hb.ERR_ARG
+    assert L.hb_run_sequenced(C.byref(g), C.byref(fl), C.byref(opts), 9, 1e-5, 10, None, one, one, reps) == hb.ERR_ARG
+    assert L.hb_run_sequenced(C.byref(g), C.byref(fl), C.byref(opts), 1, 0.0, 10, None, one, one, reps) == hb.ERR_ARG
+    assert L.hb_run_sequenced(C.byref(bad_grids[0]), C.byref(fl), C.byref(opts), 1, 1e-5, 10, None, one, one,
+                              reps) == hb.ERR_ARG
+    assert len(L.hb_last_error(None)) > 0
     assert L.hb_viscosity(None, None, None) == hb.ERR_ARG

@@ -1,0 +1,188 @@
+"""GPU parity of the steady-state driver, grid sequencing and checkpoints
+(Sec. III.A steadiness test, Sec. III.C sequencing and restart) against the
+oracle's driver (oracle/steady.py), through the C ABI.
+
+Bars: the refinement is bit-exact (the same IEEE operations in the same
+order on both sides); driven runs take the same number of steps as the
+oracle and end within 1e-9 relative of its state (the per-step difference is
+rounding, about 1e-13, carried through a few hundred dissipative steps); a
+restart from a checkpoint continues bit for bit.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import orc, steady
+from paper_1803_00417_amd import inputs
+from tests.helpers import dev, hip_objs, host, lid_spec, oracle_objs, rel_err, spec
+
+pytestmark = pytest.mark.gpu
+
+hb = pytest.importorskip("paper_1803_00417_amd.hb")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# fine grids; the state is refined from the grid one level below
+REFINE = {
+    "lid2d_32": lambda: lid_spec(2, 32, Re=100.0, HB=1.0, Pa=1e3),
+    "per2d_32": lambda: spec(2, 32, bc=((1, 1), (1, 1)), Re=10.0, HB=0.5, Pa=100.0),
+    "chan2d_8x32": lambda: spec(2, [8, 32], h=1.0 / 32, bc=((1, 1), (0, 0)), wall_u={(1, 0): (0.3, -0.2, 0.0)},
+                                Re=1.0, HB=0.2, Pa=1e3),
+    "lid3d_16": lambda: lid_spec(3, 16, Re=100.0, HB=2.0, Pa=1e3),
+    "mix3d_12x16x8": lambda: spec(3, [12, 16, 8], h=1.0 / 16, bc=((1, 1), (0, 0), (0, 0)),
+                                  wall_u={(2, 1): (1.0, 0.5, 0.0), (1, 0): (0.0, 0.0, 0.25)}, Re=20.0, HB=1.0,
+                                  Pa=200.0),
+}
+
+
+def _coarse_oracle_grid(s):
+    sc = dict(s)
+    sc["n"] = [v // 2 for v in s["n"]]
+    sc["h"] = 2.0 * s["h"]
+    return oracle_objs(sc)[0]
+
+
+@pytest.mark.parametrize("case", list(REFINE))
+def test_refine_state_bit_exact(case):
+    _say("refine", case)
+    s = REFINE[case]()
+    gc = _coarse_oracle_grid(s)
+    g, fl = hip_objs(s)
+    ctx = hb.Context(g, fl)
+    uc = inputs.random_cells(orc.cell_shape(gc, s["dim"]), seed=11, scale=0.8)
+    pc = inputs.random_cells(orc.node_shape(gc), seed=12, scale=2.0)
+    uf_o = steady.refine_cells(gc, uc)
+    pf_o = steady.refine_nodes(gc, pc)
+    gf = steady.refined_grid(gc)
+    uf = dev(np.zeros(orc.cell_shape(gf, s["dim"])))
+    pf = dev(np.zeros(orc.node_shape(gf)))
+    ctx.refine_state(dev(uc), dev(pc), uf, pf)
+    np.testing.assert_array_equal(host(uf), uf_o)
+    np.testing.assert_array_equal(host(pf), pf_o)
+
+
+def _run_both(s, tol=1e-5, max_steps=4000, dt=0.0):
+    go, flo = oracle_objs(s)
+    o = orc.make_step_opts()
+    u_o = np.zeros(orc.cell_shape(go, s["dim"]))
+    p_o = np.zeros(orc.node_shape(go))
+    r_o = steady.run_steady(go, flo, o, u_o, p_o, tol=tol, max_steps=max_steps, dt=dt)
+    g, fl = hip_objs(s)
+    ctx = hb.Context(g, fl)
+    u = dev(np.zeros_like(u_o))
+    p = dev(np.zeros_like(p_o))
+    rep, rc = ctx.run_steady(u, p, tol=tol, max_steps=max_steps, dt=dt)
+    return r_o, u_o, p_o, rep, rc, host(u), host(p)
+
+
+@pytest.mark.parametrize("case", ["lid2d_16", "chan2d_4x16"])
+def test_run_steady_parity(case):
+    _say("run_steady", case)
+    if case == "lid2d_16":
+        s, dt = lid_spec(2, 16, Re=100.0, HB=1.0, Pa=1e3), 0.0
+    else:
+        # Poiseuille flow from rest: zero velocity, so a constant step
+        s = spec(2, [4, 16], h=1.0 / 16, bc=((1, 1), (0, 0)), Re=1.0, HB=0.0, reg=hb.REG_YIELD_ONLY,
+                 f=(1.0, 0.0, 0.0))
+        dt = 0.02
+    r_o, u_o, p_o, rep, rc, u, p = _run_both(s, dt=dt)
+    _say("  oracle", r_o, " gpu", rep.steps, rep.steady, rep.t, rep.change)
+    assert r_o["steady"] and rc == hb.OK and rep.steady == 1
+    assert rep.steps == r_o["steps"]
+    assert rep.t == pytest.approx(r_o["t"], rel=1e-12)
+    assert rep.change < 1e-5
+    assert rel_err(u, u_o) <= 1e-9
+    # the pressure of Poiseuille flow is zero up to rounding on both sides, so
+    # its bar is scaled by the larger of the pressure and the velocity
+    scale = max(np.abs(p_o).max(), np.abs(u_o).max())
+    assert np.abs(p - p_o).max() <= 1e-9 * scale
+
+
+def test_run_steady_stops_at_max_steps():
+    _say("run_steady max_steps")
+    s = lid_spec(2, 16, Re=100.0, HB=1.0, Pa=1e3)
+    r_o, u_o, p_o, rep, rc, u, p = _run_both(s, max_steps=7)
+    assert rc == hb.ERR_NOCONV and rep.steps == 7 and rep.steady == 0
+    assert r_o["steps"] == 7 and not r_o["steady"]
+    assert rep.change == pytest.approx(r_o["change"], rel=1e-9)
+    assert rel_err(u, u_o) <= 1e-11
+
+
+def test_run_sequenced_parity():
+    _say("run_sequenced 8 -> 16 -> 32")
+    s = lid_spec(2, 8, Re=100.0, HB=1.0, Pa=1e3)
+    go, flo = oracle_objs(s)
+    gfin, u_o, p_o, reps_o = steady.sequence(go, flo, orc.make_step_opts(), 2)
+    g, fl = hip_objs(s)
+    u = dev(np.zeros(orc.cell_shape(gfin, 2)))
+    p = dev(np.zeros(orc.node_shape(gfin)))
+    reps, rc = hb.run_sequenced(g, fl, hb.make_step_opts(), 2, u, p)
+    _say("  oracle", [r["steps"] for r in reps_o], " gpu", [r.steps for r in reps])
+    assert rc == hb.OK
+    assert [r.steps for r in reps] == [r["steps"] for r in reps_o]
+    assert all(r.steady == 1 for r in reps)
+    assert rel_err(host(u), u_o) <= 1e-9
+    assert rel_err(host(p), p_o) <= 1e-9
+
+
+def test_checkpoint_restart_continues_bit_for_bit(tmp_path):
+    _say("checkpoint restart")
+    s = lid_spec(2, 32, Re=100.0, HB=1.0, Pa=1e3)
+    g, fl = hip_objs(s)
+    ctx = hb.Context(g, fl)
+    u = dev(np.zeros(hb.cell_shape(g, 2)))
+    p = dev(np.zeros(hb.node_shape(g)))
+    t = 0.0
+    for _ in range(5):
+        t += ctx.step(u, p).dt
+    path = str(tmp_path / "run.ckpt")
+    ctx.checkpoint_write(path, u, p, step=5, t=t)
+    assert os.path.getsize(path) == 80 + 8 * (u.numel() + p.numel())
+    for _ in range(5):
+        ctx.step(u, p, report=False)
+    ua, pa = host(u), host(p)
+    ctx2 = hb.Context(g, fl)
+    u2 = dev(np.full(hb.cell_shape(g, 2), 7.0))
+    p2 = dev(np.full(hb.node_shape(g), -3.0))
+    assert ctx2.checkpoint_read(path, u2, p2) == (5, t)
+    for _ in range(5):
+        ctx2.step(u2, p2, report=False)
+    np.testing.assert_array_equal(host(u2), ua)
+    np.testing.assert_array_equal(host(p2), pa)
+    # a checkpoint of another grid, a missing file, a truncated file and a
+    # file that is no checkpoint are refused and leave the arrays alone
+    g3, fl3 = hip_objs(lid_spec(2, 16))
+    ctx3 = hb.Context(g3, fl3)
+    u3 = dev(np.zeros(hb.cell_shape(g3, 2)))
+    p3 = dev(np.zeros(hb.node_shape(g3)))
+    with pytest.raises(hb.HBError) as e:
+        ctx3.checkpoint_read(path, u3, p3)
+    assert e.value.code == hb.ERR_ARG
+    with pytest.raises(hb.HBError) as e:
+        ctx2.checkpoint_read(str(tmp_path / "missing.ckpt"), u2, p2)
+    assert e.value.code == hb.ERR_IO
+    data = open(path, "rb").read()
+    (tmp_path / "short.ckpt").write_bytes(data[:-8])
+    with pytest.raises(hb.HBError) as e:
+        ctx2.checkpoint_read(str(tmp_path / "short.ckpt"), u2, p2)
+    assert e.value.code == hb.ERR_IO
+    (tmp_path / "junk.ckpt").write_bytes(b"x" * len(data))
+    with pytest.raises(hb.HBError) as e:
+        ctx2.checkpoint_read(str(tmp_path / "junk.ckpt"), u2, p2)
+    assert e.value.code == hb.ERR_IO
+    np.testing.assert_array_equal(host(u3), 0.0)
+
+
+def test_run_steady_rejects_bad_arguments():
+    g, fl = hip_objs(lid_spec(2, 16))
+    ctx = hb.Context(g, fl)
+    u = dev(np.zeros(hb.cell_shape(g, 2)))
+    p = dev(np.zeros(hb.node_shape(g)))
+    for tol, ms in ((0.0, 10), (-1.0, 10), (1e-5, 0)):
+        with pytest.raises(hb.HBError) as e:
+            ctx.run_steady(u, p, tol=tol, max_steps=ms)
+        assert e.value.code == hb.ERR_ARG
