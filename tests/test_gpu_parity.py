@@ -244,3 +244,55 @@ def test_error_paths():
     with pytest.raises(hb.HBError) as e:
         ctx.mg_solve(hb.OP_VISC, None, 0.1, dev(np.zeros((2,) + rhs.shape[1:])), dev(np.zeros((2,) + rhs.shape[1:])))
     assert e.value.code == hb.ERR_ARG
+
+
+@pytest.mark.parametrize("op", [hb.OP_VISC, hb.OP_MAC, hb.OP_NODAL])
+def test_zero_rhs_gives_zero_without_cycles(op):
+    # |b| = 0: the stopping test holds before the first cycle and x = 0
+    # (walls at rest: a moving wall would put its values into the viscous
+    # solve's right-hand side)
+    _say("zero rhs", op)
+    s = spec(2, [96, 48], h=1.0 / 96, Re=50.0, HB=2.0, nidx=0.7, Pa=300.0)
+    go, flo = oracle_objs(s)
+    ctx, g, fl = _ctx(s)
+    sh = {hb.OP_VISC: orc.cell_shape(go, 2), hb.OP_MAC: orc.cell_shape(go)[1:], hb.OP_NODAL: orc.node_shape(go)}[op]
+    eta = dev(np.ones(orc.cell_shape(go)[1:])) if op == hb.OP_VISC else None
+    x = dev(inputs.random_cells(sh, seed=9))
+    rep, rc = ctx.mg_solve(op, eta, 0.01, dev(np.zeros(sh)), x, hb.mg_opts())
+    assert rc == hb.OK and rep.cycles == 0
+    assert float(x.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_smallest_grid_step_parity(dim):
+    # 4 cells per axis, the smallest grid the library takes: less than one
+    # tile, two multigrid levels
+    _say("smallest grid", dim)
+    s = lid_spec(dim, 4, Re=10.0, HB=1.0, Pa=100.0)
+    go, flo = oracle_objs(s)
+    ctx, g, fl = _ctx(s)
+    o = orc.make_step_opts()
+    u_o = np.zeros(orc.cell_shape(go, dim))
+    p_o = np.zeros(orc.node_shape(go))
+    u, p = dev(u_o), dev(p_o)
+    for _ in range(3):
+        rep_o, rc_o = orc.step(go, flo, o, u_o, p_o)
+        assert rc_o == orc.OK
+        ctx.step(u, p)
+    assert rel_err(host(u), u_o) <= 1e-9
+    assert rel_err(host(p), p_o) <= 1e-9
+
+
+def test_rest_without_lid_needs_a_step():
+    # no moving wall and u = 0: the CFL step is undefined, so dt <= 0 is
+    # refused before any device work, while a given dt steps (and stays at rest)
+    _say("rest without lid")
+    s = spec(2, 16, bc=((1, 1), (1, 1)), Re=10.0, HB=0.5, Pa=100.0)
+    ctx, g, fl = _ctx(s)
+    u = dev(np.zeros(hb.cell_shape(g, 2)))
+    p = dev(np.zeros(hb.node_shape(g)))
+    with pytest.raises(hb.HBError) as e:
+        ctx.step(u, p)
+    assert e.value.code == hb.ERR_ARG
+    rep = ctx.step(u, p, dt=0.01)
+    assert rep.dt == 0.01 and float(u.abs().max()) == 0.0 and float(p.abs().max()) == 0.0
