@@ -186,3 +186,33 @@ def test_run_steady_rejects_bad_arguments():
         with pytest.raises(hb.HBError) as e:
             ctx.run_steady(u, p, tol=tol, max_steps=ms)
         assert e.value.code == hb.ERR_ARG
+
+
+def test_run_steady_parity_3d():
+    _say("run_steady 3D 8^3")
+    s = lid_spec(3, 8, Re=100.0, HB=1.0, Pa=1e3)
+    r_o, u_o, p_o, rep, rc, u, p = _run_both(s)
+    _say("  oracle", r_o["steps"], " gpu", rep.steps)
+    assert r_o["steady"] and rc == hb.OK and rep.steady == 1
+    assert rep.steps == r_o["steps"]
+    assert rel_err(u, u_o) <= 1e-9
+    assert np.abs(p - p_o).max() <= 1e-9 * max(np.abs(p_o).max(), np.abs(u_o).max())
+
+
+def test_run_sequenced_3d_refines_an_unsettled_grid():
+    # 4^3 does not settle within 300 steps: it is refined all the same, 8^3
+    # then settles, and the call reports HB_ERR_NOCONV for the first grid
+    _say("run_sequenced 3D 4 -> 8")
+    s = lid_spec(3, 4, Re=100.0, HB=1.0, Pa=1e3)
+    go, flo = oracle_objs(s)
+    gfin, u_o, p_o, reps_o = steady.sequence(go, flo, orc.make_step_opts(), 1, max_steps=300)
+    g, fl = hip_objs(s)
+    u = dev(np.zeros(orc.cell_shape(gfin, 3)))
+    p = dev(np.zeros(orc.node_shape(gfin)))
+    reps, rc = hb.run_sequenced(g, fl, hb.make_step_opts(), 1, u, p, max_steps=300)
+    _say("  oracle", [(r["steps"], r["steady"]) for r in reps_o], " gpu", [(r.steps, r.steady) for r in reps])
+    assert [r["steady"] for r in reps_o] == [False, True]
+    assert rc == hb.ERR_NOCONV
+    assert [r.steps for r in reps] == [r["steps"] for r in reps_o]
+    assert [r.steady for r in reps] == [0, 1]
+    assert rel_err(host(u), u_o) <= 1e-9
