@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--steady", type=int, default=256, metavar="N",
                     help="time to steady state on an N^2 cavity, from rest and by grid sequencing from "
-                         "(N/4)^2 (0: skip)")
+                         "(N/4)^2, then the cessation of the steady flow (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -168,6 +168,18 @@ def run_steady(n, levels=2, tol=1e-5, max_steps=12000):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     diff = float((us - u).abs().max() / u.abs().max())
+    # cessation (Sec. IV): the lid of the sequenced steady state stops; a
+    # constant step h/2 (the CFL step at lid speed), since the CFL step would
+    # grow without bound as the flow comes to rest
+    gr = hb.make_grid(2, [n, n], 1.0 / n)
+    ctx = hb.Context(gr, fl, opts)
+    y0 = ctx.yield_test(us)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    crep, crc = ctx.run_cessation(us, ps, max_steps=max_steps, dt=0.5 / n)
+    torch.cuda.synchronize()
+    t_cess = time.perf_counter() - t0
+    ctx.close()
     return {
         "workload": "2D lid-driven cavity %d^2, Bingham HB=1, Re=100, Pa=100, from rest to steady state "
                     "(largest relative change of u over a step below %g)" % (n, tol),
@@ -176,6 +188,8 @@ def run_steady(n, levels=2, tol=1e-5, max_steps=12000):
                       "steady": [bool(r.steady) for r in reps], "s": t_seq},
         "speedup": t_direct / t_seq,
         "max_rel_diff_of_final_u": diff,
+        "cessation": {"yielded_fraction_at_steady_state": y0.yielded / y0.cells, "dt": 0.5 / n,
+                      "steps": crep.steps, "stopped": bool(crep.stopped), "t_c": crep.t, "s": t_cess},
     }
 
 

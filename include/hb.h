@@ -253,6 +253,43 @@ int hb_run_sequenced(const hb_grid* coarse, const hb_fluid* fluid, const hb_step
 int hb_checkpoint_write(hb_ctx* ctx, const char* path, const double* u, const double* p, int64_t step, double t);
 int hb_checkpoint_read(hb_ctx* ctx, const char* path, double* u, double* p, int64_t* step, double* t);
 
+/* ---- yield surfaces and cessation ------------------------------------------
+ * Yield test (Sec. II, Sec. IV): in the dimensionless variables the stress
+ * is 2 eta gamma_dot, its magnitude 2 eta g (g = |gamma_dot| as in
+ * hb_viscosity, eta the regularised apparent viscosity) and the yield
+ * stress HB.  A cell is yielded where 2 eta g > HB; the unyielded cells form
+ * the plugs and dead zones whose boundaries are the yield surfaces.
+ *
+ * hb_yield: u [dim][cells] in; mask (nullable, device, caller-owned,
+ * [cells] bytes) receives 1 for a yielded cell, 0 otherwise; report
+ * (nullable; non-null waits for the result): the number of yielded cells,
+ * the cell count and the largest stress magnitude.  Single-cavity contexts.
+ *
+ * hb_run_cessation (the cessation experiment of Sec. IV): from a state,
+ * typically steady, of a run whose lid is then stopped, step (u, p) in
+ * place on the context (create it with the walls at rest; dt <= 0: CFL
+ * steps, else that constant step) until no cell is yielded, tested before
+ * the first step and after each, or max_steps steps have run.  Returns
+ * HB_OK once the flow has stopped, HB_ERR_NOCONV when max_steps ran out or a
+ * solve of the last step did not converge, HB_ERR_ARG for HB <= 0 (no yield
+ * stress, so no finite stopping), other codes as hb_step.  report
+ * (nullable): steps run, stopped flag, simulated time (the cessation time
+ * when stopped). */
+typedef struct {
+    int64_t yielded;    /* cells with 2 eta g > HB */
+    int64_t cells;      /* all cells */
+    double max_stress;  /* largest 2 eta g */
+} hb_yield_report;
+
+typedef struct {
+    int32_t steps;    /* steps run */
+    int32_t stopped;  /* 1 when no cell is yielded */
+    double t;         /* simulated time of those steps */
+} hb_cessation_report;
+
+int hb_yield(hb_ctx* ctx, const double* u, uint8_t* mask, hb_yield_report* report);
+int hb_run_cessation(hb_ctx* ctx, double* u, double* p, int max_steps, double dt, hb_cessation_report* report);
+
 /* ---- learned warm start (BF16 U-Net on the matrix cores) -----------------
  * A small convolutional U-Net (4 levels, 16/32/64/64 channels, two 3x3
  * convolutions with ReLU per level, average pooling down, nearest upsampling

@@ -1837,6 +1837,77 @@ int hb_run_sequenced(const hb_grid* coarse, const hb_fluid* fluid, const hb_step
     return rc;
 }
 
+// yield test of the state u: count of yielded cells and largest stress
+// magnitude in the slots S_SUM and S_MAX (read after fetch_slots)
+static void yield_slots(Ctx* c, const double* u, unsigned char* mask)
+{
+    set_slot(c, 0, S_SUM, 0.0);
+    set_slot(c, 0, S_MAX, 0.0);
+    double* sc = c->sc;
+    launch_yield(c, c->cv[0], u, mask, sc + S_SUM, sc + S_MAX);
+}
+
+int hb_yield(hb_ctx* ctx, const double* u, uint8_t* mask, hb_yield_report* report)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
+    if (!u) return fail(c, HB_ERR_ARG, "null array");
+    StreamGuard guard(c);
+    yield_slots(c, u, mask);
+    if (report) {
+        fetch_slots(c);
+        report->yielded = (int64_t)slot(c, 0, S_SUM);
+        report->cells = c->cv[0].nc;
+        report->max_stress = slot(c, 0, S_MAX);
+    }
+    return hipGetLastError() == hipSuccess ? HB_OK : fail(c, HB_ERR_DEVICE, "kernel launch failed");
+}
+
+int hb_run_cessation(hb_ctx* ctx, double* u, double* p, int max_steps, double dt, hb_cessation_report* report)
+{
+    if (!ctx) return HB_ERR_ARG;
+    Ctx* c = C_(ctx);
+    if (single_only(c)) return HB_ERR_ARG;
+    if (!u || !p) return fail(c, HB_ERR_ARG, "null array");
+    if (max_steps < 1) return fail(c, HB_ERR_ARG, "max_steps must be >= 1");
+    if (!(c->cv[0].fluid.HB > 0.0)) return fail(c, HB_ERR_ARG, "cessation needs a yield stress (HB > 0)");
+    StreamGuard guard(c);
+    hb_cessation_report R;
+    memset(&R, 0, sizeof(R));
+    yield_slots(c, u, nullptr);
+    fetch_slots(c);
+    int rc = HB_OK;
+    if (slot(c, 0, S_SUM) == 0.0) {
+        R.stopped = 1;
+    } else {
+        rc = HB_ERR_NOCONV;
+        for (int m = 0; m < max_steps; ++m) {
+            const int src = step_all(c, &u, &p, &dt, nullptr);
+            R.steps = m + 1;
+            if (src != HB_OK && src != HB_ERR_NOCONV) {
+                rc = src;
+                break;
+            }
+            yield_slots(c, u, nullptr);
+            fetch_slots(c);
+            R.t += slot(c, 0, S_DT);
+            if (src == HB_ERR_NOCONV) {
+                rc = src;
+                break;
+            }
+            if (slot(c, 0, S_SUM) == 0.0) {
+                R.stopped = 1;
+                rc = HB_OK;
+                break;
+            }
+        }
+    }
+    if (report) *report = R;
+    if (hipGetLastError() != hipSuccess) return fail(c, HB_ERR_DEVICE, "kernel launch failed");
+    return rc;
+}
+
 // checkpoint file: this header, then u ([dim][cells]) and p (nodes) as raw
 // doubles in host byte order
 struct CkptHeader {

@@ -318,6 +318,9 @@ void launch_max_final(Ctx* c, const int* act, int slot);
 // single-array forms, result into slot of cavity cav
 void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot);
 void red_maxdiff(Ctx* c, int cav, const double* a, const double* b, long n, int slot);
+// yield test per cell (hb_visc.hip): mask (nullable), count of yielded cells
+// added to *count, largest stress magnitude max-reduced into *maxtau
+void launch_yield(Ctx* c, const Cav& v, const double* u, unsigned char* mask, double* count, double* maxtau);
 // grid sequencing (hb_seq.hip): velocity and pressure of grid gc carried to
 // gf, the grid refined by two along every used axis
 void launch_refine_state(Ctx* c, const GridD& gc, const GridD& gf, const double* uc, const double* pc, double* uf,

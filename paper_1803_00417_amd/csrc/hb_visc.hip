@@ -23,12 +23,10 @@ __device__ inline double eta_of_g(const FluidD& fl, double g)
     return (pow(g, fl.n) + 0.5 * fl.HB) * fl.Pa * phi;
 }
 
-__global__ void k_viscosity(GridD g, FluidD fl, const double* __restrict__ u, double* __restrict__ eta)
+// g = |gamma_dot| of cell (i, j, k): centred differences with wall ghosts,
+// |A| = sqrt(sum A_ij^2 / 2) (Sec. II)
+__device__ inline double strain_norm_at(const GridD& g, const double* __restrict__ u, int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
     const long N = ncells(g);
     double G[3][3];
     for (int a = 0; a < g.dim; ++a)
@@ -45,12 +43,57 @@ __global__ void k_viscosity(GridD g, FluidD fl, const double* __restrict__ u, do
             const double e = 0.5 * (G[a][c] + G[c][a]);
             s += e * e;
         }
-    eta[cid(g, i, j, k)] = eta_of_g(fl, sqrt(0.5 * s));
+    return sqrt(0.5 * s);
+}
+
+__global__ void k_viscosity(GridD g, FluidD fl, const double* __restrict__ u, double* __restrict__ eta)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.n[0] || j >= g.n[1]) return;
+    eta[cid(g, i, j, k)] = eta_of_g(fl, strain_norm_at(g, u, i, j, k));
+}
+
+// Yield test (Sec. II, Sec. IV): in the dimensionless variables the stress
+// magnitude is 2 eta g and the yield stress HB; a cell is yielded where
+// 2 eta g > HB.  mask (nullable): 1 yielded, 0 not.  The number of yielded
+// cells is summed into *count (integers, exact in any order) and the largest
+// stress magnitude max-reduced into *maxtau.
+__global__ void k_yield(GridD g, FluidD fl, const double* __restrict__ u, unsigned char* __restrict__ mask,
+                        double* __restrict__ count, double* __restrict__ maxtau)
+{
+    __shared__ double shs[64];
+    __shared__ unsigned long long shm[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z;
+    double y = 0.0;
+    unsigned long long tb = 0ull;
+    if (i < g.n[0] && j < g.n[1]) {
+        const double gn = strain_norm_at(g, u, i, j, k);
+        const double tau = 2.0 * eta_of_g(fl, gn) * gn;
+        const bool yl = tau > fl.HB;
+        if (mask) mask[cid(g, i, j, k)] = yl ? 1 : 0;
+        y = yl ? 1.0 : 0.0;
+        tb = abits(tau);
+    }
+    y = block_sum(y, shs);
+    tb = block_umax(tb, shm);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        if (y != 0.0) atomicAdd(count, y);
+        atomic_max_bits(maxtau, tb);
+    }
 }
 
 void launch_viscosity(Ctx* c, const Cav& v, const double* u, double* eta)
 {
     k_viscosity<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, v.fl, u, eta);
+}
+
+void launch_yield(Ctx* c, const Cav& v, const double* u, unsigned char* mask, double* count, double* maxtau)
+{
+    k_yield<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, v.fl, u, mask, count, maxtau);
 }
 
 // ---------------------------------------------------------------------------

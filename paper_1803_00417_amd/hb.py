@@ -31,7 +31,7 @@ EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_so
            "hb_nn_set_params", "hb_nn_forward", "hb_nn_grad", "hb_nn_train_step", "hb_set_warm_start",
            "hb_warm_start_uses", "hb_capture", "hb_capture_read", "hb_kernel_timing", "hb_kernel_timing_read",
            "hb_tile_config", "hb_run_steady", "hb_refine_state", "hb_run_sequenced", "hb_checkpoint_write",
-           "hb_checkpoint_read"]
+           "hb_checkpoint_read", "hb_yield", "hb_run_cessation"]
 
 
 class Grid(C.Structure):
@@ -65,6 +65,14 @@ class StepReport(C.Structure):
 
 class SteadyReport(C.Structure):
     _fields_ = [("steps", C.c_int32), ("steady", C.c_int32), ("t", C.c_double), ("change", C.c_double)]
+
+
+class YieldReport(C.Structure):
+    _fields_ = [("yielded", C.c_int64), ("cells", C.c_int64), ("max_stress", C.c_double)]
+
+
+class CessationReport(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("stopped", C.c_int32), ("t", C.c_double)]
 
 
 _lib = None
@@ -118,6 +126,8 @@ def load():
                                    P(SteadyReport)]
     L.hb_checkpoint_write.argtypes = [vp, C.c_char_p, vp, vp, C.c_int64, C.c_double]
     L.hb_checkpoint_read.argtypes = [vp, C.c_char_p, vp, vp, P(C.c_int64), P(C.c_double)]
+    L.hb_yield.argtypes = [vp, vp, vp, P(YieldReport)]
+    L.hb_run_cessation.argtypes = [vp, vp, vp, C.c_int, C.c_double, P(CessationReport)]
     _lib = L
     return L
 
@@ -368,6 +378,26 @@ class Context:
         nc = cg.dim * cg.n[0] * cg.n[1] * cg.n[2]
         self._check(load().hb_refine_state(self._h, _ptr(u_coarse, nc, "u_coarse"), _ptr(p_coarse, ncn, "p_coarse"),
                                            _ptr(u, self.nvel, "u"), _ptr(p, self.nnode, "p")))
+
+    def yield_test(self, u, mask=None):
+        """hb_yield: YieldReport of the state u; mask (optional uint8 GPU
+        tensor of ncell elements) receives 1 for yielded cells"""
+        if mask is not None:
+            if not isinstance(mask, torch.Tensor) or not mask.is_cuda or mask.dtype != torch.uint8 \
+                    or not mask.is_contiguous() or mask.numel() != self.ncell:
+                raise TypeError("mask must be a contiguous uint8 GPU tensor of %d elements" % self.ncell)
+        rep = YieldReport()
+        self._check(load().hb_yield(self._h, _ptr(u, self.nvel, "u"),
+                                    C.c_void_p(mask.data_ptr()) if mask is not None else None, C.byref(rep)))
+        return rep
+
+    def run_cessation(self, u, p, max_steps=10000, dt=0.0, allow=(ERR_NOCONV,)):
+        """hb_run_cessation: step until no cell is yielded; (CessationReport, rc)"""
+        rep = CessationReport()
+        rc = load().hb_run_cessation(self._h, _ptr(u, self.nvel, "u"), _ptr(p, self.nnode, "p"), int(max_steps),
+                                     float(dt), C.byref(rep))
+        self._check(rc, allow)
+        return rep, rc
 
     def checkpoint_write(self, path, u, p, step=0, t=0.0):
         self._check(load().hb_checkpoint_write(self._h, os.fsencode(path), _ptr(u, self.nvel, "u"),

@@ -37,17 +37,19 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_1803_00417_amd import hb
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hb.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                    'sizeof(hb_grid),sizeof(hb_fluid),sizeof(hb_mg_opts),sizeof(hb_mg_report),'
                    'sizeof(hb_step_opts),sizeof(hb_step_report),offsetof(hb_grid,wall_u),'
-                   'offsetof(hb_step_opts,proj),sizeof(hb_steady_report),offsetof(hb_steady_report,change));'
+                   'offsetof(hb_step_opts,proj),sizeof(hb_steady_report),offsetof(hb_steady_report,change),'
+                   'sizeof(hb_yield_report),sizeof(hb_cessation_report));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(hb.Grid), C.sizeof(hb.Fluid), C.sizeof(hb.MGOpts), C.sizeof(hb.MGReport),
             C.sizeof(hb.StepOpts), C.sizeof(hb.StepReport), hb.Grid.wall_u.offset, hb.StepOpts.proj.offset,
-            C.sizeof(hb.SteadyReport), hb.SteadyReport.change.offset]
+            C.sizeof(hb.SteadyReport), hb.SteadyReport.change.offset, C.sizeof(hb.YieldReport),
+            C.sizeof(hb.CessationReport)]
     assert got == want
 
 
@@ -78,6 +80,8 @@ def test_create_rejects_invalid_descriptors_without_device_work():
     assert L.hb_refine_state(None, None, None, None, None) == hb.ERR_ARG
     assert L.hb_checkpoint_write(None, b"x", None, None, 0, 0.0) == hb.ERR_ARG
     assert L.hb_checkpoint_read(None, b"x", None, None, None, None) == hb.ERR_ARG
+    assert L.hb_yield(None, None, None, None) == hb.ERR_ARG
+    assert L.hb_run_cessation(None, None, None, 10, 0.0, None) == hb.ERR_ARG
     # the sequenced driver checks its arguments before it creates anything
     reps = (hb.SteadyReport * 2)()
     one = C.c_void_p(1)

@@ -1,0 +1,132 @@
+"""GPU parity of the yield diagnostics and the cessation protocol (Sec. II,
+Sec. IV) against the oracle (oracle/yielding.py), through the C ABI.
+
+Bars: the yield mask equals the oracle's cell for cell (the stress is an
+FP64 value compared with HB on both sides; the inputs keep every cell at
+least 1e-5 from the threshold, far above the 1e-13 the two sides can
+differ by), the count matches, and the largest stress agrees to 1e-13;
+cessation runs take the oracle's number of steps and end within 1e-9 of its
+state.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import orc, yielding
+from paper_1803_00417_amd import inputs
+from tests.helpers import dev, hip_objs, host, lid_spec, oracle_objs, rel_err, spec
+
+pytestmark = pytest.mark.gpu
+
+hb = pytest.importorskip("paper_1803_00417_amd.hb")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+CASES = {
+    "lid2d_32": lambda: lid_spec(2, 32, Re=100.0, HB=1.0, Pa=100.0),
+    "lid2d_96x48": lambda: spec(2, [96, 48], h=1.0 / 96, wall_u={(1, 1): (1.0, 0.0, 0.0)}, Re=50.0, HB=2.0,
+                                nidx=0.7, Pa=300.0),
+    "per2d_32": lambda: spec(2, 32, bc=((1, 1), (1, 1)), Re=10.0, HB=0.5, nidx=1.3, Pa=100.0),
+    "lid3d_16": lambda: lid_spec(3, 16, Re=100.0, HB=1.0, Pa=100.0),
+    "mix3d_12x16x8": lambda: spec(3, [12, 16, 8], h=1.0 / 16, bc=((1, 1), (0, 0), (0, 0)),
+                                  wall_u={(2, 1): (1.0, 0.5, 0.0)}, Re=20.0, HB=1.0, nidx=0.6, Pa=200.0),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_yield_mask_parity(case):
+    _say("yield mask", case)
+    s = CASES[case]()
+    go, flo = oracle_objs(s)
+    g, fl = hip_objs(s)
+    ctx = hb.Context(g, fl)
+    u = inputs.smooth_cells(orc.cell_shape(go, s["dim"]), seed=31, scale=0.005 * s["HB"])
+    m_o, tau_o = yielding.yielded(go, flo, u)
+    margin = np.abs(tau_o - flo.HB).min() / flo.HB
+    _say("  yielded fraction %.3f, closest relative distance to the yield stress %.1e" % (m_o.mean(), margin))
+    assert margin > 1e-10 and 0 < m_o.sum() < m_o.size
+    mask = torch.zeros(ctx.ncell, dtype=torch.uint8, device="cuda")
+    rep = ctx.yield_test(dev(u), mask)
+    m = host(mask).reshape(m_o.shape).astype(bool)
+    np.testing.assert_array_equal(m, m_o)
+    assert rep.yielded == int(m_o.sum()) and rep.cells == m_o.size
+    assert rep.max_stress == pytest.approx(tau_o.max(), rel=1e-13)
+    rep2 = ctx.yield_test(dev(u))
+    assert rep2.yielded == rep.yielded and rep2.max_stress == rep.max_stress
+
+
+def _cessation_both(s_moving, s_rest, dt, prepare):
+    go, flo = oracle_objs(s_moving)
+    u0, p0 = prepare(go, flo)
+    gr, flr = oracle_objs(s_rest)
+    u_o, p_o = u0.copy(), p0.copy()
+    r_o = yielding.run_cessation(gr, flr, orc.make_step_opts(), u_o, p_o, max_steps=3000, dt=dt)
+    g, fl = hip_objs(s_rest)
+    ctx = hb.Context(g, fl)
+    u, p = dev(u0), dev(p0)
+    rep, rc = ctx.run_cessation(u, p, max_steps=3000, dt=dt)
+    return r_o, u_o, rep, rc, host(u)
+
+
+def test_cessation_lid_cavity_parity():
+    # steady Bingham cavity (oracle), then the lid stops: constant step h/2
+    _say("cessation lid 16^2")
+    n = 16
+    s_moving = lid_spec(2, n, Re=100.0, HB=1.0, Pa=100.0)
+    s_rest = spec(2, n, Re=100.0, HB=1.0, Pa=100.0)
+
+    def prepare(go, flo):
+        from oracle import steady
+        u = np.zeros(orc.cell_shape(go, 2))
+        p = np.zeros(orc.node_shape(go))
+        r = steady.run_steady(go, flo, orc.make_step_opts(), u, p)
+        assert r["steady"]
+        return u, p
+    r_o, u_o, rep, rc, u = _cessation_both(s_moving, s_rest, 0.5 / n, prepare)
+    _say("  oracle", r_o, " gpu", rep.steps, rep.stopped, rep.t)
+    assert r_o["stopped"] and rc == hb.OK and rep.stopped == 1
+    assert rep.steps == r_o["steps"] and rep.t == pytest.approx(r_o["t"], rel=1e-12)
+    assert np.abs(u - u_o).max() <= 1e-9 * np.abs(u_o).max()
+
+
+def test_cessation_poiseuille_parity():
+    # steady Bingham channel flow, then the driving force is removed
+    _say("cessation channel")
+    ny = 16
+    s_moving = spec(2, [4, ny], h=1.0 / ny, bc=((1, 1), (0, 0)), Re=1.0, HB=0.1, Pa=1e3, f=(1.0, 0.0, 0.0))
+    s_rest = spec(2, [4, ny], h=1.0 / ny, bc=((1, 1), (0, 0)), Re=1.0, HB=0.1, Pa=1e3)
+
+    def prepare(go, flo):
+        from oracle import steady
+        u = np.zeros(orc.cell_shape(go, 2))
+        p = np.zeros(orc.node_shape(go))
+        r = steady.run_steady(go, flo, orc.make_step_opts(), u, p, tol=1e-8, dt=0.02)
+        assert r["steady"]
+        return u, p
+    r_o, u_o, rep, rc, u = _cessation_both(s_moving, s_rest, 0.005, prepare)
+    _say("  oracle", r_o, " gpu", rep.steps, rep.stopped, rep.t)
+    assert r_o["stopped"] and rc == hb.OK and rep.stopped == 1
+    assert rep.steps == r_o["steps"]
+    assert np.abs(u - u_o).max() <= 1e-9 * np.abs(u_o).max() + 1e-15
+
+
+def test_cessation_edge_cases():
+    g, fl = hip_objs(spec(2, 16, Re=100.0, HB=1.0, Pa=100.0))
+    ctx = hb.Context(g, fl)
+    u = dev(np.zeros(hb.cell_shape(g, 2)))
+    p = dev(np.zeros(hb.node_shape(g)))
+    # at rest nothing is yielded: stopped before any step
+    rep, rc = ctx.run_cessation(u, p, max_steps=10, dt=0.01)
+    assert rc == hb.OK and rep.stopped == 1 and rep.steps == 0 and rep.t == 0.0
+    with pytest.raises(hb.HBError) as e:
+        ctx.run_cessation(u, p, max_steps=0, dt=0.01)
+    assert e.value.code == hb.ERR_ARG
+    # no yield stress: the flow never stops in finite time
+    g2, fl2 = hip_objs(spec(2, 16, Re=100.0, HB=0.0, Pa=100.0))
+    ctx2 = hb.Context(g2, fl2)
+    with pytest.raises(hb.HBError) as e:
+        ctx2.run_cessation(u, p, max_steps=10, dt=0.01)
+    assert e.value.code == hb.ERR_ARG
