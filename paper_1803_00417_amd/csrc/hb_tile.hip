@@ -569,8 +569,21 @@ __device__ inline R prolong_at(const GridD& gc, const R* __restrict__ e, int si,
     return prolong_sum<R>(nb, sgn);
 }
 
+// coarse patch of a tile whose prolonged positions need no coarse cell
+// beyond the grid: PW x PH coarse cells per component, from (cx0, cy0)
+template <int H, class CF>
+struct CoarsePatch {
+    static constexpr int PW = (CF::TX + 2 * H) / 2 + 2, PH = (CF::TY + 2 * H) / 2 + 2, PN = PW * PH;
+};
+
 // PRO: x of the fill is x + P e (the coarse correction of a V-cycle folded
-// into the first sweep after it): pe the coarse iterate, gc its grid.
+// into the first sweep after it): pe the coarse iterate, gc its grid.  Where
+// every coarse value the tile's positions read lies inside the coarse grid
+// (no wall image, no periodic wrap), the block first stages that coarse
+// patch in LDS (patch: 2 PN values after the staged arrays) and reads the
+// four values of each position from it; elsewhere each position reads them
+// from global memory after its other loads.  Either way a position adds the
+// same four values in the same order as the prolongation kernel.
 template <bool FINE, int H, typename R, class CF, bool PRO>
 __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, const R* __restrict__ b,
                                    const R* __restrict__ coef, R* s, int ox, int oy, long N,
@@ -583,12 +596,9 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
     const bool inner = ox - H >= 0 && ox + T::TX + H <= g.n[0] && oy - H >= 0 && oy + T::TY + H <= g.n[1];
     const long fo1 = FINE ? 0 : foffset(g, 1);
     R v[NA][K];
-    // PRO: the coarse values of each position, loaded with the rest and
-    // added after every load is in flight
-    constexpr int KP = PRO ? K : 1;
-    R pv[KP][2][4], ps[KP][2];
     bool pok[K], png[K];
-    const long Nc = PRO ? ncells(gc) : 0;
+    constexpr int KP = PRO ? K : 1;
+    int sx[KP], sy[KP];   // PRO: the source cell of each position
 #pragma unroll
     for (int u = 0; u < K; ++u) {
         const int t = threadIdx.x + u * TH;
@@ -600,17 +610,12 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
         const long idx = inner ? cid(g, i, j, 0) : tile_src<2>(g, i, j, 0, ok, ng, src);
         pok[u] = ok;
         png[u] = ng;
+        if constexpr (PRO) {
+            sx[u] = src[0];
+            sy[u] = src[1];
+        }
         v[ST_X0][u] = x[idx];
         v[ST_X1][u] = x[N + idx];
-        if constexpr (PRO) {
-            long q[4];
-            prolong_src<R>(gc, src[0], src[1], R(-1), q, ps[u]);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                pv[u][0][k] = pe[q[k]];
-                pv[u][1][k] = pe[Nc + q[k]];
-            }
-        }
         // b is read only at cells that are updated, which lie in the box
         v[ST_B0][u] = b[idx];
         v[ST_B1][u] = b[N + idx];
@@ -632,13 +637,67 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
             v[ST_FY][u] = coef[fo1 + fid(g, 1, bx, by, 0)];
         }
     }
+    if constexpr (PRO) {
+        const long Nc = ncells(gc);
+        // positions 2 .. n - 3 along both axes: coarse cells C and C +- 1
+        // inside the coarse grid
+        const bool in_patch = ox - H >= 2 && ox + T::TX + H <= g.n[0] - 2 && oy - H >= 2 &&
+                              oy + T::TY + H <= g.n[1] - 2;
+        if (in_patch) {
+            using P = CoarsePatch<H, CF>;
+            R* patch = s + NA * T::NS;
+            const int cx0 = (ox - H) / 2 - 1, cy0 = (oy - H) / 2 - 1;
+            constexpr int KQ = (2 * P::PN + TH - 1) / TH;
+            R cp[KQ];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                const int t = threadIdx.x + q * TH;
+                const int tt = t < 2 * P::PN ? t : 0;
+                const int c = tt / P::PN, r = tt - c * P::PN;
+                const int py = r / P::PW, px = r - py * P::PW;
+                cp[q] = pe[c * Nc + cid(gc, cx0 + px, cy0 + py, 0)];
+            }
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                const int t = threadIdx.x + q * TH;
+                if (t < 2 * P::PN) patch[t] = cp[q];
+            }
+            __syncthreads();
+            const R one[2] = {R(1), R(1)};
+#pragma unroll
+            for (int u = 0; u < K; ++u) {
+                const int C0 = sx[u] >> 1, C1 = sy[u] >> 1;
+                const int J0 = C0 + ((sx[u] & 1) ? 1 : -1), J1 = C1 + ((sy[u] & 1) ? 1 : -1);
+                const int at[4] = {(C1 - cy0) * P::PW + (C0 - cx0), (C1 - cy0) * P::PW + (J0 - cx0),
+                                   (J1 - cy0) * P::PW + (C0 - cx0), (J1 - cy0) * P::PW + (J0 - cx0)};
+                R n0[4], n1[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    n0[k] = patch[at[k]];
+                    n1[k] = patch[P::PN + at[k]];
+                }
+                v[ST_X0][u] = v[ST_X0][u] + prolong_sum<R>(n0, one);
+                v[ST_X1][u] = v[ST_X1][u] + prolong_sum<R>(n1, one);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < K; ++u) {
+                long q[4];
+                R sg[2], n0[4], n1[4];
+                prolong_src<R>(gc, sx[u], sy[u], R(-1), q, sg);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    n0[k] = pe[q[k]];
+                    n1[k] = pe[Nc + q[k]];
+                }
+                v[ST_X0][u] = v[ST_X0][u] + prolong_sum<R>(n0, sg);
+                v[ST_X1][u] = v[ST_X1][u] + prolong_sum<R>(n1, sg);
+            }
+        }
+    }
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-        R x0 = v[ST_X0][u], x1 = v[ST_X1][u];
-        if constexpr (PRO) {
-            x0 = x0 + prolong_sum<R>(pv[u][0], ps[u]);
-            x1 = x1 + prolong_sum<R>(pv[u][1], ps[u]);
-        }
+        const R x0 = v[ST_X0][u], x1 = v[ST_X1][u];
         v[ST_X0][u] = pok[u] ? (png[u] ? -x0 : x0) : R(0);
         v[ST_X1][u] = pok[u] ? (png[u] ? -x1 : x1) : R(0);
         if (FINE) v[ST_E][u] = pok[u] ? v[ST_E][u] : R(0);
@@ -724,8 +783,20 @@ __device__ inline void staged_sweeps(const GridD& g, R* s, R dt, R ihh, int ox, 
 // 2x2 children, coarse x = 0), as the residual-restriction kernel would
 // after it.  The sweeps then run one ring wider (halo 4 NSW + 1, last half
 // step on ring 1), so every value the residual reads is final.
+// waves per SIMD asked of the register allocator: the finest level's launch
+// that folds in the prolongation is held to two workgroups per compute unit
+// where its LDS fits twice (160 KB per CU), so a launch over twice as many
+// tiles as compute units runs in one round
 template <bool FINE, typename R, class CF, int NSW, bool PRO, bool RES>
-__global__ void __launch_bounds__(CF::THREADS)
+constexpr int tsweep_waves()
+{
+    constexpr size_t lds = sizeof(R) * ((FINE ? 5 : 6) * Tile<2, 4 * NSW + (RES ? 1 : 0), CF>::NS +
+                                        (PRO ? 2 * CoarsePatch<4 * NSW, CF>::PN : 0));
+    return FINE && PRO && 2 * lds <= 160 * 1024 ? 2 * CF::THREADS / 256 : 1;
+}
+
+template <bool FINE, typename R, class CF, int NSW, bool PRO, bool RES>
+__global__ void __launch_bounds__(CF::THREADS, (tsweep_waves<FINE, R, CF, NSW, PRO, RES>()))
 k_tsweepN(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, const R* __restrict__ xcura,
           R* __restrict__ xnexta, const R* __restrict__ ba, const R* __restrict__ pea, const GridD* __restrict__ gct,
           const long* __restrict__ oct, R* __restrict__ bca, R* __restrict__ xca)
@@ -1411,11 +1482,20 @@ void launch_tresid_restr(Ctx* c, const Level& L, const BV& v, const GridD* gc, c
     }
 }
 
-// dynamic LDS of a staged launch
-template <bool FINE, typename R, class CF, int NSW, bool RES>
+// dynamic LDS of a staged launch (PRO: with the coarse patch)
+template <bool FINE, typename R, class CF, int NSW, bool RES, bool PRO = false>
 constexpr size_t staged_lds()
 {
-    return sizeof(R) * ((FINE ? 5 : 6) * Tile<2, 4 * NSW + (RES ? 1 : 0), CF>::NS + (RES ? 2 * CF::TX * CF::TY : 0));
+    return sizeof(R) * ((FINE ? 5 : 6) * Tile<2, 4 * NSW + (RES ? 1 : 0), CF>::NS + (RES ? 2 * CF::TX * CF::TY : 0) +
+                        (PRO ? 2 * CoarsePatch<4 * NSW, CF>::PN : 0));
+}
+
+// the largest of a candidate's launches (coarse level, FP64)
+template <class CF, int NSW>
+constexpr size_t staged_lds_max()
+{
+    const size_t r = staged_lds<false, double, CF, NSW, true>(), p = staged_lds<false, double, CF, NSW, false, true>();
+    return r > p ? r : p;
 }
 
 template <bool FINE, bool PRO, bool RES, typename R, class CF, int NSW>
@@ -1423,7 +1503,7 @@ static void staged_launch(Ctx* c, bool timed, double bytes, dim3 grid, const BV&
                           R* xnext, const R* b, const R* pe, const GridD* gct, const long* oct, R* bc, R* xc)
 {
     tlaunch(c, timed, bytes, k_tsweepN<FINE, R, CF, NSW, PRO, RES>, grid, dim3(CF::THREADS),
-            staged_lds<FINE, R, CF, NSW, RES>(), vv, coef, (const double*)c->sc, xcur, xnext, b, pe, gct, oct, bc, xc);
+            staged_lds<FINE, R, CF, NSW, RES, PRO>(), vv, coef, (const double*)c->sc, xcur, xnext, b, pe, gct, oct, bc, xc);
 }
 
 template <bool FINE, typename R, class CAND>
@@ -1529,14 +1609,15 @@ static void allow_all(size_t bytes, std::index_sequence<I...>)
 void sweep2_allow_lds(size_t bytes) { allow_all(bytes, std::make_index_sequence<kSweep2Cands>{}); }
 
 // dynamic LDS bytes of candidate k running nsw sweeps per launch (FP64,
-// coarse level, with the residual epilogue: the largest case)
+// coarse level: the larger of the launches with the residual epilogue and
+// with the coarse patch)
 template <size_t... I>
 static size_t sweep2_lds_of(int k, int nsw, std::index_sequence<I...>)
 {
     size_t out = 0;
     ((k == (int)I ? (void)(out = std::tuple_element_t<I, Sweep2Cands>::STAGED
-                                     ? (nsw == 2 ? staged_lds<false, double, typename std::tuple_element_t<I, Sweep2Cands>::CF, 2, true>()
-                                                 : staged_lds<false, double, typename std::tuple_element_t<I, Sweep2Cands>::CF, 1, true>())
+                                     ? (nsw == 2 ? staged_lds_max<typename std::tuple_element_t<I, Sweep2Cands>::CF, 2>()
+                                                 : staged_lds_max<typename std::tuple_element_t<I, Sweep2Cands>::CF, 1>())
                                      : sizeof(double) * 3 *
                                            Tile<2, 4, typename std::tuple_element_t<I, Sweep2Cands>::CF>::NS)
                   : void()),
