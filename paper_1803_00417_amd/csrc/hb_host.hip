@@ -1635,8 +1635,7 @@ int hb_tile_config(const hb_ctx* ctx, int op, int level, int* tx, int* ty, int* 
         th = sh.threads;
         sw = L.sweeps;
     } else {
-        nodal_sweep_tile(c->dim, L.tile, tx, ty);
-        th = c->dim == 2 ? 256 : 512;
+        nodal_sweep_tile(c->dim, L.tile, tx, ty, &th);
         sw = L.sweeps;
     }
     if (threads) *threads = th;

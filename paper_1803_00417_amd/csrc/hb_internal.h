@@ -447,7 +447,7 @@ template <typename R> void launch_nodal_gs(Ctx* c, const Level& L, const BV& v, 
 // nsw (1, or 2 in 2D with every periodic extent at least 8) whole
 // Gauss-Seidel sweeps from cur into next (one launch; 3D: one sweep, two launches),
 // with candidate tile `tile` (0 .. kNodalCands - 1); nodal_sweep_tile gives
-// its extents
+// its extents and thread count
 // (2D: pe folds the prolongation of the coarse iterate in, bc/xc the
 // residual restriction to the coarse level, v then also carrying the coarse
 // level, gct/oct its tables; every periodic extent at least the halo:
@@ -456,8 +456,8 @@ template <typename R>
 void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int tile,
                         int nsw = 1, const R* pe = nullptr, const GridD* gct = nullptr, const long* oct = nullptr,
                         R* bc = nullptr, R* xc = nullptr);
-void nodal_sweep_tile(int dim, int tile, int* tx, int* ty);
-constexpr int kNodalCands = 3;
+void nodal_sweep_tile(int dim, int tile, int* tx, int* ty, int* threads);
+constexpr int kNodalCands = 4;
 // r = b - K x (slot >= 0: FP64 only, max-norm into each cavity's slot) or y = K x (b null)
 template <typename R>
 void launch_nodal_resid(Ctx* c, const Level& L, const BV& v, const R* x, const R* b, R* r, int slot);

@@ -194,9 +194,12 @@ template <int TX_, int TY_, int PZ_, int TH_>
 struct NG4 {
     static constexpr int TX = TX_, TY = TY_, PZ = PZ_, TH = TH_;
 };
-using NG4Tiles2 = std::tuple<NG4<64, 16, 1, 256>, NG4<128, 8, 1, 256>, NG4<32, 32, 1, 256>>;
-using NG4Tiles3 = std::tuple<NG4<64, 8, 2, 512>, NG4<32, 16, 2, 512>, NG4<64, 4, 4, 512>>;
-constexpr int kNG4Tiles = 3;
+using NG4Tiles2 = std::tuple<NG4<64, 16, 1, 256>, NG4<128, 8, 1, 256>, NG4<32, 32, 1, 256>, NG4<64, 16, 1, 1024>>;
+using NG4Tiles3 = std::tuple<NG4<64, 8, 2, 512>, NG4<32, 16, 2, 512>, NG4<64, 4, 4, 512>, NG4<64, 8, 2, 1024>>;
+constexpr int kNG4Tiles = 4;
+static_assert(kNG4Tiles == kNodalCands && std::tuple_size_v<NG4Tiles2> == kNG4Tiles &&
+                  std::tuple_size_v<NG4Tiles3> == kNG4Tiles,
+              "nodal candidate count");
 
 // 2D, NSW = 2: two whole sweeps in one launch.  Colour c of sweep w runs on
 // the tile grown by 4 (NSW - 1 - w) + 3 - c in x and 2 (NSW - 1 - w) + (1 for
@@ -514,23 +517,20 @@ void launch_nodal_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* ne
     else nodal_sweep_pick<3, R, NG4Tiles3>(c, L, v, cur, next, b, k, 1, nullptr, nullptr, nullptr, nullptr, nullptr, seq);
 }
 
-void nodal_sweep_tile(int dim, int k, int* tx, int* ty)
+template <class TILES, size_t... I>
+static void nodal_tile_of(int k, int* tx, int* ty, int* th, std::index_sequence<I...>)
 {
-    if (dim == 2) {
-        const int txs[] = {std::tuple_element_t<0, NG4Tiles2>::TX, std::tuple_element_t<1, NG4Tiles2>::TX,
-                           std::tuple_element_t<2, NG4Tiles2>::TX};
-        const int tys[] = {std::tuple_element_t<0, NG4Tiles2>::TY, std::tuple_element_t<1, NG4Tiles2>::TY,
-                           std::tuple_element_t<2, NG4Tiles2>::TY};
-        *tx = txs[k];
-        *ty = tys[k];
-    } else {
-        const int txs[] = {std::tuple_element_t<0, NG4Tiles3>::TX, std::tuple_element_t<1, NG4Tiles3>::TX,
-                           std::tuple_element_t<2, NG4Tiles3>::TX};
-        const int tys[] = {std::tuple_element_t<0, NG4Tiles3>::TY, std::tuple_element_t<1, NG4Tiles3>::TY,
-                           std::tuple_element_t<2, NG4Tiles3>::TY};
-        *tx = txs[k];
-        *ty = tys[k];
-    }
+    ((k == (int)I ? (void)(*tx = std::tuple_element_t<I, TILES>::TX, *ty = std::tuple_element_t<I, TILES>::TY,
+                           *th = std::tuple_element_t<I, TILES>::TH)
+                  : void()),
+     ...);
+}
+
+void nodal_sweep_tile(int dim, int k, int* tx, int* ty, int* th)
+{
+    constexpr auto seq = std::make_index_sequence<kNG4Tiles>{};
+    if (dim == 2) nodal_tile_of<NG4Tiles2>(k, tx, ty, th, seq);
+    else nodal_tile_of<NG4Tiles3>(k, tx, ty, th, seq);
 }
 
 template <typename R>

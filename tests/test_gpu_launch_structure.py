@@ -141,7 +141,7 @@ def test_autotuner_reports_candidate_tiles():
                      (64, 16, 512, 1), (64, 16, 512, 2), (32, 16, 1024, 1), (32, 16, 1024, 2), (16, 8, 256, 1),
                      (16, 8, 256, 2)},
             "nodal": {(64, 16, 256, 1), (128, 8, 256, 1), (32, 32, 256, 1), (64, 16, 256, 2), (128, 8, 256, 2),
-                      (32, 32, 256, 2)}}
+                      (32, 32, 256, 2), (64, 16, 1024, 1), (64, 16, 1024, 2)}}
     tv = [ctx.tile_config(hb.OP_VISC, l) for l in range(8)]
     tn = [ctx.tile_config(hb.OP_NODAL, l) for l in range(8)]
     _say("  tensor", tv, "nodal", tn)
@@ -155,7 +155,10 @@ def test_autotuner_reports_candidate_tiles():
     ctx.close()
     # walls only: the staged candidate runs two sweeps per launch
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "4"})
-    assert ctx.tile_config(hb.OP_VISC, 0) == (64, 16, 512, 2) and ctx.tile_config(hb.OP_NODAL, 0) == (128, 8, 256, 2)
+    assert ctx.tile_config(hb.OP_VISC, 0) == (64, 16, 512, 2) and ctx.tile_config(hb.OP_NODAL, 0) == (64, 16, 256, 2)
+    ctx.close()
+    ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "3"})
+    assert ctx.tile_config(hb.OP_NODAL, 0) == (64, 16, 1024, 2)
     ctx.close()
     # a periodic extent below 8 allows one sweep per launch only
     s = CASES["chan2d_8x32"]()
