@@ -398,7 +398,7 @@ struct SweepShape {
     int tx, ty, threads, nsw;
     bool staged;
 };
-constexpr int kSweep2Cands = 7;
+constexpr int kSweep2Cands = 8;
 // bc/xc (optional): the launch ends a pre-smoothing and also restricts the
 // residual of its result to the coarse level (coarse b, coarse x = 0; v
 // then also carries the coarse level), as launch_tresid_restr would after it.

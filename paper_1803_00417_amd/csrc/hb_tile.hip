@@ -43,7 +43,7 @@ struct SweepCand {
 using Sweep2Cands = std::tuple<SweepCand<TileShape<64, 8, 1, 256>, 1, false>, SweepCand<TileShape<32, 16, 1, 256>, 1, false>,
                                SweepCand<TileShape<128, 4, 1, 256>, 1, false>, SweepCand<TileShape<32, 16, 1, 512>, 2, true>,
                                SweepCand<TileShape<64, 16, 1, 512>, 2, true>, SweepCand<TileShape<32, 16, 1, 1024>, 2, true>,
-                               SweepCand<TileShape<16, 8, 1, 256>, 2, true>>;
+                               SweepCand<TileShape<16, 8, 1, 256>, 2, true>, SweepCand<TileShape<16, 8, 1, 1024>, 2, true>>;
 static_assert(std::tuple_size_v<Sweep2Cands> == kSweep2Cands, "candidate count");
 
 

@@ -50,7 +50,7 @@ PLAIN = {"tail": {"HB_TAIL": "0"}, "fuse": {"HB_FUSE": "0"}, "both": {"HB_TAIL":
          # on every level with the coarse tail off
          "tile3": {"HB_TILE": "3"}, "tile4_notail": {"HB_TILE": "4", "HB_TAIL": "0"},
          "tile5_notail": {"HB_TILE": "5", "HB_TAIL": "0"}, "tile6": {"HB_TILE": "6"},
-         "tile6_notail": {"HB_TILE": "6", "HB_TAIL": "0"}}
+         "tile6_notail": {"HB_TILE": "6", "HB_TAIL": "0"}, "tile7": {"HB_TILE": "7"}}
 
 
 def _context(make, env):
@@ -139,7 +139,7 @@ def test_autotuner_reports_candidate_tiles():
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {})
     cand = {"visc": {(64, 8, 256, 1), (32, 16, 256, 1), (128, 4, 256, 1), (32, 16, 512, 1), (32, 16, 512, 2),
                      (64, 16, 512, 1), (64, 16, 512, 2), (32, 16, 1024, 1), (32, 16, 1024, 2), (16, 8, 256, 1),
-                     (16, 8, 256, 2)},
+                     (16, 8, 256, 2), (16, 8, 1024, 1), (16, 8, 1024, 2)},
             "nodal": {(64, 16, 256, 1), (128, 8, 256, 1), (32, 32, 256, 1), (64, 16, 256, 2), (128, 8, 256, 2),
                       (32, 32, 256, 2), (64, 16, 1024, 1), (64, 16, 1024, 2)}}
     tv = [ctx.tile_config(hb.OP_VISC, l) for l in range(8)]
