@@ -109,10 +109,26 @@ typedef struct {
     double bnorm;        /* |b|_inf of the system solved */
 } hb_mg_report;
 
+/* Step options.  pred_visc and theta choose between readings of Sec. III.A:
+ *   pred_visc = 1 puts the explicit stress divergence 2E into the forcing of
+ *     the Taylor prediction of the face states, as eq:iamr:extrap prints it;
+ *     0 (default) predicts with -G p + f only.  With 2E the face states take
+ *     (dt/2) div tau^m, which is unstable once the diffusion number
+ *     dt eta/(Re h^2) is large (a Newtonian Re = 1 cavity at dt = h/2 from
+ *     16^2, and the Bingham Re = 1 cavity of Sec. IV), so it is off by default.
+ *   theta is the implicit weight of the viscous update: 0.5 (or 0) is the
+ *     Crank-Nicolson update printed in Sec. III.A, 1 backward Euler;
+ *     0.5 <= theta <= 1.  The solve is (I - 2 theta dt div(eta/Re
+ *     gamma_dot(.))) u* = b with 2 (1 - theta) dt E in b.  Crank-Nicolson is
+ *     not L-stable: with the lagged, strongly varying viscosity of a yield-
+ *     stress fluid its stiff modes keep the velocity changing by about 1e-2
+ *     per step at Re = 1, so runs to a steady state there use theta = 1. */
 typedef struct {
     double cfl;          /* dt = cfl h / max(U_wall, max |u|) when dt <= 0 */
     int32_t mac_project; /* 1: project the face advection velocity (default) */
     hb_mg_opts mac, visc, proj;
+    int32_t pred_visc;   /* 1: explicit stress divergence in the predictor forcing */
+    double theta;        /* implicit weight of the viscous update (0: 0.5) */
 } hb_step_opts;
 
 typedef struct {
@@ -154,10 +170,12 @@ int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt,
                 const double* rhs, double* x, const hb_mg_opts* opts,
                 hb_mg_report* report);
 
-/* The advection stage: viscosity-weighted explicit term E = div(eta/Re
- * gamma_dot(u)), the Godunov prediction with forcing -G p + 2E + f, the MAC
- * projection of the face velocity, and the viscous-solve right-hand side
- *   b = u - dt [u^MAC . grad u~] + dt (-G p + E + f).
+/* The advection stage (Sec. III.A, eq:iamr:extrap and the provisional
+ * velocity): viscosity-weighted explicit term E = div(eta/Re gamma_dot(u)),
+ * the Godunov prediction with forcing -G p + f (-G p + 2E + f with
+ * pred_visc), the MAC projection of the face velocity, and the viscous-solve
+ * right-hand side
+ *   b = u - dt [u^MAC . grad u~] + dt (-G p + 2 (1 - theta) E + f).
  * u: [dim][cells], p: nodes, eta: [cells] (from hb_viscosity), b: [dim][cells]
  * out.  umac (faces), conv ([dim][cells], the convective term) nullable. */
 int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta,

@@ -68,6 +68,12 @@ typedef struct {
     double cfl;
     int mac_project;          /* 1: project the face velocity (default) */
     orc_mg_opts mac, visc, proj;
+    int pred_visc;            /* 1: the explicit stress divergence enters the
+                                 forcing of the Taylor prediction (as printed in
+                                 eq:iamr:extrap); 0 (default): -G p + f only */
+    double theta;             /* implicit weight of the viscous update: 0.5 (or
+                                 0) Crank-Nicolson as printed in Sec. III.A,
+                                 1 backward Euler */
 } orc_step_opts;
 
 typedef struct {
@@ -113,6 +119,7 @@ int orc_tensor_diagonal(const orc_grid* g, const orc_fluid* fl, const double* et
 
 /* ---- the step ------------------------------------------------------------ */
 double orc_cfl_dt(const orc_grid* g, double cfl, const double* u);
+double orc_theta(const orc_step_opts* o);
 /* Godunov stage: from u^m, p^{m-1/2}, eta_hat and dt produce the viscous-solve
  * right-hand side b (before wall terms), and optionally the explicit term E,
  * the MAC velocity (per axis, concatenated face arrays) and the convective

@@ -62,7 +62,8 @@ class MGReport(C.Structure):
 
 class StepOpts(C.Structure):
     _fields_ = [("cfl", C.c_double), ("mac_project", C.c_int),
-                ("mac", MGOpts), ("visc", MGOpts), ("proj", MGOpts)]
+                ("mac", MGOpts), ("visc", MGOpts), ("proj", MGOpts),
+                ("pred_visc", C.c_int), ("theta", C.c_double)]
 
 
 class StepReport(C.Structure):
@@ -152,10 +153,12 @@ def make_fluid(Re=1.0, HB=0.0, n=1.0, Pa=1e3, reg=REG_PAPER, f=(0.0, 0.0, 0.0)):
 
 
 def make_step_opts(cfl=0.5, tol=1e-10, max_cycles=100, nu=2, mac_project=1, fixed=0,
-                   visc_krylov=1):
+                   visc_krylov=1, pred_visc=0, theta=0.5):
     o = StepOpts()
     o.cfl = cfl
     o.mac_project = mac_project
+    o.pred_visc = pred_visc
+    o.theta = theta
     for m in (o.mac, o.visc, o.proj):
         m.tol, m.max_cycles, m.fixed, m.nu1, m.nu2, m.krylov = tol, max_cycles, fixed, nu, nu, 0
     o.visc.krylov = visc_krylov

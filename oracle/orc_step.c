@@ -55,11 +55,19 @@ static long face_off(const orc_grid* g, int a)
     return off;
 }
 
+/* implicit weight of the viscous update; 0 selects Crank-Nicolson */
+double orc_theta(const orc_step_opts* o)
+{
+    return o->theta > 0.0 ? o->theta : 0.5;
+}
+
 /* Godunov predictor, MAC projection and the right-hand side of the viscous
- * solve:  b = u - dt A + dt(-G p + E + f),  with
+ * solve:  b = u - dt A + dt(-G p + 2(1 - theta) E + f),  with
  *   E = div(eta_e gamma_dot(u^m)) (half the explicit stress divergence),
- *   F = -G p + 2E + f            (the forcing used in the Taylor prediction),
- *   A = [u^MAC . grad u~]         (convective term, non-conservative form). */
+ *   F = -G p + f, or -G p + 2E + f with pred_visc (the forcing of the Taylor
+ *       prediction, eq:iamr:extrap),
+ *   A = [u^MAC . grad u~]         (convective term, non-conservative form).
+ * Crank-Nicolson (theta = 1/2) is the update printed in Sec. III.A. */
 int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
                const double* u, const double* p, const double* eta, double dt,
                double* b, double* E_out, double* umac_out, double* A_out,
@@ -78,9 +86,13 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
     double* F = (double*)xcalloc(N * d, sizeof(double));
     orc_visc_div(g, eta_e, u, 0, E);
     orc_grad_node(g, p, Gp);
+    /* weight of E in the predictor forcing: 2 (the whole stress divergence,
+     * as printed) or 0; and in b: 2 (1 - theta), 1 for Crank-Nicolson */
+    const double wF = o->pred_visc ? 2.0 : 0.0;
+    const double wb = 2.0 * (1.0 - orc_theta(o));
     for (int c = 0; c < d; ++c)
         for (long i = 0; i < N; ++i)
-            F[(long)c * N + i] = -Gp[(long)c * N + i] + 2.0 * E[(long)c * N + i] + fl->f[c];
+            F[(long)c * N + i] = -Gp[(long)c * N + i] + wF * E[(long)c * N + i] + fl->f[c];
 
     const double delta = 1e-12 * fmax(orc_lid_speed(g), vmax_abs(u, N * d));
 
@@ -243,7 +255,7 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
     for (int c = 0; c < d; ++c)
         for (long i = 0; i < N; ++i) {
             long q = (long)c * N + i;
-            b[q] = u[q] - dt * A[q] + dt * (-Gp[q] + E[q] + fl->f[c]);
+            b[q] = u[q] - dt * A[q] + dt * (-Gp[q] + wb * E[q] + fl->f[c]);
         }
     if (E_out) memcpy(E_out, E, sizeof(double) * N * d);
     if (umac_out) memcpy(umac_out, umac, sizeof(double) * nf_tot);
@@ -302,7 +314,8 @@ int orc_step(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
     if (rc == ORC_OK || rc == ORC_ERR_NOCONV) {
         rc2 = rc;
         memcpy(us, u, sizeof(double) * N * d);
-        rc = orc_mg_solve(g, fl, ORC_OP_VISC, eta, dt, b, us, &o->visc, &R.visc);
+        /* (I - 2 theta dt div(eta_e gamma_dot(.))) u* = b */
+        rc = orc_mg_solve(g, fl, ORC_OP_VISC, eta, 2.0 * orc_theta(o) * dt, b, us, &o->visc, &R.visc);
         if (rc == ORC_OK) rc = rc2;
     }
     if (rc == ORC_OK || rc == ORC_ERR_NOCONV) {

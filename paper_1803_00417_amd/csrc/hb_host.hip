@@ -1003,14 +1003,16 @@ static int step_all(Ctx* c, double* const* u, double* const* p, const double* dt
         uv[b] = u[b];
         pv[b] = p[b];
         launch_viscosity(c, v, u[b], v.eta);
-        visc_setup(c, b, v.eta, dt[b]);
+        // the solve's operator is I - 2 theta dt div(eta/Re gamma_dot(.))
+        visc_setup(c, b, v.eta, 2.0 * c->opts.theta * dt[b]);
         advect_predict(c, b, u[b], p[b], dt[b]);
+        v.step_dt = dt[b];
     }
     int rc = advect_finish(c, uc, dt, rhs, conv, &mrep, reports ? &divr : nullptr);
     if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
     for (int b = 0; b < nb; ++b) {
         Cav& v = c->cv[b];
-        launch_visc_wall_rhs(c, v.g, c->visc.L[0].beta + c->visc.L[0].hof[b], dt[b], v.rhs,
+        launch_visc_wall_rhs(c, v.g, c->visc.L[0].beta + c->visc.L[0].hof[b], 2.0 * c->opts.theta * dt[b], v.rhs,
                              c->visc.lvl0_b + c->visc.L[0].hou[b]);
         copy(c, v.ustar, u[b], v.dim * v.nc);
     }
@@ -1239,10 +1241,13 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
     }
     if (!valid_opts(opts->mac) || !valid_opts(opts->visc) || !valid_opts(opts->proj)) return bad("invalid multigrid options");
     if (!(opts->cfl > 0.0)) return bad("cfl must be positive");
+    if (!(opts->theta == 0.0 || (opts->theta >= 0.5 && opts->theta <= 1.0))) return bad("theta must be 0 or in [0.5, 1]");
+    if (opts->pred_visc != 0 && opts->pred_visc != 1) return bad("pred_visc must be 0 or 1");
 
     Ctx* c = new (std::nothrow) ::hb_ctx();
     if (!c) return bad("out of host memory");
     c->opts = *opts;
+    if (c->opts.theta == 0.0) c->opts.theta = 0.5;
     c->user = (hipStream_t)hip_stream;
     c->nb = count;
     c->dim = grids[0].dim;
@@ -1720,7 +1725,7 @@ static int run_steady(Ctx* c, double* u, double* p, double tol, int max_steps, d
         red_maxdiff(c, 0, u, c->uold, n, S_CHG);
         red_maxabs(c, 0, c->uold, n, S_CHGREF);
         fetch_slots(c);
-        R.t += slot(c, 0, S_DT);
+        R.t += c->cv[0].step_dt;
         const double ref = slot(c, 0, S_CHGREF);
         R.change = ref > 0.0 ? slot(c, 0, S_CHG) / ref : HUGE_VAL;
         if (src == HB_ERR_NOCONV) {
@@ -1890,7 +1895,7 @@ int hb_run_cessation(hb_ctx* ctx, double* u, double* p, int max_steps, double dt
             }
             yield_slots(c, u, nullptr);
             fetch_slots(c);
-            R.t += slot(c, 0, S_DT);
+            R.t += c->cv[0].step_dt;
             if (src == HB_ERR_NOCONV) {
                 rc = src;
                 break;

@@ -228,6 +228,7 @@ struct Cav {
     int dim = 2;
     long nc = 0, nn = 0, nf = 0;
     double ulid = 0.0;
+    double step_dt = 0.0;   // dt of the last step (host copy)
     double* sc = nullptr;    // its scalar slots (device)
     double* hsc = nullptr;   // their pinned host mirror
     double *eta = nullptr, *E = nullptr, *Gp = nullptr, *F = nullptr, *S = nullptr, *trans = nullptr;

@@ -88,21 +88,24 @@ void launch_grad_node(Ctx* c, const Cav& v, const double* p, double* Gp)
     k_grad_node<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, p, Gp);
 }
 
-// F = -G p + 2E + f (the forcing of the Taylor prediction)
-__global__ void k_forcing(long n, int dim, double f0, double f1, double f2, const double* __restrict__ Gp,
+// F = -G p + wF E + f, the forcing of the Taylor prediction: wF = 2 puts
+// the whole explicit stress divergence in (as eq:iamr:extrap prints it),
+// wF = 0 leaves it out
+__global__ void k_forcing(long n, int dim, double wF, double f0, double f1, double f2, const double* __restrict__ Gp,
                           const double* __restrict__ E, double* __restrict__ F)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * dim) return;
     const int c = (int)(t / n);
     const double f = c == 0 ? f0 : (c == 1 ? f1 : f2);
-    F[t] = -Gp[t] + 2.0 * E[t] + f;
+    F[t] = -Gp[t] + wF * E[t] + f;
 }
 
 void launch_forcing(Ctx* c, const Cav& v)
 {
     const long n = v.nc * v.dim;
-    k_forcing<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(v.nc, v.dim, v.fl.f[0], v.fl.f[1], v.fl.f[2], v.Gp, v.E, v.F);
+    const double wF = c->opts.pred_visc ? 2.0 : 0.0;
+    k_forcing<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(v.nc, v.dim, wF, v.fl.f[0], v.fl.f[1], v.fl.f[2], v.Gp, v.E, v.F);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,8 +308,9 @@ void launch_mac_update(Ctx* c, const Cav& v)
 }
 
 // convective term A = sum_a mean(u^MAC_a) (q~_hi - q~_lo)/h with the full
-// states upwinded by u^MAC, and b = u - dt A + dt (-G p + E + f)
-__global__ void k_advect_rhs(GridD g, double dt, double ulid, double f0, double f1, double f2,
+// states upwinded by u^MAC, and b = u - dt A + dt (-G p + wb E + f) with
+// wb = 2 (1 - theta) (1 for Crank-Nicolson)
+__global__ void k_advect_rhs(GridD g, double dt, double wb, double ulid, double f0, double f1, double f2,
                              const double* __restrict__ sc, const double* __restrict__ u,
                              const double* __restrict__ umac, const double* __restrict__ qLf,
                              const double* __restrict__ qRf, const double* __restrict__ Gp,
@@ -336,7 +340,7 @@ __global__ void k_advect_rhs(GridD g, double dt, double ulid, double f0, double 
     for (int q = 0; q < d; ++q) {
         const long e = q * N + q0;
         const double f = q == 0 ? f0 : (q == 1 ? f1 : f2);
-        b[e] = u[e] - dt * A[q] + dt * (-Gp[e] + E[e] + f);
+        b[e] = u[e] - dt * A[q] + dt * (-Gp[e] + wb * E[e] + f);
         if (conv) conv[e] = A[q];
     }
 }
@@ -344,7 +348,8 @@ __global__ void k_advect_rhs(GridD g, double dt, double ulid, double f0, double 
 void launch_advect_rhs(Ctx* c, const Cav& v, const double* u, double dt, double* b, double* conv)
 {
     k_advect_rhs<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(
-        v.g, dt, v.ulid, v.fl.f[0], v.fl.f[1], v.fl.f[2], v.sc, u, v.umac, v.qLf, v.qRf, v.Gp, v.E, v.nf, b, conv);
+        v.g, dt, 2.0 * (1.0 - c->opts.theta), v.ulid, v.fl.f[0], v.fl.f[1], v.fl.f[2], v.sc, u, v.umac, v.qLf, v.qRf,
+        v.Gp, v.E, v.nf, b, conv);
 }
 
 // ---------------------------------------------------------------------------

@@ -55,7 +55,8 @@ class MGReport(C.Structure):
 
 class StepOpts(C.Structure):
     _fields_ = [("cfl", C.c_double), ("mac_project", C.c_int32),
-                ("mac", MGOpts), ("visc", MGOpts), ("proj", MGOpts)]
+                ("mac", MGOpts), ("visc", MGOpts), ("proj", MGOpts),
+                ("pred_visc", C.c_int32), ("theta", C.c_double)]
 
 
 class StepReport(C.Structure):
@@ -190,10 +191,12 @@ def mg_opts(tol=1e-10, max_cycles=100, fixed=0, nu1=2, nu2=2, krylov=0, precisio
 
 
 def make_step_opts(cfl=0.5, tol=1e-10, max_cycles=100, nu=2, mac_project=1, fixed=0,
-                   visc_krylov=1, precision=PREC_FP64):
+                   visc_krylov=1, precision=PREC_FP64, pred_visc=0, theta=0.5):
     o = StepOpts()
     o.cfl = cfl
     o.mac_project = mac_project
+    o.pred_visc = pred_visc
+    o.theta = theta
     for m in (o.mac, o.visc, o.proj):
         m.tol_rel, m.max_cycles, m.fixed_cycles = tol, max_cycles, fixed
         m.nu1, m.nu2, m.krylov, m.precision = nu, nu, 0, precision

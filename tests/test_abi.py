@@ -37,11 +37,11 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_1803_00417_amd import hb
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "hb.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                    'sizeof(hb_grid),sizeof(hb_fluid),sizeof(hb_mg_opts),sizeof(hb_mg_report),'
                    'sizeof(hb_step_opts),sizeof(hb_step_report),offsetof(hb_grid,wall_u),'
                    'offsetof(hb_step_opts,proj),sizeof(hb_steady_report),offsetof(hb_steady_report,change),'
-                   'sizeof(hb_yield_report),sizeof(hb_cessation_report));'
+                   'sizeof(hb_yield_report),sizeof(hb_cessation_report),offsetof(hb_step_opts,theta));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -49,7 +49,7 @@ def test_struct_layouts_match_header(tmp_path):
     want = [C.sizeof(hb.Grid), C.sizeof(hb.Fluid), C.sizeof(hb.MGOpts), C.sizeof(hb.MGReport),
             C.sizeof(hb.StepOpts), C.sizeof(hb.StepReport), hb.Grid.wall_u.offset, hb.StepOpts.proj.offset,
             C.sizeof(hb.SteadyReport), hb.SteadyReport.change.offset, C.sizeof(hb.YieldReport),
-            C.sizeof(hb.CessationReport)]
+            C.sizeof(hb.CessationReport), hb.StepOpts.theta.offset]
     assert got == want
 
 

@@ -211,6 +211,25 @@ def test_step_parity_channel_fixed_dt():
     assert worst < 1e-9, worst
 
 
+@pytest.mark.parametrize("case", ["lid2d_32", "lid3d_16", "chan2d_8x32"])
+@pytest.mark.parametrize("opt", [dict(pred_visc=1), dict(theta=1.0), dict(pred_visc=1, theta=0.75)],
+                         ids=["pred_visc", "backward_euler", "pred_visc_theta075"])
+def test_step_parity_step_options(case, opt):
+    # the readings of the predictor forcing and of the viscous update
+    _say("step options", case, opt)
+    s = CASES[case]()
+    worst, rep, rep_o = _run_steps(s, 5, dt=0.01 if case.startswith("chan") else 0.0, **opt)
+    assert worst < 1e-9, worst
+
+
+def test_step_parity_bingham_re1_backward_euler():
+    # the Re = 1, Bi = 10, Pa = 400 cavity of Sec. IV under backward Euler
+    _say("step bingham Re1 theta=1")
+    s = lid_spec(2, 32, Re=1.0, HB=10.0, Pa=400.0)
+    worst, rep, rep_o = _run_steps(s, 20, theta=1.0)
+    assert worst < 1e-9, worst
+
+
 def test_step_is_deterministic():
     _say("determinism")
     s = CASES["lid2d_96x48"]()
