@@ -114,6 +114,15 @@ int orc_mg_solve(const orc_grid* g, const orc_fluid* fl, int op, const double* e
 int orc_dense_matrix(const orc_grid* g, const orc_fluid* fl, int op, const double* eta,
                      double dt, double* A);
 int orc_dense_solve(int N, double* A, double* b);  /* LU, partial pivoting, in place */
+/* Multigrid transfers of the cell problems (for the pins): x += P e, the
+ * (bi/tri)linear prolongation from the coarse grid gc (every cell count of gf
+ * halved) with the homogeneous ghost e(wall) = wall_sign e(inner) beyond a wall
+ * (-1: the Dirichlet viscous problem, +1: the Neumann MAC problem); and the
+ * coarse face viscosity as the mean of the fine faces tiling each coarse face
+ * (face arrays per axis, concatenated). */
+void orc_prolong_cells(const orc_grid* gf, const orc_grid* gc, int ncomp, double wall_sign, const double* e,
+                       double* x);
+void orc_restrict_faces(const orc_grid* gf, const orc_grid* gc, const double* bf, double* bc);
 /* Diagonal used by the tensor Gauss-Seidel smoother ([dim][cells]). */
 int orc_tensor_diagonal(const orc_grid* g, const orc_fluid* fl, const double* eta, double dt, double* out);
 

@@ -99,6 +99,10 @@ def lib():
         L.orc_dense_matrix.argtypes = [P(Grid), P(Fluid), C.c_int, dp, C.c_double, dp]
         L.orc_dense_solve.argtypes = [C.c_int, dp, dp]
         L.orc_tensor_diagonal.argtypes = [P(Grid), P(Fluid), dp, C.c_double, dp]
+        L.orc_prolong_cells.argtypes = [P(Grid), P(Grid), C.c_int, C.c_double, dp, dp]
+        L.orc_prolong_cells.restype = None
+        L.orc_restrict_faces.argtypes = [P(Grid), P(Grid), dp, dp]
+        L.orc_restrict_faces.restype = None
         L.orc_cfl_dt.restype = C.c_double
         L.orc_cfl_dt.argtypes = [P(Grid), C.c_double, dp]
         L.orc_advect.argtypes = [P(Grid), P(Fluid), P(StepOpts), dp, dp, dp, C.c_double,
@@ -269,6 +273,37 @@ def tensor_diagonal(g, fl, eta, dt):
     eta = np.ascontiguousarray(eta, dtype=np.float64)
     out = np.zeros(cell_shape(g, g.dim), dtype=np.float64)
     lib().orc_tensor_diagonal(C.byref(g), C.byref(fl), _p(eta), float(dt), _p(out))
+    return out
+
+
+def coarse_grid(g):
+    """the next multigrid level of g: every used cell count halved, spacing
+    doubled, same boundaries, walls at rest"""
+    c = Grid()
+    C.pointer(c)[0] = g
+    for a in range(g.dim):
+        c.n[a] = g.n[a] // 2
+    c.h = 2.0 * g.h
+    for a in range(3):
+        for s in range(2):
+            for q in range(3):
+                c.wall_u[a][s][q] = 0.0
+    return c
+
+
+def prolong_cells(gf, gc, e, wall_sign, x=None):
+    """x + P e for a cell field e on gc ([C][cells]); returns the new x"""
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    ncomp = e.shape[0]
+    out = np.zeros(cell_shape(gf, ncomp)) if x is None else np.array(x, dtype=np.float64, copy=True)
+    lib().orc_prolong_cells(C.byref(gf), C.byref(gc), ncomp, float(wall_sign), _p(e), _p(out))
+    return out
+
+
+def restrict_faces(gf, gc, bf):
+    bf = np.ascontiguousarray(bf, dtype=np.float64)
+    out = np.zeros(face_total(gc), dtype=np.float64)
+    lib().orc_restrict_faces(C.byref(gf), C.byref(gc), _p(bf), _p(out))
     return out
 
 

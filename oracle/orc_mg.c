@@ -625,3 +625,16 @@ int orc_tensor_diagonal(const orc_grid* g, const orc_fluid* fl, const double* et
     free(beta);
     return ORC_OK;
 }
+
+/* ---- transfers exposed for the pins ------------------------------------------ */
+
+void orc_prolong_cells(const orc_grid* gf, const orc_grid* gc, int ncomp, double wall_sign, const double* e,
+                       double* x)
+{
+    prolong_cells(gf, gc, ncomp, wall_sign, e, x);
+}
+
+void orc_restrict_faces(const orc_grid* gf, const orc_grid* gc, const double* bf, double* bc)
+{
+    restrict_faces(gf, gc, bf, bc);
+}

@@ -417,6 +417,208 @@ def test_poisson_mg_contraction_h_independent(op):
     assert rates[1] < 1.5 * rates[0]
 
 
+# --------------------------------------------------------------------------
+# the tensor V-cycle on its own (krylov = 0): contraction, fixed point, and
+# its transfers against exact results on linear fields
+# --------------------------------------------------------------------------
+
+def _visc_rates(bc, etakind, ns=(32, 64), cyc=(3, 6), dt=1.0):
+    rates = []
+    for n in ns:
+        g = orc.make_grid(2, [n, n], 1.0 / n, bc=bc)
+        fl = orc.make_fluid(Re=1.0)
+        sh = orc.cell_shape(g)[1:]
+        if etakind == "const":
+            eta = np.ones(sh)
+        else:       # log-uniform, e^U(-2, 2) cell by cell
+            eta = np.exp(np.random.default_rng(5).uniform(-2.0, 2.0, sh))
+        rhs = np.random.default_rng(0).standard_normal(orc.cell_shape(g, 2))
+        r = []
+        for c in cyc:
+            _, _, rep = orc.mg_solve(g, fl, orc.OP_VISC, eta, dt, rhs, max_cycles=c, fixed=1, krylov=0)
+            r.append(rep.rel_resid)
+        rates.append((r[1] / r[0]) ** (1.0 / (cyc[1] - cyc[0])))
+    return rates
+
+
+@pytest.mark.parametrize("bc", [None, ((1, 1), (0, 0)), ((1, 1), (1, 1))], ids=["walls", "channel", "periodic"])
+@pytest.mark.parametrize("etakind,bound", [("const", 0.2), ("loguniform", 0.5)])
+def test_tensor_vcycle_contraction_h_independent(bc, etakind, bound):
+    # plain V(2,2) on the viscous-dominated Helmholtz problem (dt eta/h^2 up
+    # to 4e3): a per-cycle factor below a bound that stays level from 32^2
+    # to 64^2, as geometric multigrid gives when smoother, transfers and
+    # coarse operators are consistent
+    rates = _visc_rates(bc, etakind)
+    assert max(rates) < bound, rates
+    assert rates[1] < 1.2 * rates[0], rates
+
+
+@pytest.mark.parametrize("d,n,bc", [(2, 8, None), (2, 8, ((1, 1), (0, 0))), (3, 4, None),
+                                    (3, 4, ((0, 0), (1, 1), (0, 0)))])
+def test_tensor_vcycle_keeps_the_exact_solution(d, n, bc):
+    # the dense solution is a fixed point of one V-cycle: the smoother is a
+    # splitting of the same operator and the coarse correction of a zero
+    # residual is zero, so any inconsistent term moves it
+    rng = np.random.default_rng(11)
+    g = orc.make_grid(d, [n] * d, 1.0 / n, bc=bc)
+    fl = orc.make_fluid(Re=2.0)
+    eta = np.exp(rng.uniform(-1, 2, orc.cell_shape(g)[1:]))
+    dt = 0.07
+    rhs = rng.standard_normal(orc.cell_shape(g, d))
+    A = orc.dense_matrix(g, fl, orc.OP_VISC, eta, dt)
+    xd = np.linalg.solve(A, rhs.ravel()).reshape(rhs.shape)
+    x, rc, rep = orc.mg_solve(g, fl, orc.OP_VISC, eta, dt, rhs, x0=xd, max_cycles=1, fixed=1, krylov=0)
+    assert rc == orc.OK and rep.cycles == 1
+    assert np.abs(x - xd).max() < 1e-12 * np.abs(xd).max()
+
+
+def _restrict_mean(gf, gc, f):
+    """mean of the 2^d children of every coarse cell ([C][nz][ny][nx])"""
+    d = gf.dim
+    C, nz, ny, nx = f.shape
+    if d == 2:
+        return f.reshape(C, 1, ny // 2, 2, nx // 2, 2).mean(axis=(3, 5))
+    return f.reshape(C, nz // 2, 2, ny // 2, 2, nx // 2, 2).mean(axis=(2, 4, 6))
+
+
+@pytest.mark.parametrize("d,bc", [(2, None), (2, ((1, 1), (0, 0))), (3, None), (3, ((0, 0), (0, 0), (1, 1)))])
+def test_tensor_vcycle_two_grid_correction(d, bc):
+    # on a 6^d grid the hierarchy has two levels (6 and 3 cells per axis),
+    # so one V-cycle without smoothing from zero is the two-grid coarse
+    # correction x = P A_2h^-1 R b: R the mean of the children, A_2h the
+    # operator rediscretised at 2h (constant viscosity, so the averaged coarse
+    # face viscosities equal the fine ones), P the linear prolongation with
+    # the odd (Dirichlet) image beyond walls
+    rng = np.random.default_rng(21)
+    gf = orc.make_grid(d, [6] * d, 1.0 / 6, bc=bc)
+    gc = orc.coarse_grid(gf)
+    fl = orc.make_fluid(Re=1.0)
+    dt = 0.3
+    b = rng.standard_normal(orc.cell_shape(gf, d))
+    x, rc, rep = orc.mg_solve(gf, fl, orc.OP_VISC, np.full(orc.cell_shape(gf)[1:], 1.5), dt, b,
+                              max_cycles=1, fixed=1, nu1=0, nu2=0, krylov=0)
+    assert rc == orc.OK
+    Ac = orc.dense_matrix(gc, fl, orc.OP_VISC, np.full(orc.cell_shape(gc)[1:], 1.5), dt)
+    ec = np.linalg.solve(Ac, _restrict_mean(gf, gc, b).ravel()).reshape(orc.cell_shape(gc, d))
+    ref = orc.prolong_cells(gf, gc, ec, -1.0)
+    assert np.abs(x - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+def test_tensor_plain_vcycles_equal_dense_lu(d, n):
+    rng = np.random.default_rng(8)
+    g = orc.lid_cavity(d, n)
+    fl = orc.make_fluid(Re=3.0)
+    dt = 0.05
+    eta = np.exp(rng.uniform(-1, 3, orc.cell_shape(g)[1:]))
+    rhs = rng.standard_normal(orc.cell_shape(g, d))
+    x, rc, rep = orc.mg_solve(g, fl, orc.OP_VISC, eta, dt, rhs, tol=1e-13, max_cycles=200, krylov=0)
+    assert rc == orc.OK
+    A = orc.dense_matrix(g, fl, orc.OP_VISC, eta, dt)
+    zero = np.zeros_like(rhs)
+    wall = zero - dt * orc.visc_div(g, eta / fl.Re, zero, hom=0)
+    xd = np.linalg.solve(A, rhs.ravel() - wall.ravel())
+    np.testing.assert_allclose(x.ravel(), xd, atol=1e-11 * np.abs(xd).max())
+
+
+def _centres(g, a):
+    return (np.arange(g.n[a]) + 0.5) * g.h
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_prolongation_exact_on_linear_fields_odd_at_walls(d):
+    # the viscous problem's corrections vanish on the walls (homogeneous
+    # Dirichlet): a coarse field linear in every coordinate and zero on the
+    # walls of one axis is prolonged exactly, the neighbour beyond that wall
+    # being the odd image -e (wall sign -1); other axes are periodic
+    n = 8
+    bc = [(orc.PERIODIC, orc.PERIODIC)] * d
+    bc[d - 1] = (orc.WALL, orc.WALL)
+    gf = orc.make_grid(d, [n] * d, 1.0 / n, bc=bc)
+    gc = orc.coarse_grid(gf)
+
+    def field(g):
+        # linear along the wall axis, odd about its low wall; constant along
+        # periodic axes (a periodic linear field does not exist)
+        z = _centres(g, d - 1)
+        shp = [1, 1, 1]
+        shp[2 - (d - 1)] = len(z)
+        f = np.broadcast_to((0.7 * z).reshape(shp), cell_shape_3(g)).copy()
+        return f[None]
+
+    e = field(gc)
+    x = orc.prolong_cells(gf, gc, e, -1.0)
+    # exact below the mid-plane (the image of the high wall makes the
+    # field piecewise linear, so compare the half next to the low wall)
+    ref = field(gf)
+    half = [slice(None)] * 4
+    half[1 + 2 - (d - 1)] = slice(0, n // 2)
+    assert np.abs(x[tuple(half)] - ref[tuple(half)]).max() < 1e-14
+    # with the even image (+1) the cells next to the wall are wrong
+    xw = orc.prolong_cells(gf, gc, e, 1.0)
+    assert np.abs(xw[tuple(half)] - ref[tuple(half)]).max() > 0.01
+
+
+def test_prolongation_exact_on_linear_fields_interior_and_even_at_walls():
+    # the MAC problem (zero flux, wall sign +1): a constant is prolonged
+    # exactly everywhere, and a linear field exactly away from the walls
+    gf = orc.lid_cavity(2, 16)
+    gc = orc.coarse_grid(gf)
+    e = np.full(orc.cell_shape(gc), 1.3)
+    assert np.abs(orc.prolong_cells(gf, gc, e, 1.0) - 1.3).max() < 1e-15
+    assert np.abs(orc.prolong_cells(gf, gc, e, -1.0) - 1.3).max() > 0.5
+    X, Y = np.meshgrid(_centres(gc, 0), _centres(gc, 1), indexing="xy")
+    e = (0.3 + 1.1 * X - 0.6 * Y)[None, None]
+    Xf, Yf = np.meshgrid(_centres(gf, 0), _centres(gf, 1), indexing="xy")
+    x = orc.prolong_cells(gf, gc, e, 1.0)[0, 0]
+    ref = 0.3 + 1.1 * Xf - 0.6 * Yf
+    assert np.abs(x[1:-1, 1:-1] - ref[1:-1, 1:-1]).max() < 1e-14
+
+
+def cell_shape_3(g):
+    return orc.cell_shape(g)[1:]
+
+
+def _face_centres(g, a):
+    """coordinates (x, y, z) of every face of axis a, in the face array order"""
+    ext = [g.n[0], g.n[1], g.n[2]]
+    nfa = g.n[a] if g.bc[a][0] == orc.PERIODIC else g.n[a] + 1
+    ext[a] = nfa
+    ks, js, is_ = np.meshgrid(np.arange(ext[2]), np.arange(ext[1]), np.arange(ext[0]), indexing="ij")
+    idx = [is_, js, ks]
+    xyz = []
+    for b in range(3):
+        if b >= g.dim:
+            xyz.append(np.zeros_like(is_, dtype=float))
+        elif b == a:
+            xyz.append(idx[b] * g.h)
+        else:
+            xyz.append((idx[b] + 0.5) * g.h)
+    return [c.ravel() for c in xyz]
+
+
+@pytest.mark.parametrize("d,bc", [(2, None), (2, ((1, 1), (0, 0))), (3, None), (3, ((0, 0), (1, 1), (0, 0)))])
+def test_face_viscosity_restriction_is_the_exact_face_average(d, bc):
+    # a coarse face is tiled by the 2^(d-1) fine faces at the same position
+    # along its axis; for a face field linear in every coordinate their mean
+    # is the field at the coarse face centre
+    n = 8
+    gf = orc.make_grid(d, [n] * d, 1.0 / n, bc=bc)
+    gc = orc.coarse_grid(gf)
+    c = np.array([0.4, 1.3, -0.7, 0.9])
+
+    def lin(g):
+        out = []
+        for a in range(d):
+            x, y, z = _face_centres(g, a)
+            out.append(c[0] + c[1] * x + c[2] * y + c[3] * z + 0.5 * a)
+        return np.concatenate(out)
+
+    got = orc.restrict_faces(gf, gc, lin(gf))
+    assert got.shape == lin(gc).shape
+    assert np.abs(got - lin(gc)).max() < 1e-14
+
+
 def test_mg_failure_paths():
     g = orc.lid_cavity(2, 16)
     fl = orc.make_fluid(Re=1.0)

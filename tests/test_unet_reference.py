@@ -56,3 +56,21 @@ def test_gradient_matches_finite_differences(seed):
         pm[i] -= h
         fd = (unet.loss(unet.forward(pp, x)[0], t) - unet.loss(unet.forward(pm, x)[0], t)) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * gmax + 1e-5 * abs(g[i]), (i, fd, g[i])
+
+
+def test_bf16_rounding_matches_torch():
+    # rbf is round-to-nearest-even to BF16; torch's float32 -> bfloat16
+    # conversion is the independent reference (CPU)
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    x = np.concatenate([
+        rng.standard_normal(20000) * 10.0 ** rng.uniform(-30, 30, 20000),
+        # exact ties between two BF16 neighbours (both parities of the kept bit)
+        np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 2.0 ** -130 * (1 + 2.0 ** -8)]),
+        np.array([0.0, -0.0, 1.0, -3.0, 3.0e38, 1e-40, 65504.0]),
+    ]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = unet.rbf(x)
+    same = (got == ref) | (np.isnan(got) & np.isnan(ref))
+    assert same.all(), x[~same][:5]
+
