@@ -191,6 +191,21 @@ int hb_project(hb_ctx* ctx, const double* ustar, double* p, double dt, double* u
 /* dt from the CFL condition: cfl h / max(max wall speed, max |u|). */
 int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the value
+ * of hb_cfl_dt without a context and without any allocation, bit for bit.
+ * grid: as for hb_create (wall speeds of non-periodic faces enter U_wall);
+ * u: [dim][cells] device FP64 in; dt_out: ONE device double out (caller-
+ * owned), cfl h / max(U_wall, max |u|), 0 when both vanish, NaN when u holds
+ * a non-finite value.  Asynchronous on hip_stream (NULL: default stream);
+ * nothing is read back, so it may be captured in a graph.  Its scratch is a
+ * static device array of 16384 words per GPU, shared by every call on that
+ * GPU: calls that overlap on one GPU race.  HB_ERR_ARG (message in
+ * hb_last_error(NULL)) for a null pointer, an invalid grid, cfl <= 0, or more
+ * than 67,108,864 velocity values (dim x cells); HB_ERR_DEVICE if the
+ * scratch address cannot be taken or a launch fails. */
+int hb_cfl_dt_noalloc(const hb_grid* grid, double cfl, const double* u, double* dt_out, void* hip_stream);
+
 /* One full time step in place: u^m -> u^{m+1}, p^{m-1/2} -> p^{m+1/2}.
  * dt <= 0 selects the CFL time step.  report nullable. */
 int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report);

@@ -18,6 +18,8 @@ namespace hb {
 
 static thread_local std::string g_create_err;
 
+void set_global_error(const char* msg) { g_create_err = msg; }
+
 #define HB_TRY(expr)                                                         \
     do {                                                                     \
         hipError_t e_ = (expr);                                              \
@@ -1089,7 +1091,7 @@ static void kt_free(Ctx* c)
 // creation
 // ---------------------------------------------------------------------------
 
-static const char* check_grid(const hb_grid* grid)
+const char* check_grid(const hb_grid* grid)
 {
     if (grid->dim != 2 && grid->dim != 3) return "dim must be 2 or 3";
     for (int a = 0; a < grid->dim; ++a) {

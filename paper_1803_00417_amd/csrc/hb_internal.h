@@ -298,6 +298,10 @@ struct Ctx {
 // next start/stop event pair of the kernel timer, counting one launch of
 // `bytes` algorithmic bytes
 void kt_pair(Ctx* c, hipEvent_t* start, hipEvent_t* stop, double bytes);
+// grid descriptor check of hb_create (message, or nullptr when valid), and
+// the thread's message for calls without a context (hb_last_error(NULL))
+const char* check_grid(const hb_grid* grid);
+void set_global_error(const char* msg);
 void kt_harvest(Ctx* c);
 
 // ---- launch helpers --------------------------------------------------------

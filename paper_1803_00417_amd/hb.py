@@ -31,7 +31,7 @@ EXPORTS = ["hb_create", "hb_destroy", "hb_last_error", "hb_viscosity", "hb_mg_so
            "hb_nn_set_params", "hb_nn_forward", "hb_nn_grad", "hb_nn_train_step", "hb_set_warm_start",
            "hb_warm_start_uses", "hb_capture", "hb_capture_read", "hb_kernel_timing", "hb_kernel_timing_read",
            "hb_tile_config", "hb_run_steady", "hb_refine_state", "hb_run_sequenced", "hb_checkpoint_write",
-           "hb_checkpoint_read", "hb_yield", "hb_run_cessation"]
+           "hb_checkpoint_read", "hb_yield", "hb_run_cessation", "hb_cfl_dt_noalloc"]
 
 
 class Grid(C.Structure):
@@ -129,6 +129,7 @@ def load():
     L.hb_checkpoint_read.argtypes = [vp, C.c_char_p, vp, vp, P(C.c_int64), P(C.c_double)]
     L.hb_yield.argtypes = [vp, vp, vp, P(YieldReport)]
     L.hb_run_cessation.argtypes = [vp, vp, vp, C.c_int, C.c_double, P(CessationReport)]
+    L.hb_cfl_dt_noalloc.argtypes = [P(Grid), C.c_double, vp, vp, vp]
     _lib = L
     return L
 
@@ -243,6 +244,20 @@ def _ptr(t, numel, name):
     if numel is not None and t.numel() != numel:
         raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
     return C.c_void_p(t.data_ptr())
+
+
+def cfl_dt_noalloc(grid, cfl, u, dt_out, stream=None):
+    """hb_cfl_dt_noalloc: the CFL step of u on grid into the one-element
+    float64 GPU tensor dt_out, asynchronously, without a context or any
+    allocation (stream: a torch stream, default the current one)."""
+    L = load()
+    n = grid.dim * grid.n[0] * grid.n[1] * grid.n[2]
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = L.hb_cfl_dt_noalloc(C.byref(grid), float(cfl), _ptr(u, n, "u"), _ptr(dt_out, 1, "dt_out"),
+                             C.c_void_p(stream.cuda_stream))
+    if rc != OK:
+        raise HBError(rc, L.hb_last_error(None).decode())
 
 
 class Context:
