@@ -29,9 +29,15 @@
  * and never frees caller memory.
  *
  * Streams.  Work runs asynchronously on the hipStream_t given to hb_create
- * (NULL = the default stream).  A call that fills a report, or that must
- * choose dt from the CFL condition or decide multigrid convergence, reads
- * scalars back and therefore synchronises the stream before returning.
+ * (NULL = the default stream).  Multigrid convergence is decided on the
+ * device: after each V-cycle (or BiCGStab half step) a small kernel tests
+ * the residual and stops the cavity, and the cycle kernels skip stopped
+ * cavities; the host only waits for the active count one check point late,
+ * so the GPU always has the next cycle queued.  A call reads its outcome
+ * (return code, report) once at its end, and a step whose dt comes from the
+ * CFL condition reads max |u| once at its start; both synchronise.  A solve
+ * that meets a non-finite value leaves the outputs of that call undefined
+ * (the call returns HB_ERR_NONFINITE).
  *
  * Errors.  Functions return HB_OK or a negative code; nothing throws or
  * aborts across the ABI.  Arguments are checked before any device work.

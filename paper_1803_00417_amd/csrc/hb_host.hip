@@ -113,6 +113,7 @@ static std::vector<GridD> level_grids(const GridD& g0)
 static int build_mg(Ctx* c, MG& m, int op)
 {
     m.op = op;
+    m.rec = op == HB_OP_VISC ? S_REC_VISC : (op == HB_OP_MAC ? S_REC_MAC : S_REC_NODAL);
     m.ncomp = op == HB_OP_VISC ? c->dim : 1;
     const int nb = c->nb;
     std::vector<std::vector<GridD>> lg(nb);
@@ -600,76 +601,66 @@ static void precond(Ctx* c, MG& m, const double* r, double* z, int nu1, int nu2,
     L.b = sb;
 }
 
-// ---- per-cavity bookkeeping of a batched solve ---------------------------
-
-struct SolveOut {
-    int cycles = 0;
-    double rel = 0.0, bn = 0.0;
-    int rc = HB_OK;
-};
-
-// copy a flag array to the device unless the device already holds it
-static void upload_flags(Ctx* c, int* dev, const int* host)
-{
-    std::vector<int>& shadow = dev == c->act ? c->dact : (dev == c->act2 ? c->dact2 : c->dsel);
-    if ((int)shadow.size() == c->nb && std::equal(shadow.begin(), shadow.end(), host)) return;
-    shadow.assign(host, host + c->nb);
-    set_flags(c, dev, host);
-}
+// ---- the solve loop ----------------------------------------------------------
+//
+// Every convergence decision is taken on the device (k_conv, one small kernel
+// per check point: after the first residual, after each V-cycle, after each
+// BiCGStab half step), in the order a host-driven loop would take it, and the
+// cycle kernels skip the cavities it has stopped.  The host only has to know
+// when to stop launching: after queueing the work up to check point j + 1 it
+// waits for the active count of check point j, so the GPU always has the
+// next block of work queued while the host waits, and the block queued after
+// the last active check point finds every cavity stopped.  The per-cavity
+// outcome (|b|, cycles, relative residual, return code) stays in the
+// operator's record slots until the host reads all slots once per step.
 
 static double slot(const Ctx* c, int b, int s) { return c->hsc[(long)b * S_NSLOT + s]; }
 
-// the convergence test before a cycle: true when the cavity stops here
-static bool stops(SolveOut& so, const hb_mg_opts& o)
-{
-    if (o.fixed_cycles) return so.cycles >= o.max_cycles;
-    if (so.rel <= o.tol_rel) return true;
-    if (so.cycles >= o.max_cycles) {
-        so.rc = HB_ERR_NOCONV;
-        return true;
+struct ConvLoop {
+    Ctx* c;
+    ConvArgs a{};
+    unsigned long long prev = 0, last = 0;
+    ConvLoop(Ctx* cc, const MG& m, const hb_mg_opts& o) : c(cc)
+    {
+        a.nb = cc->nb;
+        a.rec = m.rec;
+        a.tol = o.tol_rel;
+        a.max_cycles = o.max_cycles;
+        a.fixed = o.fixed_cycles;
     }
-    return false;
-}
-
-static int any_set(const Ctx* c, const int* f)
-{
-    int n = 0;
-    for (int b = 0; b < c->nb; ++b) n += f[b] != 0;
-    return n;
-}
+    // a check point whose active count is published
+    void check(int mode, int cur_sel = 0)
+    {
+        a.mode = mode;
+        a.cur_sel = cur_sel;
+        a.seq = ++c->cseq;
+        launch_conv(c, a);
+        prev = last;
+        last = a.seq;
+    }
+    // a rule applied without publication
+    void apply(int mode)
+    {
+        a.mode = mode;
+        a.cur_sel = 0;
+        a.seq = 0;
+        launch_conv(c, a);
+    }
+    // true while the check point before the last one had active cavities
+    bool lagged_active() const { return prev == 0 || wait_active(c, prev) != 0; }
+};
 
 // Multigrid (optionally BiCGStab-accelerated) solves A x = b of every cavity
 // on the prepared level-0 systems; x, b are level-0 arenas.  Cavities stop
 // independently.  With mixed precision every V-cycle runs in FP32 on the
 // FP64 residual (defect correction, or the BiCGStab preconditioner);
-// residuals, norms and the iterate stay FP64.  The pinned host flag arrays
-// are written only after a synchronisation, so no upload still in flight
-// reads them.
-static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o, std::vector<SolveOut>& so)
+// residuals, norms and the iterate stay FP64.  Requires CV_BEGIN.
+static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o)
 {
     Level& L = m.L[0];
-    const int nb = c->nb;
     const bool lo = o.precision == HB_PREC_MIXED;
-    int* act = c->hact;
-    int* act2 = c->hact2;
-    // cavities with b = 0 have x = 0; the others start active
-    for (int i = 0; i < nb; ++i) {
-        act[i] = so[i].rc == HB_OK && so[i].bn != 0.0;
-        act2[i] = so[i].rc == HB_OK && so[i].bn == 0.0;
-    }
-    upload_flags(c, c->act2, act2);
-    seg_fill(c, seg_of(m, c->act2), x, 0.0);
-    upload_flags(c, c->act, act);
     const SegV sv = seg_of(m, c->act);
-    auto take_rel = [&](int i) {
-        so[i].rel = slot(c, i, S_MAX) / so[i].bn;
-        if (!std::isfinite(so[i].rel)) {
-            so[i].rc = HB_ERR_NONFINITE;
-            return false;
-        }
-        return true;
-    };
-
+    ConvLoop cl(c, m, o);
     if (!o.krylov) {
         // Plain V-cycles.  FP64: on the level's double buffer seeded with x.
         // Mixed: x in the first FP64 buffer; each cycle corrects it by one
@@ -678,19 +669,8 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o,
         double* xw = L.xb[0];
         seg_copy(c, sv, xw, x);
         resid0(c, m, xw, b, L.r, c->act);
-        fetch_slots(c);
-        for (int i = 0; i < nb; ++i) {
-            c->hsel[i] = 0;
-            if (act[i] && !take_rel(i)) act[i] = 0;
-        }
-        for (;;) {
-            for (int i = 0; i < nb; ++i)
-                if (act[i] && stops(so[i], o)) {
-                    act[i] = 0;
-                    c->hsel[i] = lo ? 0 : L.cur;
-                }
-            if (!any_set(c, act)) break;
-            upload_flags(c, c->act, act);
+        cl.check(CV_INIT, 0);
+        for (int k = 0; k < o.max_cycles; ++k) {
             if (lo) {
                 L.cur = 0;
                 seg_to_f32(c, sv, L.r, L.fb, L.fx[0]);
@@ -701,102 +681,49 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o,
                 vcycle<double>(c, m, 0, o.nu1, o.nu2);
                 resid0(c, m, L.X(), b, L.r, c->act);
             }
-            fetch_slots(c);
-            for (int i = 0; i < nb; ++i) {
-                if (!act[i]) continue;
-                ++so[i].cycles;
-                if (!take_rel(i)) {
-                    act[i] = 0;
-                    c->hsel[i] = lo ? 0 : L.cur;
-                }
-            }
+            cl.check(CV_CYCLE, lo ? 0 : L.cur);
+            if (!cl.lagged_active()) break;
         }
         // copy out each cavity's iterate from the buffer it ended in
-        for (int i = 0; i < nb; ++i) act2[i] = so[i].bn != 0.0 && so[i].rc != HB_ERR_NONFINITE ? 1 : 0;
-        upload_flags(c, c->act2, act2);
-        upload_flags(c, c->sel, c->hsel);
+        cl.apply(CV_END_PLAIN);
         seg_copy_sel(c, seg_of(m, c->act2), x, L.xb[0], L.xb[1], c->sel);
-        fetch_slots(c);   // the flag uploads above have completed
         return;
     }
 
-    // BiCGStab with its scalars kept on the device, per cavity: two host
-    // reads per iteration (the residual norms that decide convergence)
+    // BiCGStab with its scalars kept on the device, per cavity
     double *r = c->kr, *rh = c->krh, *p = c->kp, *v = c->kv, *ph = c->kph, *s = c->ks, *sh = c->ksh, *t = c->kt;
     resid0(c, m, x, b, r, c->act);
     seg_copy(c, sv, rh, r);
     seg_fill(c, sv, p, 0.0);
     seg_fill(c, sv, v, 0.0);
     bicg_init_scalars(c, c->act);
-    fetch_slots(c);
-    for (int i = 0; i < nb; ++i)
-        if (act[i] && !take_rel(i)) act[i] = 0;
-    for (;;) {
-        for (int i = 0; i < nb; ++i)
-            if (act[i] && stops(so[i], o)) act[i] = 0;
-        if (!any_set(c, act)) break;
-        upload_flags(c, c->act, act);
+    cl.check(CV_INIT, 0);
+    // a cavity may take one V-cycle past max_cycles (its last half step)
+    for (int k = 0; k < o.max_cycles + 1; k += 2) {
         seg_dot_then(c, sv, rh, r, S_DOT0, 1, -1);   // rho, beta
         bicg_p_dev(c, sv, p, r, v);
         precond(c, m, p, ph, o.nu1, o.nu2, lo);
         apply0(c, m, ph, v);
         seg_dot_then(c, sv, rh, v, S_DOT1, 2, S_MAX);   // alpha; S_MAX cleared for the max of s
         sub_scaled_max_dev(c, sv, s, r, S_ALPHA, v, S_MAX);
-        fetch_slots(c);
+        cl.check(CV_HALF);
         // cavities that finish at the half step: x += alpha ph, r = s
-        for (int i = 0; i < nb; ++i) {
-            act2[i] = 0;
-            if (!act[i]) continue;
-            ++so[i].cycles;
-            if (slot(c, i, S_RHO) == 0.0) {
-                so[i].rc = HB_ERR_NOCONV;
-                act[i] = 0;
-                continue;
-            }
-            const double srel = slot(c, i, S_MAX) / so[i].bn;
-            if ((!o.fixed_cycles && srel <= o.tol_rel) || (o.fixed_cycles && so[i].cycles >= o.max_cycles)) {
-                act2[i] = 1;
-                act[i] = 0;
-                so[i].rel = srel;
-            }
-        }
-        if (any_set(c, act2)) {
-            upload_flags(c, c->act2, act2);
-            const SegV sv2 = seg_of(m, c->act2);
-            bicg_x_dev(c, sv2, x, ph, nullptr, false);
-            seg_copy(c, sv2, r, s);
-        }
-        upload_flags(c, c->act, act);
-        if (!any_set(c, act)) {
-            fetch_slots(c);
-            break;
-        }
+        const SegV sv2 = seg_of(m, c->act2);
+        bicg_x_dev(c, sv2, x, ph, nullptr, false);
+        seg_copy(c, sv2, r, s);
+        if (!cl.lagged_active()) break;
         precond(c, m, s, sh, o.nu1, o.nu2, lo);
         apply0(c, m, sh, t);
         seg_dot2_then(c, sv, t, t, S_DOT0, s, S_DOT1, 3, S_MAX);   // t.t, t.s, omega; S_MAX cleared for the max of r
         bicg_x_dev(c, sv, x, ph, sh, true);
         sub_scaled_max_dev(c, sv, r, s, S_OMEGA, t, S_MAX);
-        fetch_slots(c);
-        for (int i = 0; i < nb; ++i) {
-            if (!act[i]) continue;
-            ++so[i].cycles;
-            if (!take_rel(i)) {
-                act[i] = 0;
-                continue;
-            }
-            if (slot(c, i, S_OMEGA) == 0.0) {
-                so[i].rc = HB_ERR_NOCONV;
-                act[i] = 0;
-            }
-        }
+        cl.check(CV_FULL);
+        if (!cl.lagged_active()) break;
     }
     // the true residual of every solved cavity
-    for (int i = 0; i < nb; ++i) act[i] = so[i].bn != 0.0 && so[i].rc != HB_ERR_NONFINITE ? 1 : 0;
-    upload_flags(c, c->act, act);
+    cl.apply(CV_END_KRYLOV);
     resid0(c, m, x, b, L.r, c->act);
-    fetch_slots(c);
-    for (int i = 0; i < nb; ++i)
-        if (act[i]) take_rel(i);
+    cl.apply(CV_FINAL);
 }
 
 // Start of a nodal solve of a single-cavity context: record the initial
@@ -839,40 +766,43 @@ static void nodal_prestart(Ctx* c, MG& m, double* x)
 }
 
 // Solve with the right-hand sides already in m.lvl0_b (VISC: wall part
-// added; NODAL/MAC: mean removed by this function).  x: level-0 arena.
-static int solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o, std::vector<SolveOut>& so)
+// added; NODAL/MAC: mean removed by this function).  x: level-0 arena.  The
+// outcome stays on the device (solve_outcome reads it).
+static void solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o)
 {
-    const int nb = c->nb;
-    so.assign(nb, SolveOut());
     const SegV all = seg_of(m, nullptr);
     if (m.op != HB_OP_VISC) seg_sub_mean(c, all, m.lvl0_b);
     if (m.op == HB_OP_NODAL && (c->ws || c->cap)) nodal_prestart(c, m, x);
     seg_maxabs(c, all, m.lvl0_b, S_MAX);
     seg_maxabs(c, all, x, S_MAX2);
-    fetch_slots(c);
-    int rc = HB_OK;
-    for (int i = 0; i < nb; ++i) {
-        so[i].bn = slot(c, i, S_MAX);
-        if (!std::isfinite(so[i].bn) || !std::isfinite(slot(c, i, S_MAX2))) so[i].rc = HB_ERR_NONFINITE;
-    }
     if (o.precision == HB_PREC_MIXED) ensure_f32(c, m);
-    solve_core(c, m, x, m.lvl0_b, o, so);
+    ConvLoop(c, m, o).apply(CV_BEGIN);
+    // cavities with b = 0 have x = 0
+    seg_fill(c, seg_of(m, c->act2), x, 0.0);
+    solve_core(c, m, x, m.lvl0_b, o);
     if (m.op != HB_OP_VISC) seg_sub_mean(c, all, x);
     if (m.op == HB_OP_NODAL && c->cap) launch_axpy(c, c->cap_e, x, c->cap_x0, -1.0, m.L[0].nu);
-    for (int i = 0; i < nb; ++i) {
-        if (so[i].rc == HB_ERR_NONFINITE) rc = HB_ERR_NONFINITE;
-        else if (so[i].rc == HB_ERR_NOCONV && rc == HB_OK) rc = HB_ERR_NOCONV;
+}
+
+// The outcome of the last solve of m per cavity, from the slots a
+// fetch_slots has brought to the host, and the worst return code.
+static int solve_outcome(Ctx* c, const MG& m, std::vector<hb_mg_report>* rep)
+{
+    int rc = HB_OK;
+    for (int b = 0; b < c->nb; ++b) {
+        const double* R = c->hsc + (long)b * S_NSLOT + m.rec;
+        const int src = (int)R[R_RC];
+        if (rep) {
+            (*rep)[b].cycles = (int)R[R_CYC];
+            (*rep)[b].rel_resid = R[R_REL];
+            (*rep)[b].bnorm = R[R_BN];
+        }
+        if (src == HB_ERR_NONFINITE) rc = HB_ERR_NONFINITE;
+        else if (src == HB_ERR_NOCONV && rc == HB_OK) rc = HB_ERR_NOCONV;
     }
     if (rc == HB_ERR_NOCONV) c->err = "multigrid did not reach the tolerance within max_cycles";
     if (rc == HB_ERR_NONFINITE) c->err = "non-finite right-hand side, guess or residual in a multigrid solve";
     return rc;
-}
-
-static void to_report(const SolveOut& s, hb_mg_report* r)
-{
-    r->cycles = s.cycles;
-    r->rel_resid = s.rel;
-    r->bnorm = s.bn;
 }
 
 static bool valid_opts(const hb_mg_opts& o)
@@ -908,12 +838,12 @@ static void advect_predict(Ctx* c, int b, const double* u, const double* p, doub
 }
 
 // MAC projection of every cavity's face velocity, then each cavity's
-// viscous right-hand side into rhs (and conv when given)
-static int advect_finish(Ctx* c, const std::vector<const double*>& u, const std::vector<double>& dt,
-                         const std::vector<double*>& rhs, const std::vector<double*>& conv,
-                         std::vector<hb_mg_report>* mrep, std::vector<double>* div_rel)
+// viscous right-hand side into rhs (and conv when given); with div_rel, the
+// MAC divergence after the projection relative to before it (host reads)
+static void advect_finish(Ctx* c, const std::vector<const double*>& u, const std::vector<double>& dt,
+                          const std::vector<double*>& rhs, const std::vector<double*>& conv,
+                          std::vector<double>* div_rel)
 {
-    int rc = HB_OK;
     const int nb = c->nb;
     std::vector<double> d0(nb, 0.0);
     if (c->opts.mac_project) {
@@ -923,11 +853,9 @@ static int advect_finish(Ctx* c, const std::vector<const double*>& u, const std:
             for (int b = 0; b < nb; ++b) d0[b] = slot(c, b, S_MAX);
         }
         fill(c, c->macphi, 0.0, c->mac.L[0].nu);
-        std::vector<SolveOut> so;
-        rc = solve_prepared(c, c->mac, c->macphi, c->opts.mac, so);
+        solve_prepared(c, c->mac, c->macphi, c->opts.mac);
         for (int b = 0; b < nb; ++b) {
             launch_mac_update(c, c->cv[b]);
-            if (mrep) to_report(so[b], &(*mrep)[b]);
             if (div_rel) {
                 launch_mac_div(c, c->cv[b], c->cv[b].umac, c->cv[b].macrhs);
                 red_maxabs(c, b, c->cv[b].macrhs, c->cv[b].nc, S_MAX);
@@ -940,18 +868,25 @@ static int advect_finish(Ctx* c, const std::vector<const double*>& u, const std:
     } else {
         for (int b = 0; b < nb; ++b) {
             copy(c, c->cv[b].umac, c->cv[b].uadv, c->cv[b].nf);
-            if (mrep) memset(&(*mrep)[b], 0, sizeof(hb_mg_report));
             if (div_rel) (*div_rel)[b] = 0.0;
         }
     }
     for (int b = 0; b < nb; ++b) launch_advect_rhs(c, c->cv[b], u[b], dt[b], rhs[b], conv[b]);
-    return rc;
+}
+
+// outcome of the step's MAC solve (zero reports when it does not run)
+static int mac_outcome(Ctx* c, std::vector<hb_mg_report>* rep)
+{
+    if (c->opts.mac_project) return solve_outcome(c, c->mac, rep);
+    if (rep)
+        for (auto& r : *rep) memset(&r, 0, sizeof(r));
+    return HB_OK;
 }
 
 // projection of every cavity: V = ustar/dt + G p, K phi = weak div V,
 // u = ustar + dt (G p - G phi), p = phi
-static int project_all(Ctx* c, const std::vector<const double*>& ustar, const std::vector<double*>& p,
-                       const std::vector<double>& dt, const std::vector<double*>& u, std::vector<hb_mg_report>* rep)
+static void project_all(Ctx* c, const std::vector<const double*>& ustar, const std::vector<double*>& p,
+                        const std::vector<double>& dt, const std::vector<double*>& u)
 {
     const int nb = c->nb;
     for (int b = 0; b < nb; ++b) {
@@ -960,15 +895,12 @@ static int project_all(Ctx* c, const std::vector<const double*>& ustar, const st
         launch_proj_rhs(c, v, ustar[b], dt[b], c->nodal.lvl0_b + c->nodal.L[0].ho[b]);
         copy(c, v.phi, p[b], v.nn);
     }
-    std::vector<SolveOut> so;
-    int rc = solve_prepared(c, c->nodal, c->phi, c->opts.proj, so);
+    solve_prepared(c, c->nodal, c->phi, c->opts.proj);
     for (int b = 0; b < nb; ++b) {
         Cav& v = c->cv[b];
         launch_proj_update(c, v, ustar[b], v.phi, dt[b], u[b]);
         copy(c, p[b], v.phi, v.nn);
-        if (rep) to_report(so[b], &(*rep)[b]);
     }
-    return rc;
 }
 
 // One full step of every cavity in place.  dt[b] <= 0 selects the CFL time
@@ -1010,21 +942,15 @@ static int step_all(Ctx* c, double* const* u, double* const* p, const double* dt
         advect_predict(c, b, u[b], p[b], dt[b]);
         v.step_dt = dt[b];
     }
-    int rc = advect_finish(c, uc, dt, rhs, conv, &mrep, reports ? &divr : nullptr);
-    if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
+    advect_finish(c, uc, dt, rhs, conv, reports ? &divr : nullptr);
     for (int b = 0; b < nb; ++b) {
         Cav& v = c->cv[b];
         launch_visc_wall_rhs(c, v.g, c->visc.L[0].beta + c->visc.L[0].hof[b], 2.0 * c->opts.theta * dt[b], v.rhs,
                              c->visc.lvl0_b + c->visc.L[0].hou[b]);
         copy(c, v.ustar, u[b], v.dim * v.nc);
     }
-    std::vector<SolveOut> so;
-    int rc2 = solve_prepared(c, c->visc, c->ustar, c->opts.visc, so);
-    for (int b = 0; b < nb; ++b) to_report(so[b], &vrep[b]);
-    rc = worse(rc2, rc);
-    if (rc != HB_OK && rc != HB_ERR_NOCONV) return rc;
-    rc2 = project_all(c, us, pv, dt, uv, &prep);
-    rc = worse(rc2, rc);
+    solve_prepared(c, c->visc, c->ustar, c->opts.visc);
+    project_all(c, us, pv, dt, uv);
     if (reports) {
         for (int b = 0; b < nb; ++b) {
             Cav& v = c->cv[b];
@@ -1032,7 +958,14 @@ static int step_all(Ctx* c, double* const* u, double* const* p, const double* dt
             launch_weak_div(c, v, u[b], v.rnode);
             red_maxabs(c, b, v.rnode, v.nn, S_MAX2);
         }
-        fetch_slots(c);
+    }
+    // the one read of the step's outcome: the solves' records (and the
+    // diagnostics of a report)
+    fetch_slots(c);
+    int rc = mac_outcome(c, &mrep);
+    rc = worse(solve_outcome(c, c->visc, &vrep), rc);
+    rc = worse(solve_outcome(c, c->nodal, &prep), rc);
+    if (reports) {
         for (int b = 0; b < nb; ++b) {
             hb_step_report& R = reports[b];
             memset(&R, 0, sizeof(R));
@@ -1268,6 +1201,8 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
     bool ok = dalloc(&c->sc, (long)S_NSLOT * count) == hipSuccess &&
               hipHostMalloc((void**)&c->hsc, sizeof(double) * S_NSLOT * count, pin) == hipSuccess &&
               hipHostMalloc((void**)&c->hseq, sizeof(unsigned long long), pin) == hipSuccess &&
+              hipHostMalloc((void**)&c->hring, sizeof(unsigned long long) * kRing, pin) == hipSuccess &&
+              hipHostGetDevicePointer((void**)&c->dring, c->hring, 0) == hipSuccess &&
               hipHostGetDevicePointer((void**)&c->dhsc, c->hsc, 0) == hipSuccess &&
               hipHostGetDevicePointer((void**)&c->dhseq, c->hseq, 0) == hipSuccess &&
               dalloc(&c->partial, 2L * kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
@@ -1280,6 +1215,7 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
     if (!ok) return give_up(HB_ERR_OOM, "device allocation failed");
     memset(c->hsc, 0, sizeof(double) * S_NSLOT * count);
     *c->hseq = 0;
+    for (int i = 0; i < kRing; ++i) c->hring[i] = ~0ull;
     c->cv.resize(count);
     for (int b = 0; b < count; ++b) {
         Cav& v = c->cv[b];
@@ -1392,6 +1328,7 @@ static void destroy_ctx(Ctx* c)
     (void)hipFree(c->cap_x0);
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hseq) (void)hipHostFree(c->hseq);
+    if (c->hring) (void)hipHostFree(c->hring);
     if (c->hact) (void)hipHostFree(c->hact);
     if (c->hact2) (void)hipHostFree(c->hact2);
     if (c->hsel) (void)hipHostFree(c->hsel);
@@ -1492,9 +1429,11 @@ int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt, const double*
     } else {
         copy(c, m.lvl0_b, rhs, m.L[0].nu);
     }
-    std::vector<SolveOut> so;
-    const int rc = solve_prepared(c, m, x, o, so);
-    if (report) to_report(so[0], report);
+    solve_prepared(c, m, x, o);
+    fetch_slots(c);
+    std::vector<hb_mg_report> rep(1);
+    const int rc = solve_outcome(c, m, &rep);
+    if (report) *report = rep[0];
     return rc;
 }
 
@@ -1511,10 +1450,12 @@ int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta, 
     red_maxabs(c, 0, u, v.dim * v.nc, S_MAXU);
     visc_setup(c, 0, eta, dt);
     advect_predict(c, 0, u, p, dt);
-    std::vector<hb_mg_report> mrep(1);
-    const int rc = advect_finish(c, {u}, {dt}, {b}, {conv}, &mrep, nullptr);
-    if (mac_report) *mac_report = mrep[0];
+    advect_finish(c, {u}, {dt}, {b}, {conv}, nullptr);
     if (umac) copy(c, umac, v.umac, v.nf);
+    fetch_slots(c);
+    std::vector<hb_mg_report> mrep(1);
+    const int rc = mac_outcome(c, &mrep);
+    if (mac_report) *mac_report = mrep[0];
     if (hipStreamSynchronize(c->s) != hipSuccess) return fail(c, HB_ERR_DEVICE, "stream synchronisation failed");
     return rc;
 }
@@ -1527,8 +1468,10 @@ int hb_project(hb_ctx* ctx, const double* ustar, double* p, double dt, double* u
     if (!ustar || !p || !u) return fail(c, HB_ERR_ARG, "null array");
     if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
     StreamGuard guard(c);
+    project_all(c, {ustar}, {p}, {dt}, {u});
+    fetch_slots(c);
     std::vector<hb_mg_report> rep(1);
-    const int rc = project_all(c, {ustar}, {p}, {dt}, {u}, &rep);
+    const int rc = solve_outcome(c, c->nodal, &rep);
     if (report) *report = rep[0];
     return rc;
 }

@@ -31,8 +31,34 @@ enum Slot {
     S_CHG = 13, S_CHGREF = 14,
     // BiCGStab scalars, computed and used on the device
     S_RHO = 8, S_RHOP = 9, S_ALPHA = 10, S_OMEGA = 11, S_BETA = 12,
-    S_NSLOT = 16
+    // per-solve records, kept on the device while the solve runs (decided
+    // there, read by the host once per step): |b|_inf, relative residual,
+    // V-cycles, return code; one record per operator
+    S_REC_MAC = 16, S_REC_VISC = 20, S_REC_NODAL = 24,
+    S_NSLOT = 32
 };
+enum RecField { R_BN = 0, R_REL = 1, R_CYC = 2, R_RC = 3 };
+
+// Convergence decisions of a multigrid solve, taken on the device by one
+// small kernel per check point (the host only learns, one check point late,
+// whether any cavity is still active).
+enum ConvMode {
+    CV_BEGIN = 0,      // record |b| (slot S_MAX) and the finiteness of b, x; set the active flags
+    CV_INIT = 1,       // after the first residual: relative residual, stop test
+    CV_CYCLE = 2,      // after a V-cycle (plain iteration): count it, residual, stop test
+    CV_HALF = 3,       // BiCGStab half step: count, finish on |s| (flags act2)
+    CV_FULL = 4,       // BiCGStab full step: count, residual, breakdown, stop test
+    CV_END_PLAIN = 5,  // act2 = the cavities whose iterate is copied out
+    CV_END_KRYLOV = 6, // act = the cavities whose true residual is taken
+    CV_FINAL = 7       // relative true residual of those
+};
+struct ConvArgs {
+    int nb, rec, mode, cur_sel;
+    double tol;
+    int max_cycles, fixed;
+    unsigned long long seq;   // publication number of the active count (0: none)
+};
+constexpr int kRing = 8;      // entries of the pinned ring of active counts
 
 // Batched view of one multigrid level, passed by value to the cycle kernels.
 // Block z index = cavity * zb + z-block within the cavity.
@@ -42,9 +68,10 @@ struct BV {
     const long* of;     // per cavity offset of the face arrays (tensor problem)
     const int* act;     // per cavity active flag (nullptr: all active)
     int zb;             // z-blocks per cavity in the launch grid
-    // Single-cavity contexts: the grids travel in the kernel arguments, the
-    // offsets are 0 and the cavity is active whenever the host launches, so
-    // a block's first data loads do not wait for table reads.
+    // Single-cavity contexts: the grids travel in the kernel arguments and
+    // the offsets are 0, so a block's first data loads wait only for its
+    // active flag (the device stops a converged solve; the host does not
+    // know when).
     int one = 0;
     GridD g1{};         // the cavity's grid on this level (dim 0: takes no part)
     GridD g2{};         // its grid on the paired level of a transfer kernel
@@ -87,7 +114,7 @@ __device__ inline bool bv_enter_at(const BV& v, int bzg, int& cav, int& bz, Grid
         cav = 0;
         bz = bzg;
         g = v.g1;
-        return g.dim != 0;
+        return g.dim != 0 && (!v.act || v.act[0]);
     }
     cav = bzg / v.zb;
     bz = bzg - cav * v.zb;
@@ -106,7 +133,7 @@ __device__ inline bool bv_enter(const BV& v, int& cav, int& bz, GridD& g)
         cav = 0;
         bz = blockIdx.z;
         g = v.g1;
-        return g.dim != 0;
+        return g.dim != 0 && (!v.act || v.act[0]);
     }
     cav = blockIdx.z / v.zb;
     bz = blockIdx.z - cav * v.zb;
@@ -217,6 +244,7 @@ struct MG {
     int tail_lt = -1;
     size_t tail_lds[2] = {0, 0};
     TailPlan* tplan = nullptr;    // per cavity (device)
+    int rec = S_REC_MAC;          // first slot of this operator's solve record
 };
 
 // one cavity of a context: its descriptors and the step's scratch
@@ -271,6 +299,11 @@ struct Ctx {
     double* dhsc = nullptr;               // device addresses of hsc and hseq
     unsigned long long* dhseq = nullptr;
     unsigned long long pub = 0;           // last publication number
+    // active counts published by the convergence kernels: entry seq % kRing
+    // holds (count << 32) | (seq & 0xffffffff) (pinned, device-mapped)
+    unsigned long long* hring = nullptr;
+    unsigned long long* dring = nullptr;
+    unsigned long long cseq = 0;          // last check point number
     double* partial = nullptr;   // reduction partials (2 x kRedBlocks per cavity)
     unsigned long long* mpart = nullptr;   // max-norm partials (kSubMax per cavity, kept zero between uses)
     int* act = nullptr;          // device active flags (nb)
@@ -347,6 +380,12 @@ struct FlagArgs {
 };
 void set_flags(Ctx* c, int* dev, const int* host);
 void fetch_slots(Ctx* c);  // all slots to c->hsc once the stream's work so far has completed
+// launch the convergence kernel of a check point; publish (a.seq != 0) the
+// number of cavities still active
+void launch_conv(Ctx* c, const ConvArgs& a);
+// wait until check point seq has published; returns its active count (-1
+// if it never did, even after a stream synchronisation)
+int wait_active(Ctx* c, unsigned long long seq);
 void copy(Ctx* c, double* dst, const double* src, long n);
 void fill(Ctx* c, double* dst, double v, long n);
 // segmented forms over the batch (per cavity slot, inactive cavities skipped)

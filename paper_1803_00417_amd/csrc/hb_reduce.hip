@@ -97,6 +97,139 @@ void fetch_slots(Ctx* c)
     (void)hipMemcpy(c->hsc, c->sc, sizeof(double) * n, hipMemcpyDeviceToHost);
 }
 
+// ---- convergence decisions on the device -----------------------------------
+
+__device__ inline bool conv_stops(double* R, const ConvArgs& a)
+{
+    const double cyc = R[R_CYC];
+    if (a.fixed) return cyc >= (double)a.max_cycles;
+    if (R[R_REL] <= a.tol) return true;
+    if (cyc >= (double)a.max_cycles) {
+        R[R_RC] = (double)HB_ERR_NOCONV;
+        return true;
+    }
+    return false;
+}
+
+// relative residual from slot S_MAX; false (and NONFINITE) when not finite
+__device__ inline bool conv_take_rel(double* S, double* R)
+{
+    const double rel = S[S_MAX] / R[R_BN];
+    R[R_REL] = rel;
+    if (!isfinite(rel)) {
+        R[R_RC] = (double)HB_ERR_NONFINITE;
+        return false;
+    }
+    return true;
+}
+
+// One thread per cavity applies the check point's rule (the rules of a
+// host-driven loop, in the same order), then the block counts the cavities
+// still active and thread 0 publishes the count with the check point number
+// by one system-scope release store into the pinned ring.
+__global__ void __launch_bounds__(1024) k_conv(ConvArgs a, double* __restrict__ sc, int* __restrict__ act,
+                                               int* __restrict__ act2, int* __restrict__ sel,
+                                               unsigned long long* ring)
+{
+    __shared__ double sh[1024 / 64];
+    double nact = 0.0;
+    for (int i = threadIdx.x; i < a.nb; i += blockDim.x) {
+        double* S = sc + (long)i * S_NSLOT;
+        double* R = S + a.rec;
+        switch (a.mode) {
+        case CV_BEGIN: {
+            const double bn = S[S_MAX];
+            const bool ok = isfinite(bn) && isfinite(S[S_MAX2]);
+            R[R_BN] = bn;
+            R[R_REL] = 0.0;
+            R[R_CYC] = 0.0;
+            R[R_RC] = ok ? (double)HB_OK : (double)HB_ERR_NONFINITE;
+            act[i] = ok && bn != 0.0;
+            act2[i] = ok && bn == 0.0;
+            sel[i] = 0;
+            break;
+        }
+        case CV_INIT:
+        case CV_CYCLE:
+            if (!act[i]) break;
+            if (a.mode == CV_CYCLE) R[R_CYC] += 1.0;
+            if (!conv_take_rel(S, R) || conv_stops(R, a)) {
+                act[i] = 0;
+                sel[i] = a.cur_sel;
+            }
+            break;
+        case CV_HALF: {
+            act2[i] = 0;
+            if (!act[i]) break;
+            R[R_CYC] += 1.0;
+            if (S[S_RHO] == 0.0) {
+                R[R_RC] = (double)HB_ERR_NOCONV;
+                act[i] = 0;
+                break;
+            }
+            const double srel = S[S_MAX] / R[R_BN];
+            if ((!a.fixed && srel <= a.tol) || (a.fixed && R[R_CYC] >= (double)a.max_cycles)) {
+                act2[i] = 1;
+                act[i] = 0;
+                R[R_REL] = srel;
+            }
+            break;
+        }
+        case CV_FULL:
+            if (!act[i]) break;
+            R[R_CYC] += 1.0;
+            if (!conv_take_rel(S, R)) {
+                act[i] = 0;
+                break;
+            }
+            if (S[S_OMEGA] == 0.0) {
+                R[R_RC] = (double)HB_ERR_NOCONV;
+                act[i] = 0;
+                break;
+            }
+            if (conv_stops(R, a)) act[i] = 0;
+            break;
+        case CV_END_PLAIN:
+            act2[i] = R[R_BN] != 0.0 && R[R_RC] != (double)HB_ERR_NONFINITE;
+            break;
+        case CV_END_KRYLOV:
+            act[i] = R[R_BN] != 0.0 && R[R_RC] != (double)HB_ERR_NONFINITE;
+            break;
+        case CV_FINAL:
+            if (act[i]) conv_take_rel(S, R);
+            break;
+        }
+        nact += act[i] != 0 ? 1.0 : 0.0;
+    }
+    nact = block_sum(nact, sh);
+    if (threadIdx.x == 0 && a.seq) {
+        const unsigned long long w = ((unsigned long long)nact << 32) | (a.seq & 0xffffffffull);
+        __hip_atomic_store(ring + a.seq % kRing, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+void launch_conv(Ctx* c, const ConvArgs& a)
+{
+    const int nt = c->nb >= 1024 ? 1024 : ((c->nb + 63) / 64) * 64;
+    k_conv<<<1, nt, 0, c->s>>>(a, c->sc, c->act, c->act2, c->sel, c->dring);
+}
+
+int wait_active(Ctx* c, unsigned long long seq)
+{
+    volatile unsigned long long* e = c->hring + seq % kRing;
+    const unsigned long long lo = seq & 0xffffffffull;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned it = 1;; ++it) {
+        const unsigned long long w = __atomic_load_n(const_cast<unsigned long long*>(e), __ATOMIC_ACQUIRE);
+        if ((w & 0xffffffffull) == lo) return (int)(w >> 32);
+        __builtin_ia32_pause();
+        if ((it & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
+    }
+    (void)hipStreamSynchronize(c->s);
+    const unsigned long long w = __atomic_load_n(const_cast<unsigned long long*>(e), __ATOMIC_ACQUIRE);
+    return (w & 0xffffffffull) == lo ? (int)(w >> 32) : -1;
+}
+
 // per-cavity flags passed by value (a copy command costs the runtime more
 // than a launch)
 __global__ void k_set_flags(int* __restrict__ dev, FlagArgs a)
