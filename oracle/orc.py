@@ -15,7 +15,11 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(HERE, "liborc.so")
+# the parity build (single-threaded, every loop in order) and, for timing
+# only, the same sources built with OpenMP (ORC_OMP=1 in the environment)
+LIB_SERIAL = os.path.join(HERE, "liborc.so")
+LIB_OMP = os.path.join(HERE, "liborc_omp.so")
+LIB = LIB_OMP if os.environ.get("ORC_OMP") == "1" else LIB_SERIAL
 SOURCES = ["orc_core.c", "orc_mg.c", "orc_step.c"]
 
 WALL, PERIODIC = 0, 1
@@ -26,18 +30,21 @@ OK, ERR_ARG, ERR_NOCONV, ERR_NONFINITE = 0, -1, -3, -4
 
 def build(force=False):
     """Compile liborc.so with gcc (no FMA contraction, so rounding is the
-    plain IEEE sequence written in the source)."""
+    plain IEEE sequence written in the source), and liborc_omp.so, the same
+    sources with OpenMP over the planes and rows of the heavy loops (CPU
+    timing only)."""
     srcs = [os.path.join(HERE, s) for s in SOURCES]
     hdrs = [os.path.join(HERE, s) for s in ("orc.h", "orc_internal.h")]
-    if not force and os.path.exists(LIB):
-        t = os.path.getmtime(LIB)
-        if all(os.path.getmtime(s) <= t for s in srcs + hdrs):
-            return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off",
-           "-o", tmp] + srcs + ["-lm"]
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    for lib_path, extra in ((LIB_SERIAL, []), (LIB_OMP, ["-fopenmp"])):
+        if not force and os.path.exists(lib_path):
+            t = os.path.getmtime(lib_path)
+            if all(os.path.getmtime(s) <= t for s in srcs + hdrs):
+                continue
+        tmp = lib_path + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off"] + extra + \
+              ["-o", tmp] + srcs + ["-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, lib_path)
     return LIB
 
 

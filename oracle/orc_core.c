@@ -153,6 +153,7 @@ void orc_visc_div_faces(const orc_grid* g, const double* beta, const double* u, 
 {
     const long N = ncells(g);
     for (int c = 0; c < g->dim; ++c)
+        ORC_PAR_KJ
         for (int k = 0; k < g->n[2]; ++k)
             for (int j = 0; j < g->n[1]; ++j)
                 for (int i = 0; i < g->n[0]; ++i)

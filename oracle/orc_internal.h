@@ -102,6 +102,15 @@ static inline void* xcalloc(long n, long sz)
     return p;
 }
 
+/* Timing build only (compiled with -fopenmp): the planes and rows of a loop
+ * nest, or of one colour of a smoother, split over threads.  The parity
+ * build has no OpenMP and runs every loop in order. */
+#ifdef _OPENMP
+#define ORC_PAR_KJ _Pragma("omp parallel for collapse(2) schedule(static)")
+#else
+#define ORC_PAR_KJ
+#endif
+
 static inline double vmax_abs(const double* v, long n)
 {
     double m = 0.0;

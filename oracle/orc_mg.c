@@ -130,6 +130,7 @@ static void smooth_visc(const mg_t* m, level_t* l, int sweeps)
     for (int s = 0; s < sweeps; ++s)
         for (int c = 0; c < g->dim; ++c)
             for (int colour = 0; colour < 2; ++colour)
+                ORC_PAR_KJ
                 for (int k = 0; k < g->n[2]; ++k)
                     for (int j = 0; j < g->n[1]; ++j)
                         for (int i = 0; i < g->n[0]; ++i) {
@@ -148,6 +149,7 @@ static void smooth_mac(level_t* l, int sweeps)
     const double ih2 = 1.0 / (g->h * g->h);
     for (int s = 0; s < sweeps; ++s)
         for (int colour = 0; colour < 2; ++colour)
+            ORC_PAR_KJ
             for (int k = 0; k < g->n[2]; ++k)
                 for (int j = 0; j < g->n[1]; ++j)
                     for (int i = 0; i < g->n[0]; ++i) {
@@ -175,6 +177,7 @@ static void smooth_nodal(level_t* l, int sweeps)
     const int ncol = 1 << g->dim;
     for (int s = 0; s < sweeps; ++s)
         for (int colour = 0; colour < ncol; ++colour)
+            ORC_PAR_KJ
             for (int k = 0; k < nnodes(g, 2); ++k)
                 for (int j = 0; j < nnodes(g, 1); ++j)
                     for (int i = 0; i < nnodes(g, 0); ++i) {
@@ -201,6 +204,7 @@ static void restrict_cells(const orc_grid* gf, const orc_grid* gc, int ncomp, co
     const long Nf = ncells(gf), Nc = ncells(gc);
     const int nch = 1 << gf->dim;
     for (int q = 0; q < ncomp; ++q)
+        ORC_PAR_KJ
         for (int k = 0; k < gc->n[2]; ++k)
             for (int j = 0; j < gc->n[1]; ++j)
                 for (int i = 0; i < gc->n[0]; ++i) {
@@ -225,6 +229,7 @@ static void prolong_cells(const orc_grid* gf, const orc_grid* gc, int ncomp, dou
     const int d = gf->dim;
     const int nco = 1 << d;
     for (int q = 0; q < ncomp; ++q)
+        ORC_PAR_KJ
         for (int k = 0; k < gf->n[2]; ++k)
             for (int j = 0; j < gf->n[1]; ++j)
                 for (int i = 0; i < gf->n[0]; ++i) {

@@ -130,3 +130,31 @@ def test_cessation_edge_cases():
     with pytest.raises(hb.HBError) as e:
         ctx2.run_cessation(u, p, max_steps=10, dt=0.01)
     assert e.value.code == hb.ERR_ARG
+
+
+def test_cessation_time_of_the_paper_case():
+    # Sec. IV, fig:rest-steady-cessation-2d: Re = 1, Bi = 10, Pa = 400; the
+    # lid is stopped at t = 0.0205552 and the flow comes to rest at
+    # t_c = 1.2844e-3 after that (256^2 in the paper).  Here 128^2, constant
+    # dt = 1e-5, backward Euler viscous update (the paper's own step size is
+    # not stated): within 5% of the printed value (256^2 with dt = 2.5e-6
+    # gives 1.2975e-3, and the dt -> 0 extrapolation 1.285e-3).
+    _say("cessation of the paper's Re=1, Bi=10 cavity at 128^2")
+    n, dt = 128, 1e-5
+    fl = hb.make_fluid(Re=1.0, HB=10.0, n=1.0, Pa=400.0)
+    opts = hb.make_step_opts(theta=1.0)
+    g = hb.lid_cavity(2, n)
+    ctx = hb.Context(g, fl, opts)
+    u = torch.zeros(hb.cell_shape(g, 2), dtype=torch.float64, device="cuda")
+    p = torch.zeros(hb.node_shape(g), dtype=torch.float64, device="cuda")
+    nsteps = int(round(0.0205552 / dt))
+    rep, rc = ctx.run_steady(u, p, tol=1e-300, max_steps=nsteps, dt=dt)
+    assert rep.steps == nsteps and abs(rep.t - nsteps * dt) < 1e-12
+    assert float(u.abs().max()) <= 1.0
+    ctx.close()
+    ctx = hb.Context(hb.make_grid(2, [n, n], 1.0 / n), fl, opts)
+    crep, crc = ctx.run_cessation(u, p, max_steps=1000, dt=dt)
+    ctx.close()
+    assert crc == hb.OK and crep.stopped
+    _say("  t_c = %.4e (paper 1.2844e-3)" % crep.t)
+    assert abs(crep.t - 1.2844e-3) < 0.05 * 1.2844e-3
