@@ -410,7 +410,7 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C =
                 launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n);
             L.cur ^= 1;
             s += n - 1;
-        } else if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0)) {
+        } else if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0 || c->fine3 == 1)) {
             // fused red-black sweep per component into the other buffer (2D,
             // and the small 3D levels, where it halves the launches)
             for (int q = 0; q < c->dim; ++q)
@@ -638,6 +638,8 @@ struct ConvLoop {
         prev = last;
         last = a.seq;
     }
+    // the max-norm of the next residual is finished by the next check
+    void defer() { c->defer_mf = true; }
     // a rule applied without publication
     void apply(int mode)
     {
@@ -668,6 +670,7 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o)
         L.cur = 0;
         double* xw = L.xb[0];
         seg_copy(c, sv, xw, x);
+        cl.defer();
         resid0(c, m, xw, b, L.r, c->act);
         cl.check(CV_INIT, 0);
         for (int k = 0; k < o.max_cycles; ++k) {
@@ -676,9 +679,11 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o)
                 seg_to_f32(c, sv, L.r, L.fb, L.fx[0]);
                 vcycle<float>(c, m, 0, o.nu1, o.nu2);
                 seg_add_f32(c, sv, xw, LB<float>::x(L));
+                cl.defer();
                 resid0(c, m, xw, b, L.r, c->act);
             } else {
                 vcycle<double>(c, m, 0, o.nu1, o.nu2);
+                cl.defer();
                 resid0(c, m, L.X(), b, L.r, c->act);
             }
             cl.check(CV_CYCLE, lo ? 0 : L.cur);
@@ -708,20 +713,18 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o)
         sub_scaled_max_dev(c, sv, s, r, S_ALPHA, v, S_MAX);
         cl.check(CV_HALF);
         // cavities that finish at the half step: x += alpha ph, r = s
-        const SegV sv2 = seg_of(m, c->act2);
-        bicg_x_dev(c, sv2, x, ph, nullptr, false);
-        seg_copy(c, sv2, r, s);
+        bicg_half_finish(c, seg_of(m, c->act2), x, ph, r, s);
         if (!cl.lagged_active()) break;
         precond(c, m, s, sh, o.nu1, o.nu2, lo);
         apply0(c, m, sh, t);
         seg_dot2_then(c, sv, t, t, S_DOT0, s, S_DOT1, 3, S_MAX);   // t.t, t.s, omega; S_MAX cleared for the max of r
-        bicg_x_dev(c, sv, x, ph, sh, true);
-        sub_scaled_max_dev(c, sv, r, s, S_OMEGA, t, S_MAX);
+        bicg_full_update(c, sv, x, ph, sh, r, s, t, S_MAX);       // x += alpha ph + omega sh, r = s - omega t
         cl.check(CV_FULL);
         if (!cl.lagged_active()) break;
     }
     // the true residual of every solved cavity
     cl.apply(CV_END_KRYLOV);
+    cl.defer();
     resid0(c, m, x, b, L.r, c->act);
     cl.apply(CV_FINAL);
 }
@@ -1251,6 +1254,9 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         // and per component in the 2D tensor smoother
         const char* f = std::getenv("HB_FUSE");
         c->fuse = !(f && f[0] == '0');
+        // HB_FINE3=k selects the finest 3D tensor smoother (experiment switch)
+        const char* f3 = std::getenv("HB_FINE3");
+        c->fine3 = f3 ? std::atoi(f3) : 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 8192) {
             c->lds_budget = (size_t)lim - 4096;
@@ -1300,6 +1306,8 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
 
 static void destroy_ctx(Ctx* c)
 {
+    if (const char* st = std::getenv("HB_STATS"))
+        if (st[0] == '1') fprintf(stderr, "[hb] host waits: %ld, %.3f s\n", c->waits, c->wait_s);
     if (!c) return;
     if (c->s) (void)hipStreamSynchronize(c->s);
     kt_free(c);

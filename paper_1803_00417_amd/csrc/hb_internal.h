@@ -57,6 +57,9 @@ struct ConvArgs {
     double tol;
     int max_cycles, fixed;
     unsigned long long seq;   // publication number of the active count (0: none)
+    // single-cavity contexts: the final pass of the max-norm just before the
+    // check (slot, or -1), done by the check kernel itself
+    int mf_slot, mf_act;
 };
 constexpr int kRing = 8;      // entries of the pinned ring of active counts
 
@@ -304,6 +307,13 @@ struct Ctx {
     unsigned long long* hring = nullptr;
     unsigned long long* dring = nullptr;
     unsigned long long cseq = 0;          // last check point number
+    // a max-norm final pass deferred to the next convergence check
+    // (single-cavity contexts): requested by defer_mf, held in mf_slot
+    bool defer_mf = false;
+    int mf_slot = -1;
+    const int* mf_act = nullptr;
+    double wait_s = 0.0;                  // host time spent waiting for the device (HB_STATS=1)
+    long waits = 0;
     double* partial = nullptr;   // reduction partials (2 x kRedBlocks per cavity)
     unsigned long long* mpart = nullptr;   // max-norm partials (kSubMax per cavity, kept zero between uses)
     int* act = nullptr;          // device active flags (nb)
@@ -325,6 +335,7 @@ struct Ctx {
     size_t lds_budget = 0;        // dynamic LDS bytes one workgroup may use
     bool tail = false;            // coarse levels in one single-workgroup launch
     bool fuse = true;             // fused-colour nodal sweeps
+    int fine3 = 0;                // finest 3D tensor smoother variant
     std::string err;
 };
 
@@ -382,7 +393,14 @@ void set_flags(Ctx* c, int* dev, const int* host);
 void fetch_slots(Ctx* c);  // all slots to c->hsc once the stream's work so far has completed
 // launch the convergence kernel of a check point; publish (a.seq != 0) the
 // number of cavities still active
-void launch_conv(Ctx* c, const ConvArgs& a);
+void launch_conv(Ctx* c, ConvArgs a);
+// launch a deferred max-norm final pass that no check consumed
+void flush_max_final(Ctx* c);
+// BiCGStab: x += alpha ph, r = s (cavities finishing at the half step); and
+// x += alpha ph + omega sh, r = s - omega t with max|r| into slot mslot
+void bicg_half_finish(Ctx* c, const SegV& s, double* x, const double* ph, double* r, const double* sv);
+void bicg_full_update(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, double* r,
+                      const double* sv, const double* t, int mslot);
 // wait until check point seq has published; returns its active count (-1
 // if it never did, even after a stream synchronisation)
 int wait_active(Ctx* c, unsigned long long seq);

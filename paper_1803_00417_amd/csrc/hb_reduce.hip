@@ -81,6 +81,7 @@ __global__ void k_publish(const double* __restrict__ sc, double* hsc, int n, uns
 
 void fetch_slots(Ctx* c)
 {
+    flush_max_final(c);
     const int n = S_NSLOT * c->nb;
     const unsigned long long want = ++c->pub;
     k_publish<<<1, kT, 0, c->s>>>(c->sc, c->dhsc, n, c->dhseq, want);
@@ -88,7 +89,11 @@ void fetch_slots(Ctx* c)
     // work); if the word is still not visible, copy the slots the slow way
     const auto t0 = std::chrono::steady_clock::now();
     for (unsigned it = 1;; ++it) {
-        if (__atomic_load_n(c->hseq, __ATOMIC_ACQUIRE) == want) return;
+        if (__atomic_load_n(c->hseq, __ATOMIC_ACQUIRE) == want) {
+            c->wait_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            ++c->waits;
+            return;
+        }
         __builtin_ia32_pause();
         if ((it & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
     }
@@ -129,9 +134,23 @@ __device__ inline bool conv_take_rel(double* S, double* R)
 // by one system-scope release store into the pinned ring.
 __global__ void __launch_bounds__(1024) k_conv(ConvArgs a, double* __restrict__ sc, int* __restrict__ act,
                                                int* __restrict__ act2, int* __restrict__ sel,
-                                               unsigned long long* ring)
+                                               unsigned long long* ring, unsigned long long* __restrict__ mp)
 {
     __shared__ double sh[1024 / 64];
+    __shared__ unsigned long long shm[1024 / 64];
+    if (a.mf_slot >= 0) {
+        // the max-norm's final pass (one cavity): the largest partial word,
+        // the words cleared, the slot written when the cavity is active
+        unsigned long long m = 0ull;
+        for (int i = threadIdx.x; i < kSubMax; i += blockDim.x) {
+            const unsigned long long v = mp[i];
+            m = v > m ? v : m;
+            mp[i] = 0ull;
+        }
+        m = block_umax(m, shm);
+        if (threadIdx.x == 0 && (!a.mf_act || act[0])) sc[a.mf_slot] = __longlong_as_double((long long)m);
+        __syncthreads();
+    }
     double nact = 0.0;
     for (int i = threadIdx.x; i < a.nb; i += blockDim.x) {
         double* S = sc + (long)i * S_NSLOT;
@@ -208,10 +227,24 @@ __global__ void __launch_bounds__(1024) k_conv(ConvArgs a, double* __restrict__ 
     }
 }
 
-void launch_conv(Ctx* c, const ConvArgs& a)
+void launch_conv(Ctx* c, ConvArgs a)
 {
-    const int nt = c->nb >= 1024 ? 1024 : ((c->nb + 63) / 64) * 64;
-    k_conv<<<1, nt, 0, c->s>>>(a, c->sc, c->act, c->act2, c->sel, c->dring);
+    a.mf_slot = -1;
+    a.mf_act = 0;
+    if (c->mf_slot >= 0) {
+        // only the check's own act flags are read by the fused final pass
+        if (c->mf_act && c->mf_act != c->act) {
+            flush_max_final(c);
+        } else {
+            a.mf_slot = c->mf_slot;
+            a.mf_act = c->mf_act != nullptr;
+            c->mf_slot = -1;
+        }
+    }
+    c->defer_mf = false;
+    int nt = c->nb >= 1024 ? 1024 : ((c->nb + 63) / 64) * 64;
+    if (a.mf_slot >= 0) nt = 256;
+    k_conv<<<1, nt, 0, c->s>>>(a, c->sc, c->act, c->act2, c->sel, c->dring, c->mpart);
 }
 
 int wait_active(Ctx* c, unsigned long long seq)
@@ -221,7 +254,11 @@ int wait_active(Ctx* c, unsigned long long seq)
     const auto t0 = std::chrono::steady_clock::now();
     for (unsigned it = 1;; ++it) {
         const unsigned long long w = __atomic_load_n(const_cast<unsigned long long*>(e), __ATOMIC_ACQUIRE);
-        if ((w & 0xffffffffull) == lo) return (int)(w >> 32);
+        if ((w & 0xffffffffull) == lo) {
+            c->wait_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            ++c->waits;
+            return (int)(w >> 32);
+        }
         __builtin_ia32_pause();
         if ((it & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
     }
@@ -291,7 +328,23 @@ __global__ void k_max_final(const int* __restrict__ act, unsigned long long* __r
 
 void launch_max_final(Ctx* c, const int* act, int slot)
 {
+    flush_max_final(c);
+    if (c->defer_mf && c->nb == 1) {
+        // the next convergence check does this pass (one launch fewer)
+        c->defer_mf = false;
+        c->mf_slot = slot;
+        c->mf_act = act;
+        return;
+    }
     k_max_final<<<c->nb, kT, 0, c->s>>>(act, c->mpart, c->sc, slot);
+}
+
+void flush_max_final(Ctx* c)
+{
+    if (c->mf_slot < 0) return;
+    const int slot = c->mf_slot;
+    c->mf_slot = -1;
+    k_max_final<<<c->nb, kT, 0, c->s>>>(c->mf_act, c->mpart, c->sc, slot);
 }
 
 // ---- segmented over the batch -------------------------------------------------
@@ -617,6 +670,55 @@ __global__ void k_bicg_x_dev(SegV sv, double* __restrict__ x, const double* __re
 void bicg_x_dev(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, bool with_omega)
 {
     k_bicg_x_dev<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, x, ph, sh, c->sc, with_omega ? 1 : 0);
+}
+
+// x = alpha ph + x and r = s (the cavities that finish at the half step)
+__global__ void k_bicg_half_finish(SegV sv, double* __restrict__ x, const double* __restrict__ ph,
+                                   double* __restrict__ r, const double* __restrict__ s, const double* __restrict__ scb)
+{
+    SEG_ENTER(sv, off, n);
+    const double alpha = scb[(long)cav_ * S_NSLOT + S_ALPHA];
+    SEG_LOOP(i, n)
+    {
+        x[off + i] = alpha * ph[off + i] + 1.0 * x[off + i];
+        r[off + i] = s[off + i];
+    }
+}
+
+void bicg_half_finish(Ctx* c, const SegV& s, double* x, const double* ph, double* r, const double* sv)
+{
+    k_bicg_half_finish<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, x, ph, r, sv, c->sc);
+}
+
+// x += alpha ph + omega sh; r = s - omega t with max|r| (atomic, into a
+// slot the dot product's final pass cleared)
+__global__ void k_bicg_full_update(SegV sv, double* __restrict__ x, const double* __restrict__ ph,
+                                   const double* __restrict__ shv, double* __restrict__ r,
+                                   const double* __restrict__ s, const double* __restrict__ t,
+                                   double* __restrict__ scb, int mslot)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    SEG_ENTER(sv, off, n);
+    const double* sc = scb + (long)cav_ * S_NSLOT;
+    const double alpha = sc[S_ALPHA], omega = sc[S_OMEGA];
+    unsigned long long m = 0ull;
+    SEG_LOOP(i, n)
+    {
+        x[off + i] += alpha * ph[off + i] + omega * shv[off + i];
+        const double v = s[off + i] - omega * t[off + i];
+        r[off + i] = v;
+        const unsigned long long bb = abits(v);
+        m = bb > m ? bb : m;
+    }
+    m = block_umax(m, sh);
+    if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav_ * S_NSLOT + mslot, m);
+}
+
+void bicg_full_update(Ctx* c, const SegV& s, double* x, const double* ph, const double* shv, double* r,
+                      const double* sv, const double* t, int mslot)
+{
+    k_bicg_full_update<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, x, ph, shv, r, sv, t, c->sc,
+                                                                                mslot);
 }
 
 }  // namespace hb
