@@ -378,11 +378,14 @@ int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e);
  * components, or two where the level's autotuned candidate runs two sweeps
  * per launch; 3D: one colour of one component); hb_kernel_timing_read
  * synchronises, and returns the number of timed launches, their summed
- * device time and their summed algorithmic bytes (2D: both x components, eta/Re
- * and both b components read once, x written once, per launch whatever its
- * sweep count, plus both components of the coarse iterate where the launch
- * adds the prolongation of a V-cycle's coarse correction; 3D: every x component and eta/Re read once, the colour's b
- * read and x written; words of the storage type).  Enabling resets the
+ * device time and their summed algorithmic bytes, counted per red-black
+ * sweep of all components (every x component, eta/Re and every b component
+ * read once, every x component written once: 7 words per cell in 2D, 10 in
+ * 3D) times the part of a sweep the launch runs (2D: one or two sweeps; 3D:
+ * one colour of one component, a sixth), plus in 2D both components of the
+ * coarse iterate where the launch adds the prolongation of a V-cycle's
+ * coarse correction, and of the coarse right-hand side and iterate where it
+ * ends with the restriction; words of the storage type).  Enabling resets the
  * counters. */
 int hb_kernel_timing(hb_ctx* ctx, int enable);
 int hb_kernel_timing_read(hb_ctx* ctx, int64_t* launches, double* total_ms, double* alg_bytes);

@@ -1425,13 +1425,13 @@ void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fin
                     const R* b)
 {
     const bool timed = fine && kt_take(c);
-    // algorithmic bytes of one fused red-black sweep of one component: every
-    // component of x and the coefficients (eta/Re per cell on the finest
-    // level, face viscosities below) read once, b_c read once, x_c written
-    // once
+    // algorithmic bytes counted per red-black sweep of all components (every
+    // component of x, the coefficients and every component of b read once,
+    // x written once); a launch sweeps one component, 1/dim of a sweep
     const double N = level_cells(L);
     const double coefw = fine ? N : level_faces(L);
-    const double bytes = sizeof(R) * (L.gmax.dim * N + coefw + 2.0 * N);
+    const double dim = L.gmax.dim;
+    const double bytes = sizeof(R) * (3.0 * dim * N + coefw) / dim;
     if (L.gmax.dim == 2) {
         if (fine) tsmooth_impl<2, true, R>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
         else tsmooth_impl<2, false, R>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
@@ -1514,13 +1514,16 @@ static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, con
     const bool timed = FINE && kt_take(c);
     BV vv = v;
     const dim3 grid = tile_grid<2, CF>(c, L, vv);
-    // algorithmic bytes of a launch (one sweep or several in LDS): both
-    // components of x, eta/Re and both components of b read once, x written
-    // once; with a folded prolongation also both components of the coarse
-    // iterate (N/4 cells each)
+    // algorithmic bytes of a launch, counted per red-black sweep of both
+    // components (both components of x, eta/Re and both components of b
+    // read once, x written once: 7 words per cell) times the sweeps the
+    // launch runs; with a folded prolongation also both components of the
+    // coarse iterate read, with a folded restriction both components of the
+    // coarse right-hand side and iterate written (N/4 cells each)
     const double N = level_cells(L);
+    const int sweeps = (CAND::STAGED && CAND::NSW >= 2 && nsw == 2) ? 2 : 1;
     const double bytes =
-        sizeof(R) * (2.0 * N + N + 2.0 * N + 2.0 * N + (pe ? 2.0 * N / 4.0 : 0.0) + (bc ? 4.0 * N / 4.0 : 0.0));
+        sizeof(R) * (7.0 * N * sweeps + (pe ? 2.0 * N / 4.0 : 0.0) + (bc ? 4.0 * N / 4.0 : 0.0));
     if constexpr (!CAND::STAGED) {
         using T = Tile<2, 4, CF>;
         const size_t lds = sizeof(R) * (FINE ? 3 : 2) * T::NS;
@@ -1635,10 +1638,12 @@ void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, 
     const size_t lds = sizeof(R) * (3 + (fine ? 1 : 0)) * T::NS;
     BV vv = v;
     const dim3 grid = tile_grid<3>(c, L, vv);
-    // algorithmic bytes of one half sweep: every component of x and the
-    // coefficients read once, the active colour of b read and of x written
+    // algorithmic bytes counted per red-black sweep of all three components
+    // (every component of x, eta/Re and every component of b read once, x
+    // written once: 10 words per cell); a launch runs one colour of one
+    // component, a sixth of a sweep
     const double N = level_cells(L);
-    const double bytes = sizeof(R) * (3.0 * N + N + N);
+    const double bytes = sizeof(R) * 10.0 * N / 6.0;
     if (fine) tlaunch(c, timed, bytes, k_trb3<true, R>, grid, dim3(256), lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
     else tlaunch(c, timed, bytes, k_trb3<false, R>, grid, dim3(256), lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
 }
