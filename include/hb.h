@@ -24,9 +24,16 @@
  *                                  array of axis a has n_a + 1 (wall) or n_a
  *                                  (periodic) faces along a and n_b cells
  *                                  along the other axes.
- * The library owns only the scratch it allocates in hb_create (multigrid
- * hierarchies, face arrays, reduction buffers); it never allocates afterwards
- * and never frees caller memory.
+ * The library owns only the scratch it allocates: in hb_create (multigrid
+ * hierarchies, face arrays, reduction buffers: everything hb_step and the
+ * per-stage calls use) and, on their first use on a context, in the calls
+ * that need more: hb_run_steady and hb_run_cessation (one velocity-sized
+ * buffer), hb_set_warm_start (the network's input, output and node fields),
+ * hb_capture (three fields of the captured solve); a network allocates its
+ * activations in hb_nn_forward/grad/train_step for each new (n, H, W).  Such
+ * an allocation is all or nothing (a failure frees what it had allocated
+ * and returns HB_ERR_OOM).  The library never frees caller memory.
+ * hb_cfl_dt_noalloc allocates nothing at all.
  *
  * Streams.  Work runs asynchronously on the hipStream_t given to hb_create
  * (NULL = the default stream).  Multigrid convergence is decided on the
@@ -59,7 +66,7 @@ enum {
     HB_ERR_DEVICE = -2,     /* a HIP call failed */
     HB_ERR_NOCONV = -3,     /* a solve hit max_cycles; outputs hold the last iterate */
     HB_ERR_NONFINITE = -4,  /* NaN/Inf in an input or produced by a solve */
-    HB_ERR_OOM = -5,        /* device allocation failed in hb_create */
+    HB_ERR_OOM = -5,        /* a device allocation failed (hb_create, or a call's first use) */
     HB_ERR_IO = -6          /* a checkpoint file could not be opened, read or written */
 };
 
@@ -364,9 +371,12 @@ int hb_set_warm_start(hb_ctx* ctx, int op, hb_nn* nn);
 /* number of solves so far that started from the network's guess */
 int hb_warm_start_uses(const hb_ctx* ctx);
 
-/* Training data: while enabled, each nodal solve of cavity 0 records its
- * initial residual r0 = b - K x0 and its correction e = x - x0 (FP64, node
- * layout); hb_capture_read copies the last pair to caller device arrays. */
+/* Training and analysis data: while enabled for op (HB_OP_NODAL or
+ * HB_OP_VISC), each solve of that operator on a single-cavity context
+ * records its initial residual r0 = b - A x0 and its correction e = x - x0
+ * (FP64; node layout, or [dim][cells] for the viscous solve, whose b holds
+ * the wall terms); hb_capture_read copies the last pair to caller device
+ * arrays. */
 int hb_capture(hb_ctx* ctx, int op, int enable);
 int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e);
 

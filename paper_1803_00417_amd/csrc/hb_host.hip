@@ -79,6 +79,22 @@ static hipError_t dalloc(T** p, long n)
     return hipMalloc((void**)p, sizeof(T) * (size_t)(n > 0 ? n : 1));
 }
 
+// allocate n device buffers, all or none (on failure every one is freed
+// and nulled)
+static bool alloc_all(void** b, const size_t* sz, int n)
+{
+    for (int i = 0; i < n; ++i) {
+        if (hipMalloc(&b[i], sz[i]) != hipSuccess) {
+            for (int k = 0; k < n; ++k) {
+                if (b[k]) (void)hipFree(b[k]);
+                b[k] = nullptr;
+            }
+            return false;
+        }
+    }
+    return true;
+}
+
 template <typename T>
 static hipError_t upload(T* dst, const std::vector<T>& src)
 {
@@ -776,6 +792,12 @@ static void solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o)
     const SegV all = seg_of(m, nullptr);
     if (m.op != HB_OP_VISC) seg_sub_mean(c, all, m.lvl0_b);
     if (m.op == HB_OP_NODAL && (c->ws || c->cap)) nodal_prestart(c, m, x);
+    if (m.op == HB_OP_VISC && c->capv) {
+        // training data / analysis: initial residual and guess of the solve
+        resid0(c, m, x, m.lvl0_b, m.L[0].r, nullptr);
+        copy(c, c->capv_r0, m.L[0].r, m.L[0].nu);
+        copy(c, c->capv_x0, x, m.L[0].nu);
+    }
     seg_maxabs(c, all, m.lvl0_b, S_MAX);
     seg_maxabs(c, all, x, S_MAX2);
     if (o.precision == HB_PREC_MIXED) ensure_f32(c, m);
@@ -785,6 +807,7 @@ static void solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o)
     solve_core(c, m, x, m.lvl0_b, o);
     if (m.op != HB_OP_VISC) seg_sub_mean(c, all, x);
     if (m.op == HB_OP_NODAL && c->cap) launch_axpy(c, c->cap_e, x, c->cap_x0, -1.0, m.L[0].nu);
+    if (m.op == HB_OP_VISC && c->capv) launch_axpy(c, c->capv_e, x, c->capv_x0, -1.0, m.L[0].nu);
 }
 
 // The outcome of the last solve of m per cavity, from the slots a
@@ -1334,6 +1357,9 @@ static void destroy_ctx(Ctx* c)
     (void)hipFree(c->cap_r0);
     (void)hipFree(c->cap_e);
     (void)hipFree(c->cap_x0);
+    (void)hipFree(c->capv_r0);
+    (void)hipFree(c->capv_e);
+    (void)hipFree(c->capv_x0);
     if (c->hsc) (void)hipHostFree(c->hsc);
     if (c->hseq) (void)hipHostFree(c->hseq);
     if (c->hring) (void)hipHostFree(c->hring);
@@ -1536,11 +1562,16 @@ int hb_set_warm_start(hb_ctx* ctx, int op, hb_nn* nn)
     NNet* t = nn_of(nn);
     if (nn_channels_in(t) != 1 || nn_channels_out(t) != 1) return fail(c, HB_ERR_ARG, "the warm-start network maps 1 channel to 1");
     if (!c->ws_in) {
+        // all five buffers or none: a failed allocation frees the others
         const long nc = c->cv[0].nc, nn_ = c->nodal.L[0].nu;
-        if (hipMalloc((void**)&c->ws_in, 4 * nc) != hipSuccess || hipMalloc((void**)&c->ws_out, 4 * nc) != hipSuccess ||
-            hipMalloc((void**)&c->ws_y, 8 * nn_) != hipSuccess || hipMalloc((void**)&c->ws_z, 8 * nn_) != hipSuccess ||
-            hipMalloc((void**)&c->ws_x1, 8 * nn_) != hipSuccess)
-            return fail(c, HB_ERR_OOM, "device allocation failed");
+        void* b[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        const size_t sz[5] = {(size_t)4 * nc, (size_t)4 * nc, (size_t)8 * nn_, (size_t)8 * nn_, (size_t)8 * nn_};
+        if (!alloc_all(b, sz, 5)) return fail(c, HB_ERR_OOM, "device allocation failed");
+        c->ws_in = (float*)b[0];
+        c->ws_out = (float*)b[1];
+        c->ws_y = (double*)b[2];
+        c->ws_z = (double*)b[3];
+        c->ws_x1 = (double*)b[4];
     }
     c->ws = t;
     return HB_OK;
@@ -1550,17 +1581,27 @@ int hb_capture(hb_ctx* ctx, int op, int enable)
 {
     if (!ctx) return HB_ERR_ARG;
     Ctx* c = C_(ctx);
-    if (op != HB_OP_NODAL) return fail(c, HB_ERR_ARG, "capture serves the nodal projection solve only");
+    if (op != HB_OP_NODAL && op != HB_OP_VISC) return fail(c, HB_ERR_ARG, "capture serves the nodal and viscous solves");
     if (single_only(c)) return HB_ERR_ARG;
-    if (enable && !c->cap_r0) {
-        const long n = c->nodal.L[0].nu;
-        if (hipMalloc((void**)&c->cap_r0, 8 * n) != hipSuccess || hipMalloc((void**)&c->cap_e, 8 * n) != hipSuccess ||
-            hipMalloc((void**)&c->cap_x0, 8 * n) != hipSuccess)
-            return fail(c, HB_ERR_OOM, "device allocation failed");
-        (void)hipMemset(c->cap_r0, 0, 8 * n);
-        (void)hipMemset(c->cap_e, 0, 8 * n);
+    const bool visc = op == HB_OP_VISC;
+    double** r0 = visc ? &c->capv_r0 : &c->cap_r0;
+    double** e = visc ? &c->capv_e : &c->cap_e;
+    double** x0 = visc ? &c->capv_x0 : &c->cap_x0;
+    if (enable && !*r0) {
+        // all three buffers or none
+        const long n = (visc ? c->visc : c->nodal).L[0].nu;
+        void* b[3] = {nullptr, nullptr, nullptr};
+        const size_t sz[3] = {(size_t)8 * n, (size_t)8 * n, (size_t)8 * n};
+        if (!alloc_all(b, sz, 3)) return fail(c, HB_ERR_OOM, "device allocation failed");
+        *r0 = (double*)b[0];
+        *e = (double*)b[1];
+        *x0 = (double*)b[2];
+        StreamGuard guard(c);
+        fill(c, *r0, 0.0, n);
+        fill(c, *e, 0.0, n);
+        if (hipStreamSynchronize(c->s) != hipSuccess) return fail(c, HB_ERR_DEVICE, "stream synchronisation failed");
     }
-    c->cap = enable != 0;
+    (visc ? c->capv : c->cap) = enable != 0;
     return HB_OK;
 }
 
@@ -1568,10 +1609,14 @@ int hb_capture_read(hb_ctx* ctx, int op, double* r0, double* e)
 {
     if (!ctx) return HB_ERR_ARG;
     Ctx* c = C_(ctx);
-    if (op != HB_OP_NODAL || !r0 || !e || !c->cap_r0) return fail(c, HB_ERR_ARG, "nothing captured");
+    const bool visc = op == HB_OP_VISC;
+    const double* cr = visc ? c->capv_r0 : c->cap_r0;
+    const double* ce = visc ? c->capv_e : c->cap_e;
+    if ((op != HB_OP_NODAL && !visc) || !r0 || !e || !cr) return fail(c, HB_ERR_ARG, "nothing captured");
     StreamGuard guard(c);
-    copy(c, r0, c->cap_r0, c->nodal.L[0].nu);
-    copy(c, e, c->cap_e, c->nodal.L[0].nu);
+    const long n = (visc ? c->visc : c->nodal).L[0].nu;
+    copy(c, r0, cr, n);
+    copy(c, e, ce, n);
     return hipStreamSynchronize(c->s) == hipSuccess ? HB_OK : fail(c, HB_ERR_DEVICE, "stream synchronisation failed");
 }
 

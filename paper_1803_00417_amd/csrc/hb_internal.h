@@ -331,6 +331,9 @@ struct Ctx {
     double *ws_y = nullptr, *ws_z = nullptr, *ws_x1 = nullptr;   // node fields
     bool cap = false;
     double *cap_r0 = nullptr, *cap_e = nullptr, *cap_x0 = nullptr;
+    // the same for the viscous solve ([dim][cells] layout)
+    bool capv = false;
+    double *capv_r0 = nullptr, *capv_e = nullptr, *capv_x0 = nullptr;
     long ws_report_used = 0;      // solves that started from the network's guess
     size_t lds_budget = 0;        // dynamic LDS bytes one workgroup may use
     bool tail = false;            // coarse levels in one single-workgroup launch

@@ -363,11 +363,12 @@ class Context:
         rc = load().hb_tile_config(self._h, op, level, C.byref(tx), C.byref(ty), C.byref(th), C.byref(sw))
         return (tx.value, ty.value, th.value, sw.value) if rc == OK else None
 
-    def capture(self, enable):
-        self._check(load().hb_capture(self._h, OP_NODAL, int(enable)))
+    def capture(self, enable, op=OP_NODAL):
+        self._check(load().hb_capture(self._h, op, int(enable)))
 
-    def capture_read(self, r0, e):
-        self._check(load().hb_capture_read(self._h, OP_NODAL, _ptr(r0, self.nnode, "r0"), _ptr(e, self.nnode, "e")))
+    def capture_read(self, r0, e, op=OP_NODAL):
+        n = self.nvel if op == OP_VISC else self.nnode
+        self._check(load().hb_capture_read(self._h, op, _ptr(r0, n, "r0"), _ptr(e, n, "e")))
 
     def step(self, u, p, dt=0.0, report=True, allow=()):
         rep = StepReport() if report else None
