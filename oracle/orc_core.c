@@ -33,6 +33,7 @@ int orc_viscosity(const orc_grid* g, const orc_fluid* fl, const double* u, doubl
     const int d = g->dim;
     const long N = ncells(g);
     const double h = g->h;
+    ORC_PAR_KJ
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
             for (int i = 0; i < g->n[0]; ++i) {
@@ -70,6 +71,7 @@ void orc_eta_faces(const orc_grid* g, const double* eta_e, double* beta)
     for (int a = 0; a < g->dim; ++a) {
         int ext[3] = {g->n[0], g->n[1], g->n[2]};
         ext[a] = nfaces(g, a);
+        ORC_PAR_KJ
         for (int k = 0; k < ext[2]; ++k)
             for (int j = 0; j < ext[1]; ++j)
                 for (int i = 0; i < ext[0]; ++i) {
@@ -214,12 +216,44 @@ static long corner_node(const orc_grid* g, int i, int j, int k, int bits)
     return nid(g, p[0], p[1], p[2]);
 }
 
+
+#ifdef _OPENMP
+/* Timing build: the cells touching node (i,j,k) and the node's corner index
+ * in each, in the order of the cells' linear index (the order in which the
+ * serial loops over cells add their contributions to the node, so a gather
+ * in this order forms the same sums).  Returns the count. */
+static int node_cells(const orc_grid* g, int i, int j, int k, long* cell, int* corner)
+{
+    const int d = g->dim;
+    const int node[3] = {i, j, k};
+    int cnt = 0;
+    for (int m = 0; m < (1 << d); ++m) {
+        int c[3] = {0, 0, 0};
+        int ok = 1;
+        for (int a = 0; a < d; ++a) {
+            int v = node[a] - ((m >> a) & 1);   /* the node is corner bit (m>>a)&1 of cell v */
+            if (v < 0) { if (is_periodic(g, a)) v += g->n[a]; else ok = 0; }
+            if (v >= g->n[a]) ok = 0;
+            c[a] = v;
+        }
+        if (!ok) continue;
+        long id = cid(g, c[0], c[1], c[2]);
+        int t = cnt++;
+        while (t > 0 && cell[t - 1] > id) { cell[t] = cell[t - 1]; corner[t] = corner[t - 1]; --t; }
+        cell[t] = id;
+        corner[t] = m;
+    }
+    return cnt;
+}
+#endif
+
 /* (G phi)_a = mean over the cell's 2^(d-1) edges along a of (phi_hi - phi_lo)/h */
 void orc_grad_node(const orc_grid* g, const double* phi, double* out)
 {
     const int d = g->dim;
     const long N = ncells(g);
     const int nc = 1 << d;
+    ORC_PAR_KJ
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
             for (int i = 0; i < g->n[0]; ++i)
@@ -241,6 +275,28 @@ void orc_weak_div(const orc_grid* g, const double* V, double* r)
     const long N = ncells(g);
     const int nc = 1 << d;
     const double w = pow(0.5 * g->h, d - 1);
+#ifdef _OPENMP
+    ORC_PAR_KJ
+    for (int k = 0; k < nnodes(g, 2); ++k)
+        for (int j = 0; j < nnodes(g, 1); ++j)
+            for (int i = 0; i < nnodes(g, 0); ++i) {
+                long cell[8];
+                int corner[8];
+                const int cnt = node_cells(g, i, j, k, cell, corner);
+                double acc = 0.0;
+                for (int t = 0; t < cnt; ++t) {
+                    double s = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        double sg = ((corner[t] >> a) & 1) ? 1.0 : -1.0;
+                        s += sg * w * V[(long)a * N + cell[t]];
+                    }
+                    acc += s;
+                }
+                r[nid(g, i, j, k)] = acc;
+            }
+    (void)nc;
+    return;
+#endif
     memset(r, 0, sizeof(double) * orc_node_count(g));
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
@@ -282,6 +338,29 @@ void orc_apply_K(const orc_grid* g, const double* phi, double* out)
     const int nc = 1 << d;
     double Ke[8][8];
     q1_element(d, g->h, Ke);
+#ifdef _OPENMP
+    ORC_PAR_KJ
+    for (int k = 0; k < nnodes(g, 2); ++k)
+        for (int j = 0; j < nnodes(g, 1); ++j)
+            for (int i = 0; i < nnodes(g, 0); ++i) {
+                long cell[8];
+                int corner[8];
+                const int cnt = node_cells(g, i, j, k, cell, corner);
+                double acc = 0.0;
+                for (int t = 0; t < cnt; ++t) {
+                    const long c = cell[t];
+                    const int ci = (int)(c % g->n[0]), cj = (int)((c / g->n[0]) % g->n[1]),
+                              ck = (int)(c / ((long)g->n[0] * g->n[1]));
+                    long ids[8];
+                    for (int b = 0; b < nc; ++b) ids[b] = corner_node(g, ci, cj, ck, b);
+                    double s = 0.0;
+                    for (int q = 0; q < nc; ++q) s += Ke[corner[t]][q] * phi[ids[q]];
+                    acc += s;
+                }
+                out[nid(g, i, j, k)] = acc;
+            }
+    return;
+#endif
     memset(out, 0, sizeof(double) * orc_node_count(g));
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
@@ -340,6 +419,7 @@ static long face_offset(const orc_grid* g, int a)
 /* D_mac: sum over axes of (F(hi face) - F(lo face)) / h */
 void orc_mac_div(const orc_grid* g, const double* faces, double* out)
 {
+    ORC_PAR_KJ
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
             for (int i = 0; i < g->n[0]; ++i) {
@@ -362,6 +442,7 @@ void orc_mac_grad(const orc_grid* g, const double* phi, double* faces)
         double* F = faces + face_offset(g, a);
         int ext[3] = {g->n[0], g->n[1], g->n[2]};
         ext[a] = nfaces(g, a);
+        ORC_PAR_KJ
         for (int k = 0; k < ext[2]; ++k)
             for (int j = 0; j < ext[1]; ++j)
                 for (int i = 0; i < ext[0]; ++i) {

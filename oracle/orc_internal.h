@@ -106,10 +106,13 @@ static inline void* xcalloc(long n, long sz)
  * nest, or of one colour of a smoother, split over threads.  The parity
  * build has no OpenMP and runs every loop in order. */
 #ifdef _OPENMP
-#define ORC_PAR_KJ _Pragma("omp parallel for collapse(2) schedule(static)")
+#define ORC_PAR_KJ _Pragma("omp parallel for collapse(2) schedule(static) if (orc_par_ok(g))")
 #else
 #define ORC_PAR_KJ
 #endif
+
+/* a loop nest over a grid is worth splitting only on the larger levels */
+static inline int orc_par_ok(const orc_grid* g) { return (long)g->n[0] * g->n[1] * g->n[2] >= 4096; }
 
 static inline double vmax_abs(const double* v, long n)
 {

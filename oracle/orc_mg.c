@@ -203,6 +203,8 @@ static void restrict_cells(const orc_grid* gf, const orc_grid* gc, int ncomp, co
 {
     const long Nf = ncells(gf), Nc = ncells(gc);
     const int nch = 1 << gf->dim;
+    const orc_grid* g = gc;   /* the grid the loop nest runs over */
+    (void)g;
     for (int q = 0; q < ncomp; ++q)
         ORC_PAR_KJ
         for (int k = 0; k < gc->n[2]; ++k)
@@ -228,6 +230,8 @@ static void prolong_cells(const orc_grid* gf, const orc_grid* gc, int ncomp, dou
     const long Nf = ncells(gf), Nc = ncells(gc);
     const int d = gf->dim;
     const int nco = 1 << d;
+    const orc_grid* g = gf;   /* the grid the loop nest runs over */
+    (void)g;
     for (int q = 0; q < ncomp; ++q)
         ORC_PAR_KJ
         for (int k = 0; k < gf->n[2]; ++k)

@@ -100,6 +100,7 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
     double* S = (double*)xcalloc(N * d * d, sizeof(double));
     for (int a = 0; a < d; ++a)
         for (int q = 0; q < d; ++q)
+            ORC_PAR_KJ
             for (int k = 0; k < g->n[2]; ++k)
                 for (int j = 0; j < g->n[1]; ++j)
                     for (int i = 0; i < g->n[0]; ++i) {
@@ -121,6 +122,7 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
         int ext[3] = {g->n[0], g->n[1], g->n[2]};
         ext[a] = nfaces(g, a);
         const long off = face_off(g, a);
+        ORC_PAR_KJ
         for (int k = 0; k < ext[2]; ++k)
             for (int j = 0; j < ext[1]; ++j)
                 for (int i = 0; i < ext[0]; ++i) {
@@ -152,6 +154,7 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
     for (int bb = 0; bb < d; ++bb) {
         const long off = face_off(g, bb);
         for (int q = 0; q < d; ++q)
+            ORC_PAR_KJ
             for (int k = 0; k < g->n[2]; ++k)
                 for (int j = 0; j < g->n[1]; ++j)
                     for (int i = 0; i < g->n[0]; ++i) {
@@ -175,6 +178,7 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
         int ext[3] = {g->n[0], g->n[1], g->n[2]};
         ext[a] = nfaces(g, a);
         const long off = face_off(g, a);
+        ORC_PAR_KJ
         for (int k = 0; k < ext[2]; ++k)
             for (int j = 0; j < ext[1]; ++j)
                 for (int i = 0; i < ext[0]; ++i) {
@@ -238,6 +242,7 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
     for (int a = 0; a < d; ++a) {
         const long off = face_off(g, a);
         for (int q = 0; q < d; ++q)
+            ORC_PAR_KJ
             for (int k = 0; k < g->n[2]; ++k)
                 for (int j = 0; j < g->n[1]; ++j)
                     for (int i = 0; i < g->n[0]; ++i) {

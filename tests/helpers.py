@@ -42,3 +42,47 @@ def rel_err(a, b):
     d = np.abs(np.asarray(a) - np.asarray(b)).max()
     s = np.abs(np.asarray(b)).max()
     return d / s if s > 0 else d
+
+
+_ORACLE_STEPS = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import orc
+from paper_1803_00417_amd import inputs
+name, nsteps, out = sys.argv[2], int(sys.argv[3]), sys.argv[4]
+w = inputs.WORKLOADS[name]
+g = orc.lid_cavity(w["dim"], w["n"])
+fl = orc.make_fluid(Re=w["Re"], HB=w["HB"], n=w["nidx"], Pa=w["Pa"])
+o = orc.make_step_opts(cfl=w["cfl"])
+u = np.zeros(orc.cell_shape(g, w["dim"]))
+p = np.zeros(orc.node_shape(g))
+dts = []
+for _ in range(nsteps):
+    rep, rc = orc.step(g, fl, o, u, p)
+    assert rc == orc.OK, rc
+    dts.append(rep.dt)
+np.savez(out, u=u, p=p, dt=np.array(dts))
+"""
+
+
+def oracle_workload_steps(name, nsteps, tmpdir, threads=16):
+    """the oracle's state after nsteps steps of a workload from rest, run in
+    a child process by the OpenMP build of the oracle (the same loops,
+    split over threads; no reductions are split, so the values are those of
+    the single-threaded build)"""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    env = dict(os.environ)
+    env["OMP_NUM_THREADS"] = str(max(1, min(threads, avail)))
+    env["ORC_OMP"] = "1"
+    out = os.path.join(str(tmpdir), "oracle_%s_%d.npz" % (name, nsteps))
+    subprocess.run([sys.executable, "-c", _ORACLE_STEPS, root, name, str(nsteps), out], env=env, check=True)
+    d = np.load(out)
+    return d["u"], d["p"], d["dt"]

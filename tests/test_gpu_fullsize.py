@@ -1,10 +1,12 @@
 """GPU parity at the benchmark's full sizes, in the launch configuration the
 benchmark times (default options, tiles chosen by the autotuner): the 2D
 512^2 cavity step against the oracle's whole steps; at 3D 128^3, where an
-oracle step takes minutes, the pieces the oracle computes in seconds (the
-viscosity, one V-cycle of each solve) and properties every step must have
-at any size (solve residuals, the MAC divergence, the CFL step, the mirror
-symmetry of the cavity); the 64-cavity batch, sampled cavity by cavity.
+oracle step takes minutes on one core, a whole step against the oracle's
+OpenMP build, the pieces the single-threaded oracle computes in seconds
+(the viscosity, one V-cycle of each solve) and properties every step must
+have at any size (solve residuals, the MAC divergence, the CFL step, the
+mirror symmetry of the cavity); ten 2D steps; the 64-cavity batch, sampled
+cavity by cavity.
 
 Bars as in the smaller parity tests: 1e-13 for the viscosity, 1e-12 for a
 fixed V-cycle, 1e-9 for whole steps; bit for bit for batch against single.
@@ -14,7 +16,7 @@ import pytest
 
 from oracle import orc
 from paper_1803_00417_amd import inputs
-from tests.helpers import dev, hip_objs, host, lid_spec, oracle_objs, rel_err
+from tests.helpers import dev, hip_objs, host, lid_spec, oracle_objs, oracle_workload_steps, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +51,48 @@ def test_step_parity_cavity2d_512_two_steps():
         _say("  step", k, "rel err u", rel_err(host(u), u_o), "p", rel_err(host(p), p_o))
     assert rel_err(host(u), u_o) <= 1e-9
     assert rel_err(host(p), p_o) <= 1e-9
+
+
+def _gpu_steps(name, nsteps, precision=0):
+    s, w = _workload_spec(name)
+    g, fl = hip_objs(s)
+    ctx = hb.Context(g, fl, hb.make_step_opts(cfl=w["cfl"], precision=precision))
+    u = dev(np.zeros(hb.cell_shape(g, w["dim"])))
+    p = dev(np.zeros(hb.node_shape(g)))
+    dts = []
+    for _ in range(nsteps):
+        rep = ctx.step(u, p)
+        dts.append(rep.dt)
+        assert rep.visc.rel_resid <= 1e-10 and rep.proj.rel_resid <= 1e-10 and rep.mac.rel_resid <= 1e-10
+    ctx.close()
+    return host(u), host(p), np.array(dts)
+
+
+def test_step_parity_cavity3d_128_whole_step(tmp_path):
+    # a whole step of the 3D workload against the oracle (its OpenMP build,
+    # in a child process), element by element; mixed precision is held to
+    # the solves' tolerance
+    _say("full size: 3D 128^3 cavity, 1 step from rest against the oracle")
+    u_o, p_o, dt_o = oracle_workload_steps("cavity3d_128", 1, tmp_path)
+    u, p, dts = _gpu_steps("cavity3d_128", 1)
+    np.testing.assert_allclose(dts, dt_o, rtol=1e-12)
+    eu, ep = rel_err(u.reshape(u_o.shape), u_o), rel_err(p.reshape(p_o.shape), p_o)
+    _say("  fp64: rel err u %.2e p %.2e" % (eu, ep))
+    assert eu <= 1e-9 and ep <= 1e-9
+    u, p, _ = _gpu_steps("cavity3d_128", 1, precision=1)
+    eu, ep = rel_err(u.reshape(u_o.shape), u_o), rel_err(p.reshape(p_o.shape), p_o)
+    _say("  mixed: rel err u %.2e p %.2e" % (eu, ep))
+    assert eu <= 1e-7 and ep <= 1e-7
+
+
+def test_step_parity_cavity2d_512_ten_steps(tmp_path):
+    _say("full size: 2D 512^2 cavity, 10 steps from rest against the oracle")
+    u_o, p_o, dt_o = oracle_workload_steps("cavity2d_512_n0.5", 10, tmp_path)
+    u, p, dts = _gpu_steps("cavity2d_512_n0.5", 10)
+    np.testing.assert_allclose(dts, dt_o, rtol=1e-12)
+    eu, ep = rel_err(u.reshape(u_o.shape), u_o), rel_err(p.reshape(p_o.shape), p_o)
+    _say("  fp64: rel err u %.2e p %.2e" % (eu, ep))
+    assert eu <= 1e-9 and ep <= 1e-9
 
 
 def test_viscosity_parity_cavity3d_128():

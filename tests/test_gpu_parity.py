@@ -39,6 +39,23 @@ def _say(*a):
     print(*a, flush=True)
 
 
+@pytest.mark.parametrize("dim,nidx", [(2, 1.5), (3, 1.5), (2, 1.0)])
+def test_viscosity_parity_yield_only(dim, nidx):
+    # the yield-only regularisation: g^(n-1) + (HB/2)(1 - exp(-Pa g))/g,
+    # with n > 1 (the power-law term is not regularised)
+    _say("viscosity yield-only", dim, nidx)
+    s = lid_spec(dim, 16 if dim == 3 else 48, Re=10.0, HB=3.0, nidx=nidx, Pa=500.0, reg=orc.REG_YIELD_ONLY)
+    go, flo = oracle_objs(s)
+    ctx, g, fl = _ctx(s)
+    u = inputs.random_cells(orc.cell_shape(go, dim), seed=5, scale=0.7)
+    u[:, :, :3, :] = 0.0        # a region at rest: g = 0 there
+    eta_o, rc = orc.viscosity(go, flo, u)
+    assert rc == orc.OK
+    eta = dev(np.zeros(orc.cell_shape(go)[1:]))
+    ctx.viscosity(dev(u), eta)
+    assert rel_err(host(eta), eta_o) < 1e-13
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_viscosity_parity(case):
     _say("viscosity", case)
