@@ -394,6 +394,10 @@ static void build(mg_t* m, const orc_grid* g, const orc_fluid* fl, int op, const
         int can = (l < MAXLEV);
         for (int a = 0; a < cur.dim; ++a)
             if ((cur.n[a] & 1) || cur.n[a] / 2 < 2) can = 0;
+        /* the scalar problems (MAC, nodal) stop at the first level of at most
+         * 64 cells (2D 8^2, 3D 4^3), solved densely; the tensor problem goes
+         * down to the smallest even extents */
+        if (op != ORC_OP_VISC && ncells(&cur) <= 64) can = 0;
         if (!can) break;
         orc_grid nx = cur;
         for (int a = 0; a < cur.dim; ++a) nx.n[a] = cur.n[a] / 2;

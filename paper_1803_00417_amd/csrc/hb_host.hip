@@ -105,9 +105,11 @@ static hipError_t upload(T* dst, const std::vector<T>& src)
 // hierarchy
 // ---------------------------------------------------------------------------
 
-// grids of the levels of one cavity: coarsen by 2 while every extent is even
-// and its half is at least 2
-static std::vector<GridD> level_grids(const GridD& g0)
+// The levels of one cavity's hierarchy for problem op: halve every extent
+// while all are even and at least 4; the MAC and nodal hierarchies stop at
+// the first level of at most 64 cells (2D 8^2, 3D 4^3), whose dense inverse
+// is formed once per context, and so skip the smallest levels' sweeps
+static std::vector<GridD> level_grids(const GridD& g0, int op)
 {
     std::vector<GridD> out;
     GridD cur = g0;
@@ -116,6 +118,7 @@ static std::vector<GridD> level_grids(const GridD& g0)
         bool can = (int)out.size() < kMaxLev;
         for (int a = 0; a < cur.dim; ++a)
             if ((cur.n[a] & 1) || cur.n[a] / 2 < 2) can = false;
+        if (op != HB_OP_VISC && ncells(cur) <= 64) can = false;
         if (!can) break;
         GridD nx = cur;
         for (int a = 0; a < cur.dim; ++a) nx.n[a] = cur.n[a] / 2;
@@ -136,7 +139,7 @@ static int build_mg(Ctx* c, MG& m, int op)
     m.nlev = 0;
     m.nlevc.resize(nb);
     for (int b = 0; b < nb; ++b) {
-        lg[b] = level_grids(c->cv[b].g);
+        lg[b] = level_grids(c->cv[b].g, op);
         m.nlevc[b] = (int)lg[b].size();
         m.nlev = std::max(m.nlev, m.nlevc[b]);
     }

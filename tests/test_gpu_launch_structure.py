@@ -166,5 +166,6 @@ def test_autotuner_reports_candidate_tiles():
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "3", "HB_TAIL": "0"})
     assert ctx.tile_config(hb.OP_VISC, 0) == (32, 16, 512, 2)
     assert ctx.tile_config(hb.OP_VISC, 1) == (32, 16, 512, 1)
-    assert ctx.tile_config(hb.OP_NODAL, 0)[3] == 2 and ctx.tile_config(hb.OP_NODAL, 1)[3] == 1
+    # the nodal hierarchy stops at 4x16 = 64 cells: level 1 is its coarsest
+    assert ctx.tile_config(hb.OP_NODAL, 0)[3] == 2 and ctx.tile_config(hb.OP_NODAL, 1) is None
     ctx.close()
