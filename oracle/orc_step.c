@@ -23,12 +23,17 @@ static double slope4(const double q[5])
     return sgn(dc[1]) * dmin(fabs(d4), dlim[1]);
 }
 
-/* Riemann problem of the inviscid Burgers equation for the normal velocity */
-static double riemann(double uL, double uR)
+/* Burgers Riemann solution for the normal velocity (Sec. III.A, the
+ * Godunov predictor): uL for a right-moving wave (0 for a rarefaction with
+ * uL <= 0), uR for a left-moving one; a stationary shock, |uL + uR| within
+ * the dead band, takes the mean of the two */
+static double riemann(double uL, double uR, double delta)
 {
-    if (uL > 0.0 && uL + uR > 0.0) return uL;
-    if (uR < 0.0 && uL + uR < 0.0) return uR;
-    return 0.0;
+    const double s = uL + uR;
+    const double l = uL > 0.0 ? uL : 0.0, r = uR < 0.0 ? uR : 0.0;
+    if (s > delta) return l;
+    if (s < -delta) return r;
+    return 0.5 * (l + r);
 }
 
 /* upwind choice between two face states with a dead band of width delta */
@@ -142,7 +147,7 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
                         qL[q] = U(q, cL) + (0.5 - dt * U(a, cL) / (2.0 * h)) * SL(a, q, cL);
                         qR[q] = U(q, cR) - (0.5 + dt * U(a, cR) / (2.0 * h)) * SL(a, q, cR);
                     }
-                    double uh = riemann(qL[a], qR[a]);
+                    double uh = riemann(qL[a], qR[a], delta);
                     uhat[f] = uh;
                     for (int q = 0; q < d; ++q)
                         qhat[(long)q * nf_tot + f] = (q == a) ? uh : upwind(uh, qL[q], qR[q], delta);
@@ -210,7 +215,7 @@ int orc_advect(const orc_grid* g, const orc_fluid* fl, const orc_step_opts* o,
                         qLf[(long)q * nf_tot + f] = vl;
                         qRf[(long)q * nf_tot + f] = vr;
                     }
-                    uadv[f] = riemann(qLf[(long)a * nf_tot + f], qRf[(long)a * nf_tot + f]);
+                    uadv[f] = riemann(qLf[(long)a * nf_tot + f], qRf[(long)a * nf_tot + f], delta);
                 }
     }
 

@@ -30,12 +30,17 @@ __device__ inline double limited_slope(const double q[5])
     return sgn(dc[1]) * lesser(fabs(d4), dl[1]);
 }
 
-// Burgers Riemann solution for the normal velocity
-__device__ inline double burgers(double uL, double uR)
+// Burgers Riemann solution for the normal velocity: uL when the wave moves
+// right (uL + uR > delta; 0 for a rarefaction with uL <= 0), uR when it
+// moves left, and inside the dead band |uL + uR| <= delta, where a
+// stationary shock's side is decided by rounding, the mean of the two
+__device__ inline double burgers(double uL, double uR, double delta)
 {
-    if (uL > 0.0 && uL + uR > 0.0) return uL;
-    if (uR < 0.0 && uL + uR < 0.0) return uR;
-    return 0.0;
+    const double s = uL + uR;
+    const double l = uL > 0.0 ? uL : 0.0, r = uR < 0.0 ? uR : 0.0;
+    if (s > delta) return l;
+    if (s < -delta) return r;
+    return 0.5 * (l + r);
 }
 
 __device__ inline double upwind(double vel, double qL, double qR, double delta)
@@ -165,7 +170,7 @@ __global__ void k_trace_normal(GridD g, int a, double dt, double ulid, const dou
         qL[q] = u[q * N + cL] + (0.5 - dt * u[a * N + cL] / (2.0 * g.h)) * S[((long)a * d + q) * N + cL];
         qR[q] = u[q * N + cR] - (0.5 + dt * u[a * N + cR] / (2.0 * g.h)) * S[((long)a * d + q) * N + cR];
     }
-    const double uh = burgers(qL[a], qR[a]);
+    const double uh = burgers(qL[a], qR[a], delta);
     uhat[f] = uh;
     for (int q = 0; q < d; ++q) qhat[q * nf + f] = (q == a) ? uh : upwind(uh, qL[q], qR[q], delta);
 }
@@ -209,7 +214,8 @@ void launch_transverse(Ctx* c, const Cav& v)
 
 // full face states: traced normal part - dt/2 transverse terms + dt/2 forcing;
 // the advection velocity is the Burgers solution of the normal component
-__global__ void k_trace_full(GridD g, int a, double dt, const double* __restrict__ u, const double* __restrict__ S,
+__global__ void k_trace_full(GridD g, int a, double dt, double ulid, const double* __restrict__ sc,
+                             const double* __restrict__ u, const double* __restrict__ S,
                              const double* __restrict__ T, const double* __restrict__ F, long nf,
                              double* __restrict__ qLf, double* __restrict__ qRf, double* __restrict__ uadv)
 {
@@ -247,7 +253,7 @@ __global__ void k_trace_full(GridD g, int a, double dt, const double* __restrict
         qLf[q * nf + f] = vl;
         qRf[q * nf + f] = vr;
     }
-    uadv[f] = burgers(qLf[a * nf + f], qRf[a * nf + f]);
+    uadv[f] = burgers(qLf[a * nf + f], qRf[a * nf + f], deadband(sc, ulid));
 }
 
 void launch_trace_full(Ctx* c, const Cav& v, const double* u, double dt)
@@ -255,7 +261,7 @@ void launch_trace_full(Ctx* c, const Cav& v, const double* u, double dt)
     const GridD& g = v.g;
     for (int a = 0; a < g.dim; ++a)
         k_trace_full<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(
-            g, a, dt, u, v.S, v.trans, v.F, v.nf, v.qLf, v.qRf, v.uadv);
+            g, a, dt, v.ulid, v.sc, u, v.S, v.trans, v.F, v.nf, v.qLf, v.qRf, v.uadv);
 }
 
 // ---------------------------------------------------------------------------

@@ -968,6 +968,30 @@ def test_advection_mirror_equivariance(d, axis):
     np.testing.assert_allclose(bm, ref, atol=1e-11 * np.abs(b).max())
 
 
+def test_step_continuous_at_symmetric_ties():
+    # the 3D lid cavity is symmetric about its z mid-plane, so after a step
+    # the traced normal velocities meet there as uL = -uR: a stationary
+    # shock of the Burgers Riemann problem, whose side rounding alone would
+    # decide.  Rounding-level noise (1e-17 absolute) on the state may then
+    # move the next step by rounding only.  Taken with the explicit viscous
+    # stress in the predictor and theta = 0.75, where the tie lies in a
+    # region of velocities of order 1e-8.
+    g = orc.lid_cavity(3, 16)
+    fl = orc.make_fluid(Re=100.0, HB=2.0, Pa=1e3)
+    o = orc.make_step_opts(pred_visc=1, theta=0.75)
+    u = np.zeros(orc.cell_shape(g, 3))
+    p = np.zeros(orc.node_shape(g))
+    assert orc.step(g, fl, o, u, p)[1] == orc.OK
+    ua, pa = u.copy(), p.copy()
+    assert orc.step(g, fl, o, ua, pa)[1] == orc.OK
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        ub = u + 1e-17 * rng.standard_normal(u.shape)
+        pb = p + 1e-17 * rng.standard_normal(p.shape)
+        assert orc.step(g, fl, o, ub, pb)[1] == orc.OK
+        assert np.abs(ub - ua).max() < 1e-13 * np.abs(ua).max()
+
+
 def test_advection_axis_exchange_equivariance():
     # exchanging x and y (and the velocity components) commutes with the stage
     rng = np.random.default_rng(4)
