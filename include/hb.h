@@ -36,7 +36,11 @@
  * hb_cfl_dt_noalloc allocates nothing at all.
  *
  * Streams.  Work runs asynchronously on the hipStream_t given to hb_create
- * (NULL = the default stream).  Multigrid convergence is decided on the
+ * (NULL = the default stream): each call orders the library's internal
+ * streams after the work already on it and orders that stream after the
+ * call's results.  One internal stream carries the step; a second one runs
+ * the per-step dense factorisation of the viscous coarsest level beside the
+ * advection stage, joined before the viscous solve.  Multigrid convergence is decided on the
  * device: after each V-cycle (or BiCGStab half step) a small kernel tests
  * the residual and stops the cavity, and the cycle kernels skip stopped
  * cavities; the host only waits for the active count one check point late,

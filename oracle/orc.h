@@ -18,9 +18,8 @@
  *     approximate projection);
  *   - multigrid: Sec. III.D names AMReX cell and nodal multigrid but gives no
  *     detail; the V-cycle here is a textbook geometric multigrid (coarsening
- *     by two while every extent is even and at least 4; the MAC and nodal
- *     hierarchies stop at the first level of at most 64 cells; dense LU on
- *     the coarsest level).
+ *     by two while every extent is even and at least 4, stopping at the first
+ *     level with at most 128 unknowns; dense LU on the coarsest level).
  *
  * Conventions.  All arrays are FP64, x fastest: a cell field with C components
  * is [C][nz][ny][nx]; nodal fields are [nnz][nny][nnx] with nn_a = n_a + 1 on

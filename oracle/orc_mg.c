@@ -26,6 +26,9 @@ typedef struct {
     int* piv;
 } mg_t;
 
+/* largest dense coarsest system the hierarchy stops at */
+#define ORC_MG_DENSE_MAX 128
+
 static long unknowns(const orc_grid* g, int op)
 {
     if (op == ORC_OP_VISC) return ncells(g) * g->dim;
@@ -394,10 +397,10 @@ static void build(mg_t* m, const orc_grid* g, const orc_fluid* fl, int op, const
         int can = (l < MAXLEV);
         for (int a = 0; a < cur.dim; ++a)
             if ((cur.n[a] & 1) || cur.n[a] / 2 < 2) can = 0;
-        /* the scalar problems (MAC, nodal) stop at the first level of at most
-         * 64 cells (2D 8^2, 3D 4^3), solved densely; the tensor problem goes
-         * down to the smallest even extents */
-        if (op != ORC_OP_VISC && ncells(&cur) <= 64) can = 0;
+        /* stop at the first level with at most ORC_MG_DENSE_MAX unknowns
+         * (MAC 8^2 / 4^3 cells, nodal 9^2 / 5^3 nodes, tensor 2 x 8^2 in 2D
+         * and 3 x 2^3 in 3D); that level is solved densely */
+        if (L->nu <= ORC_MG_DENSE_MAX) can = 0;
         if (!can) break;
         orc_grid nx = cur;
         for (int a = 0; a < cur.dim; ++a) nx.n[a] = cur.n[a] / 2;

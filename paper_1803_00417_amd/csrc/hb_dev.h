@@ -7,6 +7,8 @@
 namespace hb {
 
 constexpr int kMaxLev = 24;
+// largest dense coarsest system a hierarchy stops at (unknowns)
+constexpr int kDenseMax = 128;
 constexpr int kMaxTail = 8;   // levels handled by the single-workgroup coarse V-cycle
 
 // Grid of one multigrid level, passed to kernels by value.

@@ -105,10 +105,17 @@ static hipError_t upload(T* dst, const std::vector<T>& src)
 // hierarchy
 // ---------------------------------------------------------------------------
 
+// unknowns of problem op on grid g
+static long op_unknowns(const GridD& g, int op)
+{
+    if (op == HB_OP_VISC) return (long)g.dim * ncells(g);
+    return op == HB_OP_MAC ? ncells(g) : nnodes(g);
+}
+
 // The levels of one cavity's hierarchy for problem op: halve every extent
-// while all are even and at least 4; the MAC and nodal hierarchies stop at
-// the first level of at most 64 cells (2D 8^2, 3D 4^3), whose dense inverse
-// is formed once per context, and so skip the smallest levels' sweeps
+// while all are even and at least 4, and stop at the first level with at
+// most kDenseMax unknowns (MAC 8^2 / 4^3 cells, nodal 9^2 / 5^3 nodes,
+// tensor 2 x 8^2 in 2D, 3 x 2^3 in 3D), which is solved by its dense inverse
 static std::vector<GridD> level_grids(const GridD& g0, int op)
 {
     std::vector<GridD> out;
@@ -118,7 +125,7 @@ static std::vector<GridD> level_grids(const GridD& g0, int op)
         bool can = (int)out.size() < kMaxLev;
         for (int a = 0; a < cur.dim; ++a)
             if ((cur.n[a] & 1) || cur.n[a] / 2 < 2) can = false;
-        if (op != HB_OP_VISC && ncells(cur) <= 64) can = false;
+        if (op_unknowns(cur, op) <= kDenseMax) can = false;
         if (!can) break;
         GridD nx = cur;
         for (int a = 0; a < cur.dim; ++a) nx.n[a] = cur.n[a] / 2;
@@ -308,8 +315,31 @@ static void factor_coarsest(Ctx* c, MG& m, int b)
         launch_nodal_dense(c, g, N, c->cv[b].dense_E, A);
     }
     if (m.op != HB_OP_VISC) launch_add_ones(c, N, A);
-    launch_lu_factor(c, N, A, m.piv + d.poff);
-    launch_lu_inverse(c, N, A, m.piv + d.poff, m.Ainv + d.aoff);
+    launch_dense_inverse(c, N, A, m.piv + d.poff, m.Ainv + d.aoff, m.op == HB_OP_VISC);
+}
+
+// The tensor problem's coarsest factorisation of cavity b on the second
+// stream: it needs the coefficients just written on s, and only the viscous
+// solve reads its result (join_visc_factor), so it overlaps whatever s runs
+// in between.
+static void factor_visc_async(Ctx* c, int b)
+{
+    (void)hipEventRecord(c->ev_f0, c->s);
+    (void)hipStreamWaitEvent(c->s2, c->ev_f0, 0);
+    hipStream_t keep = c->s;
+    c->s = c->s2;   // the launch helpers enqueue on c->s
+    factor_coarsest(c, c->visc, b);
+    c->s = keep;
+    (void)hipEventRecord(c->ev_f1, c->s2);
+    c->visc_factor_pending = true;
+}
+
+// order s after every factorisation factor_visc_async enqueued
+static void join_visc_factor(Ctx* c)
+{
+    if (!c->visc_factor_pending) return;
+    (void)hipStreamWaitEvent(c->s, c->ev_f1, 0);
+    c->visc_factor_pending = false;
 }
 
 // face viscosities of every level of cavity b from its cell viscosity eta
@@ -326,7 +356,7 @@ static void visc_setup(Ctx* c, int b, const double* eta, double dt)
         launch_restrict_faces(c, m.L[l - 1].hg[b], m.L[l].hg[b], m.L[l - 1].beta + m.L[l - 1].hof[b],
                               m.L[l].beta + m.L[l].hof[b]);
     m.f32_ready = false;
-    factor_coarsest(c, m, b);
+    factor_visc_async(c, b);
 }
 
 // FP32 copies of the tensor coefficients for mixed-precision cycles (the
@@ -792,6 +822,7 @@ static void nodal_prestart(Ctx* c, MG& m, double* x)
 // outcome stays on the device (solve_outcome reads it).
 static void solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o)
 {
+    if (m.op == HB_OP_VISC) join_visc_factor(c);
     const SegV all = seg_of(m, nullptr);
     if (m.op != HB_OP_VISC) seg_sub_mean(c, all, m.lvl0_b);
     if (m.op == HB_OP_NODAL && (c->ws || c->cap)) nodal_prestart(c, m, x);
@@ -1221,8 +1252,11 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         return code;
     };
     if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_f0, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_f1, hipEventDisableTiming) != hipSuccess)
         return give_up(HB_ERR_DEVICE, "stream or event creation failed");
     // the slot mirror and its publication word are coherent pinned memory
     // the device writes directly (fetch_slots)
@@ -1332,9 +1366,10 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
 
 static void destroy_ctx(Ctx* c)
 {
+    if (!c) return;
     if (const char* st = std::getenv("HB_STATS"))
         if (st[0] == '1') fprintf(stderr, "[hb] host waits: %ld, %.3f s\n", c->waits, c->wait_s);
-    if (!c) return;
+    if (c->s2) (void)hipStreamSynchronize(c->s2);
     if (c->s) (void)hipStreamSynchronize(c->s);
     kt_free(c);
     free_mg(c->visc);
@@ -1371,6 +1406,9 @@ static void destroy_ctx(Ctx* c)
     if (c->hsel) (void)hipHostFree(c->hsel);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->ev_f0) (void)hipEventDestroy(c->ev_f0);
+    if (c->ev_f1) (void)hipEventDestroy(c->ev_f1);
+    if (c->s2) (void)hipStreamDestroy(c->s2);
     if (c->s) (void)hipStreamDestroy(c->s);
     delete static_cast<::hb_ctx*>(c);
 }

@@ -283,9 +283,16 @@ struct KTimer {
 
 struct Ctx {
     hb_step_opts opts;
-    hipStream_t s = nullptr;      // the library's own stream (all work runs here)
+    hipStream_t s = nullptr;      // the library's own stream (all work runs here
+                                  // but the factorisation below)
     hipStream_t user = nullptr;   // the caller's stream, ordered with s by events
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // the per-step dense coarsest factorisation of the tensor problem runs on
+    // s2, overlapping the advection stage on s: ev_f0 (on s) orders it after
+    // the coefficients, ev_f1 (on s2) orders the viscous solve after it
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_f0 = nullptr, ev_f1 = nullptr;
+    bool visc_factor_pending = false;
     int nb = 1;                   // cavities
     int dim = 2;                  // common dimension
     std::vector<Cav> cv;
@@ -535,6 +542,7 @@ void launch_nodal_dense(Ctx* c, const GridD& g, int N, const double* E, double* 
 void launch_add_ones(Ctx* c, int N, double* A);
 void launch_lu_factor(Ctx* c, int N, double* A, int* piv);
 void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* Ainv);
+void launch_dense_inverse(Ctx* c, int N, double* A, int* piv, double* Ainv, bool definite);
 // x = A^{-1} b for the cavities whose coarsest level is lev (FP64 accumulation)
 template <typename R>
 void launch_coarse_solve(Ctx* c, const MG& m, int lev, const int* act, const R* b, R* x);

@@ -469,6 +469,78 @@ void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* 
     k_lu_inverse<<<(N + 63) / 64, 64, 0, c->s>>>(N, LU, piv, Ainv);
 }
 
+// Inverse of a dense N x N matrix, N <= kDenseMax, whose symmetric part is
+// positive definite (the coarsest tensor viscous operator I - dt
+// div(eta (grad u + grad u^T)), slightly unsymmetric at walls), by one
+// workgroup: Gauss-Jordan elimination in place, without pivoting, which such
+// matrices do not need.  The matrix lives in registers: thread t holds
+// column t % 128 of rows t / 128 + 8m, m = 0..15.  Step k passes column k
+// and row k through LDS (double-buffered by the parity of k, so one barrier
+// per step), every thread forms the scaled pivot row itself, and the update
+// of its sixteen elements touches registers only.
+constexpr int kGJThreads = 1024, kGJCols = 128, kGJRows = kGJThreads / kGJCols;
+constexpr int kGJPer = kDenseMax / kGJRows;
+static_assert(kGJCols >= kDenseMax && kGJPer * kGJRows == kDenseMax, "register layout covers the largest system");
+
+__global__ void __launch_bounds__(kGJThreads) k_gj_inverse(int N, const double* __restrict__ A, double* __restrict__ Ainv)
+{
+    __shared__ double ck[2][kDenseMax];   // column k before step k
+    __shared__ double rw[2][kDenseMax];   // row k before step k
+    const int tid = threadIdx.x, j = tid % kGJCols, rg = tid / kGJCols;
+    // rows and columns from N to kDenseMax - 1 hold zeros and stay zero
+    // (their pivot-column and pivot-row entries are zero), so every thread
+    // runs the same branch-free update
+    double v[kGJPer];
+#pragma unroll
+    for (int m = 0; m < kGJPer; ++m) {
+        const int i = rg + kGJRows * m;
+        v[m] = (j < N && i < N) ? A[(long)i * N + j] : 0.0;
+    }
+    for (int k = 0; k < N; ++k) {
+        double* cc = ck[k & 1];
+        double* rr = rw[k & 1];
+        if (j == k)
+#pragma unroll
+            for (int m = 0; m < kGJPer; ++m) cc[rg + kGJRows * m] = v[m];
+        if (rg == k % kGJRows) {
+            double a = 0.0;
+#pragma unroll
+            for (int m = 0; m < kGJPer; ++m)
+                if (rg + kGJRows * m == k) a = v[m];
+            rr[j] = a;
+        }
+        __syncthreads();
+        const double d = 1.0 / cc[k];
+        const double r = (j == k ? 1.0 : rr[j]) * d;
+        const bool pc = j == k;
+#pragma unroll
+        for (int m = 0; m < kGJPer; ++m) {
+            const int i = rg + kGJRows * m;
+            const double t = (pc ? 0.0 : v[m]) - cc[i] * r;
+            v[m] = i == k ? r : t;
+        }
+    }
+    if (j < N)
+#pragma unroll
+        for (int m = 0; m < kGJPer; ++m) {
+            const int i = rg + kGJRows * m;
+            if (i < N) Ainv[(long)i * N + j] = v[m];
+        }
+}
+
+// explicit inverse of a dense coarsest matrix: in registers for the tensor
+// problem (positive definite symmetric part, no pivoting), by LU with partial
+// pivoting otherwise (A is overwritten by its factors)
+void launch_dense_inverse(Ctx* c, int N, double* A, int* piv, double* Ainv, bool definite)
+{
+    if (definite && N <= kDenseMax) {
+        k_gj_inverse<<<1, kGJThreads, 0, c->s>>>(N, A, Ainv);
+    } else {
+        launch_lu_factor(c, N, A, piv);
+        launch_lu_inverse(c, N, A, piv, Ainv);
+    }
+}
+
 // x = A^{-1} b for the cavities whose coarsest level is lev; one row per
 // thread (block y = cavity), accumulated in FP64
 template <typename R>

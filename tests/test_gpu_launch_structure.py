@@ -160,12 +160,14 @@ def test_autotuner_reports_candidate_tiles():
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "3"})
     assert ctx.tile_config(hb.OP_NODAL, 0) == (64, 16, 1024, 2)
     ctx.close()
-    # a periodic extent below 8 allows one sweep per launch only
-    s = CASES["chan2d_8x32"]()
+    # a periodic extent below 8 allows one sweep per launch only: on an 8x64
+    # channel level 1 (4x32) still smooths, level 2 (2x16, 64 unknowns per
+    # component pair) is the tensor problem's dense coarsest
+    s = spec(2, [8, 64], h=1.0 / 64, bc=((1, 1), (0, 0)), Re=1.0, HB=0.2, Pa=1e3, f=(1.0, 0.0, 0.0))
     g, fl = hip_objs(s)
     ctx = _context(lambda: hb.Context(g, fl, hb.make_step_opts()), {"HB_TILE": "3", "HB_TAIL": "0"})
     assert ctx.tile_config(hb.OP_VISC, 0) == (32, 16, 512, 2)
     assert ctx.tile_config(hb.OP_VISC, 1) == (32, 16, 512, 1)
-    # the nodal hierarchy stops at 4x16 = 64 cells: level 1 is its coarsest
-    assert ctx.tile_config(hb.OP_NODAL, 0)[3] == 2 and ctx.tile_config(hb.OP_NODAL, 1) is None
+    assert ctx.tile_config(hb.OP_VISC, 2) is None
+    assert ctx.tile_config(hb.OP_NODAL, 0)[3] == 2 and ctx.tile_config(hb.OP_NODAL, 1)[3] == 1
     ctx.close()

@@ -330,11 +330,11 @@ def test_tensor_operator_mms_second_order(d):
 # multigrid against dense direct solves on 8^2 (and 4^3)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("op,d,n", [(orc.OP_VISC, 2, 8), (orc.OP_VISC, 3, 4), (orc.OP_NODAL, 2, 16),
+@pytest.mark.parametrize("op,d,n", [(orc.OP_VISC, 2, 16), (orc.OP_VISC, 3, 4), (orc.OP_NODAL, 2, 16),
                                     (orc.OP_NODAL, 3, 8), (orc.OP_MAC, 2, 16), (orc.OP_MAC, 3, 8)])
 def test_mg_equals_dense_lu(op, d, n):
-    # (the scalar hierarchies stop at 64 cells, so their grids are one
-    # refinement larger than the tensor ones to run real V-cycles)
+    # (the hierarchies stop at 128 unknowns, so the grids are large enough
+    # for at least one level above the dense solve)
     rng = np.random.default_rng(7 + op)
     g = orc.lid_cavity(d, n)
     fl = orc.make_fluid(Re=3.0)
@@ -485,14 +485,17 @@ def _restrict_mean(gf, gc, f):
 
 @pytest.mark.parametrize("d,bc", [(2, None), (2, ((1, 1), (0, 0))), (3, None), (3, ((0, 0), (0, 0), (1, 1)))])
 def test_tensor_vcycle_two_grid_correction(d, bc):
-    # on a 6^d grid the hierarchy has two levels (6 and 3 cells per axis),
-    # so one V-cycle without smoothing from zero is the two-grid coarse
+    # on a 10^2 or 6^3 grid the hierarchy has two levels (10 and 5, or 6 and
+    # 3 cells per axis: odd extents stop the coarsening, and the fine level
+    # has more than the 128 unknowns of a dense stop), so one V-cycle
+    # without smoothing from zero is the two-grid coarse
     # correction x = P A_2h^-1 R b: R the mean of the children, A_2h the
     # operator rediscretised at 2h (constant viscosity, so the averaged coarse
     # face viscosities equal the fine ones), P the linear prolongation with
     # the odd (Dirichlet) image beyond walls
     rng = np.random.default_rng(21)
-    gf = orc.make_grid(d, [6] * d, 1.0 / 6, bc=bc)
+    n = 10 if d == 2 else 6
+    gf = orc.make_grid(d, [n] * d, 1.0 / n, bc=bc)
     gc = orc.coarse_grid(gf)
     fl = orc.make_fluid(Re=1.0)
     dt = 0.3
@@ -506,7 +509,7 @@ def test_tensor_vcycle_two_grid_correction(d, bc):
     assert np.abs(x - ref).max() < 1e-13 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 4)])
 def test_tensor_plain_vcycles_equal_dense_lu(d, n):
     rng = np.random.default_rng(8)
     g = orc.lid_cavity(d, n)
