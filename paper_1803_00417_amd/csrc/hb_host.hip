@@ -285,6 +285,7 @@ static void free_mg(MG& m)
         (void)hipFree(L.nuc);
     }
     (void)hipFree(m.cs);
+    (void)hipFree(m.dd);
     (void)hipFree(m.tplan);
     (void)hipFree(m.A);
     (void)hipFree(m.Ainv);
@@ -296,8 +297,8 @@ static void free_mg(MG& m)
         if (m.gexec[p]) (void)hipGraphExecDestroy(m.gexec[p]);
 }
 
-// dense coarsest matrix of cavity b from its current coefficients, LU and
-// inverse
+// dense coarsest matrix of cavity b of the MAC or nodal problem (constant),
+// A + 1 1^T / N, LU and inverse; at context creation
 static void factor_coarsest(Ctx* c, MG& m, int b)
 {
     const CoarseD& d = m.hcs[b];
@@ -306,35 +307,30 @@ static void factor_coarsest(Ctx* c, MG& m, int b)
     const GridD& g = C.hg[b];
     double* A = m.A + d.aoff;
     launch_identity(c, N, c->cv[b].dense_E);
-    if (m.op == HB_OP_VISC) {
-        const double dt = c->cv[b].hsc[S_DT];
-        launch_visc_dense(c, g, C.beta + C.hof[b], dt, N, c->cv[b].dense_E, A);
-    } else if (m.op == HB_OP_MAC) {
-        launch_mac_dense(c, g, N, c->cv[b].dense_E, A);
-    } else {
-        launch_nodal_dense(c, g, N, c->cv[b].dense_E, A);
-    }
-    if (m.op != HB_OP_VISC) launch_add_ones(c, N, A);
-    launch_dense_inverse(c, N, A, m.piv + d.poff, m.Ainv + d.aoff, m.op == HB_OP_VISC);
+    if (m.op == HB_OP_MAC) launch_mac_dense(c, g, N, c->cv[b].dense_E, A);
+    else launch_nodal_dense(c, g, N, c->cv[b].dense_E, A);
+    launch_add_ones(c, N, A);
+    launch_dense_inverse(c, N, A, m.piv + d.poff, m.Ainv + d.aoff);
 }
 
-// The tensor problem's coarsest factorisation of cavity b on the second
-// stream: it needs the coefficients just written on s, and only the viscous
-// solve reads its result (join_visc_factor), so it overlaps whatever s runs
-// in between.
-static void factor_visc_async(Ctx* c, int b)
+// The tensor problem's coarsest matrices of every cavity (new with every
+// viscosity), assembled and inverted on the second stream: the work needs
+// the coefficients just written on s, and only the viscous solve reads its
+// result (join_visc_factor), so it overlaps whatever s runs in between.
+static void factor_visc_async(Ctx* c)
 {
     (void)hipEventRecord(c->ev_f0, c->s);
     (void)hipStreamWaitEvent(c->s2, c->ev_f0, 0);
     hipStream_t keep = c->s;
     c->s = c->s2;   // the launch helpers enqueue on c->s
-    factor_coarsest(c, c->visc, b);
+    launch_visc_dense_batch(c, c->visc);
+    launch_gj_inverse_batch(c, c->visc);
     c->s = keep;
     (void)hipEventRecord(c->ev_f1, c->s2);
     c->visc_factor_pending = true;
 }
 
-// order s after every factorisation factor_visc_async enqueued
+// order s after the factorisation factor_visc_async enqueued
 static void join_visc_factor(Ctx* c)
 {
     if (!c->visc_factor_pending) return;
@@ -343,12 +339,12 @@ static void join_visc_factor(Ctx* c)
 }
 
 // face viscosities of every level of cavity b from its cell viscosity eta
-// (not /Re), its dt into the device slot, and its coarsest factorisation
+// (not /Re) and its coefficient dt into the device slot; the coarsest
+// matrices follow for all cavities at once (factor_visc_async)
 static void visc_setup(Ctx* c, int b, const double* eta, double dt)
 {
     MG& m = c->visc;
     Cav& v = c->cv[b];
-    v.hsc[S_DT] = dt;   // host copy, used for the dense assembly
     set_slot(c, b, S_DT, dt);
     launch_eta_over_re(c, v, eta, m.etae + m.L[0].ho[b]);
     launch_eta_faces(c, v, v.g, eta, m.L[0].beta + m.L[0].hof[b]);
@@ -356,7 +352,6 @@ static void visc_setup(Ctx* c, int b, const double* eta, double dt)
         launch_restrict_faces(c, m.L[l - 1].hg[b], m.L[l].hg[b], m.L[l - 1].beta + m.L[l - 1].hof[b],
                               m.L[l].beta + m.L[l].hof[b]);
     m.f32_ready = false;
-    factor_visc_async(c, b);
 }
 
 // FP32 copies of the tensor coefficients for mixed-precision cycles (the
@@ -999,8 +994,11 @@ static int step_all(Ctx* c, double* const* u, double* const* p, const double* dt
         launch_viscosity(c, v, u[b], v.eta);
         // the solve's operator is I - 2 theta dt div(eta/Re gamma_dot(.))
         visc_setup(c, b, v.eta, 2.0 * c->opts.theta * dt[b]);
+    }
+    factor_visc_async(c);
+    for (int b = 0; b < nb; ++b) {
         advect_predict(c, b, u[b], p[b], dt[b]);
-        v.step_dt = dt[b];
+        c->cv[b].step_dt = dt[b];
     }
     advect_finish(c, uc, dt, rhs, conv, reports ? &divr : nullptr);
     for (int b = 0; b < nb; ++b) {
@@ -1358,6 +1356,24 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         factor_coarsest(c, c->mac, b);
         factor_coarsest(c, c->nodal, b);
     }
+    // the tensor problem's per-step assembly: per-cavity table and unit
+    // vectors (the MAC and nodal assemblies above used them first)
+    {
+        MG& m = c->visc;
+        std::vector<DenseD> dd(count);
+        for (int b = 0; b < count; ++b) {
+            const CoarseD& d = m.hcs[b];
+            const Level& C = m.L[d.lev];
+            dd[b].g = C.hg[b];
+            dd[b].beta = C.beta + C.hof[b];
+            dd[b].aoff = d.aoff;
+            dd[b].N = d.N;
+            dd[b].E = c->cv[b].dense_E;
+            launch_identity(c, d.N, c->cv[b].dense_E);
+        }
+        if (dalloc(&m.dd, count) != hipSuccess || upload(m.dd, dd) != hipSuccess)
+            return give_up(HB_ERR_OOM, "device allocation failed");
+    }
     autotune(c);
     if (hipStreamSynchronize(c->s) != hipSuccess) return give_up(HB_ERR_DEVICE, "stream synchronisation failed during set-up");
     *out = c;
@@ -1500,6 +1516,7 @@ int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt, const double*
     StreamGuard guard(c);
     if (op == HB_OP_VISC) {
         visc_setup(c, 0, eta, dt);
+        factor_visc_async(c);
         launch_visc_wall_rhs(c, c->cv[0].g, m.L[0].beta, dt, rhs, m.lvl0_b);
     } else {
         copy(c, m.lvl0_b, rhs, m.L[0].nu);

@@ -203,6 +203,17 @@ struct CoarseD {
     long xoff;      // offset of its unknowns in that level's arenas
 };
 
+// what the batched assembly of a cavity's dense coarsest tensor matrix
+// needs: the coarsest grid, the offset of its face viscosities in that
+// level's arena, the matrix offset and size, and the cavity's unit vectors
+struct DenseD {
+    GridD g;
+    const double* beta;
+    long aoff;
+    int N;
+    const double* E;
+};
+
 // one level of a cavity's coarse tail (hb_tail.hip): its grid, LDS layout
 // (offsets in storage elements) and the offset of its face arrays
 struct TailLevel {
@@ -227,6 +238,7 @@ struct MG {
     std::vector<int> nlevc;  // levels per cavity
     std::vector<CoarseD> hcs;
     CoarseD* cs = nullptr;   // device copy
+    DenseD* dd = nullptr;    // tensor problem: per-cavity dense assembly table
     int ncmax = 0;           // largest coarsest system
     double* A = nullptr;     // coarsest dense matrices -> LU factors (arena)
     int* piv = nullptr;
@@ -448,6 +460,7 @@ void launch_restrict_faces(Ctx* c, const GridD& gf, const GridD& gc, const doubl
 void launch_visc_div(Ctx* c, const GridD& g, const double* beta, const double* u, double* out);
 void launch_visc_wall_rhs(Ctx* c, const GridD& g, const double* beta, double dt, const double* rhs, double* out);
 void launch_visc_dense(Ctx* c, const GridD& g, const double* beta, double dt, int N, const double* E, double* A);
+void launch_visc_dense_batch(Ctx* c, const MG& m);
 void launch_eta_over_re(Ctx* c, const Cav& v, const double* eta, double* etae);
 
 // ---- LDS-tiled tensor kernels, batched (hb_tile.hip) ------------------------
@@ -542,7 +555,8 @@ void launch_nodal_dense(Ctx* c, const GridD& g, int N, const double* E, double* 
 void launch_add_ones(Ctx* c, int N, double* A);
 void launch_lu_factor(Ctx* c, int N, double* A, int* piv);
 void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* Ainv);
-void launch_dense_inverse(Ctx* c, int N, double* A, int* piv, double* Ainv, bool definite);
+void launch_dense_inverse(Ctx* c, int N, double* A, int* piv, double* Ainv);
+void launch_gj_inverse_batch(Ctx* c, const MG& m);
 // x = A^{-1} b for the cavities whose coarsest level is lev (FP64 accumulation)
 template <typename R>
 void launch_coarse_solve(Ctx* c, const MG& m, int lev, const int* act, const R* b, R* x);

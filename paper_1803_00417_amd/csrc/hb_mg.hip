@@ -482,8 +482,15 @@ constexpr int kGJThreads = 1024, kGJCols = 128, kGJRows = kGJThreads / kGJCols;
 constexpr int kGJPer = kDenseMax / kGJRows;
 static_assert(kGJCols >= kDenseMax && kGJPer * kGJRows == kDenseMax, "register layout covers the largest system");
 
-__global__ void __launch_bounds__(kGJThreads) k_gj_inverse(int N, const double* __restrict__ A, double* __restrict__ Ainv)
+__global__ void __launch_bounds__(kGJThreads) k_gj_inverse(const CoarseD* __restrict__ cs, const double* __restrict__ Aa,
+                                                           double* __restrict__ Ainva)
 {
+    // one workgroup per cavity; larger systems take the LU path
+    const CoarseD cd = cs[blockIdx.x];
+    const int N = cd.N;
+    if (N > kDenseMax) return;
+    const double* __restrict__ A = Aa + cd.aoff;
+    double* __restrict__ Ainv = Ainva + cd.aoff;
     __shared__ double ck[2][kDenseMax];   // column k before step k
     __shared__ double rw[2][kDenseMax];   // row k before step k
     const int tid = threadIdx.x, j = tid % kGJCols, rg = tid / kGJCols;
@@ -528,16 +535,26 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_inverse(int N, const double* 
         }
 }
 
-// explicit inverse of a dense coarsest matrix: in registers for the tensor
-// problem (positive definite symmetric part, no pivoting), by LU with partial
-// pivoting otherwise (A is overwritten by its factors)
-void launch_dense_inverse(Ctx* c, int N, double* A, int* piv, double* Ainv, bool definite)
+// explicit inverse of a dense coarsest matrix by LU with partial pivoting
+// (A is overwritten by its factors)
+void launch_dense_inverse(Ctx* c, int N, double* A, int* piv, double* Ainv)
 {
-    if (definite && N <= kDenseMax) {
-        k_gj_inverse<<<1, kGJThreads, 0, c->s>>>(N, A, Ainv);
-    } else {
-        launch_lu_factor(c, N, A, piv);
-        launch_lu_inverse(c, N, A, piv, Ainv);
+    launch_lu_factor(c, N, A, piv);
+    launch_lu_inverse(c, N, A, piv, Ainv);
+}
+
+// explicit inverses of the tensor problem's coarsest matrices of every
+// cavity (positive definite symmetric part): one workgroup per cavity in
+// registers, LU for the few systems above kDenseMax
+void launch_gj_inverse_batch(Ctx* c, const MG& m)
+{
+    k_gj_inverse<<<c->nb, kGJThreads, 0, c->s>>>(m.cs, m.A, m.Ainv);
+    for (int b = 0; b < c->nb; ++b) {
+        const CoarseD& d = m.hcs[b];
+        if (d.N > kDenseMax) {
+            launch_lu_factor(c, d.N, m.A + d.aoff, m.piv + d.poff);
+            launch_lu_inverse(c, d.N, m.A + d.aoff, m.piv + d.poff, m.Ainv + d.aoff);
+        }
     }
 }
 

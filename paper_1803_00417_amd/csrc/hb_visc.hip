@@ -230,6 +230,31 @@ void launch_visc_dense(Ctx* c, const GridD& g, const double* beta, double dt, in
     k_visc_dense<<<dim3((N + 255) / 256, N), 256, 0, c->s>>>(g, beta, dt, N, E, A);
 }
 
+// the same for every cavity in one launch (block z = cavity), with the
+// cavity's coefficient 2 theta dt from its scalar slot
+__global__ void k_visc_dense_batch(const DenseD* __restrict__ dd, const double* __restrict__ sc, double* __restrict__ A)
+{
+    const int cav = blockIdx.z;
+    const DenseD& d = dd[cav];
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    const int col = blockIdx.y;
+    if (row >= d.N || col >= d.N) return;
+    const GridD g = d.g;
+    const long Nc = ncells(g);
+    const int c = (int)(row / Nc);
+    const long q = row % Nc;
+    const int i = (int)(q % g.n[0]), j = (int)((q / g.n[0]) % g.n[1]), k = (int)(q / ((long)g.n[0] * g.n[1]));
+    const double dt = sc[(long)cav * S_NSLOT + S_DT];
+    const double* x = d.E + (long)col * d.N;
+    A[d.aoff + (long)row * d.N + col] = x[row] - dt * visc_div_at<true, false>(g, d.beta, x, c, i, j, k);
+}
+
+void launch_visc_dense_batch(Ctx* c, const MG& m)
+{
+    const int n = m.ncmax;
+    k_visc_dense_batch<<<dim3((n + 255) / 256, n, c->nb), 256, 0, c->s>>>(m.dd, c->sc, m.A);
+}
+
 __global__ void k_eta_over_re(long n, double Re, const double* __restrict__ eta, double* __restrict__ etae)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
