@@ -338,19 +338,32 @@ static void join_visc_factor(Ctx* c)
     c->visc_factor_pending = false;
 }
 
-// face viscosities of every level of cavity b from its cell viscosity eta
-// (not /Re) and its coefficient dt into the device slot; the coarsest
-// matrices follow for all cavities at once (factor_visc_async)
-static void visc_setup(Ctx* c, int b, const double* eta, double dt)
+// Upload the per-call table.  The two halves of the pinned staging buffer
+// are used in turn; every call that uploads ends by waiting for its stream
+// (fetch_slots), so a half is never rewritten while its copy is pending.
+static void set_io(Ctx* c, const std::vector<CavIO>& io)
+{
+    c->io_half ^= 1;
+    CavIO* h = c->hio + (long)c->io_half * c->nb;
+    memcpy(h, io.data(), sizeof(CavIO) * c->nb);
+    (void)hipMemcpyAsync(c->cio, h, sizeof(CavIO) * c->nb, hipMemcpyHostToDevice, c->s);
+}
+
+static CavIO io_zero()
+{
+    CavIO z;
+    memset(&z, 0, sizeof(z));
+    return z;
+}
+
+// face viscosities of every level of every cavity from its cell viscosity
+// (CavIO::eta, not /Re) and its operator coefficient (CavIO::vdt) into the
+// slot S_DT; the coarsest matrices follow (factor_visc_async)
+static void visc_setup(Ctx* c)
 {
     MG& m = c->visc;
-    Cav& v = c->cv[b];
-    set_slot(c, b, S_DT, dt);
-    launch_eta_over_re(c, v, eta, m.etae + m.L[0].ho[b]);
-    launch_eta_faces(c, v, v.g, eta, m.L[0].beta + m.L[0].hof[b]);
-    for (int l = 1; l < m.nlevc[b]; ++l)
-        launch_restrict_faces(c, m.L[l - 1].hg[b], m.L[l].hg[b], m.L[l - 1].beta + m.L[l - 1].hof[b],
-                              m.L[l].beta + m.L[l].hof[b]);
+    stage_visc_coef(c);
+    for (int l = 1; l < m.nlev; ++l) stage_restrict_faces(c, l);
     m.f32_ready = false;
 }
 
@@ -877,27 +890,26 @@ static int worse(int rc, int cur)
 // stages of the step (per cavity around the batched solves)
 // ---------------------------------------------------------------------------
 
-// the Godunov prediction up to the MAC divergence (into the MAC right-hand
-// side of cavity b); requires visc_setup and S_MAXU = max|u|
-static void advect_predict(Ctx* c, int b, const double* u, const double* p, double dt)
+// the Godunov prediction of every cavity up to the MAC divergence (into
+// the MAC right-hand sides); requires visc_setup, the per-call table and
+// S_MAXU = max|u|
+static void advect_predict(Ctx* c)
 {
-    Cav& v = c->cv[b];
-    launch_visc_div(c, v.g, c->visc.L[0].beta + c->visc.L[0].hof[b], u, v.E);
-    launch_grad_node(c, v, p, v.Gp);
-    launch_forcing(c, v);
-    launch_slopes(c, v, u);
-    launch_trace_normal(c, v, u, dt);
-    launch_transverse(c, v);
-    launch_trace_full(c, v, u, dt);
-    if (c->opts.mac_project) launch_mac_div(c, v, v.uadv, c->mac.lvl0_b + c->mac.L[0].ho[b]);
+    stage_visc_div(c);
+    stage_grad_node(c);
+    stage_forcing(c);
+    stage_slopes(c);
+    stage_trace_normal(c);
+    stage_transverse(c);
+    stage_trace_full(c);
+    if (c->opts.mac_project) stage_mac_div(c, 0);
 }
 
 // MAC projection of every cavity's face velocity, then each cavity's
-// viscous right-hand side into rhs (and conv when given); with div_rel, the
-// MAC divergence after the projection relative to before it (host reads)
-static void advect_finish(Ctx* c, const std::vector<const double*>& u, const std::vector<double>& dt,
-                          const std::vector<double*>& rhs, const std::vector<double*>& conv,
-                          std::vector<double>* div_rel)
+// viscous right-hand side into CavIO::b (and CavIO::conv when set); with
+// div_rel, the MAC divergence after the projection relative to before it
+// (host reads)
+static void advect_finish(Ctx* c, std::vector<double>* div_rel)
 {
     const int nb = c->nb;
     std::vector<double> d0(nb, 0.0);
@@ -909,14 +921,10 @@ static void advect_finish(Ctx* c, const std::vector<const double*>& u, const std
         }
         fill(c, c->macphi, 0.0, c->mac.L[0].nu);
         solve_prepared(c, c->mac, c->macphi, c->opts.mac);
-        for (int b = 0; b < nb; ++b) {
-            launch_mac_update(c, c->cv[b]);
-            if (div_rel) {
-                launch_mac_div(c, c->cv[b], c->cv[b].umac, c->cv[b].macrhs);
-                red_maxabs(c, b, c->cv[b].macrhs, c->cv[b].nc, S_MAX);
-            }
-        }
+        stage_mac_update(c);
         if (div_rel) {
+            stage_mac_div(c, 1);
+            stage_maxabs(c, SF_MACRHS, S_MAX);
             fetch_slots(c);
             for (int b = 0; b < nb; ++b) (*div_rel)[b] = d0[b] > 0.0 ? slot(c, b, S_MAX) / d0[b] : 0.0;
         }
@@ -926,7 +934,7 @@ static void advect_finish(Ctx* c, const std::vector<const double*>& u, const std
             if (div_rel) (*div_rel)[b] = 0.0;
         }
     }
-    for (int b = 0; b < nb; ++b) launch_advect_rhs(c, c->cv[b], u[b], dt[b], rhs[b], conv[b]);
+    stage_advect_rhs(c);
 }
 
 // outcome of the step's MAC solve (zero reports when it does not run)
@@ -938,24 +946,17 @@ static int mac_outcome(Ctx* c, std::vector<hb_mg_report>* rep)
     return HB_OK;
 }
 
-// projection of every cavity: V = ustar/dt + G p, K phi = weak div V,
-// u = ustar + dt (G p - G phi), p = phi
-static void project_all(Ctx* c, const std::vector<const double*>& ustar, const std::vector<double*>& p,
-                        const std::vector<double>& dt, const std::vector<double*>& u)
+// projection of every cavity (per-call table: ustar, p, uout, dt):
+// V = ustar/dt + G p, K phi = weak div V, uout = ustar + dt (G p - G phi),
+// p = phi
+static void project_all(Ctx* c)
 {
-    const int nb = c->nb;
-    for (int b = 0; b < nb; ++b) {
-        Cav& v = c->cv[b];
-        launch_grad_node(c, v, p[b], v.Gp);
-        launch_proj_rhs(c, v, ustar[b], dt[b], c->nodal.lvl0_b + c->nodal.L[0].ho[b]);
-        copy(c, v.phi, p[b], v.nn);
-    }
+    stage_grad_node(c);
+    stage_proj_rhs(c);
+    stage_copy(c, SF_PHI, SF_P);
     solve_prepared(c, c->nodal, c->phi, c->opts.proj);
-    for (int b = 0; b < nb; ++b) {
-        Cav& v = c->cv[b];
-        launch_proj_update(c, v, ustar[b], v.phi, dt[b], u[b]);
-        copy(c, p[b], v.phi, v.nn);
-    }
+    stage_proj_update(c);
+    stage_copy(c, SF_P, SF_PHI);
 }
 
 // One full step of every cavity in place.  dt[b] <= 0 selects the CFL time
@@ -963,10 +964,14 @@ static void project_all(Ctx* c, const std::vector<const double*>& ustar, const s
 static int step_all(Ctx* c, double* const* u, double* const* p, const double* dt_in, hb_step_report* reports)
 {
     const int nb = c->nb;
+    std::vector<CavIO> io(nb, io_zero());
     for (int b = 0; b < nb; ++b) {
-        red_maxabs(c, b, u[b], c->cv[b].dim * c->cv[b].nc, S_MAXU);
-        red_maxabs(c, b, p[b], c->cv[b].nn, S_MAX2);
+        io[b].u = u[b];
+        io[b].p = p[b];
     }
+    set_io(c, io);
+    stage_maxabs(c, SF_U, S_MAXU);
+    stage_maxabs(c, SF_P, S_MAX2);
     fetch_slots(c);
     std::vector<double> dt(nb);
     for (int b = 0; b < nb; ++b) {
@@ -982,40 +987,32 @@ static int step_all(Ctx* c, double* const* u, double* const* p, const double* dt
     }
     std::vector<hb_mg_report> mrep(nb), vrep(nb), prep(nb);
     std::vector<double> divr(nb, 0.0);
-    std::vector<const double*> uc(nb), us(nb);
-    std::vector<double*> rhs(nb), conv(nb, nullptr), uv(nb), pv(nb);
     for (int b = 0; b < nb; ++b) {
         Cav& v = c->cv[b];
-        uc[b] = u[b];
-        us[b] = v.ustar;
-        rhs[b] = v.rhs;
-        uv[b] = u[b];
-        pv[b] = p[b];
-        launch_viscosity(c, v, u[b], v.eta);
+        io[b].eta = v.eta;
+        io[b].b = v.rhs;
+        io[b].conv = nullptr;
+        io[b].ustar = v.ustar;
+        io[b].uout = u[b];
+        io[b].dt = dt[b];
         // the solve's operator is I - 2 theta dt div(eta/Re gamma_dot(.))
-        visc_setup(c, b, v.eta, 2.0 * c->opts.theta * dt[b]);
+        io[b].vdt = 2.0 * c->opts.theta * dt[b];
+        v.step_dt = dt[b];
     }
+    set_io(c, io);
+    stage_viscosity(c);
+    visc_setup(c);
     factor_visc_async(c);
-    for (int b = 0; b < nb; ++b) {
-        advect_predict(c, b, u[b], p[b], dt[b]);
-        c->cv[b].step_dt = dt[b];
-    }
-    advect_finish(c, uc, dt, rhs, conv, reports ? &divr : nullptr);
-    for (int b = 0; b < nb; ++b) {
-        Cav& v = c->cv[b];
-        launch_visc_wall_rhs(c, v.g, c->visc.L[0].beta + c->visc.L[0].hof[b], 2.0 * c->opts.theta * dt[b], v.rhs,
-                             c->visc.lvl0_b + c->visc.L[0].hou[b]);
-        copy(c, v.ustar, u[b], v.dim * v.nc);
-    }
+    advect_predict(c);
+    advect_finish(c, reports ? &divr : nullptr);
+    stage_visc_wall_rhs(c);
+    stage_copy(c, SF_USTAR, SF_U);
     solve_prepared(c, c->visc, c->ustar, c->opts.visc);
-    project_all(c, us, pv, dt, uv);
+    project_all(c);
     if (reports) {
-        for (int b = 0; b < nb; ++b) {
-            Cav& v = c->cv[b];
-            red_maxabs(c, b, u[b], v.dim * v.nc, S_MAX);
-            launch_weak_div(c, v, u[b], v.rnode);
-            red_maxabs(c, b, v.rnode, v.nn, S_MAX2);
-        }
+        stage_maxabs(c, SF_UOUT, S_MAX);
+        stage_weak_div_u(c);
+        stage_maxabs(c, SF_RNODE, S_MAX2);
     }
     // the one read of the step's outcome: the solves' records (and the
     // diagnostics of a report)
@@ -1220,6 +1217,87 @@ static void autotune(Ctx* c)
         if (x) (void)hipEventDestroy(x);
 }
 
+// The stage kernels' tables: per cavity its grid, fluid and buffers, the
+// face-viscosity restrictions per level, and the largest extents over the
+// cavities (launch grids), checked against the device's grid limit.
+static int build_stage_tables(Ctx* c)
+{
+    const int nb = c->nb;
+    std::vector<CavK> ck(nb);
+    int cx[3] = {1, 1, 1}, fx[3] = {1, 1, 1}, nx[3] = {1, 1, 1};
+    for (int b = 0; b < nb; ++b) {
+        const Cav& v = c->cv[b];
+        CavK& K = ck[b];
+        memset(&K, 0, sizeof(K));
+        K.g = v.g;
+        K.fl = v.fl;
+        K.ulid = v.ulid;
+        K.nc = v.nc;
+        K.nf = v.nf;
+        K.nn = v.nn;
+        K.sc = v.sc;
+        K.eta = v.eta;
+        K.E = v.E;
+        K.Gp = v.Gp;
+        K.F = v.F;
+        K.S = v.S;
+        K.trans = v.trans;
+        K.uhat = v.uhat;
+        K.qhat = v.qhat;
+        K.qLf = v.qLf;
+        K.qRf = v.qRf;
+        K.uadv = v.uadv;
+        K.umac = v.umac;
+        K.macrhs = v.macrhs;
+        K.rnode = v.rnode;
+        K.rhs = v.rhs;
+        K.ustar = v.ustar;
+        K.phi = v.phi;
+        K.macphi = v.macphi;
+        K.beta0 = c->visc.L[0].beta + c->visc.L[0].hof[b];
+        K.etae = c->visc.etae + c->visc.L[0].ho[b];
+        K.macb = c->mac.lvl0_b + c->mac.L[0].ho[b];
+        K.nodb = c->nodal.lvl0_b + c->nodal.L[0].ho[b];
+        K.viscb = c->visc.lvl0_b + c->visc.L[0].hou[b];
+        for (int e = 0; e < 3; ++e) {
+            cx[e] = std::max(cx[e], v.g.n[e]);
+            nx[e] = std::max(nx[e], nnode(v.g, e));
+            for (int a = 0; a < v.g.dim; ++a) fx[e] = std::max(fx[e], fext(v.g, a, e));
+        }
+    }
+    const MG& m = c->visc;
+    std::vector<RFace> rf((size_t)std::max(m.nlev - 1, 1) * nb);
+    c->rfx.assign(m.nlev, {1, 1, 1});
+    for (int l = 1; l < m.nlev; ++l)
+        for (int b = 0; b < nb; ++b) {
+            RFace& R = rf[(size_t)(l - 1) * nb + b];
+            memset(&R, 0, sizeof(R));
+            if (m.nlevc[b] <= l) continue;
+            R.gf = m.L[l - 1].hg[b];
+            R.gc = m.L[l].hg[b];
+            R.bf = m.L[l - 1].beta + m.L[l - 1].hof[b];
+            R.bc = m.L[l].beta + m.L[l].hof[b];
+            for (int e = 0; e < 3; ++e)
+                for (int a = 0; a < R.gc.dim; ++a) c->rfx[l][e] = std::max(c->rfx[l][e], fext(R.gc, a, e));
+        }
+    int dev = 0, zmax = 65535;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&zmax, hipDeviceAttributeMaxGridDimZ, dev);
+    const long zneed = (long)nb * std::max({(long)cx[2], (long)nx[2], 3L * fx[2], 2L * c->dim});
+    if (zneed > zmax) return HB_ERR_ARG;
+    memcpy(c->cx, cx, sizeof(cx));
+    memcpy(c->fx, fx, sizeof(fx));
+    memcpy(c->nx, nx, sizeof(nx));
+    if (dalloc(&c->ck, nb) != hipSuccess || upload(c->ck, ck) != hipSuccess) return HB_ERR_OOM;
+    if (dalloc(&c->rface, (long)rf.size()) != hipSuccess || upload(c->rface, rf) != hipSuccess) return HB_ERR_OOM;
+    if (dalloc(&c->cio, nb) != hipSuccess) return HB_ERR_OOM;
+    if (hipHostMalloc((void**)&c->hio, sizeof(CavIO) * 2 * nb, 0) != hipSuccess) {
+        c->hio = nullptr;
+        return HB_ERR_OOM;
+    }
+    memset(c->hio, 0, sizeof(CavIO) * 2 * nb);
+    return HB_OK;
+}
+
 static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, const hb_step_opts* opts,
                       void* hip_stream, Ctx** out)
 {
@@ -1374,6 +1452,11 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         if (dalloc(&m.dd, count) != hipSuccess || upload(m.dd, dd) != hipSuccess)
             return give_up(HB_ERR_OOM, "device allocation failed");
     }
+    {
+        const int rc2 = build_stage_tables(c);
+        if (rc2 != HB_OK) return give_up(rc2, rc2 == HB_ERR_OOM ? "device allocation failed"
+                                                               : "batch too large for the stage launch grid");
+    }
     autotune(c);
     if (hipStreamSynchronize(c->s) != hipSuccess) return give_up(HB_ERR_DEVICE, "stream synchronisation failed during set-up");
     *out = c;
@@ -1388,6 +1471,10 @@ static void destroy_ctx(Ctx* c)
     if (c->s2) (void)hipStreamSynchronize(c->s2);
     if (c->s) (void)hipStreamSynchronize(c->s);
     kt_free(c);
+    (void)hipFree(c->ck);
+    (void)hipFree(c->cio);
+    (void)hipFree(c->rface);
+    if (c->hio) (void)hipHostFree(c->hio);
     free_mg(c->visc);
     free_mg(c->mac);
     free_mg(c->nodal);
@@ -1515,9 +1602,14 @@ int hb_mg_solve(hb_ctx* ctx, int op, const double* eta, double dt, const double*
     MG& m = op == HB_OP_VISC ? c->visc : (op == HB_OP_MAC ? c->mac : c->nodal);
     StreamGuard guard(c);
     if (op == HB_OP_VISC) {
-        visc_setup(c, 0, eta, dt);
+        std::vector<CavIO> io(1, io_zero());
+        io[0].eta = eta;
+        io[0].vdt = dt;
+        io[0].b = const_cast<double*>(rhs);   // read only (the wall terms' base)
+        set_io(c, io);
+        visc_setup(c);
         factor_visc_async(c);
-        launch_visc_wall_rhs(c, c->cv[0].g, m.L[0].beta, dt, rhs, m.lvl0_b);
+        stage_visc_wall_rhs(c);
     } else {
         copy(c, m.lvl0_b, rhs, m.L[0].nu);
     }
@@ -1539,10 +1631,19 @@ int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta, 
     if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
     StreamGuard guard(c);
     Cav& v = c->cv[0];
-    red_maxabs(c, 0, u, v.dim * v.nc, S_MAXU);
-    visc_setup(c, 0, eta, dt);
-    advect_predict(c, 0, u, p, dt);
-    advect_finish(c, {u}, {dt}, {b}, {conv}, nullptr);
+    std::vector<CavIO> io(1, io_zero());
+    io[0].u = u;
+    io[0].p = const_cast<double*>(p);   // read only here
+    io[0].eta = eta;
+    io[0].b = b;
+    io[0].conv = conv;
+    io[0].dt = dt;
+    io[0].vdt = dt;
+    set_io(c, io);
+    stage_maxabs(c, SF_U, S_MAXU);
+    visc_setup(c);
+    advect_predict(c);
+    advect_finish(c, nullptr);
     if (umac) copy(c, umac, v.umac, v.nf);
     fetch_slots(c);
     std::vector<hb_mg_report> mrep(1);
@@ -1560,7 +1661,13 @@ int hb_project(hb_ctx* ctx, const double* ustar, double* p, double dt, double* u
     if (!ustar || !p || !u) return fail(c, HB_ERR_ARG, "null array");
     if (!(dt > 0.0)) return fail(c, HB_ERR_ARG, "dt must be positive");
     StreamGuard guard(c);
-    project_all(c, {ustar}, {p}, {dt}, {u});
+    std::vector<CavIO> io(1, io_zero());
+    io[0].ustar = ustar;
+    io[0].p = p;
+    io[0].uout = u;
+    io[0].dt = dt;
+    set_io(c, io);
+    project_all(c);
     fetch_slots(c);
     std::vector<hb_mg_report> rep(1);
     const int rc = solve_outcome(c, c->nodal, &rep);

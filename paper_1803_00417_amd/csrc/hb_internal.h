@@ -11,6 +11,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "../../include/hb.h"
@@ -282,6 +283,44 @@ struct Cav {
     double *macphi = nullptr, *ustar = nullptr, *phi = nullptr;
 };
 
+// Per-cavity arguments of the step's stage kernels (viscosity, face
+// coefficients, Godunov prediction, MAC correction, projection right-hand
+// side and update), one entry per cavity in a device table built at context
+// creation: each stage kernel runs over all cavities in one launch, block z
+// = (cavity, axis for face loops, z plane).
+struct CavK {
+    GridD g;
+    FluidD fl;
+    double ulid;
+    long nc, nf, nn;
+    double* sc;   // the cavity's scalar slots
+    double *eta, *E, *Gp, *F, *S, *trans, *uhat, *qhat, *qLf, *qRf, *uadv, *umac, *macrhs, *rnode, *rhs, *ustar, *phi;
+    double* macphi;             // MAC potential (view into the MAC arena)
+    double *beta0, *etae;       // level-0 face viscosities and eta/Re (viscous arenas)
+    double *macb, *nodb, *viscb;   // level-0 right-hand sides of the MAC, nodal and viscous problems
+};
+
+// Per-call arrays and scalars of each cavity, uploaded once per call
+struct CavIO {
+    const double* u;       // velocity: viscosity and advection input
+    double* p;             // pressure (the projection overwrites it)
+    const double* eta;     // viscosity the face coefficients come from
+    double* b;             // advection output; the viscous solve's right-hand side
+    double* conv;          // optional convective term
+    const double* ustar;   // projection input
+    double* uout;          // projection output
+    double dt;             // time step
+    double vdt;            // the viscous operator's coefficient (2 theta dt)
+};
+
+// one cavity's face-viscosity restriction from level l - 1 to level l
+// (gc.dim == 0: the cavity has no level l)
+struct RFace {
+    GridD gf, gc;
+    const double* bf;
+    double* bc;
+};
+
 // HIP-event timing of every launch of one kernel (measurement support)
 struct KTimer {
     bool on = false;
@@ -305,6 +344,17 @@ struct Ctx {
     hipStream_t s2 = nullptr;
     hipEvent_t ev_f0 = nullptr, ev_f1 = nullptr;
     bool visc_factor_pending = false;
+    // stage-kernel tables: per cavity (constant), per call (uploaded from the
+    // pinned staging buffer hio, two halves used in turn), the face-viscosity
+    // restrictions per level, and the largest cell, face and node extents over
+    // the cavities (the launch grids)
+    CavK* ck = nullptr;
+    CavIO* cio = nullptr;
+    CavIO* hio = nullptr;
+    int io_half = 0;
+    RFace* rface = nullptr;   // [level - 1][cavity]
+    std::vector<std::array<int, 3>> rfx;   // per level: largest coarse face extents
+    int cx[3] = {1, 1, 1}, fx[3] = {1, 1, 1}, nx[3] = {1, 1, 1};
     int nb = 1;                   // cavities
     int dim = 2;                  // common dimension
     std::vector<Cav> cv;
@@ -455,13 +505,8 @@ void bicg_x_dev(Ctx* c, const SegV& s, double* x, const double* ph, const double
 
 // ---- viscosity and tensor operator, per cavity (hb_visc.hip) ----------------
 void launch_viscosity(Ctx* c, const Cav& v, const double* u, double* eta);
-void launch_eta_faces(Ctx* c, const Cav& v, const GridD& g, const double* eta, double* beta);
-void launch_restrict_faces(Ctx* c, const GridD& gf, const GridD& gc, const double* bf, double* bc);
-void launch_visc_div(Ctx* c, const GridD& g, const double* beta, const double* u, double* out);
-void launch_visc_wall_rhs(Ctx* c, const GridD& g, const double* beta, double dt, const double* rhs, double* out);
 void launch_visc_dense(Ctx* c, const GridD& g, const double* beta, double dt, int N, const double* E, double* A);
 void launch_visc_dense_batch(Ctx* c, const MG& m);
-void launch_eta_over_re(Ctx* c, const Cav& v, const double* eta, double* etae);
 
 // ---- LDS-tiled tensor kernels, batched (hb_tile.hip) ------------------------
 // R = storage and arithmetic precision of the cycle; fine = coef is eta/Re
@@ -585,17 +630,27 @@ void launch_cell_to_node(Ctx* c, const GridD& g, const float* v, double* out);
 void launch_axpy(Ctx* c, double* y, const double* x, const double* a, double s, long n);   // y = x + s a
 
 // ---- step stages, per cavity (hb_step.hip) ----------------------------------
-void launch_grad_node(Ctx* c, const Cav& v, const double* p, double* Gp);
-void launch_forcing(Ctx* c, const Cav& v);
-void launch_slopes(Ctx* c, const Cav& v, const double* u);
-void launch_trace_normal(Ctx* c, const Cav& v, const double* u, double dt);
-void launch_transverse(Ctx* c, const Cav& v);
-void launch_trace_full(Ctx* c, const Cav& v, const double* u, double dt);
-void launch_mac_div(Ctx* c, const Cav& v, const double* faces, double* out);
-void launch_mac_update(Ctx* c, const Cav& v);
-void launch_advect_rhs(Ctx* c, const Cav& v, const double* u, double dt, double* b, double* conv);
-void launch_proj_rhs(Ctx* c, const Cav& v, const double* ustar, double dt, double* r);
-void launch_weak_div(Ctx* c, const Cav& v, const double* V, double* r);
-void launch_proj_update(Ctx* c, const Cav& v, const double* ustar, const double* phi, double dt, double* u);
+// stage kernels over every cavity (tables c->ck and c->cio)
+void stage_grad_node(Ctx* c);                 // Gp = G p
+void stage_forcing(Ctx* c);
+void stage_slopes(Ctx* c);
+void stage_trace_normal(Ctx* c);
+void stage_transverse(Ctx* c);
+void stage_trace_full(Ctx* c);
+void stage_mac_div(Ctx* c, int after);        // after: div of u^MAC into macrhs, else of u^adv into the MAC rhs
+void stage_mac_update(Ctx* c);
+void stage_advect_rhs(Ctx* c);
+void stage_proj_rhs(Ctx* c);
+void stage_weak_div_u(Ctx* c);                // rnode = weak div of uout
+void stage_proj_update(Ctx* c);
+void stage_viscosity(Ctx* c);                 // eta = eta(u)
+void stage_visc_coef(Ctx* c);                 // eta/Re, level-0 faces, coefficient slot
+void stage_restrict_faces(Ctx* c, int level);
+void stage_visc_div(Ctx* c);                  // E = div(eta_e gamma_dot(u)) with the cavity's faces
+void stage_visc_wall_rhs(Ctx* c);             // viscous level-0 rhs = b + wall terms
+// field selectors of the stage copies and max-norms
+enum StageField { SF_U, SF_P, SF_UOUT, SF_RNODE, SF_MACRHS, SF_USTAR, SF_PHI };
+void stage_copy(Ctx* c, int dst, int src);    // SF_USTAR <- SF_U, SF_PHI <- SF_P, SF_P <- SF_PHI
+void stage_maxabs(Ctx* c, int field, int slot);
 
 }  // namespace hb

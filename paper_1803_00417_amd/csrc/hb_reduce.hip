@@ -347,6 +347,69 @@ void flush_max_final(Ctx* c)
     k_max_final<<<c->nb, kT, 0, c->s>>>(c->mf_act, c->mpart, c->sc, slot);
 }
 
+// ---- stage fields of every cavity (tables c->ck, c->cio) ----------------------
+
+// a stage field of one cavity and its length
+__device__ inline const double* stage_field(const CavK& K, const CavIO& IO, int f, long& n)
+{
+    const long nv = (long)K.g.dim * K.nc;
+    switch (f) {
+    case SF_U: n = nv; return IO.u;
+    case SF_P: n = K.nn; return IO.p;
+    case SF_UOUT: n = nv; return IO.uout;
+    case SF_RNODE: n = K.nn; return K.rnode;
+    case SF_MACRHS: n = K.nc; return K.macrhs;
+    case SF_USTAR: n = nv; return K.ustar;
+    default: n = K.nn; return K.phi;
+    }
+}
+
+// dst <- src of every cavity (block y = cavity)
+__global__ void k_stage_copy(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int dst, int src)
+{
+    const CavK& K = ck[blockIdx.y];
+    const CavIO& IO = io[blockIdx.y];
+    long n, m;
+    double* d = const_cast<double*>(stage_field(K, IO, dst, n));
+    const double* s = stage_field(K, IO, src, m);
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+static long stage_longest(const Ctx* c)
+{
+    long mx = 1;
+    for (const Cav& v : c->cv) mx = std::max(mx, std::max((long)v.dim * v.nc, v.nn));
+    return mx;
+}
+
+void stage_copy(Ctx* c, int dst, int src)
+{
+    k_stage_copy<<<dim3(blocks_for(stage_longest(c), 8192), c->nb), kT, 0, c->s>>>(c->ck, c->cio, dst, src);
+}
+
+// max |field| of every cavity into its slot (the slot zeroed first); the
+// same fixed block count per cavity as the single-array reduction
+__global__ void k_stage_maxabs(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int f, int slot)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    const CavK& K = ck[blockIdx.y];
+    long n;
+    const double* v = stage_field(K, io[blockIdx.y], f, n);
+    unsigned long long m = 0ull;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const unsigned long long b = abits(v[i]);
+        m = b > m ? b : m;
+    }
+    m = block_umax(m, sh);
+    if (threadIdx.x == 0) atomic_max_bits(K.sc + slot, m);
+}
+
+void stage_maxabs(Ctx* c, int field, int slot)
+{
+    seg_set_zero(c, slot);
+    k_stage_maxabs<<<dim3(blocks_for(stage_longest(c), kRedBlocks), c->nb), kT, 0, c->s>>>(c->ck, c->cio, field, slot);
+}
+
 // ---- segmented over the batch -------------------------------------------------
 
 // this block's cavity segment; the block returns when the cavity is inactive

@@ -78,51 +78,95 @@ __device__ inline double grad_node_at(const GridD& g, const double* __restrict__
     return s / (double)(nc / 2);
 }
 
-__global__ void k_grad_node(GridD g, const double* __restrict__ p, double* __restrict__ Gp)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Every stage kernel below runs over all cavities of the context in one
+// launch.  Cell and node loops: block z = cavity * planes + z plane; face
+// loops: block z = (cavity * 3 + axis) * planes + z plane.  A block whose
+// indices fall outside its cavity's extents returns.
+#define STAGE_ENTER(zb)                                                   \
+    const int cav = blockIdx.z / (zb), k = blockIdx.z - cav * (zb);       \
+    const CavK& K = ck[cav];                                               \
+    const CavIO& IO = io[cav];                                             \
+    (void)IO;                                                              \
+    const GridD& g = K.g;                                                  \
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;                   \
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
+
+#define STAGE_CELL(zb)                                                    \
+    STAGE_ENTER(zb)                                                        \
+    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return;
+
+#define STAGE_NODE(zb)                                                    \
+    STAGE_ENTER(zb)                                                        \
+    if (i >= nnode(g, 0) || j >= nnode(g, 1) || k >= nnode(g, 2)) return;
+
+#define STAGE_FACE(zb)                                                    \
+    const int zz_ = blockIdx.z / (zb), k = blockIdx.z - zz_ * (zb);       \
+    const int cav = zz_ / 3, a = zz_ - 3 * cav;                            \
+    const CavK& K = ck[cav];                                               \
+    const CavIO& IO = io[cav];                                             \
+    (void)IO;                                                              \
+    const GridD& g = K.g;                                                  \
+    if (a >= g.dim) return;                                                \
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;                   \
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;                   \
+    if (i >= fext(g, a, 0) || j >= fext(g, a, 1) || k >= fext(g, a, 2)) return;
+
+#define STAGE_ARGS const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb
+
+static dim3 cell_grid(const Ctx* c) { return dim3((c->cx[0] + kBlk.x - 1) / kBlk.x, (c->cx[1] + kBlk.y - 1) / kBlk.y, c->cx[2] * c->nb); }
+static dim3 node_grid(const Ctx* c) { return dim3((c->nx[0] + kBlk.x - 1) / kBlk.x, (c->nx[1] + kBlk.y - 1) / kBlk.y, c->nx[2] * c->nb); }
+static dim3 face_grid(const Ctx* c) { return dim3((c->fx[0] + kBlk.x - 1) / kBlk.x, (c->fx[1] + kBlk.y - 1) / kBlk.y, c->fx[2] * 3 * c->nb); }
+
+// Gp = G p, the cell average of the Q1 gradient of the pressure
+// (the bodies take the cavity's arrays as restrict-qualified arguments: the
+// table they come from says nothing about aliasing)
+__device__ __forceinline__ void grad_node_body(const GridD& g, const double* __restrict__ p, double* __restrict__ Gp,
+                                               int i, int j, int k)
+{
     const long N = ncells(g), q = cid(g, i, j, k);
     for (int a = 0; a < g.dim; ++a) Gp[a * N + q] = grad_node_at(g, p, a, i, j, k);
 }
 
-void launch_grad_node(Ctx* c, const Cav& v, const double* p, double* Gp)
+__global__ void k_grad_node(STAGE_ARGS)
 {
-    k_grad_node<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, p, Gp);
+    STAGE_CELL(zb);
+    grad_node_body(g, IO.p, K.Gp, i, j, k);
 }
+
+void stage_grad_node(Ctx* c) { k_grad_node<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
 
 // F = -G p + wF E + f, the forcing of the Taylor prediction: wF = 2 puts
 // the whole explicit stress divergence in (as eq:iamr:extrap prints it),
 // wF = 0 leaves it out
-__global__ void k_forcing(long n, int dim, double wF, double f0, double f1, double f2, const double* __restrict__ Gp,
-                          const double* __restrict__ E, double* __restrict__ F)
+__device__ __forceinline__ void forcing_body(const GridD& g, const FluidD& fl, double wF, const double* __restrict__ Gp,
+                                             const double* __restrict__ E, double* __restrict__ F, int i, int j, int k)
 {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * dim) return;
-    const int c = (int)(t / n);
-    const double f = c == 0 ? f0 : (c == 1 ? f1 : f2);
-    F[t] = -Gp[t] + wF * E[t] + f;
+    const long N = ncells(g), q0 = cid(g, i, j, k);
+    for (int c = 0; c < g.dim; ++c) {
+        const long t = c * N + q0;
+        F[t] = -Gp[t] + wF * E[t] + fl.f[c];
+    }
 }
 
-void launch_forcing(Ctx* c, const Cav& v)
+__global__ void k_forcing(STAGE_ARGS, double wF)
 {
-    const long n = v.nc * v.dim;
+    STAGE_CELL(zb);
+    forcing_body(g, K.fl, wF, K.Gp, K.E, K.F, i, j, k);
+}
+
+void stage_forcing(Ctx* c)
+{
     const double wF = c->opts.pred_visc ? 2.0 : 0.0;
-    k_forcing<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(v.nc, v.dim, wF, v.fl.f[0], v.fl.f[1], v.fl.f[2], v.Gp, v.E, v.F);
+    k_forcing<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], wF);
 }
 
 // ---------------------------------------------------------------------------
 // Godunov prediction
 // ---------------------------------------------------------------------------
 
-__global__ void k_slopes(GridD g, const double* __restrict__ u, double* __restrict__ S)
+__device__ __forceinline__ void slopes_body(const GridD& g, const double* __restrict__ u, double* __restrict__ S,
+                                            int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
     const long N = ncells(g), q0 = cid(g, i, j, k);
     const int d = g.dim;
     for (int a = 0; a < d; ++a)
@@ -137,20 +181,20 @@ __global__ void k_slopes(GridD g, const double* __restrict__ u, double* __restri
         }
 }
 
-void launch_slopes(Ctx* c, const Cav& v, const double* u)
+__global__ void k_slopes(STAGE_ARGS)
 {
-    k_slopes<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, u, v.S);
+    STAGE_CELL(zb);
+    slopes_body(g, IO.u, K.S, i, j, k);
 }
 
+void stage_slopes(Ctx* c) { k_slopes<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+
 // normal-only traced states on a-faces, upwinded by their Burgers solution
-__global__ void k_trace_normal(GridD g, int a, double dt, double ulid, const double* __restrict__ sc,
-                               const double* __restrict__ u, const double* __restrict__ S, long nf,
-                               double* __restrict__ uhat, double* __restrict__ qhat)
+__device__ __forceinline__ void trace_normal_body(const GridD& g, int a, double dt, double delta, long nf,
+                                                  const double* __restrict__ u, const double* __restrict__ S,
+                                                  double* __restrict__ uhat, double* __restrict__ qhat, int i, int j,
+                                                  int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= fext(g, a, 0) || j >= fext(g, a, 1)) return;
     const int d = g.dim;
     const long N = ncells(g);
     const long f = foffset(g, a) + fid(g, a, i, j, k);
@@ -164,7 +208,6 @@ __global__ void k_trace_normal(GridD g, int a, double dt, double ulid, const dou
         return;
     }
     const long cL = cid(g, L[0], L[1], L[2]), cR = cid(g, R[0], R[1], R[2]);
-    const double delta = deadband(sc, ulid);
     double qL[3], qR[3];
     for (int q = 0; q < d; ++q) {
         qL[q] = u[q * N + cL] + (0.5 - dt * u[a * N + cL] / (2.0 * g.h)) * S[((long)a * d + q) * N + cL];
@@ -175,22 +218,19 @@ __global__ void k_trace_normal(GridD g, int a, double dt, double ulid, const dou
     for (int q = 0; q < d; ++q) qhat[q * nf + f] = (q == a) ? uh : upwind(uh, qL[q], qR[q], delta);
 }
 
-void launch_trace_normal(Ctx* c, const Cav& v, const double* u, double dt)
+__global__ void k_trace_normal(STAGE_ARGS)
 {
-    const GridD& g = v.g;
-    for (int a = 0; a < g.dim; ++a)
-        k_trace_normal<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(
-            g, a, dt, v.ulid, v.sc, u, v.S, v.nf, v.uhat, v.qhat);
+    STAGE_FACE(zb);
+    trace_normal_body(g, a, IO.dt, deadband(K.sc, K.ulid), K.nf, IO.u, K.S, K.uhat, K.qhat, i, j, k);
 }
 
+void stage_trace_normal(Ctx* c) { k_trace_normal<<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]); }
+
 // transverse terms at cells: (u_b dq/dx_b)^ = mean face velocity x difference
-__global__ void k_transverse(GridD g, long nf, const double* __restrict__ uhat, const double* __restrict__ qhat,
-                             double* __restrict__ T)
+__device__ __forceinline__ void transverse_body(const GridD& g, long nf, const double* __restrict__ uhat,
+                                                const double* __restrict__ qhat, double* __restrict__ T, int i, int j,
+                                                int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
     const int d = g.dim;
     const long N = ncells(g), q0 = cid(g, i, j, k);
     for (int b = 0; b < d; ++b) {
@@ -207,22 +247,22 @@ __global__ void k_transverse(GridD g, long nf, const double* __restrict__ uhat, 
     }
 }
 
-void launch_transverse(Ctx* c, const Cav& v)
+__global__ void k_transverse(STAGE_ARGS)
 {
-    k_transverse<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, v.nf, v.uhat, v.qhat, v.trans);
+    STAGE_CELL(zb);
+    transverse_body(g, K.nf, K.uhat, K.qhat, K.trans, i, j, k);
 }
+
+void stage_transverse(Ctx* c) { k_transverse<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
 
 // full face states: traced normal part - dt/2 transverse terms + dt/2 forcing;
 // the advection velocity is the Burgers solution of the normal component
-__global__ void k_trace_full(GridD g, int a, double dt, double ulid, const double* __restrict__ sc,
-                             const double* __restrict__ u, const double* __restrict__ S,
-                             const double* __restrict__ T, const double* __restrict__ F, long nf,
-                             double* __restrict__ qLf, double* __restrict__ qRf, double* __restrict__ uadv)
+__device__ __forceinline__ void trace_full_body(const GridD& g, int a, double dt, double delta, long nf,
+                                                const double* __restrict__ u, const double* __restrict__ S,
+                                                const double* __restrict__ T, const double* __restrict__ F,
+                                                double* __restrict__ qLf, double* __restrict__ qRf,
+                                                double* __restrict__ uadv, int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= fext(g, a, 0) || j >= fext(g, a, 1)) return;
     const int d = g.dim;
     const long N = ncells(g);
     const long f = foffset(g, a) + fid(g, a, i, j, k);
@@ -253,27 +293,26 @@ __global__ void k_trace_full(GridD g, int a, double dt, double ulid, const doubl
         qLf[q * nf + f] = vl;
         qRf[q * nf + f] = vr;
     }
-    uadv[f] = burgers(qLf[a * nf + f], qRf[a * nf + f], deadband(sc, ulid));
+    uadv[f] = burgers(qLf[a * nf + f], qRf[a * nf + f], delta);
 }
 
-void launch_trace_full(Ctx* c, const Cav& v, const double* u, double dt)
+__global__ void k_trace_full(STAGE_ARGS)
 {
-    const GridD& g = v.g;
-    for (int a = 0; a < g.dim; ++a)
-        k_trace_full<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(
-            g, a, dt, v.ulid, v.sc, u, v.S, v.trans, v.F, v.nf, v.qLf, v.qRf, v.uadv);
+    STAGE_FACE(zb);
+    trace_full_body(g, a, IO.dt, deadband(K.sc, K.ulid), K.nf, IO.u, K.S, K.trans, K.F, K.qLf, K.qRf, K.uadv, i, j, k);
 }
+
+void stage_trace_full(Ctx* c) { k_trace_full<<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]); }
 
 // ---------------------------------------------------------------------------
 // MAC projection of the advection velocity
 // ---------------------------------------------------------------------------
 
-__global__ void k_mac_div(GridD g, const double* __restrict__ F, double* __restrict__ out)
+// cell divergence of a face field: of u^adv into the MAC right-hand side
+// (after = 0), or of u^MAC into macrhs (after = 1)
+__device__ __forceinline__ void mac_div_body(const GridD& g, const double* __restrict__ F, double* __restrict__ out,
+                                             int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
     double s = 0.0;
     for (int a = 0; a < g.dim; ++a) {
         int hi[3] = {i, j, k};
@@ -285,19 +324,19 @@ __global__ void k_mac_div(GridD g, const double* __restrict__ F, double* __restr
     out[cid(g, i, j, k)] = s;
 }
 
-void launch_mac_div(Ctx* c, const Cav& v, const double* faces, double* out)
+__global__ void k_mac_div(STAGE_ARGS, int after)
 {
-    k_mac_div<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, faces, out);
+    STAGE_CELL(zb);
+    mac_div_body(g, after ? K.umac : K.uadv, after ? K.macrhs : K.macb, i, j, k);
 }
 
+void stage_mac_div(Ctx* c, int after) { k_mac_div<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], after); }
+
 // u^MAC = u^adv - G_mac phi (the gradient vanishes on wall faces)
-__global__ void k_mac_update(GridD g, int a, const double* __restrict__ uadv, const double* __restrict__ phi,
-                             double* __restrict__ umac)
+__device__ __forceinline__ void mac_update_body(const GridD& g, int a, const double* __restrict__ uadv,
+                                                const double* __restrict__ phi, double* __restrict__ umac, int i, int j,
+                                                int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= fext(g, a, 0) || j >= fext(g, a, 1)) return;
     const long f = foffset(g, a) + fid(g, a, i, j, k);
     int R[3] = {i, j, k}, L[3] = {i, j, k};
     L[a] -= 1;
@@ -306,29 +345,25 @@ __global__ void k_mac_update(GridD g, int a, const double* __restrict__ uadv, co
     umac[f] = uadv[f] - gphi;
 }
 
-void launch_mac_update(Ctx* c, const Cav& v)
+__global__ void k_mac_update(STAGE_ARGS)
 {
-    const GridD& g = v.g;
-    for (int a = 0; a < g.dim; ++a)
-        k_mac_update<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(g, a, v.uadv, v.macphi, v.umac);
+    STAGE_FACE(zb);
+    mac_update_body(g, a, K.uadv, K.macphi, K.umac, i, j, k);
 }
+
+void stage_mac_update(Ctx* c) { k_mac_update<<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]); }
 
 // convective term A = sum_a mean(u^MAC_a) (q~_hi - q~_lo)/h with the full
 // states upwinded by u^MAC, and b = u - dt A + dt (-G p + wb E + f) with
 // wb = 2 (1 - theta) (1 for Crank-Nicolson)
-__global__ void k_advect_rhs(GridD g, double dt, double wb, double ulid, double f0, double f1, double f2,
-                             const double* __restrict__ sc, const double* __restrict__ u,
-                             const double* __restrict__ umac, const double* __restrict__ qLf,
-                             const double* __restrict__ qRf, const double* __restrict__ Gp,
-                             const double* __restrict__ E, long nf, double* __restrict__ b, double* __restrict__ conv)
+__device__ __forceinline__ void advect_rhs_body(const GridD& g, const FluidD& fl, double dt, double wb, double delta,
+                                                long nf, const double* __restrict__ u, const double* __restrict__ umac,
+                                                const double* __restrict__ qLf, const double* __restrict__ qRf,
+                                                const double* __restrict__ Gp, const double* __restrict__ E,
+                                                double* __restrict__ b, double* __restrict__ conv, int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
     const int d = g.dim;
     const long N = ncells(g), q0 = cid(g, i, j, k);
-    const double delta = deadband(sc, ulid);
     double A[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < d; ++a) {
         int hi[3] = {i, j, k};
@@ -345,17 +380,21 @@ __global__ void k_advect_rhs(GridD g, double dt, double wb, double ulid, double 
     }
     for (int q = 0; q < d; ++q) {
         const long e = q * N + q0;
-        const double f = q == 0 ? f0 : (q == 1 ? f1 : f2);
-        b[e] = u[e] - dt * A[q] + dt * (-Gp[e] + wb * E[e] + f);
+        b[e] = u[e] - dt * A[q] + dt * (-Gp[e] + wb * E[e] + fl.f[q]);
         if (conv) conv[e] = A[q];
     }
 }
 
-void launch_advect_rhs(Ctx* c, const Cav& v, const double* u, double dt, double* b, double* conv)
+__global__ void k_advect_rhs(STAGE_ARGS, double wb)
 {
-    k_advect_rhs<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(
-        v.g, dt, 2.0 * (1.0 - c->opts.theta), v.ulid, v.fl.f[0], v.fl.f[1], v.fl.f[2], v.sc, u, v.umac, v.qLf, v.qRf,
-        v.Gp, v.E, v.nf, b, conv);
+    STAGE_CELL(zb);
+    advect_rhs_body(g, K.fl, IO.dt, wb, deadband(K.sc, K.ulid), K.nf, IO.u, K.umac, K.qLf, K.qRf, K.Gp, K.E, IO.b,
+                    IO.conv, i, j, k);
+}
+
+void stage_advect_rhs(Ctx* c)
+{
+    k_advect_rhs<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], 2.0 * (1.0 - c->opts.theta));
 }
 
 // ---------------------------------------------------------------------------
@@ -363,15 +402,13 @@ void launch_advect_rhs(Ctx* c, const Cav& v, const double* u, double dt, double*
 // ---------------------------------------------------------------------------
 
 // r_k = sum over cells touching node k of sum_a s_a (h/2)^(d-1) V_a, where
-// V = ustar/dt + G p (or V itself when dt == 0 and Gp == nullptr)
+// V = ustar/dt + G p into the nodal right-hand side (PROJ), or V = uout into
+// rnode
 template <bool PROJ>
-__global__ void k_weak_div(GridD g, double dt, const double* __restrict__ V, const double* __restrict__ Gp,
-                           double* __restrict__ r)
+__device__ __forceinline__ void weak_div_body(const GridD& g, double dt, const double* __restrict__ V,
+                                              const double* __restrict__ Gp, double* __restrict__ r, int i, int j,
+                                              int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= nnode(g, 0) || j >= nnode(g, 1)) return;
     const int d = g.dim;
     const long N = ncells(g);
     const double w = d == 2 ? 0.5 * g.h : (0.5 * g.h) * (0.5 * g.h);
@@ -399,26 +436,21 @@ __global__ void k_weak_div(GridD g, double dt, const double* __restrict__ V, con
     r[nid(g, i, j, k)] = s;
 }
 
-void launch_proj_rhs(Ctx* c, const Cav& v, const double* ustar, double dt, double* r)
+template <bool PROJ>
+__global__ void k_weak_div(STAGE_ARGS)
 {
-    const GridD& g = v.g;
-    k_weak_div<true><<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, dt, ustar, v.Gp, r);
+    STAGE_NODE(zb);
+    weak_div_body<PROJ>(g, IO.dt, PROJ ? IO.ustar : IO.uout, K.Gp, PROJ ? K.nodb : K.rnode, i, j, k);
 }
 
-void launch_weak_div(Ctx* c, const Cav& v, const double* V, double* r)
-{
-    const GridD& g = v.g;
-    k_weak_div<false><<<grid3(nnode(g, 0), nnode(g, 1), nnode(g, 2), kBlk), kBlk, 0, c->s>>>(g, 0.0, V, nullptr, r);
-}
+void stage_proj_rhs(Ctx* c) { k_weak_div<true><<<node_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->nx[2]); }
+void stage_weak_div_u(Ctx* c) { k_weak_div<false><<<node_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->nx[2]); }
 
-// u = ustar + dt (G p - G phi)
-__global__ void k_proj_update(GridD g, double dt, const double* __restrict__ ustar, const double* __restrict__ Gp,
-                              const double* __restrict__ phi, double* __restrict__ u)
+// uout = ustar + dt (G p - G phi)
+__device__ __forceinline__ void proj_update_body(const GridD& g, double dt, const double* __restrict__ ustar,
+                                                 const double* __restrict__ Gp, const double* __restrict__ phi,
+                                                 double* __restrict__ u, int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
     const long N = ncells(g), q = cid(g, i, j, k);
     for (int a = 0; a < g.dim; ++a) {
         const double gphi = grad_node_at(g, phi, a, i, j, k);
@@ -426,9 +458,12 @@ __global__ void k_proj_update(GridD g, double dt, const double* __restrict__ ust
     }
 }
 
-void launch_proj_update(Ctx* c, const Cav& v, const double* ustar, const double* phi, double dt, double* u)
+__global__ void k_proj_update(STAGE_ARGS)
 {
-    k_proj_update<<<grid3(v.g.n[0], v.g.n[1], v.g.n[2], kBlk), kBlk, 0, c->s>>>(v.g, dt, ustar, v.Gp, phi, u);
+    STAGE_CELL(zb);
+    proj_update_body(g, IO.dt, IO.ustar, K.Gp, K.phi, IO.uout, i, j, k);
 }
+
+void stage_proj_update(Ctx* c) { k_proj_update<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
 
 }  // namespace hb

@@ -100,12 +100,11 @@ void launch_yield(Ctx* c, const Cav& v, const double* u, unsigned char* mask, do
 // face viscosity: fine faces from cells, coarse faces from fine faces
 // ---------------------------------------------------------------------------
 
-__global__ void k_eta_faces(GridD g, int a, double Re, const double* __restrict__ eta, double* __restrict__ beta)
+// face (i, j, k) of axis a: the mean of eta/Re of its two cells, or of the
+// interior cell on a wall face
+__device__ __forceinline__ void face_eta(const GridD& g, int a, double Re, const double* __restrict__ eta,
+                                double* __restrict__ beta, int i, int j, int k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= fext(g, a, 0) || j >= fext(g, a, 1)) return;
     int R[3] = {i, j, k}, L[3] = {i, j, k};
     L[a] -= 1;
     const bool okL = wrap(g, L), okR = wrap(g, R);
@@ -119,19 +118,10 @@ __global__ void k_eta_faces(GridD g, int a, double Re, const double* __restrict_
     beta[foffset(g, a) + fid(g, a, i, j, k)] = v;
 }
 
-void launch_eta_faces(Ctx* c, const Cav& v, const GridD& g, const double* eta, double* beta)
+// coarse face (i, j, k) of axis a = mean of the 2^(d-1) fine faces tiling it
+__device__ __forceinline__ void restrict_face(const GridD& gf, const GridD& gc, int a, const double* __restrict__ bf,
+                                     double* __restrict__ bc, int i, int j, int k)
 {
-    for (int a = 0; a < g.dim; ++a)
-        k_eta_faces<<<grid3(fext(g, a, 0), fext(g, a, 1), fext(g, a, 2), kBlk), kBlk, 0, c->s>>>(g, a, v.fl.Re, eta, beta);
-}
-
-// coarse face = mean of the 2^(d-1) fine faces tiling it
-__global__ void k_restrict_faces(GridD gf, GridD gc, int a, const double* __restrict__ bf, double* __restrict__ bc)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= fext(gc, a, 0) || j >= fext(gc, a, 1)) return;
     const int I[3] = {i, j, k};
     const double* F = bf + foffset(gf, a);
     double s = 0.0;
@@ -146,45 +136,22 @@ __global__ void k_restrict_faces(GridD gf, GridD gc, int a, const double* __rest
     bc[foffset(gc, a) + fid(gc, a, i, j, k)] = s / (double)cnt;
 }
 
-void launch_restrict_faces(Ctx* c, const GridD& gf, const GridD& gc, const double* bf, double* bc)
-{
-    for (int a = 0; a < gf.dim; ++a)
-        k_restrict_faces<<<grid3(fext(gc, a, 0), fext(gc, a, 1), fext(gc, a, 2), kBlk), kBlk, 0, c->s>>>(gf, gc, a, bf, bc);
-}
-
 // ---------------------------------------------------------------------------
 // tensor flux and divergence
 // ---------------------------------------------------------------------------
-
-__global__ void k_visc_div(GridD g, const double* __restrict__ beta, const double* __restrict__ u, double* __restrict__ out)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.n[0] || j >= g.n[1]) return;
-    const long N = ncells(g), q = cid(g, i, j, k);
-    for (int c = 0; c < g.dim; ++c) out[c * N + q] = visc_div_at<false, false>(g, beta, u, c, i, j, k);
-}
-
-void launch_visc_div(Ctx* c, const GridD& g, const double* beta, const double* u, double* out)
-{
-    k_visc_div<<<grid3(g.n[0], g.n[1], g.n[2], kBlk), kBlk, 0, c->s>>>(g, beta, u, out);
-}
 
 // out = rhs + dt div(beta gamma_dot(0 with wall values)): the inhomogeneous
 // wall part of the operator moved to the right-hand side.  The stencil of a
 // cell reaches one cell along each axis, so only cells in the first layer
 // along a wall axis see a wall value; elsewhere the term is zero.  out = rhs
-// is copied first, then one thread per boundary-layer cell (block z = wall
-// face 2 a + side; a cell on several layers is taken by its lowest axis)
-// adds the wall term.
-__global__ void k_visc_wall_rhs(GridD g, const double* __restrict__ beta, double dt, const double* __restrict__ rhs,
-                                double* __restrict__ out)
+// is copied first, then one thread per boundary-layer cell of wall face
+// (a, side), at in-face position (u, w), adds the wall term (a cell on
+// several layers is taken by its lowest axis).
+__device__ __forceinline__ void visc_wall_at(const GridD& g, const double* __restrict__ beta, double dt,
+                                    const double* __restrict__ rhs, double* __restrict__ out, int a, int side, int u, int w)
 {
-    const int a = blockIdx.z >> 1, side = blockIdx.z & 1;
     if (a >= g.dim || g.per[a]) return;
     const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;
-    const int u = blockIdx.x * blockDim.x + threadIdx.x, w = blockIdx.y * blockDim.y + threadIdx.y;
     if (u >= g.n[b0] || w >= g.n[b1]) return;
     int p[3];
     p[a] = side ? g.n[a] - 1 : 0;
@@ -195,18 +162,6 @@ __global__ void k_visc_wall_rhs(GridD g, const double* __restrict__ beta, double
     const long N = ncells(g), q = cid(g, p[0], p[1], p[2]);
     for (int c = 0; c < g.dim; ++c)
         out[c * N + q] = rhs[c * N + q] + dt * visc_div_at<false, true>(g, beta, nullptr, c, p[0], p[1], p[2]);
-}
-
-void launch_visc_wall_rhs(Ctx* c, const GridD& g, const double* beta, double dt, const double* rhs, double* out)
-{
-    copy(c, out, rhs, (long)g.dim * ncells(g));
-    int e0 = 1, e1 = 1;
-    for (int a = 0; a < g.dim; ++a) {
-        const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;
-        e0 = e0 > g.n[b0] ? e0 : g.n[b0];
-        e1 = e1 > g.n[b1] ? e1 : g.n[b1];
-    }
-    k_visc_wall_rhs<<<grid3(e0, e1, 2 * g.dim, kBlk), kBlk, 0, c->s>>>(g, beta, dt, rhs, out);
 }
 
 // dense matrix of the homogeneous operator, column j = A e_j (E holds the
@@ -239,7 +194,7 @@ __global__ void k_visc_dense_batch(const DenseD* __restrict__ dd, const double* 
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     const int col = blockIdx.y;
     if (row >= d.N || col >= d.N) return;
-    const GridD g = d.g;
+    const GridD& g = d.g;
     const long Nc = ncells(g);
     const int c = (int)(row / Nc);
     const long q = row % Nc;
@@ -255,16 +210,143 @@ void launch_visc_dense_batch(Ctx* c, const MG& m)
     k_visc_dense_batch<<<dim3((n + 255) / 256, n, c->nb), 256, 0, c->s>>>(m.dd, c->sc, m.A);
 }
 
-__global__ void k_eta_over_re(long n, double Re, const double* __restrict__ eta, double* __restrict__ etae)
+// ---------------------------------------------------------------------------
+// the same stages over every cavity in one launch (tables c->ck, c->cio;
+// block z = cavity * planes + plane, face loops (cavity * 3 + axis) * planes
+// + plane)
+// ---------------------------------------------------------------------------
+
+static dim3 cells_of(const Ctx* c) { return dim3((c->cx[0] + kBlk.x - 1) / kBlk.x, (c->cx[1] + kBlk.y - 1) / kBlk.y, c->cx[2] * c->nb); }
+
+// eta = eta(u) of every cavity
+__global__ void k_stage_viscosity(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb)
 {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) etae[i] = eta[i] / Re;
+    const int cav = blockIdx.z / zb, k = blockIdx.z - cav * zb;
+    const CavK& K = ck[cav];
+    const GridD& g = K.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return;
+    K.eta[cid(g, i, j, k)] = eta_of_g(K.fl, strain_norm_at(g, io[cav].u, i, j, k));
 }
 
-void launch_eta_over_re(Ctx* c, const Cav& v, const double* eta, double* etae)
+void stage_viscosity(Ctx* c) { k_stage_viscosity<<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+
+// eta/Re at cells and the coefficient slot (the operator's 2 theta dt) of
+// every cavity
+__global__ void k_stage_eta_over_re(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb)
 {
-    const long n = v.nc;
-    k_eta_over_re<<<(unsigned)((n + 255) / 256), 256, 0, c->s>>>(n, v.fl.Re, eta, etae);
+    const int cav = blockIdx.z / zb, k = blockIdx.z - cav * zb;
+    const CavK& K = ck[cav];
+    const CavIO& IO = io[cav];
+    const GridD& g = K.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i == 0 && j == 0 && k == 0) K.sc[S_DT] = IO.vdt;
+    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return;
+    const long q = cid(g, i, j, k);
+    K.etae[q] = IO.eta[q] / K.fl.Re;
 }
+
+// level-0 face viscosities of every cavity
+__global__ void k_stage_eta_faces(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb)
+{
+    const int zz = blockIdx.z / zb, k = blockIdx.z - zz * zb;
+    const int cav = zz / 3, a = zz - 3 * cav;
+    const CavK& K = ck[cav];
+    const GridD& g = K.g;
+    if (a >= g.dim) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= fext(g, a, 0) || j >= fext(g, a, 1) || k >= fext(g, a, 2)) return;
+    face_eta(g, a, K.fl.Re, io[cav].eta, K.beta0, i, j, k);
+}
+
+void stage_visc_coef(Ctx* c)
+{
+    k_stage_eta_over_re<<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+    k_stage_eta_faces<<<dim3((c->fx[0] + kBlk.x - 1) / kBlk.x, (c->fx[1] + kBlk.y - 1) / kBlk.y, c->fx[2] * 3 * c->nb),
+                        kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+}
+
+// face viscosities of level l of every cavity from level l - 1 (entries with
+// gc.dim == 0: no such level)
+__global__ void k_stage_restrict_faces(const RFace* __restrict__ rf, int zb)
+{
+    const int zz = blockIdx.z / zb, k = blockIdx.z - zz * zb;
+    const int cav = zz / 3, a = zz - 3 * cav;
+    const RFace& R = rf[cav];
+    const GridD& gc = R.gc;
+    if (a >= gc.dim) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= fext(gc, a, 0) || j >= fext(gc, a, 1) || k >= fext(gc, a, 2)) return;
+    restrict_face(R.gf, gc, a, R.bf, R.bc, i, j, k);
+}
+
+void stage_restrict_faces(Ctx* c, int l)
+{
+    const int* e = c->rfx[l].data();
+    k_stage_restrict_faces<<<dim3((e[0] + kBlk.x - 1) / kBlk.x, (e[1] + kBlk.y - 1) / kBlk.y, e[2] * 3 * c->nb), kBlk, 0,
+                             c->s>>>(c->rface + (long)(l - 1) * c->nb, e[2]);
+}
+
+// E = div(eta_e gamma_dot(u)) of every cavity, level-0 faces (the body
+// takes the arrays restrict-qualified: the table says nothing about
+// aliasing)
+__device__ __forceinline__ void visc_div_body(const GridD& g, const double* __restrict__ beta,
+                                              const double* __restrict__ u, double* __restrict__ out, int i, int j,
+                                              int k)
+{
+    const long N = ncells(g), q = cid(g, i, j, k);
+    for (int c = 0; c < g.dim; ++c) out[c * N + q] = visc_div_at<false, false>(g, beta, u, c, i, j, k);
+}
+
+__global__ void k_stage_visc_div(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb)
+{
+    const int cav = blockIdx.z / zb, k = blockIdx.z - cav * zb;
+    const CavK& K = ck[cav];
+    const GridD& g = K.g;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return;
+    visc_div_body(g, K.beta0, io[cav].u, K.E, i, j, k);
+}
+
+void stage_visc_div(Ctx* c) { k_stage_visc_div<<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+
+// the viscous level-0 right-hand side of every cavity: b plus the wall part
+// of the operator (coefficient from the slot); block z = cavity * 2 dim +
+// wall face 2 a + side, after a copy of b
+__global__ void k_stage_visc_wall(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int nz)
+{
+    const int cav = blockIdx.z / nz, w2 = blockIdx.z - cav * nz;
+    const CavK& K = ck[cav];
+    const int a = w2 >> 1, side = w2 & 1;
+    visc_wall_at(K.g, K.beta0, K.sc[S_DT], io[cav].b, K.viscb, a, side, blockIdx.x * blockDim.x + threadIdx.x,
+                 blockIdx.y * blockDim.y + threadIdx.y);
+}
+
+__global__ void k_stage_copy_b(const CavK* __restrict__ ck, const CavIO* __restrict__ io)
+{
+    const CavK& K = ck[blockIdx.y];
+    const long n = (long)K.g.dim * K.nc;
+    const double* __restrict__ b = io[blockIdx.y].b;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) K.viscb[i] = b[i];
+}
+
+void stage_visc_wall_rhs(Ctx* c)
+{
+    long nmax = 1;
+    int e0 = 1, e1 = 1;
+    for (const Cav& v : c->cv) {
+        nmax = std::max(nmax, (long)v.dim * v.nc);
+        for (int a = 0; a < v.g.dim; ++a) {
+            const int b0 = a == 0 ? 1 : 0, b1 = a == 2 ? 1 : 2;
+            e0 = std::max(e0, v.g.n[b0]);
+            e1 = std::max(e1, v.g.n[b1]);
+        }
+    }
+    const long nblk = std::min((nmax + 255) / 256, 8192L);
+    k_stage_copy_b<<<dim3((unsigned)nblk, c->nb), 256, 0, c->s>>>(c->ck, c->cio);
+    k_stage_visc_wall<<<grid3(e0, e1, 2 * c->dim * c->nb, kBlk), kBlk, 0, c->s>>>(c->ck, c->cio, 2 * c->dim);
+}
+
+
 
 }  // namespace hb
