@@ -199,13 +199,20 @@ int hb_advect(hb_ctx* ctx, const double* u, const double* p, const double* eta,
               double dt, double* b, double* umac, double* conv,
               hb_mg_report* mac_report);
 
-/* Approximate projection: V = ustar/dt + G p; K phi = weak div V;
- * u = ustar + dt (G p - G phi); p = phi (mean zero).  ustar [dim][cells] in,
- * p nodes in/out, u [dim][cells] out (may alias ustar). */
+/* Approximate projection (Sec. III.A, the projection step and pressure
+ * update that close the algorithm): V = ustar/dt + G p; K phi = weak div V;
+ * u = ustar + dt (G p - G phi); p = phi (mean zero).  The printed velocity
+ * update has no + dt G p term, which would leave D u = -dt D G p; with it, u
+ * is dt times the projection of V.
+ * ustar [dim][cells] in, p nodes in/out, u [dim][cells] out (may alias
+ * ustar). */
 int hb_project(hb_ctx* ctx, const double* ustar, double* p, double dt, double* u,
                hb_mg_report* report);
 
-/* dt from the CFL condition: cfl h / max(max wall speed, max |u|). */
+/* dt from the CFL condition: cfl h / max(max wall speed, max |u|).  The
+ * paper fixes no time-step rule (it notes only that the step shrinks with
+ * the grid spacing, Sec. III.C, and times runs at constant dt, Sec. V);
+ * this advective CFL bound is the library's rule for dt <= 0. */
 int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -223,8 +230,10 @@ int hb_cfl_dt(hb_ctx* ctx, const double* u, double* dt_out);
  * scratch address cannot be taken or a launch fails. */
 int hb_cfl_dt_noalloc(const hb_grid* grid, double cfl, const double* u, double* dt_out, void* hip_stream);
 
-/* One full time step in place: u^m -> u^{m+1}, p^{m-1/2} -> p^{m+1/2}.
- * dt <= 0 selects the CFL time step.  report nullable. */
+/* One full time step of Sec. III.A in place: u^m -> u^{m+1},
+ * p^{m-1/2} -> p^{m+1/2} (viscosity, advection stage, coupled viscous
+ * solve, projection; the calls above in that order, on the library's own
+ * buffers).  dt <= 0 selects the CFL time step.  report nullable. */
 int hb_step(hb_ctx* ctx, double* u, double* p, double dt, hb_step_report* report);
 
 /* Batched sweeps: one context holding `count` independent cavities of the
