@@ -47,11 +47,16 @@ constexpr int kStrip = 64;   // pixels of one row per convolution block (4 waves
 // MFMA operand layout (16x16x16): lane l holds A[l%16][4(l/16)+j],
 // B[4(l/16)+j][l%16], and D[4(l/16)+j][l%16], j = 0..3.
 // ---------------------------------------------------------------------------
-template <int MT>
+// CIN > 0 fixes the input channel count at compile time, so the tap and
+// channel loops unroll and the weight loads (from L2) can be issued well
+// ahead of the MFMAs that use them; CIN = 0 takes it from cin_rt.  Same
+// products in the same order either way.
+template <int MT, int CIN = 0>
 __global__ void __launch_bounds__(256)
 k_conv3(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const float* __restrict__ bias, int H, int W,
-        int Cin, int relu, uint16_t* __restrict__ y, float* __restrict__ yf)
+        int cin_rt, int relu, uint16_t* __restrict__ y, float* __restrict__ yf)
 {
+    const int Cin = CIN > 0 ? CIN : cin_rt;
     extern __shared__ __align__(16) uint16_t sx[];   // [3][kStrip + 2][Cin]
     const int b = blockIdx.z, yr = blockIdx.y, x0 = blockIdx.x * kStrip;
     const int cols = kStrip + 2;
@@ -71,10 +76,12 @@ k_conv3(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const fl
     f32x4 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap % 3;
         const uint16_t* brow = sx + (dy * cols + px + dx) * Cin + 4 * kg;
         const uint16_t* wt = w + (long)tap * Cin + 4 * kg;
+#pragma unroll
         for (int c0 = 0; c0 < Cin; c0 += 16) {
             const bf16x4 B = *(const bf16x4*)(brow + c0);
 #pragma unroll
@@ -87,16 +94,22 @@ k_conv3(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w, const fl
     const int xx = x0 + px;
     if (xx >= W) return;
     const long base = (((long)b * H + yr) * W + xx) * (MT * 16);
+    // a lane's four channels 4 kg .. 4 kg + 3 of tile m are contiguous (NHWC):
+    // one 8-byte (bf16) or 16-byte (fp32) store each
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int m = 0; m < MT; ++m) {
+        const int co = m * 16 + 4 * kg;
+        float v[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int co = m * 16 + 4 * kg + j;
-            float v = acc[m][j] + (bias ? bias[co] : 0.0f);
-            if (relu) v = fmaxf(v, 0.0f);
-            if (y) y[base + co] = f2bf(v);
-            if (yf) yf[base + co] = v;
+            v[j] = acc[m][j] + (bias ? bias[co + j] : 0.0f);
+            if (relu) v[j] = fmaxf(v[j], 0.0f);
         }
+        if (y)
+            *(uint2*)(y + base + co) = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                                                  (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
+        if (yf) *(float4*)(yf + base + co) = make_float4(v[0], v[1], v[2], v[3]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -172,18 +185,33 @@ __global__ void k_unpack_out(const float* __restrict__ y, long P, int cpad, int 
     NN_LOOP(i, P * cout) o[i] = y[(i / cout) * cpad + i % cout];
 }
 
+// 2x2 average pooling, four channels per thread (C is a multiple of 16 and
+// every activation has fewer than 2^31 values)
 __global__ void k_pool2(const uint16_t* __restrict__ x, int n, int H, int W, int C, uint16_t* __restrict__ y)
 {
-    const int h = H / 2, w = W / 2;
-    NN_LOOP(i, (long)n * h * w * C)
-    {
-        const int c = (int)(i % C);
-        const long q = i / C;
-        const int X = (int)(q % w), Y = (int)((q / w) % h);
-        const long b = q / ((long)w * h);
-        const long s = ((b * H + 2 * Y) * W + 2 * X) * C + c;
-        const float v = bf2f(x[s]) + bf2f(x[s + C]) + bf2f(x[s + (long)W * C]) + bf2f(x[s + (long)W * C + C]);
-        y[i] = f2bf(0.25f * v);
+    const int h = H / 2, w = W / 2, C4 = C / 4;
+    const int total = n * h * w * C4;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int c = 4 * (i % C4), q = i / C4;
+        const int X = q % w, Y = (q / w) % h, b = q / (w * h);
+        const long s = ((long)(b * H + 2 * Y) * W + 2 * X) * C + c;
+        const uint2 p00 = *(const uint2*)(x + s), p01 = *(const uint2*)(x + s + C);
+        const uint2 p10 = *(const uint2*)(x + s + (long)W * C), p11 = *(const uint2*)(x + s + (long)W * C + C);
+        const uint32_t a00[2] = {p00.x, p00.y}, a01[2] = {p01.x, p01.y}, a10[2] = {p10.x, p10.y}, a11[2] = {p11.x, p11.y};
+        uint32_t o[2];
+#pragma unroll
+        for (int hw = 0; hw < 2; ++hw) {
+            uint32_t r = 0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int sh = 16 * k;
+                const float v = bf2f((uint16_t)(a00[hw] >> sh)) + bf2f((uint16_t)(a01[hw] >> sh)) +
+                                bf2f((uint16_t)(a10[hw] >> sh)) + bf2f((uint16_t)(a11[hw] >> sh));
+                r |= (uint32_t)f2bf(0.25f * v) << sh;
+            }
+            o[hw] = r;
+        }
+        *(uint2*)(y + (long)q * C + c) = make_uint2(o[0], o[1]);
     }
 }
 
@@ -201,17 +229,19 @@ __global__ void k_pool2_bwd(const float* __restrict__ dy, int n, int H, int W, i
 }
 
 // y[b, y, x, 0:Ca] = up(a)[..], y[.., Ca:Ca+Cb] = s  (a at half resolution)
+// four channels per thread (Ca and Cb are multiples of 16, so a group never
+// straddles the two sources)
 __global__ void k_up_concat(const uint16_t* __restrict__ a, int Ca, const uint16_t* __restrict__ s, int Cb, int n, int H,
                             int W, uint16_t* __restrict__ y)
 {
-    const int C = Ca + Cb;
-    NN_LOOP(i, (long)n * H * W * C)
-    {
-        const int c = (int)(i % C);
-        const long q = i / C;
-        const int xx = (int)(q % W), yy = (int)((q / W) % H);
-        const long b = q / ((long)W * H);
-        y[i] = c < Ca ? a[((b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Ca + c] : s[q * Cb + (c - Ca)];
+    const int C = Ca + Cb, C4 = C / 4;
+    const int total = n * H * W * C4;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int c = 4 * (i % C4), q = i / C4;
+        const int xx = q % W, yy = (q / W) % H, b = q / (W * H);
+        const uint16_t* src = c < Ca ? a + ((long)(b * (H / 2) + yy / 2) * (W / 2) + xx / 2) * Ca + c
+                                     : s + (long)q * Cb + (c - Ca);
+        *(uint2*)(y + (long)q * C + c) = *(const uint2*)src;
     }
 }
 
@@ -409,6 +439,10 @@ static int nn_shape(NNet* t, int n, int H, int W)
         a.W = W >> dims[i][0];
         a.C = dims[i][1];
         const long e = (long)n * a.H * a.W * a.C;
+        if (e >= (1L << 31)) {   // the layout kernels index activations with 32 bits
+            nn_free_acts(t);
+            return HB_ERR_ARG;
+        }
         big = e > big ? e : big;
         if (hipMalloc((void**)&a.a, 2 * e) != hipSuccess || hipMalloc((void**)&a.g, 4 * e) != hipSuccess) {
             nn_free_acts(t);
@@ -436,11 +470,22 @@ static void conv_fwd(NNet* t, int li, const Act& in, Act& out, float* yf)
     const size_t lds = 2 * 3 * (kStrip + 2) * (size_t)l.cin;
     const float* b = t->w + l.boff;
     uint16_t* y = yf ? nullptr : out.a;
-    switch (l.cout / 16) {
-    case 1: k_conv3<1><<<grid, 256, lds, t->s>>>(in.a, l.w16, b, in.H, in.W, l.cin, l.relu, y, yf); break;
-    case 2: k_conv3<2><<<grid, 256, lds, t->s>>>(in.a, l.w16, b, in.H, in.W, l.cin, l.relu, y, yf); break;
-    default: k_conv3<4><<<grid, 256, lds, t->s>>>(in.a, l.w16, b, in.H, in.W, l.cin, l.relu, y, yf); break;
-    }
+#define HB_CONV(M, C) k_conv3<M, C><<<grid, 256, lds, t->s>>>(in.a, l.w16, b, in.H, in.W, l.cin, l.relu, y, yf)
+    // the network's (output tiles, input channels) pairs with the channel
+    // count fixed at compile time; anything else with it at run time
+    const int mt = l.cout / 16;
+    if (mt == 1 && l.cin == 16) HB_CONV(1, 16);
+    else if (mt == 1 && l.cin == 48) HB_CONV(1, 48);
+    else if (mt == 2 && l.cin == 16) HB_CONV(2, 16);
+    else if (mt == 2 && l.cin == 32) HB_CONV(2, 32);
+    else if (mt == 2 && l.cin == 96) HB_CONV(2, 96);
+    else if (mt == 4 && l.cin == 32) HB_CONV(4, 32);
+    else if (mt == 4 && l.cin == 64) HB_CONV(4, 64);
+    else if (mt == 4 && l.cin == 128) HB_CONV(4, 128);
+    else if (mt == 1) HB_CONV(1, 0);
+    else if (mt == 2) HB_CONV(2, 0);
+    else HB_CONV(4, 0);
+#undef HB_CONV
 }
 
 // backward of layer li: out.g (fp32) -> parameter gradients, and in.g +=
@@ -483,11 +528,11 @@ static void forward(NNet* t)
     std::vector<Act>& A = t->A;
     const int n = t->n;
     auto pool = [&](const Act& a, Act& b) {
-        k_pool2<<<nn_blocks((long)n * b.H * b.W * b.C), 256, 0, t->s>>>(a.a, n, a.H, a.W, a.C, b.a);
+        k_pool2<<<nn_blocks((long)n * b.H * b.W * b.C / 4), 256, 0, t->s>>>(a.a, n, a.H, a.W, a.C, b.a);
     };
     auto upcat = [&](const Act& lo, const Act& skip, Act& out) {
-        k_up_concat<<<nn_blocks((long)n * out.H * out.W * out.C), 256, 0, t->s>>>(lo.a, lo.C, skip.a, skip.C, n, out.H,
-                                                                                   out.W, out.a);
+        k_up_concat<<<nn_blocks((long)n * out.H * out.W * out.C / 4), 256, 0, t->s>>>(lo.a, lo.C, skip.a, skip.C, n,
+                                                                                       out.H, out.W, out.a);
     };
     conv_fwd(t, 0, A[A_IN], A[A_E0A], nullptr);
     conv_fwd(t, 1, A[A_E0A], A[A_E0], nullptr);
