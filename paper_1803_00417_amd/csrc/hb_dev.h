@@ -20,42 +20,79 @@ struct GridD {
     double wall_u[3][2][3];
 };
 
-__host__ __device__ inline long ncells(const GridD& g) { return (long)g.n[0] * g.n[1] * g.n[2]; }
+// The same grid with its dimension fixed at compile time, for kernels
+// instantiated per dimension (loops over the axes unroll, index arithmetic
+// folds).  The wall velocities stay in the descriptor it was made from.
+// Every grid helper below takes either kind.
+template <int DIM>
+struct GridS {
+    static constexpr int dim = DIM;
+    int n[3];
+    double h;
+    int per[3];
+    const double (*wall_u)[2][3];
+};
 
-__host__ __device__ inline int nnode(const GridD& g, int a)
+template <int DIM>
+__device__ inline GridS<DIM> grid_s(const GridD& g)
+{
+    GridS<DIM> s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.n[a] = g.n[a];
+        s.per[a] = g.per[a];
+    }
+    s.h = g.h;
+    s.wall_u = g.wall_u;
+    return s;
+}
+
+template <class G>
+__host__ __device__ inline long ncells(const G& g) { return (long)g.n[0] * g.n[1] * g.n[2]; }
+
+template <class G>
+__host__ __device__ inline int nnode(const G& g, int a)
 {
     return a >= g.dim ? 1 : (g.per[a] ? g.n[a] : g.n[a] + 1);
 }
-__host__ __device__ inline long nnodes(const GridD& g) { return (long)nnode(g, 0) * nnode(g, 1) * nnode(g, 2); }
+template <class G>
+__host__ __device__ inline long nnodes(const G& g) { return (long)nnode(g, 0) * nnode(g, 1) * nnode(g, 2); }
 
-__host__ __device__ inline int nface(const GridD& g, int a) { return g.per[a] ? g.n[a] : g.n[a] + 1; }
+template <class G>
+__host__ __device__ inline int nface(const G& g, int a) { return g.per[a] ? g.n[a] : g.n[a] + 1; }
 
 // extent along b of the face array of axis a
-__host__ __device__ inline int fext(const GridD& g, int a, int b) { return b == a ? nface(g, a) : g.n[b]; }
+template <class G>
+__host__ __device__ inline int fext(const G& g, int a, int b) { return b == a ? nface(g, a) : g.n[b]; }
 
-__host__ __device__ inline long fcount(const GridD& g, int a)
+template <class G>
+__host__ __device__ inline long fcount(const G& g, int a)
 {
     return (long)fext(g, a, 0) * fext(g, a, 1) * fext(g, a, 2);
 }
 
-__host__ __device__ inline long foffset(const GridD& g, int a)
+template <class G>
+__host__ __device__ inline long foffset(const G& g, int a)
 {
     long o = 0;
     for (int b = 0; b < a; ++b) o += fcount(g, b);
     return o;
 }
 
-__host__ __device__ inline long cid(const GridD& g, int i, int j, int k)
+template <class G>
+__host__ __device__ inline long cid(const G& g, int i, int j, int k)
 {
     return ((long)k * g.n[1] + j) * g.n[0] + i;
 }
 
-__host__ __device__ inline long nid(const GridD& g, int i, int j, int k)
+template <class G>
+__host__ __device__ inline long nid(const G& g, int i, int j, int k)
 {
     return ((long)k * nnode(g, 1) + j) * nnode(g, 0) + i;
 }
 
-__host__ __device__ inline long fid(const GridD& g, int a, int i, int j, int k)
+template <class G>
+__host__ __device__ inline long fid(const G& g, int a, int i, int j, int k)
 {
     return ((long)k * fext(g, a, 1) + j) * fext(g, a, 0) + i;
 }
@@ -63,8 +100,8 @@ __host__ __device__ inline long fid(const GridD& g, int a, int i, int j, int k)
 // Value of component c of a cell field at (i,j,k), which may lie up to two
 // cells outside the box along one wall axis: wall ghosts are the odd
 // reflection 2 u_b - q(mirror) (u_b = 0 when hom); periodic axes wrap.
-template <bool HOM>
-__device__ inline double cval(const GridD& g, const double* __restrict__ q, int c, int i, int j, int k)
+template <bool HOM, class G>
+__device__ inline double cval(const G& g, const double* __restrict__ q, int c, int i, int j, int k)
 {
     int p[3] = {i, j, k};
     int oa = -1, side = 0;
@@ -90,7 +127,8 @@ __device__ inline double cval(const GridD& g, const double* __restrict__ q, int 
 
 // wrap a cell index on periodic axes (callers pass indices at most one box
 // length outside); returns false when the index lies beyond a wall
-__device__ inline bool wrap(const GridD& g, int p[3])
+template <class G>
+__device__ inline bool wrap(const G& g, int p[3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -115,7 +153,8 @@ __device__ inline double vload(const double* p)
 
 // cell G moved into the box (per axis clamp): an in-range index for a cell
 // whose value is then not used
-__device__ inline long cid_clamped(const GridD& g, const int G[3])
+template <class GR>
+__device__ inline long cid_clamped(const GR& g, const int G[3])
 {
     int p[3];
 #pragma unroll

@@ -9,8 +9,8 @@
 namespace hb {
 
 // value of component c; ZI: the interior is zero and only wall values remain
-template <bool HOM, bool ZI>
-__device__ inline double uval(const GridD& g, const double* __restrict__ u, int c, int i, int j, int k)
+template <bool HOM, bool ZI, class G>
+__device__ inline double uval(const G& g, const double* __restrict__ u, int c, int i, int j, int k)
 {
     if (!ZI) return cval<HOM>(g, u + (long)c * ncells(g), c, i, j, k);
     int p[3] = {i, j, k};
@@ -25,8 +25,8 @@ __device__ inline double uval(const GridD& g, const double* __restrict__ u, int 
 // flux of component c through the face normal to a whose hi-side cell is
 // (i,j,k): beta (du_c/dx_a + du_a/dx_c)/2 with the transverse derivative
 // averaged from the two cells' centred differences (zero on wall faces)
-template <bool HOM, bool ZI>
-__device__ inline double visc_flux(const GridD& g, const double* __restrict__ beta, const double* __restrict__ u,
+template <bool HOM, bool ZI, class G>
+__device__ inline double visc_flux(const G& g, const double* __restrict__ beta, const double* __restrict__ u,
                                    int c, int a, int i, int j, int k)
 {
     int R[3] = {i, j, k}, L[3] = {i, j, k};
@@ -51,11 +51,12 @@ __device__ inline double visc_flux(const GridD& g, const double* __restrict__ be
     return bf * 0.5 * (dn + cross);
 }
 
-template <bool HOM, bool ZI>
-__device__ inline double visc_div_at(const GridD& g, const double* __restrict__ beta, const double* __restrict__ u,
+template <bool HOM, bool ZI, class G>
+__device__ inline double visc_div_at(const G& g, const double* __restrict__ beta, const double* __restrict__ u,
                                      int c, int i, int j, int k)
 {
     double s = 0.0;
+#pragma unroll
     for (int a = 0; a < g.dim; ++a) {
         int hi[3] = {i, j, k};
         hi[a] += 1;
@@ -65,7 +66,8 @@ __device__ inline double visc_div_at(const GridD& g, const double* __restrict__ 
 }
 
 // diagonal of the homogeneous operator for component c
-__device__ inline double visc_diag(const GridD& g, const double* __restrict__ beta, double dt, int c, int i, int j, int k)
+template <class G>
+__device__ inline double visc_diag(const G& g, const double* __restrict__ beta, double dt, int c, int i, int j, int k)
 {
     double coef = 0.0;
     for (int a = 0; a < g.dim; ++a)

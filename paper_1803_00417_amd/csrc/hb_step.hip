@@ -60,13 +60,16 @@ __device__ inline double deadband(const double* sc, double ulid)
 // ---------------------------------------------------------------------------
 
 // cell average of the Q1 gradient of a nodal field
-__device__ inline double grad_node_at(const GridD& g, const double* __restrict__ p, int a, int i, int j, int k)
+template <class GR>
+__device__ inline double grad_node_at(const GR& g, const double* __restrict__ p, int a, int i, int j, int k)
 {
     const int nc = 1 << g.dim;
     double s = 0.0;
+#pragma unroll
     for (int bits = 0; bits < nc; ++bits) {
         if (!((bits >> a) & 1)) continue;
         int hi[3] = {i, j, k}, lo[3] = {i, j, k};
+        #pragma unroll
         for (int b = 0; b < g.dim; ++b) {
             hi[b] += (bits >> b) & 1;
             lo[b] += ((bits & ~(1 << a)) >> b) & 1;
@@ -87,7 +90,7 @@ __device__ inline double grad_node_at(const GridD& g, const double* __restrict__
     const CavK& K = ck[cav];                                               \
     const CavIO& IO = io[cav];                                             \
     (void)IO;                                                              \
-    const GridD& g = K.g;                                                  \
+    const GridS<DIM> g = grid_s<DIM>(K.g);                                 \
     const int i = blockIdx.x * blockDim.x + threadIdx.x;                   \
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
 
@@ -105,7 +108,7 @@ __device__ inline double grad_node_at(const GridD& g, const double* __restrict__
     const CavK& K = ck[cav];                                               \
     const CavIO& IO = io[cav];                                             \
     (void)IO;                                                              \
-    const GridD& g = K.g;                                                  \
+    const GridS<DIM> g = grid_s<DIM>(K.g);                                 \
     if (a >= g.dim) return;                                                \
     const int i = blockIdx.x * blockDim.x + threadIdx.x;                   \
     const int j = blockIdx.y * blockDim.y + threadIdx.y;                   \
@@ -120,34 +123,44 @@ static dim3 face_grid(const Ctx* c) { return dim3((c->fx[0] + kBlk.x - 1) / kBlk
 // Gp = G p, the cell average of the Q1 gradient of the pressure
 // (the bodies take the cavity's arrays as restrict-qualified arguments: the
 // table they come from says nothing about aliasing)
-__device__ __forceinline__ void grad_node_body(const GridD& g, const double* __restrict__ p, double* __restrict__ Gp,
+template <class GR>
+__device__ __forceinline__ void grad_node_body(const GR& g, const double* __restrict__ p, double* __restrict__ Gp,
                                                int i, int j, int k)
 {
     const long N = ncells(g), q = cid(g, i, j, k);
+    #pragma unroll
     for (int a = 0; a < g.dim; ++a) Gp[a * N + q] = grad_node_at(g, p, a, i, j, k);
 }
 
+template <int DIM>
 __global__ void k_grad_node(STAGE_ARGS)
 {
     STAGE_CELL(zb);
     grad_node_body(g, IO.p, K.Gp, i, j, k);
 }
 
-void stage_grad_node(Ctx* c) { k_grad_node<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+void stage_grad_node(Ctx* c)
+{
+    if (c->dim == 2) k_grad_node<2><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+    else k_grad_node<3><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+}
 
 // F = -G p + wF E + f, the forcing of the Taylor prediction: wF = 2 puts
 // the whole explicit stress divergence in (as eq:iamr:extrap prints it),
 // wF = 0 leaves it out
-__device__ __forceinline__ void forcing_body(const GridD& g, const FluidD& fl, double wF, const double* __restrict__ Gp,
+template <class GR>
+__device__ __forceinline__ void forcing_body(const GR& g, const FluidD& fl, double wF, const double* __restrict__ Gp,
                                              const double* __restrict__ E, double* __restrict__ F, int i, int j, int k)
 {
     const long N = ncells(g), q0 = cid(g, i, j, k);
+    #pragma unroll
     for (int c = 0; c < g.dim; ++c) {
         const long t = c * N + q0;
         F[t] = -Gp[t] + wF * E[t] + fl.f[c];
     }
 }
 
+template <int DIM>
 __global__ void k_forcing(STAGE_ARGS, double wF)
 {
     STAGE_CELL(zb);
@@ -157,19 +170,23 @@ __global__ void k_forcing(STAGE_ARGS, double wF)
 void stage_forcing(Ctx* c)
 {
     const double wF = c->opts.pred_visc ? 2.0 : 0.0;
-    k_forcing<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], wF);
+    if (c->dim == 2) k_forcing<2><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], wF);
+    else k_forcing<3><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], wF);
 }
 
 // ---------------------------------------------------------------------------
 // Godunov prediction
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void slopes_body(const GridD& g, const double* __restrict__ u, double* __restrict__ S,
+template <class GR>
+__device__ __forceinline__ void slopes_body(const GR& g, const double* __restrict__ u, double* __restrict__ S,
                                             int i, int j, int k)
 {
     const long N = ncells(g), q0 = cid(g, i, j, k);
     const int d = g.dim;
+    #pragma unroll
     for (int a = 0; a < d; ++a)
+        #pragma unroll
         for (int q = 0; q < d; ++q) {
             double st[5];
             for (int t = 0; t < 5; ++t) {
@@ -181,16 +198,22 @@ __device__ __forceinline__ void slopes_body(const GridD& g, const double* __rest
         }
 }
 
+template <int DIM>
 __global__ void k_slopes(STAGE_ARGS)
 {
     STAGE_CELL(zb);
     slopes_body(g, IO.u, K.S, i, j, k);
 }
 
-void stage_slopes(Ctx* c) { k_slopes<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+void stage_slopes(Ctx* c)
+{
+    if (c->dim == 2) k_slopes<2><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+    else k_slopes<3><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+}
 
 // normal-only traced states on a-faces, upwinded by their Burgers solution
-__device__ __forceinline__ void trace_normal_body(const GridD& g, int a, double dt, double delta, long nf,
+template <class GR>
+__device__ __forceinline__ void trace_normal_body(const GR& g, int a, double dt, double delta, long nf,
                                                   const double* __restrict__ u, const double* __restrict__ S,
                                                   double* __restrict__ uhat, double* __restrict__ qhat, int i, int j,
                                                   int k)
@@ -204,35 +227,45 @@ __device__ __forceinline__ void trace_normal_body(const GridD& g, int a, double 
     if (!okL || !okR) {
         const int side = okL ? 1 : 0;
         uhat[f] = 0.0;
+        #pragma unroll
         for (int q = 0; q < d; ++q) qhat[q * nf + f] = g.wall_u[a][side][q];
         return;
     }
     const long cL = cid(g, L[0], L[1], L[2]), cR = cid(g, R[0], R[1], R[2]);
     double qL[3], qR[3];
+    #pragma unroll
     for (int q = 0; q < d; ++q) {
         qL[q] = u[q * N + cL] + (0.5 - dt * u[a * N + cL] / (2.0 * g.h)) * S[((long)a * d + q) * N + cL];
         qR[q] = u[q * N + cR] - (0.5 + dt * u[a * N + cR] / (2.0 * g.h)) * S[((long)a * d + q) * N + cR];
     }
     const double uh = burgers(qL[a], qR[a], delta);
     uhat[f] = uh;
+    #pragma unroll
     for (int q = 0; q < d; ++q) qhat[q * nf + f] = (q == a) ? uh : upwind(uh, qL[q], qR[q], delta);
 }
 
+template <int DIM>
 __global__ void k_trace_normal(STAGE_ARGS)
 {
     STAGE_FACE(zb);
     trace_normal_body(g, a, IO.dt, deadband(K.sc, K.ulid), K.nf, IO.u, K.S, K.uhat, K.qhat, i, j, k);
 }
 
-void stage_trace_normal(Ctx* c) { k_trace_normal<<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]); }
+void stage_trace_normal(Ctx* c)
+{
+    if (c->dim == 2) k_trace_normal<2><<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+    else k_trace_normal<3><<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+}
 
 // transverse terms at cells: (u_b dq/dx_b)^ = mean face velocity x difference
-__device__ __forceinline__ void transverse_body(const GridD& g, long nf, const double* __restrict__ uhat,
+template <class GR>
+__device__ __forceinline__ void transverse_body(const GR& g, long nf, const double* __restrict__ uhat,
                                                 const double* __restrict__ qhat, double* __restrict__ T, int i, int j,
                                                 int k)
 {
     const int d = g.dim;
     const long N = ncells(g), q0 = cid(g, i, j, k);
+    #pragma unroll
     for (int b = 0; b < d; ++b) {
         int hi[3] = {i, j, k};
         hi[b] += 1;
@@ -240,6 +273,7 @@ __device__ __forceinline__ void transverse_body(const GridD& g, long nf, const d
         const long flo = foffset(g, b) + fid(g, b, i, j, k);
         const long fhi = foffset(g, b) + fid(g, b, hi[0], hi[1], hi[2]);
         const double ubar = 0.5 * (uhat[flo] + uhat[fhi]);
+        #pragma unroll
         for (int q = 0; q < d; ++q) {
             const double dq = (qhat[q * nf + fhi] - qhat[q * nf + flo]) / g.h;
             T[((long)b * d + q) * N + q0] = ubar * dq;
@@ -247,17 +281,23 @@ __device__ __forceinline__ void transverse_body(const GridD& g, long nf, const d
     }
 }
 
+template <int DIM>
 __global__ void k_transverse(STAGE_ARGS)
 {
     STAGE_CELL(zb);
     transverse_body(g, K.nf, K.uhat, K.qhat, K.trans, i, j, k);
 }
 
-void stage_transverse(Ctx* c) { k_transverse<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+void stage_transverse(Ctx* c)
+{
+    if (c->dim == 2) k_transverse<2><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+    else k_transverse<3><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+}
 
 // full face states: traced normal part - dt/2 transverse terms + dt/2 forcing;
 // the advection velocity is the Burgers solution of the normal component
-__device__ __forceinline__ void trace_full_body(const GridD& g, int a, double dt, double delta, long nf,
+template <class GR>
+__device__ __forceinline__ void trace_full_body(const GR& g, int a, double dt, double delta, long nf,
                                                 const double* __restrict__ u, const double* __restrict__ S,
                                                 const double* __restrict__ T, const double* __restrict__ F,
                                                 double* __restrict__ qLf, double* __restrict__ qRf,
@@ -272,6 +312,7 @@ __device__ __forceinline__ void trace_full_body(const GridD& g, int a, double dt
     if (!okL || !okR) {
         const int side = okL ? 1 : 0;
         uadv[f] = 0.0;
+        #pragma unroll
         for (int q = 0; q < d; ++q) {
             qLf[q * nf + f] = g.wall_u[a][side][q];
             qRf[q * nf + f] = g.wall_u[a][side][q];
@@ -279,8 +320,10 @@ __device__ __forceinline__ void trace_full_body(const GridD& g, int a, double dt
         return;
     }
     const long cL = cid(g, L[0], L[1], L[2]), cR = cid(g, R[0], R[1], R[2]);
+    #pragma unroll
     for (int q = 0; q < d; ++q) {
         double tl = 0.0, tr = 0.0;
+        #pragma unroll
         for (int b = 0; b < d; ++b) {
             if (b == a) continue;
             tl += T[((long)b * d + q) * N + cL];
@@ -296,13 +339,18 @@ __device__ __forceinline__ void trace_full_body(const GridD& g, int a, double dt
     uadv[f] = burgers(qLf[a * nf + f], qRf[a * nf + f], delta);
 }
 
+template <int DIM>
 __global__ void k_trace_full(STAGE_ARGS)
 {
     STAGE_FACE(zb);
     trace_full_body(g, a, IO.dt, deadband(K.sc, K.ulid), K.nf, IO.u, K.S, K.trans, K.F, K.qLf, K.qRf, K.uadv, i, j, k);
 }
 
-void stage_trace_full(Ctx* c) { k_trace_full<<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]); }
+void stage_trace_full(Ctx* c)
+{
+    if (c->dim == 2) k_trace_full<2><<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+    else k_trace_full<3><<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+}
 
 // ---------------------------------------------------------------------------
 // MAC projection of the advection velocity
@@ -310,10 +358,12 @@ void stage_trace_full(Ctx* c) { k_trace_full<<<face_grid(c), kBlk, 0, c->s>>>(c-
 
 // cell divergence of a face field: of u^adv into the MAC right-hand side
 // (after = 0), or of u^MAC into macrhs (after = 1)
-__device__ __forceinline__ void mac_div_body(const GridD& g, const double* __restrict__ F, double* __restrict__ out,
+template <class GR>
+__device__ __forceinline__ void mac_div_body(const GR& g, const double* __restrict__ F, double* __restrict__ out,
                                              int i, int j, int k)
 {
     double s = 0.0;
+    #pragma unroll
     for (int a = 0; a < g.dim; ++a) {
         int hi[3] = {i, j, k};
         hi[a] += 1;
@@ -324,16 +374,22 @@ __device__ __forceinline__ void mac_div_body(const GridD& g, const double* __res
     out[cid(g, i, j, k)] = s;
 }
 
+template <int DIM>
 __global__ void k_mac_div(STAGE_ARGS, int after)
 {
     STAGE_CELL(zb);
     mac_div_body(g, after ? K.umac : K.uadv, after ? K.macrhs : K.macb, i, j, k);
 }
 
-void stage_mac_div(Ctx* c, int after) { k_mac_div<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], after); }
+void stage_mac_div(Ctx* c, int after)
+{
+    if (c->dim == 2) k_mac_div<2><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], after);
+    else k_mac_div<3><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], after);
+}
 
 // u^MAC = u^adv - G_mac phi (the gradient vanishes on wall faces)
-__device__ __forceinline__ void mac_update_body(const GridD& g, int a, const double* __restrict__ uadv,
+template <class GR>
+__device__ __forceinline__ void mac_update_body(const GR& g, int a, const double* __restrict__ uadv,
                                                 const double* __restrict__ phi, double* __restrict__ umac, int i, int j,
                                                 int k)
 {
@@ -345,18 +401,24 @@ __device__ __forceinline__ void mac_update_body(const GridD& g, int a, const dou
     umac[f] = uadv[f] - gphi;
 }
 
+template <int DIM>
 __global__ void k_mac_update(STAGE_ARGS)
 {
     STAGE_FACE(zb);
     mac_update_body(g, a, K.uadv, K.macphi, K.umac, i, j, k);
 }
 
-void stage_mac_update(Ctx* c) { k_mac_update<<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]); }
+void stage_mac_update(Ctx* c)
+{
+    if (c->dim == 2) k_mac_update<2><<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+    else k_mac_update<3><<<face_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+}
 
 // convective term A = sum_a mean(u^MAC_a) (q~_hi - q~_lo)/h with the full
 // states upwinded by u^MAC, and b = u - dt A + dt (-G p + wb E + f) with
 // wb = 2 (1 - theta) (1 for Crank-Nicolson)
-__device__ __forceinline__ void advect_rhs_body(const GridD& g, const FluidD& fl, double dt, double wb, double delta,
+template <class GR>
+__device__ __forceinline__ void advect_rhs_body(const GR& g, const FluidD& fl, double dt, double wb, double delta,
                                                 long nf, const double* __restrict__ u, const double* __restrict__ umac,
                                                 const double* __restrict__ qLf, const double* __restrict__ qRf,
                                                 const double* __restrict__ Gp, const double* __restrict__ E,
@@ -365,6 +427,7 @@ __device__ __forceinline__ void advect_rhs_body(const GridD& g, const FluidD& fl
     const int d = g.dim;
     const long N = ncells(g), q0 = cid(g, i, j, k);
     double A[3] = {0.0, 0.0, 0.0};
+    #pragma unroll
     for (int a = 0; a < d; ++a) {
         int hi[3] = {i, j, k};
         hi[a] += 1;
@@ -372,12 +435,14 @@ __device__ __forceinline__ void advect_rhs_body(const GridD& g, const FluidD& fl
         const long flo = foffset(g, a) + fid(g, a, i, j, k);
         const long fhi = foffset(g, a) + fid(g, a, hi[0], hi[1], hi[2]);
         const double ulo = umac[flo], uhi = umac[fhi];
+        #pragma unroll
         for (int q = 0; q < d; ++q) {
             const double tlo = upwind(ulo, qLf[q * nf + flo], qRf[q * nf + flo], delta);
             const double thi = upwind(uhi, qLf[q * nf + fhi], qRf[q * nf + fhi], delta);
             A[q] += 0.5 * (ulo + uhi) * (thi - tlo) / g.h;
         }
     }
+    #pragma unroll
     for (int q = 0; q < d; ++q) {
         const long e = q * N + q0;
         b[e] = u[e] - dt * A[q] + dt * (-Gp[e] + wb * E[e] + fl.f[q]);
@@ -385,6 +450,7 @@ __device__ __forceinline__ void advect_rhs_body(const GridD& g, const FluidD& fl
     }
 }
 
+template <int DIM>
 __global__ void k_advect_rhs(STAGE_ARGS, double wb)
 {
     STAGE_CELL(zb);
@@ -394,7 +460,9 @@ __global__ void k_advect_rhs(STAGE_ARGS, double wb)
 
 void stage_advect_rhs(Ctx* c)
 {
-    k_advect_rhs<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], 2.0 * (1.0 - c->opts.theta));
+    const double wb = 2.0 * (1.0 - c->opts.theta);
+    if (c->dim == 2) k_advect_rhs<2><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], wb);
+    else k_advect_rhs<3><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2], wb);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,8 +472,8 @@ void stage_advect_rhs(Ctx* c)
 // r_k = sum over cells touching node k of sum_a s_a (h/2)^(d-1) V_a, where
 // V = ustar/dt + G p into the nodal right-hand side (PROJ), or V = uout into
 // rnode
-template <bool PROJ>
-__device__ __forceinline__ void weak_div_body(const GridD& g, double dt, const double* __restrict__ V,
+template <bool PROJ, class GR>
+__device__ __forceinline__ void weak_div_body(const GR& g, double dt, const double* __restrict__ V,
                                               const double* __restrict__ Gp, double* __restrict__ r, int i, int j,
                                               int k)
 {
@@ -414,9 +482,11 @@ __device__ __forceinline__ void weak_div_body(const GridD& g, double dt, const d
     const double w = d == 2 ? 0.5 * g.h : (0.5 * g.h) * (0.5 * g.h);
     const int node[3] = {i, j, k};
     double s = 0.0;
+#pragma unroll
     for (int me = 0; me < (1 << d); ++me) {     // node is corner `me` of the cell
         int cc[3] = {0, 0, 0};
         bool ok = true;
+        #pragma unroll
         for (int a = 0; a < d; ++a) {
             int v = node[a] - ((me >> a) & 1);
             if (v < 0) { if (g.per[a]) v += g.n[a]; else ok = false; }
@@ -426,6 +496,7 @@ __device__ __forceinline__ void weak_div_body(const GridD& g, double dt, const d
         if (!ok) continue;
         const long q = cid(g, cc[0], cc[1], cc[2]);
         double t = 0.0;
+        #pragma unroll
         for (int a = 0; a < d; ++a) {
             const double sg = ((me >> a) & 1) ? 1.0 : -1.0;
             const double Va = PROJ ? V[a * N + q] / dt + Gp[a * N + q] : V[a * N + q];
@@ -436,34 +507,50 @@ __device__ __forceinline__ void weak_div_body(const GridD& g, double dt, const d
     r[nid(g, i, j, k)] = s;
 }
 
-template <bool PROJ>
+template <bool PROJ, int DIM>
 __global__ void k_weak_div(STAGE_ARGS)
 {
     STAGE_NODE(zb);
     weak_div_body<PROJ>(g, IO.dt, PROJ ? IO.ustar : IO.uout, K.Gp, PROJ ? K.nodb : K.rnode, i, j, k);
 }
 
-void stage_proj_rhs(Ctx* c) { k_weak_div<true><<<node_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->nx[2]); }
-void stage_weak_div_u(Ctx* c) { k_weak_div<false><<<node_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->nx[2]); }
+void stage_proj_rhs(Ctx* c)
+{
+    if (c->dim == 2) k_weak_div<true, 2><<<node_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->nx[2]);
+    else k_weak_div<true, 3><<<node_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->nx[2]);
+}
+
+void stage_weak_div_u(Ctx* c)
+{
+    if (c->dim == 2) k_weak_div<false, 2><<<node_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->nx[2]);
+    else k_weak_div<false, 3><<<node_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->nx[2]);
+}
 
 // uout = ustar + dt (G p - G phi)
-__device__ __forceinline__ void proj_update_body(const GridD& g, double dt, const double* __restrict__ ustar,
+template <class GR>
+__device__ __forceinline__ void proj_update_body(const GR& g, double dt, const double* __restrict__ ustar,
                                                  const double* __restrict__ Gp, const double* __restrict__ phi,
                                                  double* __restrict__ u, int i, int j, int k)
 {
     const long N = ncells(g), q = cid(g, i, j, k);
+    #pragma unroll
     for (int a = 0; a < g.dim; ++a) {
         const double gphi = grad_node_at(g, phi, a, i, j, k);
         u[a * N + q] = ustar[a * N + q] + dt * (Gp[a * N + q] - gphi);
     }
 }
 
+template <int DIM>
 __global__ void k_proj_update(STAGE_ARGS)
 {
     STAGE_CELL(zb);
     proj_update_body(g, IO.dt, IO.ustar, K.Gp, K.phi, IO.uout, i, j, k);
 }
 
-void stage_proj_update(Ctx* c) { k_proj_update<<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+void stage_proj_update(Ctx* c)
+{
+    if (c->dim == 2) k_proj_update<2><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+    else k_proj_update<3><<<cell_grid(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+}
 
 }  // namespace hb

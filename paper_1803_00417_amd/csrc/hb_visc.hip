@@ -25,11 +25,14 @@ __device__ inline double eta_of_g(const FluidD& fl, double g)
 
 // g = |gamma_dot| of cell (i, j, k): centred differences with wall ghosts,
 // |A| = sqrt(sum A_ij^2 / 2) (Sec. II)
-__device__ inline double strain_norm_at(const GridD& g, const double* __restrict__ u, int i, int j, int k)
+template <class GR>
+__device__ inline double strain_norm_at(const GR& g, const double* __restrict__ u, int i, int j, int k)
 {
     const long N = ncells(g);
     double G[3][3];
+#pragma unroll
     for (int a = 0; a < g.dim; ++a)
+#pragma unroll
         for (int c = 0; c < g.dim; ++c) {
             int p[3] = {i, j, k}, m[3] = {i, j, k};
             p[a] += 1;
@@ -38,7 +41,9 @@ __device__ inline double strain_norm_at(const GridD& g, const double* __restrict
             G[a][c] = (cval<false>(g, q, c, p[0], p[1], p[2]) - cval<false>(g, q, c, m[0], m[1], m[2])) / (2.0 * g.h);
         }
     double s = 0.0;
+#pragma unroll
     for (int a = 0; a < g.dim; ++a)
+#pragma unroll
         for (int c = 0; c < g.dim; ++c) {
             const double e = 0.5 * (G[a][c] + G[c][a]);
             s += e * e;
@@ -102,7 +107,8 @@ void launch_yield(Ctx* c, const Cav& v, const double* u, unsigned char* mask, do
 
 // face (i, j, k) of axis a: the mean of eta/Re of its two cells, or of the
 // interior cell on a wall face
-__device__ __forceinline__ void face_eta(const GridD& g, int a, double Re, const double* __restrict__ eta,
+template <class GR>
+__device__ __forceinline__ void face_eta(const GR& g, int a, double Re, const double* __restrict__ eta,
                                 double* __restrict__ beta, int i, int j, int k)
 {
     int R[3] = {i, j, k}, L[3] = {i, j, k};
@@ -119,16 +125,19 @@ __device__ __forceinline__ void face_eta(const GridD& g, int a, double Re, const
 }
 
 // coarse face (i, j, k) of axis a = mean of the 2^(d-1) fine faces tiling it
-__device__ __forceinline__ void restrict_face(const GridD& gf, const GridD& gc, int a, const double* __restrict__ bf,
+template <class GR>
+__device__ __forceinline__ void restrict_face(const GR& gf, const GR& gc, int a, const double* __restrict__ bf,
                                      double* __restrict__ bc, int i, int j, int k)
 {
     const int I[3] = {i, j, k};
     const double* F = bf + foffset(gf, a);
     double s = 0.0;
     int cnt = 0;
+#pragma unroll
     for (int t = 0; t < (1 << gf.dim); ++t) {
         if ((t >> a) & 1) continue;
         int p[3] = {0, 0, 0};
+#pragma unroll
         for (int b = 0; b < gf.dim; ++b) p[b] = (b == a) ? 2 * I[b] : 2 * I[b] + ((t >> b) & 1);
         s += F[fid(gf, a, p[0], p[1], p[2])];
         ++cnt;
@@ -147,7 +156,8 @@ __device__ __forceinline__ void restrict_face(const GridD& gf, const GridD& gc, 
 // is copied first, then one thread per boundary-layer cell of wall face
 // (a, side), at in-face position (u, w), adds the wall term (a cell on
 // several layers is taken by its lowest axis).
-__device__ __forceinline__ void visc_wall_at(const GridD& g, const double* __restrict__ beta, double dt,
+template <class GR>
+__device__ __forceinline__ void visc_wall_at(const GR& g, const double* __restrict__ beta, double dt,
                                     const double* __restrict__ rhs, double* __restrict__ out, int a, int side, int u, int w)
 {
     if (a >= g.dim || g.per[a]) return;
@@ -160,8 +170,11 @@ __device__ __forceinline__ void visc_wall_at(const GridD& g, const double* __res
     for (int b = 0; b < a; ++b)
         if (!g.per[b] && (p[b] == 0 || p[b] == g.n[b] - 1)) return;
     const long N = ncells(g), q = cid(g, p[0], p[1], p[2]);
-    for (int c = 0; c < g.dim; ++c)
+#pragma unroll
+    for (int c = 0; c < g.dim; ++c) {
         out[c * N + q] = rhs[c * N + q] + dt * visc_div_at<false, true>(g, beta, nullptr, c, p[0], p[1], p[2]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 // dense matrix of the homogeneous operator, column j = A e_j (E holds the
@@ -219,17 +232,22 @@ void launch_visc_dense_batch(Ctx* c, const MG& m)
 static dim3 cells_of(const Ctx* c) { return dim3((c->cx[0] + kBlk.x - 1) / kBlk.x, (c->cx[1] + kBlk.y - 1) / kBlk.y, c->cx[2] * c->nb); }
 
 // eta = eta(u) of every cavity
+template <int DIM>
 __global__ void k_stage_viscosity(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb)
 {
     const int cav = blockIdx.z / zb, k = blockIdx.z - cav * zb;
     const CavK& K = ck[cav];
-    const GridD& g = K.g;
+    const GridS<DIM> g = grid_s<DIM>(K.g);
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return;
     K.eta[cid(g, i, j, k)] = eta_of_g(K.fl, strain_norm_at(g, io[cav].u, i, j, k));
 }
 
-void stage_viscosity(Ctx* c) { k_stage_viscosity<<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+void stage_viscosity(Ctx* c)
+{
+    if (c->dim == 2) k_stage_viscosity<2><<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+    else k_stage_viscosity<3><<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+}
 
 // eta/Re at cells and the coefficient slot (the operator's 2 theta dt) of
 // every cavity
@@ -247,12 +265,13 @@ __global__ void k_stage_eta_over_re(const CavK* __restrict__ ck, const CavIO* __
 }
 
 // level-0 face viscosities of every cavity
+template <int DIM>
 __global__ void k_stage_eta_faces(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb)
 {
     const int zz = blockIdx.z / zb, k = blockIdx.z - zz * zb;
     const int cav = zz / 3, a = zz - 3 * cav;
     const CavK& K = ck[cav];
-    const GridD& g = K.g;
+    const GridS<DIM> g = grid_s<DIM>(K.g);
     if (a >= g.dim) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= fext(g, a, 0) || j >= fext(g, a, 1) || k >= fext(g, a, 2)) return;
@@ -262,63 +281,79 @@ __global__ void k_stage_eta_faces(const CavK* __restrict__ ck, const CavIO* __re
 void stage_visc_coef(Ctx* c)
 {
     k_stage_eta_over_re<<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
-    k_stage_eta_faces<<<dim3((c->fx[0] + kBlk.x - 1) / kBlk.x, (c->fx[1] + kBlk.y - 1) / kBlk.y, c->fx[2] * 3 * c->nb),
-                        kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+    const dim3 fg((c->fx[0] + kBlk.x - 1) / kBlk.x, (c->fx[1] + kBlk.y - 1) / kBlk.y, c->fx[2] * 3 * c->nb);
+    if (c->dim == 2) k_stage_eta_faces<2><<<fg, kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
+    else k_stage_eta_faces<3><<<fg, kBlk, 0, c->s>>>(c->ck, c->cio, c->fx[2]);
 }
 
 // face viscosities of level l of every cavity from level l - 1 (entries with
 // gc.dim == 0: no such level)
+template <int DIM>
 __global__ void k_stage_restrict_faces(const RFace* __restrict__ rf, int zb)
 {
     const int zz = blockIdx.z / zb, k = blockIdx.z - zz * zb;
     const int cav = zz / 3, a = zz - 3 * cav;
     const RFace& R = rf[cav];
-    const GridD& gc = R.gc;
-    if (a >= gc.dim) return;
+    if (R.gc.dim == 0 || a >= DIM) return;
+    const GridS<DIM> gc = grid_s<DIM>(R.gc), gf = grid_s<DIM>(R.gf);
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= fext(gc, a, 0) || j >= fext(gc, a, 1) || k >= fext(gc, a, 2)) return;
-    restrict_face(R.gf, gc, a, R.bf, R.bc, i, j, k);
+    restrict_face(gf, gc, a, R.bf, R.bc, i, j, k);
 }
 
 void stage_restrict_faces(Ctx* c, int l)
 {
     const int* e = c->rfx[l].data();
-    k_stage_restrict_faces<<<dim3((e[0] + kBlk.x - 1) / kBlk.x, (e[1] + kBlk.y - 1) / kBlk.y, e[2] * 3 * c->nb), kBlk, 0,
-                             c->s>>>(c->rface + (long)(l - 1) * c->nb, e[2]);
+    const dim3 fg((e[0] + kBlk.x - 1) / kBlk.x, (e[1] + kBlk.y - 1) / kBlk.y, e[2] * 3 * c->nb);
+    if (c->dim == 2) k_stage_restrict_faces<2><<<fg, kBlk, 0, c->s>>>(c->rface + (long)(l - 1) * c->nb, e[2]);
+    else k_stage_restrict_faces<3><<<fg, kBlk, 0, c->s>>>(c->rface + (long)(l - 1) * c->nb, e[2]);
 }
 
 // E = div(eta_e gamma_dot(u)) of every cavity, level-0 faces (the body
 // takes the arrays restrict-qualified: the table says nothing about
 // aliasing)
-__device__ __forceinline__ void visc_div_body(const GridD& g, const double* __restrict__ beta,
+template <class GR>
+__device__ __forceinline__ void visc_div_body(const GR& g, const double* __restrict__ beta,
                                               const double* __restrict__ u, double* __restrict__ out, int i, int j,
                                               int k)
 {
     const long N = ncells(g), q = cid(g, i, j, k);
-    for (int c = 0; c < g.dim; ++c) out[c * N + q] = visc_div_at<false, false>(g, beta, u, c, i, j, k);
+    // one component at a time (a scheduling barrier between them keeps the
+    // loads of one component's stencil from piling up with the next's)
+#pragma unroll
+    for (int c = 0; c < g.dim; ++c) {
+        out[c * N + q] = visc_div_at<false, false>(g, beta, u, c, i, j, k);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
+template <int DIM>
 __global__ void k_stage_visc_div(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb)
 {
     const int cav = blockIdx.z / zb, k = blockIdx.z - cav * zb;
     const CavK& K = ck[cav];
-    const GridD& g = K.g;
+    const GridS<DIM> g = grid_s<DIM>(K.g);
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return;
     visc_div_body(g, K.beta0, io[cav].u, K.E, i, j, k);
 }
 
-void stage_visc_div(Ctx* c) { k_stage_visc_div<<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]); }
+void stage_visc_div(Ctx* c)
+{
+    if (c->dim == 2) k_stage_visc_div<2><<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+    else k_stage_visc_div<3><<<cells_of(c), kBlk, 0, c->s>>>(c->ck, c->cio, c->cx[2]);
+}
 
 // the viscous level-0 right-hand side of every cavity: b plus the wall part
 // of the operator (coefficient from the slot); block z = cavity * 2 dim +
 // wall face 2 a + side, after a copy of b
+template <int DIM>
 __global__ void k_stage_visc_wall(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int nz)
 {
     const int cav = blockIdx.z / nz, w2 = blockIdx.z - cav * nz;
     const CavK& K = ck[cav];
     const int a = w2 >> 1, side = w2 & 1;
-    visc_wall_at(K.g, K.beta0, K.sc[S_DT], io[cav].b, K.viscb, a, side, blockIdx.x * blockDim.x + threadIdx.x,
+    visc_wall_at(grid_s<DIM>(K.g), K.beta0, K.sc[S_DT], io[cav].b, K.viscb, a, side, blockIdx.x * blockDim.x + threadIdx.x,
                  blockIdx.y * blockDim.y + threadIdx.y);
 }
 
@@ -344,7 +379,9 @@ void stage_visc_wall_rhs(Ctx* c)
     }
     const long nblk = std::min((nmax + 255) / 256, 8192L);
     k_stage_copy_b<<<dim3((unsigned)nblk, c->nb), 256, 0, c->s>>>(c->ck, c->cio);
-    k_stage_visc_wall<<<grid3(e0, e1, 2 * c->dim * c->nb, kBlk), kBlk, 0, c->s>>>(c->ck, c->cio, 2 * c->dim);
+    const dim3 wg = grid3(e0, e1, 2 * c->dim * c->nb, kBlk);
+    if (c->dim == 2) k_stage_visc_wall<2><<<wg, kBlk, 0, c->s>>>(c->ck, c->cio, 2 * c->dim);
+    else k_stage_visc_wall<3><<<wg, kBlk, 0, c->s>>>(c->ck, c->cio, 2 * c->dim);
 }
 
 
