@@ -105,22 +105,23 @@ void launch_yield(Ctx* c, const Cav& v, const double* u, unsigned char* mask, do
 // face viscosity: fine faces from cells, coarse faces from fine faces
 // ---------------------------------------------------------------------------
 
-// face (i, j, k) of axis a: the mean of eta/Re of its two cells, or of the
-// interior cell on a wall face
+// face (i, j, k) of axis a: the mean of eta/Re of its two cells, or that of
+// the interior cell on a wall face (etae: eta/Re per cell, formed by
+// k_stage_eta_over_re as eta / Re)
 template <class GR>
-__device__ __forceinline__ void face_eta(const GR& g, int a, double Re, const double* __restrict__ eta,
-                                double* __restrict__ beta, int i, int j, int k)
+__device__ __forceinline__ void face_eta(const GR& g, int a, const double* __restrict__ etae,
+                                         double* __restrict__ beta, int i, int j, int k)
 {
     int R[3] = {i, j, k}, L[3] = {i, j, k};
     L[a] -= 1;
     const bool okL = wrap(g, L), okR = wrap(g, R);
     double v;
     if (okL && okR)
-        v = 0.5 * (eta[cid(g, L[0], L[1], L[2])] / Re + eta[cid(g, R[0], R[1], R[2])] / Re);
+        v = 0.5 * (etae[cid(g, L[0], L[1], L[2])] + etae[cid(g, R[0], R[1], R[2])]);
     else if (okL)
-        v = eta[cid(g, L[0], L[1], L[2])] / Re;
+        v = etae[cid(g, L[0], L[1], L[2])];
     else
-        v = eta[cid(g, R[0], R[1], R[2])] / Re;
+        v = etae[cid(g, R[0], R[1], R[2])];
     beta[foffset(g, a) + fid(g, a, i, j, k)] = v;
 }
 
@@ -264,7 +265,7 @@ __global__ void k_stage_eta_over_re(const CavK* __restrict__ ck, const CavIO* __
     K.etae[q] = IO.eta[q] / K.fl.Re;
 }
 
-// level-0 face viscosities of every cavity
+// level-0 face viscosities of every cavity (after k_stage_eta_over_re)
 template <int DIM>
 __global__ void k_stage_eta_faces(const CavK* __restrict__ ck, const CavIO* __restrict__ io, int zb)
 {
@@ -275,7 +276,7 @@ __global__ void k_stage_eta_faces(const CavK* __restrict__ ck, const CavIO* __re
     if (a >= g.dim) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= fext(g, a, 0) || j >= fext(g, a, 1) || k >= fext(g, a, 2)) return;
-    face_eta(g, a, K.fl.Re, io[cav].eta, K.beta0, i, j, k);
+    face_eta(g, a, K.etae, K.beta0, i, j, k);
 }
 
 void stage_visc_coef(Ctx* c)
