@@ -564,7 +564,7 @@ static void vcycle(Ctx* c, MG& m, int l, int nu1, int nu2)
 {
     using B = LB<R>;
     Level& L = m.L[l];
-    if (l == 1 && !m.capturing && !m.gfail[prec_index<R>()] && m.nlev > 2 && (nu1 + nu2) % 2 == 0) {
+    if (l == 1 && c->graph && !m.capturing && !m.gfail[prec_index<R>()] && m.nlev > 2 && (nu1 + nu2) % 2 == 0) {
         coarse_graph<R>(c, m, nu1, nu2);
         return;
     }
@@ -1393,6 +1393,13 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
         // HB_FINE3=k selects the finest 3D tensor smoother (experiment switch)
         const char* f3 = std::getenv("HB_FINE3");
         c->fine3 = f3 ? std::atoi(f3) : 0;
+        // HB_GRAPH=1: the coarse levels of a V-cycle are replayed as one
+        // captured graph instead of launched one by one.  Off by default: the
+        // host issues a step's launches without waiting on the device, so it
+        // stays ahead of the queue, and a graph replay costs the device more
+        // time than the same kernels launched directly.
+        const char* gr = std::getenv("HB_GRAPH");
+        c->graph = gr && gr[0] == '1';
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 8192) {
             c->lds_budget = (size_t)lim - 4096;

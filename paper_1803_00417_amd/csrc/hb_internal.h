@@ -408,6 +408,7 @@ struct Ctx {
     bool tail = false;            // coarse levels in one single-workgroup launch
     bool fuse = true;             // fused-colour nodal sweeps
     int fine3 = 0;                // finest 3D tensor smoother variant
+    bool graph = false;           // coarse levels replayed as a captured graph
     std::string err;
 };
 

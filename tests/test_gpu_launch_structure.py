@@ -2,10 +2,12 @@
 replace: the single-workgroup coarse V-cycle (every level below a size limit
 in one launch, data in LDS; HB_TAIL=0 turns it off), the fused sweeps (all
 colours, or in 2D both tensor components, of a sweep in one launch;
-HB_FUSE=0), and each candidate tile of the autotuned sweeps (HB_TILE=k
+HB_FUSE=0), each candidate tile of the autotuned sweeps (HB_TILE=k
 forces candidate k; in 2D, candidates 3.. of the tensor sweep stage
 everything in LDS and run two sweeps per launch where the level allows it,
-as do the nodal sweeps and the MAC sweeps).
+as do the nodal sweeps and the MAC sweeps), and the coarse levels of a
+V-cycle replayed as a captured HIP graph (HB_GRAPH=1) instead of launched
+one by one.
 
 Each runs the same arithmetic per cell or node in the same order (the same
 Gauss-Seidel ordering, residual, restriction, prolongation and FP64
@@ -50,11 +52,13 @@ PLAIN = {"tail": {"HB_TAIL": "0"}, "fuse": {"HB_FUSE": "0"}, "both": {"HB_TAIL":
          # on every level with the coarse tail off
          "tile3": {"HB_TILE": "3"}, "tile4_notail": {"HB_TILE": "4", "HB_TAIL": "0"},
          "tile5_notail": {"HB_TILE": "5", "HB_TAIL": "0"}, "tile6": {"HB_TILE": "6"},
-         "tile6_notail": {"HB_TILE": "6", "HB_TAIL": "0"}, "tile7": {"HB_TILE": "7"}}
+         "tile6_notail": {"HB_TILE": "6", "HB_TAIL": "0"}, "tile7": {"HB_TILE": "7"},
+         # coarse levels replayed as a captured graph
+         "graph": {"HB_GRAPH": "1"}, "graph_notail": {"HB_GRAPH": "1", "HB_TAIL": "0"}}
 
 
 def _context(make, env):
-    old = {k: os.environ.get(k) for k in ("HB_TAIL", "HB_FUSE", "HB_TILE")}
+    old = {k: os.environ.get(k) for k in ("HB_TAIL", "HB_FUSE", "HB_TILE", "HB_GRAPH")}
     for k in old:
         os.environ.pop(k, None)
     os.environ.update(env)
@@ -114,7 +118,7 @@ def test_launch_structure_in_batch_is_bit_identical():
     specs = [CASES["lid2d_64"](), CASES["lid2d_96x48"](), lid_spec(2, 16, Re=5.0, HB=3.0, nidx=0.4, Pa=400.0),
              CASES["chan2d_8x32"]()]
     outs = []
-    for env in ({}, PLAIN["both"]):
+    for env in ({}, PLAIN["both"], PLAIN["graph"]):
         objs = [hip_objs(s) for s in specs]
         ctx = _context(lambda: hb.BatchContext([g for g, _ in objs], [f for _, f in objs], hb.make_step_opts()),
                        env)
@@ -127,9 +131,10 @@ def test_launch_structure_in_batch_is_bit_identical():
             ctx.step(us, ps, [_dt(s) for s in specs])
         outs.append(([host(u) for u in us], [host(p) for p in ps]))
         ctx.close()
-    for b in range(len(specs)):
-        assert np.array_equal(outs[0][0][b], outs[1][0][b]), b
-        assert np.array_equal(outs[0][1][b], outs[1][1][b]), b
+    for o in outs[1:]:
+        for b in range(len(specs)):
+            assert np.array_equal(outs[0][0][b], o[0][b]), b
+            assert np.array_equal(outs[0][1][b], o[1][b]), b
 
 
 def test_autotuner_reports_candidate_tiles():
