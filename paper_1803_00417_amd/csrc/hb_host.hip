@@ -760,22 +760,27 @@ static void solve_core(Ctx* c, MG& m, double* x, double* b, const hb_mg_opts& o)
     seg_fill(c, sv, v, 0.0);
     bicg_init_scalars(c, c->act);
     cl.check(CV_INIT, 0);
+    // Each dot product is a partial pass whose total the kernel that needs
+    // the scalar takes itself; rho's partials after the first come from the
+    // update of r.
+    double* rp = rho_partials(c);
+    seg_dot_part(c, sv, rh, r, nullptr, rp, -1);
     // a cavity may take one V-cycle past max_cycles (its last half step)
     for (int k = 0; k < o.max_cycles + 1; k += 2) {
-        seg_dot_then(c, sv, rh, r, S_DOT0, 1, -1);   // rho, beta
-        bicg_p_dev(c, sv, p, r, v);
+        bicg_p_rho(c, sv, p, r, v, rp);   // rho, beta; p = r + beta (p - omega v)
         precond(c, m, p, ph, o.nu1, o.nu2, lo);
         apply0(c, m, ph, v);
-        seg_dot_then(c, sv, rh, v, S_DOT1, 2, S_MAX);   // alpha; S_MAX cleared for the max of s
-        sub_scaled_max_dev(c, sv, s, r, S_ALPHA, v, S_MAX);
+        seg_dot_part(c, sv, rh, v, nullptr, c->partial, S_MAX);   // r^.v; S_MAX cleared for the max of s
+        bicg_s_alpha(c, sv, s, r, v, c->partial, S_MAX);           // alpha; s = r - alpha v
         cl.check(CV_HALF);
         // cavities that finish at the half step: x += alpha ph, r = s
         bicg_half_finish(c, seg_of(m, c->act2), x, ph, r, s);
         if (!cl.lagged_active()) break;
         precond(c, m, s, sh, o.nu1, o.nu2, lo);
         apply0(c, m, sh, t);
-        seg_dot2_then(c, sv, t, t, S_DOT0, s, S_DOT1, 3, S_MAX);   // t.t, t.s, omega; S_MAX cleared for the max of r
-        bicg_full_update(c, sv, x, ph, sh, r, s, t, S_MAX);       // x += alpha ph + omega sh, r = s - omega t
+        seg_dot_part(c, sv, t, t, s, c->partial, S_MAX);   // t.t, t.s; S_MAX cleared for the max of r
+        // omega; x += alpha ph + omega sh, r = s - omega t, the next rho's partials
+        bicg_full_update(c, sv, x, ph, sh, r, s, t, S_MAX, c->partial, rh, rp);
         cl.check(CV_FULL);
         if (!cl.lagged_active()) break;
     }
@@ -1344,7 +1349,7 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
               hipHostGetDevicePointer((void**)&c->dring, c->hring, 0) == hipSuccess &&
               hipHostGetDevicePointer((void**)&c->dhsc, c->hsc, 0) == hipSuccess &&
               hipHostGetDevicePointer((void**)&c->dhseq, c->hseq, 0) == hipSuccess &&
-              dalloc(&c->partial, 2L * kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
+              dalloc(&c->partial, 3L * kRedBlocks * count) == hipSuccess && dalloc(&c->act, count) == hipSuccess &&
               dalloc(&c->mpart, (long)kSubMax * count) == hipSuccess &&
               hipMemsetAsync(c->mpart, 0, sizeof(unsigned long long) * kSubMax * count, c->s) == hipSuccess &&
               dalloc(&c->act2, count) == hipSuccess && dalloc(&c->sel, count) == hipSuccess &&

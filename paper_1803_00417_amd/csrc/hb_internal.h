@@ -383,7 +383,7 @@ struct Ctx {
     const int* mf_act = nullptr;
     double wait_s = 0.0;                  // host time spent waiting for the device (HB_STATS=1)
     long waits = 0;
-    double* partial = nullptr;   // reduction partials (2 x kRedBlocks per cavity)
+    double* partial = nullptr;   // reduction partials (3 x kRedBlocks per cavity)
     unsigned long long* mpart = nullptr;   // max-norm partials (kSubMax per cavity, kept zero between uses)
     int* act = nullptr;          // device active flags (nb)
     int* hact = nullptr;         // pinned host staging of the flags
@@ -472,8 +472,11 @@ void flush_max_final(Ctx* c);
 // BiCGStab: x += alpha ph, r = s (cavities finishing at the half step); and
 // x += alpha ph + omega sh, r = s - omega t with max|r| into slot mslot
 void bicg_half_finish(Ctx* c, const SegV& s, double* x, const double* ph, double* r, const double* sv);
+// omega from the partials of t.t and t.s, x += alpha ph + omega sh, r = s -
+// omega t with its max-norm into mslot, and the partials of the next rho
 void bicg_full_update(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, double* r,
-                      const double* sv, const double* t, int mslot);
+                      const double* sv, const double* t, int mslot, const double* part, const double* rh,
+                      double* rpart);
 // wait until check point seq has published; returns its active count (-1
 // if it never did, even after a stream synchronisation)
 int wait_active(Ctx* c, unsigned long long seq);
@@ -483,13 +486,10 @@ void fill(Ctx* c, double* dst, double v, long n);
 void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot);
 void seg_set_zero(Ctx* c, int slot);                       // every cavity
 void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot);
-// the same, then BiCGStab scalar update `then` (1 rho and beta, 2 alpha)
-// and clearing slot `zero` (-1: none)
-void seg_dot_then(Ctx* c, const SegV& s, const double* a, const double* b, int slot, int then, int zero);
-// slot0 = a.b0 and slot1 = a.b1 in one pass, then scalar update `then` (3
-// omega) and clearing slot `zero`
-void seg_dot2_then(Ctx* c, const SegV& s, const double* a, const double* b0, int slot0, const double* b1, int slot1,
-                   int then, int zero);
+// partial pass only: a.b0 (and a.b1) per block into part, clearing slot
+// `zero` (-1: none); the kernel that uses the product totals the partials
+void seg_dot_part(Ctx* c, const SegV& s, const double* a, const double* b0, const double* b1, double* part, int zero);
+double* rho_partials(Ctx* c);   // partials of BiCGStab's rho (the third row block of c->partial)
 void seg_sub_mean(Ctx* c, const SegV& s, double* v);
 void seg_copy(Ctx* c, const SegV& s, double* dst, const double* src);
 void seg_fill(Ctx* c, const SegV& s, double* dst, double v);
@@ -500,8 +500,10 @@ void seg_from_f32(Ctx* c, const SegV& s, const float* e, double* x);
 void flat_to_f32(Ctx* c, const double* src, float* dst, long n);
 // device-scalar BiCGStab steps (scalars in each cavity's slots S_RHO .. S_BETA)
 void bicg_init_scalars(Ctx* c, const int* act);
-void bicg_p_dev(Ctx* c, const SegV& s, double* p, const double* r, const double* v);
-void sub_scaled_max_dev(Ctx* c, const SegV& s, double* out, const double* a, int sslot, const double* b, int mslot);
+// rho and beta from rho's partials, p = r + beta (p - omega v)
+void bicg_p_rho(Ctx* c, const SegV& s, double* p, const double* r, const double* v, const double* part);
+// alpha from the partials of r^.v, s = r - alpha v with its max-norm into mslot
+void bicg_s_alpha(Ctx* c, const SegV& s, double* out, const double* r, const double* v, const double* part, int mslot);
 void bicg_x_dev(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, bool with_omega);
 
 // ---- viscosity and tensor operator, per cavity (hb_visc.hip) ----------------

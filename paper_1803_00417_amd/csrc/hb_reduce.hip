@@ -468,39 +468,37 @@ void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot)
     k_seg_maxabs<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, v, c->sc, slot);
 }
 
-// one BiCGStab scalar update of a cavity's slots (which: 0 initial values,
-// 1 rho and beta, 2 alpha, 3 omega)
-__device__ inline void bicg_scalar(double* sc, int which)
+// BiCGStab's scalars, each in one place: the initial values, beta from the
+// new rho, alpha from r^.v, omega from (t.t, t.s)
+__device__ inline void bicg_init(double* sc)
 {
-    if (which == 0) {            // initial values
-        sc[S_RHOP] = 1.0;
-        sc[S_ALPHA] = 1.0;
-        sc[S_OMEGA] = 1.0;
-    } else if (which == 1) {     // rho and beta
-        const double rho = sc[S_DOT0];
-        sc[S_RHO] = rho;
-        sc[S_BETA] = (rho / sc[S_RHOP]) * (sc[S_ALPHA] / sc[S_OMEGA]);
-    } else if (which == 2) {     // alpha
-        sc[S_ALPHA] = sc[S_RHO] / sc[S_DOT1];
-    } else {                     // omega from (t.t, t.s); rho_prev = rho
-        const double tt = sc[S_DOT0];
-        sc[S_OMEGA] = tt > 0.0 ? sc[S_DOT1] / tt : 0.0;
-        sc[S_RHOP] = sc[S_RHO];
-    }
+    sc[S_RHOP] = 1.0;
+    sc[S_ALPHA] = 1.0;
+    sc[S_OMEGA] = 1.0;
 }
+__device__ inline double bicg_beta(const double* sc, double rho)
+{
+    return (rho / sc[S_RHOP]) * (sc[S_ALPHA] / sc[S_OMEGA]);
+}
+__device__ inline double bicg_alpha(const double* sc, double rv) { return sc[S_RHO] / rv; }
+__device__ inline double bicg_omega(double tt, double ts) { return tt > 0.0 ? ts / tt : 0.0; }
 
-// BiCGStab dot products: a partial pass (one or two products of a with b0,
-// b1 per block; block x of cavity y owns the index set
-// {x*T + t + k*kRedBlocks*T}, so every run gives the same bits) and a final pass of one block per cavity that adds the partials
-// in a fixed order, applies the scalar update that
-// follows (`then`) and clears slot `zero` (the max-norm slot the next
-// update kernel fills with atomic maxima).  No block waits on another: a
-// device-scope release per block would write back the XCD's L2 each time.
+// Dot products: a partial pass (one or two products of a with b0, b1 per
+// block; block x of cavity y owns the index set {x*T + t + k*kRedBlocks*T},
+// so every run gives the same bits) and a total of the partials in a fixed
+// order, taken either by a final pass of one block per cavity (dot_total in
+// k_seg_dot_final) or by every block of the kernel that uses the product
+// (the BiCGStab updates below).  No block waits on another: a device-scope
+// release per block would write back the XCD's L2 each time.  The partial
+// pass also clears slot `zero` (-1: none), the max-norm slot the kernel
+// after it fills with atomic maxima.
 __global__ void k_seg_dot_partial(SegV sv, const double* __restrict__ a, const double* __restrict__ b0,
-                                  const double* __restrict__ b1, double* __restrict__ part)
+                                  const double* __restrict__ b1, double* __restrict__ part, double* __restrict__ scb,
+                                  int zero)
 {
     __shared__ double sh[kT / 64];
     SEG_ENTER(sv, off, n);
+    if (zero >= 0 && blockIdx.x == 0 && threadIdx.x == 0) scb[(long)cav_ * S_NSLOT + zero] = 0.0;
     double s0 = 0.0, s1 = 0.0;
     SEG_LOOP(i, n)
     {
@@ -515,50 +513,51 @@ __global__ void k_seg_dot_partial(SegV sv, const double* __restrict__ a, const d
     }
 }
 
-__global__ void k_seg_dot_final(SegV sv, const double* __restrict__ part, double* __restrict__ scb, int slot0,
-                                int slot1, int then, int zero)
+// total of partial row `row` (kRedBlocks words) in a block of kT threads:
+// thread t adds words t, t + kT, ..., then the block's fixed tree; the
+// result is returned to every thread
+__device__ inline double dot_total(const double* __restrict__ part, long row, double* sh, double* bcast)
 {
-    __shared__ double sh[kT / 64];
+    double t0 = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) t0 += part[row * kRedBlocks + i];
+    t0 = block_sum(t0, sh);
+    if (threadIdx.x == 0) *bcast = t0;
+    __syncthreads();
+    return *bcast;
+}
+
+__global__ void k_seg_dot_final(SegV sv, const double* __restrict__ part, double* __restrict__ scb, int slot0,
+                                int slot1)
+{
+    __shared__ double sh[kT / 64], bc;
     const int cav = blockIdx.x;
     if (sv.act && !sv.act[cav]) return;
-    double t0 = 0.0, t1 = 0.0;
-    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) t0 += part[(long)cav * kRedBlocks + i];
-    t0 = block_sum(t0, sh);
-    if (slot1 >= 0) {
-        for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) t1 += part[((long)gridDim.x + cav) * kRedBlocks + i];
-        t1 = block_sum(t1, sh);
-    }
+    const double t0 = dot_total(part, cav, sh, &bc);
+    const double t1 = slot1 >= 0 ? dot_total(part, (long)gridDim.x + cav, sh, &bc) : 0.0;
     if (threadIdx.x == 0) {
         double* sc = scb + (long)cav * S_NSLOT;
         sc[slot0] = t0;
         if (slot1 >= 0) sc[slot1] = t1;
-        if (then) bicg_scalar(sc, then);
-        if (zero >= 0) sc[zero] = 0.0;
     }
 }
 
-static void dot_launch(Ctx* c, const SegV& s, const double* a, const double* b0, const double* b1, int slot0, int slot1,
-                       int then, int zero)
+void seg_dot_part(Ctx* c, const SegV& s, const double* a, const double* b0, const double* b1, double* part, int zero)
 {
-    k_seg_dot_partial<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, a, b0, b1, c->partial);
-    k_seg_dot_final<<<c->nb, kT, 0, c->s>>>(s, c->partial, c->sc, slot0, b1 ? slot1 : -1, then, zero);
+    k_seg_dot_partial<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, a, b0, b1, part, c->sc, zero);
+}
+
+static void dot_launch(Ctx* c, const SegV& s, const double* a, const double* b0, const double* b1, int slot0, int slot1)
+{
+    seg_dot_part(c, s, a, b0, b1, c->partial, -1);
+    k_seg_dot_final<<<c->nb, kT, 0, c->s>>>(s, c->partial, c->sc, slot0, b1 ? slot1 : -1);
 }
 
 void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot)
 {
-    dot_launch(c, s, a, b, nullptr, slot, -1, 0, -1);
+    dot_launch(c, s, a, b, nullptr, slot, -1);
 }
 
-void seg_dot_then(Ctx* c, const SegV& s, const double* a, const double* b, int slot, int then, int zero)
-{
-    dot_launch(c, s, a, b, nullptr, slot, -1, then, zero);
-}
-
-void seg_dot2_then(Ctx* c, const SegV& s, const double* a, const double* b0, int slot0, const double* b1, int slot1,
-                   int then, int zero)
-{
-    dot_launch(c, s, a, b0, b1, slot0, slot1, then, zero);
-}
+double* rho_partials(Ctx* c) { return c->partial + 2L * kRedBlocks * c->nb; }
 
 // v -= sum(v) / n per cavity, the sum taken from the slot
 __global__ void k_seg_sub_mean(SegV sv, double* __restrict__ v, const double* __restrict__ sc)
@@ -570,7 +569,7 @@ __global__ void k_seg_sub_mean(SegV sv, double* __restrict__ v, const double* __
 
 void seg_sub_mean(Ctx* c, const SegV& s, double* v)
 {
-    dot_launch(c, s, v, nullptr, nullptr, S_SUM, -1, 0, -1);
+    dot_launch(c, s, v, nullptr, nullptr, S_SUM, -1);
     k_seg_sub_mean<<<seg_grid(c, 4096L * c->nb), kT, 0, c->s>>>(s, v, c->sc);
 }
 
@@ -662,58 +661,73 @@ void flat_to_f32(Ctx* c, const double* src, float* dst, long n)
 
 // ---- BiCGStab updates, with each cavity's scalars read from its slots -------
 
-__global__ void k_bicg_scalars(double* scb, int nb, const int* act, int which)
+__global__ void k_bicg_init(double* scb, int nb, const int* act)
 {
     const int cav = blockIdx.x * blockDim.x + threadIdx.x;
     if (cav >= nb || (act && !act[cav])) return;
-    bicg_scalar(scb + (long)cav * S_NSLOT, which);
+    bicg_init(scb + (long)cav * S_NSLOT);
 }
 
-static void bicg_scalars(Ctx* c, const int* act, int which)
+void bicg_init_scalars(Ctx* c, const int* act)
 {
-    k_bicg_scalars<<<(c->nb + 63) / 64, 64, 0, c->s>>>(c->sc, c->nb, act, which);
+    k_bicg_init<<<(c->nb + 63) / 64, 64, 0, c->s>>>(c->sc, c->nb, act);
 }
-void bicg_init_scalars(Ctx* c, const int* act) { bicg_scalars(c, act, 0); }
 
-// p = r + beta (p - omega v)
-__global__ void k_bicg_p_dev(SegV sv, double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
-                             const double* __restrict__ scb)
+// rho = r^.r from its partials (every block takes the same total), beta;
+// p = r + beta (p - omega v).  Block 0 of the cavity records rho and beta.
+__global__ void k_bicg_p_rho(SegV sv, double* __restrict__ p, const double* __restrict__ r,
+                             const double* __restrict__ v, double* __restrict__ scb, const double* __restrict__ part)
 {
+    __shared__ double sh[kT / 64], bc;
     SEG_ENTER(sv, off, n);
-    const double* sc = scb + (long)cav_ * S_NSLOT;
-    const double beta = sc[S_BETA], omega = sc[S_OMEGA];
+    double* sc = scb + (long)cav_ * S_NSLOT;
+    const double rho = dot_total(part, cav_, sh, &bc);
+    const double beta = bicg_beta(sc, rho), omega = sc[S_OMEGA];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_DOT0] = rho;
+        sc[S_RHO] = rho;
+        sc[S_BETA] = beta;
+    }
     SEG_LOOP(i, n) p[off + i] = r[off + i] + beta * (p[off + i] - omega * v[off + i]);
 }
 
-void bicg_p_dev(Ctx* c, const SegV& s, double* p, const double* r, const double* v)
+void bicg_p_rho(Ctx* c, const SegV& s, double* p, const double* r, const double* v, const double* part)
 {
-    k_bicg_p_dev<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, p, r, v, c->sc);
+    k_bicg_p_rho<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, p, r, v, c->sc, part);
 }
 
-// out = a - s b (s from a slot), with the max-norm of out into another slot
-__global__ void k_sub_scaled_max_dev(SegV sv, double* __restrict__ out, const double* __restrict__ a, int sslot,
-                                     const double* __restrict__ b, double* __restrict__ scb, int mslot)
+// alpha = rho / r^.v from its partials; s = r - alpha v, with the max-norm
+// of s into slot mslot (cleared by the partial pass).  Block 0 records r^.v
+// and alpha.
+__global__ void k_bicg_s_alpha(SegV sv, double* __restrict__ out, const double* __restrict__ r,
+                               const double* __restrict__ v, double* __restrict__ scb, const double* __restrict__ part,
+                               int mslot)
 {
+    __shared__ double shd[kT / 64], bc;
     __shared__ unsigned long long sh[kT / 64];
     SEG_ENTER(sv, off, n);
-    const double s = scb[(long)cav_ * S_NSLOT + sslot];
+    double* sc = scb + (long)cav_ * S_NSLOT;
+    const double rv = dot_total(part, cav_, shd, &bc);
+    const double alpha = bicg_alpha(sc, rv);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_DOT1] = rv;
+        sc[S_ALPHA] = alpha;
+    }
     unsigned long long m = 0ull;
     SEG_LOOP(i, n)
     {
-        const double v = a[off + i] - s * b[off + i];
-        out[off + i] = v;
-        const unsigned long long bb = abits(v);
+        const double w = r[off + i] - alpha * v[off + i];
+        out[off + i] = w;
+        const unsigned long long bb = abits(w);
         m = bb > m ? bb : m;
     }
     m = block_umax(m, sh);
-    if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav_ * S_NSLOT + mslot, m);
+    if (threadIdx.x == 0) atomic_max_bits(sc + mslot, m);
 }
 
-// the max-norm slot must have been cleared (the dot product's final pass
-// before it does so)
-void sub_scaled_max_dev(Ctx* c, const SegV& s, double* out, const double* a, int sslot, const double* b, int mslot)
+void bicg_s_alpha(Ctx* c, const SegV& s, double* out, const double* r, const double* v, const double* part, int mslot)
 {
-    k_sub_scaled_max_dev<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, a, sslot, b, c->sc, mslot);
+    k_bicg_s_alpha<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, r, v, c->sc, part, mslot);
 }
 
 // x += alpha ph + omega sh (with_omega), or x = alpha ph + x
@@ -753,35 +767,53 @@ void bicg_half_finish(Ctx* c, const SegV& s, double* x, const double* ph, double
     k_bicg_half_finish<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, x, ph, r, sv, c->sc);
 }
 
-// x += alpha ph + omega sh; r = s - omega t with max|r| (atomic, into a
-// slot the dot product's final pass cleared)
+// omega from the partials of t.t and t.s; x += alpha ph + omega sh; r = s -
+// omega t with max|r| (atomic, into slot mslot, cleared by the partial
+// pass) and the partials of the next rho = r^.r into rpart.  Launched with
+// kRedBlocks blocks per cavity, so those partials are the ones the partial
+// pass would form.  Block 0 records t.t, t.s, omega and rho_prev = rho.
 __global__ void k_bicg_full_update(SegV sv, double* __restrict__ x, const double* __restrict__ ph,
                                    const double* __restrict__ shv, double* __restrict__ r,
                                    const double* __restrict__ s, const double* __restrict__ t,
-                                   double* __restrict__ scb, int mslot)
+                                   double* __restrict__ scb, int mslot, const double* __restrict__ part,
+                                   const double* __restrict__ rh, double* __restrict__ rpart)
 {
+    __shared__ double shd[kT / 64], bc;
     __shared__ unsigned long long sh[kT / 64];
     SEG_ENTER(sv, off, n);
-    const double* sc = scb + (long)cav_ * S_NSLOT;
-    const double alpha = sc[S_ALPHA], omega = sc[S_OMEGA];
+    double* sc = scb + (long)cav_ * S_NSLOT;
+    const double tt = dot_total(part, cav_, shd, &bc);
+    const double ts = dot_total(part, (long)gridDim.y + cav_, shd, &bc);
+    const double omega = bicg_omega(tt, ts), alpha = sc[S_ALPHA];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_DOT0] = tt;
+        sc[S_DOT1] = ts;
+        sc[S_OMEGA] = omega;
+        sc[S_RHOP] = sc[S_RHO];
+    }
     unsigned long long m = 0ull;
+    double rho = 0.0;
     SEG_LOOP(i, n)
     {
         x[off + i] += alpha * ph[off + i] + omega * shv[off + i];
         const double v = s[off + i] - omega * t[off + i];
         r[off + i] = v;
+        rho += rh[off + i] * v;
         const unsigned long long bb = abits(v);
         m = bb > m ? bb : m;
     }
     m = block_umax(m, sh);
-    if (threadIdx.x == 0) atomic_max_bits(scb + (long)cav_ * S_NSLOT + mslot, m);
+    if (threadIdx.x == 0) atomic_max_bits(sc + mslot, m);
+    rho = block_sum(rho, shd);
+    if (threadIdx.x == 0) rpart[(long)cav_ * kRedBlocks + blockIdx.x] = rho;
 }
 
 void bicg_full_update(Ctx* c, const SegV& s, double* x, const double* ph, const double* shv, double* r,
-                      const double* sv, const double* t, int mslot)
+                      const double* sv, const double* t, int mslot, const double* part, const double* rh,
+                      double* rpart)
 {
-    k_bicg_full_update<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, x, ph, shv, r, sv, t, c->sc,
-                                                                                mslot);
+    k_bicg_full_update<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, x, ph, shv, r, sv, t, c->sc, mslot, part, rh,
+                                                                  rpart);
 }
 
 }  // namespace hb
