@@ -457,14 +457,17 @@ static void smooth(Ctx* c, MG& m, int l, int sweeps, bool pair, const Level* C =
             // both components of the sweep in one launch; with `pair`, two
             // sweeps per launch where the level's candidate runs them so
             const int n = (pair && L.sweeps == 2 && sweeps - s >= 2) ? 2 : 1;
+            // a zero level-0 iterate is not read (nullptr: the sweep takes zeros)
+            const R* xc = (l == 0 && s == 0 && m.zero0) ? nullptr : B::x(L);
             if (s == 0 && C)
                 launch_tsweep2<R>(c, L, paired(v, *C), tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n,
                                   B::x(*C), C->gall, C->o);
             else if (s + n == sweeps && RC)
-                launch_tsweep2<R>(c, L, paired(v, *RC), tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile,
-                                  n, nullptr, RC->gall, RC->o, B::b(*RC), B::x(*RC));
+                launch_tsweep2<R>(c, L, paired(v, *RC), tcoef<R>(m, l), l == 0, xc, B::xo(L), B::b(L), L.tile, n,
+                                  nullptr, RC->gall, RC->o, B::b(*RC), B::x(*RC));
             else
-                launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, B::x(L), B::xo(L), B::b(L), L.tile, n);
+                launch_tsweep2<R>(c, L, v, tcoef<R>(m, l), l == 0, xc, B::xo(L), B::b(L), L.tile, n);
+            if (l == 0) m.zero0 = false;
             L.cur ^= 1;
             s += n - 1;
         } else if (m.op == HB_OP_VISC && (c->dim == 2 || l > 0 || c->fine3 == 1)) {
@@ -651,8 +654,12 @@ static void precond(Ctx* c, MG& m, const double* r, double* z, int nu1, int nu2,
     double* sx = L.xb[0];
     L.b = const_cast<double*>(r);
     L.xb[0] = z;
-    seg_fill(c, sv, z, 0.0);
+    // The 2D fused tensor sweep starts from zeros without reading z; every
+    // other first launch reads it, so z is cleared for them.
+    if (m.op == HB_OP_VISC && c->dim == 2 && c->fuse && nu1 > 0) m.zero0 = true;
+    else seg_fill(c, sv, z, 0.0);
     vcycle<double>(c, m, 0, nu1, nu2);
+    m.zero0 = false;
     if (L.cur != 0) seg_copy(c, sv, z, L.X());
     L.xb[0] = sx;
     L.b = sb;

@@ -255,6 +255,9 @@ struct MG {
     int gnu1[2] = {-1, -1}, gnu2[2] = {-1, -1};
     bool gfail[2] = {false, false};
     bool capturing = false;
+    // level 0's iterate is zero (a preconditioner cycle): the first sweep
+    // takes zeros instead of reading it, so the buffer need not be cleared
+    bool zero0 = false;
     // levels tail_lt.. of a V-cycle run by one workgroup per cavity in LDS
     // (-1: none); its dynamic LDS bytes per precision
     int tail_lt = -1;

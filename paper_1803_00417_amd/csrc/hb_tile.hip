@@ -121,7 +121,7 @@ __device__ inline void fill_batched(const GridD& g, const R* const* q, const boo
         const long idx = inner ? cid(g, i, j, k) : tile_src<DIM>(g, i, j, k, ok, ng);
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-            const R x = q[a][idx];
+            const R x = q[a] ? q[a][idx] : R(0);   // a null array reads as zeros
             v[a][u] = ok ? ((ng && !mirror[a]) ? -x : x) : R(0);
         }
     }
@@ -450,7 +450,8 @@ k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     TILE_ENTER(2, T);
     const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
     const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
-    const R* xcur = xcura + 2 * cell0;
+    // xcura == nullptr: the sweep starts from zeros
+    const R* xcur = xcura ? xcura + 2 * cell0 : nullptr;
     R* xnext = xnexta + 2 * cell0;
     const R* b = ba + 2 * cell0;
     const long N = ncells(g);
@@ -465,7 +466,7 @@ k_tsweep2(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     h2.setup(g, ox, oy, b + N, coef);
     h3.setup(g, ox, oy, b + N, coef);
     {
-        const R* q[3] = {xcur, xcur + N, coef};
+        const R* q[3] = {xcur, xcur ? xcur + N : nullptr, coef};
         const bool mir[3] = {false, false, true};
         fill_batched<2, 4, FINE ? 3 : 2, R, CF>(g, q, mir, s, ox, oy, 0);
     }
@@ -614,8 +615,8 @@ __device__ inline void fill_staged(const GridD& g, const R* __restrict__ x, cons
             sx[u] = src[0];
             sy[u] = src[1];
         }
-        v[ST_X0][u] = x[idx];
-        v[ST_X1][u] = x[N + idx];
+        v[ST_X0][u] = x ? x[idx] : R(0);
+        v[ST_X1][u] = x ? x[N + idx] : R(0);
         // b is read only at cells that are updated, which lie in the box
         v[ST_B0][u] = b[idx];
         v[ST_B1][u] = b[N + idx];
@@ -808,7 +809,8 @@ k_tsweepN(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     TILE_ENTER(2, T);
     const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
     const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
-    const R* xcur = xcura + 2 * cell0;
+    // xcura == nullptr: the sweeps start from zeros
+    const R* xcur = xcura ? xcura + 2 * cell0 : nullptr;
     R* xnext = xnexta + 2 * cell0;
     const R* b = ba + 2 * cell0;
     const long N = ncells(g);
@@ -1522,8 +1524,9 @@ static void tsweep2_impl(Ctx* c, const Level& L, const BV& v, const R* coef, con
     // coarse right-hand side and iterate written (N/4 cells each)
     const double N = level_cells(L);
     const int sweeps = (CAND::STAGED && CAND::NSW >= 2 && nsw == 2) ? 2 : 1;
-    const double bytes =
-        sizeof(R) * (7.0 * N * sweeps + (pe ? 2.0 * N / 4.0 : 0.0) + (bc ? 4.0 * N / 4.0 : 0.0));
+    // (a launch that starts from zeros does not read x: 2 words fewer)
+    const double bytes = sizeof(R) * (7.0 * N * sweeps - (xcur ? 0.0 : 2.0 * N) + (pe ? 2.0 * N / 4.0 : 0.0) +
+                                      (bc ? 4.0 * N / 4.0 : 0.0));
     if constexpr (!CAND::STAGED) {
         using T = Tile<2, 4, CF>;
         const size_t lds = sizeof(R) * (FINE ? 3 : 2) * T::NS;
