@@ -222,8 +222,12 @@ __global__ void __launch_bounds__(1024) k_conv(ConvArgs a, double* __restrict__ 
     }
     nact = block_sum(nact, sh);
     if (threadIdx.x == 0 && a.seq) {
+        // the host reads only this word (the count), so the store needs no
+        // release ordering of the kernel's other writes: a relaxed
+        // system-scope store reaches the coherent pinned ring without the
+        // cache write-back a release would take
         const unsigned long long w = ((unsigned long long)nact << 32) | (a.seq & 0xffffffffull);
-        __hip_atomic_store(ring + a.seq % kRing, w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(ring + a.seq % kRing, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
