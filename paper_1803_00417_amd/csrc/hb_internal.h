@@ -507,7 +507,6 @@ void bicg_init_scalars(Ctx* c, const int* act);
 void bicg_p_rho(Ctx* c, const SegV& s, double* p, const double* r, const double* v, const double* part);
 // alpha from the partials of r^.v, s = r - alpha v with its max-norm into mslot
 void bicg_s_alpha(Ctx* c, const SegV& s, double* out, const double* r, const double* v, const double* part, int mslot);
-void bicg_x_dev(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, bool with_omega);
 
 // ---- viscosity and tensor operator, per cavity (hb_visc.hip) ----------------
 void launch_viscosity(Ctx* c, const Cav& v, const double* u, double* eta);

@@ -734,25 +734,6 @@ void bicg_s_alpha(Ctx* c, const SegV& s, double* out, const double* r, const dou
     k_bicg_s_alpha<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, r, v, c->sc, part, mslot);
 }
 
-// x += alpha ph + omega sh (with_omega), or x = alpha ph + x
-__global__ void k_bicg_x_dev(SegV sv, double* __restrict__ x, const double* __restrict__ ph,
-                             const double* __restrict__ sh_, const double* __restrict__ scb, int with_omega)
-{
-    SEG_ENTER(sv, off, n);
-    const double* sc = scb + (long)cav_ * S_NSLOT;
-    const double alpha = sc[S_ALPHA], omega = sc[S_OMEGA];
-    SEG_LOOP(i, n)
-    {
-        if (with_omega) x[off + i] += alpha * ph[off + i] + omega * sh_[off + i];
-        else x[off + i] = alpha * ph[off + i] + 1.0 * x[off + i];
-    }
-}
-
-void bicg_x_dev(Ctx* c, const SegV& s, double* x, const double* ph, const double* sh, bool with_omega)
-{
-    k_bicg_x_dev<<<seg_grid(c, 8192L * c->nb), kT, 0, c->s>>>(s, x, ph, sh, c->sc, with_omega ? 1 : 0);
-}
-
 // x = alpha ph + x and r = s (the cavities that finish at the half step)
 __global__ void k_bicg_half_finish(SegV sv, double* __restrict__ x, const double* __restrict__ ph,
                                    double* __restrict__ r, const double* __restrict__ s, const double* __restrict__ scb)
