@@ -11,6 +11,17 @@ namespace hb {
 
 static constexpr int kT = 256;
 
+// Blocks per cavity of a max-norm whose blocks meet on one slot: every
+// block's atomic queues on that address, so a few long blocks beat many
+// short ones while they still stream the vector at full rate (a maximum is
+// exact in any order): one block per 8192 values, between 64 and
+// kRedBlocks.
+static long maxnorm_blocks(long n)
+{
+    const long b = n / 8192;
+    return b < 64 ? 64 : (b > kRedBlocks ? kRedBlocks : b);
+}
+
 static unsigned blocks_for(long n, long cap)
 {
     const long nb = (n + kT - 1) / kT;
@@ -411,7 +422,8 @@ __global__ void k_stage_maxabs(const CavK* __restrict__ ck, const CavIO* __restr
 void stage_maxabs(Ctx* c, int field, int slot)
 {
     seg_set_zero(c, slot);
-    k_stage_maxabs<<<dim3(blocks_for(stage_longest(c), kRedBlocks), c->nb), kT, 0, c->s>>>(c->ck, c->cio, field, slot);
+    const long n = stage_longest(c);
+    k_stage_maxabs<<<dim3(blocks_for(n, maxnorm_blocks(n)), c->nb), kT, 0, c->s>>>(c->ck, c->cio, field, slot);
 }
 
 // ---- segmented over the batch -------------------------------------------------
@@ -431,14 +443,21 @@ static long seg_longest(const MG& m)
     return mx;
 }
 
-// grid of a segmented launch: blocks per cavity sized for the longest
-// segment of any level-0 arena, at most cap blocks in total
-static dim3 seg_grid(const Ctx* c, long cap)
+// the longest segment of any level-0 arena
+static long seg_max_len(const Ctx* c)
 {
     long mx = seg_longest(c->visc);
     const long a = seg_longest(c->mac), b = seg_longest(c->nodal);
     if (a > mx) mx = a;
     if (b > mx) mx = b;
+    return mx;
+}
+
+// grid of a segmented launch: blocks per cavity sized for the longest
+// segment of any level-0 arena, at most cap blocks in total
+static dim3 seg_grid(const Ctx* c, long cap)
+{
+    const long mx = seg_max_len(c);
     long per = cap / c->nb;
     if (per < 1) per = 1;
     return dim3(blocks_for(mx, per), c->nb);
@@ -469,7 +488,7 @@ __global__ void k_seg_maxabs(SegV sv, const double* __restrict__ v, double* __re
 void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot)
 {
     seg_set_zero(c, slot);
-    k_seg_maxabs<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, v, c->sc, slot);
+    k_seg_maxabs<<<seg_grid(c, maxnorm_blocks(seg_max_len(c)) * c->nb), kT, 0, c->s>>>(s, v, c->sc, slot);
 }
 
 // BiCGStab's scalars, each in one place: the initial values, beta from the
@@ -701,11 +720,11 @@ void bicg_p_rho(Ctx* c, const SegV& s, double* p, const double* r, const double*
 }
 
 // alpha = rho / r^.v from its partials; s = r - alpha v, with the max-norm
-// of s into slot mslot (cleared by the partial pass).  Block 0 records r^.v
-// and alpha.
+// of s into slot mslot (cleared by the partial pass), or into the partial
+// words mp.  Block 0 records r^.v and alpha.
 __global__ void k_bicg_s_alpha(SegV sv, double* __restrict__ out, const double* __restrict__ r,
                                const double* __restrict__ v, double* __restrict__ scb, const double* __restrict__ part,
-                               int mslot)
+                               int mslot, unsigned long long* __restrict__ mp)
 {
     __shared__ double shd[kT / 64], bc;
     __shared__ unsigned long long sh[kT / 64];
@@ -726,12 +745,29 @@ __global__ void k_bicg_s_alpha(SegV sv, double* __restrict__ out, const double* 
         m = bb > m ? bb : m;
     }
     m = block_umax(m, sh);
-    if (threadIdx.x == 0) atomic_max_bits(sc + mslot, m);
+    if (threadIdx.x == 0) {
+        if (mp) max_partial(mp, cav_, blockIdx.x, m);
+        else atomic_max_bits(sc + mslot, m);
+    }
+}
+
+// The max-norm's blocks meet on the cavity's slot (a batch) or, in a
+// single-cavity context, spread over the partial words that the next
+// convergence check combines into the slot.
+static unsigned long long* bicg_max_words(Ctx* c) { return c->nb == 1 ? c->mpart : nullptr; }
+
+static void bicg_max_final(Ctx* c, int mslot)
+{
+    if (c->nb != 1) return;
+    c->defer_mf = true;
+    launch_max_final(c, c->act, mslot);
 }
 
 void bicg_s_alpha(Ctx* c, const SegV& s, double* out, const double* r, const double* v, const double* part, int mslot)
 {
-    k_bicg_s_alpha<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, r, v, c->sc, part, mslot);
+    k_bicg_s_alpha<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, out, r, v, c->sc, part, mslot,
+                                                                           bicg_max_words(c));
+    bicg_max_final(c, mslot);
 }
 
 // x = alpha ph + x and r = s (the cavities that finish at the half step)
@@ -753,15 +789,17 @@ void bicg_half_finish(Ctx* c, const SegV& s, double* x, const double* ph, double
 }
 
 // omega from the partials of t.t and t.s; x += alpha ph + omega sh; r = s -
-// omega t with max|r| (atomic, into slot mslot, cleared by the partial
-// pass) and the partials of the next rho = r^.r into rpart.  Launched with
+// omega t with max|r| (into slot mslot, cleared by the partial pass, or
+// into the partial words mp) and the partials of the next rho = r^.r into
+// rpart.  Launched with
 // kRedBlocks blocks per cavity, so those partials are the ones the partial
 // pass would form.  Block 0 records t.t, t.s, omega and rho_prev = rho.
 __global__ void k_bicg_full_update(SegV sv, double* __restrict__ x, const double* __restrict__ ph,
                                    const double* __restrict__ shv, double* __restrict__ r,
                                    const double* __restrict__ s, const double* __restrict__ t,
                                    double* __restrict__ scb, int mslot, const double* __restrict__ part,
-                                   const double* __restrict__ rh, double* __restrict__ rpart)
+                                   const double* __restrict__ rh, double* __restrict__ rpart,
+                                   unsigned long long* __restrict__ mp)
 {
     __shared__ double shd[kT / 64], bc;
     __shared__ unsigned long long sh[kT / 64];
@@ -788,7 +826,10 @@ __global__ void k_bicg_full_update(SegV sv, double* __restrict__ x, const double
         m = bb > m ? bb : m;
     }
     m = block_umax(m, sh);
-    if (threadIdx.x == 0) atomic_max_bits(sc + mslot, m);
+    if (threadIdx.x == 0) {
+        if (mp) max_partial(mp, cav_, blockIdx.x, m);
+        else atomic_max_bits(sc + mslot, m);
+    }
     rho = block_sum(rho, shd);
     if (threadIdx.x == 0) rpart[(long)cav_ * kRedBlocks + blockIdx.x] = rho;
 }
@@ -798,7 +839,8 @@ void bicg_full_update(Ctx* c, const SegV& s, double* x, const double* ph, const 
                       double* rpart)
 {
     k_bicg_full_update<<<dim3(kRedBlocks, c->nb), kT, 0, c->s>>>(s, x, ph, shv, r, sv, t, c->sc, mslot, part, rh,
-                                                                  rpart);
+                                                                  rpart, bicg_max_words(c));
+    bicg_max_final(c, mslot);
 }
 
 }  // namespace hb
