@@ -51,7 +51,7 @@ void red_maxabs(Ctx* c, int cav, const double* v, long n, int slot)
     double* out = c->sc + (long)cav * S_NSLOT + slot;
     k_set<<<1, 1, 0, c->s>>>(out, 0.0);
     if (n <= 0) return;
-    k_maxabs<<<blocks_for(n, kRedBlocks), kT, 0, c->s>>>(v, n, out);
+    k_maxabs<<<blocks_for(n, maxnorm_blocks(n)), kT, 0, c->s>>>(v, n, out);
 }
 
 // largest |a - b| (the change of a field over a step)
@@ -72,7 +72,7 @@ void red_maxdiff(Ctx* c, int cav, const double* a, const double* b, long n, int 
     double* out = c->sc + (long)cav * S_NSLOT + slot;
     k_set<<<1, 1, 0, c->s>>>(out, 0.0);
     if (n <= 0) return;
-    k_maxdiff<<<blocks_for(n, kRedBlocks), kT, 0, c->s>>>(a, b, n, out);
+    k_maxdiff<<<blocks_for(n, maxnorm_blocks(n)), kT, 0, c->s>>>(a, b, n, out);
 }
 
 // Publication of the slots: one block copies them into the coherent pinned
