@@ -852,8 +852,7 @@ static void solve_prepared(Ctx* c, MG& m, double* x, const hb_mg_opts& o)
         copy(c, c->capv_r0, m.L[0].r, m.L[0].nu);
         copy(c, c->capv_x0, x, m.L[0].nu);
     }
-    seg_maxabs(c, all, m.lvl0_b, S_MAX);
-    seg_maxabs(c, all, x, S_MAX2);
+    seg_maxabs2(c, all, m.lvl0_b, S_MAX, x, S_MAX2);
     if (o.precision == HB_PREC_MIXED) ensure_f32(c, m);
     ConvLoop(c, m, o).apply(CV_BEGIN);
     // cavities with b = 0 have x = 0

@@ -487,6 +487,7 @@ void copy(Ctx* c, double* dst, const double* src, long n);
 void fill(Ctx* c, double* dst, double v, long n);
 // segmented forms over the batch (per cavity slot, inactive cavities skipped)
 void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot);
+void seg_maxabs2(Ctx* c, const SegV& s, const double* a, int slot0, const double* b, int slot1);
 void seg_set_zero(Ctx* c, int slot);                       // every cavity
 void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot);
 // partial pass only: a.b0 (and a.b1) per block into part, clearing slot

@@ -491,6 +491,43 @@ void seg_maxabs(Ctx* c, const SegV& s, const double* v, int slot)
     k_seg_maxabs<<<seg_grid(c, maxnorm_blocks(seg_max_len(c)) * c->nb), kT, 0, c->s>>>(s, v, c->sc, slot);
 }
 
+__global__ void k_seg_set2(double* sc, int slot0, int slot1, int nb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) {
+        sc[(long)i * S_NSLOT + slot0] = 0.0;
+        sc[(long)i * S_NSLOT + slot1] = 0.0;
+    }
+}
+
+// max |a| into slot0 and max |b| into slot1 of every cavity in one pass
+__global__ void k_seg_maxabs2(SegV sv, const double* __restrict__ a, const double* __restrict__ b,
+                              double* __restrict__ sc, int slot0, int slot1)
+{
+    __shared__ unsigned long long sh[kT / 64];
+    SEG_ENTER(sv, off, n);
+    unsigned long long ma = 0ull, mb = 0ull;
+    SEG_LOOP(i, n)
+    {
+        const unsigned long long x = abits(a[off + i]), y = abits(b[off + i]);
+        ma = x > ma ? x : ma;
+        mb = y > mb ? y : mb;
+    }
+    ma = block_umax(ma, sh);
+    mb = block_umax(mb, sh);
+    if (threadIdx.x == 0) {
+        atomic_max_bits(sc + (long)cav_ * S_NSLOT + slot0, ma);
+        atomic_max_bits(sc + (long)cav_ * S_NSLOT + slot1, mb);
+    }
+}
+
+void seg_maxabs2(Ctx* c, const SegV& s, const double* a, int slot0, const double* b, int slot1)
+{
+    k_seg_set2<<<(c->nb + 63) / 64, 64, 0, c->s>>>(c->sc, slot0, slot1, c->nb);
+    k_seg_maxabs2<<<seg_grid(c, maxnorm_blocks(seg_max_len(c)) * c->nb), kT, 0, c->s>>>(s, a, b, c->sc, slot0,
+                                                                                       slot1);
+}
+
 // BiCGStab's scalars, each in one place: the initial values, beta from the
 // new rho, alpha from r^.v, omega from (t.t, t.s)
 __device__ inline void bicg_init(double* sc)
@@ -582,18 +619,23 @@ void seg_dot(Ctx* c, const SegV& s, const double* a, const double* b, int slot)
 
 double* rho_partials(Ctx* c) { return c->partial + 2L * kRedBlocks * c->nb; }
 
-// v -= sum(v) / n per cavity, the sum taken from the slot
-__global__ void k_seg_sub_mean(SegV sv, double* __restrict__ v, const double* __restrict__ sc)
+// v -= sum(v) / n per cavity, every block totalling the sum's partials
+// itself (block 0 records the sum in slot S_SUM)
+__global__ void k_seg_sub_mean(SegV sv, double* __restrict__ v, double* __restrict__ sc,
+                               const double* __restrict__ part)
 {
+    __shared__ double sh[kT / 64], bc;
     SEG_ENTER(sv, off, n);
-    const double m = sc[(long)cav_ * S_NSLOT + S_SUM] / (double)n;
+    const double sum = dot_total(part, cav_, sh, &bc);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[(long)cav_ * S_NSLOT + S_SUM] = sum;
+    const double m = sum / (double)n;
     SEG_LOOP(i, n) v[off + i] -= m;
 }
 
 void seg_sub_mean(Ctx* c, const SegV& s, double* v)
 {
-    dot_launch(c, s, v, nullptr, nullptr, S_SUM, -1);
-    k_seg_sub_mean<<<seg_grid(c, 4096L * c->nb), kT, 0, c->s>>>(s, v, c->sc);
+    seg_dot_part(c, s, v, nullptr, nullptr, c->partial, -1);
+    k_seg_sub_mean<<<seg_grid(c, (long)kRedBlocks * c->nb), kT, 0, c->s>>>(s, v, c->sc, c->partial);
 }
 
 __global__ void k_seg_copy(SegV sv, double* __restrict__ d, const double* __restrict__ s)
