@@ -169,9 +169,11 @@ __device__ inline unsigned long long abits(double v)
     return (unsigned long long)__double_as_longlong(fabs(v));
 }
 
+// (a maximum with 0 changes no word: blocks without values, such as those
+// past the end of a small cavity of a batch, issue no atomic)
 __device__ inline void atomic_max_bits(double* addr, unsigned long long v)
 {
-    atomicMax(reinterpret_cast<unsigned long long*>(addr), v);
+    if (v) atomicMax(reinterpret_cast<unsigned long long*>(addr), v);
 }
 
 // block-wide unsigned max (block of at most 1024 threads); valid in thread 0
