@@ -29,6 +29,8 @@ struct TileShape {
 template <int DIM> struct TileCfg;
 template <> struct TileCfg<2> : TileShape<64, 8, 1, 256> {};
 template <> struct TileCfg<3> : TileShape<32, 4, 4, 512> {};
+// tile of the 3D fused MAC sweep (k_mac_sweep)
+using Mac3Tile = TileShape<32, 8, 8, 1024>;
 // Candidates of the 2D fused tensor sweep, chosen per level by the
 // autotuner (index 0 is the default): the tile with its thread count, the
 // most sweeps one launch may run (NSW), and whether b and the face
@@ -185,11 +187,11 @@ __device__ inline R tile_visc_div(const GridD& g, const R* bfc, const R* s, cons
 // cell of the active colour walked by thread slot t of a region (the tile
 // plus `ring` cells); returns false when t is past the region or the cell lies
 // beyond a wall.  Cells across a periodic boundary are the wrapped cells.
-template <int DIM>
+template <int DIM, class CF = TileCfg<DIM>>
 __device__ inline bool colour_cell(const GridD& g, int t, int ring, int colour, int ox, int oy, int oz, int G[3],
                                    int L[3])
 {
-    using T = Tile<DIM, 2>;
+    using T = Tile<DIM, 2, CF>;
     const int RX = T::TX + 2 * ring, RY = T::TY + 2 * ring, RZ = DIM == 3 ? T::TZ + 2 * ring : 1;
     const int HX = RX / 2;
     if (t >= HX * RY * RZ) {
@@ -889,13 +891,13 @@ k_tsweepN(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
 // one-colour kernel, whose per-cell arithmetic this repeats, so the result
 // is the same bit for bit.
 // ---------------------------------------------------------------------------
-template <int DIM, typename R>
-__global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
+template <int DIM, typename R, class CF = TileCfg<DIM>>
+__global__ void __launch_bounds__(CF::THREADS)
 k_mac_sweep(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* __restrict__ ba)
 {
-    using T = Tile<DIM, 2>;
+    using T = Tile<DIM, 2, CF>;
     TILE_ENTER(DIM, T);
-    constexpr int TH = TileCfg<DIM>::THREADS;
+    constexpr int TH = CF::THREADS;
     constexpr int RZ1 = DIM == 3 ? T::TZ + 2 : 1;
     constexpr int KR = ((T::TX + 2) / 2 * (T::TY + 2) * RZ1 + TH - 1) / TH;
     constexpr int KB = (T::TX / 2 * T::TY * T::TZ + TH - 1) / TH;
@@ -909,7 +911,7 @@ k_mac_sweep(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* __
     // a colour's slots: LDS index, neighbour mask (bit 2a + side), diagonal, b
     auto setup = [&](int t, int ring, int colour, int& L, int& m, R& dg, R& bq) {
         int G[3], Lc[3];
-        const bool ok = colour_cell<DIM>(g, t, ring, colour, ox, oy, oz, G, Lc);
+        const bool ok = colour_cell<DIM, CF>(g, t, ring, colour, ox, oy, oz, G, Lc);
         L = T::at(Lc[0], Lc[1], Lc[2]);
         int cnt = 0;
         m = 0;
@@ -934,7 +936,7 @@ k_mac_sweep(BV v, const R* __restrict__ cura, R* __restrict__ nexta, const R* __
     {
         const R* q[1] = {cur};
         const bool mir[1] = {false};
-        fill_batched<DIM, 2, 1, R>(g, q, mir, s, ox, oy, oz);
+        fill_batched<DIM, 2, 1, R, CF>(g, q, mir, s, ox, oy, oz);
     }
     __syncthreads();
     auto update = [&](int l, int m, R dg, R bq) {
@@ -1681,8 +1683,11 @@ void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next
         const dim3 grid = tile_grid<2>(c, L, vv);
         k_mac_sweep<2, R><<<grid, TileCfg<2>::THREADS, sizeof(R) * Tile<2, 2>::NS, c->s>>>(vv, cur, next, b);
     } else {
-        const dim3 grid = tile_grid<3>(c, L, vv);
-        k_mac_sweep<3, R><<<grid, TileCfg<3>::THREADS, sizeof(R) * Tile<3, 2>::NS, c->s>>>(vv, cur, next, b);
+        // 3D: a 32x8x8 tile with 1024 threads stages 2.5 positions per cell
+        // (halo 2) where the 32x4x4 default tile stages 4.5
+        using CF = Mac3Tile;
+        const dim3 grid = tile_grid<3, CF>(c, L, vv);
+        k_mac_sweep<3, R, CF><<<grid, CF::THREADS, sizeof(R) * Tile<3, 2, CF>::NS, c->s>>>(vv, cur, next, b);
     }
 }
 
