@@ -1416,6 +1416,7 @@ static int create_ctx(const hb_grid* grids, const hb_fluid* fluids, int count, c
             c->lds_budget = (size_t)lim - 4096;
             tail_allow_lds(c->lds_budget);
             sweep2_allow_lds(c->lds_budget);
+            tsmooth_allow_lds(c->lds_budget);
         }
     }
     int rc;

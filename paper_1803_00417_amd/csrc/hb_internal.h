@@ -545,6 +545,7 @@ void launch_tsweep2(Ctx* c, const Level& L, const BV& v, const R* coef, bool fin
 SweepShape sweep2_shape(int tile);
 size_t sweep2_lds(int tile, int nsw);
 void sweep2_allow_lds(size_t bytes);
+void tsmooth_allow_lds(size_t bytes);
 template <typename R>
 void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b);
 template <typename R>

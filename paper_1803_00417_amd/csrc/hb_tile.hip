@@ -31,6 +31,9 @@ template <> struct TileCfg<2> : TileShape<64, 8, 1, 256> {};
 template <> struct TileCfg<3> : TileShape<32, 4, 4, 512> {};
 // tile of the 3D fused MAC sweep (k_mac_sweep)
 using Mac3Tile = TileShape<32, 8, 8, 1024>;
+// tile of the 3D coarse-level tensor smoother (k_tsmooth): a deeper tile
+// than TileCfg<3> stages fewer halo cells per updated cell
+using Tsm3Tile = TileShape<16, 8, 8, 1024>;
 // Candidates of the 2D fused tensor sweep, chosen per level by the
 // autotuner (index 0 is the default): the tile with its thread count, the
 // most sweeps one launch may run (NSW), and whether b and the face
@@ -239,12 +242,12 @@ extern __shared__ __align__(16) unsigned char tile_lds[];
     if (ox >= g.n[0] || oy >= g.n[1] || oz >= g.n[2]) return;                               \
     const long cell0 = bv_o(v, cav);
 
-template <int DIM, bool FINE, int c, typename R>
-__global__ void __launch_bounds__(TileCfg<DIM>::THREADS)
+template <int DIM, bool FINE, int c, typename R, class CF = TileCfg<DIM>>
+__global__ void __launch_bounds__(CF::THREADS)
 k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, const R* __restrict__ xcura,
           const R* xnext_ina, R* xnexta, const R* __restrict__ ba)
 {
-    using T = Tile<DIM, 2>;
+    using T = Tile<DIM, 2, CF>;
     TILE_ENTER(DIM, T);
     const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
     const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
@@ -252,7 +255,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
     const R* xnext_in = xnext_ina + DIM * cell0;
     R* xnext = xnexta + DIM * cell0;
     const R* b = ba + DIM * cell0;
-    constexpr int TH = TileCfg<DIM>::THREADS;
+    constexpr int TH = CF::THREADS;
     constexpr int RZ1 = DIM == 3 ? T::TZ + 2 : 1;
     constexpr int KR = ((T::TX + 2) / 2 * (T::TY + 2) * RZ1 + TH - 1) / TH;   // red slots per thread
     constexpr int KB = (T::TX / 2 * T::TY * T::TZ + TH - 1) / TH;            // black slots per thread
@@ -268,7 +271,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
 #pragma unroll
     for (int u = 0; u < KR; ++u) {
         int L[3];
-        rOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 1, 0, ox, oy, oz, rG[u], L);
+        rOk[u] = colour_cell<DIM, CF>(g, threadIdx.x + u * TH, 1, 0, ox, oy, oz, rG[u], L);
         rL[u] = T::at(L[0], L[1], L[2]);
         rB[u] = bc[cid_clamped(g, rG[u])];
         if (!FINE) load_faces<DIM, R>(g, coef, rG[u], rF[u]);
@@ -279,7 +282,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
 #pragma unroll
     for (int u = 0; u < KB; ++u) {
         int L[3];
-        kOk[u] = colour_cell<DIM>(g, threadIdx.x + u * TH, 0, 1, ox, oy, oz, kG[u], L);
+        kOk[u] = colour_cell<DIM, CF>(g, threadIdx.x + u * TH, 0, 1, ox, oy, oz, kG[u], L);
         kL[u] = T::at(L[0], L[1], L[2]);
         kB[u] = bc[cid_clamped(g, kG[u])];
         if (!FINE) load_faces<DIM, R>(g, coef, kG[u], kF[u]);
@@ -291,7 +294,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
         for (int a = 0; a < DIM; ++a) { q[a] = (a < c ? xnext_in : xcur) + a * N; mir[a] = false; }
         q[DIM] = coef;
         mir[DIM] = true;
-        fill_batched<DIM, 2, DIM + (FINE ? 1 : 0), R>(g, q, mir, s, ox, oy, oz);
+        fill_batched<DIM, 2, DIM + (FINE ? 1 : 0), R, CF>(g, q, mir, s, ox, oy, oz);
     }
     __syncthreads();
     R* sc = s + c * T::NS;
@@ -310,7 +313,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
             if (threadIdx.x + u * TH >= NR) continue;
             R dg;
             const R vd =
-                tile_visc_div<DIM, 2, FINE, R>(g, rF[u], s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
+                tile_visc_div<DIM, 2, FINE, R, CF>(g, rF[u], s, e, c, rG[u], wall_mask<DIM>(g, rG[u]), rL[u], dt, &dg);
             const R xc = sc[rL[u]];
             const R Au = xc - dt * vd;
             nv[u] = xc + (rB[u] - Au) / dg;
@@ -327,7 +330,7 @@ k_tsmooth(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, con
             if (threadIdx.x + u * TH >= NB) continue;
             R dg;
             const R vd =
-                tile_visc_div<DIM, 2, FINE, R>(g, kF[u], s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
+                tile_visc_div<DIM, 2, FINE, R, CF>(g, kF[u], s, e, c, kG[u], wall_mask<DIM>(g, kG[u]), kL[u], dt, &dg);
             const R xc = sc[kL[u]];
             const R Au = xc - dt * vd;
             nv[u] = xc + (kB[u] - Au) / dg;
@@ -1405,22 +1408,22 @@ static void tlaunch(Ctx* c, bool timed, double bytes, K k, dim3 grid, dim3 block
     }
 }
 
-template <int DIM, bool FINE, typename R>
+template <int DIM, bool FINE, typename R, class CF = TileCfg<DIM>>
 static void tsmooth_impl(Ctx* c, const Level& L, BV v, const R* coef, int comp, const R* xcur, R* xnext, const R* b,
                          bool timed, double bytes)
 {
-    const size_t lds = sizeof(R) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 2>::NS;
-    const dim3 grid = tile_grid<DIM>(c, L, v);
-    constexpr int TH = TileCfg<DIM>::THREADS;
+    const size_t lds = sizeof(R) * (DIM + (FINE ? 1 : 0)) * Tile<DIM, 2, CF>::NS;
+    const dim3 grid = tile_grid<DIM, CF>(c, L, v);
+    constexpr int TH = CF::THREADS;
     const R* xin = xnext;
     if (comp == 0)
-        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, 0, R>, grid, dim3(TH), lds, v, coef, (const double*)c->sc, xcur,
-                xin, xnext, b);
+        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, 0, R, CF>, grid, dim3(TH), lds, v, coef, (const double*)c->sc,
+                xcur, xin, xnext, b);
     else if (comp == 1)
-        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, 1, R>, grid, dim3(TH), lds, v, coef, (const double*)c->sc, xcur,
-                xin, xnext, b);
+        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, 1, R, CF>, grid, dim3(TH), lds, v, coef, (const double*)c->sc,
+                xcur, xin, xnext, b);
     else
-        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, (DIM == 3 ? 2 : 1), R>, grid, dim3(TH), lds, v, coef,
+        tlaunch(c, timed, bytes, k_tsmooth<DIM, FINE, (DIM == 3 ? 2 : 1), R, CF>, grid, dim3(TH), lds, v, coef,
                 (const double*)c->sc, xcur, xin, xnext, b);
 }
 
@@ -1442,8 +1445,22 @@ void launch_tsmooth(Ctx* c, const Level& L, const BV& v, const R* coef, bool fin
     } else if (fine) {
         tsmooth_impl<3, true, R>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
     } else {
-        tsmooth_impl<3, false, R>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
+        tsmooth_impl<3, false, R, Tsm3Tile>(c, L, v, coef, comp, xcur, xnext, b, timed, bytes);
     }
+}
+
+// the 3D coarse-level tile stages more than the default 64 KB of LDS in FP64
+void tsmooth_allow_lds(size_t bytes)
+{
+    auto allow = [&](const void* k) {
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    };
+    allow(reinterpret_cast<const void*>(&k_tsmooth<3, false, 0, double, Tsm3Tile>));
+    allow(reinterpret_cast<const void*>(&k_tsmooth<3, false, 1, double, Tsm3Tile>));
+    allow(reinterpret_cast<const void*>(&k_tsmooth<3, false, 2, double, Tsm3Tile>));
+    allow(reinterpret_cast<const void*>(&k_tsmooth<3, false, 0, float, Tsm3Tile>));
+    allow(reinterpret_cast<const void*>(&k_tsmooth<3, false, 1, float, Tsm3Tile>));
+    allow(reinterpret_cast<const void*>(&k_tsmooth<3, false, 2, float, Tsm3Tile>));
 }
 
 template <int DIM>
