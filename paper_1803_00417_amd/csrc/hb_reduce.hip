@@ -115,6 +115,25 @@ void fetch_slots(Ctx* c)
 
 // ---- convergence decisions on the device -----------------------------------
 
+// The largest of a cavity's kSubMax partial words, read by one 256-thread
+// block, and the words cleared: every load is issued before the first
+// clear, so the pass costs one memory round trip rather than one per word.
+__device__ inline unsigned long long take_max_words(unsigned long long* __restrict__ w)
+{
+    static_assert(kSubMax % 256 == 0, "whole words per thread");
+    constexpr int PER = kSubMax / 256;
+    unsigned long long v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v[u] = w[threadIdx.x + 256 * u];
+    unsigned long long m = 0ull;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        m = v[u] > m ? v[u] : m;
+        w[threadIdx.x + 256 * u] = 0ull;
+    }
+    return m;
+}
+
 __device__ inline bool conv_stops(double* R, const ConvArgs& a)
 {
     const double cyc = R[R_CYC];
@@ -152,12 +171,7 @@ __global__ void __launch_bounds__(1024) k_conv(ConvArgs a, double* __restrict__ 
     if (a.mf_slot >= 0) {
         // the max-norm's final pass (one cavity): the largest partial word,
         // the words cleared, the slot written when the cavity is active
-        unsigned long long m = 0ull;
-        for (int i = threadIdx.x; i < kSubMax; i += blockDim.x) {
-            const unsigned long long v = mp[i];
-            m = v > m ? v : m;
-            mp[i] = 0ull;
-        }
+        unsigned long long m = take_max_words(mp);
         m = block_umax(m, shm);
         if (threadIdx.x == 0 && (!a.mf_act || act[0])) sc[a.mf_slot] = __longlong_as_double((long long)m);
         __syncthreads();
@@ -331,12 +345,8 @@ __global__ void k_max_final(const int* __restrict__ act, unsigned long long* __r
     __shared__ unsigned long long sh[kT / 64];
     const int cav = blockIdx.x;
     unsigned long long* w = mp + (long)cav * kSubMax;
-    unsigned long long m = 0ull;
-    for (int i = threadIdx.x; i < kSubMax; i += blockDim.x) {
-        const unsigned long long v = w[i];
-        m = v > m ? v : m;
-        w[i] = 0ull;
-    }
+    static_assert(kT == 256, "one 256-thread block per cavity");
+    unsigned long long m = take_max_words(w);
     m = block_umax(m, sh);
     if (threadIdx.x == 0 && (!act || act[cav])) sc[(long)cav * S_NSLOT + slot] = __longlong_as_double((long long)m);
 }
