@@ -34,6 +34,11 @@ using Mac3Tile = TileShape<32, 8, 8, 1024>;
 // tile of the 3D coarse-level tensor smoother (k_tsmooth): a deeper tile
 // than TileCfg<3> stages fewer halo cells per updated cell
 using Tsm3Tile = TileShape<16, 8, 8, 1024>;
+// tile of the one-colour 3D tensor sweep (k_trb3): one thread per cell of
+// the colour; 8 rows deep, it stages 2.0 cells per updated cell against
+// 2.4 for a 32x4x4 tile, and its FP64 stage (64 KB) still lets two blocks
+// share a CU
+using Trb3Tile = TileShape<32, 8, 4, 512>;
 // Candidates of the 2D fused tensor sweep, chosen per level by the
 // autotuner (index 0 is the default): the tile with its thread count, the
 // most sweeps one launch may run (NSW), and whether b and the face
@@ -139,12 +144,13 @@ __device__ inline void fill_batched(const GridD& g, const R* const* q, const boo
     }
 }
 
-// fill of the 3D halo-1 tile by a 256-thread block (k_trb3)
-template <bool FINE, typename R>
+// fill of the 3D halo-1 tile for k_trb3: all arrays present, so no load is
+// guarded
+template <bool FINE, typename R, class CF>
 __device__ inline void fill_tile1(const GridD& g, const R* const* q, const bool* mirror, R* s, int ox, int oy, int oz)
 {
-    using T = Tile<3, 1>;
-    constexpr int TH = 256;
+    using T = Tile<3, 1, CF>;
+    constexpr int TH = CF::THREADS;
     constexpr int NA = FINE ? 4 : 3;
     constexpr int K = (T::NS + TH - 1) / TH;
     const bool inner = ox - 1 >= 0 && ox + T::TX + 1 <= g.n[0] && oy - 1 >= 0 && oy + T::TY + 1 <= g.n[1] &&
@@ -1320,13 +1326,13 @@ k_tresid_restr(BV v, const GridD* __restrict__ gct, const long* __restrict__ oct
 // two-colour sweep (whose 2-cell halo is large relative to a 3D tile).
 // ---------------------------------------------------------------------------
 
-template <bool FINE, typename R>
-__global__ void __launch_bounds__(256)
+template <bool FINE, typename R, class CF = Trb3Tile>
+__global__ void __launch_bounds__(CF::THREADS)
 k_trb3(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c, int colour, R* xa,
        const R* __restrict__ ba)
 {
-    using T = Tile<3, 1>;
-    static_assert(T::TX * T::TY * T::TZ / 2 == 256, "one cell of the colour per thread");
+    using T = Tile<3, 1, CF>;
+    static_assert(T::TX * T::TY * T::TZ / 2 == CF::THREADS, "one cell of the colour per thread");
     TILE_ENTER(3, T);
     const R dt = (R)vload(scb + (long)cav * S_NSLOT + S_DT);
     const R* coef = FINE ? coefa + cell0 : coefa + bv_of(v, cav);
@@ -1348,13 +1354,13 @@ k_trb3(BV v, const R* __restrict__ coefa, const double* __restrict__ scb, int c,
     {
         const R* q[4] = {x, x + N, x + 2 * N, coef};
         const bool mir[4] = {false, false, false, true};
-        fill_tile1<FINE, R>(g, q, mir, s, ox, oy, oz);
+        fill_tile1<FINE, R, CF>(g, q, mir, s, ox, oy, oz);
     }
     __syncthreads();
     if (!ok) return;
     const int l = T::at(G[0] - ox + 1, ry + 1, rz + 1);
     R dg;
-    const R vd = tile_visc_div<3, 1, FINE, R>(g, bf, s, e, c, G, wall_mask<3>(g, G), l, dt, &dg);
+    const R vd = tile_visc_div<3, 1, FINE, R, CF>(g, bf, s, e, c, G, wall_mask<3>(g, G), l, dt, &dg);
     const R xc = s[c * T::NS + l];
     const R Au = xc - dt * vd;
     x[c * N + q0] = xc + (bv - Au) / dg;
@@ -1655,20 +1661,23 @@ size_t sweep2_lds(int k, int nsw) { return sweep2_lds_of(k, nsw, std::make_index
 template <typename R>
 void launch_trb3(Ctx* c, const Level& L, const BV& v, const R* coef, bool fine, int comp, int colour, R* x, const R* b)
 {
-    using T = Tile<3, 1>;
+    using CF = Trb3Tile;
+    using T = Tile<3, 1, CF>;
     const bool timed = fine && kt_take(c);
     const size_t lds = sizeof(R) * (3 + (fine ? 1 : 0)) * T::NS;
     BV vv = v;
-    const dim3 grid = tile_grid<3>(c, L, vv);
+    const dim3 grid = tile_grid<3, CF>(c, L, vv);
     // algorithmic bytes counted per red-black sweep of all three components
     // (every component of x, eta/Re and every component of b read once, x
     // written once: 10 words per cell); a launch runs one colour of one
     // component, a sixth of a sweep
     const double N = level_cells(L);
     const double bytes = sizeof(R) * 10.0 * N / 6.0;
-    if (fine) tlaunch(c, timed, bytes, k_trb3<true, R>, grid, dim3(256), lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
-    else tlaunch(c, timed, bytes, k_trb3<false, R>, grid, dim3(256), lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
+    const dim3 blk(CF::THREADS);
+    if (fine) tlaunch(c, timed, bytes, k_trb3<true, R, CF>, grid, blk, lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
+    else tlaunch(c, timed, bytes, k_trb3<false, R, CF>, grid, blk, lds, vv, coef, (const double*)c->sc, comp, colour, x, b);
 }
+
 
 template <typename R>
 void launch_mac_sweep(Ctx* c, const Level& L, const BV& v, const R* cur, R* next, const R* b, int nsw, const R* pe,
