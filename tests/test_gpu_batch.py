@@ -38,7 +38,9 @@ def _specs3d():
     return [lid_spec(3, 16, Re=100.0, HB=2.0, Pa=1e3),
             spec(3, [12, 16, 8], h=1.0 / 16, bc=((1, 1), (0, 0), (0, 0)), wall_u={(2, 1): (1.0, 0.5, 0.0)},
                  Re=20.0, HB=1.0, nidx=0.6, Pa=200.0),
-            lid_spec(3, 8, Re=10.0, HB=0.5, nidx=1.2, Pa=300.0)]
+            lid_spec(3, 8, Re=10.0, HB=0.5, nidx=1.2, Pa=300.0),
+            spec(3, [24, 12, 6], h=1.0 / 24, bc=((0, 0), (0, 0), (1, 1)), wall_u={(1, 1): (1.0, 0.0, 0.3)},
+                 Re=30.0, HB=1.5, nidx=0.8, Pa=300.0)]
 
 
 def _zeros(s):

@@ -28,6 +28,10 @@ CASES = {
                                 f=(1.0, 0.0, 0.0)),
     "mix3d_12x16x8": lambda: spec(3, [12, 16, 8], h=1.0 / 16, bc=((1, 1), (0, 0), (0, 0)),
                                   wall_u={(2, 1): (1.0, 0.5, 0.0)}, Re=20.0, HB=1.0, nidx=0.6, Pa=200.0),
+    # tiles cut in every axis: 24 cells against 32-wide tiles, 12 against
+    # 8- and 16-deep ones, 6 against 4 and 8, with a periodic axis across them
+    "rag3d_24x12x6": lambda: spec(3, [24, 12, 6], h=1.0 / 24, bc=((0, 0), (0, 0), (1, 1)),
+                                  wall_u={(1, 1): (1.0, 0.0, 0.3)}, Re=30.0, HB=1.5, nidx=0.8, Pa=300.0),
 }
 
 SOLVE_TOL = 2e-6
@@ -135,7 +139,7 @@ def test_mixed_step_cavity2d_64_fifty_steps():
     assert worst < SOLVE_TOL
 
 
-@pytest.mark.parametrize("case", ["lid3d_16", "mix3d_12x16x8"])
+@pytest.mark.parametrize("case", ["lid3d_16", "mix3d_12x16x8", "rag3d_24x12x6"])
 def test_mixed_step_short_runs(case):
     _say("mixed step", case)
     worst = _steps(CASES[case](), 5)

@@ -27,6 +27,10 @@ CASES = {
     "lid3d_16": lambda: lid_spec(3, 16, Re=100.0, HB=2.0, Pa=1e3),
     "mix3d_12x16x8": lambda: spec(3, [12, 16, 8], h=1.0 / 16, bc=((1, 1), (0, 0), (0, 0)),
                                   wall_u={(2, 1): (1.0, 0.5, 0.0)}, Re=20.0, HB=1.0, nidx=0.6, Pa=200.0),
+    # tiles cut in every axis: 24 cells against 32-wide tiles, 12 against
+    # 8- and 16-deep ones, 6 against 4 and 8, with a periodic axis across them
+    "rag3d_24x12x6": lambda: spec(3, [24, 12, 6], h=1.0 / 24, bc=((0, 0), (0, 0), (1, 1)),
+                                  wall_u={(1, 1): (1.0, 0.0, 0.3)}, Re=30.0, HB=1.5, nidx=0.8, Pa=300.0),
 }
 
 
@@ -71,7 +75,7 @@ def test_viscosity_parity(case):
     assert rel_err(host(eta), eta_o) < 1e-13
 
 
-@pytest.mark.parametrize("case", ["lid2d_32", "lid2d_96x48", "per2d_32", "lid3d_16", "mix3d_12x16x8"])
+@pytest.mark.parametrize("case", ["lid2d_32", "lid2d_96x48", "per2d_32", "lid3d_16", "mix3d_12x16x8", "rag3d_24x12x6"])
 @pytest.mark.parametrize("op", [hb.OP_VISC, hb.OP_MAC, hb.OP_NODAL])
 def test_mg_fixed_cycles_parity(case, op):
     _say("mg fixed", case, op)
@@ -100,7 +104,7 @@ def test_mg_fixed_cycles_parity(case, op):
         assert rel_err(host(xd).reshape(sh), xo) < 1e-12, (krylov, rel_err(host(xd).reshape(sh), xo))
 
 
-@pytest.mark.parametrize("case", ["lid2d_96x48", "lid3d_16", "chan2d_8x32"])
+@pytest.mark.parametrize("case", ["lid2d_96x48", "lid3d_16", "chan2d_8x32", "rag3d_24x12x6"])
 @pytest.mark.parametrize("op", [hb.OP_VISC, hb.OP_MAC, hb.OP_NODAL])
 def test_mg_converged_parity(case, op):
     _say("mg converged", case, op)
@@ -213,7 +217,7 @@ def test_step_parity_cavity2d_64_fifty_steps():
     assert rep.visc.rel_resid <= 1e-10 and rep.proj.rel_resid <= 1e-10 and rep.div_mac_rel <= 1e-10
 
 
-@pytest.mark.parametrize("case", ["lid3d_16", "mix3d_12x16x8", "per2d_32", "lid2d_96x48"])
+@pytest.mark.parametrize("case", ["lid3d_16", "mix3d_12x16x8", "per2d_32", "lid2d_96x48", "rag3d_24x12x6"])
 def test_step_parity_short_runs(case):
     _say("step", case)
     s = CASES[case]()
