@@ -493,7 +493,9 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_inverse(const CoarseD* __rest
     double* __restrict__ Ainv = Ainva + cd.aoff;
     __shared__ double ck[2][kDenseMax];   // column k before step k
     __shared__ double rw[2][kDenseMax];   // row k before step k
-    const int tid = threadIdx.x, j = tid % kGJCols, rg = tid / kGJCols;
+    // a wave's 64 lanes share their row group (128 threads per group), so
+    // the group index is a scalar
+    const int tid = threadIdx.x, j = tid % kGJCols, rg = __builtin_amdgcn_readfirstlane(tid / kGJCols);
     // rows and columns from N to kDenseMax - 1 hold zeros and stay zero
     // (their pivot-column and pivot-row entries are zero), so every thread
     // runs the same branch-free update
@@ -519,12 +521,23 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_inverse(const CoarseD* __rest
         __syncthreads();
         const double d = 1.0 / cc[k];
         const double r = (j == k ? 1.0 : rr[j]) * d;
-        const bool pc = j == k;
+        // only the wave whose 64 columns hold column k needs the pivot
+        // column's select; every other wave runs the plain update
+        if (((tid % kGJCols) >> 6) == (k >> 6)) {
+            const bool pc = j == k;
 #pragma unroll
-        for (int m = 0; m < kGJPer; ++m) {
-            const int i = rg + kGJRows * m;
-            const double t = (pc ? 0.0 : v[m]) - cc[i] * r;
-            v[m] = i == k ? r : t;
+            for (int m = 0; m < kGJPer; ++m) v[m] = (pc ? 0.0 : v[m]) - cc[rg + kGJRows * m] * r;
+        } else {
+#pragma unroll
+            for (int m = 0; m < kGJPer; ++m) v[m] = v[m] - cc[rg + kGJRows * m] * r;
+        }
+        // row k (held by one row group, element k / kGJRows) becomes the
+        // scaled pivot row
+        if (rg == k % kGJRows) {
+            const int mk = k / kGJRows;
+#pragma unroll
+            for (int m = 0; m < kGJPer; ++m)
+                if (m == mk) v[m] = r;
         }
     }
     if (j < N)
