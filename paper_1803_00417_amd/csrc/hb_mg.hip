@@ -474,7 +474,8 @@ void launch_lu_inverse(Ctx* c, int N, const double* LU, const int* piv, double* 
 // div(eta (grad u + grad u^T)), slightly unsymmetric at walls), by one
 // workgroup: Gauss-Jordan elimination in place, without pivoting, which such
 // matrices do not need.  The matrix lives in registers: thread t holds
-// column t % 128 of rows t / 128 + 8m, m = 0..15.  Step k passes column k
+// column t % 128 of rows 16 (t / 128) + m, m = 0..15 (contiguous, so the
+// pivot column's entries a thread needs are read from LDS in wide loads).  Step k passes column k
 // and row k through LDS (double-buffered by the parity of k, so one barrier
 // per step), every thread forms the scaled pivot row itself, and the update
 // of its sixteen elements touches registers only.
@@ -502,7 +503,7 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_inverse(const CoarseD* __rest
     double v[kGJPer];
 #pragma unroll
     for (int m = 0; m < kGJPer; ++m) {
-        const int i = rg + kGJRows * m;
+        const int i = kGJPer * rg + m;
         v[m] = (j < N && i < N) ? A[(long)i * N + j] : 0.0;
     }
     for (int k = 0; k < N; ++k) {
@@ -510,12 +511,12 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_inverse(const CoarseD* __rest
         double* rr = rw[k & 1];
         if (j == k)
 #pragma unroll
-            for (int m = 0; m < kGJPer; ++m) cc[rg + kGJRows * m] = v[m];
-        if (rg == k % kGJRows) {
+            for (int m = 0; m < kGJPer; ++m) cc[kGJPer * rg + m] = v[m];
+        if (rg == k / kGJPer) {
             double a = 0.0;
 #pragma unroll
             for (int m = 0; m < kGJPer; ++m)
-                if (rg + kGJRows * m == k) a = v[m];
+                if (m == k % kGJPer) a = v[m];
             rr[j] = a;
         }
         __syncthreads();
@@ -526,15 +527,15 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_inverse(const CoarseD* __rest
         if (((tid % kGJCols) >> 6) == (k >> 6)) {
             const bool pc = j == k;
 #pragma unroll
-            for (int m = 0; m < kGJPer; ++m) v[m] = (pc ? 0.0 : v[m]) - cc[rg + kGJRows * m] * r;
+            for (int m = 0; m < kGJPer; ++m) v[m] = (pc ? 0.0 : v[m]) - cc[kGJPer * rg + m] * r;
         } else {
 #pragma unroll
-            for (int m = 0; m < kGJPer; ++m) v[m] = v[m] - cc[rg + kGJRows * m] * r;
+            for (int m = 0; m < kGJPer; ++m) v[m] = v[m] - cc[kGJPer * rg + m] * r;
         }
-        // row k (held by one row group, element k / kGJRows) becomes the
+        // row k (held by one row group, element k % kGJPer) becomes the
         // scaled pivot row
-        if (rg == k % kGJRows) {
-            const int mk = k / kGJRows;
+        if (rg == k / kGJPer) {
+            const int mk = k % kGJPer;
 #pragma unroll
             for (int m = 0; m < kGJPer; ++m)
                 if (m == mk) v[m] = r;
@@ -543,7 +544,7 @@ __global__ void __launch_bounds__(kGJThreads) k_gj_inverse(const CoarseD* __rest
     if (j < N)
 #pragma unroll
         for (int m = 0; m < kGJPer; ++m) {
-            const int i = rg + kGJRows * m;
+            const int i = kGJPer * rg + m;
             if (i < N) Ainv[(long)i * N + j] = v[m];
         }
 }
